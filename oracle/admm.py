@@ -1,0 +1,256 @@
+"""Algorithms 1 and 2 of Section IV, step by step, in FP64.
+
+Algorithm 1 (analysis case; Eqs. analysis_ADMM, iter_ADMM1, iter_ADMM2,
+subu_trans), with t^0 = u^0 = 0 (the paper leaves them to choice):
+    x^{l+1} = (rho T^H T + beta H^H H)^+ (beta H^H y + rho T^H (t^l - u^l))
+    t^{l+1} = soft(T x^{l+1} + u^l, lambda / rho)
+    u^{l+1} = u^l + T x^{l+1} - t^{l+1}
+
+Algorithm 2 (synthesis case; Eqs. synthesis_ADMM, iterd_ADMM1..3, subu_dic),
+with z^0 = t^0 = u^0 = 0:
+    x^{l+1} = (c_P I + beta H^H H)^-1 (beta H^H y + P^H D~ z^l)
+    z^{l+1} = argmin_z 1/2 ||D~ z - P x^{l+1}||^2 + rho/2 ||z - t^l + u^l||^2
+        patch dictionary:  z_j = (rho I + D^T D)^-1 (D^T P_j x + rho (t_j - u_j))
+                           (Eq. solz_patch2)
+        conv dictionary:   (rho I + Theta^H Theta) F z = Theta^H F x + rho F (t - u)
+                           solved per frequency by Sherman-Morrison
+                           (Eqs. solz_DFT, solz_DFT_SM)
+    t^{l+1} = soft(z^{l+1} + u^l, lambda / rho)          (Eq. softADMM)
+    u^{l+1} = u^l + z^{l+1} - t^{l+1}
+
+The penalty rho is fixed and a fixed number of iterations is run (the paper's
+adaptive rho and relative-change stopping rule, Section IV-C, are not part of
+this reference). Iterations return x^L.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import model, priors, xupdate
+
+
+def _tier(S, N1, N2, tier):
+    if tier == "auto":
+        return "dense" if S * N1 * N2 <= 2048 else "freq"
+    return tier
+
+
+# ================================================================ analysis
+def analysis_objective(x, y, psf, transform, lam, beta):
+    """beta/2 ||y - Hx||^2 + lambda ||T x||_1 (Eq. rls with Eq. analysis)."""
+    r = y - model.forward(x, psf)
+    return 0.5 * beta * np.sum(r * r) + lam * np.sum(np.abs(transform.T(x)))
+
+
+class AnalysisADMM:
+    """Algorithm 1 for T in {dct2d, tv2d, tv3d} and Phi = l1."""
+
+    def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto"):
+        K, S, N1, N2 = psf.shape
+        self.psf = psf
+        self.K, self.S, self.N1, self.N2 = K, S, N1, N2
+        self.lam, self.rho, self.beta = float(lam), float(rho), float(beta)
+        self.T = priors.make_transform(kind, S, N1, N2)
+        self.tier = _tier(S, N1, N2, tier)
+        if self.tier == "dense":
+            reg = rho * xupdate.dense_TtT(self.T, S, N1, N2)
+            self.solver = xupdate.DenseSolver(
+                psf, beta, reg, annihilates_constants=(kind == "tv2d"))
+        else:
+            band_lap = self.T.band_laplacian() if kind == "tv3d" else None
+            self.solver = xupdate.FreqSolver(
+                psf, beta, rho, self.T.gram_symbol(N1, N2), band_lap)
+
+    def x_update(self, data, t, u):
+        extra = self.rho * self.T.Tt(t - u)
+        if self.tier == "dense":
+            return self.solver.solve(data + extra)
+        return self.solver.solve(data, extra)
+
+    def run(self, y, iters, callback=None, state=None):
+        """Run ``iters`` iterations from t = u = 0 (or from ``state``).
+        Returns (x, t, u)."""
+        data = self.solver.data_term(y)
+        if state is None:
+            t = np.zeros(self.T.shape)
+            u = np.zeros(self.T.shape)
+        else:
+            t, u = (a.copy() for a in state)
+        x = None
+        kappa = self.lam / self.rho
+        for it in range(iters):
+            x = self.x_update(data, t, u)
+            w = self.T.T(x)
+            t_new = priors.soft(w + u, kappa)
+            u = u + w - t_new
+            t = t_new
+            if callback is not None:
+                callback(it, x, t, u)
+        return x, t, u
+
+    def kkt(self, y, x, t, u):
+        """Relative KKT residuals of the split problem at (x, t, u):
+        primal ||Tx - t||, stationarity in x ||beta H^T (Hx - y) + rho T^T u||,
+        and the prox fixed point ||t - soft(t + u, lambda/rho)||."""
+        Tx = self.T.T(x)
+        r1 = np.linalg.norm(Tx - t) / max(np.linalg.norm(Tx), 1e-300)
+        g = self.beta * model.adjoint(model.forward(x, self.psf) - y, self.psf) \
+            + self.rho * self.T.Tt(u)
+        r2 = np.linalg.norm(g) / max(
+            np.linalg.norm(self.beta * model.adjoint(y, self.psf)), 1e-300)
+        r3 = np.linalg.norm(t - priors.soft(t + u, self.lam / self.rho)) / max(
+            np.linalg.norm(t), 1e-300)
+        return r1, r2, r3
+
+
+# ================================================================ synthesis: patches
+def patch_objective(x, z, y, psf, patches, D, lam, beta):
+    """beta/2 ||y - Hx||^2 + 1/2 sum_j ||D z_j - P_j x||^2 + lambda ||z||_1
+    (Eq. rls with Eq. patch_based)."""
+    r = y - model.forward(x, psf)
+    q = D @ z - patches.extract(x)
+    return 0.5 * beta * np.sum(r * r) + 0.5 * np.sum(q * q) + lam * np.sum(np.abs(z))
+
+
+class PatchADMM:
+    """Algorithm 2 with the patch-based dictionary prior.
+
+    D has shape (n, A) with n = Q*Q*S (column a = atom a, element layout as in
+    ``priors.Patches``); codes z, t, u have shape (A, J)."""
+
+    def __init__(self, psf, D, Q, stride, lam, rho, beta, tier="auto"):
+        K, S, N1, N2 = psf.shape
+        self.psf = psf
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.D = np.asarray(D, dtype=np.float64)
+        self.P = priors.Patches(S, N1, N2, Q, stride)
+        assert self.D.shape[0] == self.P.n
+        self.lam, self.rho, self.beta = float(lam), float(rho), float(beta)
+        self.tier = _tier(S, N1, N2, tier)
+        cP = self.P.c_P
+        if self.tier == "dense":
+            self.solver = xupdate.DenseSolver(psf, beta, cP * np.eye(S * N1 * N2))
+        else:
+            self.solver = xupdate.FreqSolver(psf, beta, cP, np.ones((N1, N2)))
+        A = self.D.shape[1]
+        self.zgram = rho * np.eye(A) + self.D.T @ self.D     # rho I + D^T D
+
+    def x_update(self, data, z):
+        extra = self.P.adjoint(self.D @ z)                    # P^H D~ z
+        if self.tier == "dense":
+            return self.solver.solve(data + extra)
+        return self.solver.solve(data, extra)
+
+    def z_update(self, x, t, u):
+        """Eq. solz_patch2 for all patches at once."""
+        rhs = self.D.T @ self.P.extract(x) + self.rho * (t - u)
+        return np.linalg.solve(self.zgram, rhs)
+
+    def run(self, y, iters, callback=None):
+        data = self.solver.data_term(y)
+        A = self.D.shape[1]
+        z = np.zeros((A, self.P.J))
+        t = np.zeros_like(z)
+        u = np.zeros_like(z)
+        kappa = self.lam / self.rho
+        x = None
+        for it in range(iters):
+            x = self.x_update(data, z)
+            z = self.z_update(x, t, u)
+            t_new = priors.soft(z + u, kappa)
+            u = u + z - t_new
+            t = t_new
+            if callback is not None:
+                callback(it, x, z, t, u)
+        return x, z, t, u
+
+
+# ================================================================ synthesis: conv dictionary
+def conv_objective(x, z, y, psf, cd, lam, beta):
+    """beta/2 ||y - Hx||^2 + 1/2 ||D~ z - x||^2 + lambda ||z||_1."""
+    r = y - model.forward(x, psf)
+    q = cd.synth(z) - x
+    return 0.5 * beta * np.sum(r * r) + 0.5 * np.sum(q * q) + lam * np.sum(np.abs(z))
+
+
+def sherman_morrison(theta, c, rho):
+    """Eq. solz_DFT_SM at every frequency: solve (rho I + a a^H) v = c for the
+    M-vector v, where a = conj(theta) collects the filter spectra at that
+    frequency (so that Theta^H Theta = a a^H):
+        v = rho^-1 (c - a (a^H c) / (rho + a^H a)).
+    theta: (M, ...) complex; c: (M, ...) complex."""
+    a = np.conj(theta)
+    ahc = np.sum(np.conj(a) * c, axis=0)
+    aha = np.sum(np.abs(a) ** 2, axis=0)
+    return (c - a * (ahc / (rho + aha))[None]) / rho
+
+
+class ConvADMM:
+    """Algorithm 2 with a common 2D convolutional dictionary for every band
+    (P = I, c_P = 1). Codes z, t, u have shape (M, S, N1, N2)."""
+
+    def __init__(self, psf, filters, lam, rho, beta, tier="auto"):
+        K, S, N1, N2 = psf.shape
+        self.psf = psf
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.cd = priors.ConvDict2D(np.asarray(filters, dtype=np.float64), S, N1, N2)
+        self.M = self.cd.M
+        self.lam, self.rho, self.beta = float(lam), float(rho), float(beta)
+        self.tier = _tier(S, N1, N2, tier)
+        if self.tier == "dense":
+            self.solver = xupdate.DenseSolver(psf, beta, np.eye(S * N1 * N2))
+        else:
+            self.solver = xupdate.FreqSolver(psf, beta, 1.0, np.ones((N1, N2)))
+        self.theta = self.cd.spectra()                           # (M, N1, N2)
+
+    def synth(self, z):
+        if self.tier == "dense":
+            return self.cd.synth(z)
+        zh = np.fft.fft2(z, axes=(-2, -1))
+        return np.real(np.fft.ifft2(np.einsum("mab,msab->sab", self.theta, zh),
+                                    axes=(-2, -1)))
+
+    def x_update(self, data, z):
+        extra = self.synth(z)
+        if self.tier == "dense":
+            return self.solver.solve(data + extra)
+        return self.solver.solve(data, extra)
+
+    def z_update(self, x, t, u):
+        """Eq. solz_DFT: c = Theta^H F x + rho F (t - u), then Sherman-Morrison
+        per frequency and per band, then inverse DFT."""
+        xh = np.fft.fft2(x, axes=(-2, -1))                       # (S, N1, N2)
+        gh = np.fft.fft2(t - u, axes=(-2, -1))                   # (M, S, N1, N2)
+        c = np.conj(self.theta)[:, None] * xh[None] + self.rho * gh
+        v = sherman_morrison(self.theta[:, None], c, self.rho)
+        return np.real(np.fft.ifft2(v, axes=(-2, -1)))
+
+    def run(self, y, iters, callback=None):
+        data = self.solver.data_term(y)
+        z = np.zeros((self.M, self.S, self.N1, self.N2))
+        t = np.zeros_like(z)
+        u = np.zeros_like(z)
+        kappa = self.lam / self.rho
+        x = None
+        for it in range(iters):
+            x = self.x_update(data, z)
+            z = self.z_update(x, t, u)
+            t_new = priors.soft(z + u, kappa)
+            u = u + z - t_new
+            t = t_new
+            if callback is not None:
+                callback(it, x, z, t, u)
+        return x, z, t, u
+
+
+def psnr(x, ref, peak=1.0):
+    """10 log10(peak^2 / MSE) over all voxels (peak 1 for data in [0, 1])."""
+    mse = np.mean((np.asarray(x) - np.asarray(ref)) ** 2)
+    return 10.0 * np.log10(peak * peak / mse)
+
+
+def rel_l2(a, b):
+    """||a - b|| / ||b||."""
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))

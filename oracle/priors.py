@@ -1,0 +1,221 @@
+"""Priors of Section III and their elementary operators.
+
+* Analysis prior R(x) = lambda * ||T x||_1 (Eq. analysis with Phi = l1):
+  - T = orthonormal 2D DCT-II applied to each slice (a unitary transform, so
+    T^H T = I as assumed below Eq. solx_Trans);
+  - T = anisotropic discrete gradient on each slice (circular forward
+    differences along both image axes; "multidimensional discrete derivative
+    operators" of Section III-A);
+  - T = the same plus a forward difference along the band axis (3D case,
+    non-circular, no term after the last band).
+* Soft thresholding, the l1 proximal map (Eq. solt_trans), sign(0) = -1.
+* Patch extraction P_j for Q x Q x T patches spanning all bands (Eq.
+  patch_based), extracted circularly at a fixed stride.
+* Convolutional dictionary synthesis for 2D correlations: each band is
+  sum_m d_m * z_{m,s} with a common set of L x L filters (the 2D-correlation
+  variant of Eq. conv_dic, Section III-B.2).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .model import conv_circ, corr_circ
+
+
+# ---------------------------------------------------------------- soft threshold
+def soft(w: np.ndarray, tau: float) -> np.ndarray:
+    """Eq. solt_trans: w_i -> sign(w_i) max(|w_i| - tau, 0), sign(w) = 1 if
+    w > 0 else -1 (the value at w = 0 is 0 either way)."""
+    sgn = np.where(w > 0, 1.0, -1.0)
+    return sgn * np.maximum(np.abs(w) - tau, 0.0)
+
+
+# ---------------------------------------------------------------- DCT
+def dct_matrix(n: int) -> np.ndarray:
+    """Orthonormal DCT-II matrix C[k, m] = a_k cos(pi (2m + 1) k / (2n)),
+    a_0 = sqrt(1/n), a_k = sqrt(2/n) otherwise (rows are the basis vectors)."""
+    k = np.arange(n)[:, None].astype(np.float64)
+    m = np.arange(n)[None, :].astype(np.float64)
+    c = np.cos(math.pi * (2.0 * m + 1.0) * k / (2.0 * n))
+    a = np.full((n, 1), math.sqrt(2.0 / n))
+    a[0, 0] = math.sqrt(1.0 / n)
+    return a * c
+
+
+class DCT2D:
+    """T x = C_{N1} x_s C_{N2}^T for every slice (2D transform per slice)."""
+
+    name = "dct2d"
+
+    def __init__(self, S: int, N1: int, N2: int):
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.C1 = dct_matrix(N1)
+        self.C2 = dct_matrix(N2)
+        self.shape = (1, S, N1, N2)
+
+    def T(self, x):
+        return np.einsum("ab,sbc,dc->sad", self.C1, x, self.C2)[None]
+
+    def Tt(self, w):
+        return np.einsum("ba,sbc,cd->sad", self.C1, w[0], self.C2)
+
+    def gram_symbol(self, N1, N2):
+        """T^H T = I: the per-frequency symbol is 1."""
+        return np.ones((N1, N2))
+
+
+class TV2D:
+    """Anisotropic gradient per slice, circular forward differences:
+    w[0] = x[n1 + 1, n2] - x[n1, n2],  w[1] = x[n1, n2 + 1] - x[n1, n2]."""
+
+    name = "tv2d"
+
+    def __init__(self, S: int, N1: int, N2: int):
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.shape = (2, S, N1, N2)
+
+    def T(self, x):
+        w = np.empty((2,) + x.shape)
+        w[0] = np.roll(x, -1, axis=1) - x
+        w[1] = np.roll(x, -1, axis=2) - x
+        return w
+
+    def Tt(self, w):
+        return (np.roll(w[0], 1, axis=1) - w[0]) + (np.roll(w[1], 1, axis=2) - w[1])
+
+    def gram_symbol(self, N1, N2):
+        """T^T T is the circular Laplacian; its DFT symbol is
+        (2 - 2 cos w1) + (2 - 2 cos w2)."""
+        w1 = 2.0 * math.pi * np.arange(N1)[:, None] / N1
+        w2 = 2.0 * math.pi * np.arange(N2)[None, :] / N2
+        return (2.0 - 2.0 * np.cos(w1)) + (2.0 - 2.0 * np.cos(w2))
+
+
+class TV3D(TV2D):
+    """TV2D plus a band-axis forward difference w[2][s] = x[s + 1] - x[s] for
+    s < S - 1 and w[2][S - 1] = 0 (no wrap along the bands)."""
+
+    name = "tv3d"
+
+    def __init__(self, S: int, N1: int, N2: int):
+        super().__init__(S, N1, N2)
+        self.shape = (3, S, N1, N2)
+
+    def T(self, x):
+        w = np.zeros((3,) + x.shape)
+        w[:2] = super().T(x)
+        w[2, :-1] = x[1:] - x[:-1]
+        return w
+
+    def Tt(self, w):
+        g = super().Tt(w[:2])
+        q = w[2].copy()
+        q[-1] = 0.0
+        g[1:] += q[:-1]
+        g -= q
+        return g
+
+    def band_laplacian(self):
+        """D_s^T D_s for the band difference: the S x S path-graph Laplacian."""
+        S = self.S
+        L = np.zeros((S, S))
+        for s in range(S - 1):
+            L[s, s] += 1.0
+            L[s + 1, s + 1] += 1.0
+            L[s, s + 1] -= 1.0
+            L[s + 1, s] -= 1.0
+        return L
+
+
+def make_transform(kind: str, S: int, N1: int, N2: int):
+    return {"dct2d": DCT2D, "tv2d": TV2D, "tv3d": TV3D}[kind](S, N1, N2)
+
+
+# ---------------------------------------------------------------- patches
+class Patches:
+    """Q x Q x S patches spanning all bands (Eq. patch_based with T = S),
+    taken circularly at positions (i*st, j*st), i < N1/st, j < N2/st.
+
+    Patch vector layout: element s*Q*Q + a*Q + b is
+    x[s, (i*st + a) mod N1, (j*st + b) mod N2]; patch index j = i*(N2/st) + j.
+    With st dividing Q, every pixel lies in (Q/st)^2 patches, so
+    P^T P = (Q/st)^2 I (the constant t of Eq. solx_synt)."""
+
+    def __init__(self, S: int, N1: int, N2: int, Q: int, st: int):
+        assert N1 % st == 0 and N2 % st == 0
+        self.S, self.N1, self.N2, self.Q, self.st = S, N1, N2, Q, st
+        self.J1, self.J2 = N1 // st, N2 // st
+        self.J = self.J1 * self.J2
+        self.n = Q * Q * S
+        s, a, b = np.meshgrid(np.arange(S), np.arange(Q), np.arange(Q), indexing="ij")
+        self._s, self._a, self._b = s.ravel(), a.ravel(), b.ravel()
+
+    def extract(self, x: np.ndarray) -> np.ndarray:
+        """X = [P_1 x | ... | P_J x], shape (n, J)."""
+        X = np.empty((self.n, self.J))
+        for i in range(self.J1):
+            for j in range(self.J2):
+                r = (i * self.st + self._a) % self.N1
+                c = (j * self.st + self._b) % self.N2
+                X[:, i * self.J2 + j] = x[self._s, r, c]
+        return X
+
+    def adjoint(self, X: np.ndarray) -> np.ndarray:
+        """sum_j P_j^T X[:, j] (overlap-add of patches back onto the grid)."""
+        x = np.zeros((self.S, self.N1, self.N2))
+        for i in range(self.J1):
+            for j in range(self.J2):
+                r = (i * self.st + self._a) % self.N1
+                c = (j * self.st + self._b) % self.N2
+                np.add.at(x, (self._s, r, c), X[:, i * self.J2 + j])
+        return x
+
+    @property
+    def c_P(self) -> float:
+        return float((self.Q // self.st) ** 2)
+
+
+# ---------------------------------------------------------------- conv dictionary
+def filter_on_grid(d: np.ndarray, N1: int, N2: int) -> np.ndarray:
+    """Place an L x L filter on the N1 x N2 torus, centred at [0, 0]: tap
+    (a, b) sits at offset (a - L//2, b - L//2)."""
+    L = d.shape[0]
+    h = np.zeros((N1, N2))
+    for a in range(L):
+        for b in range(L):
+            h[(a - L // 2) % N1, (b - L // 2) % N2] += d[a, b]
+    return h
+
+
+class ConvDict2D:
+    """Common convolutional dictionary for every band (2D-correlation variant of
+    Eq. conv_dic): band s is approximated by sum_m d_m * z_{m,s}; P = I."""
+
+    def __init__(self, filters: np.ndarray, S: int, N1: int, N2: int):
+        self.M = filters.shape[0]
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.h = np.stack([filter_on_grid(f, N1, N2) for f in filters])
+
+    def synth(self, z: np.ndarray) -> np.ndarray:
+        """D~ z, z of shape (M, S, N1, N2) -> (S, N1, N2), spatial convolutions."""
+        out = np.zeros((self.S, self.N1, self.N2))
+        for m in range(self.M):
+            for s in range(self.S):
+                out[s] += conv_circ(z[m, s], self.h[m])
+        return out
+
+    def analysis(self, x: np.ndarray) -> np.ndarray:
+        """D~^T x -> (M, S, N1, N2), spatial correlations."""
+        z = np.empty((self.M, self.S, self.N1, self.N2))
+        for m in range(self.M):
+            for s in range(self.S):
+                z[m, s] = corr_circ(x[s], self.h[m])
+        return z
+
+    def spectra(self) -> np.ndarray:
+        """theta_m = 2D DFT of the grid-placed filters, shape (M, N1, N2)."""
+        return np.fft.fft2(self.h)

@@ -1,0 +1,444 @@
+"""Pins of the FP64 oracle against facts fixed by mathematics or by
+independent libraries (not against the oracle itself).
+
+Each test names the paper passage whose oracle function it pins."""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.ndimage
+import scipy.optimize
+
+from oracle import admm, model, priors, xupdate
+from paper_2006_08303_amd import synth
+
+
+def _rng(i=0):
+    return np.random.default_rng(12345 + i)
+
+
+def _dft_matrix(n):
+    """Explicit DFT matrix from complex exponentials (no FFT library)."""
+    k = np.arange(n)
+    return np.exp(-2j * math.pi * np.outer(k, k) / n)
+
+
+def _small_problem(K=2, S=2, N1=8, N2=8, seed=0, gauss=True):
+    rng = _rng(seed)
+    if gauss:
+        psf = synth.gaussian_psfs(rng, K, S, N1, N2, sigma_range=(0.6, 1.5))
+    else:
+        psf = synth.disk_psfs(K, S, N1, N2, r_max=2.0)
+    x = rng.uniform(0, 1, (S, N1, N2))
+    return x, psf
+
+
+# ------------------------------------------------------------------ forward model
+def test_conv_matches_scipy_wrap():
+    """Eq. forward model: circular convolution equals scipy.ndimage's
+    wrap-mode convolution with the kernel re-centred."""
+    rng = _rng(1)
+    N1, N2 = 12, 10
+    x = rng.standard_normal((N1, N2))
+    h = np.zeros((N1, N2))
+    taps = {(0, 0): 0.4, (1, 0): 0.2, (0, -1): 0.15, (-2, 3): 0.25}
+    for (a, b), v in taps.items():
+        h[a % N1, b % N2] = v
+    # compact kernel with centre (c, c): tap (a, b) at [c + a, c + b]
+    c = 3
+    kc = np.zeros((2 * c + 1, 2 * c + 1))
+    for (a, b), v in taps.items():
+        kc[c + a, c + b] = v
+    ref = scipy.ndimage.convolve(x, kc, mode="wrap", origin=0)
+    assert np.allclose(model.conv_circ(x, h), ref, atol=1e-13)
+
+
+def test_convolution_theorem_explicit_dft():
+    """Section IV-A.1: H_{k,s} = F^H Lambda_{k,s} F, with Lambda the DFT of h.
+    Checked with explicit DFT matrices, independent of numpy.fft."""
+    rng = _rng(2)
+    N1, N2 = 6, 8
+    x = rng.standard_normal((N1, N2))
+    h = rng.standard_normal((N1, N2))
+    W1, W2 = _dft_matrix(N1), _dft_matrix(N2)
+    lhs = W1 @ model.conv_circ(x, h) @ W2.T
+    rhs = (W1 @ h @ W2.T) * (W1 @ x @ W2.T)
+    assert np.allclose(lhs, rhs, atol=1e-11)
+
+
+def test_adjoint_identity():
+    """<Hx, y> = <x, H^T y> (transpose of the block matrix of Eq. forwardModel)."""
+    x, psf = _small_problem(K=3, S=2, N1=16, N2=12)
+    y = _rng(3).standard_normal((3, 16, 12))
+    lhs = np.vdot(model.forward(x, psf), y)
+    rhs = np.vdot(x, model.adjoint(y, psf))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_dense_H_matches_operator():
+    """The explicit BCCB block matrix reproduces the spatial operator."""
+    x, psf = _small_problem(K=2, S=3, N1=6, N2=6)
+    H = model.dense_H(psf)
+    assert np.allclose(H @ x.ravel(), model.forward(x, psf).ravel(), atol=1e-13)
+    y = _rng(4).standard_normal((2, 6, 6))
+    assert np.allclose(H.T @ y.ravel(), model.adjoint(y, psf).ravel(), atol=1e-13)
+
+
+def test_parseval_unitary_dft():
+    """Unitary 2D DFT preserves energy (F_2D of Section IV-A.1 is unitary)."""
+    x = _rng(5).standard_normal((8, 8))
+    W = _dft_matrix(8) / math.sqrt(8)
+    assert np.isclose(np.sum(x * x), np.sum(np.abs(W @ x @ W.T) ** 2), rtol=1e-13)
+
+
+# ------------------------------------------------------------------ priors
+def test_dct_matrix_matches_scipy_and_is_orthonormal():
+    """The unitary T of Eq. analysis (DCT-II, orthonormal)."""
+    for n in (1, 2, 8, 13):
+        C = priors.dct_matrix(n)
+        assert np.allclose(C @ C.T, np.eye(n), atol=1e-13)
+        v = _rng(n).standard_normal(n)
+        assert np.allclose(C @ v, scipy.fft.dct(v, type=2, norm="ortho"), atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["dct2d", "tv2d", "tv3d"])
+def test_transform_adjoint(kind):
+    T = priors.make_transform(kind, 3, 8, 6)
+    x = _rng(6).standard_normal((3, 8, 6))
+    w = _rng(7).standard_normal(T.shape)
+    if kind == "tv3d":
+        w[2, -1] = 0.0
+    assert np.isclose(np.vdot(T.T(x), w), np.vdot(x, T.Tt(w)), rtol=1e-12)
+
+
+def test_tv_symbol_matches_impulse_response():
+    """T^T T of the anisotropic TV is circulant with DFT symbol
+    (2 - 2cos w1) + (2 - 2cos w2) (used by the frequency-domain x-update)."""
+    T = priors.TV2D(1, 8, 10)
+    d = np.zeros((1, 8, 10))
+    d[0, 0, 0] = 1.0
+    imp = T.Tt(T.T(d))[0]
+    W1, W2 = _dft_matrix(8), _dft_matrix(10)
+    assert np.allclose(W1 @ imp @ W2.T, T.gram_symbol(8, 10), atol=1e-12)
+
+
+def test_tv3d_band_laplacian():
+    """The band-difference part of T^T T acts on per-band constants as the
+    path-graph Laplacian."""
+    S = 5
+    T = priors.TV3D(S, 4, 4)
+    c = _rng(8).standard_normal(S)
+    x = np.broadcast_to(c[:, None, None], (S, 4, 4)).copy()
+    out = T.Tt(T.T(x))[:, 0, 0]
+    L = np.diag([1, 2, 2, 2, 1]) - np.diag(np.ones(4), 1) - np.diag(np.ones(4), -1)
+    assert np.allclose(out, L @ c, atol=1e-13)
+    assert np.allclose(T.band_laplacian(), L)
+
+
+def test_soft_is_l1_prox_bruteforce():
+    """Eq. solt_trans: soft(w, tau) = argmin_t tau|t| + 1/2 (t - w)^2."""
+    grid = np.linspace(-4, 4, 160001)
+    for w in (-2.3, -0.4, 0.0, 0.2, 1.7, 3.1):
+        for tau in (0.0, 0.3, 1.0):
+            f = tau * np.abs(grid) + 0.5 * (grid - w) ** 2
+            assert abs(priors.soft(np.array(w), tau) - grid[np.argmin(f)]) < 1e-4
+    # sign(0) = -1 is immaterial: soft(0) = 0
+    assert priors.soft(np.array(0.0), 0.5) == 0.0
+
+
+def test_patch_PtP_is_scaled_identity():
+    """Eq. solx_synt: P^H P = t I; for Q = 8 and stride 4, t = 4."""
+    P = priors.Patches(2, 16, 16, Q=8, st=4)
+    n = 2 * 16 * 16
+    M = np.zeros((n, n))
+    e = np.zeros((2, 16, 16))
+    for i in range(n):
+        e.flat[i] = 1.0
+        M[:, i] = P.adjoint(P.extract(e)).ravel()
+        e.flat[i] = 0.0
+    assert np.allclose(M, 4.0 * np.eye(n))
+    assert P.c_P == 4.0
+    # extract / adjoint are transposes of each other
+    x = _rng(9).standard_normal((2, 16, 16))
+    X = _rng(10).standard_normal((P.n, P.J))
+    assert np.isclose(np.vdot(P.extract(x), X), np.vdot(x, P.adjoint(X)))
+
+
+def test_patch_layout():
+    """Element s*Q*Q + a*Q + b of patch (i, j) is x[s, i*st + a, j*st + b]."""
+    S, N = 3, 16
+    x = np.arange(S * N * N, dtype=float).reshape(S, N, N)
+    P = priors.Patches(S, N, N, Q=8, st=4)
+    X = P.extract(x)
+    i, j, s, a, b = 3, 2, 1, 5, 7
+    assert X[s * 64 + a * 8 + b, i * 4 + j] == x[s, (i * 4 + a) % N, (j * 4 + b) % N]
+
+
+def test_conv_dict_spectra_and_adjoint():
+    """Eq. conv_dic: D_m = F^H Theta_m F; synth/analysis are transposes."""
+    filt = synth.random_unit_filters(_rng(11), 3, 5)
+    cd = priors.ConvDict2D(filt, 2, 10, 12)
+    z = _rng(12).standard_normal((3, 2, 10, 12))
+    x = _rng(13).standard_normal((2, 10, 12))
+    assert np.isclose(np.vdot(cd.synth(z), x), np.vdot(z, cd.analysis(x)))
+    W1, W2 = _dft_matrix(10), _dft_matrix(12)
+    lhs = W1 @ cd.synth(z)[1] @ W2.T
+    rhs = sum((W1 @ cd.h[m] @ W2.T) * (W1 @ z[m, 1] @ W2.T) for m in range(3))
+    assert np.allclose(lhs, rhs, atol=1e-10)
+
+
+# ------------------------------------------------------------------ x-update
+def test_recursive_block_inverse():
+    """Eq. recinv (recursive 2x2 block inversion) equals the direct inverse."""
+    rng = _rng(14)
+    for S in (1, 2, 3, 4, 5, 8):
+        A = rng.standard_normal((6, S, S)) + 1j * rng.standard_normal((6, S, S))
+        psi = A @ np.conj(np.swapaxes(A, -1, -2)) + 0.1 * np.eye(S)
+        inv = xupdate.recursive_block_inverse(psi)
+        assert np.allclose(inv @ psi, np.eye(S)[None], atol=1e-10)
+
+
+@pytest.mark.parametrize("kind", ["dct2d", "tv2d", "tv3d"])
+def test_freq_solve_equals_dense_solve(kind):
+    """Eq. solx_Trans_DFT equals Eq. solx_Trans (the dense normal equations)."""
+    x, psf = _small_problem(K=2, S=2, N1=8, N2=8, seed=1)
+    rho, beta = 0.05, 1.3
+    T = priors.make_transform(kind, 2, 8, 8)
+    dense = xupdate.DenseSolver(psf, beta, rho * xupdate.dense_TtT(T, 2, 8, 8),
+                                annihilates_constants=(kind == "tv2d"))
+    freq = xupdate.FreqSolver(psf, beta, rho, T.gram_symbol(8, 8),
+                              T.band_laplacian() if kind == "tv3d" else None)
+    y = model.forward(x, psf) + 0.01 * _rng(15).standard_normal((2, 8, 8))
+    q = _rng(16).standard_normal(T.shape)
+    if kind == "tv3d":
+        q[2, -1] = 0
+    extra = rho * T.Tt(q)
+    xd = dense.solve(dense.data_term(y) + extra)
+    xf = freq.solve(freq.data_term(y), extra)
+    assert np.allclose(xd, xf, atol=1e-10 * np.max(np.abs(xd)))
+    # and it is the minimum-norm minimiser: full pseudo-inverse of the normal matrix
+    H = model.dense_H(psf)
+    A = beta * H.T @ H + rho * xupdate.dense_TtT(T, 2, 8, 8)
+    ref = np.linalg.pinv(A, rcond=1e-12, hermitian=True) @ (beta * H.T @ y.ravel() + extra.ravel())
+    assert np.allclose(xd.ravel(), ref, atol=1e-9 * np.max(np.abs(ref)))
+
+
+def test_tv2d_dc_block_is_singular_with_unit_sum_kernels():
+    """With TV on every slice and unit-sum kernels the DC block is rank one
+    (so the reading of a minimum-norm minimiser matters)."""
+    _, psf = _small_problem(K=2, S=2, N1=8, N2=8, seed=2)
+    lam = xupdate.psf_spectra(psf)
+    T = priors.TV2D(2, 8, 8)
+    psi = xupdate.gram_blocks(lam, 1.0, T.gram_symbol(8, 8), 0.01)
+    ev = np.linalg.eigvalsh(psi[0, 0])
+    assert ev[0] < 1e-12 * ev[-1]
+    assert np.all(np.linalg.eigvalsh(psi[1:, :]) > 0)
+
+
+def test_synthesis_freq_equals_dense():
+    """Eq. solx_synt_DFT equals Eq. solx_synt."""
+    x, psf = _small_problem(K=3, S=2, N1=8, N2=8, seed=3)
+    beta, cP = 7.0, 4.0
+    dense = xupdate.DenseSolver(psf, beta, cP * np.eye(2 * 64))
+    freq = xupdate.FreqSolver(psf, beta, cP, np.ones((8, 8)))
+    y = model.forward(x, psf)
+    extra = _rng(17).standard_normal((2, 8, 8))
+    assert np.allclose(dense.solve(dense.data_term(y) + extra),
+                       freq.solve(freq.data_term(y), extra), atol=1e-11)
+
+
+# ------------------------------------------------------------------ Algorithm 1
+def test_dct_identity_blur_closed_form():
+    """Algorithm 1 with H = I (delta kernels, K = S) solves
+    min beta/2 ||y - x||^2 + lambda ||Cx||_1, whose minimiser is
+    C^T soft(C y, lambda / beta) (orthonormal-basis denoising)."""
+    S, N = 2, 8
+    psf = np.zeros((S, S, N, N))
+    for s in range(S):
+        psf[s, s, 0, 0] = 1.0
+    y = _rng(18).standard_normal((S, N, N))
+    lam, beta, rho = 0.3, 1.0, 0.7
+    alg = admm.AnalysisADMM(psf, "dct2d", lam, rho, beta, tier="freq")
+    x, _, _ = alg.run(y, 400)
+    T = priors.DCT2D(S, N, N)
+    ref = T.Tt(priors.soft(T.T(y), lam / beta))
+    assert np.allclose(x, ref, atol=1e-9)
+
+
+def _qp_reference(y, psf, lam, beta, S, N):
+    """min beta/2 ||y - H C^T c||^2 + lambda ||c||_1 as a bound-constrained
+    smooth problem in (p, q >= 0), c = p - q, solved by L-BFGS-B."""
+    H = model.dense_H(psf)
+    C = priors.dct_matrix(N)
+    Cst = np.kron(np.eye(S), np.kron(C, C))     # x = Cst^T c
+    A = H @ Cst.T
+    b = y.ravel()
+    n = A.shape[1]
+
+    def f(pq):
+        c = pq[:n] - pq[n:]
+        r = A @ c - b
+        g = beta * (A.T @ r)
+        val = 0.5 * beta * r @ r + lam * np.sum(pq)
+        return val, np.concatenate([g + lam, -g + lam])
+
+    res = scipy.optimize.minimize(f, np.zeros(2 * n), jac=True, method="L-BFGS-B",
+                                  bounds=[(0, None)] * (2 * n),
+                                  options=dict(maxiter=20000, ftol=1e-16, gtol=1e-12,
+                                               maxcor=50))
+    c = res.x[:n] - res.x[n:]
+    return (Cst.T @ c).reshape(S, N, N), res.fun
+
+
+def test_dct_admm_matches_bruteforce_qp():
+    """Algorithm 1 (DCT-l1) converges to the minimiser found by a generic
+    bound-constrained optimiser."""
+    S, N = 2, 6
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=4)
+    y = model.forward(x0, psf) + 0.02 * _rng(19).standard_normal((2, N, N))
+    lam, beta, rho = 0.02, 1.0, 0.2
+    alg = admm.AnalysisADMM(psf, "dct2d", lam, rho, beta, tier="dense")
+    x, t, u = alg.run(y, 3000)
+    xr, fr = _qp_reference(y, psf, lam, beta, S, N)
+    f = admm.analysis_objective(x, y, psf, alg.T, lam, beta)
+    assert f <= fr + 1e-9 * abs(fr)
+    assert np.allclose(x, xr, atol=2e-5)
+
+
+@pytest.mark.parametrize("kind", ["dct2d", "tv2d", "tv3d"])
+def test_admm_kkt_vanishes(kind):
+    """At convergence the KKT residuals of the split problem vanish and the
+    running minimum of the objective is non-increasing."""
+    S, N = 2, 8
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=5)
+    y = model.forward(x0, psf) + 0.01 * _rng(20).standard_normal((2, N, N))
+    alg = admm.AnalysisADMM(psf, kind, lam=0.01, rho=0.1, beta=1.0, tier="dense")
+    fs = []
+    alg_cb = lambda it, x, t, u: fs.append(
+        admm.analysis_objective(x, y, psf, alg.T, alg.lam, alg.beta))
+    x, t, u = alg.run(y, 4000, callback=alg_cb)
+    r1, r2, r3 = alg.kkt(y, x, t, u)
+    assert max(r1, r2, r3) < 1e-9
+    assert fs[-1] < fs[0]
+    run_min = np.minimum.accumulate(fs)
+    assert np.all(np.diff(run_min) <= 0)
+
+
+def test_admm_lambda_zero_gives_least_squares():
+    """With lambda = 0 the fixed point is the (minimum-norm) least-squares
+    solution (beta H^T H)^+ beta H^T y."""
+    S, N = 2, 6
+    rng = _rng(6)
+    psf = synth.gaussian_psfs(rng, 3, S, N, N, sigma_range=(0.3, 0.7))
+    x0 = rng.uniform(0, 1, (S, N, N))
+    y = model.forward(x0, psf) + 0.01 * _rng(21).standard_normal((3, N, N))
+    alg = admm.AnalysisADMM(psf, "dct2d", lam=0.0, rho=0.05, beta=1.0, tier="dense")
+    x, _, _ = alg.run(y, 3000)
+    H = model.dense_H(psf)
+    ref = np.linalg.pinv(H.T @ H, rcond=1e-13, hermitian=True) @ (H.T @ y.ravel())
+    assert np.allclose(x.ravel(), ref, atol=1e-7)
+
+
+def test_dense_and_freq_tiers_agree_over_iterations():
+    """Tier D and tier F implement the same iteration (TV2D, singular DC)."""
+    x0, psf = _small_problem(K=2, S=2, N1=16, N2=16, seed=7)
+    y = model.forward(x0, psf) + 0.01 * _rng(22).standard_normal((2, 16, 16))
+    a = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="dense").run(y, 30)[0]
+    b = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq").run(y, 30)[0]
+    assert admm.rel_l2(b, a) < 1e-10
+
+
+# ------------------------------------------------------------------ Algorithm 2
+def test_patch_z_update_is_subproblem_minimiser():
+    """Eq. solz_patch2 minimises Eq. iterd_ADMM2 for the patch prior: the
+    gradient D^T (D z - P x) + rho (z - t + u) vanishes."""
+    S, N = 2, 8
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=8)
+    D = synth.random_unit_atoms(_rng(23), 4 * 4 * S, 40)
+    alg = admm.PatchADMM(psf, D, Q=4, stride=2, lam=1e-3, rho=0.3, beta=10.0)
+    t = _rng(24).standard_normal((40, alg.P.J))
+    u = _rng(25).standard_normal((40, alg.P.J))
+    z = alg.z_update(x0, t, u)
+    g = D.T @ (D @ z - alg.P.extract(x0)) + 0.3 * (z - t + u)
+    assert np.max(np.abs(g)) < 1e-10
+
+
+def test_patch_x_update_is_subproblem_minimiser():
+    """Eq. solx_synt minimises Eq. iterd_ADMM1 (squared norms): gradient
+    beta H^T (Hx - y) + P^T (P x - D z) vanishes."""
+    S, N = 2, 8
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=9)
+    D = synth.random_unit_atoms(_rng(26), 4 * 4 * S, 40)
+    y = model.forward(x0, psf)
+    for tier in ("dense", "freq"):
+        alg = admm.PatchADMM(psf, D, Q=4, stride=2, lam=1e-3, rho=0.3, beta=10.0, tier=tier)
+        z = _rng(27).standard_normal((40, alg.P.J))
+        x = alg.x_update(alg.solver.data_term(y), z)
+        g = 10.0 * model.adjoint(model.forward(x, psf) - y, psf) \
+            + alg.P.adjoint(alg.P.extract(x) - D @ z)
+        assert np.max(np.abs(g)) < 1e-9
+
+
+def test_patch_admm_kkt():
+    """Algorithm 2 (patch prior) approaches a KKT point of the synthesis problem:
+    z = t, stationarity in x and z, and the prox fixed point. (ADMM converges
+    sublinearly here; the residuals are checked at a level where a dropped or
+    mis-signed term would show as an O(1) residual.)"""
+    S, N = 2, 8
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=10)
+    y = model.forward(x0, psf) + 0.01 * _rng(28).standard_normal((2, N, N))
+    D = synth.random_unit_atoms(_rng(29), 4 * 4 * S, 32)
+    lam, rho, beta = 1e-2, 1.0, 5.0
+    alg = admm.PatchADMM(psf, D, Q=4, stride=2, lam=lam, rho=rho, beta=beta)
+    x, z, t, u = alg.run(y, 3000)
+    assert np.linalg.norm(z - t) < 1e-6 * np.linalg.norm(z)
+    scale = np.max(np.abs(beta * model.adjoint(y, psf)))
+    gx = beta * model.adjoint(model.forward(x, psf) - y, psf) \
+        + alg.P.adjoint(alg.P.extract(x) - D @ z)
+    assert np.max(np.abs(gx)) < 1e-5 * scale
+    gz = D.T @ (D @ z - alg.P.extract(x)) + rho * u
+    assert np.max(np.abs(gz)) < 5e-5 * np.max(np.abs(D.T @ alg.P.extract(x)))
+    assert np.linalg.norm(t - priors.soft(t + u, lam / rho)) < 1e-6 * np.linalg.norm(t)
+
+
+def test_sherman_morrison_equals_dense_solve():
+    """Eq. solz_DFT_SM equals a dense solve of (rho I + Theta^H Theta) v = c."""
+    rng = _rng(30)
+    M = 7
+    theta = rng.standard_normal((M, 5)) + 1j * rng.standard_normal((M, 5))
+    c = rng.standard_normal((M, 5)) + 1j * rng.standard_normal((M, 5))
+    for rho in (1e-4, 0.3, 10.0):
+        v = admm.sherman_morrison(theta, c, rho)
+        for f in range(5):
+            a = np.conj(theta[:, f])
+            A = rho * np.eye(M) + np.outer(a, np.conj(a))
+            assert np.allclose(v[:, f], np.linalg.solve(A, c[:, f]), rtol=1e-9, atol=1e-12)
+
+
+def test_conv_z_update_is_subproblem_minimiser():
+    """Eq. solz / solz_DFT: the gradient D~^T (D~ z - x) + rho (z - t + u)
+    vanishes (checked with the spatial-domain dictionary operators)."""
+    S, N, M = 2, 12, 3
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=11)
+    filt = synth.random_unit_filters(_rng(31), M, 5)
+    alg = admm.ConvADMM(psf, filt, lam=1e-3, rho=0.2, beta=5.0, tier="freq")
+    t = _rng(32).standard_normal((M, S, N, N))
+    u = _rng(33).standard_normal((M, S, N, N))
+    z = alg.z_update(x0, t, u)
+    g = alg.cd.analysis(alg.cd.synth(z) - x0) + 0.2 * (z - t + u)
+    assert np.max(np.abs(g)) < 1e-10
+
+
+def test_conv_admm_tiers_agree_and_converge():
+    """Algorithm 2 (conv prior): the spatial (dense) and frequency tiers run
+    the same iteration, and the iteration reaches z = t."""
+    S, N, M = 2, 8, 3
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=12)
+    y = model.forward(x0, psf) + 0.01 * _rng(34).standard_normal((2, N, N))
+    filt = synth.random_unit_filters(_rng(35), M, 3)
+    a = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="dense").run(y, 20)
+    b = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq").run(y, 20)
+    assert admm.rel_l2(b[0], a[0]) < 1e-10
+    x, z, t, u = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq").run(y, 2000)
+    assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
