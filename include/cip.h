@@ -1,0 +1,131 @@
+/*
+ * cip.h -- C ABI of the MI355X (gfx950) library for ADMM reconstruction of
+ * convolutional inverse problems in multidimensional imaging
+ * (Dogan & Oktem, arXiv 2006.08303).
+ *
+ * Problem (Section II, Eq. forward model): K measurements of S unknown planes,
+ *     y_k = sum_{s=1..S} h_{k,s} * x_s + w_k,      k = 1..K,
+ * with circular 2D convolutions on an N1 x N2 grid. The library solves the
+ * regularised least-squares problem of Section III (Eq. rls),
+ *     min_x  beta/2 ||y - H x||^2 + R(x),
+ * with the ADMM iterations of Section IV (Algorithm 1 for analysis priors,
+ * Algorithm 2 for synthesis priors), every step of which runs as hand-written
+ * HIP kernels on the GPU.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments named d_* are DEVICE pointers (HIP global memory),
+ *     owned by the caller; the library never allocates, frees or retains them
+ *     beyond the call, except the plan workspace (see cip_plan_create).
+ *   - Arrays are float32, C order (row-major), the last index fastest:
+ *       x   : [S][N1][N2]        unknown planes
+ *       y   : [K][N1][N2]        measurements
+ *       psf : [K][S][N1][N2]     blur kernels h_{k,s}, stored unshifted on the
+ *                                torus: element [k][s][0][0] is the tap at zero
+ *                                offset, [k][s][N1-1][0] the tap at offset -1.
+ *   - `stream` is a hipStream_t (NULL = default stream). Every call enqueues
+ *     work on that stream and returns without waiting for it, except
+ *     cip_plan_create, which waits for its own precompute to finish.
+ *   - Return value: CIP_OK (0) on success or a negative CIP_E* code; the
+ *     message of the last failure on the calling thread is available from
+ *     cip_last_error(). A failed call leaves the plan usable.
+ *   - Supported grids: N1 and N2 powers of two with 16 <= N <= 2048; N1 must
+ *     also be a multiple of 8 (the row tile). 1 <= K, S <= 8.
+ */
+#ifndef CIP_H_
+#define CIP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CIP_OK = 0,
+  CIP_EINVAL = -1,        /* bad argument (null pointer, size out of range)  */
+  CIP_EUNSUPPORTED = -2,  /* valid request this build cannot serve (grid size,
+                             prior kind)                                       */
+  CIP_ENOSPC = -3,        /* workspace smaller than cip_plan_workspace_bytes */
+  CIP_EHIP = -4,          /* a HIP runtime call failed                        */
+};
+
+/* Priors (Section III). */
+typedef enum {
+  /* Analysis prior R(x) = lambda ||T x||_1 (Eq. analysis), T = circular forward
+   * differences along both image axes of every plane (anisotropic TV). */
+  CIP_PRIOR_TV2D = 0,
+  /* As TV2D plus a forward difference along the plane (band) axis, without
+   * wrap-around (3D correlations, Section III-A). */
+  CIP_PRIOR_TV3D = 1,
+  /* Analysis prior with T = orthonormal 2D DCT-II of every plane. */
+  CIP_PRIOR_DCT2D = 2,
+} cip_prior_kind;
+
+typedef struct {
+  int kind;       /* cip_prior_kind                                          */
+  double beta;    /* data-fidelity weight beta of Eq. rls (> 0)              */
+} cip_prior_desc;
+
+typedef struct cip_plan_s* cip_plan_t;
+
+/* Bytes of device workspace a plan of this shape needs (Algorithm 1/2, step 2
+ * tables, solver state and staging). Returns CIP_EUNSUPPORTED for grids or
+ * priors this build does not serve. No GPU work. */
+int cip_plan_workspace_bytes(int K, int S, int N1, int N2, const cip_prior_desc* prior,
+                             size_t* bytes);
+
+/* Create a plan: uploads twiddle tables, transforms the kernels (FP64 FFTs)
+ * and computes, at every 2D frequency w, the FP64 pseudo-inverse of
+ *     Psi(w) = rho tau(w) I + beta Lambda(w)^H Lambda(w)
+ * (Alg. 1 step 2; below Eq. solx_Trans_DFT; tau = 1 for a unitary T, the
+ * Laplacian symbol for TV; TV3D adds rho times the band path-graph Laplacian).
+ * Eigenvalues below 1e-12 times the largest one at that frequency are treated
+ * as zero (minimum-norm x-update where Psi is singular, e.g. the DC block with
+ * unit-sum kernels and TV). Results are stored in FP32 in the workspace.
+ *   d_psf      : [K][S][N1][N2] float32 device array, read during the call only.
+ *   rho, lambda: ADMM penalty (> 0) and regularisation weight (>= 0); the
+ *                soft threshold is lambda / rho (Eq. solt_trans).
+ *   d_workspace: device buffer of at least cip_plan_workspace_bytes bytes,
+ *                256-byte aligned, owned by the caller, kept by the plan until
+ *                cip_plan_destroy and not touched by the caller meanwhile.
+ * Blocks until the precompute on `stream` has finished. */
+int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf,
+                    const cip_prior_desc* prior, double rho, double lambda,
+                    void* d_workspace, size_t ws_bytes, void* stream, cip_plan_t* out);
+
+/* y = H x (Eq. forward model without noise): d_x [S][N1][N2] -> d_y [K][N1][N2].
+ * FP32 FFTs; d_x and d_y must not overlap. */
+int cip_forward(cip_plan_t plan, const float* d_x, float* d_y, void* stream);
+
+/* x = H^T y (x_s = sum_k h_{k,s} correlated with y_k): d_y [K][N1][N2] ->
+ * d_x [S][N1][N2]. FP32 FFTs; must not overlap. */
+int cip_adjoint(cip_plan_t plan, const float* d_y, float* d_x, void* stream);
+
+/* Run `iters` >= 1 ADMM iterations (Algorithm 1) from t = u = 0 on the
+ * measurements d_y [K][N1][N2] and write x^iters to d_x [S][N1][N2].
+ * Per iteration: x-update in the frequency domain (Eq. solx_Trans_DFT),
+ * soft thresholding (Eq. solt_trans) and dual update (Eq. subu_trans).
+ * A plan runs one solve at a time (its state lives in the workspace). */
+int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* stream);
+
+/* Release the host-side plan object (the workspace stays the caller's). */
+int cip_plan_destroy(cip_plan_t plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cip_last_error(void);
+
+/* ---- instrumentation ------------------------------------------------------
+ * Average device time, in microseconds, of `reps` back-to-back launches of
+ * one kernel of the solver on `stream`, measured with HIP events recorded on
+ * that stream. The plan must have run cip_solve at least once (the kernels
+ * then operate on its current state). which: 0 = fused row pass of one ADMM
+ * iteration, 1 = fused column pass (FFTs + per-frequency solve). Blocks until
+ * the timed launches finish. */
+int cip_time_kernel(cip_plan_t plan, int which, int reps, void* stream, double* avg_us);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CIP_H_ */

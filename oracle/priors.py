@@ -58,10 +58,10 @@ class DCT2D:
         self.shape = (1, S, N1, N2)
 
     def T(self, x):
-        return np.einsum("ab,sbc,dc->sad", self.C1, x, self.C2)[None]
+        return (self.C1 @ x @ self.C2.T)[None]
 
     def Tt(self, w):
-        return np.einsum("ba,sbc,cd->sad", self.C1, w[0], self.C2)
+        return self.C1.T @ w[0] @ self.C2
 
     def gram_symbol(self, N1, N2):
         """T^H T = I: the per-frequency symbol is 1."""

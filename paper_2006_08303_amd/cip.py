@@ -1,0 +1,137 @@
+"""ctypes binding of the C ABI in include/cip.h.
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library. Device memory and streams come from PyTorch (ROCm build); the
+library is loaded from this package directory and a missing library is an
+error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcip.so")
+
+CIP_PRIOR_TV2D = 0
+CIP_PRIOR_TV3D = 1
+CIP_PRIOR_DCT2D = 2
+PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D}
+
+
+class CipError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cip error {code}: {msg}")
+        self.code = code
+
+
+class _PriorDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("beta", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.cip_plan_workspace_bytes.argtypes = [i, i, i, i, ctypes.POINTER(_PriorDesc),
+                                               ctypes.POINTER(sz)]
+        L.cip_plan_create.argtypes = [i, i, i, i, vp, ctypes.POINTER(_PriorDesc), d, d, vp, sz,
+                                      vp, ctypes.POINTER(vp)]
+        L.cip_forward.argtypes = [vp, vp, vp, vp]
+        L.cip_adjoint.argtypes = [vp, vp, vp, vp]
+        L.cip_solve.argtypes = [vp, vp, i, vp, vp]
+        L.cip_plan_destroy.argtypes = [vp]
+        L.cip_last_error.restype = ctypes.c_char_p
+        L.cip_time_kernel.argtypes = [vp, i, i, vp, ctypes.POINTER(d)]
+        for name in ("cip_plan_workspace_bytes", "cip_plan_create", "cip_forward", "cip_adjoint",
+                     "cip_solve", "cip_plan_destroy", "cip_time_kernel"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise CipError(rc, lib().cip_last_error().decode())
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, shape, name):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0):
+    desc = _PriorDesc(PRIORS[prior], float(beta))
+    n = ctypes.c_size_t()
+    _check(lib().cip_plan_workspace_bytes(K, S, N1, N2, ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+class Plan:
+    """One problem shape and operator: y_k = sum_s h_{k,s} * x_s.
+
+    psf: float32 CUDA tensor [K, S, N1, N2] (unshifted kernels, origin at [0, 0])."""
+
+    def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, stream=None):
+        K, S, N1, N2 = psf.shape
+        self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
+        self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
+        desc = _PriorDesc(PRIORS[prior], float(beta))
+        nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
+        h = ctypes.c_void_p()
+        _check(lib().cip_plan_create(self.K, self.S, self.N1, self.N2,
+                                     _dev_f32(psf, (K, S, N1, N2), "psf"), ctypes.byref(desc),
+                                     self.rho, self.lam, ctypes.c_void_p(self.workspace.data_ptr()),
+                                     nbytes, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def forward(self, x, out=None, stream=None):
+        y = out if out is not None else torch.empty((self.K, self.N1, self.N2),
+                                                    dtype=torch.float32, device=x.device)
+        _check(lib().cip_forward(self._h, _dev_f32(x, (self.S, self.N1, self.N2), "x"),
+                                 _dev_f32(y, (self.K, self.N1, self.N2), "y"), _stream_ptr(stream)))
+        return y
+
+    def adjoint(self, y, out=None, stream=None):
+        x = out if out is not None else torch.empty((self.S, self.N1, self.N2),
+                                                    dtype=torch.float32, device=y.device)
+        _check(lib().cip_adjoint(self._h, _dev_f32(y, (self.K, self.N1, self.N2), "y"),
+                                 _dev_f32(x, (self.S, self.N1, self.N2), "x"), _stream_ptr(stream)))
+        return x
+
+    def solve(self, y, iters, out=None, stream=None):
+        x = out if out is not None else torch.empty((self.S, self.N1, self.N2),
+                                                    dtype=torch.float32, device=y.device)
+        _check(lib().cip_solve(self._h, _dev_f32(y, (self.K, self.N1, self.N2), "y"), int(iters),
+                               _dev_f32(x, (self.S, self.N1, self.N2), "x"), _stream_ptr(stream)))
+        return x
+
+    def time_kernel(self, which, reps, stream=None):
+        us = ctypes.c_double()
+        _check(lib().cip_time_kernel(self._h, int(which), int(reps), _stream_ptr(stream),
+                                     ctypes.byref(us)))
+        return us.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cip_plan_destroy(h)
+            self._h = None

@@ -1,0 +1,289 @@
+// LDS-resident Stockham FFT building blocks for gfx950 (wave64).
+//
+// A length-N transform is carried by a group of T = N / PPT threads; thread t
+// holds PPT complex values in registers. On entry and on exit of `fft_group`,
+// register slot q of thread t holds element t + T*q (input x, output X), so
+// global loads and stores in that order are coalesced. The first radix is
+// PPT (taken straight from registers), middle stages exchange through LDS
+// (real and imaginary parts in separate padded float arrays to avoid bank
+// conflicts), and a last, smaller radix finishes lengths that are not a power
+// of PPT. Twiddles come from a per-length table W_N^m = exp(-2 pi i m / N)
+// computed on the host in double precision.
+//
+// The in-register DFT kernels use compile-time twiddles (constexpr cos/sin).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cip {
+
+template <typename R> struct cx { R x, y; };
+template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename R> __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename R> __device__ __forceinline__ cx<R> conjx(cx<R> a) { return {a.x, -a.y}; }
+template <typename R> __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <int DIR, typename R> __device__ __forceinline__ cx<R> mul_mi(cx<R> a) {
+  if constexpr (DIR > 0) return {a.y, -a.x};   // -i * a
+  else return {-a.y, a.x};                     // +i * a
+}
+
+// ---------------------------------------------------------------- constexpr trig
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double cexpr_sin_series(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / double((2 * n) * (2 * n + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cexpr_cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / double((2 * n - 1) * (2 * n));
+    sum += term;
+  }
+  return sum;
+}
+// cos / sin of 2 pi k / n, exact symmetry handling for the common angles
+constexpr double ccos2pi(int k, int n) {
+  k = ((k % n) + n) % n;
+  if (4 * k == n) return 0.0;
+  if (4 * k == 3 * n) return 0.0;
+  if (2 * k == n) return -1.0;
+  if (k == 0) return 1.0;
+  double a = 2.0 * kPi * double(k) / double(n);
+  if (a > kPi) a -= 2.0 * kPi;
+  return cexpr_cos_series(a);
+}
+constexpr double csin2pi(int k, int n) {
+  k = ((k % n) + n) % n;
+  if (k == 0 || 2 * k == n) return 0.0;
+  if (4 * k == n) return 1.0;
+  if (4 * k == 3 * n) return -1.0;
+  double a = 2.0 * kPi * double(k) / double(n);
+  if (a > kPi) a -= 2.0 * kPi;
+  return cexpr_sin_series(a);
+}
+
+// Multiply by W_n^k (DIR = +1: exp(-2 pi i k / n); DIR = -1: conjugate),
+// with trivial angles special-cased at compile time.
+template <int DIR, int K, int NN, typename R>
+__device__ __forceinline__ cx<R> twc(cx<R> a) {
+  constexpr int k = ((K % NN) + NN) % NN;
+  if constexpr (k == 0) return a;
+  else if constexpr (4 * k == NN) return mul_mi<DIR>(a);
+  else if constexpr (2 * k == NN) return {-a.x, -a.y};
+  else if constexpr (4 * k == 3 * NN) return mul_mi<-DIR>(a);
+  else {
+    constexpr double c = ccos2pi(k, NN);
+    constexpr double s = -double(DIR) * csin2pi(k, NN);
+    return {a.x * R(c) - a.y * R(s), a.x * R(s) + a.y * R(c)};
+  }
+}
+
+// ---------------------------------------------------------------- in-register DFTs
+template <int P> struct smallest_factor {
+  static constexpr int value = (P % 4 == 0 && P > 4) ? 4 : (P % 2 == 0 ? 2 : (P % 3 == 0 ? 3 : P));
+};
+
+// 3-point DFT: X1,2 = a - (b + c)/2 -+ DIR * i * sin(pi/3) * (b - c)
+template <int DIR, typename R> __device__ __forceinline__ void dft3(cx<R>& a, cx<R>& b, cx<R>& c) {
+  constexpr double s3 = 0.86602540378443864676372317075294;
+  cx<R> t1 = b + c;
+  cx<R> t2 = {a.x - R(0.5) * t1.x, a.y - R(0.5) * t1.y};
+  cx<R> d = b - c;
+  // t3 = -DIR * i * s3 * d = (DIR * s3 * d.y, -DIR * s3 * d.x)
+  cx<R> t3 = {R(double(DIR) * s3) * d.y, R(-double(DIR) * s3) * d.x};
+  a = a + t1;
+  b = t2 + t3;
+  c = t2 - t3;
+}
+
+template <int K, int M, int F, int MM, int P, int DIR, typename R, int STRIDE>
+__device__ __forceinline__ void static_for_k(cx<R> (&sub)[F][MM], cx<R>* v);
+
+// DFT of length P, in place, natural order in and out (stride-1 array).
+template <int P, int DIR, typename R, int STRIDE = 1>
+__device__ __forceinline__ void dft(cx<R>* v) {
+  if constexpr (P == 1) {
+    return;
+  } else if constexpr (P == 2) {
+    cx<R> a = v[0], b = v[STRIDE];
+    v[0] = a + b;
+    v[STRIDE] = a - b;
+  } else if constexpr (P == 3) {
+    dft3<DIR>(v[0], v[STRIDE], v[2 * STRIDE]);
+  } else if constexpr (P == 4) {
+    cx<R> a = v[0], b = v[STRIDE], c = v[2 * STRIDE], d = v[3 * STRIDE];
+    cx<R> s0 = a + c, s1 = a - c, s2 = b + d, s3 = mul_mi<DIR>(b - d);
+    v[0] = s0 + s2;
+    v[2 * STRIDE] = s0 - s2;
+    v[STRIDE] = s1 + s3;
+    v[3 * STRIDE] = s1 - s3;
+  } else {
+    // decimation in time by factor F: P = F * M
+    constexpr int F = smallest_factor<P>::value;
+    constexpr int M = P / F;
+    cx<R> sub[F][M];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int m = 0; m < M; ++m) sub[f][m] = v[(m * F + f) * STRIDE];
+#pragma unroll
+    for (int f = 0; f < F; ++f) dft<M, DIR, R, 1>(sub[f]);
+    // combine: X[k + M*r] = sum_f W_P^{f (k + M r)} Sub_f[k]
+    //        = sum_f W_F^{f r} (W_P^{f k} Sub_f[k])
+    static_for_k<0, M, F, M, P, DIR, R, STRIDE>(sub, v);
+  }
+}
+
+template <int F, int K, int P, int DIR, typename R, int f = 0>
+__device__ __forceinline__ void twiddle_col_impl(cx<R>* col) {
+  if constexpr (f < F) {
+    col[f] = twc<DIR, f * K, P>(col[f]);
+    twiddle_col_impl<F, K, P, DIR, R, f + 1>(col);
+  }
+}
+
+template <int K, int M, int F, int MM, int P, int DIR, typename R, int STRIDE>
+__device__ __forceinline__ void static_for_k(cx<R> (&sub)[F][MM], cx<R>* v) {
+  if constexpr (K < M) {
+    cx<R> col[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) col[f] = sub[f][K];
+    twiddle_col_impl<F, K, P, DIR, R>(col);
+    dft<F, DIR, R, 1>(col);
+#pragma unroll
+    for (int r = 0; r < F; ++r) v[(K + M * r) * STRIDE] = col[r];
+    static_for_k<K + 1, M, F, MM, P, DIR, R, STRIDE>(sub, v);
+  }
+}
+
+// ---------------------------------------------------------------- LDS layout
+// Padded index: one spare slot every 32 floats breaks power-of-two strides.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
+constexpr int padded_len(int n) { return n + (n >> 5) + 1; }
+
+// ---------------------------------------------------------------- group FFT
+// Stockham radix sequence: PPT, PPT, ..., PPT, LAST with PPT^m * LAST = N.
+template <int N, int PPT> struct fft_shape {
+  static constexpr int T = N / PPT;
+  static constexpr int count_full(int n) { return n % PPT == 0 && n >= PPT ? 1 + count_full(n / PPT) : 0; }
+  static constexpr int pow_ppt(int m) { return m == 0 ? 1 : PPT * pow_ppt(m - 1); }
+  static constexpr int NFULL = count_full(N);
+  static constexpr int LAST = N / pow_ppt(NFULL);   // 1 if N is a power of PPT
+  static_assert(N % PPT == 0, "N must be a multiple of PPT");
+  static_assert(PPT % LAST == 0, "last radix must divide PPT");
+};
+
+// One Stockham stage with radix RS on the LDS array (re, im), for a group of
+// T threads. Ns = product of the radices already applied.
+template <int N, int PPT, int RS, int DIR, typename R>
+__device__ __forceinline__ void stage_lds(R* re, R* im, int t, int Ns, const cx<R>* __restrict__ tw,
+                                          cx<R>* v /* PPT slots, scratch */, bool last) {
+  constexpr int T = N / PPT;
+  constexpr int NB = PPT / RS;            // butterflies per thread
+  constexpr int STR = N / RS;
+  // read
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    int j = t + T * b;
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      int idx = pad(j + r * STR);
+      v[b * RS + r] = cx<R>{re[idx], im[idx]};
+    }
+  }
+  // twiddle + butterfly
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    int j = t + T * b;
+    int k = j % Ns;
+    int step = N / (Ns * RS);
+#pragma unroll
+    for (int r = 1; r < RS; ++r) {
+      cx<R> w = tw[r * k * step];
+      if (DIR < 0) w.y = -w.y;
+      v[b * RS + r] = cmul(v[b * RS + r], w);
+    }
+    dft<RS, DIR, R>(&v[b * RS]);
+  }
+  __syncthreads();
+  if (!last) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      int j = t + T * b;
+      int k = j % Ns;
+      int base = (j / Ns) * Ns * RS + k;
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        int idx = pad(base + r * Ns);
+        re[idx] = v[b * RS + r].x;
+        im[idx] = v[b * RS + r].y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Full transform. In: reg[q] = x[t + T q]. Out: reg[q] = X[t + T q].
+// (re, im) is this group's LDS scratch of padded_len(N) floats each. The
+// caller must make sure no thread still reads (re, im) from a previous use:
+// this routine starts by writing to them only after its first radix, which is
+// preceded by a barrier.
+template <int N, int PPT, int DIR, typename R>
+__device__ __forceinline__ void fft_group(cx<R>* reg, R* re, R* im, int t, const cx<R>* __restrict__ tw) {
+  using S = fft_shape<N, PPT>;
+  constexpr int T = S::T;
+  if constexpr (N == 1) return;
+  // first radix: PPT, straight from registers, Ns = 1 (no twiddles)
+  dft<PPT, DIR, R>(reg);
+  if constexpr (S::NFULL == 1 && S::LAST == 1) {
+    // N == PPT: a single group-local DFT, output slot r = element r
+    return;
+  } else {
+    __syncthreads();
+    // write stage-1 output: j = t, base = j * PPT
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      int idx = pad(t * PPT + r);
+      re[idx] = reg[r].x;
+      im[idx] = reg[r].y;
+    }
+    __syncthreads();
+    int Ns = PPT;
+    // middle full-radix stages
+#pragma unroll
+    for (int s = 1; s < S::NFULL; ++s) {
+      bool last = (s == S::NFULL - 1) && (S::LAST == 1);
+      stage_lds<N, PPT, PPT, DIR, R>(re, im, t, Ns, tw, reg, last);
+      Ns *= PPT;
+    }
+    if constexpr (S::LAST > 1) {
+      stage_lds<N, PPT, S::LAST, DIR, R>(re, im, t, Ns, tw, reg, true);
+      // slot layout after last stage: butterfly b, output r -> element
+      // t + T*(b + r*NB); registers are currently ordered [b][r].
+      constexpr int NB = PPT / S::LAST;
+      cx<R> tmp[PPT];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < S::LAST; ++r) tmp[b + r * NB] = reg[b * S::LAST + r];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) reg[q] = tmp[q];
+    }
+    (void)T;
+  }
+}
+
+}  // namespace cip
