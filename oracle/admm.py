@@ -209,8 +209,8 @@ class ConvADMM:
         if self.tier == "dense":
             return self.cd.synth(z)
         zh = np.fft.fft2(z, axes=(-2, -1))
-        return np.real(np.fft.ifft2(np.einsum("mab,msab->sab", self.theta, zh),
-                                    axes=(-2, -1)))
+        return np.ascontiguousarray(np.real(np.fft.ifft2(
+            np.einsum("mab,msab->sab", self.theta, zh), axes=(-2, -1))))
 
     def x_update(self, data, z):
         extra = self.synth(z)
@@ -225,7 +225,7 @@ class ConvADMM:
         gh = np.fft.fft2(t - u, axes=(-2, -1))                   # (M, S, N1, N2)
         c = np.conj(self.theta)[:, None] * xh[None] + self.rho * gh
         v = sherman_morrison(self.theta[:, None], c, self.rho)
-        return np.real(np.fft.ifft2(v, axes=(-2, -1)))
+        return np.ascontiguousarray(np.real(np.fft.ifft2(v, axes=(-2, -1))))
 
     def run(self, y, iters, callback=None):
         data = self.solver.data_term(y)

@@ -121,7 +121,7 @@ class FreqSolver:
         """x = F^-1 Psi^+ (bhat + F extra_spatial); ``extra_spatial`` is
         rho T^H (t - u) (analysis) or P^H D~ z (synthesis)."""
         rhs = bhat + np.fft.fft2(extra_spatial, axes=(-2, -1))
-        return np.real(np.fft.ifft2(self.solve_hat(rhs), axes=(-2, -1)))
+        return np.ascontiguousarray(np.real(np.fft.ifft2(self.solve_hat(rhs), axes=(-2, -1))))
 
 
 # ---------------------------------------------------------------- dense tier

@@ -1,33 +1,64 @@
-"""Compile the HIP library for gfx950 (hipcc, in-tree)."""
+"""Compile the HIP library for gfx950 (hipcc, in-tree).
+
+Translation units: csrc/cip.hip (C ABI, plan, operators, row passes) and one
+csrc/col_pass.hip instance per supported column length. They are compiled in
+parallel and linked into paper_2006_08303_amd/libcip.so.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcip.so")
-SOURCES = [os.path.join(HERE, "csrc", "cip.hip")]
+CSRC = os.path.join(HERE, "csrc")
+SIZES = (16, 32, 64, 128, 256, 512, 1024, 2048)
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), *SOURCES, "-o", tmp]
+    extra = [f"-D{d}" for d in defines]
+    tmpdir = tempfile.mkdtemp(prefix="cipbuild_")
+    jobs = [(os.path.join(CSRC, "cip.hip"), os.path.join(tmpdir, "cip.o"), [])]
+    for n in SIZES:
+        jobs.append((os.path.join(CSRC, "col_pass.hip"), os.path.join(tmpdir, f"col_{n}.o"),
+                     [f"-DCIP_COL_N={n}"]))
+    procs = []
+    for src, obj, d in jobs:
+        cmd = [hipcc, *FLAGS, *extra, *d, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                            text=True)))
+    failed = False
+    for cmd, p in procs:
+        outp, _ = p.communicate()
+        if p.returncode != 0:
+            failed = True
+            sys.stderr.write(outp)
+    if failed:
+        raise RuntimeError("hipcc failed compiling libcip")
+    tmp = out + ".tmp"
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for _, o, _ in jobs], "-o", tmp]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
+        print(" ".join(link), flush=True)
+    r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libcip.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("hipcc failed linking libcip.so")
+    os.replace(tmp, out)
+    for _, o, _ in jobs:
+        os.remove(o)
+    os.rmdir(tmpdir)
+    return out
 
 
 if __name__ == "__main__":

@@ -13,7 +13,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcip.so")
+LIB_PATH = os.environ.get("CIP_LIBRARY_PATH") or os.path.join(_HERE, "libcip.so")
 
 CIP_PRIOR_TV2D = 0
 CIP_PRIOR_TV3D = 1

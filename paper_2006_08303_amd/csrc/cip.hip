@@ -12,9 +12,19 @@
 
 #include "cip.h"
 #include "gram.hpp"
+#include "col_pass.hpp"
 #include "kernels.hpp"
+#include "launch.hpp"
 
 using namespace cip;
+
+namespace cip {
+// Exact float -> double promotion of one plane (plan time).
+__global__ void k_promote(const float* __restrict__ src, double* __restrict__ dst, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+}  // namespace cip
 
 namespace {
 
@@ -39,7 +49,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // Workspace carve-up. Every field is a byte offset into the caller's buffer.
 struct Layout {
   size_t twN1f, twN2f, twN1d, twN2d;  // FFT twiddles
-  size_t fw1, iv1, ia1, fw2, iv2, ia2;  // DCT tables (N1 and N2)
+  size_t ew1, ew2;                      // DCT tables exp(-i pi k / 2N) (N1 and N2)
   size_t lam32, Adiag, Aoff, Mm, xh0;   // per-frequency tables
   size_t bufA, bufB;                    // RT staging (max(K,S) planes)
   size_t state;                         // ADMM state
@@ -69,12 +79,8 @@ Layout make_layout(int K, int S, int N1, int N2, int kind) {
   L.twN2f = take(N2 * 8);
   L.twN1d = take(N1 * 16);
   L.twN2d = take(N2 * 16);
-  L.fw1 = take(N1 * 8);
-  L.iv1 = take(N1 * 8);
-  L.ia1 = take(N1 * 4);
-  L.fw2 = take(N2 * 8);
-  L.iv2 = take(N2 * 8);
-  L.ia2 = take(N2 * 4);
+  L.ew1 = take(N1 * 8);
+  L.ew2 = take(N2 * 8);
   L.lam32 = take((size_t)K * S * F * 8);
   L.Adiag = take((size_t)S * F * 4);
   L.Aoff = take((size_t)(S * (S - 1) / 2) * F * 8 + 8);
@@ -117,41 +123,28 @@ struct cip_plan_s {
 // ---------------------------------------------------------------- launch helpers
 namespace {
 
-template <typename KernelT, typename... Args>
-hipError_t launch(KernelT kern, int grid, int block, size_t lds, hipStream_t st, Args... args) {
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, args...);
-  return hipGetLastError();
-}
 
-constexpr int ppt_rt(int N) { return N >= 16 ? 16 : N; }
 
-#define DISPATCH_N(N, CALL)                                   \
-  switch (N) {                                                \
-    case 16: { constexpr int NN = 16; CALL; } break;          \
-    case 32: { constexpr int NN = 32; CALL; } break;          \
-    case 64: { constexpr int NN = 64; CALL; } break;          \
-    case 128: { constexpr int NN = 128; CALL; } break;        \
-    case 256: { constexpr int NN = 256; CALL; } break;        \
-    case 512: { constexpr int NN = 512; CALL; } break;        \
-    case 1024: { constexpr int NN = 1024; CALL; } break;      \
-    case 2048: { constexpr int NN = 2048; CALL; } break;      \
-    default: return hipErrorInvalidValue;                     \
+#define DISPATCH_N(N, ...)                                           \
+  switch (N) {                                                       \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;          \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;          \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;          \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;        \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;        \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;        \
+    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;      \
+    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;      \
+    default: return hipErrorInvalidValue;                            \
   }
 
 template <typename Re>
 hipError_t row_r2c(const Re* in, cx<Re>* out, int P, int N1, int N2, const cx<Re>* tw, hipStream_t st) {
   constexpr bool staged = sizeof(Re) == 4;
   DISPATCH_N(N2, {
-    const int T = NN / ppt_rt(NN);
+    const int T = NN / ppt_row<NN>();
     const int ng = staged ? PAIRS : 1;
-    size_t fft_l = (size_t)ng * 2 * padded_len(NN) * sizeof(Re);
-    size_t stg_l = staged ? (size_t)(NN / 2 + 1) * RT * 2 * sizeof(Re) : 0;
-    size_t lds = fft_l > stg_l ? fft_l : stg_l;
+    size_t lds = (size_t)(2 * NN + row_work_floats<NN, Re>(ng, staged)) * sizeof(Re);
     int grid = staged ? P * (N1 / RT) : P * (N1 / 2);
     return launch(k_row_r2c<NN, Re, staged>, grid, ng * T, lds, st, in, out, N1, tw);
   });
@@ -161,10 +154,8 @@ hipError_t row_r2c(const Re* in, cx<Re>* out, int P, int N1, int N2, const cx<Re
 hipError_t row_c2r(const cx<float>* in, float* out, int P, int N1, int N2, float scale,
                    const cx<float>* tw, hipStream_t st) {
   DISPATCH_N(N2, {
-    const int T = NN / ppt_rt(NN);
-    size_t fft_l = (size_t)PAIRS * 2 * padded_len(NN) * 4;
-    size_t stg_l = (size_t)(NN / 2 + 1) * RT * 2 * 4;
-    size_t lds = fft_l > stg_l ? fft_l : stg_l;
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
     return launch(k_row_c2r<NN>, P * (N1 / RT), PAIRS * T, lds, st, in, out, N1, scale, tw);
   });
   return hipSuccess;
@@ -175,8 +166,8 @@ hipError_t col_op(const cx<Re>* in, void* out, int Pin, int Pout, int N1, int H2
                   const cx<Re>* tw, const cx<Re>* mat, int spec_plane, hipStream_t st) {
   const int PM = Pin > Pout ? Pin : Pout;
   DISPATCH_N(N1, {
-    const int T = NN / ppt_rt(NN);
-    size_t lds = (size_t)PM * 2 * padded_len(NN) * sizeof(Re);
+    const int T = NN / ppt_col<NN>();
+    size_t lds = (size_t)(2 * NN + PM * 2 * padded_len(NN)) * sizeof(Re);
     return launch(k_col_op<NN, Re, OP>, H2, PM * T, lds, st, in, out, Pin, Pout, H2, tw, mat,
                   spec_plane);
   });
@@ -187,14 +178,12 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
   const Layout& L = p->L;
   float kappa = (float)(p->lambda / p->rho);
   DISPATCH_N(p->N2, {
-    const int T = NN / ppt_rt(NN);
-    size_t fft_l = (size_t)PAIRS * 2 * padded_len(NN) * 4;
-    size_t stg_l = (size_t)(NN / 2 + 1) * RT * 2 * 4;
-    size_t lds = fft_l > stg_l ? fft_l : stg_l;
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(4 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
     return launch(k_admm_row_dct<NN>, p->S * (p->N1 / RT), PAIRS * T, lds, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), p->at<float>(L.state),
-                  p->N1, p->at<const cx<float>>(L.twN2f), p->at<const cx<float>>(L.fw2),
-                  p->at<const cx<float>>(L.iv2), p->at<const float>(L.ia2), kappa, mode, xout);
+                  p->N1, p->at<const cx<float>>(L.twN2f), p->at<const cx<float>>(L.ew2), kappa,
+                  mode, xout);
   });
   return hipSuccess;
 }
@@ -202,19 +191,25 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
 hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
   const Layout& L = p->L;
   const bool dct = p->kind == CIP_PRIOR_DCT2D;
-  DISPATCH_N(p->N1, {
-    const int T = NN / ppt_rt(NN);
-    size_t lds = (size_t)p->S * 2 * padded_len(NN) * 4;
-    auto args = [&](auto kern) {
-      return launch(kern, p->H2, p->S * T, lds, st, p->at<const cx<float>>(L.bufA),
-                    p->at<cx<float>>(L.bufB), p->S, p->H2, p->at<const float>(L.Adiag),
-                    p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.xh0),
-                    p->at<const cx<float>>(L.twN1f), p->at<const cx<float>>(L.fw1),
-                    p->at<const cx<float>>(L.iv1), p->at<const float>(L.ia1), zero_in, dct_out);
-    };
-    return dct ? args(k_admm_col<NN, true>) : args(k_admm_col<NN, false>);
-  });
-  return hipSuccess;
+#define CIP_COL_CASE(NN)                                                                        \
+  case NN:                                                                                      \
+    return admm_col_launch_##NN(p->S, dct, p->at<const cx<float>>(L.bufA),                      \
+                                p->at<cx<float>>(L.bufB), p->H2, p->at<const float>(L.Adiag),    \
+                                p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.xh0),   \
+                                p->at<const cx<float>>(L.twN1f), p->at<const cx<float>>(L.ew1),  \
+                                zero_in, dct_out, st);
+  switch (p->N1) {
+    CIP_COL_CASE(16)
+    CIP_COL_CASE(32)
+    CIP_COL_CASE(64)
+    CIP_COL_CASE(128)
+    CIP_COL_CASE(256)
+    CIP_COL_CASE(512)
+    CIP_COL_CASE(1024)
+    CIP_COL_CASE(2048)
+  }
+#undef CIP_COL_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t gram(cip_plan_t p, hipStream_t st) {
@@ -252,26 +247,45 @@ hipError_t gram(cip_plan_t p, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-void twiddles(int N, std::vector<cx<float>>& f, std::vector<cx<double>>& d) {
-  f.resize(N);
-  d.resize(N);
-  for (int m = 0; m < N; ++m) {
-    double a = 2.0 * M_PI * (double)m / (double)N;
-    d[m] = cx<double>{std::cos(a), -std::sin(a)};
-    f[m] = cx<float>{(float)d[m].x, (float)d[m].y};
+// Stage twiddle table of a length-N group FFT with PPT points per thread,
+// in the order the device stages read it (see fft_shape): for every stage
+// after the first, [k < Ns][r = 1 .. RS-1] -> W_{Ns RS}^{r k}, computed in
+// double precision. Padded with zeros to N entries.
+void stage_twiddles(int N, int PPT, std::vector<cx<double>>& d) {
+  d.assign(N, cx<double>{0.0, 0.0});
+  int nfull = 0, n = N;
+  while (n % PPT == 0 && n >= PPT) {
+    n /= PPT;
+    ++nfull;
   }
+  const int last = n;
+  int off = 0, ns = PPT;
+  auto put = [&](int ns_, int rs) {
+    for (int k = 0; k < ns_; ++k)
+      for (int r = 1; r < rs; ++r) {
+        double a = 2.0 * M_PI * (double)r * (double)k / ((double)ns_ * rs);
+        d[off + k * (rs - 1) + r - 1] = cx<double>{std::cos(a), -std::sin(a)};
+      }
+    off += ns_ * (rs - 1);
+  };
+  for (int s = 1; s < nfull; ++s) {
+    put(ns, PPT);
+    ns *= PPT;
+  }
+  if (last > 1) put(ns, last);
 }
 
-void dct_tables(int N, std::vector<cx<float>>& fw, std::vector<cx<float>>& iv, std::vector<float>& ia) {
-  fw.resize(N);
-  iv.resize(N);
-  ia.resize(N);
+void twiddles(int N, int PPT, std::vector<cx<float>>& f, std::vector<cx<double>>& d) {
+  stage_twiddles(N, PPT, d);
+  f.resize(N);
+  for (int m = 0; m < N; ++m) f[m] = cx<float>{(float)d[m].x, (float)d[m].y};
+}
+
+void dct_table(int N, std::vector<cx<float>>& ew) {
+  ew.resize(N);
   for (int k = 0; k < N; ++k) {
-    double al = k == 0 ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
     double a = M_PI * (double)k / (2.0 * N);
-    fw[k] = cx<float>{(float)(al * std::cos(a)), (float)(-al * std::sin(a))};
-    iv[k] = cx<float>{(float)(std::cos(a) / N), (float)(std::sin(a) / N)};
-    ia[k] = (float)(1.0 / al);
+    ew[k] = cx<float>{(float)std::cos(a), (float)(-std::sin(a))};
   }
 }
 
@@ -329,25 +343,20 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
                                               hipGetErrorString(e_));               \
   } while (0)
 
-  std::vector<cx<float>> t1f, t2f, fw, iv;
+  std::vector<cx<float>> t1f, t2f, fw;
   std::vector<cx<double>> t1d, t2d;
-  std::vector<float> ia;
-  twiddles(N1, t1f, t1d);
-  twiddles(N2, t2f, t2d);
+  twiddles(N1, ppt_col_n(N1), t1f, t1d);   // column transforms (length N1)
+  twiddles(N2, ppt_row_n(N2), t2f, t2d);   // row transforms (length N2)
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN1f), t1f.data(), N1 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN2f), t2f.data(), N2 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN1d), t1d.data(), N1 * 16, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN2d), t2d.data(), N2 * 16, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipStreamSynchronize(st));
-  dct_tables(N1, fw, iv, ia);
-  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.fw1), fw.data(), N1 * 8, hipMemcpyHostToDevice, st));
-  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.iv1), iv.data(), N1 * 8, hipMemcpyHostToDevice, st));
-  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.ia1), ia.data(), N1 * 4, hipMemcpyHostToDevice, st));
+  dct_table(N1, fw);
+  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.ew1), fw.data(), N1 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipStreamSynchronize(st));
-  dct_tables(N2, fw, iv, ia);
-  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.fw2), fw.data(), N2 * 8, hipMemcpyHostToDevice, st));
-  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.iv2), iv.data(), N2 * 8, hipMemcpyHostToDevice, st));
-  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.ia2), ia.data(), N2 * 4, hipMemcpyHostToDevice, st));
+  dct_table(N2, fw);
+  PLAN_HIP(hipMemcpyAsync(p->at<void>(L.ew2), fw.data(), N2 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipStreamSynchronize(st));
 
   // FP64 spectra of the K*S kernels: each float plane is promoted exactly to
@@ -446,8 +455,8 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *avg_us = 1000.0 * ms / reps;
   return CIP_OK;
 }

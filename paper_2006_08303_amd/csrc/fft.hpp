@@ -170,119 +170,163 @@ __device__ __forceinline__ void static_for_k(cx<R> (&sub)[F][MM], cx<R>* v) {
 }
 
 // ---------------------------------------------------------------- LDS layout
-// Padded index: one spare slot every 32 floats breaks power-of-two strides.
-__device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
-constexpr int padded_len(int n) { return n + (n >> 5) + 1; }
+// Padded index: one spare slot every 16 floats. Strides that are multiples of
+// 16 stay affine (pad(a + 16 c) = pad(a) + 17 c), so unrolled accesses fold
+// into immediate LDS offsets, and power-of-two strides spread over banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
+
+// Synchronise the threads of one transform group. (A wave-level barrier is
+// not used: with one group per wavefront and several wavefronts per
+// work-group it produced wrong results on gfx950, so groups always use the
+// work-group barrier.)
+template <int T> __device__ __forceinline__ void group_sync() { __syncthreads(); }
 
 // ---------------------------------------------------------------- group FFT
 // Stockham radix sequence: PPT, PPT, ..., PPT, LAST with PPT^m * LAST = N.
+// Twiddles of every stage after the first are stored per stage as
+// [k in 0..Ns)[r in 1..RS) = W_{Ns RS}^{r k} (forward sign), so a thread reads
+// its RS - 1 twiddles at consecutive addresses.
 template <int N, int PPT> struct fft_shape {
   static constexpr int T = N / PPT;
   static constexpr int count_full(int n) { return n % PPT == 0 && n >= PPT ? 1 + count_full(n / PPT) : 0; }
   static constexpr int pow_ppt(int m) { return m == 0 ? 1 : PPT * pow_ppt(m - 1); }
   static constexpr int NFULL = count_full(N);
   static constexpr int LAST = N / pow_ppt(NFULL);   // 1 if N is a power of PPT
+  // offset of the twiddles of middle stage s (1 .. NFULL-1); s = NFULL: last stage
+  static constexpr int stage_off(int s) {
+    int off = 0, ns = PPT;
+    for (int i = 1; i < s; ++i) {
+      off += ns * (PPT - 1);
+      ns *= PPT;
+    }
+    return off;
+  }
+  static constexpr int TW_ENTRIES = stage_off(NFULL) + (LAST > 1 ? pow_ppt(NFULL) * (LAST - 1) : 0);
   static_assert(N % PPT == 0, "N must be a multiple of PPT");
   static_assert(PPT % LAST == 0, "last radix must divide PPT");
 };
 
-// One Stockham stage with radix RS on the LDS array (re, im), for a group of
-// T threads. Ns = product of the radices already applied.
-template <int N, int PPT, int RS, int DIR, typename R>
-__device__ __forceinline__ void stage_lds(R* re, R* im, int t, int Ns, const cx<R>* __restrict__ tw,
-                                          cx<R>* v /* PPT slots, scratch */, bool last) {
+// One Stockham stage with radix RS on the group's LDS array (re, im), after
+// radices with product NS have been applied.
+template <int N, int PPT, int RS, int NS, int TWOFF, int DIR, bool LASTSTAGE, typename R>
+__device__ __forceinline__ void stage_lds(R* re, R* im, int t, const cx<R>* tws, cx<R>* v) {
   constexpr int T = N / PPT;
-  constexpr int NB = PPT / RS;            // butterflies per thread
+  constexpr int NB = PPT / RS;   // butterflies per thread
   constexpr int STR = N / RS;
-  // read
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    int j = t + T * b;
+    const int j = t + T * b;
+    if constexpr (STR % 16 == 0) {
+      const int pj = pad(j);
 #pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      int idx = pad(j + r * STR);
-      v[b * RS + r] = cx<R>{re[idx], im[idx]};
+      for (int r = 0; r < RS; ++r) {
+        const int idx = pj + r * (STR + STR / 16);
+        v[b * RS + r] = cx<R>{re[idx], im[idx]};
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        const int idx = pad(j + r * STR);
+        v[b * RS + r] = cx<R>{re[idx], im[idx]};
+      }
     }
   }
-  // twiddle + butterfly
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    int j = t + T * b;
-    int k = j % Ns;
-    int step = N / (Ns * RS);
+    const int j = t + T * b;
+    const int k = j % NS;
+    const cx<R>* w = tws + TWOFF + k * (RS - 1) - 1;
 #pragma unroll
     for (int r = 1; r < RS; ++r) {
-      cx<R> w = tw[r * k * step];
-      if (DIR < 0) w.y = -w.y;
-      v[b * RS + r] = cmul(v[b * RS + r], w);
+      cx<R> ww = w[r];
+      if (DIR < 0) ww.y = -ww.y;
+      v[b * RS + r] = cmul(v[b * RS + r], ww);
     }
     dft<RS, DIR, R>(&v[b * RS]);
   }
-  __syncthreads();
-  if (!last) {
+  group_sync<T>();
+  if constexpr (!LASTSTAGE) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      int j = t + T * b;
-      int k = j % Ns;
-      int base = (j / Ns) * Ns * RS + k;
+      const int j = t + T * b;
+      const int k = j % NS;
+      const int base = (j / NS) * NS * RS + k;
+      if constexpr (NS % 16 == 0) {
+        const int pb = pad(base);
 #pragma unroll
-      for (int r = 0; r < RS; ++r) {
-        int idx = pad(base + r * Ns);
-        re[idx] = v[b * RS + r].x;
-        im[idx] = v[b * RS + r].y;
+        for (int r = 0; r < RS; ++r) {
+          const int idx = pb + r * (NS + NS / 16);
+          re[idx] = v[b * RS + r].x;
+          im[idx] = v[b * RS + r].y;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+          const int idx = pad(base + r * NS);
+          re[idx] = v[b * RS + r].x;
+          im[idx] = v[b * RS + r].y;
+        }
       }
     }
-    __syncthreads();
+    group_sync<T>();
   }
 }
 
-// Full transform. In: reg[q] = x[t + T q]. Out: reg[q] = X[t + T q].
-// (re, im) is this group's LDS scratch of padded_len(N) floats each. The
-// caller must make sure no thread still reads (re, im) from a previous use:
-// this routine starts by writing to them only after its first radix, which is
-// preceded by a barrier.
+template <int N, int PPT, int DIR, typename R, int S>
+__device__ __forceinline__ void middle_stages(R* re, R* im, int t, const cx<R>* tws, cx<R>* reg) {
+  using SH = fft_shape<N, PPT>;
+  if constexpr (S < SH::NFULL) {
+    constexpr bool last = (S == SH::NFULL - 1) && (SH::LAST == 1);
+    stage_lds<N, PPT, PPT, SH::pow_ppt(S), SH::stage_off(S), DIR, last, R>(re, im, t, tws, reg);
+    middle_stages<N, PPT, DIR, R, S + 1>(re, im, t, tws, reg);
+  }
+}
+
+// Full transform of a group. In: reg[q] = x[t + T q]. Out: reg[q] = X[t + T q].
+// (re, im): this group's LDS scratch of padded_len(N) floats each; tws: the
+// stage twiddle table (LDS). The routine starts with a group barrier before
+// its first LDS write, so callers may still have been reading (re, im).
+// DIR = +1: forward (exp(-2 pi i jk/N)); DIR = -1: inverse, unnormalised.
 template <int N, int PPT, int DIR, typename R>
-__device__ __forceinline__ void fft_group(cx<R>* reg, R* re, R* im, int t, const cx<R>* __restrict__ tw) {
-  using S = fft_shape<N, PPT>;
-  constexpr int T = S::T;
+__device__ __forceinline__ void fft_group(cx<R>* reg, R* re, R* im, int t, const cx<R>* tws) {
+  using SH = fft_shape<N, PPT>;
+  constexpr int T = SH::T;
   if constexpr (N == 1) return;
-  // first radix: PPT, straight from registers, Ns = 1 (no twiddles)
-  dft<PPT, DIR, R>(reg);
-  if constexpr (S::NFULL == 1 && S::LAST == 1) {
-    // N == PPT: a single group-local DFT, output slot r = element r
-    return;
+  dft<PPT, DIR, R>(reg);   // first radix (Ns = 1, no twiddles)
+  if constexpr (SH::NFULL == 1 && SH::LAST == 1) {
+    return;   // N == PPT
   } else {
-    __syncthreads();
-    // write stage-1 output: j = t, base = j * PPT
+    group_sync<T>();
+    if constexpr (PPT <= 16) {
+      const int pb = pad(t * PPT);
 #pragma unroll
-    for (int r = 0; r < PPT; ++r) {
-      int idx = pad(t * PPT + r);
-      re[idx] = reg[r].x;
-      im[idx] = reg[r].y;
-    }
-    __syncthreads();
-    int Ns = PPT;
-    // middle full-radix stages
+      for (int r = 0; r < PPT; ++r) {
+        re[pb + r] = reg[r].x;
+        im[pb + r] = reg[r].y;
+      }
+    } else {
 #pragma unroll
-    for (int s = 1; s < S::NFULL; ++s) {
-      bool last = (s == S::NFULL - 1) && (S::LAST == 1);
-      stage_lds<N, PPT, PPT, DIR, R>(re, im, t, Ns, tw, reg, last);
-      Ns *= PPT;
+      for (int r = 0; r < PPT; ++r) {
+        re[pad(t * PPT + r)] = reg[r].x;
+        im[pad(t * PPT + r)] = reg[r].y;
+      }
     }
-    if constexpr (S::LAST > 1) {
-      stage_lds<N, PPT, S::LAST, DIR, R>(re, im, t, Ns, tw, reg, true);
-      // slot layout after last stage: butterfly b, output r -> element
-      // t + T*(b + r*NB); registers are currently ordered [b][r].
-      constexpr int NB = PPT / S::LAST;
+    group_sync<T>();
+    middle_stages<N, PPT, DIR, R, 1>(re, im, t, tws, reg);
+    if constexpr (SH::LAST > 1) {
+      stage_lds<N, PPT, SH::LAST, SH::pow_ppt(SH::NFULL), SH::stage_off(SH::NFULL), DIR, true, R>(
+          re, im, t, tws, reg);
+      // butterfly b, output r -> element t + T (b + r NB); registers are [b][r]
+      constexpr int NB = PPT / SH::LAST;
       cx<R> tmp[PPT];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int r = 0; r < S::LAST; ++r) tmp[b + r * NB] = reg[b * S::LAST + r];
+        for (int r = 0; r < SH::LAST; ++r) tmp[b + r * NB] = reg[b * SH::LAST + r];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) reg[q] = tmp[q];
     }
-    (void)T;
   }
 }
 

@@ -19,7 +19,19 @@ namespace cip {
 constexpr int RT = 8;          // rows per row tile
 constexpr int PAIRS = RT / 2;  // row pairs per row-pass work-group
 
-template <int N> constexpr int ppt_for() { return N >= 16 ? 16 : N; }
+// Points per thread of the length-N transforms in row passes and column
+// passes (a group of N / PPT threads carries one transform).
+#ifndef CIP_PPT_ROW_1024
+#define CIP_PPT_ROW_1024 16
+#endif
+#ifndef CIP_PPT_COL_1024
+#define CIP_PPT_COL_1024 16
+#endif
+constexpr int ppt_default(int N) { return N >= 16 ? 16 : N; }
+constexpr int ppt_row_n(int N) { return N == 1024 ? CIP_PPT_ROW_1024 : ppt_default(N); }
+constexpr int ppt_col_n(int N) { return N == 1024 ? CIP_PPT_COL_1024 : ppt_default(N); }
+template <int N> constexpr int ppt_row() { return ppt_row_n(N); }
+template <int N> constexpr int ppt_col() { return ppt_col_n(N); }
 
 __device__ __forceinline__ size_t rt_tile_base(int p, int n1, int N1, int H2) {
   return (((size_t)p * (N1 / RT) + (n1 / RT)) * H2) * RT;
@@ -39,31 +51,126 @@ template <typename Re> __device__ __forceinline__ void stc(Re* re, Re* im, int i
   im[pad(i)] = v.y;
 }
 
+// ---------------------------------------------------------------- LDS helpers
+// Padding for the row-tile staging arrays ([k2][RT] order, stride RT floats).
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+constexpr int pad8_len(int n) { return n + (n >> 3) + 1; }
+
+// Copy n complex values from global memory into LDS (whole work-group).
+template <typename Re>
+__device__ __forceinline__ void lds_load_table(cx<Re>* dst, const cx<Re>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Floats of LDS used by a row-pass work-group of NG row pairs.
+template <int N2, typename Re> constexpr int row_work_floats(int ng, bool staged) {
+  int fft = ng * 2 * padded_len(N2);
+  int stg = staged ? 2 * pad8_len((N2 / 2 + 1) * RT) : 0;
+  return fft > stg ? fft : stg;
+}
+
+// Load one RT row tile (H2 x RT complex, contiguous) into the padded staging
+// arrays sre / sim.
+__device__ __forceinline__ void tile_to_staging(const cx<float>* __restrict__ src, float* sre,
+                                                float* sim, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    cx<float> z = src[i];
+    sre[pad8(i)] = z.x;
+    sim[pad8(i)] = z.y;
+  }
+}
+__device__ __forceinline__ void staging_to_tile(cx<float>* __restrict__ dst, const float* sre,
+                                                const float* sim, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = cx<float>{sre[pad8(i)], sim[pad8(i)]};
+}
+
+// From the staged half spectra of rows a = 2g, b = 2g + 1 of the tile, build
+// the full spectrum Z[k] = A[k] + i B[k] (Hermitian extension of A and B), in
+// the group register order (slot q holds k = t + T q).
+template <int N2, int PPT>
+__device__ __forceinline__ void staging_to_pair(cx<float>* v, const float* sre, const float* sim,
+                                                int g, int t) {
+  constexpr int T = N2 / PPT;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    int k = t + T * q;
+    int kk = k <= N2 / 2 ? k : N2 - k;
+    float sg = k <= N2 / 2 ? 1.f : -1.f;
+    int i = kk * RT + 2 * g;
+    cx<float> A = {sre[pad8(i)], sg * sim[pad8(i)]};
+    cx<float> B = {sre[pad8(i + 1)], sg * sim[pad8(i + 1)]};
+    v[q] = cx<float>{A.x - B.y, A.y + B.x};
+  }
+}
+
+// Split the spectrum Z of a packed pair (z = a + i b) into the half spectra
+// A[k] = (Z[k] + conj Z[N-k]) / 2, B[k] = (Z[k] - conj Z[N-k]) / 2i,
+// k = 0..N/2, and write them to the staging arrays as rows 2g, 2g + 1. `v`
+// holds Z in group register order on entry. The group scratch (re, im) may
+// alias the staging arrays.
+template <int N2, int PPT>
+__device__ __forceinline__ void pair_to_staging(cx<float>* v, float* re, float* im, float* sre,
+                                                float* sim, int g, int t) {
+  constexpr int T = N2 / PPT;
+  constexpr int QH = (N2 / 2) / T + 1;   // slots that can hold k <= N/2
+  group_sync<T>();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+  group_sync<T>();
+  cx<float> A[QH], B[QH];
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    int k = t + T * q;
+    if (k <= N2 / 2) {
+      cx<float> Z = ldc(re, im, k);
+      cx<float> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
+      cx<float> s = Z + Zc, d = Z - Zc;
+      A[q] = cx<float>{0.5f * s.x, 0.5f * s.y};
+      B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    int k = t + T * q;
+    if (k <= N2 / 2) {
+      int i = k * RT + 2 * g;
+      sre[pad8(i)] = A[q].x;
+      sim[pad8(i)] = A[q].y;
+      sre[pad8(i + 1)] = B[q].x;
+      sim[pad8(i + 1)] = B[q].y;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- DCT via FFT
 // Orthonormal DCT-II of a complex sequence (real and imaginary parts
 // transformed independently), computed with one N-point FFT of the
-// even/odd-reordered sequence and a post-twiddle (Makhoul's method).
-//   fw[k] = a_k exp(-i pi k / 2N),  a_0 = sqrt(1/N), a_k = sqrt(2/N).
+// even/odd-reordered sequence and a post-twiddle (Makhoul's method):
+//   X[k] = a_k Re(E[k] Va[k]) + i a_k Re(E[k] Vb[k]),  E[k] = exp(-i pi k / 2N),
+//   a_0 = sqrt(1/N), a_k = sqrt(2/N), Va / Vb the spectra of the reordered
+//   real / imaginary parts (separated from one complex FFT).
+// `ew` is the LDS table E[0..N).
 template <int N, int PPT>
 __device__ __forceinline__ void dct_fwd_group(cx<float>* reg, float* re, float* im, int t,
-                                              const cx<float>* __restrict__ tw,
-                                              const cx<float>* __restrict__ fw) {
+                                              const cx<float>* tw, const cx<float>* ew) {
   constexpr int T = N / PPT;
-  __syncthreads();
+  const float a0 = __builtin_sqrtf(1.0f / N), a1 = __builtin_sqrtf(2.0f / N);
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int n = t + T * q;
     int p = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
     stc(re, im, p, reg[q]);
   }
-  __syncthreads();
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) reg[q] = ldc(re, im, t + T * q);
   fft_group<N, PPT, +1>(reg, re, im, t, tw);
-  __syncthreads();
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, reg[q]);
-  __syncthreads();
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
@@ -71,78 +178,72 @@ __device__ __forceinline__ void dct_fwd_group(cx<float>* reg, float* re, float* 
     cx<float> V = ldc(re, im, k);
     cx<float> Vc = conjx(ldc(re, im, kk));
     cx<float> s = V + Vc, d = V - Vc;
-    cx<float> Va = {0.5f * s.x, 0.5f * s.y};
-    cx<float> Vb = {0.5f * d.y, -0.5f * d.x};   // (V - conj V[N-k]) / 2i
-    cx<float> c = fw[k];
-    reg[q] = cx<float>{c.x * Va.x - c.y * Va.y, c.x * Vb.x - c.y * Vb.y};
+    // Va = s / 2, Vb = d / 2i = (d.y, -d.x) / 2; fold the 1/2 into alpha
+    cx<float> e = ew[k];
+    float al = 0.5f * (k == 0 ? a0 : a1);
+    reg[q] = cx<float>{al * (e.x * s.x - e.y * s.y), al * (e.x * d.y + e.y * d.x)};
   }
 }
 
-// Inverse (DCT-III, orthonormal) of a complex coefficient sequence:
-//   V[k] = iv[k] (Y[k] ia[k] - i Y[N-k] ia[N-k]),  V[0] = iv[0] Y[0] ia[0],
-//   iv[k] = exp(i pi k / 2N) / N, ia[k] = 1 / a_k,
+// Inverse (DCT-III, orthonormal) of a complex coefficient sequence Y:
+//   V[k] = conj(E[k]) / N * (Y[k] / a_k - i Y[N-k] / a_{N-k}),  V[0] = Y[0] / (N a_0),
 // then an inverse FFT and the inverse even/odd reordering.
 template <int N, int PPT>
 __device__ __forceinline__ void dct_inv_group(cx<float>* reg, float* re, float* im, int t,
-                                              const cx<float>* __restrict__ tw,
-                                              const cx<float>* __restrict__ iv,
-                                              const float* __restrict__ ia) {
+                                              const cx<float>* tw, const cx<float>* ew) {
   constexpr int T = N / PPT;
-  __syncthreads();
+  const float ia0 = __builtin_sqrtf((float)N) / N, ia1 = __builtin_sqrtf(0.5f * N) / N;
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, reg[q]);
-  __syncthreads();
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
     cx<float> Yk = ldc(re, im, k);
-    float sk = ia[k];
-    cx<float> a = {Yk.x * sk, Yk.y * sk};
-    if (k != 0) {
-      int kk = N - k;
-      cx<float> Yn = ldc(re, im, kk);
-      float sn = ia[kk];
-      a.x += Yn.y * sn;    // - i * Yn
-      a.y -= Yn.x * sn;
+    cx<float> a;
+    if (k == 0) {
+      a = cx<float>{Yk.x * ia0, Yk.y * ia0};
+    } else {
+      cx<float> Yn = ldc(re, im, N - k);
+      a = cx<float>{(Yk.x + Yn.y) * ia1, (Yk.y - Yn.x) * ia1};   // Yk - i Yn
     }
-    reg[q] = cmul(iv[k], a);
+    cx<float> e = ew[k];
+    reg[q] = cmulc(a, e);   // a * conj(E[k])
   }
   fft_group<N, PPT, -1>(reg, re, im, t, tw);
-  __syncthreads();
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int m = t + T * q;
     int pos = (m < N / 2) ? 2 * m : 2 * N - 2 * m - 1;
     stc(re, im, pos, reg[q]);
   }
-  __syncthreads();
+  group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) reg[q] = ldc(re, im, t + T * q);
 }
 
-// Exact float -> double promotion of one plane (plan time).
-__global__ void k_promote(const float* __restrict__ src, double* __restrict__ dst, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (double)src[i];
-}
 
 // ---------------------------------------------------------------- row passes
-// Two real rows a, b are carried by one complex FFT (z = a + i b).
+// Two real rows a, b are carried by one complex FFT (z = a + i b). LDS layout
+// of every row kernel: [twiddles N2 complex][work region].
 
 // Real-to-complex FFT of every row: in [P][N1][N2] -> out RT [P][N1/RT][H2][RT].
-// One work-group per (plane, pair of rows) when STAGED = false (any type), or
-// per (plane, row tile) with a coalesced tile store when STAGED = true.
+// STAGED (float): one work-group per (plane, row tile), coalesced tile store.
+// Otherwise (double, plan time): one work-group per (plane, row pair).
 template <int N2, typename Re, bool STAGED>
 __global__ void k_row_r2c(const Re* __restrict__ in, cx<Re>* __restrict__ out, int N1,
-                          const cx<Re>* __restrict__ tw) {
-  constexpr int PPT = ppt_for<N2>();
+                          const cx<Re>* __restrict__ twg) {
+  constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
-  constexpr int NG = STAGED ? PAIRS : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Re* lds = reinterpret_cast<Re*>(smem_raw);
+  cx<Re>* tw = reinterpret_cast<cx<Re>*>(smem_raw);
+  Re* lds = reinterpret_cast<Re*>(smem_raw) + 2 * N2;
+  lds_load_table(tw, twg, N2);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
-  int p, row0;  // plane and first row handled by this work-group
+  int p, row0;
   if (STAGED) {
     const int tiles = N1 / RT;
     p = blockIdx.x / tiles;
@@ -163,47 +264,28 @@ __global__ void k_row_r2c(const Re* __restrict__ in, cx<Re>* __restrict__ out, i
     int n = t + T * q;
     v[q] = cx<Re>{xa[n], xb[n]};
   }
+  __syncthreads();   // twiddle table ready
   fft_group<N2, PPT, +1>(v, re, im, t, tw);
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
-  __syncthreads();
-  cx<Re> A[PPT], B[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k = t + T * q;
-    if (k <= N2 / 2) {
-      cx<Re> Z = ldc(re, im, k);
-      cx<Re> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
-      cx<Re> s = Z + Zc, d = Z - Zc;
-      A[q] = cx<Re>{Re(0.5) * s.x, Re(0.5) * s.y};
-      B[q] = cx<Re>{Re(0.5) * d.y, Re(-0.5) * d.x};
-    }
-  }
   if constexpr (STAGED) {
+    float* sre = lds;
+    float* sim = lds + pad8_len(H2 * RT);
+    pair_to_staging<N2, PPT>(v, re, im, sre, sim, g, t);
     __syncthreads();
-    Re* st = lds;   // [H2][RT] complex, aliases the FFT scratch
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      int k = t + T * q;
-      if (k <= N2 / 2) {
-        int ia = (k * RT + 2 * g) * 2;
-        st[ia] = A[q].x;
-        st[ia + 1] = A[q].y;
-        st[ia + 2] = B[q].x;
-        st[ia + 3] = B[q].y;
-      }
-    }
-    __syncthreads();
-    cx<Re>* dst = out + rt_tile_base(p, row0, N1, H2);
-    for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) dst[i] = cx<Re>{st[2 * i], st[2 * i + 1]};
+    staging_to_tile(out + rt_tile_base(p, row0, N1, H2), sre, sim, H2 * RT);
   } else {
+    group_sync<T>();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+    group_sync<T>();
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       int k = t + T * q;
       if (k <= N2 / 2) {
-        out[rt_idx(p, ra, k, N1, H2)] = A[q];
-        out[rt_idx(p, ra + 1, k, N1, H2)] = B[q];
+        cx<Re> Z = ldc(re, im, k);
+        cx<Re> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
+        cx<Re> s = Z + Zc, d = Z - Zc;
+        out[rt_idx(p, ra, k, N1, H2)] = cx<Re>{Re(0.5) * s.x, Re(0.5) * s.y};
+        out[rt_idx(p, ra + 1, k, N1, H2)] = cx<Re>{Re(0.5) * d.y, Re(-0.5) * d.x};
       }
     }
   }
@@ -213,36 +295,26 @@ __global__ void k_row_r2c(const Re* __restrict__ in, cx<Re>* __restrict__ out, i
 // scaled by `scale`. One work-group per (plane, row tile).
 template <int N2>
 __global__ void k_row_c2r(const cx<float>* __restrict__ in, float* __restrict__ out, int N1,
-                          float scale, const cx<float>* __restrict__ tw) {
-  constexpr int PPT = ppt_for<N2>();
+                          float scale, const cx<float>* __restrict__ twg) {
+  constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* lds = reinterpret_cast<float*>(smem_raw);
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
   const int p = blockIdx.x / tiles, row0 = (blockIdx.x % tiles) * RT;
   float* re = lds + g * 2 * padded_len(N2);
   float* im = re + padded_len(N2);
-  float* st = lds;
-  const cx<float>* src = in + rt_tile_base(p, row0, N1, H2);
-  for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
-    cx<float> z = src[i];
-    st[2 * i] = z.x;
-    st[2 * i + 1] = z.y;
-  }
+  float* sre = lds;
+  float* sim = lds + pad8_len(H2 * RT);
+  lds_load_table(tw, twg, N2);
+  tile_to_staging(in + rt_tile_base(p, row0, N1, H2), sre, sim, H2 * RT);
   __syncthreads();
   cx<float> v[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k = t + T * q;
-    int kk = k <= N2 / 2 ? k : N2 - k;
-    float sg = k <= N2 / 2 ? 1.f : -1.f;
-    int ia = (kk * RT + 2 * g) * 2;
-    cx<float> A = {st[ia], sg * st[ia + 1]};
-    cx<float> B = {st[ia + 2], sg * st[ia + 3]};
-    v[q] = cx<float>{A.x - B.y, A.y + B.x};
-  }
+  staging_to_pair<N2, PPT>(v, sre, sim, g, t);
+  __syncthreads();   // staging aliases the group scratch
   fft_group<N2, PPT, -1>(v, re, im, t, tw);
   float* xa = out + ((size_t)p * N1 + row0 + 2 * g) * N2;
   float* xb = xa + N2;
@@ -265,29 +337,28 @@ enum ColOp { OP_FWD = 0, OP_ADJ = 1, OP_XHAT0 = 2, OP_SPEC = 3 };
 //   OP_ADJ  : out_s = sum_k conj(Lam[k][s]) in_k
 //   OP_XHAT0: out_s = sum_k M[s][k] in_k                 (M FL [S*K])
 //   OP_SPEC : out_0 = in_0, stored at FL plane `spec_plane`
+// LDS: [twiddles N1 complex][PM planes x 2 x padded N1].
 template <int N1, typename Re, int OP>
 __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv, int Pin, int Pout,
-                         int H2, const cx<Re>* __restrict__ tw, const cx<Re>* __restrict__ mat,
+                         int H2, const cx<Re>* __restrict__ twg, const cx<Re>* __restrict__ mat,
                          int spec_plane) {
-  constexpr int PPT = ppt_for<N1>();
+  constexpr int PPT = ppt_col<N1>();
   constexpr int T = N1 / PPT;
+  constexpr int PL = padded_len(N1);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Re* lds = reinterpret_cast<Re*>(smem_raw);
+  cx<Re>* tw = reinterpret_cast<cx<Re>*>(smem_raw);
+  Re* lds = reinterpret_cast<Re*>(smem_raw) + 2 * N1;
   const int k2 = blockIdx.x;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int PM = blockDim.x / T;
-  constexpr int PL = padded_len(N1);
   Re* re = lds + g * 2 * PL;
   Re* im = re + PL;
+  lds_load_table(tw, twg, N1);
   cx<Re> v[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q)
     v[q] = g < Pin ? in[rt_idx(g, t + T * q, k2, N1, H2)] : cx<Re>{Re(0), Re(0)};
+  __syncthreads();
   fft_group<N1, PPT, +1>(v, re, im, t, tw);
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
-  __syncthreads();
   const size_t F = (size_t)N1 * H2;
   if constexpr (OP == OP_SPEC) {
     cx<Re>* out = reinterpret_cast<cx<Re>*>(outv);
@@ -297,6 +368,10 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
     }
     return;
   } else {
+    group_sync<T>();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+    group_sync<T>();
     // per-frequency map; each thread owns whole frequencies
     for (int k1 = threadIdx.x; k1 < N1; k1 += blockDim.x) {
       cx<Re> xin[8];
@@ -306,8 +381,7 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
         cx<Re> acc = {Re(0), Re(0)};
         for (int j = 0; j < Pin; ++j) {
           cx<Re> m;
-          if (OP == OP_FWD) m = mat[(size_t)(o * Pin + j) * F + f];
-          else if (OP == OP_ADJ) m = conjx(mat[(size_t)(j * Pout + o) * F + f]);
+          if (OP == OP_ADJ) m = conjx(mat[(size_t)(j * Pout + o) * F + f]);
           else m = mat[(size_t)(o * Pin + j) * F + f];
           acc = acc + cmul(m, xin[j]);
         }
@@ -328,14 +402,13 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
 #pragma unroll
       for (int q = 0; q < PPT; ++q) out[rt_idx(g, t + T * q, k2, N1, H2)] = v[q];
     }
-    (void)PM;
   }
 }
 
-// ---------------------------------------------------------------- ADMM, DCT prior
-// State: v = T x^l + u^{l-1} per DCT coefficient (one float per voxel). From
-// v the pair (t, u) of Algorithm 1 is t = soft(v, kappa), u = clip(v, kappa),
-// so t - u = 2 soft(v) - v and the next v = T x^{l+1} + clip(v).
+// ---------------------------------------------------------------- ADMM state
+// State per constraint component: v = T x^l + u^{l-1}. From v the pair (t, u)
+// of Algorithm 1 is t = soft(v, kappa), u = clip(v, kappa) (kappa = lambda /
+// rho), so t - u = 2 soft(v) - v and the next v = T x^{l+1} + clip(v).
 __device__ __forceinline__ float soft_f(float v, float k) {
   return v > k ? v - k : (v < -k ? v + k : 0.f);
 }
@@ -348,43 +421,50 @@ enum RowMode { ROW_FIRST = 0, ROW_FULL = 1, ROW_FINAL = 2 };
 // row-frequency domain) -> row DCT gives w = T x^l -> prox + dual update of v
 // -> inverse row DCT of t - u -> forward row FFT -> RT output for the next
 // column pass. ROW_FINAL stops after the inverse row FFT and writes x.
+// LDS: [twiddles N2][DCT table E N2][work region].
 template <int N2>
-__global__ void __launch_bounds__(PAIRS * (N2 / ppt_for<N2>()))
+__global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()), 2)
 k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
-               float* __restrict__ vstate, int N1, const cx<float>* __restrict__ tw,
-               const cx<float>* __restrict__ fw, const cx<float>* __restrict__ iv,
-               const float* __restrict__ ia, float kappa, int mode, float* __restrict__ xout) {
-  constexpr int PPT = ppt_for<N2>();
+               float* __restrict__ vstate, int N1, const cx<float>* __restrict__ twg,
+               const cx<float>* __restrict__ ewg, float kappa, int mode,
+               float* __restrict__ xout) {
+  constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* lds = reinterpret_cast<float*>(smem_raw);
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  cx<float>* ew = tw + N2;
+  float* lds = reinterpret_cast<float*>(smem_raw) + 4 * N2;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
   const int s = blockIdx.x / tiles, row0 = (blockIdx.x % tiles) * RT;
+  const int ra = row0 + 2 * g;
   float* re = lds + g * 2 * padded_len(N2);
   float* im = re + padded_len(N2);
-  float* st = lds;
-  const cx<float>* src = Yin + rt_tile_base(s, row0, N1, H2);
-  for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
-    cx<float> z = src[i];
-    st[2 * i] = z.x;
-    st[2 * i + 1] = z.y;
+  float* sre = lds;
+  float* sim = lds + pad8_len(H2 * RT);
+  lds_load_table(tw, twg, N2);
+  if (mode != ROW_FINAL) lds_load_table(ew, ewg, N2);
+  tile_to_staging(Yin + rt_tile_base(s, row0, N1, H2), sre, sim, H2 * RT);
+  // prefetch the state of rows a, b (latency overlaps the two FFTs below)
+  float* va = vstate + ((size_t)s * N1 + ra) * N2;
+  float* vb = va + N2;
+  float oa[PPT], ob[PPT];
+  if (mode == ROW_FULL) {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      oa[q] = va[t + T * q];
+      ob[q] = vb[t + T * q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) oa[q] = ob[q] = 0.f;
   }
   __syncthreads();
   cx<float> v[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k = t + T * q;
-    int kk = k <= N2 / 2 ? k : N2 - k;
-    float sg = k <= N2 / 2 ? 1.f : -1.f;
-    int ia2 = (kk * RT + 2 * g) * 2;
-    cx<float> A = {st[ia2], sg * st[ia2 + 1]};
-    cx<float> B = {st[ia2 + 2], sg * st[ia2 + 3]};
-    v[q] = cx<float>{A.x - B.y, A.y + B.x};
-  }
+  staging_to_pair<N2, PPT>(v, sre, sim, g, t);
+  __syncthreads();   // staging aliases the group scratch
   fft_group<N2, PPT, -1>(v, re, im, t, tw);
-  const int ra = row0 + 2 * g;
   if (mode == ROW_FINAL) {
     float* xa = xout + ((size_t)s * N1 + ra) * N2;
     float* xb = xa + N2;
@@ -396,56 +476,21 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     }
     return;
   }
-  dct_fwd_group<N2, PPT>(v, re, im, t, tw, fw);
-  float* va = vstate + ((size_t)s * N1 + ra) * N2;
-  float* vb = va + N2;
+  dct_fwd_group<N2, PPT>(v, re, im, t, tw, ew);
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
-    float oa = 0.f, ob = 0.f;
-    if (mode != ROW_FIRST) {
-      oa = va[k];
-      ob = vb[k];
-    }
-    float na = v[q].x + clip_f(oa, kappa);
-    float nb = v[q].y + clip_f(ob, kappa);
+    float na = v[q].x + clip_f(oa[q], kappa);
+    float nb = v[q].y + clip_f(ob[q], kappa);
     va[k] = na;
     vb[k] = nb;
     v[q] = cx<float>{2.f * soft_f(na, kappa) - na, 2.f * soft_f(nb, kappa) - nb};
   }
-  dct_inv_group<N2, PPT>(v, re, im, t, tw, iv, ia);
+  dct_inv_group<N2, PPT>(v, re, im, t, tw, ew);
   fft_group<N2, PPT, +1>(v, re, im, t, tw);
+  pair_to_staging<N2, PPT>(v, re, im, sre, sim, g, t);
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
-  __syncthreads();
-  cx<float> A[PPT], B[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k = t + T * q;
-    if (k <= N2 / 2) {
-      cx<float> Z = ldc(re, im, k);
-      cx<float> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
-      cx<float> sm = Z + Zc, d = Z - Zc;
-      A[q] = cx<float>{0.5f * sm.x, 0.5f * sm.y};
-      B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k = t + T * q;
-    if (k <= N2 / 2) {
-      int i2 = (k * RT + 2 * g) * 2;
-      st[i2] = A[q].x;
-      st[i2 + 1] = A[q].y;
-      st[i2 + 2] = B[q].x;
-      st[i2 + 3] = B[q].y;
-    }
-  }
-  __syncthreads();
-  cx<float>* dst = Gout + rt_tile_base(s, row0, N1, H2);
-  for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) dst[i] = cx<float>{st[2 * i], st[2 * i + 1]};
+  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), sre, sim, H2 * RT);
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
@@ -457,56 +502,87 @@ __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
 //   X(w) = xh0(w) + A(w) g(w)    (A = rho Psi^+ / (N1 N2), packed Hermitian)
 // -> inverse column FFT -> [column DCT] -> RT output.
 // DCT = true for the DCT prior (T acts on both axes), false for TV priors.
-template <int N1, bool DCT>
-__global__ void __launch_bounds__(8 * (N1 / ppt_for<N1>()))
-k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int S, int H2,
+// The solve tables of this thread's frequencies are loaded at kernel start so
+// that their latency overlaps the first transforms.
+// LDS: [twiddles N1][DCT table E N1][S x 2 x padded N1].
+template <int N1, bool DCT, int S>
+__global__ void __launch_bounds__(S * (N1 / ppt_col<N1>()))
+k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int H2,
            const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
-           const cx<float>* __restrict__ xh0, const cx<float>* __restrict__ tw,
-           const cx<float>* __restrict__ fw, const cx<float>* __restrict__ iv,
-           const float* __restrict__ ia, int zero_in, int dct_out) {
-  constexpr int PPT = ppt_for<N1>();
+           const cx<float>* __restrict__ xh0, const cx<float>* __restrict__ twg,
+           const cx<float>* __restrict__ ewg, int zero_in, int dct_out) {
+  constexpr int PPT = ppt_col<N1>();
   constexpr int T = N1 / PPT;
   constexpr int PL = padded_len(N1);
+  constexpr int SO = S > 1 ? S - 1 : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* lds = reinterpret_cast<float*>(smem_raw);
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  cx<float>* ew = tw + N1;
+  float* lds = reinterpret_cast<float*>(smem_raw) + 4 * N1;
   const int k2 = blockIdx.x;
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  // plane index; uniform across a wavefront when a group spans whole waves
+  const int g = (T % 64 == 0) ? __builtin_amdgcn_readfirstlane(threadIdx.x / T)
+                              : (int)(threadIdx.x / T);
+  const int t = threadIdx.x % T;
   float* re = lds + g * 2 * PL;
   float* im = re + PL;
+  const size_t F = (size_t)N1 * H2;
+  const size_t f0 = (size_t)k2 * N1 + t;
+  // solve tables: x_hat0 of plane g, row g of A
+  cx<float> pxh[PPT], pao[SO][PPT];
+  float pdg[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) pxh[q] = xh0[(size_t)g * F + f0 + T * q];
+  if (!zero_in) {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) pdg[q] = Adiag[(size_t)g * F + f0 + T * q];
+#pragma unroll
+    for (int jj = 0; jj < S - 1; ++jj) {
+      const int j = jj < g ? jj : jj + 1;
+      const int e = g < j ? pair_index(g, j, S) : pair_index(j, g, S);
+      const cx<float>* src = Aoff + (size_t)e * F + f0;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        cx<float> a = src[T * q];
+        pao[jj][q] = g < j ? a : conjx(a);
+      }
+    }
+  }
+  lds_load_table(tw, twg, N1);
+  if (DCT) lds_load_table(ew, ewg, N1);
   cx<float> v[PPT];
   if (!zero_in) {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) v[q] = Gin[rt_idx(g, t + T * q, k2, N1, H2)];
-    if constexpr (DCT) dct_inv_group<N1, PPT>(v, re, im, t, tw, iv, ia);
+  }
+  __syncthreads();
+  if (!zero_in) {
+    if constexpr (DCT) dct_inv_group<N1, PPT>(v, re, im, t, tw, ew);
     fft_group<N1, PPT, +1>(v, re, im, t, tw);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
     __syncthreads();
-  }
-  const size_t F = (size_t)N1 * H2;
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k1 = t + T * q;
-    size_t f = (size_t)k2 * N1 + k1;
-    cx<float> acc = xh0[(size_t)g * F + f];
-    if (!zero_in) {
-      float d = Adiag[(size_t)g * F + f];
+    for (int q = 0; q < PPT; ++q) {
+      const int k1 = t + T * q;
       cx<float> gg = ldc(re, im, k1);
-      acc.x += d * gg.x;
-      acc.y += d * gg.y;
-      for (int j = 0; j < S; ++j) {
-        if (j == g) continue;
-        cx<float> a = (g < j) ? Aoff[(size_t)pair_index(g, j, S) * F + f]
-                              : conjx(Aoff[(size_t)pair_index(j, g, S) * F + f]);
-        acc = acc + cmul(a, ldc(lds + j * 2 * PL, lds + j * 2 * PL + PL, k1));
+      cx<float> acc = {pxh[q].x + pdg[q] * gg.x, pxh[q].y + pdg[q] * gg.y};
+#pragma unroll
+      for (int jj = 0; jj < S - 1; ++jj) {
+        const int j = jj < g ? jj : jj + 1;
+        acc = acc + cmul(pao[jj][q], ldc(lds + j * 2 * PL, lds + j * 2 * PL + PL, k1));
       }
+      v[q] = acc;
     }
-    v[q] = acc;
+    __syncthreads();   // every plane's scratch was read by the solve
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) v[q] = pxh[q];
   }
   fft_group<N1, PPT, -1>(v, re, im, t, tw);
   if constexpr (DCT) {
-    if (dct_out) dct_fwd_group<N1, PPT>(v, re, im, t, tw, fw);
+    if (dct_out) dct_fwd_group<N1, PPT>(v, re, im, t, tw, ew);
   }
 #pragma unroll
   for (int q = 0; q < PPT; ++q) Yout[rt_idx(g, t + T * q, k2, N1, H2)] = v[q];
