@@ -103,8 +103,8 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     return fail(CIP_EUNSUPPORTED, "N1 and N2 must be powers of two in [16, 2048]");
   if (state_floats_per_voxel(prior->kind) < 0)
     return fail(CIP_EUNSUPPORTED, "unsupported prior kind");
-  if (prior->kind != CIP_PRIOR_DCT2D)
-    return fail(CIP_EUNSUPPORTED, "this build serves the DCT2D prior only");
+  if (prior->kind == CIP_PRIOR_TV3D)
+    return fail(CIP_EUNSUPPORTED, "this build serves the DCT2D and TV2D priors");
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
   return CIP_OK;
 }
@@ -186,6 +186,29 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
                   mode, xout);
   });
   return hipSuccess;
+}
+
+// Row pass of the TV2D prior; pass number l >= 1 of the solve (state buffers
+// alternate so that halo rows of the previous state stay readable).
+hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st) {
+  const Layout& L = p->L;
+  float kappa = (float)(p->lambda / p->rho);
+  const size_t buf = (size_t)2 * p->S * p->N1 * p->N2;
+  const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
+  float* vout = p->at<float>(L.state) + (size_t)(l & 1) * buf;
+  DISPATCH_N(p->N2, {
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(2 * NN + tv_work_floats<NN>()) * 4;
+    return launch(k_admm_row_tv<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
+                  p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
+                  p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0);
+  });
+  return hipSuccess;
+}
+
+hipError_t admm_row(cip_plan_t p, int l, hipStream_t st) {
+  if (p->kind == CIP_PRIOR_DCT2D) return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr);
+  return admm_row_tv(p, l, st);
 }
 
 hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
@@ -425,7 +448,7 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   // iteration 1 (t = u = 0): column pass only
   HIP_TRY(admm_col(p, 1, iters > 1 ? 1 : 0, st));
   for (int l = 1; l < iters; ++l) {
-    HIP_TRY(admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr));
+    HIP_TRY(admm_row(p, l, st));
     HIP_TRY(admm_col(p, 0, l < iters - 1 ? 1 : 0, st));
   }
   HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
@@ -448,7 +471,7 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, st));
   for (int r = 0; r < reps; ++r) {
-    if (which == 0) HIP_TRY(admm_row_dct(p, ROW_FULL, st, nullptr));
+    if (which == 0) HIP_TRY(admm_row(p, 2 + (r & 1), st));
     else HIP_TRY(admm_col(p, 0, 1, st));
   }
   HIP_TRY(hipEventRecord(e1, st));

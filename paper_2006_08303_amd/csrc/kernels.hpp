@@ -493,6 +493,189 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), sre, sim, H2 * RT);
 }
 
+// Row pass of one ADMM iteration for the anisotropic TV prior on every plane
+// (T = [D_v; D_h], circular forward differences along n1 and n2). One
+// work-group per (plane, tile of RT rows), with one halo row on each side:
+//   1. inverse row FFT of rows r0-1 .. r0+RT (column-pass output) -> x rows;
+//   2. w_v = x[n1+1] - x[n1], w_h = x[n2+1] - x[n2]; state update
+//      v_new = w + clip(v_old) for the RT own rows (both components) and the
+//      halo row r0-1 (vertical component, recomputed, not stored);
+//      q = t - u = 2 soft(v_new) - v_new;
+//   3. g = T^T q = (q_v[n1-1] - q_v[n1]) + (q_h[n2-1] - q_h[n2]) for own rows;
+//   4. forward row FFT of g -> RT output.
+// The state is double-buffered (vin -> vout) because neighbouring tiles read
+// the halo row of vin. Layout of each buffer: [component][S][N1][N2],
+// component 0 = vertical (n1) difference, 1 = horizontal (n2) difference.
+// LDS: [twiddles N2][work: max(5 group scratches, staging 10 x H2, q arrays)].
+template <int N2> constexpr int tv_work_floats() {
+  constexpr int H2 = N2 / 2 + 1;
+  constexpr int fft = (PAIRS + 1) * 2 * padded_len(N2);
+  constexpr int stg = 2 * pad8_len(H2 * (RT + 2));
+  constexpr int xr = (RT + 2) * N2;
+  constexpr int qq = 2 * (RT + 1) * N2;   // QV and QH, RT + 1 rows each
+  constexpr int a = fft > stg ? fft : stg;
+  constexpr int b = xr > qq ? xr : qq;
+  return a > b ? a : b;
+}
+
+template <int N2>
+__global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
+k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
+              const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
+              const cx<float>* __restrict__ twg, float kappa, int first) {
+  constexpr int PPT = ppt_row<N2>();
+  constexpr int T = N2 / PPT;
+  constexpr int H2 = N2 / 2 + 1;
+  constexpr int NR = RT + 2;   // rows in LDS: halo, RT own rows, halo
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int tiles = N1 / RT;
+  const int s = blockIdx.x / tiles, row0 = (blockIdx.x % tiles) * RT;
+  float* re = lds + g * 2 * padded_len(N2);
+  float* im = re + padded_len(N2);
+  float* sre = lds;
+  float* sim = lds + pad8_len(H2 * NR);
+  lds_load_table(tw, twg, N2);
+  // stage rows r0-1 .. r0+RT ([k2][NR] order); own rows come from one tile
+  {
+    const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
+    for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
+      const int k2 = i / RT, r = i % RT;
+      cx<float> z = tile[i];
+      sre[pad8(k2 * NR + r + 1)] = z.x;
+      sim[pad8(k2 * NR + r + 1)] = z.y;
+    }
+    const int lo = (row0 - 1 + N1) % N1, hi = (row0 + RT) % N1;
+    for (int i = threadIdx.x; i < 2 * H2; i += blockDim.x) {
+      const int k2 = i % H2, h = i / H2;
+      cx<float> z = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
+      const int r = h ? NR - 1 : 0;
+      sre[pad8(k2 * NR + r)] = z.x;
+      sim[pad8(k2 * NR + r)] = z.y;
+    }
+  }
+  __syncthreads();
+  // group g: local rows 2g, 2g+1 (global r0-1+2g, r0+2g)
+  cx<float> v[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    int k = t + T * q;
+    int kk = k <= N2 / 2 ? k : N2 - k;
+    float sg = k <= N2 / 2 ? 1.f : -1.f;
+    int i = kk * NR + 2 * g;
+    cx<float> A = {sre[pad8(i)], sg * sim[pad8(i)]};
+    cx<float> B = {sre[pad8(i + 1)], sg * sim[pad8(i + 1)]};
+    v[q] = cx<float>{A.x - B.y, A.y + B.x};
+  }
+  __syncthreads();
+  fft_group<N2, PPT, -1>(v, re, im, t, tw);
+  // x rows -> LDS [NR][N2]
+  __syncthreads();
+  float* X = lds;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    X[(2 * g) * N2 + t + T * q] = v[q].x;
+    X[(2 * g + 1) * N2 + t + T * q] = v[q].y;
+  }
+  __syncthreads();
+  // state update for local rows 0 (halo, vertical only) .. RT
+  const size_t plane = (size_t)N1 * N2;
+  const size_t cstride = (size_t)S * plane;   // component stride within a buffer
+  constexpr int NE = (RT + 1) * N2;
+  constexpr int PER = (NE + (PAIRS + 1) * T - 1) / ((PAIRS + 1) * T);
+  float qv[PER], qh[PER];
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int e = threadIdx.x + it * blockDim.x;
+    if (e < NE) {
+      const int lr = e / N2, n2 = e % N2;   // lr 0 = halo row r0-1
+      const int n1 = (row0 - 1 + lr + N1) % N1;
+      const float x0 = X[lr * N2 + n2];
+      const float wv = X[(lr + 1) * N2 + n2] - x0;
+      const size_t o = (size_t)s * plane + (size_t)n1 * N2 + n2;
+      const float ov = first ? 0.f : vin[o];
+      const float nv = wv + clip_f(ov, kappa);
+      qv[it] = 2.f * soft_f(nv, kappa) - nv;
+      if (lr > 0) {
+        const float wh = X[lr * N2 + ((n2 + 1) & (N2 - 1))] - x0;
+        const float oh = first ? 0.f : vin[cstride + o];
+        const float nh = wh + clip_f(oh, kappa);
+        qh[it] = 2.f * soft_f(nh, kappa) - nh;
+        vout[o] = nv;
+        vout[cstride + o] = nh;
+      }
+    }
+  }
+  __syncthreads();
+  float* QV = lds;                    // [RT + 1][N2], row 0 = halo
+  float* QH = lds + (RT + 1) * N2;    // [RT + 1][N2], row 0 unused
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int e = threadIdx.x + it * blockDim.x;
+    if (e < NE) {
+      QV[e] = qv[it];
+      if (e >= N2) QH[e] = qh[it];
+    }
+  }
+  __syncthreads();
+  // g = T^T q for own rows; group g (< PAIRS) packs local rows 1+2g, 2+2g
+  const bool active = g < PAIRS;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n2 = t + T * q;
+    const int nm = (n2 - 1) & (N2 - 1);
+    float ga = 0.f, gb = 0.f;
+    if (active) {
+      const int la = 1 + 2 * g, lb = la + 1;
+      ga = (QH[la * N2 + nm] - QH[la * N2 + n2]) + (QV[(la - 1) * N2 + n2] - QV[la * N2 + n2]);
+      gb = (QH[lb * N2 + nm] - QH[lb * N2 + n2]) + (QV[(lb - 1) * N2 + n2] - QV[lb * N2 + n2]);
+    }
+    v[q] = cx<float>{ga, gb};
+  }
+  __syncthreads();
+  fft_group<N2, PPT, +1>(v, re, im, t, tw);
+  // split into half spectra of the two rows and stage as tile rows 2g, 2g+1
+  float* ore = lds;
+  float* oim = lds + pad8_len(H2 * RT);
+  {
+    constexpr int QH2 = (N2 / 2) / T + 1;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+    __syncthreads();
+    cx<float> A[QH2], B[QH2];
+#pragma unroll
+    for (int q = 0; q < QH2; ++q) {
+      int k = t + T * q;
+      if (k <= N2 / 2) {
+        cx<float> Z = ldc(re, im, k);
+        cx<float> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
+        cx<float> sm = Z + Zc, d = Z - Zc;
+        A[q] = cx<float>{0.5f * sm.x, 0.5f * sm.y};
+        B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < QH2; ++q) {
+        int k = t + T * q;
+        if (k <= N2 / 2) {
+          int i = k * RT + 2 * g;
+          ore[pad8(i)] = A[q].x;
+          oim[pad8(i)] = A[q].y;
+          ore[pad8(i + 1)] = B[q].x;
+          oim[pad8(i + 1)] = B[q].y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), ore, oim, H2 * RT);
+}
+
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
   return i * S - i * (i + 1) / 2 + (j - i - 1);
 }

@@ -125,3 +125,55 @@ def test_full_size_1024_operators_and_solve():
     err = admm.rel_l2(got, ref)
     print(f"1024^2 DCT 3 iters: rel_l2 = {err:.3e}", flush=True)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("N,K,S,iters,kind", [(64, 2, 2, 50, "rects_gauss"), (64, 3, 3, 1, "smooth_disk"),
+                                              (128, 3, 3, 20, "smooth_disk"), (32, 1, 1, 10, "rects_gauss"),
+                                              (64, 2, 3, 15, "smooth_disk"), (16, 2, 2, 8, "rects_gauss")])
+def test_tv2d_solve_matches_oracle(N, K, S, iters, kind):
+    """Anisotropic TV (config-1 parameters: lambda = 1e-3, rho = 1e-2,
+    beta = 1); with unit-sum kernels the DC block is singular and both sides
+    take the minimum-norm x-update."""
+    print(f"tv2d solve N={N} K={K} S={S} iters={iters} {kind}", flush=True)
+    x, psf, y = _problem(kind, N, K, S, 1)
+    lam, rho, beta = 1e-3, 1e-2, 1.0
+    ref = admm.AnalysisADMM(psf, "tv2d", lam, rho, beta, tier="freq").run(y, iters)[0]
+    plan = cip.Plan(_t(psf), "tv2d", rho, lam, beta)
+    got = _np(plan.solve(_t(y), iters))
+    err = admm.rel_l2(got, ref)
+    print(f"  rel_l2 = {err:.3e}  psnr gpu {admm.psnr(got, x):.2f} dB oracle {admm.psnr(ref, x):.2f}",
+          flush=True)
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("prior", ["dct2d", "tv2d"])
+def test_rectangular_grid(prior):
+    """N1 != N2 (64 x 128 and 128 x 32)."""
+    for (N1, N2) in [(64, 128), (128, 32)]:
+        rng = np.random.default_rng(11)
+        K, S = 2, 3
+        psf = synth.gaussian_psfs(rng, K, S, N1, N2, sigma_range=(0.8, 2.5))
+        psf = psf.astype(np.float32).astype(np.float64)
+        x = rng.uniform(0, 1, (S, N1, N2))
+        y = model.forward(x, psf) + 0.01 * rng.standard_normal((K, N1, N2))
+        y = y.astype(np.float32).astype(np.float64)
+        lam, rho = (1e-2, 0.1) if prior == "dct2d" else (1e-3, 1e-2)
+        ref = admm.AnalysisADMM(psf, prior, lam, rho, 1.0, tier="freq").run(y, 12)[0]
+        plan = cip.Plan(_t(psf), prior, rho, lam, 1.0)
+        got = _np(plan.solve(_t(y), 12))
+        assert admm.rel_l2(got, ref) < 1e-4, (N1, N2)
+
+
+def test_tv2d_full_size_1024():
+    """TV2D at the headline shape (K = S = 3, 1024 x 1024), 3 iterations."""
+    N, K, S = 1024, 3, 3
+    x, psf, noise = synth.problem("smooth_disk", N, K, S, seed_config=3)
+    hx = model.forward(x, psf)
+    y = (hx + model.snr_noise_scale(hx, 30.0)[:, None, None] * noise)
+    y = y.astype(np.float32).astype(np.float64)
+    ref = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq").run(y, 3)[0]
+    plan = cip.Plan(_t(psf), "tv2d", 1e-2, 1e-3, 1.0)
+    got = _np(plan.solve(_t(y), 3))
+    err = admm.rel_l2(got, ref)
+    print(f"1024^2 TV2D 3 iters: rel_l2 = {err:.3e}", flush=True)
+    assert err < 1e-4
