@@ -170,7 +170,7 @@ __device__ __forceinline__ void static_for_k(cx<R> (&sub)[F][MM], cx<R>* v) {
 }
 
 // ---------------------------------------------------------------- LDS layout
-// Padded index: one spare slot every 16 floats. Strides that are multiples of
+// Padded index: one spare slot every 16 entries. Strides that are multiples of
 // 16 stay affine (pad(a + 16 c) = pad(a) + 17 c), so unrolled accesses fold
 // into immediate LDS offsets, and power-of-two strides spread over banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
@@ -207,10 +207,10 @@ template <int N, int PPT> struct fft_shape {
   static_assert(PPT % LAST == 0, "last radix must divide PPT");
 };
 
-// One Stockham stage with radix RS on the group's LDS array (re, im), after
+// One Stockham stage with radix RS on the group's LDS array buf, after
 // radices with product NS have been applied.
 template <int N, int PPT, int RS, int NS, int TWOFF, int DIR, bool LASTSTAGE, typename R>
-__device__ __forceinline__ void stage_lds(R* re, R* im, int t, const cx<R>* tws, cx<R>* v) {
+__device__ __forceinline__ void stage_lds(cx<R>* buf, int t, const cx<R>* tws, cx<R>* v) {
   constexpr int T = N / PPT;
   constexpr int NB = PPT / RS;   // butterflies per thread
   constexpr int STR = N / RS;
@@ -222,13 +222,13 @@ __device__ __forceinline__ void stage_lds(R* re, R* im, int t, const cx<R>* tws,
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         const int idx = pj + r * (STR + STR / 16);
-        v[b * RS + r] = cx<R>{re[idx], im[idx]};
+        v[b * RS + r] = buf[idx];
       }
     } else {
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         const int idx = pad(j + r * STR);
-        v[b * RS + r] = cx<R>{re[idx], im[idx]};
+        v[b * RS + r] = buf[idx];
       }
     }
   }
@@ -257,15 +257,13 @@ __device__ __forceinline__ void stage_lds(R* re, R* im, int t, const cx<R>* tws,
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
           const int idx = pb + r * (NS + NS / 16);
-          re[idx] = v[b * RS + r].x;
-          im[idx] = v[b * RS + r].y;
+          buf[idx] = v[b * RS + r];
         }
       } else {
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
           const int idx = pad(base + r * NS);
-          re[idx] = v[b * RS + r].x;
-          im[idx] = v[b * RS + r].y;
+          buf[idx] = v[b * RS + r];
         }
       }
     }
@@ -274,22 +272,22 @@ __device__ __forceinline__ void stage_lds(R* re, R* im, int t, const cx<R>* tws,
 }
 
 template <int N, int PPT, int DIR, typename R, int S>
-__device__ __forceinline__ void middle_stages(R* re, R* im, int t, const cx<R>* tws, cx<R>* reg) {
+__device__ __forceinline__ void middle_stages(cx<R>* buf, int t, const cx<R>* tws, cx<R>* reg) {
   using SH = fft_shape<N, PPT>;
   if constexpr (S < SH::NFULL) {
     constexpr bool last = (S == SH::NFULL - 1) && (SH::LAST == 1);
-    stage_lds<N, PPT, PPT, SH::pow_ppt(S), SH::stage_off(S), DIR, last, R>(re, im, t, tws, reg);
-    middle_stages<N, PPT, DIR, R, S + 1>(re, im, t, tws, reg);
+    stage_lds<N, PPT, PPT, SH::pow_ppt(S), SH::stage_off(S), DIR, last, R>(buf, t, tws, reg);
+    middle_stages<N, PPT, DIR, R, S + 1>(buf, t, tws, reg);
   }
 }
 
 // Full transform of a group. In: reg[q] = x[t + T q]. Out: reg[q] = X[t + T q].
-// (re, im): this group's LDS scratch of padded_len(N) floats each; tws: the
+// buf: this group's LDS scratch of padded_len(N) complex values; tws: the
 // stage twiddle table (LDS). The routine starts with a group barrier before
-// its first LDS write, so callers may still have been reading (re, im).
+// its first LDS write, so callers may still have been reading buf.
 // DIR = +1: forward (exp(-2 pi i jk/N)); DIR = -1: inverse, unnormalised.
 template <int N, int PPT, int DIR, typename R>
-__device__ __forceinline__ void fft_group(cx<R>* reg, R* re, R* im, int t, const cx<R>* tws) {
+__device__ __forceinline__ void fft_group(cx<R>* reg, cx<R>* buf, int t, const cx<R>* tws) {
   using SH = fft_shape<N, PPT>;
   constexpr int T = SH::T;
   if constexpr (N == 1) return;
@@ -302,21 +300,19 @@ __device__ __forceinline__ void fft_group(cx<R>* reg, R* re, R* im, int t, const
       const int pb = pad(t * PPT);
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        re[pb + r] = reg[r].x;
-        im[pb + r] = reg[r].y;
+        buf[pb + r] = reg[r];
       }
     } else {
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        re[pad(t * PPT + r)] = reg[r].x;
-        im[pad(t * PPT + r)] = reg[r].y;
+        buf[pad(t * PPT + r)] = reg[r];
       }
     }
     group_sync<T>();
-    middle_stages<N, PPT, DIR, R, 1>(re, im, t, tws, reg);
+    middle_stages<N, PPT, DIR, R, 1>(buf, t, tws, reg);
     if constexpr (SH::LAST > 1) {
       stage_lds<N, PPT, SH::LAST, SH::pow_ppt(SH::NFULL), SH::stage_off(SH::NFULL), DIR, true, R>(
-          re, im, t, tws, reg);
+          buf, t, tws, reg);
       // butterfly b, output r -> element t + T (b + r NB); registers are [b][r]
       constexpr int NB = PPT / SH::LAST;
       cx<R> tmp[PPT];

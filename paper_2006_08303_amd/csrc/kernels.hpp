@@ -43,12 +43,24 @@ __device__ __forceinline__ size_t fl_idx(int e, int k1, int k2, int N1, int H2) 
   return ((size_t)e * H2 + k2) * N1 + k1;
 }
 
-template <typename Re> __device__ __forceinline__ cx<Re> ldc(const Re* re, const Re* im, int i) {
-  return cx<Re>{re[pad(i)], im[pad(i)]};
+// Work-group index remap so that consecutive logical indices run on the same
+// XCD: the hardware deals work-groups round-robin over the 8 XCDs, each with
+// its own L2, while neighbouring columns / row tiles share cache lines.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  constexpr int NX = 8;
+  const int per = (n + NX - 1) / NX;
+  const int tall = n % NX == 0 ? NX : n % NX;
+  const int x = b % NX, i = b / NX;
+  return x < tall ? x * per + i : tall * per + (x - tall) * (per - 1) + i;
 }
-template <typename Re> __device__ __forceinline__ void stc(Re* re, Re* im, int i, cx<Re> v) {
-  re[pad(i)] = v.x;
-  im[pad(i)] = v.y;
+
+// Complex LDS arrays are interleaved (one 8- or 16-byte access per value)
+// and padded with pad().
+template <typename Re> __device__ __forceinline__ cx<Re> ldc(const cx<Re>* b, int i) {
+  return b[pad(i)];
+}
+template <typename Re> __device__ __forceinline__ void stc(cx<Re>* b, int i, cx<Re> v) {
+  b[pad(i)] = v;
 }
 
 // ---------------------------------------------------------------- LDS helpers
@@ -70,26 +82,22 @@ template <int N2, typename Re> constexpr int row_work_floats(int ng, bool staged
 }
 
 // Load one RT row tile (H2 x RT complex, contiguous) into the padded staging
-// arrays sre / sim.
-__device__ __forceinline__ void tile_to_staging(const cx<float>* __restrict__ src, float* sre,
-                                                float* sim, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    cx<float> z = src[i];
-    sre[pad8(i)] = z.x;
-    sim[pad8(i)] = z.y;
-  }
+// array (complex, padded with pad8).
+__device__ __forceinline__ void tile_to_staging(const cx<float>* __restrict__ src, cx<float>* stg,
+                                                int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) stg[pad8(i)] = src[i];
 }
-__device__ __forceinline__ void staging_to_tile(cx<float>* __restrict__ dst, const float* sre,
-                                                const float* sim, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = cx<float>{sre[pad8(i)], sim[pad8(i)]};
+__device__ __forceinline__ void staging_to_tile(cx<float>* __restrict__ dst, const cx<float>* stg,
+                                                int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = stg[pad8(i)];
 }
 
 // From the staged half spectra of rows a = 2g, b = 2g + 1 of the tile, build
 // the full spectrum Z[k] = A[k] + i B[k] (Hermitian extension of A and B), in
 // the group register order (slot q holds k = t + T q).
 template <int N2, int PPT>
-__device__ __forceinline__ void staging_to_pair(cx<float>* v, const float* sre, const float* sim,
-                                                int g, int t) {
+__device__ __forceinline__ void staging_to_pair(cx<float>* v, const cx<float>* stg, int g,
+                                                int t) {
   constexpr int T = N2 / PPT;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -97,8 +105,9 @@ __device__ __forceinline__ void staging_to_pair(cx<float>* v, const float* sre, 
     int kk = k <= N2 / 2 ? k : N2 - k;
     float sg = k <= N2 / 2 ? 1.f : -1.f;
     int i = kk * RT + 2 * g;
-    cx<float> A = {sre[pad8(i)], sg * sim[pad8(i)]};
-    cx<float> B = {sre[pad8(i + 1)], sg * sim[pad8(i + 1)]};
+    cx<float> A = stg[pad8(i)], B = stg[pad8(i + 1)];
+    A.y *= sg;
+    B.y *= sg;
     v[q] = cx<float>{A.x - B.y, A.y + B.x};
   }
 }
@@ -106,24 +115,24 @@ __device__ __forceinline__ void staging_to_pair(cx<float>* v, const float* sre, 
 // Split the spectrum Z of a packed pair (z = a + i b) into the half spectra
 // A[k] = (Z[k] + conj Z[N-k]) / 2, B[k] = (Z[k] - conj Z[N-k]) / 2i,
 // k = 0..N/2, and write them to the staging arrays as rows 2g, 2g + 1. `v`
-// holds Z in group register order on entry. The group scratch (re, im) may
+// holds Z in group register order on entry. The group scratch cb may
 // alias the staging arrays.
 template <int N2, int PPT>
-__device__ __forceinline__ void pair_to_staging(cx<float>* v, float* re, float* im, float* sre,
-                                                float* sim, int g, int t) {
+__device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<float>* stg, int g,
+                                                int t) {
   constexpr int T = N2 / PPT;
   constexpr int QH = (N2 / 2) / T + 1;   // slots that can hold k <= N/2
-  group_sync<T>();
+  // (called right after fft_group, which ends with a barrier)
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+  for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
   group_sync<T>();
   cx<float> A[QH], B[QH];
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
     int k = t + T * q;
     if (k <= N2 / 2) {
-      cx<float> Z = ldc(re, im, k);
-      cx<float> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
+      cx<float> Z = ldc(cb, k);
+      cx<float> Zc = conjx(ldc(cb, (N2 - k) & (N2 - 1)));
       cx<float> s = Z + Zc, d = Z - Zc;
       A[q] = cx<float>{0.5f * s.x, 0.5f * s.y};
       B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
@@ -135,10 +144,8 @@ __device__ __forceinline__ void pair_to_staging(cx<float>* v, float* re, float* 
     int k = t + T * q;
     if (k <= N2 / 2) {
       int i = k * RT + 2 * g;
-      sre[pad8(i)] = A[q].x;
-      sim[pad8(i)] = A[q].y;
-      sre[pad8(i + 1)] = B[q].x;
-      sim[pad8(i + 1)] = B[q].y;
+      stg[pad8(i)] = A[q];
+      stg[pad8(i + 1)] = B[q];
     }
   }
 }
@@ -151,32 +158,34 @@ __device__ __forceinline__ void pair_to_staging(cx<float>* v, float* re, float* 
 //   a_0 = sqrt(1/N), a_k = sqrt(2/N), Va / Vb the spectra of the reordered
 //   real / imaginary parts (separated from one complex FFT).
 // `ew` is the LDS table E[0..N).
-template <int N, int PPT>
-__device__ __forceinline__ void dct_fwd_group(cx<float>* reg, float* re, float* im, int t,
+// LEAD: synchronise before the first LDS write (not needed right after
+// fft_group, which ends with a barrier after its last LDS read).
+template <int N, int PPT, bool LEAD = true>
+__device__ __forceinline__ void dct_fwd_group(cx<float>* reg, cx<float>* cb, int t,
                                               const cx<float>* tw, const cx<float>* ew) {
   constexpr int T = N / PPT;
   const float a0 = __builtin_sqrtf(1.0f / N), a1 = __builtin_sqrtf(2.0f / N);
-  group_sync<T>();
+  if constexpr (LEAD) group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int n = t + T * q;
     int p = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
-    stc(re, im, p, reg[q]);
+    stc(cb, p, reg[q]);
   }
   group_sync<T>();
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) reg[q] = ldc(re, im, t + T * q);
-  fft_group<N, PPT, +1>(reg, re, im, t, tw);
+  for (int q = 0; q < PPT; ++q) reg[q] = ldc(cb, t + T * q);
+  fft_group<N, PPT, +1>(reg, cb, t, tw);
   group_sync<T>();
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, reg[q]);
+  for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, reg[q]);
   group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
     int kk = (N - k) & (N - 1);
-    cx<float> V = ldc(re, im, k);
-    cx<float> Vc = conjx(ldc(re, im, kk));
+    cx<float> V = ldc(cb, k);
+    cx<float> Vc = conjx(ldc(cb, kk));
     cx<float> s = V + Vc, d = V - Vc;
     // Va = s / 2, Vb = d / 2i = (d.y, -d.x) / 2; fold the 1/2 into alpha
     cx<float> e = ew[k];
@@ -188,40 +197,40 @@ __device__ __forceinline__ void dct_fwd_group(cx<float>* reg, float* re, float* 
 // Inverse (DCT-III, orthonormal) of a complex coefficient sequence Y:
 //   V[k] = conj(E[k]) / N * (Y[k] / a_k - i Y[N-k] / a_{N-k}),  V[0] = Y[0] / (N a_0),
 // then an inverse FFT and the inverse even/odd reordering.
-template <int N, int PPT>
-__device__ __forceinline__ void dct_inv_group(cx<float>* reg, float* re, float* im, int t,
+template <int N, int PPT, bool LEAD = true>
+__device__ __forceinline__ void dct_inv_group(cx<float>* reg, cx<float>* cb, int t,
                                               const cx<float>* tw, const cx<float>* ew) {
   constexpr int T = N / PPT;
   const float ia0 = __builtin_sqrtf((float)N) / N, ia1 = __builtin_sqrtf(0.5f * N) / N;
-  group_sync<T>();
+  if constexpr (LEAD) group_sync<T>();
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, reg[q]);
+  for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, reg[q]);
   group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
-    cx<float> Yk = ldc(re, im, k);
+    cx<float> Yk = ldc(cb, k);
     cx<float> a;
     if (k == 0) {
       a = cx<float>{Yk.x * ia0, Yk.y * ia0};
     } else {
-      cx<float> Yn = ldc(re, im, N - k);
+      cx<float> Yn = ldc(cb, N - k);
       a = cx<float>{(Yk.x + Yn.y) * ia1, (Yk.y - Yn.x) * ia1};   // Yk - i Yn
     }
     cx<float> e = ew[k];
     reg[q] = cmulc(a, e);   // a * conj(E[k])
   }
-  fft_group<N, PPT, -1>(reg, re, im, t, tw);
+  fft_group<N, PPT, -1>(reg, cb, t, tw);
   group_sync<T>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int m = t + T * q;
     int pos = (m < N / 2) ? 2 * m : 2 * N - 2 * m - 1;
-    stc(re, im, pos, reg[q]);
+    stc(cb, pos, reg[q]);
   }
   group_sync<T>();
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) reg[q] = ldc(re, im, t + T * q);
+  for (int q = 0; q < PPT; ++q) reg[q] = ldc(cb, t + T * q);
 }
 
 
@@ -246,16 +255,16 @@ __global__ void k_row_r2c(const Re* __restrict__ in, cx<Re>* __restrict__ out, i
   int p, row0;
   if (STAGED) {
     const int tiles = N1 / RT;
-    p = blockIdx.x / tiles;
-    row0 = (blockIdx.x % tiles) * RT;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    p = b / tiles;
+    row0 = (b % tiles) * RT;
   } else {
     const int pairs = N1 / 2;
     p = blockIdx.x / pairs;
     row0 = (blockIdx.x % pairs) * 2;
   }
   const int ra = row0 + 2 * g;
-  Re* re = lds + g * 2 * padded_len(N2);
-  Re* im = re + padded_len(N2);
+  cx<Re>* cb = reinterpret_cast<cx<Re>*>(lds) + g * padded_len(N2);
   const Re* xa = in + ((size_t)p * N1 + ra) * N2;
   const Re* xb = xa + N2;
   cx<Re> v[PPT];
@@ -265,24 +274,22 @@ __global__ void k_row_r2c(const Re* __restrict__ in, cx<Re>* __restrict__ out, i
     v[q] = cx<Re>{xa[n], xb[n]};
   }
   __syncthreads();   // twiddle table ready
-  fft_group<N2, PPT, +1>(v, re, im, t, tw);
+  fft_group<N2, PPT, +1>(v, cb, t, tw);
   if constexpr (STAGED) {
-    float* sre = lds;
-    float* sim = lds + pad8_len(H2 * RT);
-    pair_to_staging<N2, PPT>(v, re, im, sre, sim, g, t);
+    cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+    pair_to_staging<N2, PPT>(v, cb, stg, g, t);
     __syncthreads();
-    staging_to_tile(out + rt_tile_base(p, row0, N1, H2), sre, sim, H2 * RT);
+    staging_to_tile(out + rt_tile_base(p, row0, N1, H2), stg, H2 * RT);
   } else {
-    group_sync<T>();
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+    for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
     group_sync<T>();
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       int k = t + T * q;
       if (k <= N2 / 2) {
-        cx<Re> Z = ldc(re, im, k);
-        cx<Re> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
+        cx<Re> Z = ldc(cb, k);
+        cx<Re> Zc = conjx(ldc(cb, (N2 - k) & (N2 - 1)));
         cx<Re> s = Z + Zc, d = Z - Zc;
         out[rt_idx(p, ra, k, N1, H2)] = cx<Re>{Re(0.5) * s.x, Re(0.5) * s.y};
         out[rt_idx(p, ra + 1, k, N1, H2)] = cx<Re>{Re(0.5) * d.y, Re(-0.5) * d.x};
@@ -304,18 +311,17 @@ __global__ void k_row_c2r(const cx<float>* __restrict__ in, float* __restrict__ 
   float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
-  const int p = blockIdx.x / tiles, row0 = (blockIdx.x % tiles) * RT;
-  float* re = lds + g * 2 * padded_len(N2);
-  float* im = re + padded_len(N2);
-  float* sre = lds;
-  float* sim = lds + pad8_len(H2 * RT);
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = b / tiles, row0 = (b % tiles) * RT;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   lds_load_table(tw, twg, N2);
-  tile_to_staging(in + rt_tile_base(p, row0, N1, H2), sre, sim, H2 * RT);
+  tile_to_staging(in + rt_tile_base(p, row0, N1, H2), stg, H2 * RT);
   __syncthreads();
   cx<float> v[PPT];
-  staging_to_pair<N2, PPT>(v, sre, sim, g, t);
+  staging_to_pair<N2, PPT>(v, stg, g, t);
   __syncthreads();   // staging aliases the group scratch
-  fft_group<N2, PPT, -1>(v, re, im, t, tw);
+  fft_group<N2, PPT, -1>(v, cb, t, tw);
   float* xa = out + ((size_t)p * N1 + row0 + 2 * g) * N2;
   float* xb = xa + N2;
 #pragma unroll
@@ -348,17 +354,16 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<Re>* tw = reinterpret_cast<cx<Re>*>(smem_raw);
   Re* lds = reinterpret_cast<Re*>(smem_raw) + 2 * N1;
-  const int k2 = blockIdx.x;
+  const int k2 = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
-  Re* re = lds + g * 2 * PL;
-  Re* im = re + PL;
+  cx<Re>* cb = reinterpret_cast<cx<Re>*>(lds) + g * PL;
   lds_load_table(tw, twg, N1);
   cx<Re> v[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q)
     v[q] = g < Pin ? in[rt_idx(g, t + T * q, k2, N1, H2)] : cx<Re>{Re(0), Re(0)};
   __syncthreads();
-  fft_group<N1, PPT, +1>(v, re, im, t, tw);
+  fft_group<N1, PPT, +1>(v, cb, t, tw);
   const size_t F = (size_t)N1 * H2;
   if constexpr (OP == OP_SPEC) {
     cx<Re>* out = reinterpret_cast<cx<Re>*>(outv);
@@ -368,14 +373,13 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
     }
     return;
   } else {
-    group_sync<T>();
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
-    group_sync<T>();
+    for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
+    __syncthreads();
     // per-frequency map; each thread owns whole frequencies
     for (int k1 = threadIdx.x; k1 < N1; k1 += blockDim.x) {
       cx<Re> xin[8];
-      for (int j = 0; j < Pin; ++j) xin[j] = ldc(lds + j * 2 * PL, lds + j * 2 * PL + PL, k1);
+      for (int j = 0; j < Pin; ++j) xin[j] = ldc(reinterpret_cast<const cx<Re>*>(lds) + j * PL, k1);
       const size_t f = (size_t)k2 * N1 + k1;
       for (int o = 0; o < Pout; ++o) {
         cx<Re> acc = {Re(0), Re(0)};
@@ -388,15 +392,15 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
         if (OP == OP_XHAT0) {
           reinterpret_cast<cx<Re>*>(outv)[(size_t)o * F + f] = acc;
         } else {
-          stc(lds + o * 2 * PL, lds + o * 2 * PL + PL, k1, acc);
+          stc(reinterpret_cast<cx<Re>*>(lds) + o * PL, k1, acc);
         }
       }
     }
     if constexpr (OP == OP_XHAT0) return;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) v[q] = ldc(re, im, t + T * q);
-    fft_group<N1, PPT, -1>(v, re, im, t, tw);
+    for (int q = 0; q < PPT; ++q) v[q] = ldc(cb, t + T * q);
+    fft_group<N1, PPT, -1>(v, cb, t, tw);
     cx<Re>* out = reinterpret_cast<cx<Re>*>(outv);
     if (g < Pout) {
 #pragma unroll
@@ -437,15 +441,14 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   float* lds = reinterpret_cast<float*>(smem_raw) + 4 * N2;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
-  const int s = blockIdx.x / tiles, row0 = (blockIdx.x % tiles) * RT;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b / tiles, row0 = (b % tiles) * RT;
   const int ra = row0 + 2 * g;
-  float* re = lds + g * 2 * padded_len(N2);
-  float* im = re + padded_len(N2);
-  float* sre = lds;
-  float* sim = lds + pad8_len(H2 * RT);
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   lds_load_table(tw, twg, N2);
   if (mode != ROW_FINAL) lds_load_table(ew, ewg, N2);
-  tile_to_staging(Yin + rt_tile_base(s, row0, N1, H2), sre, sim, H2 * RT);
+  tile_to_staging(Yin + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
   // prefetch the state of rows a, b (latency overlaps the two FFTs below)
   float* va = vstate + ((size_t)s * N1 + ra) * N2;
   float* vb = va + N2;
@@ -462,9 +465,9 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   }
   __syncthreads();
   cx<float> v[PPT];
-  staging_to_pair<N2, PPT>(v, sre, sim, g, t);
+  staging_to_pair<N2, PPT>(v, stg, g, t);
   __syncthreads();   // staging aliases the group scratch
-  fft_group<N2, PPT, -1>(v, re, im, t, tw);
+  fft_group<N2, PPT, -1>(v, cb, t, tw);
   if (mode == ROW_FINAL) {
     float* xa = xout + ((size_t)s * N1 + ra) * N2;
     float* xb = xa + N2;
@@ -476,7 +479,7 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     }
     return;
   }
-  dct_fwd_group<N2, PPT>(v, re, im, t, tw, ew);
+  dct_fwd_group<N2, PPT, false>(v, cb, t, tw, ew);
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
@@ -486,11 +489,11 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     vb[k] = nb;
     v[q] = cx<float>{2.f * soft_f(na, kappa) - na, 2.f * soft_f(nb, kappa) - nb};
   }
-  dct_inv_group<N2, PPT>(v, re, im, t, tw, ew);
-  fft_group<N2, PPT, +1>(v, re, im, t, tw);
-  pair_to_staging<N2, PPT>(v, re, im, sre, sim, g, t);
+  dct_inv_group<N2, PPT>(v, cb, t, tw, ew);
+  fft_group<N2, PPT, +1>(v, cb, t, tw);
+  pair_to_staging<N2, PPT>(v, cb, stg, g, t);
   __syncthreads();
-  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), sre, sim, H2 * RT);
+  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
 }
 
 // Row pass of one ADMM iteration for the anisotropic TV prior on every plane
@@ -532,28 +535,23 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
-  const int s = blockIdx.x / tiles, row0 = (blockIdx.x % tiles) * RT;
-  float* re = lds + g * 2 * padded_len(N2);
-  float* im = re + padded_len(N2);
-  float* sre = lds;
-  float* sim = lds + pad8_len(H2 * NR);
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b / tiles, row0 = (b % tiles) * RT;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   lds_load_table(tw, twg, N2);
   // stage rows r0-1 .. r0+RT ([k2][NR] order); own rows come from one tile
   {
     const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
     for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
       const int k2 = i / RT, r = i % RT;
-      cx<float> z = tile[i];
-      sre[pad8(k2 * NR + r + 1)] = z.x;
-      sim[pad8(k2 * NR + r + 1)] = z.y;
+      stg[pad8(k2 * NR + r + 1)] = tile[i];
     }
     const int lo = (row0 - 1 + N1) % N1, hi = (row0 + RT) % N1;
     for (int i = threadIdx.x; i < 2 * H2; i += blockDim.x) {
       const int k2 = i % H2, h = i / H2;
-      cx<float> z = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
       const int r = h ? NR - 1 : 0;
-      sre[pad8(k2 * NR + r)] = z.x;
-      sim[pad8(k2 * NR + r)] = z.y;
+      stg[pad8(k2 * NR + r)] = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
     }
   }
   __syncthreads();
@@ -565,14 +563,14 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     int kk = k <= N2 / 2 ? k : N2 - k;
     float sg = k <= N2 / 2 ? 1.f : -1.f;
     int i = kk * NR + 2 * g;
-    cx<float> A = {sre[pad8(i)], sg * sim[pad8(i)]};
-    cx<float> B = {sre[pad8(i + 1)], sg * sim[pad8(i + 1)]};
+    cx<float> A = stg[pad8(i)], B = stg[pad8(i + 1)];
+    A.y *= sg;
+    B.y *= sg;
     v[q] = cx<float>{A.x - B.y, A.y + B.x};
   }
   __syncthreads();
-  fft_group<N2, PPT, -1>(v, re, im, t, tw);
-  // x rows -> LDS [NR][N2]
-  __syncthreads();
+  fft_group<N2, PPT, -1>(v, cb, t, tw);
+  // x rows -> LDS [NR][N2] (fft_group ended with a barrier)
   float* X = lds;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -635,23 +633,21 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     v[q] = cx<float>{ga, gb};
   }
   __syncthreads();
-  fft_group<N2, PPT, +1>(v, re, im, t, tw);
+  fft_group<N2, PPT, +1>(v, cb, t, tw);
   // split into half spectra of the two rows and stage as tile rows 2g, 2g+1
-  float* ore = lds;
-  float* oim = lds + pad8_len(H2 * RT);
+  cx<float>* ostg = reinterpret_cast<cx<float>*>(lds);
   {
     constexpr int QH2 = (N2 / 2) / T + 1;
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+    for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
     __syncthreads();
     cx<float> A[QH2], B[QH2];
 #pragma unroll
     for (int q = 0; q < QH2; ++q) {
       int k = t + T * q;
       if (k <= N2 / 2) {
-        cx<float> Z = ldc(re, im, k);
-        cx<float> Zc = conjx(ldc(re, im, (N2 - k) & (N2 - 1)));
+        cx<float> Z = ldc(cb, k);
+        cx<float> Zc = conjx(ldc(cb, (N2 - k) & (N2 - 1)));
         cx<float> sm = Z + Zc, d = Z - Zc;
         A[q] = cx<float>{0.5f * sm.x, 0.5f * sm.y};
         B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
@@ -664,16 +660,14 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
         int k = t + T * q;
         if (k <= N2 / 2) {
           int i = k * RT + 2 * g;
-          ore[pad8(i)] = A[q].x;
-          oim[pad8(i)] = A[q].y;
-          ore[pad8(i + 1)] = B[q].x;
-          oim[pad8(i + 1)] = B[q].y;
+          ostg[pad8(i)] = A[q];
+          ostg[pad8(i + 1)] = B[q];
         }
       }
     }
   }
   __syncthreads();
-  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), ore, oim, H2 * RT);
+  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), ostg, H2 * RT);
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
@@ -702,13 +696,12 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
   cx<float>* ew = tw + N1;
   float* lds = reinterpret_cast<float*>(smem_raw) + 4 * N1;
-  const int k2 = blockIdx.x;
+  const int k2 = xcd_remap(blockIdx.x, gridDim.x);
   // plane index; uniform across a wavefront when a group spans whole waves
   const int g = (T % 64 == 0) ? __builtin_amdgcn_readfirstlane(threadIdx.x / T)
                               : (int)(threadIdx.x / T);
   const int t = threadIdx.x % T;
-  float* re = lds + g * 2 * PL;
-  float* im = re + PL;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * PL;
   const size_t F = (size_t)N1 * H2;
   const size_t f0 = (size_t)k2 * N1 + t;
   // solve tables: x_hat0 of plane g, row g of A
@@ -740,21 +733,20 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   }
   __syncthreads();
   if (!zero_in) {
-    if constexpr (DCT) dct_inv_group<N1, PPT>(v, re, im, t, tw, ew);
-    fft_group<N1, PPT, +1>(v, re, im, t, tw);
-    __syncthreads();
+    if constexpr (DCT) dct_inv_group<N1, PPT, false>(v, cb, t, tw, ew);
+    fft_group<N1, PPT, +1>(v, cb, t, tw);
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) stc(re, im, t + T * q, v[q]);
+    for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int k1 = t + T * q;
-      cx<float> gg = ldc(re, im, k1);
+      cx<float> gg = ldc(cb, k1);
       cx<float> acc = {pxh[q].x + pdg[q] * gg.x, pxh[q].y + pdg[q] * gg.y};
 #pragma unroll
       for (int jj = 0; jj < S - 1; ++jj) {
         const int j = jj < g ? jj : jj + 1;
-        acc = acc + cmul(pao[jj][q], ldc(lds + j * 2 * PL, lds + j * 2 * PL + PL, k1));
+        acc = acc + cmul(pao[jj][q], ldc(reinterpret_cast<const cx<float>*>(lds) + j * PL, k1));
       }
       v[q] = acc;
     }
@@ -763,9 +755,9 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
 #pragma unroll
     for (int q = 0; q < PPT; ++q) v[q] = pxh[q];
   }
-  fft_group<N1, PPT, -1>(v, re, im, t, tw);
+  fft_group<N1, PPT, -1>(v, cb, t, tw);
   if constexpr (DCT) {
-    if (dct_out) dct_fwd_group<N1, PPT>(v, re, im, t, tw, ew);
+    if (dct_out) dct_fwd_group<N1, PPT, false>(v, cb, t, tw, ew);
   }
 #pragma unroll
   for (int q = 0; q < PPT; ++q) Yout[rt_idx(g, t + T * q, k2, N1, H2)] = v[q];
