@@ -35,14 +35,17 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(which, S, N1, N2, prior):
     """Compulsory HBM bytes of one launch of a solver kernel (FP32 data).
 
-    Row pass (DCT): read the column-pass output Y and the state v, write v and
-    the next row spectrum G: 2 * S N1 H2 * 8 + 2 * S N1 N2 * 4.
+    Row pass: read the column-pass output Y (S N1 H2 complex), read and write
+    the state (one float per voxel and constraint component: 1 for DCT, 2 for
+    TV2D), write the next row spectrum G (S N1 H2 complex):
+        2 * S N1 H2 * 8 + 2 * comps * S N1 N2 * 4.
+    (The TV halo rows, 2 extra rows per 8-row tile, are not counted.)
     Column pass: read G, the packed Hermitian A (S reals + S(S-1)/2 complex per
     frequency) and x_hat0, write Y: F * (8S + 4S + 8 S(S-1)/2 + 8S + 8S)."""
     H2 = N2 // 2 + 1
     F = N1 * H2
     if which == 0:
-        comps = 1
+        comps = 1 if prior == "dct2d" else 2
         return 2 * S * F * 8 + 2 * comps * S * N1 * N2 * 4
     return F * (8 * S + 4 * S + 8 * (S * (S - 1) // 2) + 8 * S + 8 * S)
 
@@ -86,37 +89,19 @@ def cpu_baseline(psf, y, lam, rho, beta, n_iter):
                       f"per-solve setup excluded; {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--iters", type=int, default=100)
-    ap.add_argument("--N", type=int, default=1024)
-    ap.add_argument("--bands", type=int, default=3)
-    ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the reconstruction of one problem runs on a single "
-              "device (multi-GPU sharding is a design note only); run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-    dev = torch.device("cuda:0")
-    N, K, S = args.N, args.bands, args.bands
-    lam, rho, beta = 1e-2, 0.1, 1.0
-    x, psf, noise, psf_t, x_t, noise_t = make_workload(N, K, S, dev)
-    plan = cip.Plan(psf_t, "dct2d", rho, lam, beta)
-    # measurements: y = H x + w, with H applied by the library and sigma_k set
-    # for 30 dB SNR per measurement
+PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0)}
+
+
+def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
+    lam, rho, beta = PRIOR_PARAMS[prior]
+    plan = cip.Plan(psf_t, prior, rho, lam, beta)
+    # measurements: y = H x + w, H applied by the library, sigma_k for 30 dB
     hx = plan.forward(x_t)
     sig = hx.pow(2).mean(dim=(1, 2)).sqrt() * 10 ** (-30.0 / 20.0)
     y_t = (hx + sig[:, None, None] * noise_t).contiguous()
     out = torch.empty_like(x_t)
-    stream = torch.cuda.current_stream()
-    print(f"[bench] N={N} K=S={S} iters={args.iters} warmup={args.warmup} steps={args.steps}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {prior}: N={N} K=S={S} iters={args.iters} warmup={args.warmup} "
+          f"steps={args.steps}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.solve(y_t, args.iters, out=out)
     torch.cuda.synchronize()
@@ -127,11 +112,41 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     value = N * N * args.iters * args.steps / dt / 1e6
-    print(f"[bench] {ms_step:.3f} ms/solve, {value:.1f} Mpixel*iter/s", file=sys.stderr, flush=True)
-
-    # per-kernel device time (HIP events on the launch stream)
+    print(f"[bench] {prior}: {ms_step:.3f} ms/solve, {value:.1f} Mpixel*iter/s", file=sys.stderr,
+          flush=True)
+    # per-kernel device time (HIP events recorded on the launch stream)
     times = {w: plan.time_kernel(w, args.kernel_reps) for w in (0, 1)}
-    names = {0: "k_admm_row_dct (row pass)", 1: "k_admm_col<DCT> (column pass + solve)"}
+    names = {0: f"row pass ({'k_admm_row_dct' if prior == 'dct2d' else 'k_admm_row_tv'})",
+             1: f"column pass + per-frequency solve (k_admm_col)"}
+    print(f"[bench] {prior}: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
+          flush=True)
+    return plan, y_t, lam, rho, beta, value, ms_step, times, names
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--bands", type=int, default=3)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tv", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: one reconstruction runs on a single device "
+              "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    N, K, S = args.N, args.bands, args.bands
+    x, psf, noise, psf_t, x_t, noise_t = make_workload(N, K, S, dev)
+    plan, y_t, lam, rho, beta, value, ms_step, times, names = run_prior(
+        "dct2d", N, K, S, args, psf_t, x_t, noise_t)
     dom = max(times, key=times.get)
     byt = algorithmic_bytes(dom, S, N, N, "dct2d")
     ach = byt / (times[dom] * 1e-6) / 1e9
@@ -142,8 +157,21 @@ def main():
             "other_kernel": {"name": names[1 - dom], "avg_us": round(times[1 - dom], 3),
                              "algorithmic_bytes_per_launch":
                                  algorithmic_bytes(1 - dom, S, N, N, "dct2d")}}
-    print(f"[bench] kernels: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
-          flush=True)
+    tv = None
+    if not args.no_tv:
+        _, _, _, _, _, tv_value, tv_ms, tv_times, tv_names = run_prior(
+            "tv2d", N, K, S, args, psf_t, x_t, noise_t)
+        tv = {"prior": "tv2d (lambda=1e-3, rho=1e-2, beta=1)", "value": round(tv_value, 1),
+              "ms_per_step": round(tv_ms, 4),
+              "kernels_avg_us": {tv_names[w]: round(tv_times[w], 3) for w in tv_times},
+              "algorithmic_bytes_per_launch": {tv_names[w]: algorithmic_bytes(w, S, N, N, "tv2d")
+                                               for w in tv_times}}
+    if args.copy_calib:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     cpu = None
     if not args.no_cpu:
         y = y_t.double().cpu().numpy()
@@ -167,6 +195,7 @@ def main():
                    "prior": "dct2d", "lambda": lam, "rho": rho, "beta": beta},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "tv2d": tv,
     }
     print(json.dumps(rec), flush=True)
 

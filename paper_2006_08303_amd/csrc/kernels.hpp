@@ -554,6 +554,27 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
       stg[pad8(k2 * NR + r)] = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
     }
   }
+  // prefetch the state this thread updates below (latency overlaps the FFT)
+  constexpr unsigned NT = (PAIRS + 1) * T;     // threads per work-group
+  const unsigned plane = (unsigned)N1 * N2;
+  const unsigned cstride = (unsigned)S * plane;  // component stride within a buffer
+  const unsigned m1 = (unsigned)N1 - 1;           // N1 is a power of two
+  constexpr int NE = (RT + 1) * N2;
+  constexpr int PER = (NE + NT - 1) / NT;
+  float pov[PER], poh[PER];
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const unsigned e = threadIdx.x + it * NT;
+    pov[it] = 0.f;
+    poh[it] = 0.f;
+    if (e < (unsigned)NE && !first) {
+      const unsigned lr = e / N2, n2 = e % N2;
+      const unsigned n1 = (unsigned)(row0 - 1 + (int)lr) & m1;
+      const unsigned o = s * plane + n1 * N2 + n2;
+      pov[it] = vin[o];
+      if (lr > 0) poh[it] = vin[cstride + o];
+    }
+  }
   __syncthreads();
   // group g: local rows 2g, 2g+1 (global r0-1+2g, r0+2g)
   cx<float> v[PPT];
@@ -579,27 +600,21 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   }
   __syncthreads();
   // state update for local rows 0 (halo, vertical only) .. RT
-  const size_t plane = (size_t)N1 * N2;
-  const size_t cstride = (size_t)S * plane;   // component stride within a buffer
-  constexpr int NE = (RT + 1) * N2;
-  constexpr int PER = (NE + (PAIRS + 1) * T - 1) / ((PAIRS + 1) * T);
   float qv[PER], qh[PER];
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
-    const int e = threadIdx.x + it * blockDim.x;
-    if (e < NE) {
-      const int lr = e / N2, n2 = e % N2;   // lr 0 = halo row r0-1
-      const int n1 = (row0 - 1 + lr + N1) % N1;
-      const float x0 = X[lr * N2 + n2];
-      const float wv = X[(lr + 1) * N2 + n2] - x0;
-      const size_t o = (size_t)s * plane + (size_t)n1 * N2 + n2;
-      const float ov = first ? 0.f : vin[o];
-      const float nv = wv + clip_f(ov, kappa);
+    const unsigned e = threadIdx.x + it * NT;
+    if (e < (unsigned)NE) {
+      const unsigned lr = e / N2, n2 = e % N2;   // lr 0 = halo row r0-1
+      const unsigned n1 = (unsigned)(row0 - 1 + (int)lr) & m1;
+      const float x0 = X[e];
+      const float wv = X[e + N2] - x0;
+      const unsigned o = s * plane + n1 * N2 + n2;
+      const float nv = wv + clip_f(pov[it], kappa);
       qv[it] = 2.f * soft_f(nv, kappa) - nv;
       if (lr > 0) {
         const float wh = X[lr * N2 + ((n2 + 1) & (N2 - 1))] - x0;
-        const float oh = first ? 0.f : vin[cstride + o];
-        const float nh = wh + clip_f(oh, kappa);
+        const float nh = wh + clip_f(poh[it], kappa);
         qh[it] = 2.f * soft_f(nh, kappa) - nh;
         vout[o] = nv;
         vout[cstride + o] = nh;
@@ -611,10 +626,10 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   float* QH = lds + (RT + 1) * N2;    // [RT + 1][N2], row 0 unused
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
-    const int e = threadIdx.x + it * blockDim.x;
-    if (e < NE) {
+    const unsigned e = threadIdx.x + it * NT;
+    if (e < (unsigned)NE) {
       QV[e] = qv[it];
-      if (e >= N2) QH[e] = qh[it];
+      if (e >= (unsigned)N2) QH[e] = qh[it];
     }
   }
   __syncthreads();
