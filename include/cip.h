@@ -28,8 +28,8 @@
  *   - Return value: CIP_OK (0) on success or a negative CIP_E* code; the
  *     message of the last failure on the calling thread is available from
  *     cip_last_error(). A failed call leaves the plan usable.
- *   - Supported grids: N1 and N2 powers of two with 16 <= N <= 2048; N1 must
- *     also be a multiple of 8 (the row tile). 1 <= K, S <= 8.
+ *   - Supported grids: N1 and N2 powers of two with 16 <= N <= 2048.
+ *     1 <= K, S <= 8 (analysis priors); the patch prior needs S <= 4.
  */
 #ifndef CIP_H_
 #define CIP_H_
@@ -60,11 +60,23 @@ typedef enum {
   CIP_PRIOR_TV3D = 1,
   /* Analysis prior with T = orthonormal 2D DCT-II of every plane. */
   CIP_PRIOR_DCT2D = 2,
+  /* Synthesis prior with a patch dictionary (Eq. patch_based): Q x Q x S
+   * patches spanning all planes (Q = 8), extracted circularly at stride 4
+   * (P^T P = 4 I), common dictionary D with A atoms; Algorithm 2 with the
+   * sparse-code update of Eq. solz_patch2 on BF16 MFMA (FP32 accumulation). */
+  CIP_PRIOR_PATCH = 3,
 } cip_prior_kind;
 
 typedef struct {
-  int kind;       /* cip_prior_kind                                          */
-  double beta;    /* data-fidelity weight beta of Eq. rls (> 0)              */
+  int kind;             /* cip_prior_kind                                     */
+  double beta;          /* data-fidelity weight beta of Eq. rls (> 0)         */
+  /* CIP_PRIOR_PATCH only (ignored otherwise):                                */
+  const float* dict;    /* device [n][A] float32, row-major, n = Q*Q*S; row
+                           s*Q*Q + a*Q + b is pixel (a, b) of plane s; column
+                           k is atom k. Read during cip_plan_create only.     */
+  int n_atoms;          /* A: 64, 128 or 256                                   */
+  int patch_q;          /* Q: must be 8                                        */
+  int patch_stride;     /* st: must be 4                                       */
 } cip_prior_desc;
 
 typedef struct cip_plan_s* cip_plan_t;
@@ -79,7 +91,10 @@ int cip_plan_workspace_bytes(int K, int S, int N1, int N2, const cip_prior_desc*
  * and computes, at every 2D frequency w, the FP64 pseudo-inverse of
  *     Psi(w) = rho tau(w) I + beta Lambda(w)^H Lambda(w)
  * (Alg. 1 step 2; below Eq. solx_Trans_DFT; tau = 1 for a unitary T, the
- * Laplacian symbol for TV; TV3D adds rho times the band path-graph Laplacian).
+ * Laplacian symbol for TV; TV3D adds rho times the band path-graph Laplacian;
+ * for the patch prior Psi = 4 I + beta Lambda^H Lambda, Eq. solx_synt_DFT,
+ * and M1 = D^T (rho I + D D^T)^-1 is formed in FP64 on the host and stored,
+ * with D, in BF16).
  * Eigenvalues below 1e-12 times the largest one at that frequency are treated
  * as zero (minimum-norm x-update where Psi is singular, e.g. the DC block with
  * unit-sum kernels and TV). Results are stored in FP32 in the workspace.
@@ -102,11 +117,14 @@ int cip_forward(cip_plan_t plan, const float* d_x, float* d_y, void* stream);
  * d_x [S][N1][N2]. FP32 FFTs; must not overlap. */
 int cip_adjoint(cip_plan_t plan, const float* d_y, float* d_x, void* stream);
 
-/* Run `iters` >= 1 ADMM iterations (Algorithm 1) from t = u = 0 on the
+/* Run `iters` >= 1 ADMM iterations from t = u = 0 (and z = 0) on the
  * measurements d_y [K][N1][N2] and write x^iters to d_x [S][N1][N2].
- * Per iteration: x-update in the frequency domain (Eq. solx_Trans_DFT),
- * soft thresholding (Eq. solt_trans) and dual update (Eq. subu_trans).
- * A plan runs one solve at a time (its state lives in the workspace). */
+ * Analysis priors (Algorithm 1): x-update in the frequency domain
+ * (Eq. solx_Trans_DFT), soft thresholding (Eq. solt_trans), dual update
+ * (Eq. subu_trans). Patch prior (Algorithm 2): x-update of Eq. solx_synt_DFT,
+ * sparse-code update (Eq. solz_patch2), soft thresholding (Eq. softADMM) and
+ * dual update (Eq. subu_dic). d_x is also used as working storage during the
+ * call. A plan runs one solve at a time (its state lives in the workspace). */
 int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* stream);
 
 /* Release the host-side plan object (the workspace stays the caller's). */
@@ -120,8 +138,9 @@ const char* cip_last_error(void);
  * one kernel of the solver on `stream`, measured with HIP events recorded on
  * that stream. The plan must have run cip_solve at least once (the kernels
  * then operate on its current state). which: 0 = fused row pass of one ADMM
- * iteration, 1 = fused column pass (FFTs + per-frequency solve). Blocks until
- * the timed launches finish. */
+ * iteration, 1 = fused column pass (FFTs + per-frequency solve), 2 = patch
+ * sparse-code update (patch prior only). Blocks until the timed launches
+ * finish. */
 int cip_time_kernel(cip_plan_t plan, int which, int reps, void* stream, double* avg_us);
 
 #ifdef __cplusplus

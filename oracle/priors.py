@@ -154,24 +154,25 @@ class Patches:
         s, a, b = np.meshgrid(np.arange(S), np.arange(Q), np.arange(Q), indexing="ij")
         self._s, self._a, self._b = s.ravel(), a.ravel(), b.ravel()
 
+    def _index(self):
+        """Row / column index of every patch element, shape (n, J)."""
+        if not hasattr(self, "_rows"):
+            i = np.repeat(np.arange(self.J1), self.J2)          # patch row of j
+            j = np.tile(np.arange(self.J2), self.J1)            # patch column of j
+            self._rows = (i[None, :] * self.st + self._a[:, None]) % self.N1
+            self._cols = (j[None, :] * self.st + self._b[:, None]) % self.N2
+        return self._rows, self._cols
+
     def extract(self, x: np.ndarray) -> np.ndarray:
         """X = [P_1 x | ... | P_J x], shape (n, J)."""
-        X = np.empty((self.n, self.J))
-        for i in range(self.J1):
-            for j in range(self.J2):
-                r = (i * self.st + self._a) % self.N1
-                c = (j * self.st + self._b) % self.N2
-                X[:, i * self.J2 + j] = x[self._s, r, c]
-        return X
+        rows, cols = self._index()
+        return x[self._s[:, None], rows, cols]
 
     def adjoint(self, X: np.ndarray) -> np.ndarray:
         """sum_j P_j^T X[:, j] (overlap-add of patches back onto the grid)."""
+        rows, cols = self._index()
         x = np.zeros((self.S, self.N1, self.N2))
-        for i in range(self.J1):
-            for j in range(self.J2):
-                r = (i * self.st + self._a) % self.N1
-                c = (j * self.st + self._b) % self.N2
-                np.add.at(x, (self._s, r, c), X[:, i * self.J2 + j])
+        np.add.at(x, (np.broadcast_to(self._s[:, None], rows.shape), rows, cols), X)
         return x
 
     @property

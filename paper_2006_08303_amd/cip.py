@@ -18,7 +18,9 @@ LIB_PATH = os.environ.get("CIP_LIBRARY_PATH") or os.path.join(_HERE, "libcip.so"
 CIP_PRIOR_TV2D = 0
 CIP_PRIOR_TV3D = 1
 CIP_PRIOR_DCT2D = 2
-PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D}
+CIP_PRIOR_PATCH = 3
+PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
+          "patch": CIP_PRIOR_PATCH}
 
 
 class CipError(RuntimeError):
@@ -28,7 +30,17 @@ class CipError(RuntimeError):
 
 
 class _PriorDesc(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("beta", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("beta", ctypes.c_double),
+                ("dict", ctypes.c_void_p), ("n_atoms", ctypes.c_int),
+                ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int)]
+
+
+def _desc(prior, beta, dictionary=None):
+    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4)
+    if dictionary is not None:
+        d.dict = ctypes.c_void_p(dictionary.data_ptr())
+        d.n_atoms = int(dictionary.shape[1])
+    return d
 
 
 _lib = None
@@ -77,8 +89,9 @@ def _dev_f32(t, shape, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0):
-    desc = _PriorDesc(PRIORS[prior], float(beta))
+def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0):
+    desc = _desc(prior, beta)
+    desc.n_atoms = int(n_atoms)
     n = ctypes.c_size_t()
     _check(lib().cip_plan_workspace_bytes(K, S, N1, N2, ctypes.byref(desc), ctypes.byref(n)))
     return n.value
@@ -87,14 +100,22 @@ def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0):
 class Plan:
     """One problem shape and operator: y_k = sum_s h_{k,s} * x_s.
 
-    psf: float32 CUDA tensor [K, S, N1, N2] (unshifted kernels, origin at [0, 0])."""
+    psf: float32 CUDA tensor [K, S, N1, N2] (unshifted kernels, origin at [0, 0]).
+    dictionary: for prior="patch", float32 CUDA tensor [64 S, A] (atoms as
+    columns, row s*64 + a*8 + b = pixel (a, b) of plane s)."""
 
-    def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, stream=None):
+    def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
+                 stream=None):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
-        desc = _PriorDesc(PRIORS[prior], float(beta))
-        nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta)
+        if prior == "patch":
+            if dictionary is None:
+                raise ValueError("the patch prior needs a dictionary")
+            _dev_f32(dictionary, (64 * self.S, dictionary.shape[1]), "dictionary")
+        desc = _desc(prior, beta, dictionary)
+        nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
+                                 desc.n_atoms)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
         h = ctypes.c_void_p()
         _check(lib().cip_plan_create(self.K, self.S, self.N1, self.N2,

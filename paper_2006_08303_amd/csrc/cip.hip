@@ -15,6 +15,7 @@
 #include "col_pass.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "patch_launch.hpp"
 
 using namespace cip;
 
@@ -54,6 +55,7 @@ struct Layout {
   size_t bufA, bufB;                    // RT staging (max(K,S) planes)
   size_t state;                         // ADMM state
   size_t lam64, rt64, pl64;             // plan-time FP64 scratch
+  size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
   size_t total;
 };
 
@@ -62,12 +64,14 @@ int state_floats_per_voxel(int kind) {
     case CIP_PRIOR_DCT2D: return 1;
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
+    case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
     default: return -1;
   }
 }
 
-Layout make_layout(int K, int S, int N1, int N2, int kind) {
+Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   Layout L{};
+  const int kind = prior->kind;
   const size_t H2 = N2 / 2 + 1, F = (size_t)N1 * H2, P = (size_t)(K > S ? K : S);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -92,6 +96,15 @@ Layout make_layout(int K, int S, int N1, int N2, int kind) {
   L.lam64 = take((size_t)K * S * F * 16);
   L.rt64 = take(F * 16);
   L.pl64 = take((size_t)N1 * N2 * 8);
+  if (kind == CIP_PRIOR_PATCH) {
+    const size_t nv = (size_t)64 * S, na = (size_t)prior->n_atoms;
+    const size_t J = (size_t)(N1 / 4) * (N2 / 4);
+    L.dbf = take(nv * na * 2);
+    L.m1bf = take(na * nv * 2);
+    L.vpatch = take(na * J * 4);
+    L.tbuf = take(patch_tile_buffer_floats(S, N1, N2) * 4);
+    L.rimg = take((size_t)S * N1 * N2 * 4);
+  }
   L.total = o;
   return L;
 }
@@ -104,15 +117,22 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (state_floats_per_voxel(prior->kind) < 0)
     return fail(CIP_EUNSUPPORTED, "unsupported prior kind");
   if (prior->kind == CIP_PRIOR_TV3D)
-    return fail(CIP_EUNSUPPORTED, "this build serves the DCT2D and TV2D priors");
+    return fail(CIP_EUNSUPPORTED, "this build serves the DCT2D, TV2D and patch priors");
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
+  if (prior->kind == CIP_PRIOR_PATCH) {
+    if (prior->patch_q != 8 || prior->patch_stride != 4)
+      return fail(CIP_EUNSUPPORTED, "patch prior: only 8 x 8 x S patches at stride 4");
+    if (!patch_supported(S, prior->n_atoms))
+      return fail(CIP_EUNSUPPORTED, "patch prior: needs S <= 4 and 64, 128 or 256 atoms");
+    if (!patch_grid_ok(N1, N2)) return fail(CIP_EUNSUPPORTED, "patch prior: grid too small");
+  }
   return CIP_OK;
 }
 
 }  // namespace
 
 struct cip_plan_s {
-  int K, S, N1, N2, H2, kind;
+  int K, S, N1, N2, H2, kind, n_atoms;
   double beta, rho, lambda;
   unsigned char* ws;
   Layout L;
@@ -235,6 +255,41 @@ hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+// Algorithm 2 with the patch prior. Per iteration l = 1..L:
+//   x-update (Eq. solx_synt_DFT): row FFT of r = P^T D~ z^{l-1} (r = 0 for
+//   l = 1), column FFT + per-frequency solve + inverse column FFT, inverse
+//   row FFT -> x^l (written to d_x);
+//   for l < L: sparse-code update, soft threshold and dual update on MFMA
+//   (k_patch_z), then r = P^T D~ z^l (k_patch_assemble).
+hipError_t patch_step(cip_plan_t p, const float* x, int first, hipStream_t st) {
+  const Layout& L = p->L;
+  const float kappa = (float)(p->lambda / p->rho);
+  hipError_t e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf),
+                                p->at<const uint16_t>(L.dbf), p->at<const uint16_t>(L.m1bf), p->N1,
+                                p->N2, kappa, first, st);
+  if (e != hipSuccess) return e;
+  return patch_assemble_launch(p->S, p->at<const float>(L.tbuf), p->at<float>(L.rimg), p->N1, p->N2,
+                               st);
+}
+
+hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
+  const Layout& L = p->L;
+  hipError_t e;
+  for (int l = 1; l <= iters; ++l) {
+    if (l > 1) {
+      e = row_r2c<float>(p->at<const float>(L.rimg), p->at<cx<float>>(L.bufA), p->S, p->N1, p->N2,
+                         p->at<const cx<float>>(L.twN2f), st);
+      if (e != hipSuccess) return e;
+    }
+    if ((e = admm_col(p, l == 1 ? 1 : 0, 0, st)) != hipSuccess) return e;
+    e = row_c2r(p->at<const cx<float>>(L.bufB), d_x, p->S, p->N1, p->N2, 1.0f,
+                p->at<const cx<float>>(L.twN2f), st);
+    if (e != hipSuccess) return e;
+    if (l < iters && (e = patch_step(p, d_x, l == 1 ? 1 : 0, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t gram(cip_plan_t p, hipStream_t st) {
   GramArgs a;
   a.K = p->K;
@@ -244,8 +299,11 @@ hipError_t gram(cip_plan_t p, hipStream_t st) {
   a.beta = p->beta;
   a.scale = 1.0 / ((double)p->N1 * (double)p->N2);
   a.rcond = 1e-12;
-  a.wgt = p->rho;
-  a.coefA = p->rho;
+  const bool synth = p->kind == CIP_PRIOR_PATCH;
+  // analysis: Psi = rho tau I + beta L^H L, rhs = b + rho g;
+  // patch synthesis: Psi = c_P I + beta L^H L with c_P = (Q / st)^2 = 4, rhs = b + g
+  a.wgt = synth ? 4.0 : p->rho;
+  a.coefA = synth ? 1.0 : p->rho;
   a.tv_symbol = (p->kind == CIP_PRIOR_TV2D || p->kind == CIP_PRIOR_TV3D) ? 1 : 0;
   a.band_lap = p->kind == CIP_PRIOR_TV3D ? 1 : 0;
   const Layout& L = p->L;
@@ -312,6 +370,59 @@ void dct_table(int N, std::vector<cx<float>>& ew) {
   }
 }
 
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Patch dictionary tables: D (nv x na, row-major) and
+// M1 = D^T (rho I + D D^T)^-1 (na x nv), formed in double precision with a
+// Cholesky factorisation of the nv x nv matrix rho I + D D^T, both rounded to
+// BF16 for the MFMA operands.
+void patch_dictionary_tables(const std::vector<float>& D, int nv, int na, double rho,
+                             std::vector<uint16_t>& dbf, std::vector<uint16_t>& m1bf) {
+  std::vector<double> G((size_t)nv * nv, 0.0);
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double acc = 0.0;
+      for (int a = 0; a < na; ++a) acc += (double)D[(size_t)i * na + a] * D[(size_t)j * na + a];
+      G[(size_t)i * nv + j] = G[(size_t)j * nv + i] = acc + (i == j ? rho : 0.0);
+    }
+  for (int j = 0; j < nv; ++j) {   // in-place Cholesky, lower triangle
+    double d = G[(size_t)j * nv + j];
+    for (int k = 0; k < j; ++k) d -= G[(size_t)j * nv + k] * G[(size_t)j * nv + k];
+    d = std::sqrt(d);
+    G[(size_t)j * nv + j] = d;
+    for (int i = j + 1; i < nv; ++i) {
+      double v = G[(size_t)i * nv + j];
+      for (int k = 0; k < j; ++k) v -= G[(size_t)i * nv + k] * G[(size_t)j * nv + k];
+      G[(size_t)i * nv + j] = v / d;
+    }
+  }
+  // X = (rho I + D D^T)^-1 D  (nv x na); M1 = X^T
+  std::vector<double> X((size_t)nv * na);
+  for (int a = 0; a < na; ++a) {
+    std::vector<double> y(nv);
+    for (int i = 0; i < nv; ++i) {
+      double v = D[(size_t)i * na + a];
+      for (int k = 0; k < i; ++k) v -= G[(size_t)i * nv + k] * y[k];
+      y[i] = v / G[(size_t)i * nv + i];
+    }
+    for (int i = nv - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < nv; ++k) v -= G[(size_t)k * nv + i] * X[(size_t)k * na + a];
+      X[(size_t)i * na + a] = v / G[(size_t)i * nv + i];
+    }
+  }
+  dbf.resize((size_t)nv * na);
+  m1bf.resize((size_t)na * nv);
+  for (size_t i = 0; i < dbf.size(); ++i) dbf[i] = bf16_rne(D[i]);
+  for (int a = 0; a < na; ++a)
+    for (int i = 0; i < nv; ++i) m1bf[(size_t)a * nv + i] = bf16_rne((float)X[(size_t)i * na + a]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -324,7 +435,7 @@ int cip_plan_workspace_bytes(int K, int S, int N1, int N2, const cip_prior_desc*
   int rc = validate(K, S, N1, N2, prior);
   if (rc) return rc;
   if (!bytes) return fail(CIP_EINVAL, "bytes is NULL");
-  *bytes = make_layout(K, S, N1, N2, prior->kind).total;
+  *bytes = make_layout(K, S, N1, N2, prior).total;
   return CIP_OK;
 }
 
@@ -337,7 +448,9 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   if (!(rho > 0.0) || !(lambda >= 0.0)) return fail(CIP_EINVAL, "need rho > 0 and lambda >= 0");
   if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
     return fail(CIP_EINVAL, "workspace must be 256-byte aligned");
-  Layout L = make_layout(K, S, N1, N2, prior->kind);
+  if (prior->kind == CIP_PRIOR_PATCH && !prior->dict)
+    return fail(CIP_EINVAL, "patch prior needs a dictionary");
+  Layout L = make_layout(K, S, N1, N2, prior);
   if (ws_bytes < L.total) return fail(CIP_ENOSPC, "workspace too small");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
@@ -348,6 +461,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->N2 = N2;
   p->H2 = N2 / 2 + 1;
   p->kind = prior->kind;
+  p->n_atoms = prior->kind == CIP_PRIOR_PATCH ? prior->n_atoms : 0;
   p->beta = prior->beta;
   p->rho = rho;
   p->lambda = lambda;
@@ -398,6 +512,17 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     }
   }
   PLAN_HIP(gram(p, st));
+  if (p->kind == CIP_PRIOR_PATCH) {
+    // M1 = D^T (rho I + D D^T)^-1 in FP64 on the host; D and M1 stored as BF16
+    const int nv = 64 * S, na = prior->n_atoms;
+    std::vector<float> D((size_t)nv * na);
+    PLAN_HIP(hipMemcpyAsync(D.data(), prior->dict, D.size() * 4, hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipStreamSynchronize(st));
+    std::vector<uint16_t> dbf, m1bf;
+    patch_dictionary_tables(D, nv, na, rho, dbf, m1bf);
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.dbf), dbf.data(), dbf.size() * 2, hipMemcpyHostToDevice, st));
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.m1bf), m1bf.data(), m1bf.size() * 2, hipMemcpyHostToDevice, st));
+  }
   PLAN_HIP(hipStreamSynchronize(st));
   *out = p;
   return CIP_OK;
@@ -445,6 +570,11 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   HIP_TRY((col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufA), p->at<void>(L.xh0), p->K, p->S,
                                    p->N1, p->H2, p->at<const cx<float>>(L.twN1f),
                                    p->at<const cx<float>>(L.Mm), 0, st)));
+  if (p->kind == CIP_PRIOR_PATCH) {
+    HIP_TRY(solve_patch(p, iters, d_x, st));
+    p->solved_once = true;
+    return CIP_OK;
+  }
   // iteration 1 (t = u = 0): column pass only
   HIP_TRY(admm_col(p, 1, iters > 1 ? 1 : 0, st));
   for (int l = 1; l < iters; ++l) {
@@ -464,7 +594,11 @@ int cip_plan_destroy(cip_plan_t p) {
 int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg_us) {
   if (!p || !avg_us || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
-  if (which < 0 || which > 1) return fail(CIP_EINVAL, "which must be 0 or 1");
+  if (which < 0 || which > 2) return fail(CIP_EINVAL, "which must be 0, 1 or 2");
+  if ((which == 2) != (p->kind == CIP_PRIOR_PATCH))
+    return fail(CIP_EINVAL, "which = 2 times the patch update (patch prior only)");
+  if (p->kind == CIP_PRIOR_PATCH && which == 0)
+    return fail(CIP_EINVAL, "the patch prior has no fused row pass");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -472,7 +606,11 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
   HIP_TRY(hipEventRecord(e0, st));
   for (int r = 0; r < reps; ++r) {
     if (which == 0) HIP_TRY(admm_row(p, 2 + (r & 1), st));
-    else HIP_TRY(admm_col(p, 0, 1, st));
+    else if (which == 1) HIP_TRY(admm_col(p, 0, 1, st));
+    else HIP_TRY(patch_z_launch(p->S, p->n_atoms, p->at<const float>(p->L.rimg),
+                                p->at<float>(p->L.vpatch), p->at<float>(p->L.tbuf),
+                                p->at<const uint16_t>(p->L.dbf), p->at<const uint16_t>(p->L.m1bf),
+                                p->N1, p->N2, (float)(p->lambda / p->rho), 0, st));
   }
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
