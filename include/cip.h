@@ -29,7 +29,7 @@
  *     message of the last failure on the calling thread is available from
  *     cip_last_error(). A failed call leaves the plan usable.
  *   - Supported grids: N1 and N2 powers of two with 16 <= N <= 2048.
- *     1 <= K, S <= 8 (analysis priors); the patch prior needs S <= 4.
+ *     1 <= K, S <= 8; the patch prior needs S <= 4.
  */
 #ifndef CIP_H_
 #define CIP_H_
@@ -65,6 +65,11 @@ typedef enum {
    * (P^T P = 4 I), common dictionary D with A atoms; Algorithm 2 with the
    * sparse-code update of Eq. solz_patch2 on BF16 MFMA (FP32 accumulation). */
   CIP_PRIOR_PATCH = 3,
+  /* Synthesis prior with a convolutional dictionary, 2D-correlation form
+   * (Eq. conv_dic per plane with a common set of M filters of L x L, P = I):
+   * Algorithm 2 with the frequency-domain sparse-code update of
+   * Eqs. solz_DFT / solz_DFT_SM. */
+  CIP_PRIOR_CONV2D = 4,
 } cip_prior_kind;
 
 typedef struct {
@@ -77,6 +82,12 @@ typedef struct {
   int n_atoms;          /* A: 64, 128 or 256                                   */
   int patch_q;          /* Q: must be 8                                        */
   int patch_stride;     /* st: must be 4                                       */
+  /* CIP_PRIOR_CONV2D only (ignored otherwise):                               */
+  const float* filters; /* device [M][L][L] float32, row-major; tap (a, b) acts
+                           at offset (a - L/2, b - L/2). Read during
+                           cip_plan_create only.                              */
+  int n_filters;        /* M: 1 .. 32                                          */
+  int filt_l;           /* L: 1 .. min(N1, N2)                                 */
 } cip_prior_desc;
 
 typedef struct cip_plan_s* cip_plan_t;
@@ -94,7 +105,9 @@ int cip_plan_workspace_bytes(int K, int S, int N1, int N2, const cip_prior_desc*
  * Laplacian symbol for TV; TV3D adds rho times the band path-graph Laplacian;
  * for the patch prior Psi = 4 I + beta Lambda^H Lambda, Eq. solx_synt_DFT,
  * and M1 = D^T (rho I + D D^T)^-1 is formed in FP64 on the host and stored,
- * with D, in BF16).
+ * with D, in BF16; for the convolutional prior Psi = I + beta Lambda^H Lambda
+ * and the filter spectra theta_m with 1 / (rho + sum_m |theta_m|^2) are
+ * formed in FP64).
  * Eigenvalues below 1e-12 times the largest one at that frequency are treated
  * as zero (minimum-norm x-update where Psi is singular, e.g. the DC block with
  * unit-sum kernels and TV). Results are stored in FP32 in the workspace.
@@ -121,9 +134,10 @@ int cip_adjoint(cip_plan_t plan, const float* d_y, float* d_x, void* stream);
  * measurements d_y [K][N1][N2] and write x^iters to d_x [S][N1][N2].
  * Analysis priors (Algorithm 1): x-update in the frequency domain
  * (Eq. solx_Trans_DFT), soft thresholding (Eq. solt_trans), dual update
- * (Eq. subu_trans). Patch prior (Algorithm 2): x-update of Eq. solx_synt_DFT,
- * sparse-code update (Eq. solz_patch2), soft thresholding (Eq. softADMM) and
- * dual update (Eq. subu_dic). d_x is also used as working storage during the
+ * (Eq. subu_trans). Synthesis priors (Algorithm 2): x-update of
+ * Eq. solx_synt_DFT, sparse-code update (Eq. solz_patch2 for patches,
+ * Eqs. solz_DFT / solz_DFT_SM for the convolutional dictionary), soft
+ * thresholding (Eq. softADMM) and dual update (Eq. subu_dic). d_x is also used as working storage during the
  * call. A plan runs one solve at a time (its state lives in the workspace). */
 int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* stream);
 
@@ -139,7 +153,9 @@ const char* cip_last_error(void);
  * that stream. The plan must have run cip_solve at least once (the kernels
  * then operate on its current state). which: 0 = fused row pass of one ADMM
  * iteration, 1 = fused column pass (FFTs + per-frequency solve), 2 = patch
- * sparse-code update (patch prior only). Blocks until the timed launches
+ * sparse-code update (patch prior) or frequency pass (convolutional prior).
+ * For the convolutional prior 0 is its row pass over the M*S code planes and
+ * 1 the batched forward column FFT of those planes. Blocks until the timed launches
  * finish. */
 int cip_time_kernel(cip_plan_t plan, int which, int reps, void* stream, double* avg_us);
 

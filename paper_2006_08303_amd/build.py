@@ -1,7 +1,8 @@
 """Compile the HIP library for gfx950 (hipcc, in-tree).
 
 Translation units: csrc/cip.hip (C ABI, plan, operators, row passes),
-csrc/patch.hip (patch-dictionary MFMA kernels) and one csrc/col_pass.hip
+csrc/patch.hip (patch-dictionary MFMA kernels), csrc/conv.hip
+(convolutional-dictionary kernels) and one csrc/col_pass.hip
 instance per supported column length. They are compiled in
 parallel and linked into paper_2006_08303_amd/libcip.so.
 """
@@ -29,7 +30,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     extra = [f"-D{d}" for d in defines]
     tmpdir = tempfile.mkdtemp(prefix="cipbuild_")
     jobs = [(os.path.join(CSRC, "cip.hip"), os.path.join(tmpdir, "cip.o"), []),
-            (os.path.join(CSRC, "patch.hip"), os.path.join(tmpdir, "patch.o"), [])]
+            (os.path.join(CSRC, "patch.hip"), os.path.join(tmpdir, "patch.o"), []),
+            (os.path.join(CSRC, "conv.hip"), os.path.join(tmpdir, "conv.o"), [])]
     for n in SIZES:
         jobs.append((os.path.join(CSRC, "col_pass.hip"), os.path.join(tmpdir, f"col_{n}.o"),
                      [f"-DCIP_COL_N={n}"]))

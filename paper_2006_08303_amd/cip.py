@@ -19,8 +19,9 @@ CIP_PRIOR_TV2D = 0
 CIP_PRIOR_TV3D = 1
 CIP_PRIOR_DCT2D = 2
 CIP_PRIOR_PATCH = 3
+CIP_PRIOR_CONV2D = 4
 PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
-          "patch": CIP_PRIOR_PATCH}
+          "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D}
 
 
 class CipError(RuntimeError):
@@ -32,14 +33,20 @@ class CipError(RuntimeError):
 class _PriorDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("beta", ctypes.c_double),
                 ("dict", ctypes.c_void_p), ("n_atoms", ctypes.c_int),
-                ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int)]
+                ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int),
+                ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
+                ("filt_l", ctypes.c_int)]
 
 
-def _desc(prior, beta, dictionary=None):
-    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4)
+def _desc(prior, beta, dictionary=None, filters=None):
+    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0)
     if dictionary is not None:
         d.dict = ctypes.c_void_p(dictionary.data_ptr())
         d.n_atoms = int(dictionary.shape[1])
+    if filters is not None:
+        d.filters = ctypes.c_void_p(filters.data_ptr())
+        d.n_filters = int(filters.shape[0])
+        d.filt_l = int(filters.shape[1])
     return d
 
 
@@ -89,9 +96,11 @@ def _dev_f32(t, shape, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0):
+def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0, n_filters=0, filt_l=0):
     desc = _desc(prior, beta)
     desc.n_atoms = int(n_atoms)
+    desc.n_filters = int(n_filters)
+    desc.filt_l = int(filt_l)
     n = ctypes.c_size_t()
     _check(lib().cip_plan_workspace_bytes(K, S, N1, N2, ctypes.byref(desc), ctypes.byref(n)))
     return n.value
@@ -102,10 +111,12 @@ class Plan:
 
     psf: float32 CUDA tensor [K, S, N1, N2] (unshifted kernels, origin at [0, 0]).
     dictionary: for prior="patch", float32 CUDA tensor [64 S, A] (atoms as
-    columns, row s*64 + a*8 + b = pixel (a, b) of plane s)."""
+    columns, row s*64 + a*8 + b = pixel (a, b) of plane s).
+    filters: for prior="conv2d", float32 CUDA tensor [M, L, L] (tap (a, b) at
+    offset (a - L//2, b - L//2))."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
-                 stream=None):
+                 filters=None, stream=None):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
@@ -113,9 +124,13 @@ class Plan:
             if dictionary is None:
                 raise ValueError("the patch prior needs a dictionary")
             _dev_f32(dictionary, (64 * self.S, dictionary.shape[1]), "dictionary")
-        desc = _desc(prior, beta, dictionary)
+        if prior == "conv2d":
+            if filters is None:
+                raise ValueError("the conv2d prior needs filters")
+            _dev_f32(filters, tuple(filters.shape), "filters")
+        desc = _desc(prior, beta, dictionary, filters)
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
-                                 desc.n_atoms)
+                                 desc.n_atoms, desc.n_filters, desc.filt_l)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
         h = ctypes.c_void_p()
         _check(lib().cip_plan_create(self.K, self.S, self.N1, self.N2,

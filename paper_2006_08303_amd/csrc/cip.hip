@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 #include "patch_launch.hpp"
+#include "conv_launch.hpp"
 
 using namespace cip;
 
@@ -56,6 +57,7 @@ struct Layout {
   size_t state;                         // ADMM state
   size_t lam64, rt64, pl64;             // plan-time FP64 scratch
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
+  size_t th32, gam, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t total;
 };
 
@@ -65,6 +67,7 @@ int state_floats_per_voxel(int kind) {
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
+    case CIP_PRIOR_CONV2D: return 0;
     default: return -1;
   }
 }
@@ -105,6 +108,17 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     L.tbuf = take(patch_tile_buffer_floats(S, N1, N2) * 4);
     L.rimg = take((size_t)S * N1 * N2 * 4);
   }
+  if (kind == CIP_PRIOR_CONV2D) {
+    const size_t M = (size_t)prior->n_filters;
+    L.th32 = take(M * F * 8);
+    L.gam = take(F * 4);
+    L.gv = take(M * S * F * 8);
+    L.dhat = take((size_t)S * F * 8);
+    L.xhat = take((size_t)S * F * 8);
+    L.rtc = take(M * S * F * 8);
+    L.vconv = take(M * S * (size_t)N1 * N2 * 4);
+    L.th64 = take(M * F * 16);
+  }
   L.total = o;
   return L;
 }
@@ -126,13 +140,19 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       return fail(CIP_EUNSUPPORTED, "patch prior: needs S <= 4 and 64, 128 or 256 atoms");
     if (!patch_grid_ok(N1, N2)) return fail(CIP_EUNSUPPORTED, "patch prior: grid too small");
   }
+  if (prior->kind == CIP_PRIOR_CONV2D) {
+    if (prior->n_filters < 1 || prior->n_filters > 32)
+      return fail(CIP_EUNSUPPORTED, "conv prior: 1 to 32 filters");
+    if (prior->filt_l < 1 || prior->filt_l > N1 || prior->filt_l > N2)
+      return fail(CIP_EINVAL, "conv prior: filter size must be in [1, min(N1, N2)]");
+  }
   return CIP_OK;
 }
 
 }  // namespace
 
 struct cip_plan_s {
-  int K, S, N1, N2, H2, kind, n_atoms;
+  int K, S, N1, N2, H2, kind, n_atoms, n_filters;
   double beta, rho, lambda;
   unsigned char* ws;
   Layout L;
@@ -290,6 +310,46 @@ hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
   return hipSuccess;
 }
 
+// Algorithm 2 with the convolutional prior. Per iteration l = 1..L:
+//   frequency pass: x^l = Psi^+ (b^ + d^{l-1}); for l < L also the
+//   Sherman-Morrison code update v and d^l;
+//   for l < L: inverse column FFT of v, row pass (inverse row FFT -> z^l,
+//   state update, forward row FFT of t - u), forward column FFT -> g^.
+// Finally x^L: inverse column and row FFTs of x^L.
+hipError_t conv_iter(cip_plan_t p, int l, int last, hipStream_t st) {
+  const Layout& L = p->L;
+  const size_t F = (size_t)p->N1 * p->H2;
+  const int P = p->n_filters * p->S;
+  hipError_t e = conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
+                           p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
+                           p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
+                           p->at<const float>(L.gam), p->n_filters, p->S, F, l == 1, l == 1,
+                           last ? 0 : 1, st);
+  if (e != hipSuccess || last) return e;
+  e = conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1, p->H2,
+                   p->at<const cx<float>>(L.twN1f), st);
+  if (e != hipSuccess) return e;
+  const float zscale = (float)(1.0 / ((double)p->N1 * p->N2));
+  e = conv_row(p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.rtc), p->at<float>(L.vconv), P,
+               p->N1, p->N2, p->at<const cx<float>>(L.twN2f), (float)(p->lambda / p->rho), zscale,
+               l == 1, st);
+  if (e != hipSuccess) return e;
+  return conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gv), P, p->N1, p->H2,
+                      p->at<const cx<float>>(L.twN1f), st);
+}
+
+hipError_t solve_conv(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
+  const Layout& L = p->L;
+  hipError_t e;
+  for (int l = 1; l <= iters; ++l)
+    if ((e = conv_iter(p, l, l == iters, st)) != hipSuccess) return e;
+  e = conv_col_fft(-1, p->at<const cx<float>>(L.xhat), p->at<cx<float>>(L.bufB), p->S, p->N1, p->H2,
+                   p->at<const cx<float>>(L.twN1f), st);
+  if (e != hipSuccess) return e;
+  return row_c2r(p->at<const cx<float>>(L.bufB), d_x, p->S, p->N1, p->N2,
+                 (float)(1.0 / ((double)p->N1 * p->N2)), p->at<const cx<float>>(L.twN2f), st);
+}
+
 hipError_t gram(cip_plan_t p, hipStream_t st) {
   GramArgs a;
   a.K = p->K;
@@ -299,11 +359,14 @@ hipError_t gram(cip_plan_t p, hipStream_t st) {
   a.beta = p->beta;
   a.scale = 1.0 / ((double)p->N1 * (double)p->N2);
   a.rcond = 1e-12;
-  const bool synth = p->kind == CIP_PRIOR_PATCH;
+  const bool patch = p->kind == CIP_PRIOR_PATCH, conv = p->kind == CIP_PRIOR_CONV2D;
   // analysis: Psi = rho tau I + beta L^H L, rhs = b + rho g;
-  // patch synthesis: Psi = c_P I + beta L^H L with c_P = (Q / st)^2 = 4, rhs = b + g
-  a.wgt = synth ? 4.0 : p->rho;
-  a.coefA = synth ? 1.0 : p->rho;
+  // patch synthesis: Psi = c_P I + beta L^H L with c_P = (Q / st)^2 = 4, rhs = b + g;
+  // conv synthesis: c_P = 1, and the tables are unnormalised (the frequency
+  // pass works with unnormalised spectra throughout)
+  a.wgt = patch ? 4.0 : (conv ? 1.0 : p->rho);
+  a.coefA = (patch || conv) ? 1.0 : p->rho;
+  if (conv) a.scale = 1.0;
   a.tv_symbol = (p->kind == CIP_PRIOR_TV2D || p->kind == CIP_PRIOR_TV3D) ? 1 : 0;
   a.band_lap = p->kind == CIP_PRIOR_TV3D ? 1 : 0;
   const Layout& L = p->L;
@@ -450,6 +513,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     return fail(CIP_EINVAL, "workspace must be 256-byte aligned");
   if (prior->kind == CIP_PRIOR_PATCH && !prior->dict)
     return fail(CIP_EINVAL, "patch prior needs a dictionary");
+  if (prior->kind == CIP_PRIOR_CONV2D && !prior->filters)
+    return fail(CIP_EINVAL, "conv prior needs filters");
   Layout L = make_layout(K, S, N1, N2, prior);
   if (ws_bytes < L.total) return fail(CIP_ENOSPC, "workspace too small");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -462,6 +527,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->H2 = N2 / 2 + 1;
   p->kind = prior->kind;
   p->n_atoms = prior->kind == CIP_PRIOR_PATCH ? prior->n_atoms : 0;
+  p->n_filters = prior->kind == CIP_PRIOR_CONV2D ? prior->n_filters : 0;
   p->beta = prior->beta;
   p->rho = rho;
   p->lambda = lambda;
@@ -512,6 +578,21 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     }
   }
   PLAN_HIP(gram(p, st));
+  if (p->kind == CIP_PRIOR_CONV2D) {
+    // filter spectra theta_m in FP64 (same transform path as the kernels)
+    const int M = prior->n_filters, Lf = prior->filt_l;
+    double* d_pl = p->at<double>(L.pl64);
+    for (int m = 0; m < M; ++m) {
+      PLAN_HIP(conv_place_filter(prior->filters + (size_t)m * Lf * Lf, d_pl, Lf, N1, N2, st));
+      PLAN_HIP(row_r2c<double>(d_pl, p->at<cx<double>>(L.rt64), 1, N1, N2,
+                               p->at<const cx<double>>(L.twN2d), st));
+      PLAN_HIP((col_op<double, OP_SPEC>(p->at<const cx<double>>(L.rt64), p->at<void>(L.th64), 1, 1,
+                                        N1, p->H2, p->at<const cx<double>>(L.twN1d), nullptr, m,
+                                        st)));
+    }
+    PLAN_HIP(conv_tables(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
+                         p->at<float>(L.gam), M, (size_t)N1 * p->H2, rho, st));
+  }
   if (p->kind == CIP_PRIOR_PATCH) {
     // M1 = D^T (rho I + D D^T)^-1 in FP64 on the host; D and M1 stored as BF16
     const int nv = 64 * S, na = prior->n_atoms;
@@ -570,8 +651,9 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   HIP_TRY((col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufA), p->at<void>(L.xh0), p->K, p->S,
                                    p->N1, p->H2, p->at<const cx<float>>(L.twN1f),
                                    p->at<const cx<float>>(L.Mm), 0, st)));
-  if (p->kind == CIP_PRIOR_PATCH) {
-    HIP_TRY(solve_patch(p, iters, d_x, st));
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D) {
+    if (p->kind == CIP_PRIOR_PATCH) HIP_TRY(solve_patch(p, iters, d_x, st));
+    else HIP_TRY(solve_conv(p, iters, d_x, st));
     p->solved_once = true;
     return CIP_OK;
   }
@@ -595,16 +677,34 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
   if (!p || !avg_us || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
   if (which < 0 || which > 2) return fail(CIP_EINVAL, "which must be 0, 1 or 2");
-  if ((which == 2) != (p->kind == CIP_PRIOR_PATCH))
-    return fail(CIP_EINVAL, "which = 2 times the patch update (patch prior only)");
-  if (p->kind == CIP_PRIOR_PATCH && which == 0)
-    return fail(CIP_EINVAL, "the patch prior has no fused row pass");
+  const bool conv = p->kind == CIP_PRIOR_CONV2D, patch = p->kind == CIP_PRIOR_PATCH;
+  if (which == 2 && !patch && !conv)
+    return fail(CIP_EINVAL, "which = 2 needs the patch or convolutional prior");
+  if (patch && which == 0) return fail(CIP_EINVAL, "the patch prior has no fused row pass");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, st));
   for (int r = 0; r < reps; ++r) {
+    const Layout& L = p->L;
+    const size_t F = (size_t)p->N1 * p->H2;
+    if (conv) {
+      const int P = p->n_filters * p->S;
+      if (which == 0)
+        HIP_TRY(conv_row(p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.rtc), p->at<float>(L.vconv),
+                         P, p->N1, p->N2, p->at<const cx<float>>(L.twN2f),
+                         (float)(p->lambda / p->rho), (float)(1.0 / ((double)p->N1 * p->N2)), 0, st));
+      else if (which == 1)
+        HIP_TRY(conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gv), P, p->N1,
+                             p->H2, p->at<const cx<float>>(L.twN1f), st));
+      else
+        HIP_TRY(conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
+                          p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
+                          p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
+                          p->at<const float>(L.gam), p->n_filters, p->S, F, 0, 0, 1, st));
+      continue;
+    }
     if (which == 0) HIP_TRY(admm_row(p, 2 + (r & 1), st));
     else if (which == 1) HIP_TRY(admm_col(p, 0, 1, st));
     else HIP_TRY(patch_z_launch(p->S, p->n_atoms, p->at<const float>(p->L.rimg),

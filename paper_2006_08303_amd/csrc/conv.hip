@@ -1,0 +1,62 @@
+// Launchers of the convolutional-dictionary kernels (separate translation unit).
+#include "conv.hpp"
+#include "conv_launch.hpp"
+#include "launch.hpp"
+
+namespace cip {
+
+#define CIP_DISPATCH_N(N, ...)                                     \
+  switch (N) {                                                     \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;        \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;        \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;        \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;      \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;      \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;      \
+    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;    \
+    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;    \
+    default: return hipErrorInvalidValue;                          \
+  }
+
+hipError_t conv_place_filter(const float* filt, double* dst, int L, int N1, int N2, hipStream_t st) {
+  const size_t n = (size_t)N1 * N2;
+  return launch(k_place_filter, (int)((n + 255) / 256), 256, 0, st, filt, dst, L, N1, N2);
+}
+
+hipError_t conv_tables(const cx<double>* th64, cx<float>* th32, float* gam, int M, size_t F,
+                       double rho, hipStream_t st) {
+  return launch(k_conv_tables, (int)((F + 255) / 256), 256, 0, st, th64, th32, gam, M, F, rho);
+}
+
+hipError_t conv_col_fft(int dir, const cx<float>* in, cx<float>* out, int P, int N1, int H2,
+                        const cx<float>* tw, hipStream_t st) {
+  CIP_DISPATCH_N(N1, {
+    const int T = NN / ppt_col<NN>();
+    const size_t lds = (size_t)(NN + CONV_PC * padded_len(NN)) * 8;
+    const int grid = H2 * ((P + CONV_PC - 1) / CONV_PC);
+    if (dir > 0) return launch(k_col_fft_batch<NN, 1>, grid, CONV_PC * T, lds, st, in, out, P, H2, tw);
+    return launch(k_col_fft_batch<NN, -1>, grid, CONV_PC * T, lds, st, in, out, P, H2, tw);
+  });
+  return hipSuccess;
+}
+
+hipError_t conv_freq(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<float>* xh0,
+                     const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
+                     const float* gam, int M, int S, size_t F, int first, int zero_g, int do_z,
+                     hipStream_t st) {
+  return launch(k_conv_freq, (int)((F + 127) / 128), 128, 0, st, gv, dhat, xhat, xh0, Adiag, Aoff,
+                th, gam, M, S, F, first, zero_g, do_z);
+}
+
+hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
+                    const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st) {
+  CIP_DISPATCH_N(N2, {
+    const int T = NN / ppt_row<NN>();
+    const size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
+    return launch(k_conv_row<NN>, P * (N1 / RT), PAIRS * T, lds, st, Vin, Gout, V, N1, tw, kappa,
+                  zscale, first);
+  });
+  return hipSuccess;
+}
+
+}  // namespace cip

@@ -1,0 +1,196 @@
+// Convolutional-dictionary synthesis prior, 2D-correlation form (a common set
+// of M filters d_m for every plane: plane s ~ sum_m d_m * z_{m,s}; P = I).
+//
+// One ADMM iteration of Algorithm 2, with all operators diagonal in the 2D
+// DFT domain (Section IV-B):
+//   x-update (Eq. solx_synt_DFT, c_P = 1): x^ = Psi^+ (b^ + d^), d^_s = sum_m theta_m z^_{m,s};
+//   z-update (Eqs. solz_DFT, solz_DFT_SM) per frequency and plane: with
+//     a = conj(theta) (M-vector), g^ = F(t - u),
+//     v = g^ + a (x^_s - a^H g^) gamma,  gamma = 1 / (rho + |a|^2),
+//   which equals Sherman-Morrison's rho^-1 (c - a a^H c gamma) for
+//   c = a x^_s + rho g^ but has no 1/rho (stable in FP32 for small rho);
+//   z = F^-1 v; soft threshold and dual update in space (Eq. softADMM).
+// The state per code voxel is V = z + u_prev (t = soft(V), u = clip(V),
+// t - u = 2 soft(V) - V). Transforms are unnormalised; the x^ tables carry no
+// 1/(N1 N2), which the inverse transforms apply.
+//
+// Layouts: RT and FL as in kernels.hpp; code planes p = m * S + s.
+#pragma once
+#include "kernels.hpp"
+
+namespace cip {
+
+// Filter m (L x L, row-major) placed on the N1 x N2 torus with tap (a, b) at
+// offset (a - L/2, b - L/2), promoted to double (plan time).
+__global__ void k_place_filter(const float* __restrict__ filt, double* __restrict__ dst, int L,
+                               int N1, int N2) {
+  const size_t n = (size_t)N1 * N2;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int n1 = (int)(i / N2), n2 = (int)(i % N2);
+  const int a = (n1 + L / 2) % N1, b = (n2 + L / 2) % N2;
+  dst[i] = (a < L && b < L) ? (double)filt[a * L + b] : 0.0;
+}
+
+// theta (FP32) and gamma = 1 / (rho + sum_m |theta_m|^2) (formed in FP64).
+__global__ void k_conv_tables(const cx<double>* __restrict__ th64, cx<float>* __restrict__ th32,
+                              float* __restrict__ gam, int M, size_t F, double rho) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  double s = 0.0;
+  for (int m = 0; m < M; ++m) {
+    cx<double> t = th64[(size_t)m * F + f];
+    s += t.x * t.x + t.y * t.y;
+    th32[(size_t)m * F + f] = cx<float>{(float)t.x, (float)t.y};
+  }
+  gam[f] = (float)(1.0 / (rho + s));
+}
+
+constexpr int CONV_PC = 4;   // planes per work-group in the batched column FFT
+
+// Batched column FFT, one work-group per (column k2, chunk of CONV_PC planes).
+// DIR = +1: RT -> FL (forward); DIR = -1: FL -> RT (inverse, unnormalised).
+template <int N1, int DIR>
+__global__ void k_col_fft_batch(const cx<float>* __restrict__ in, cx<float>* __restrict__ out, int P,
+                                int H2, const cx<float>* __restrict__ twg) {
+  constexpr int PPT = ppt_col<N1>();
+  constexpr int T = N1 / PPT;
+  constexpr int PL = padded_len(N1);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  cx<float>* cb = tw + N1 + (threadIdx.x / T) * PL;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int k2 = b % H2, chunk = b / H2;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int p = chunk * CONV_PC + g;
+  const bool live = p < P;
+  lds_load_table(tw, twg, N1);
+  cx<float> v[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int k1 = t + T * q;
+    if (!live) v[q] = cx<float>{0.f, 0.f};
+    else if (DIR > 0) v[q] = in[rt_idx(p, k1, k2, N1, H2)];
+    else v[q] = in[fl_idx(p, k1, k2, N1, H2)];
+  }
+  __syncthreads();
+  fft_group<N1, PPT, DIR>(v, cb, t, tw);
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int k1 = t + T * q;
+      if (DIR > 0) out[fl_idx(p, k1, k2, N1, H2)] = v[q];
+      else out[rt_idx(p, k1, k2, N1, H2)] = v[q];
+    }
+  }
+}
+
+// Frequency pass, one thread per frequency f (FL order):
+//   x^ = xh0 + A d^ (S x S, packed Hermitian A = Psi^+), stored to xhat;
+//   if do_z: per plane s the stable Sherman-Morrison update of the M codes
+//   (v overwrites g^ in gv) and the new d^_s = sum_m theta_m v_m.
+// first: d^ = 0 (z = 0); zero_g: g^ = 0 (t = u = 0).
+constexpr int CONV_MMAX = 32;   // filters per dictionary (at most)
+
+__global__ void k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat,
+                            cx<float>* __restrict__ xhat, const cx<float>* __restrict__ xh0,
+                            const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
+                            const cx<float>* __restrict__ th, const float* __restrict__ gam, int M,
+                            int S, size_t F, int first, int zero_g, int do_z) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  cx<float> d[8], xs[8];
+  for (int s = 0; s < S; ++s) d[s] = first ? cx<float>{0.f, 0.f} : dhat[(size_t)s * F + f];
+  for (int s = 0; s < S; ++s) {
+    cx<float> acc = xh0[(size_t)s * F + f];
+    const float dg = Adiag[(size_t)s * F + f];
+    acc.x += dg * d[s].x;
+    acc.y += dg * d[s].y;
+    for (int j = 0; j < S; ++j) {
+      if (j == s) continue;
+      const cx<float> a = s < j ? Aoff[(size_t)pair_index(s, j, S) * F + f]
+                                : conjx(Aoff[(size_t)pair_index(j, s, S) * F + f]);
+      acc = acc + cmul(a, d[j]);
+    }
+    xs[s] = acc;
+    xhat[(size_t)s * F + f] = acc;
+  }
+  if (!do_z) return;
+  cx<float> t[CONV_MMAX];
+#pragma unroll
+  for (int m = 0; m < CONV_MMAX; ++m)
+    if (m < M) t[m] = th[(size_t)m * F + f];
+  const float gm = gam[f];
+  for (int s = 0; s < S; ++s) {
+    cx<float> g[CONV_MMAX];
+    cx<float> ag = {0.f, 0.f};   // a^H g = sum_m theta_m g_m
+#pragma unroll
+    for (int m = 0; m < CONV_MMAX; ++m) {
+      if (m >= M) break;
+      g[m] = zero_g ? cx<float>{0.f, 0.f} : gv[((size_t)m * S + s) * F + f];
+      ag = ag + cmul(t[m], g[m]);
+    }
+    const cx<float> r = {(xs[s].x - ag.x) * gm, (xs[s].y - ag.y) * gm};
+    cx<float> dn = {0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < CONV_MMAX; ++m) {
+      if (m >= M) break;
+      const cx<float> vm = g[m] + cmulc(r, t[m]);   // g + conj(theta) r
+      gv[((size_t)m * S + s) * F + f] = vm;
+      dn = dn + cmul(t[m], vm);
+    }
+    dhat[(size_t)s * F + f] = dn;
+  }
+}
+
+// Row pass of the conv prior (pairs of rows of one code plane per group):
+// inverse row FFT of v (z = scale * result), state update V = z + clip(V),
+// w = 2 soft(V) - V, forward row FFT of w -> RT. first: V_prev = 0.
+template <int N2>
+__global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()), 2)
+k_conv_row(const cx<float>* __restrict__ Vin, cx<float>* __restrict__ Gout, float* __restrict__ V,
+           int N1, const cx<float>* __restrict__ twg, float kappa, float zscale, int first) {
+  constexpr int PPT = ppt_row<N2>();
+  constexpr int T = N2 / PPT;
+  constexpr int H2 = N2 / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int tiles = N1 / RT;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = b / tiles, row0 = (b % tiles) * RT;
+  const int ra = row0 + 2 * g;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+  lds_load_table(tw, twg, N2);
+  tile_to_staging(Vin + rt_tile_base(p, row0, N1, H2), stg, H2 * RT);
+  float* va = V + ((size_t)p * N1 + ra) * N2;
+  float* vb = va + N2;
+  float oa[PPT], ob[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    oa[q] = first ? 0.f : va[t + T * q];
+    ob[q] = first ? 0.f : vb[t + T * q];
+  }
+  __syncthreads();
+  cx<float> v[PPT];
+  staging_to_pair<N2, PPT>(v, stg, g, t);
+  __syncthreads();
+  fft_group<N2, PPT, -1>(v, cb, t, tw);
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int k = t + T * q;
+    const float na = zscale * v[q].x + clip_f(oa[q], kappa);
+    const float nb = zscale * v[q].y + clip_f(ob[q], kappa);
+    va[k] = na;
+    vb[k] = nb;
+    v[q] = cx<float>{2.f * soft_f(na, kappa) - na, 2.f * soft_f(nb, kappa) - nb};
+  }
+  fft_group<N2, PPT, +1>(v, cb, t, tw);
+  pair_to_staging<N2, PPT>(v, cb, stg, g, t);
+  __syncthreads();
+  staging_to_tile(Gout + rt_tile_base(p, row0, N1, H2), stg, H2 * RT);
+}
+
+}  // namespace cip
