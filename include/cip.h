@@ -144,6 +144,25 @@ int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* st
 /* Release the host-side plan object (the workspace stays the caller's). */
 int cip_plan_destroy(cip_plan_t plan);
 
+/* ---- batches of independent solves --------------------------------------
+ * A batch runs n independent cip_solve calls (distinct plans, each with its
+ * own measurements, iteration count and output) concurrently: the problems
+ * are spread largest-first over n_streams internal HIP streams, forked from
+ * and joined back to the stream passed to cip_batch_launch. With use_graph,
+ * cip_batch_create captures the whole batch once into a hipGraph (the solves
+ * launch no memsets or allocations) and every cip_batch_launch replays it
+ * with a single graph launch; otherwise the kernels are launched directly.
+ * The pointers passed to cip_batch_create must stay valid until
+ * cip_batch_destroy; every launch recomputes all solves from t = u = 0.
+ * Each result equals that of a lone cip_solve on the same plan (the solves
+ * share no memory). Creating a batch allocates host objects, streams and
+ * events, never device memory. */
+typedef struct cip_batch_s* cip_batch_t;
+int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
+                     float* const* d_x, int n_streams, int use_graph, cip_batch_t* out);
+int cip_batch_launch(cip_batch_t batch, void* stream);
+int cip_batch_destroy(cip_batch_t batch);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* cip_last_error(void);
 

@@ -71,8 +71,14 @@ def lib():
         L.cip_plan_destroy.argtypes = [vp]
         L.cip_last_error.restype = ctypes.c_char_p
         L.cip_time_kernel.argtypes = [vp, i, i, vp, ctypes.POINTER(d)]
+        L.cip_batch_create.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i), ctypes.POINTER(vp), i, i,
+                                       ctypes.POINTER(vp)]
+        L.cip_batch_launch.argtypes = [vp, vp]
+        L.cip_batch_destroy.argtypes = [vp]
         for name in ("cip_plan_workspace_bytes", "cip_plan_create", "cip_forward", "cip_adjoint",
-                     "cip_solve", "cip_plan_destroy", "cip_time_kernel"):
+                     "cip_solve", "cip_plan_destroy", "cip_time_kernel", "cip_batch_create",
+                     "cip_batch_launch", "cip_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -170,4 +176,42 @@ class Plan:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.cip_plan_destroy(h)
+            self._h = None
+
+
+class Batch:
+    """Independent solves run together (cip_batch_create / cip_batch_launch).
+
+    problems: list of (plan, y, iters, x) with distinct plans; y [K, N1, N2] and
+    x [S, N1, N2] float32 CUDA tensors that must outlive the batch. With
+    graph=True the whole batch is captured once into a hipGraph and every
+    launch() replays it."""
+
+    def __init__(self, problems, n_streams=4, graph=True):
+        n = len(problems)
+        if n == 0:
+            raise ValueError("empty batch")
+        vp = ctypes.c_void_p
+        plans = (vp * n)()
+        ys = (vp * n)()
+        xs = (vp * n)()
+        its = (ctypes.c_int * n)()
+        for j, (plan, y, iters, x) in enumerate(problems):
+            plans[j] = plan._h.value
+            ys[j] = _dev_f32(y, (plan.K, plan.N1, plan.N2), "y").value
+            xs[j] = _dev_f32(x, (plan.S, plan.N1, plan.N2), "x").value
+            its[j] = int(iters)
+        self._keep = list(problems)
+        h = vp()
+        _check(lib().cip_batch_create(n, plans, ys, its, xs, int(n_streams), int(bool(graph)),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().cip_batch_launch(self._h, _stream_ptr(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cip_batch_destroy(h)
             self._h = None

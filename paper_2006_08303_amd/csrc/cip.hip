@@ -4,6 +4,7 @@
 // Section IV-A), each step launched as a hand-written HIP kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -670,6 +671,140 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
 
 int cip_plan_destroy(cip_plan_t p) {
   delete p;
+  return CIP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+// Many independent solves fanned out over internal streams (fork / join on
+// the caller's stream with events), either launched directly or captured
+// once into a hipGraph and replayed with a single launch. Problems are
+// assigned to streams largest-first onto the least-loaded stream.
+struct cip_batch_s {
+  std::vector<cip_plan_t> plans;
+  std::vector<const float*> y;
+  std::vector<float*> x;
+  std::vector<int> iters;
+  std::vector<std::vector<int>> lanes;   // problem indices per stream
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int batch_enqueue(cip_batch_s* b, hipStream_t origin) {
+  HIP_TRY(hipEventRecord(b->fork, origin));
+  for (size_t i = 0; i < b->streams.size(); ++i) {
+    HIP_TRY(hipStreamWaitEvent(b->streams[i], b->fork, 0));
+    for (int j : b->lanes[i]) {
+      int rc = cip_solve(b->plans[j], b->y[j], b->iters[j], b->x[j], b->streams[i]);
+      if (rc) return rc;
+    }
+    HIP_TRY(hipEventRecord(b->join[i], b->streams[i]));
+    HIP_TRY(hipStreamWaitEvent(origin, b->join[i], 0));
+  }
+  return CIP_OK;
+}
+
+void batch_free(cip_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto e : b->join) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (auto s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
+                     float* const* d_x, int n_streams, int use_graph, cip_batch_t* out) {
+  if (n < 1 || !plans || !d_y || !iters || !d_x || !out) return fail(CIP_EINVAL, "bad argument");
+  if (n_streams < 1 || n_streams > 64) return fail(CIP_EINVAL, "n_streams must be in [1, 64]");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || !d_y[i] || !d_x[i] || iters[i] < 1) return fail(CIP_EINVAL, "bad problem entry");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(CIP_EINVAL, "a plan may appear once per batch");
+  }
+  cip_batch_s* b = new cip_batch_s();
+  b->plans.assign(plans, plans + n);
+  b->y.assign(d_y, d_y + n);
+  b->x.assign(d_x, d_x + n);
+  b->iters.assign(iters, iters + n);
+  const int ns = n_streams < n ? n_streams : n;
+  b->lanes.resize(ns);
+  std::vector<double> load(ns, 0.0), cost(n);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    const cip_plan_t p = plans[i];
+    cost[i] = (double)p->N1 * p->N2 * (p->S + p->K) * iters[i];
+  }
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  for (int i : order) {
+    int best = 0;
+    for (int k = 1; k < ns; ++k)
+      if (load[k] < load[best]) best = k;
+    b->lanes[best].push_back(i);
+    load[best] += cost[i];
+  }
+  auto bail = [&](int code, const std::string& m) {
+    batch_free(b);
+    return fail(code, m);
+  };
+  b->streams.resize(ns, nullptr);
+  b->join.resize(ns, nullptr);
+  for (int k = 0; k < ns; ++k) {
+    if (hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking) != hipSuccess)
+      return bail(CIP_EHIP, "hipStreamCreate failed");
+    if (hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess)
+      return bail(CIP_EHIP, "hipEventCreate failed");
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+    return bail(CIP_EHIP, "hipEventCreate failed");
+  if (use_graph) {
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(CIP_EHIP, "hipStreamCreate failed");
+    int rc = CIP_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) != hipSuccess) rc = CIP_EHIP;
+    if (!rc) rc = batch_enqueue(b, cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      std::string m = g_last_error;
+      return bail(rc, "graph capture failed: " + m);
+    }
+    if (e != hipSuccess || !g) return bail(CIP_EHIP, "hipStreamEndCapture failed");
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+      return bail(CIP_EHIP, "hipGraphInstantiate failed");
+  }
+  *out = b;
+  return CIP_OK;
+}
+
+int cip_batch_launch(cip_batch_t b, void* stream) {
+  if (!b) return fail(CIP_EINVAL, "NULL batch");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (b->exec) {
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    for (auto p : b->plans) p->solved_once = true;
+    return CIP_OK;
+  }
+  return batch_enqueue(b, st);
+}
+
+int cip_batch_destroy(cip_batch_t b) {
+  if (b) batch_free(b);
   return CIP_OK;
 }
 

@@ -1,0 +1,97 @@
+"""GPU tests of batched solves (cip_batch_create / cip_batch_launch).
+
+A batch of independent problems of mixed grid sizes, band counts, priors
+and iteration counts runs concurrently over internal streams, directly or as
+one captured hipGraph. Each result must equal, bit for bit, the lone
+cip_solve of the same plan (same kernels on the same data), and one of them
+is also checked against the FP64 oracle. Graph replays are repeated with
+eager work in between and every replay is compared."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm, model
+from paper_2006_08303_amd import cip, synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
+
+
+def _problems():
+    """(plan, y, iters, x_ref_input) for a mixed batch; seeds per entry."""
+    spec = [("dct2d", 256, 3, 3, 12), ("tv2d", 128, 2, 4, 9), ("dct2d", 512, 3, 2, 5),
+            ("tv2d", 64, 4, 1, 17), ("conv2d", 64, 3, 3, 6), ("patch", 64, 3, 3, 7),
+            ("dct2d", 1024, 3, 3, 3), ("tv2d", 256, 6, 5, 4)]
+    out = []
+    for j, (prior, N, K, S, iters) in enumerate(spec):
+        x, psf, noise = synth.problem("rects_gauss", N, K, S, seed_config=4) \
+            if prior in ("dct2d", "tv2d") else synth.problem("smooth_disk", N, K, S, seed_config=4)
+        y = model.measure(x, psf, noise, 30.0).astype(np.float32).astype(np.float64)
+        kw = {}
+        if prior == "conv2d":
+            kw["filters"] = _t(synth.random_unit_filters(synth.rng_for(4, 10 + j), 8, 5))
+            rho, lam, beta = 1e-4, 1.875e-6, 8.0
+        elif prior == "patch":
+            kw["dictionary"] = _t(synth.random_unit_atoms(synth.rng_for(4, 10 + j), 64 * S, 256))
+            rho, lam, beta = 1e-4, 5e-6, 500.0
+        else:
+            rho, lam, beta = 0.1, 1e-2, 1.0
+        plan = cip.Plan(_t(psf), prior, rho, lam, beta, **kw)
+        out.append((plan, _t(y), iters, (prior, psf, y, rho, lam, beta)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    probs = _problems()
+    solo = []
+    for plan, y, iters, _ in probs:
+        solo.append(plan.solve(y, iters).clone())
+    torch.cuda.synchronize()
+    return probs, solo
+
+
+@pytest.mark.parametrize("graph,n_streams", [(False, 1), (False, 4), (True, 4), (True, 8)])
+def test_batch_equals_lone_solves(batch_setup, graph, n_streams):
+    probs, solo = batch_setup
+    print(f"batch graph={graph} n_streams={n_streams} n={len(probs)}", flush=True)
+    xs = [torch.full((p.S, p.N1, p.N2), float("nan"), device=DEV) for p, _, _, _ in probs]
+    b = cip.Batch([(p, y, it, x) for (p, y, it, _), x in zip(probs, xs)],
+                  n_streams=n_streams, graph=graph)
+    for rep in range(3):
+        for x in xs:
+            x.fill_(float("nan"))      # eager work between replays
+        b.launch()
+        torch.cuda.synchronize()
+        for j, (x, ref) in enumerate(zip(xs, solo)):
+            assert torch.equal(x, ref), (rep, j, (x - ref).abs().max().item())
+
+
+def test_batch_result_matches_oracle(batch_setup):
+    """Entry 0 (DCT, 256^2, K = S = 3, 12 iterations) against the oracle."""
+    probs, solo = batch_setup
+    plan, y, iters, (prior, psf, yh, rho, lam, beta) = probs[0]
+    xs = torch.empty((plan.S, plan.N1, plan.N2), device=DEV)
+    b = cip.Batch([(plan, y, iters, xs)], n_streams=1, graph=True)
+    b.launch()
+    torch.cuda.synchronize()
+    ref = admm.AnalysisADMM(psf, prior, lam, rho, beta, tier="freq").run(yh, iters)[0]
+    err = admm.rel_l2(xs.cpu().double().numpy(), ref)
+    print(f"  rel_l2 = {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
+def test_batch_rejects_bad_arguments(batch_setup):
+    probs, _ = batch_setup
+    plan, y, iters, _ = probs[3]
+    x = torch.empty((plan.S, plan.N1, plan.N2), device=DEV)
+    with pytest.raises(cip.CipError):
+        cip.Batch([(plan, y, iters, x), (plan, y, iters, x)])   # same plan twice
+    with pytest.raises(cip.CipError):
+        cip.Batch([(plan, y, 0, x)])
+    with pytest.raises(cip.CipError):
+        cip.Batch([(plan, y, iters, x)], n_streams=0)
