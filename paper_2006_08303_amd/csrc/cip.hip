@@ -131,8 +131,6 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     return fail(CIP_EUNSUPPORTED, "N1 and N2 must be powers of two in [16, 2048]");
   if (state_floats_per_voxel(prior->kind) < 0)
     return fail(CIP_EUNSUPPORTED, "unsupported prior kind");
-  if (prior->kind == CIP_PRIOR_TV3D)
-    return fail(CIP_EUNSUPPORTED, "this build serves the DCT2D, TV2D and patch priors");
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
   if (prior->kind == CIP_PRIOR_PATCH) {
     if (prior->patch_q != 8 || prior->patch_stride != 4)
@@ -229,17 +227,22 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
   return hipSuccess;
 }
 
-// Row pass of the TV2D prior; pass number l >= 1 of the solve (state buffers
+// Row pass of the TV priors; pass number l >= 1 of the solve (state buffers
 // alternate so that halo rows of the previous state stay readable).
 hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st) {
   const Layout& L = p->L;
   float kappa = (float)(p->lambda / p->rho);
-  const size_t buf = (size_t)2 * p->S * p->N1 * p->N2;
+  const bool band = p->kind == CIP_PRIOR_TV3D;
+  const size_t buf = (size_t)(band ? 3 : 2) * p->S * p->N1 * p->N2;
   const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
   float* vout = p->at<float>(L.state) + (size_t)(l & 1) * buf;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + tv_work_floats<NN>()) * 4;
+    if (band)
+      return launch(k_admm_row_tv3<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
+                    p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
+                    p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0);
     return launch(k_admm_row_tv<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
                   p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0);

@@ -18,20 +18,19 @@ static hipError_t col_n(int S, const cx<float>* Gin, cx<float>* Yout, int H2, co
                         const cx<float>* Aoff, const cx<float>* xh0, const cx<float>* tw,
                         const cx<float>* ew, int zero_in, int dct_out, hipStream_t st) {
   const int T = NN / ppt_col<NN>();
-  size_t lds = (size_t)(4 * NN + S * 2 * padded_len(NN)) * 4;
-  auto run = [&](auto kern) {
-    return launch(kern, H2, S * T, lds, st, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew, zero_in,
-                  dct_out);
+  auto run = [&](auto kern, size_t lds_floats) {
+    return launch(kern, H2, S * T, lds_floats * 4, st, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew,
+                  zero_in, dct_out);
   };
   switch (S) {
-    case 1: return run(k_admm_col<NN, DCT, 1>);
-    case 2: return run(k_admm_col<NN, DCT, 2>);
-    case 3: return run(k_admm_col<NN, DCT, 3>);
-    case 4: return run(k_admm_col<NN, DCT, 4>);
-    case 5: return run(k_admm_col<NN, DCT, 5>);
-    case 6: return run(k_admm_col<NN, DCT, 6>);
-    case 7: return run(k_admm_col<NN, DCT, 7>);
-    case 8: return run(k_admm_col<NN, DCT, 8>);
+    case 1: return run(k_admm_col<NN, DCT, 1>, col_lds_floats<NN, DCT, 1>());
+    case 2: return run(k_admm_col<NN, DCT, 2>, col_lds_floats<NN, DCT, 2>());
+    case 3: return run(k_admm_col<NN, DCT, 3>, col_lds_floats<NN, DCT, 3>());
+    case 4: return run(k_admm_col<NN, DCT, 4>, col_lds_floats<NN, DCT, 4>());
+    case 5: return run(k_admm_col<NN, DCT, 5>, col_lds_floats<NN, DCT, 5>());
+    case 6: return run(k_admm_col<NN, DCT, 6>, col_lds_floats<NN, DCT, 6>());
+    case 7: return run(k_admm_col<NN, DCT, 7>, col_lds_floats<NN, DCT, 7>());
+    case 8: return run(k_admm_col<NN, DCT, 8>, col_lds_floats<NN, DCT, 8>());
   }
   return hipErrorInvalidValue;
 }

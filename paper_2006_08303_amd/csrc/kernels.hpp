@@ -508,7 +508,8 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
 //   4. forward row FFT of g -> RT output.
 // The state is double-buffered (vin -> vout) because neighbouring tiles read
 // the halo row of vin. Layout of each buffer: [component][S][N1][N2],
-// component 0 = vertical (n1) difference, 1 = horizontal (n2) difference.
+// component 0 = vertical (n1) difference, 1 = horizontal (n2) difference
+// (2 = band difference for TV3D).
 // LDS: [twiddles N2][work: max(5 group scratches, staging 10 x H2, q arrays)].
 template <int N2> constexpr int tv_work_floats() {
   constexpr int H2 = N2 / 2 + 1;
@@ -521,62 +522,81 @@ template <int N2> constexpr int tv_work_floats() {
   return a > b ? a : b;
 }
 
+// Global float access at a 32-bit element offset from a uniform base (the
+// address is the base plus a zero-extended byte offset, one VGPR per
+// address). Valid while 4 * off < 2^32.
+__device__ __forceinline__ float ld_off(const float* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (off << 2));
+}
+__device__ __forceinline__ void st_off(float* __restrict__ base, unsigned off, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (off << 2)) = v;
+}
+
+// Steps shared by the TV row passes (TV2D and TV3D), for plane s and the row
+// tile starting at row0. Group g < PAIRS owns rows row0 + 2g, row0 + 2g + 1
+// (local rows 1 + 2g, 2 + 2g of the LDS row block, whose row 0 is the halo
+// row r0 - 1); group PAIRS only transforms the halo pair.
+template <int N2> struct TvGeo {
+  static constexpr int PPT = ppt_row<N2>();
+  static constexpr int T = N2 / PPT;
+  static constexpr int H2 = N2 / 2 + 1;
+  static constexpr int NR = RT + 2;                // rows in LDS: halo, RT own rows, halo
+  static constexpr unsigned NT = (PAIRS + 1) * T;  // threads per work-group
+  static constexpr int NE = (RT + 1) * N2;         // state elements: halo row + own rows
+  static constexpr int PER = (NE + NT - 1) / NT;
+};
+
+// Stage rows r0-1 .. r0+RT of plane s ([k2][NR] order); own rows come from
+// one tile, the two halo rows from the neighbouring tiles.
 template <int N2>
-__global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
-k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
-              const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
-              const cx<float>* __restrict__ twg, float kappa, int first) {
-  constexpr int PPT = ppt_row<N2>();
-  constexpr int T = N2 / PPT;
-  constexpr int H2 = N2 / 2 + 1;
-  constexpr int NR = RT + 2;   // rows in LDS: halo, RT own rows, halo
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
-  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int tiles = N1 / RT;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = b / tiles, row0 = (b % tiles) * RT;
-  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
-  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
-  lds_load_table(tw, twg, N2);
-  // stage rows r0-1 .. r0+RT ([k2][NR] order); own rows come from one tile
-  {
-    const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
-    for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
-      const int k2 = i / RT, r = i % RT;
-      stg[pad8(k2 * NR + r + 1)] = tile[i];
-    }
-    const int lo = (row0 - 1 + N1) % N1, hi = (row0 + RT) % N1;
-    for (int i = threadIdx.x; i < 2 * H2; i += blockDim.x) {
-      const int k2 = i % H2, h = i / H2;
-      const int r = h ? NR - 1 : 0;
-      stg[pad8(k2 * NR + r)] = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
-    }
+__device__ __forceinline__ void tv_stage_rows(const cx<float>* __restrict__ Yin, cx<float>* stg,
+                                              int s, int row0, int N1) {
+  using G = TvGeo<N2>;
+  constexpr int H2 = G::H2, NR = G::NR;
+  const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
+  for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
+    const int k2 = i / RT, r = i % RT;
+    stg[pad8(k2 * NR + r + 1)] = tile[i];
   }
-  // prefetch the state this thread updates below (latency overlaps the FFT)
-  constexpr unsigned NT = (PAIRS + 1) * T;     // threads per work-group
-  const unsigned plane = (unsigned)N1 * N2;
-  const unsigned cstride = (unsigned)S * plane;  // component stride within a buffer
-  const unsigned m1 = (unsigned)N1 - 1;           // N1 is a power of two
-  constexpr int NE = (RT + 1) * N2;
-  constexpr int PER = (NE + NT - 1) / NT;
-  float pov[PER], poh[PER];
+  const int lo = (row0 - 1 + N1) % N1, hi = (row0 + RT) % N1;
+  for (int i = threadIdx.x; i < 2 * H2; i += blockDim.x) {
+    const int k2 = i % H2, h = i / H2;
+    const int r = h ? NR - 1 : 0;
+    stg[pad8(k2 * NR + r)] = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
+  }
+}
+
+// Load the vertical / horizontal state this thread updates in tv_spatial
+// (issued early so that the latency overlaps the transforms).
+template <int N2>
+__device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float (&pov)[TvGeo<N2>::PER],
+                                            float (&poh)[TvGeo<N2>::PER], unsigned s, int row0,
+                                            int N1, unsigned cstride, int first) {
+  using G = TvGeo<N2>;
+  const unsigned plane = (unsigned)N1 * N2, m1 = (unsigned)N1 - 1;
 #pragma unroll
-  for (int it = 0; it < PER; ++it) {
-    const unsigned e = threadIdx.x + it * NT;
+  for (int it = 0; it < G::PER; ++it) {
+    const unsigned e = threadIdx.x + it * G::NT;
     pov[it] = 0.f;
     poh[it] = 0.f;
-    if (e < (unsigned)NE && !first) {
+    if (e < (unsigned)G::NE && !first) {
       const unsigned lr = e / N2, n2 = e % N2;
       const unsigned n1 = (unsigned)(row0 - 1 + (int)lr) & m1;
       const unsigned o = s * plane + n1 * N2 + n2;
-      pov[it] = vin[o];
-      if (lr > 0) poh[it] = vin[cstride + o];
+      pov[it] = ld_off(vin, o);
+      if (lr > 0) poh[it] = ld_off(vin, cstride + o);
     }
   }
+}
+
+// Inverse row FFTs of the staged rows (two rows per group); x rows -> X =
+// lds [NR][N2]. Begins after the staging writes and ends with a barrier.
+template <int N2>
+__device__ __forceinline__ void tv_inverse_rows(const cx<float>* stg, cx<float>* cb,
+                                                const cx<float>* tw, float* X, int g, int t) {
+  using G = TvGeo<N2>;
+  constexpr int PPT = G::PPT, T = G::T, NR = G::NR;
   __syncthreads();
-  // group g: local rows 2g, 2g+1 (global r0-1+2g, r0+2g)
   cx<float> v[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -591,20 +611,33 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   }
   __syncthreads();
   fft_group<N2, PPT, -1>(v, cb, t, tw);
-  // x rows -> LDS [NR][N2] (fft_group ended with a barrier)
-  float* X = lds;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     X[(2 * g) * N2 + t + T * q] = v[q].x;
     X[(2 * g + 1) * N2 + t + T * q] = v[q].y;
   }
   __syncthreads();
-  // state update for local rows 0 (halo, vertical only) .. RT
+}
+
+// From X: state update of the vertical / horizontal components for the halo
+// row (vertical only, not stored) and the own rows, q = 2 soft(v) - v, and
+// the spatial part of T^T q for the own rows into v (two rows per group,
+// zero for group PAIRS). Overwrites X; ends with a barrier.
+template <int N2>
+__device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<N2>::PER],
+                                           const float (&poh)[TvGeo<N2>::PER],
+                                           float* __restrict__ vout, unsigned s, int row0, int N1,
+                                           unsigned cstride, float kappa, int g, int t,
+                                           cx<float> (&v)[TvGeo<N2>::PPT]) {
+  using G = TvGeo<N2>;
+  constexpr int PPT = G::PPT, T = G::T, PER = G::PER;
+  const unsigned plane = (unsigned)N1 * N2, m1 = (unsigned)N1 - 1;
+  const float* X = lds;
   float qv[PER], qh[PER];
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
-    const unsigned e = threadIdx.x + it * NT;
-    if (e < (unsigned)NE) {
+    const unsigned e = threadIdx.x + it * G::NT;
+    if (e < (unsigned)G::NE) {
       const unsigned lr = e / N2, n2 = e % N2;   // lr 0 = halo row r0-1
       const unsigned n1 = (unsigned)(row0 - 1 + (int)lr) & m1;
       const float x0 = X[e];
@@ -616,8 +649,8 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
         const float wh = X[lr * N2 + ((n2 + 1) & (N2 - 1))] - x0;
         const float nh = wh + clip_f(poh[it], kappa);
         qh[it] = 2.f * soft_f(nh, kappa) - nh;
-        vout[o] = nv;
-        vout[cstride + o] = nh;
+        st_off(vout, o, nv);
+        st_off(vout, cstride + o, nh);
       }
     }
   }
@@ -626,14 +659,13 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   float* QH = lds + (RT + 1) * N2;    // [RT + 1][N2], row 0 unused
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
-    const unsigned e = threadIdx.x + it * NT;
-    if (e < (unsigned)NE) {
+    const unsigned e = threadIdx.x + it * G::NT;
+    if (e < (unsigned)G::NE) {
       QV[e] = qv[it];
       if (e >= (unsigned)N2) QH[e] = qh[it];
     }
   }
   __syncthreads();
-  // g = T^T q for own rows; group g (< PAIRS) packs local rows 1+2g, 2+2g
   const bool active = g < PAIRS;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -648,8 +680,17 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     v[q] = cx<float>{ga, gb};
   }
   __syncthreads();
+}
+
+// Forward row FFT of v (two rows per group), split into the half spectra of
+// the two rows, staged and written as the RT tile at `tile`.
+template <int N2>
+__device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[TvGeo<N2>::PPT], float* lds,
+                                                cx<float>* cb, const cx<float>* tw,
+                                                cx<float>* __restrict__ tile, int g, int t) {
+  using G = TvGeo<N2>;
+  constexpr int PPT = G::PPT, T = G::T, H2 = G::H2;
   fft_group<N2, PPT, +1>(v, cb, t, tw);
-  // split into half spectra of the two rows and stage as tile rows 2g, 2g+1
   cx<float>* ostg = reinterpret_cast<cx<float>*>(lds);
   {
     constexpr int QH2 = (N2 / 2) / T + 1;
@@ -669,7 +710,7 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
       }
     }
     __syncthreads();
-    if (active) {
+    if (g < PAIRS) {
 #pragma unroll
       for (int q = 0; q < QH2; ++q) {
         int k = t + T * q;
@@ -682,7 +723,111 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     }
   }
   __syncthreads();
-  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), ostg, H2 * RT);
+  staging_to_tile(tile, ostg, H2 * RT);
+}
+
+template <int N2>
+__global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
+k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
+              const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
+              const cx<float>* __restrict__ twg, float kappa, int first) {
+  using G = TvGeo<N2>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
+  const int g = threadIdx.x / G::T, t = threadIdx.x % G::T;
+  const int tiles = N1 / RT;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b / tiles, row0 = (b % tiles) * RT;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+  const unsigned cstride = (unsigned)S * N1 * N2;   // component stride within a buffer
+  lds_load_table(tw, twg, N2);
+  tv_stage_rows<N2>(Yin, stg, s, row0, N1);
+  float pov[G::PER], poh[G::PER];
+  tv_prefetch<N2>(vin, pov, poh, s, row0, N1, cstride, first);
+  tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+  cx<float> v[G::PPT];
+  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, g, t, v);
+  tv_forward_rows<N2>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
+}
+
+// Row pass of the TV3D prior: T adds the band difference w_b[s] = x[s+1] -
+// x[s] (s < S - 1; none after the last plane), whose adjoint adds
+// q_b[s-1] - q_b[s] to g of plane s. One work-group per (plane s, row tile),
+// as for TV2D; to form the band terms it also inverse-transforms the same
+// rows of planes s - 1 and s + 1 (x of a neighbouring plane is recomputed
+// rather than exchanged between work-groups). q_b[s] is computed identically
+// by the work-groups of planes s and s + 1 (same inputs, same arithmetic);
+// only the former stores the band state of plane s.
+// State buffer layout [3][S][N1][N2] (vertical, horizontal, band).
+template <int N2>
+__global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
+k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
+               const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
+               const cx<float>* __restrict__ twg, float kappa, int first) {
+  using G = TvGeo<N2>;
+  constexpr int PPT = G::PPT, T = G::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int tiles = N1 / RT;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b / tiles, row0 = (b % tiles) * RT;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+  const unsigned plane = (unsigned)N1 * N2;
+  const unsigned cstride = (unsigned)S * plane;
+  const bool active = g < PAIRS;
+  // own elements of this thread: rows row0 + 2g, row0 + 2g + 1 at columns
+  // t + T q (local LDS rows 1 + 2g, 2 + 2g)
+  const unsigned oa = (unsigned)(row0 + 2 * g) * N2 + t;
+  const float* Xa = lds + (1 + 2 * g) * N2 + t;
+  const float* Xb = Xa + N2;
+  lds_load_table(tw, twg, N2);
+  tv_stage_rows<N2>(Yin, stg, s, row0, N1);
+  float pov[G::PER], poh[G::PER];
+  tv_prefetch<N2>(vin, pov, poh, s, row0, N1, cstride, first);
+  tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+  float xa[PPT], xb[PPT];   // x of plane s, own elements
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    xa[q] = active ? Xa[T * q] : 0.f;
+    xb[q] = active ? Xb[T * q] : 0.f;
+  }
+  cx<float> v[PPT];
+  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, g, t, v);
+  // band terms: first + q_b[s-1] (from plane s-1), then - q_b[s] (plane s+1)
+  for (int d = 0; d < 2; ++d) {
+    const int sn = d == 0 ? s - 1 : s + 1;   // neighbouring plane
+    if (sn < 0 || sn >= S) continue;         // uniform over the work-group
+    tv_stage_rows<N2>(Yin, stg, sn, row0, N1);
+    tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+    const unsigned bo = 2 * cstride + (unsigned)(d == 0 ? s - 1 : s) * plane + oa;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      if (active) {
+        const float pa = first ? 0.f : ld_off(vin, bo + T * q);
+        const float pb = first ? 0.f : ld_off(vin, bo + N2 + T * q);
+        const float wa = d == 0 ? xa[q] - Xa[T * q] : Xa[T * q] - xa[q];
+        const float wb = d == 0 ? xb[q] - Xb[T * q] : Xb[T * q] - xb[q];
+        const float na = wa + clip_f(pa, kappa);
+        const float nb = wb + clip_f(pb, kappa);
+        const float qa = 2.f * soft_f(na, kappa) - na;
+        const float qb = 2.f * soft_f(nb, kappa) - nb;
+        if (d == 0) {
+          v[q] = cx<float>{v[q].x + qa, v[q].y + qb};
+        } else {
+          st_off(vout, bo + T * q, na);
+          st_off(vout, bo + N2 + T * q, nb);
+          v[q] = cx<float>{v[q].x - qa, v[q].y - qb};
+        }
+      }
+    }
+    __syncthreads();   // X is read above; the next staging overwrites it
+  }
+  tv_forward_rows<N2>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
@@ -694,9 +839,22 @@ __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
 //   X(w) = xh0(w) + A(w) g(w)    (A = rho Psi^+ / (N1 N2), packed Hermitian)
 // -> inverse column FFT -> [column DCT] -> RT output.
 // DCT = true for the DCT prior (T acts on both axes), false for TV priors.
-// The solve tables of this thread's frequencies are loaded at kernel start so
-// that their latency overlaps the first transforms.
-// LDS: [twiddles N1][DCT table E N1][S x 2 x padded N1].
+// For S <= COL_PF_MAX_S the solve tables of this thread's frequencies are
+// loaded at kernel start so that their latency overlaps the first
+// transforms; for more planes that would not fit in registers and they are
+// loaded in the solve itself.
+// LDS: [twiddles N1][DCT table E N1, when it fits][S x padded N1 complex];
+// when the E table does not fit (N1 = 2048 with many planes) it is read
+// from global memory.
+constexpr int COL_PF_MAX_S = 4;
+constexpr int LDS_BYTES_MAX = 160 * 1024;
+template <int N1, int S> constexpr bool col_e_in_lds() {
+  return (4 * N1 + S * 2 * padded_len(N1)) * 4 <= LDS_BYTES_MAX;
+}
+template <int N1, bool DCT, int S> constexpr int col_lds_floats() {
+  return 2 * N1 + (DCT && col_e_in_lds<N1, S>() ? 2 * N1 : 0) + S * 2 * padded_len(N1);
+}
+
 template <int N1, bool DCT, int S>
 __global__ void __launch_bounds__(S * (N1 / ppt_col<N1>()))
 k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int H2,
@@ -706,11 +864,15 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   constexpr int PPT = ppt_col<N1>();
   constexpr int T = N1 / PPT;
   constexpr int PL = padded_len(N1);
-  constexpr int SO = S > 1 ? S - 1 : 1;
+  constexpr bool PF = S <= COL_PF_MAX_S;
+  constexpr int SO = PF && S > 1 ? S - 1 : 1;
+  constexpr int PQ = PF ? PPT : 1;
+  constexpr bool ELDS = DCT && col_e_in_lds<N1, S>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
-  cx<float>* ew = tw + N1;
-  float* lds = reinterpret_cast<float*>(smem_raw) + 4 * N1;
+  cx<float>* ewl = tw + N1;
+  const cx<float>* ew = ELDS ? ewl : ewg;
+  float* lds = reinterpret_cast<float*>(smem_raw) + (ELDS ? 4 : 2) * N1;
   const int k2 = xcd_remap(blockIdx.x, gridDim.x);
   // plane index; uniform across a wavefront when a group spans whole waves
   const int g = (T % 64 == 0) ? __builtin_amdgcn_readfirstlane(threadIdx.x / T)
@@ -720,27 +882,38 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   const size_t F = (size_t)N1 * H2;
   const size_t f0 = (size_t)k2 * N1 + t;
   // solve tables: x_hat0 of plane g, row g of A
-  cx<float> pxh[PPT], pao[SO][PPT];
-  float pdg[PPT];
+  cx<float> pxh[PPT], pao[SO][PQ];
+  float pdg[PQ];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) pxh[q] = xh0[(size_t)g * F + f0 + T * q];
-  if (!zero_in) {
+  // without prefetch: offset of A[g][j] (packed upper triangle) and the sign
+  // of its imaginary part (conjugate below the diagonal), per j != g
+  size_t arow[S > 1 ? S - 1 : 1];
+  float asgn[S > 1 ? S - 1 : 1];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) pdg[q] = Adiag[(size_t)g * F + f0 + T * q];
+  for (int jj = 0; jj < S - 1; ++jj) {
+    const int j = jj < g ? jj : jj + 1;
+    arow[jj] = (size_t)(g < j ? pair_index(g, j, S) : pair_index(j, g, S)) * F;
+    asgn[jj] = g < j ? 1.f : -1.f;
+  }
+  if (PF && !zero_in) {
 #pragma unroll
-    for (int jj = 0; jj < S - 1; ++jj) {
+    for (int q = 0; q < PQ; ++q) pdg[q] = Adiag[(size_t)g * F + f0 + T * q];
+#pragma unroll
+    for (int jj = 0; jj < SO; ++jj) {
+      if (jj >= S - 1) break;
       const int j = jj < g ? jj : jj + 1;
       const int e = g < j ? pair_index(g, j, S) : pair_index(j, g, S);
       const cx<float>* src = Aoff + (size_t)e * F + f0;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
+      for (int q = 0; q < PQ; ++q) {
         cx<float> a = src[T * q];
         pao[jj][q] = g < j ? a : conjx(a);
       }
     }
   }
   lds_load_table(tw, twg, N1);
-  if (DCT) lds_load_table(ew, ewg, N1);
+  if (ELDS) lds_load_table(ewl, ewg, N1);
   cx<float> v[PPT];
   if (!zero_in) {
 #pragma unroll
@@ -757,13 +930,24 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
     for (int q = 0; q < PPT; ++q) {
       const int k1 = t + T * q;
       cx<float> gg = ldc(cb, k1);
-      cx<float> acc = {pxh[q].x + pdg[q] * gg.x, pxh[q].y + pdg[q] * gg.y};
+      const float dg = PF ? pdg[q % PQ] : Adiag[(size_t)g * F + f0 + T * q];
+      cx<float> acc = {pxh[q].x + dg * gg.x, pxh[q].y + dg * gg.y};
 #pragma unroll
       for (int jj = 0; jj < S - 1; ++jj) {
         const int j = jj < g ? jj : jj + 1;
-        acc = acc + cmul(pao[jj][q], ldc(reinterpret_cast<const cx<float>*>(lds) + j * PL, k1));
+        cx<float> a;
+        if constexpr (PF) {
+          a = pao[jj % SO][q % PQ];
+        } else {
+          a = Aoff[arow[jj] + f0 + T * q];
+          a.y *= asgn[jj];
+        }
+        acc = acc + cmul(a, ldc(reinterpret_cast<const cx<float>*>(lds) + j * PL, k1));
       }
       v[q] = acc;
+      // without prefetch, keep the table loads of one frequency at a time
+      // (otherwise the scheduler hoists all of them and spills)
+      if constexpr (!PF) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();   // every plane's scratch was read by the solve
   } else {
