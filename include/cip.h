@@ -144,6 +144,18 @@ int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* st
 /* Release the host-side plan object (the workspace stays the caller's). */
 int cip_plan_destroy(cip_plan_t plan);
 
+/* ---- shared tables, separate solve state ---------------------------------
+ * A plan's workspace holds read-only tables (Alg. 1/2 step 2: spectra,
+ * per-frequency inverses, dictionaries) followed by the state of one solve.
+ * cip_plan_attach creates a plan that shares `base`'s tables and keeps its
+ * solve state in `d_state` (device, 256-byte aligned, at least
+ * cip_plan_state_bytes bytes, owned by the caller): several solves of the
+ * same operator then run concurrently, one per attached plan, each on its own
+ * stream. No GPU work; `base` must outlive the attached plans, which are
+ * released with cip_plan_destroy. */
+int cip_plan_state_bytes(cip_plan_t plan, size_t* bytes);
+int cip_plan_attach(cip_plan_t base, void* d_state, size_t bytes, cip_plan_t* out);
+
 /* ---- batches of independent solves --------------------------------------
  * A batch runs n independent cip_solve calls (distinct plans, each with its
  * own measurements, iteration count and output) concurrently: the problems
@@ -162,6 +174,49 @@ int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, co
                      float* const* d_x, int n_streams, int use_graph, cip_batch_t* out);
 int cip_batch_launch(cip_batch_t batch, void* stream);
 int cip_batch_destroy(cip_batch_t batch);
+
+/* ---- request server (continuous batching on one GPU) ---------------------
+ * The server owns one device arena of hbm_budget_bytes (allocated by
+ * cip_server_create, freed by cip_server_destroy; nothing else is allocated
+ * on the device afterwards). Operators (plans of fixed K, S, N1, N2, kernels,
+ * prior, rho, lambda) are registered once and keep their tables resident.
+ * Requests name an operator and carry HOST buffers: y [K][N1][N2] (read
+ * after admission) and x [S][N1][N2] (written before completion); both must
+ * stay valid until the request has finished. n_slots worker threads, each
+ * with its own HIP stream, admit queued requests oldest-first by HBM
+ * footprint (solve state + y + x must fit in the free part of the arena; a
+ * request can be overtaken by smaller ones at most 16 times), run cip_solve
+ * on a state attached to the operator's tables, and release the memory:
+ * requests arriving while others run are admitted as slots and memory free
+ * up, and their GPU work overlaps. Each result equals that of a lone
+ * cip_solve with the same operator and iteration count.
+ * Latency = completion - submission (host steady clock, seconds). */
+typedef struct cip_server_s* cip_server_t;
+typedef struct {
+  size_t hbm_budget_bytes;   /* device memory for operators and requests    */
+  int n_slots;               /* concurrent solves, 1 .. 16                  */
+} cip_server_config;
+typedef struct {
+  int op;                    /* operator id from cip_server_add_operator    */
+  const float* y;            /* host [K][N1][N2]                            */
+  float* x;                  /* host [S][N1][N2]                            */
+  int iters;                 /* ADMM iterations (>= 1)                      */
+} cip_request;
+int cip_server_create(const cip_server_config* cfg, cip_server_t* out);
+/* d_psf: device [K][S][N1][N2], read during the call. CIP_ENOSPC when the
+ * operator's workspace does not fit in the free part of the arena. */
+int cip_server_add_operator(cip_server_t server, int K, int S, int N1, int N2, const float* d_psf,
+                            const cip_prior_desc* prior, double rho, double lambda, int* op_id);
+/* Queue a request; CIP_ENOSPC when it could never fit in the budget. */
+int cip_server_submit(cip_server_t server, const cip_request* req, uint64_t* ticket);
+/* *done = 1 once the request has finished (then *latency_s is set; a failed
+ * request returns its error code), else 0. */
+int cip_server_poll(cip_server_t server, uint64_t ticket, int* done, double* latency_s);
+/* Block until the request has finished; returns its status. queue_s = time
+ * from submission to admission. Either output may be NULL. */
+int cip_server_wait(cip_server_t server, uint64_t ticket, double* latency_s, double* queue_s);
+/* Finish every queued request, stop the workers, release the arena. */
+int cip_server_destroy(cip_server_t server);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* cip_last_error(void);

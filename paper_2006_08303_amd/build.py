@@ -2,7 +2,8 @@
 
 Translation units: csrc/cip.hip (C ABI, plan, operators, row passes),
 csrc/patch.hip (patch-dictionary MFMA kernels), csrc/conv.hip
-(convolutional-dictionary kernels) and one csrc/col_pass.hip
+(convolutional-dictionary kernels), csrc/server.hip (request server on
+the plan API) and one csrc/col_pass.hip
 instance per supported column length. They are compiled in
 parallel and linked into paper_2006_08303_amd/libcip.so.
 """
@@ -31,7 +32,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     tmpdir = tempfile.mkdtemp(prefix="cipbuild_")
     jobs = [(os.path.join(CSRC, "cip.hip"), os.path.join(tmpdir, "cip.o"), []),
             (os.path.join(CSRC, "patch.hip"), os.path.join(tmpdir, "patch.o"), []),
-            (os.path.join(CSRC, "conv.hip"), os.path.join(tmpdir, "conv.o"), [])]
+            (os.path.join(CSRC, "conv.hip"), os.path.join(tmpdir, "conv.o"), []),
+            (os.path.join(CSRC, "server.hip"), os.path.join(tmpdir, "server.o"), [])]
     for n in SIZES:
         jobs.append((os.path.join(CSRC, "col_pass.hip"), os.path.join(tmpdir, f"col_{n}.o"),
                      [f"-DCIP_COL_N={n}"]))
@@ -51,7 +53,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     if failed:
         raise RuntimeError("hipcc failed compiling libcip")
     tmp = out + ".tmp"
-    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for _, o, _ in jobs], "-o", tmp]
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for _, o, _ in jobs], "-o", tmp,
+            "-lpthread"]
     if verbose:
         print(" ".join(link), flush=True)
     r = subprocess.run(link, capture_output=True, text=True)

@@ -50,6 +50,15 @@ def _desc(prior, beta, dictionary=None, filters=None):
     return d
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("y", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("iters", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -76,9 +85,22 @@ def lib():
                                        ctypes.POINTER(vp)]
         L.cip_batch_launch.argtypes = [vp, vp]
         L.cip_batch_destroy.argtypes = [vp]
+        L.cip_plan_state_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.cip_plan_attach.argtypes = [vp, vp, sz, ctypes.POINTER(vp)]
+        L.cip_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+        L.cip_server_add_operator.argtypes = [vp, i, i, i, i, vp, ctypes.POINTER(_PriorDesc), d, d,
+                                              ctypes.POINTER(i)]
+        L.cip_server_submit.argtypes = [vp, ctypes.POINTER(_Request),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.cip_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(d)]
+        L.cip_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(d), ctypes.POINTER(d)]
+        L.cip_server_destroy.argtypes = [vp]
         for name in ("cip_plan_workspace_bytes", "cip_plan_create", "cip_forward", "cip_adjoint",
                      "cip_solve", "cip_plan_destroy", "cip_time_kernel", "cip_batch_create",
-                     "cip_batch_launch", "cip_batch_destroy"):
+                     "cip_batch_launch", "cip_batch_destroy", "cip_plan_state_bytes",
+                     "cip_plan_attach", "cip_server_create", "cip_server_add_operator",
+                     "cip_server_submit", "cip_server_poll", "cip_server_wait",
+                     "cip_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -166,6 +188,11 @@ class Plan:
                                _dev_f32(x, (self.S, self.N1, self.N2), "x"), _stream_ptr(stream)))
         return x
 
+    def attach(self):
+        """A plan sharing this plan's tables with a solve state of its own
+        (cip_plan_attach); the state buffer is allocated here."""
+        return AttachedPlan(self)
+
     def time_kernel(self, which, reps, stream=None):
         us = ctypes.c_double()
         _check(lib().cip_time_kernel(self._h, int(which), int(reps), _stream_ptr(stream),
@@ -215,3 +242,85 @@ class Batch:
         if h is not None and _lib is not None:
             _lib.cip_batch_destroy(h)
             self._h = None
+
+
+class AttachedPlan(Plan):
+    """Plan that shares `base`'s tables (cip_plan_attach) and owns a solve
+    state buffer."""
+
+    def __init__(self, base):
+        self.K, self.S, self.N1, self.N2 = base.K, base.S, base.N1, base.N2
+        self.prior, self.rho, self.lam, self.beta = base.prior, base.rho, base.lam, base.beta
+        self._base = base
+        n = ctypes.c_size_t()
+        _check(lib().cip_plan_state_bytes(base._h, ctypes.byref(n)))
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=base.workspace.device)
+        h = ctypes.c_void_p()
+        _check(lib().cip_plan_attach(base._h, ctypes.c_void_p(self.workspace.data_ptr()), n.value,
+                                     ctypes.byref(h)))
+        self._h = h
+
+
+class Server:
+    """Request server (cip_server_*): operators registered once, requests
+    with host numpy buffers, continuous batching over n_slots streams."""
+
+    def __init__(self, hbm_budget_bytes, n_slots=4):
+        cfg = _ServerConfig(int(hbm_budget_bytes), int(n_slots))
+        h = ctypes.c_void_p()
+        _check(lib().cip_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        self.ops = []
+
+    def add_operator(self, psf, prior="tv3d", rho=1e-2, lam=1e-3, beta=1.0, dictionary=None,
+                     filters=None):
+        K, S, N1, N2 = (int(v) for v in psf.shape)
+        desc = _desc(prior, beta, dictionary, filters)
+        op = ctypes.c_int()
+        _check(lib().cip_server_add_operator(self._h, K, S, N1, N2,
+                                             _dev_f32(psf, (K, S, N1, N2), "psf"),
+                                             ctypes.byref(desc), float(rho), float(lam),
+                                             ctypes.byref(op)))
+        self.ops.append((K, S, N1, N2))
+        return op.value
+
+    def submit(self, op, y, x, iters):
+        """y: float32 C-contiguous numpy [K, N1, N2]; x: float32 numpy
+        [S, N1, N2] written on completion. Returns the ticket."""
+        import numpy as np
+        K, S, N1, N2 = self.ops[op]
+        for a, shp, nm in ((y, (K, N1, N2), "y"), (x, (S, N1, N2), "x")):
+            if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags.c_contiguous
+                    and a.shape == shp):
+                raise ValueError(f"{nm} must be a C-contiguous float32 array of shape {shp}")
+        req = _Request(int(op), ctypes.c_void_p(y.ctypes.data), ctypes.c_void_p(x.ctypes.data),
+                       int(iters))
+        t = ctypes.c_uint64()
+        _check(lib().cip_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (y, x)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(lib().cip_server_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(lat)))
+        return bool(done.value), lat.value
+
+    def wait(self, ticket):
+        """Block until done; returns (latency_s, queue_s)."""
+        lat, qs = ctypes.c_double(), ctypes.c_double()
+        rc = lib().cip_server_wait(self._h, int(ticket), ctypes.byref(lat), ctypes.byref(qs))
+        self._keep.pop(int(ticket), None)
+        _check(rc)
+        return lat.value, qs.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cip_server_destroy(h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()

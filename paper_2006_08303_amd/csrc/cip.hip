@@ -18,6 +18,7 @@
 #include "launch.hpp"
 #include "patch_launch.hpp"
 #include "conv_launch.hpp"
+#include "errors.hpp"
 
 using namespace cip;
 
@@ -31,12 +32,6 @@ __global__ void k_promote(const float* __restrict__ src, double* __restrict__ ds
 
 namespace {
 
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -49,17 +44,28 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Workspace carve-up. Every field is a byte offset into the caller's buffer.
+// Workspace carve-up. A plan's memory has two regions: the tables (twiddles,
+// spectra, per-frequency inverses, dictionaries; read-only once the plan is
+// built) followed by the solve state (x_hat0, staging, ADMM state; written by
+// every solve). The FP64 scratch used while the plan is built aliases the
+// state region, which is dead until the first solve. Every field is a byte
+// offset into its region; offsets into the state region carry STATE_BIT.
+// Plans attached to a built plan (cip_plan_attach) share its tables and have
+// a state region of their own.
+constexpr size_t STATE_BIT = size_t(1) << 62;
+
 struct Layout {
   size_t twN1f, twN2f, twN1d, twN2d;  // FFT twiddles
   size_t ew1, ew2;                      // DCT tables exp(-i pi k / 2N) (N1 and N2)
-  size_t lam32, Adiag, Aoff, Mm, xh0;   // per-frequency tables
+  size_t lam32, Adiag, Aoff, Mm, xh0;   // per-frequency tables (x_hat0 per solve)
   size_t bufA, bufB;                    // RT staging (max(K,S) planes)
   size_t state;                         // ADMM state
   size_t lam64, rt64, pl64;             // plan-time FP64 scratch
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
   size_t th32, gam, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
-  size_t total;
+  size_t tables;                        // bytes of the table region
+  size_t state_bytes;                   // bytes of the state region
+  size_t total;                         // tables + state_bytes
 };
 
 int state_floats_per_voxel(int kind) {
@@ -77,50 +83,62 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   Layout L{};
   const int kind = prior->kind;
   const size_t H2 = N2 / 2 + 1, F = (size_t)N1 * H2, P = (size_t)(K > S ? K : S);
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t r = o;
-    o += align256(bytes);
+  size_t ot = 0, os = 0, oc = 0;
+  auto tab = [&](size_t bytes) {
+    size_t r = ot;
+    ot += align256(bytes);
     return r;
   };
-  L.twN1f = take(N1 * 8);
-  L.twN2f = take(N2 * 8);
-  L.twN1d = take(N1 * 16);
-  L.twN2d = take(N2 * 16);
-  L.ew1 = take(N1 * 8);
-  L.ew2 = take(N2 * 8);
-  L.lam32 = take((size_t)K * S * F * 8);
-  L.Adiag = take((size_t)S * F * 4);
-  L.Aoff = take((size_t)(S * (S - 1) / 2) * F * 8 + 8);
-  L.Mm = take((size_t)S * K * F * 8);
-  L.xh0 = take((size_t)S * F * 8);
-  L.bufA = take(P * F * 8);
-  L.bufB = take(P * F * 8);
-  L.state = take((size_t)state_floats_per_voxel(kind) * S * N1 * N2 * 4);
-  L.lam64 = take((size_t)K * S * F * 16);
-  L.rt64 = take(F * 16);
-  L.pl64 = take((size_t)N1 * N2 * 8);
+  auto sta = [&](size_t bytes) {
+    size_t r = os;
+    os += align256(bytes);
+    return r | STATE_BIT;
+  };
+  auto scr = [&](size_t bytes) {   // plan-time scratch, aliases the state region
+    size_t r = oc;
+    oc += align256(bytes);
+    return r | STATE_BIT;
+  };
+  L.twN1f = tab(N1 * 8);
+  L.twN2f = tab(N2 * 8);
+  L.twN1d = tab(N1 * 16);
+  L.twN2d = tab(N2 * 16);
+  L.ew1 = tab(N1 * 8);
+  L.ew2 = tab(N2 * 8);
+  L.lam32 = tab((size_t)K * S * F * 8);
+  L.Adiag = tab((size_t)S * F * 4);
+  L.Aoff = tab((size_t)(S * (S - 1) / 2) * F * 8 + 8);
+  L.Mm = tab((size_t)S * K * F * 8);
+  L.xh0 = sta((size_t)S * F * 8);
+  L.bufA = sta(P * F * 8);
+  L.bufB = sta(P * F * 8);
+  L.state = sta((size_t)state_floats_per_voxel(kind) * S * N1 * N2 * 4);
+  L.lam64 = scr((size_t)K * S * F * 16);
+  L.rt64 = scr(F * 16);
+  L.pl64 = scr((size_t)N1 * N2 * 8);
   if (kind == CIP_PRIOR_PATCH) {
     const size_t nv = (size_t)64 * S, na = (size_t)prior->n_atoms;
     const size_t J = (size_t)(N1 / 4) * (N2 / 4);
-    L.dbf = take(nv * na * 2);
-    L.m1bf = take(na * nv * 2);
-    L.vpatch = take(na * J * 4);
-    L.tbuf = take(patch_tile_buffer_floats(S, N1, N2) * 4);
-    L.rimg = take((size_t)S * N1 * N2 * 4);
+    L.dbf = tab(nv * na * 2);
+    L.m1bf = tab(na * nv * 2);
+    L.vpatch = sta(na * J * 4);
+    L.tbuf = sta(patch_tile_buffer_floats(S, N1, N2) * 4);
+    L.rimg = sta((size_t)S * N1 * N2 * 4);
   }
   if (kind == CIP_PRIOR_CONV2D) {
     const size_t M = (size_t)prior->n_filters;
-    L.th32 = take(M * F * 8);
-    L.gam = take(F * 4);
-    L.gv = take(M * S * F * 8);
-    L.dhat = take((size_t)S * F * 8);
-    L.xhat = take((size_t)S * F * 8);
-    L.rtc = take(M * S * F * 8);
-    L.vconv = take(M * S * (size_t)N1 * N2 * 4);
-    L.th64 = take(M * F * 16);
+    L.th32 = tab(M * F * 8);
+    L.gam = tab(F * 4);
+    L.gv = sta(M * S * F * 8);
+    L.dhat = sta((size_t)S * F * 8);
+    L.xhat = sta((size_t)S * F * 8);
+    L.rtc = sta(M * S * F * 8);
+    L.vconv = sta(M * S * (size_t)N1 * N2 * 4);
+    L.th64 = scr(M * F * 16);
   }
-  L.total = o;
+  L.tables = ot;
+  L.state_bytes = os > oc ? os : oc;
+  L.total = L.tables + L.state_bytes;
   return L;
 }
 
@@ -153,10 +171,14 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
 struct cip_plan_s {
   int K, S, N1, N2, H2, kind, n_atoms, n_filters;
   double beta, rho, lambda;
-  unsigned char* ws;
+  unsigned char* ws;    // table region
+  unsigned char* sws;   // state region
   Layout L;
   bool solved_once;
-  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  bool attached;        // shares another plan's tables
+  template <typename T> T* at(size_t off) const {
+    return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
+  }
 };
 
 // ---------------------------------------------------------------- launch helpers
@@ -536,8 +558,10 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->rho = rho;
   p->lambda = lambda;
   p->ws = reinterpret_cast<unsigned char*>(d_workspace);
+  p->sws = p->ws + L.tables;
   p->L = L;
   p->solved_once = false;
+  p->attached = false;
 
   auto cleanup_fail = [&](int code, const std::string& m) {
     delete p;
@@ -674,6 +698,25 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
 
 int cip_plan_destroy(cip_plan_t p) {
   delete p;
+  return CIP_OK;
+}
+
+int cip_plan_state_bytes(cip_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return fail(CIP_EINVAL, "NULL argument");
+  *bytes = p->L.state_bytes;
+  return CIP_OK;
+}
+
+int cip_plan_attach(cip_plan_t base, void* d_state, size_t bytes, cip_plan_t* out) {
+  if (!base || !d_state || !out) return fail(CIP_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_state) % 256)
+    return fail(CIP_EINVAL, "state buffer must be 256-byte aligned");
+  if (bytes < base->L.state_bytes) return fail(CIP_ENOSPC, "state buffer too small");
+  cip_plan_s* p = new cip_plan_s(*base);
+  p->sws = reinterpret_cast<unsigned char*>(d_state);
+  p->solved_once = false;
+  p->attached = true;
+  *out = p;
   return CIP_OK;
 }
 
