@@ -123,6 +123,128 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     return plan, y_t, lam, rho, beta, value, ms_step, times, names
 
 
+def run_batch(args, dev):
+    """Many independent problems (mixed N, K, S, TV2D / DCT priors, 100
+    iterations each) as one captured batch on internal streams, against the
+    same solves issued one after another on one stream. Throughput is
+    counted in voxels (N1 N2 S) times iterations."""
+    rng = np.random.default_rng(4000)
+    sizes = [n for n in (128, 256, 384, 512, 768, 1024) if n in cip.SUPPORTED_N]
+    probs, vox = [], 0
+    for j in range(args.batch):
+        N = int(rng.choice(sizes))
+        K, S = int(rng.integers(2, 7)), int(rng.integers(2, 7))
+        prior = "tv2d" if rng.random() < 0.5 else "dct2d"
+        psf = (synth.gaussian_psfs(synth.rng_for(4, 10 + j), K, S, N, N) if rng.random() < 0.5
+               else synth.disk_psfs(K, S, N, N))
+        lam, rho, beta = PRIOR_PARAMS[prior]
+        plan = cip.Plan(torch.tensor(psf, dtype=torch.float32, device=dev), prior, rho, lam, beta)
+        y = torch.randn((K, N, N), device=dev)
+        x = torch.empty((S, N, N), device=dev)
+        probs.append((plan, y, args.iters, x))
+        vox += S * N * N
+    torch.cuda.synchronize()
+
+    def seq():
+        for p, y, it, x in probs:
+            p.solve(y, it, out=x)
+
+    b = cip.Batch(probs, n_streams=4, graph=True)
+
+    def timed(f, reps=2):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    ts, tb = timed(seq), timed(b.launch)
+    print(f"[bench] batch of {len(probs)}: sequential {ts * 1e3:.1f} ms, graph batch "
+          f"{tb * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"problems": len(probs), "sizes": sizes, "iters": args.iters,
+            "Mvoxel_iter_per_s": round(vox * args.iters / tb / 1e6, 1),
+            "sequential_Mvoxel_iter_per_s": round(vox * args.iters / ts / 1e6, 1),
+            "speedup_vs_sequential": round(ts / tb, 3),
+            "ms_batch": round(tb * 1e3, 2), "ms_sequential": round(ts * 1e3, 2),
+            "mode": "one hipGraph launch, 4 internal streams"}
+
+
+def run_serving(args, dev, n_slots):
+    """Poisson arrivals replayed against the request server: TV3D solves of
+    N x N x S problems (N, K = S drawn per request), host buffers in and out
+    (PCIe copies included in the latency). Returns latency percentiles and
+    throughput."""
+    import threading
+    rng = np.random.default_rng(5000)
+    sizes = [n for n in (256, 384, 512, 768, 1024, 1536, 2048) if n in cip.SUPPORTED_N]
+    kinds = [(N, B) for N in sizes for B in (3, 5, 8)]
+    srv = cip.Server(args.serve_budget_gb << 30, n_slots=n_slots)
+    ops, ys, pools = [], [], []
+    for j, (N, B) in enumerate(kinds):
+        psf = synth.disk_psfs(B, B, N, N)
+        ops.append(srv.add_operator(torch.tensor(psf, dtype=torch.float32, device=dev), "tv3d",
+                                    1e-2, 1e-3, 1.0))
+        ys.append(np.ascontiguousarray(
+            synth.unit_noise(synth.rng_for(5, j), B, N, N).astype(np.float32)))
+        pools.append([])
+    torch.cuda.synchronize()
+    n_req = int(args.serve_seconds * args.serve_rate)
+    gaps = rng.exponential(1.0 / args.serve_rate, n_req)
+    which = rng.integers(0, len(kinds), n_req)
+    lock = threading.Lock()
+    tickets, lat = [], []
+    done = threading.Event()
+
+    def reaper():
+        i = 0
+        while True:
+            with lock:
+                if i >= len(tickets):
+                    if done.is_set():
+                        return
+                    t = None
+                else:
+                    t, j, xb = tickets[i]
+            if t is None:
+                time.sleep(0.001)
+                continue
+            lat.append(srv.wait(t)[0])
+            with lock:
+                pools[j].append(xb)
+            i += 1
+
+    th = threading.Thread(target=reaper)
+    th.start()
+    t0 = time.perf_counter()
+    due = t0
+    for k in range(n_req):
+        due += gaps[k]
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        j = int(which[k])
+        N, B = kinds[j]
+        with lock:
+            xb = pools[j].pop() if pools[j] else np.empty((B, N, N), np.float32)
+        t = srv.submit(ops[j], ys[j], xb, args.iters)
+        with lock:
+            tickets.append((t, j, xb))
+    done.set()
+    th.join()
+    span = time.perf_counter() - t0
+    srv.close()
+    vox = sum(kinds[int(j)][0] ** 2 * kinds[int(j)][1] for j in which) * args.iters
+    lat_ms = np.array(lat) * 1e3
+    return {"slots": n_slots, "requests": n_req, "offered_req_per_s": args.serve_rate,
+            "completed_req_per_s": round(n_req / span, 2),
+            "Mvoxel_iter_per_s": round(vox / span / 1e6, 1),
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+            "makespan_s": round(span, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +257,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tv", action="store_true")
+    ap.add_argument("--batch", type=int, default=96, help="problems in the batch run (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the Poisson arrival trace (0: skip serving)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=int, default=96)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -172,6 +299,21 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    batch = run_batch(args, dev) if args.batch > 0 else None
+    serving = None
+    if args.serve_seconds > 0:
+        print(f"[bench] serving: {args.serve_seconds} s of arrivals at {args.serve_rate} req/s",
+              file=sys.stderr, flush=True)
+        conc = run_serving(args, dev, 4)
+        print(f"[bench] serving (4 slots): {conc}", file=sys.stderr, flush=True)
+        seq = run_serving(args, dev, 1)
+        print(f"[bench] serving (1 slot): {seq}", file=sys.stderr, flush=True)
+        serving = {"workload": "TV3D solves, Poisson arrivals, N in "
+                               f"{[n for n in (256, 384, 512, 768, 1024, 1536, 2048) if n in cip.SUPPORTED_N]}, "
+                               f"K = S in (3, 5, 8), {args.iters} iterations, host buffers",
+                   "continuous_batching": conc, "sequential": seq,
+                   "throughput_speedup": round(conc["Mvoxel_iter_per_s"] /
+                                               max(seq["Mvoxel_iter_per_s"], 1e-9), 3)}
     cpu = None
     if not args.no_cpu:
         y = y_t.double().cpu().numpy()
@@ -196,6 +338,10 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "tv2d": tv,
+        "batch": batch,
+        "serving": serving,
+        "latency_p50_ms": serving["continuous_batching"]["p50_ms"] if serving else None,
+        "latency_p99_ms": serving["continuous_batching"]["p99_ms"] if serving else None,
     }
     print(json.dumps(rec), flush=True)
 
