@@ -28,8 +28,9 @@
  *   - Return value: CIP_OK (0) on success or a negative CIP_E* code; the
  *     message of the last failure on the calling thread is available from
  *     cip_last_error(). A failed call leaves the plan usable.
- *   - Supported grids: N1 and N2 powers of two with 16 <= N <= 2048.
- *     1 <= K, S <= 8; the patch prior needs S <= 4.
+ *   - Supported grids: N1 and N2 in {16, 32, 64, 128, 256, 384, 512, 768,
+ *     1024, 1536, 2048} (powers of two and 3 * 2^k); 1 <= K, S <= 8; the
+ *     patch prior needs S <= 4 and power-of-two N1, N2.
  */
 #ifndef CIP_H_
 #define CIP_H_

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcip.so")
 CSRC = os.path.join(HERE, "csrc")
-SIZES = (16, 32, 64, 128, 256, 512, 1024, 2048)
+SIZES = (16, 32, 64, 128, 256, 384, 512, 768, 1024, 1536, 2048)   # as in csrc/sizes.hpp
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

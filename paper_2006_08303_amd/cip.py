@@ -15,7 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CIP_LIBRARY_PATH") or os.path.join(_HERE, "libcip.so")
 
-SUPPORTED_N = (16, 32, 64, 128, 256, 512, 1024, 2048)   # grid sizes served by the library
+SUPPORTED_N = (16, 32, 64, 128, 256, 384, 512, 768, 1024, 1536, 2048)   # grid sizes served
 
 CIP_PRIOR_TV2D = 0
 CIP_PRIOR_TV3D = 1

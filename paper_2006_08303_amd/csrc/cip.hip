@@ -19,6 +19,7 @@
 #include "patch_launch.hpp"
 #include "conv_launch.hpp"
 #include "errors.hpp"
+#include "sizes.hpp"
 
 using namespace cip;
 
@@ -145,12 +146,15 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
 int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (!prior) return fail(CIP_EINVAL, "prior descriptor is NULL");
   if (K < 1 || K > 8 || S < 1 || S > 8) return fail(CIP_EINVAL, "K and S must be in [1, 8]");
-  if (!is_pow2(N1) || !is_pow2(N2) || N1 < 16 || N2 < 16 || N1 > 2048 || N2 > 2048)
-    return fail(CIP_EUNSUPPORTED, "N1 and N2 must be powers of two in [16, 2048]");
+  if (!size_supported(N1) || !size_supported(N2))
+    return fail(CIP_EUNSUPPORTED,
+                "N1 and N2 must be powers of two in [16, 2048] or one of 384, 768, 1536");
   if (state_floats_per_voxel(prior->kind) < 0)
     return fail(CIP_EUNSUPPORTED, "unsupported prior kind");
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
   if (prior->kind == CIP_PRIOR_PATCH) {
+    if (!is_pow2(N1) || !is_pow2(N2))
+      return fail(CIP_EUNSUPPORTED, "patch prior: power-of-two grids only");
     if (prior->patch_q != 8 || prior->patch_stride != 4)
       return fail(CIP_EUNSUPPORTED, "patch prior: only 8 x 8 x S patches at stride 4");
     if (!patch_supported(S, prior->n_atoms))
@@ -186,18 +190,7 @@ namespace {
 
 
 
-#define DISPATCH_N(N, ...)                                           \
-  switch (N) {                                                       \
-    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;          \
-    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;          \
-    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;          \
-    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;        \
-    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;        \
-    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;        \
-    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;      \
-    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;      \
-    default: return hipErrorInvalidValue;                            \
-  }
+#define DISPATCH_N CIP_DISPATCH_N
 
 template <typename Re>
 hipError_t row_r2c(const Re* in, cx<Re>* out, int P, int N1, int N2, const cx<Re>* tw, hipStream_t st) {
@@ -288,14 +281,7 @@ hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
                                 p->at<const cx<float>>(L.twN1f), p->at<const cx<float>>(L.ew1),  \
                                 zero_in, dct_out, st);
   switch (p->N1) {
-    CIP_COL_CASE(16)
-    CIP_COL_CASE(32)
-    CIP_COL_CASE(64)
-    CIP_COL_CASE(128)
-    CIP_COL_CASE(256)
-    CIP_COL_CASE(512)
-    CIP_COL_CASE(1024)
-    CIP_COL_CASE(2048)
+    CIP_FOR_EACH_SIZE(CIP_COL_CASE)
   }
 #undef CIP_COL_CASE
   return hipErrorInvalidValue;
@@ -421,28 +407,22 @@ hipError_t gram(cip_plan_t p, hipStream_t st) {
 // in the order the device stages read it (see fft_shape): for every stage
 // after the first, [k < Ns][r = 1 .. RS-1] -> W_{Ns RS}^{r k}, computed in
 // double precision. Padded with zeros to N entries.
+// Stage-ordered twiddle table of fft_group (same radix sequence as
+// fft_shape: PPT first, then greedy divisors of PPT).
 void stage_twiddles(int N, int PPT, std::vector<cx<double>>& d) {
   d.assign(N, cx<double>{0.0, 0.0});
-  int nfull = 0, n = N;
-  while (n % PPT == 0 && n >= PPT) {
-    n /= PPT;
-    ++nfull;
-  }
-  const int last = n;
-  int off = 0, ns = PPT;
-  auto put = [&](int ns_, int rs) {
-    for (int k = 0; k < ns_; ++k)
+  int off = 0, ns = PPT, rem = N / PPT;
+  while (rem > 1) {
+    const int rs = next_radix(rem, PPT);
+    for (int k = 0; k < ns; ++k)
       for (int r = 1; r < rs; ++r) {
-        double a = 2.0 * M_PI * (double)r * (double)k / ((double)ns_ * rs);
+        double a = 2.0 * M_PI * (double)r * (double)k / ((double)ns * rs);
         d[off + k * (rs - 1) + r - 1] = cx<double>{std::cos(a), -std::sin(a)};
       }
-    off += ns_ * (rs - 1);
-  };
-  for (int s = 1; s < nfull; ++s) {
-    put(ns, PPT);
-    ns *= PPT;
+    off += ns * (rs - 1);
+    ns *= rs;
+    rem /= rs;
   }
-  if (last > 1) put(ns, last);
 }
 
 void twiddles(int N, int PPT, std::vector<cx<float>>& f, std::vector<cx<double>>& d) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft.hpp"
+#include "sizes.hpp"
 
 namespace cip {
 
@@ -12,14 +13,7 @@ namespace cip {
                                   int H2, const float* Adiag, const cx<float>* Aoff,           \
                                   const cx<float>* xh0, const cx<float>* tw,                   \
                                   const cx<float>* ew, int zero_in, int dct_out, hipStream_t st);
-CIP_DECLARE_COL(16)
-CIP_DECLARE_COL(32)
-CIP_DECLARE_COL(64)
-CIP_DECLARE_COL(128)
-CIP_DECLARE_COL(256)
-CIP_DECLARE_COL(512)
-CIP_DECLARE_COL(1024)
-CIP_DECLARE_COL(2048)
+CIP_FOR_EACH_SIZE(CIP_DECLARE_COL)
 #undef CIP_DECLARE_COL
 
 }  // namespace cip

@@ -2,21 +2,9 @@
 #include "conv.hpp"
 #include "conv_launch.hpp"
 #include "launch.hpp"
+#include "sizes.hpp"
 
 namespace cip {
-
-#define CIP_DISPATCH_N(N, ...)                                     \
-  switch (N) {                                                     \
-    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;        \
-    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;        \
-    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;        \
-    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;      \
-    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;      \
-    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;      \
-    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;    \
-    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;    \
-    default: return hipErrorInvalidValue;                          \
-  }
 
 hipError_t conv_place_filter(const float* filt, double* dst, int L, int N1, int N2, hipStream_t st) {
   const size_t n = (size_t)N1 * N2;

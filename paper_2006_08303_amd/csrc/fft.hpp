@@ -183,28 +183,52 @@ constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
 template <int T> __device__ __forceinline__ void group_sync() { __syncthreads(); }
 
 // ---------------------------------------------------------------- group FFT
-// Stockham radix sequence: PPT, PPT, ..., PPT, LAST with PPT^m * LAST = N.
-// Twiddles of every stage after the first are stored per stage as
-// [k in 0..Ns)[r in 1..RS) = W_{Ns RS}^{r k} (forward sign), so a thread reads
-// its RS - 1 twiddles at consecutive addresses.
+// Stockham radix sequence: PPT (first stage, from registers), then radices
+// R_1, R_2, ... each dividing PPT, chosen greedily as the largest divisor of
+// PPT that divides what remains of N / PPT (N = 1024, PPT = 16: 16, 16, 4;
+// N = 384, PPT = 12: 12, 4, 4, 2). Twiddles of every stage after the first
+// are stored per stage as [k in 0..Ns)[r in 1..Rs) = W_{Ns Rs}^{r k}
+// (forward sign), Ns the product of the earlier radices, so a thread reads
+// its Rs - 1 twiddles at consecutive addresses.
+constexpr int next_radix(int rem, int ppt) {
+  for (int d = ppt; d > 1; --d)
+    if (ppt % d == 0 && rem % d == 0) return d;
+  return 0;
+}
 template <int N, int PPT> struct fft_shape {
   static constexpr int T = N / PPT;
-  static constexpr int count_full(int n) { return n % PPT == 0 && n >= PPT ? 1 + count_full(n / PPT) : 0; }
-  static constexpr int pow_ppt(int m) { return m == 0 ? 1 : PPT * pow_ppt(m - 1); }
-  static constexpr int NFULL = count_full(N);
-  static constexpr int LAST = N / pow_ppt(NFULL);   // 1 if N is a power of PPT
-  // offset of the twiddles of middle stage s (1 .. NFULL-1); s = NFULL: last stage
-  static constexpr int stage_off(int s) {
-    int off = 0, ns = PPT;
-    for (int i = 1; i < s; ++i) {
-      off += ns * (PPT - 1);
-      ns *= PPT;
+  static constexpr int nstages() {
+    int rem = N / PPT, c = 0;
+    while (rem > 1) {
+      const int r = next_radix(rem, PPT);
+      if (r == 0) return -1;
+      rem /= r;
+      ++c;
     }
+    return c;
+  }
+  static constexpr int NST = nstages();   // stages after the first
+  static constexpr int radix(int s) {      // radix of stage s = 1 .. NST
+    int rem = N / PPT, r = 0;
+    for (int i = 1; i <= s; ++i) {
+      r = next_radix(rem, PPT);
+      rem /= r;
+    }
+    return r;
+  }
+  static constexpr int ns(int s) {         // product of the radices before stage s
+    int p = PPT;
+    for (int i = 1; i < s; ++i) p *= radix(i);
+    return p;
+  }
+  static constexpr int stage_off(int s) {  // twiddle-table offset of stage s
+    int off = 0;
+    for (int i = 1; i < s; ++i) off += ns(i) * (radix(i) - 1);
     return off;
   }
-  static constexpr int TW_ENTRIES = stage_off(NFULL) + (LAST > 1 ? pow_ppt(NFULL) * (LAST - 1) : 0);
+  static constexpr int TW_ENTRIES = stage_off(NST + 1);
   static_assert(N % PPT == 0, "N must be a multiple of PPT");
-  static_assert(PPT % LAST == 0, "last radix must divide PPT");
+  static_assert(NST >= 0, "N / PPT must factor into divisors of PPT");
 };
 
 // One Stockham stage with radix RS on the group's LDS array buf, after
@@ -272,12 +296,12 @@ __device__ __forceinline__ void stage_lds(cx<R>* buf, int t, const cx<R>* tws, c
 }
 
 template <int N, int PPT, int DIR, typename R, int S>
-__device__ __forceinline__ void middle_stages(cx<R>* buf, int t, const cx<R>* tws, cx<R>* reg) {
+__device__ __forceinline__ void later_stages(cx<R>* buf, int t, const cx<R>* tws, cx<R>* reg) {
   using SH = fft_shape<N, PPT>;
-  if constexpr (S < SH::NFULL) {
-    constexpr bool last = (S == SH::NFULL - 1) && (SH::LAST == 1);
-    stage_lds<N, PPT, PPT, SH::pow_ppt(S), SH::stage_off(S), DIR, last, R>(buf, t, tws, reg);
-    middle_stages<N, PPT, DIR, R, S + 1>(buf, t, tws, reg);
+  if constexpr (S <= SH::NST) {
+    constexpr bool last = S == SH::NST;
+    stage_lds<N, PPT, SH::radix(S), SH::ns(S), SH::stage_off(S), DIR, last, R>(buf, t, tws, reg);
+    later_stages<N, PPT, DIR, R, S + 1>(buf, t, tws, reg);
   }
 }
 
@@ -292,11 +316,11 @@ __device__ __forceinline__ void fft_group(cx<R>* reg, cx<R>* buf, int t, const c
   constexpr int T = SH::T;
   if constexpr (N == 1) return;
   dft<PPT, DIR, R>(reg);   // first radix (Ns = 1, no twiddles)
-  if constexpr (SH::NFULL == 1 && SH::LAST == 1) {
+  if constexpr (SH::NST == 0) {
     return;   // N == PPT
   } else {
     group_sync<T>();
-    if constexpr (PPT <= 16) {
+    if constexpr (16 % PPT == 0) {   // t * PPT + r stays within one padding block
       const int pb = pad(t * PPT);
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
@@ -309,17 +333,17 @@ __device__ __forceinline__ void fft_group(cx<R>* reg, cx<R>* buf, int t, const c
       }
     }
     group_sync<T>();
-    middle_stages<N, PPT, DIR, R, 1>(buf, t, tws, reg);
-    if constexpr (SH::LAST > 1) {
-      stage_lds<N, PPT, SH::LAST, SH::pow_ppt(SH::NFULL), SH::stage_off(SH::NFULL), DIR, true, R>(
-          buf, t, tws, reg);
-      // butterfly b, output r -> element t + T (b + r NB); registers are [b][r]
-      constexpr int NB = PPT / SH::LAST;
+    later_stages<N, PPT, DIR, R, 1>(buf, t, tws, reg);
+    // last stage: butterfly b, output r -> element t + T (b + r NB), where
+    // registers hold [b][r]; reorder to reg[q] = X[t + T q]
+    constexpr int RL = SH::radix(SH::NST);
+    if constexpr (RL < PPT) {
+      constexpr int NB = PPT / RL;
       cx<R> tmp[PPT];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int r = 0; r < SH::LAST; ++r) tmp[b + r * NB] = reg[b * SH::LAST + r];
+        for (int r = 0; r < RL; ++r) tmp[b + r * NB] = reg[b * RL + r];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) reg[q] = tmp[q];
     }

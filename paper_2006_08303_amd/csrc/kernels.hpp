@@ -27,7 +27,10 @@ constexpr int PAIRS = RT / 2;  // row pairs per row-pass work-group
 #ifndef CIP_PPT_COL_1024
 #define CIP_PPT_COL_1024 16
 #endif
-constexpr int ppt_default(int N) { return N >= 16 ? 16 : N; }
+// Lengths with a factor 3 (3 * 2^k) use 12 points per thread, so that the
+// radix-3 butterfly lies in the first, in-register stage; the later stages
+// then use radices 4 and 2 (divisors of 12).
+constexpr int ppt_default(int N) { return N % 3 == 0 ? 12 : (N >= 16 ? 16 : N); }
 constexpr int ppt_row_n(int N) { return N == 1024 ? CIP_PPT_ROW_1024 : ppt_default(N); }
 constexpr int ppt_col_n(int N) { return N == 1024 ? CIP_PPT_COL_1024 : ppt_default(N); }
 template <int N> constexpr int ppt_row() { return ppt_row_n(N); }
@@ -132,7 +135,7 @@ __device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<
     int k = t + T * q;
     if (k <= N2 / 2) {
       cx<float> Z = ldc(cb, k);
-      cx<float> Zc = conjx(ldc(cb, (N2 - k) & (N2 - 1)));
+      cx<float> Zc = conjx(ldc(cb, k == 0 ? 0 : N2 - k));
       cx<float> s = Z + Zc, d = Z - Zc;
       A[q] = cx<float>{0.5f * s.x, 0.5f * s.y};
       B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
@@ -183,7 +186,7 @@ __device__ __forceinline__ void dct_fwd_group(cx<float>* reg, cx<float>* cb, int
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
-    int kk = (N - k) & (N - 1);
+    int kk = k == 0 ? 0 : N - k;
     cx<float> V = ldc(cb, k);
     cx<float> Vc = conjx(ldc(cb, kk));
     cx<float> s = V + Vc, d = V - Vc;
@@ -289,7 +292,7 @@ __global__ void k_row_r2c(const Re* __restrict__ in, cx<Re>* __restrict__ out, i
       int k = t + T * q;
       if (k <= N2 / 2) {
         cx<Re> Z = ldc(cb, k);
-        cx<Re> Zc = conjx(ldc(cb, (N2 - k) & (N2 - 1)));
+        cx<Re> Zc = conjx(ldc(cb, k == 0 ? 0 : N2 - k));
         cx<Re> s = Z + Zc, d = Z - Zc;
         out[rt_idx(p, ra, k, N1, H2)] = cx<Re>{Re(0.5) * s.x, Re(0.5) * s.y};
         out[rt_idx(p, ra + 1, k, N1, H2)] = cx<Re>{Re(0.5) * d.y, Re(-0.5) * d.x};
@@ -573,7 +576,7 @@ __device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float
                                             float (&poh)[TvGeo<N2>::PER], unsigned s, int row0,
                                             int N1, unsigned cstride, int first) {
   using G = TvGeo<N2>;
-  const unsigned plane = (unsigned)N1 * N2, m1 = (unsigned)N1 - 1;
+  const unsigned plane = (unsigned)N1 * N2;
 #pragma unroll
   for (int it = 0; it < G::PER; ++it) {
     const unsigned e = threadIdx.x + it * G::NT;
@@ -581,7 +584,7 @@ __device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float
     poh[it] = 0.f;
     if (e < (unsigned)G::NE && !first) {
       const unsigned lr = e / N2, n2 = e % N2;
-      const unsigned n1 = (unsigned)(row0 - 1 + (int)lr) & m1;
+      const unsigned n1 = (row0 == 0 && lr == 0) ? (unsigned)N1 - 1 : (unsigned)(row0 - 1) + lr;
       const unsigned o = s * plane + n1 * N2 + n2;
       pov[it] = ld_off(vin, o);
       if (lr > 0) poh[it] = ld_off(vin, cstride + o);
@@ -631,7 +634,7 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
                                            cx<float> (&v)[TvGeo<N2>::PPT]) {
   using G = TvGeo<N2>;
   constexpr int PPT = G::PPT, T = G::T, PER = G::PER;
-  const unsigned plane = (unsigned)N1 * N2, m1 = (unsigned)N1 - 1;
+  const unsigned plane = (unsigned)N1 * N2;
   const float* X = lds;
   float qv[PER], qh[PER];
 #pragma unroll
@@ -639,14 +642,14 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
     const unsigned e = threadIdx.x + it * G::NT;
     if (e < (unsigned)G::NE) {
       const unsigned lr = e / N2, n2 = e % N2;   // lr 0 = halo row r0-1
-      const unsigned n1 = (unsigned)(row0 - 1 + (int)lr) & m1;
+      const unsigned n1 = (row0 == 0 && lr == 0) ? (unsigned)N1 - 1 : (unsigned)(row0 - 1) + lr;
       const float x0 = X[e];
       const float wv = X[e + N2] - x0;
       const unsigned o = s * plane + n1 * N2 + n2;
       const float nv = wv + clip_f(pov[it], kappa);
       qv[it] = 2.f * soft_f(nv, kappa) - nv;
       if (lr > 0) {
-        const float wh = X[lr * N2 + ((n2 + 1) & (N2 - 1))] - x0;
+        const float wh = X[lr * N2 + (n2 + 1 == N2 ? 0 : n2 + 1)] - x0;
         const float nh = wh + clip_f(poh[it], kappa);
         qh[it] = 2.f * soft_f(nh, kappa) - nh;
         st_off(vout, o, nv);
@@ -670,7 +673,7 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int n2 = t + T * q;
-    const int nm = (n2 - 1) & (N2 - 1);
+    const int nm = n2 == 0 ? N2 - 1 : n2 - 1;
     float ga = 0.f, gb = 0.f;
     if (active) {
       const int la = 1 + 2 * g, lb = la + 1;
@@ -703,7 +706,7 @@ __device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[TvGeo<N2>::PPT], 
       int k = t + T * q;
       if (k <= N2 / 2) {
         cx<float> Z = ldc(cb, k);
-        cx<float> Zc = conjx(ldc(cb, (N2 - k) & (N2 - 1)));
+        cx<float> Zc = conjx(ldc(cb, k == 0 ? 0 : N2 - k));
         cx<float> sm = Z + Zc, d = Z - Zc;
         A[q] = cx<float>{0.5f * sm.x, 0.5f * sm.y};
         B[q] = cx<float>{0.5f * d.y, -0.5f * d.x};
