@@ -30,6 +30,34 @@ sys.path.insert(0, ROOT)
 from paper_2006_08303_amd import cip, synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "admm_dct_1024_hbm_traffic.json")
+# sources that define the row and column kernels measured by the counters
+KERNEL_SOURCES = ("paper_2006_08303_amd/csrc/kernels.hpp", "paper_2006_08303_amd/csrc/fft.hpp",
+                  "paper_2006_08303_amd/csrc/col_pass.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(which):
+    """Counter-measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each
+    scaled by the copy-kernel calibration) of the 1024^2 K=S=3 DCT kernels,
+    from the committed profile summary; None when the kernel sources have
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get("col" if which == 1 else "row")
 
 
 def algorithmic_bytes(which, S, N1, N2, prior):
@@ -121,6 +149,34 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     print(f"[bench] {prior}: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
           flush=True)
     return plan, y_t, lam, rho, beta, value, ms_step, times, names
+
+
+def run_concurrent(args, dev, psf_t, y_t):
+    """The same K=S=3 1024^2 DCT problem, `args.concurrent` independent copies
+    solved together (one captured batch over as many streams): the working
+    set then exceeds the 256 MB Infinity Cache, and the GPU is filled with
+    work from several solves at once."""
+    n = args.concurrent
+    lam, rho, beta = PRIOR_PARAMS["dct2d"]
+    plans = [cip.Plan(psf_t, "dct2d", rho, lam, beta) for _ in range(n)]
+    xs = [torch.empty((plans[0].S, plans[0].N1, plans[0].N2), device=dev) for _ in range(n)]
+    b = cip.Batch([(plans[i], y_t, args.iters, xs[i]) for i in range(n)], n_streams=n, graph=True)
+    b.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    N = plans[0].N1
+    byt = algorithmic_bytes(0, 3, N, N, "dct2d") + algorithmic_bytes(1, 3, N, N, "dct2d")
+    print(f"[bench] {n} concurrent solves: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    return {"problems": n, "ms_per_batch": round(dt * 1e3, 3),
+            "Mpixel_iter_per_s": round(n * N * N * args.iters / dt / 1e6, 1),
+            "algorithmic_GB_per_s": round(byt / (dt / (n * args.iters)) / 1e9, 1),
+            "hbm_frac": round(byt / (dt / (n * args.iters)) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "row + column pass algorithmic bytes per iteration over the measured time "
+                    "per problem-iteration"}
 
 
 def run_batch(args, dev):
@@ -258,6 +314,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--batch", type=int, default=96, help="problems in the batch run (0: skip)")
+    ap.add_argument("--concurrent", type=int, default=8,
+                    help="copies of the headline problem solved together (0: skip)")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline DCT solve and kernel timings only (for profiler runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the Poisson arrival trace (0: skip serving)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -265,6 +325,9 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.quick:
+        args.no_cpu, args.no_tv, args.batch, args.serve_seconds, args.concurrent = \
+            True, True, 0, 0.0, 0
     if args.gpus != 1:
         print("bench.py measures one GPU: one reconstruction runs on a single device "
               "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
@@ -278,7 +341,8 @@ def main():
     byt = algorithmic_bytes(dom, S, N, N, "dct2d")
     ach = byt / (times[dom] * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom) if (N, S) == (1024, 3) else None,
             "kernel": names[dom], "avg_us": round(times[dom], 3),
             "algorithmic_bytes_per_launch": byt,
             "other_kernel": {"name": names[1 - dom], "avg_us": round(times[1 - dom], 3),
@@ -299,20 +363,21 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    conc = run_concurrent(args, dev, psf_t, y_t) if args.concurrent > 1 else None
     batch = run_batch(args, dev) if args.batch > 0 else None
     serving = None
     if args.serve_seconds > 0:
         print(f"[bench] serving: {args.serve_seconds} s of arrivals at {args.serve_rate} req/s",
               file=sys.stderr, flush=True)
-        conc = run_serving(args, dev, 4)
-        print(f"[bench] serving (4 slots): {conc}", file=sys.stderr, flush=True)
+        srv4 = run_serving(args, dev, 4)
+        print(f"[bench] serving (4 slots): {srv4}", file=sys.stderr, flush=True)
         seq = run_serving(args, dev, 1)
         print(f"[bench] serving (1 slot): {seq}", file=sys.stderr, flush=True)
         serving = {"workload": "TV3D solves, Poisson arrivals, N in "
                                f"{[n for n in (256, 384, 512, 768, 1024, 1536, 2048) if n in cip.SUPPORTED_N]}, "
                                f"K = S in (3, 5, 8), {args.iters} iterations, host buffers",
-                   "continuous_batching": conc, "sequential": seq,
-                   "throughput_speedup": round(conc["Mvoxel_iter_per_s"] /
+                   "continuous_batching": srv4, "sequential": seq,
+                   "throughput_speedup": round(srv4["Mvoxel_iter_per_s"] /
                                                max(seq["Mvoxel_iter_per_s"], 1e-9), 3)}
     cpu = None
     if not args.no_cpu:
@@ -338,6 +403,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "tv2d": tv,
+        "concurrent_1024": conc,
         "batch": batch,
         "serving": serving,
         "latency_p50_ms": serving["continuous_batching"]["p50_ms"] if serving else None,
