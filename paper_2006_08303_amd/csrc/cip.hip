@@ -231,10 +231,14 @@ hipError_t col_op(const cx<Re>* in, void* out, int Pin, int Pout, int N1, int H2
 hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
   const Layout& L = p->L;
   float kappa = (float)(p->lambda / p->rho);
+#ifndef CIP_ROW_DCT_NP
+#define CIP_ROW_DCT_NP 4
+#endif
+  constexpr int NP = CIP_ROW_DCT_NP;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
-    size_t lds = (size_t)(4 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    return launch(k_admm_row_dct<NN>, p->S * (p->N1 / RT), PAIRS * T, lds, st,
+    size_t lds = (size_t)(4 * NN + row_work_floats<NN, float>(NP, true)) * 4;
+    return launch(k_admm_row_dct<NN, NP>, p->S * (p->N1 / RT) * (PAIRS / NP), NP * T, lds, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), p->at<float>(L.state),
                   p->N1, p->at<const cx<float>>(L.twN2f), p->at<const cx<float>>(L.ew2), kappa,
                   mode, xout);

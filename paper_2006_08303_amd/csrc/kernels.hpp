@@ -77,10 +77,11 @@ __device__ __forceinline__ void lds_load_table(cx<Re>* dst, const cx<Re>* __rest
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
-// Floats of LDS used by a row-pass work-group of NG row pairs.
+// Floats of LDS used by a row-pass work-group of NG row pairs (staging holds
+// the work-group's 2 NG rows of the tile).
 template <int N2, typename Re> constexpr int row_work_floats(int ng, bool staged) {
   int fft = ng * 2 * padded_len(N2);
-  int stg = staged ? 2 * pad8_len((N2 / 2 + 1) * RT) : 0;
+  int stg = staged ? 2 * pad8_len((N2 / 2 + 1) * 2 * ng) : 0;
   return fft > stg ? fft : stg;
 }
 
@@ -95,10 +96,25 @@ __device__ __forceinline__ void staging_to_tile(cx<float>* __restrict__ dst, con
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = stg[pad8(i)];
 }
 
+// Part of a tile: rows r0 .. r0 + SW - 1 of each of the H2 columns
+// (staging [k2][SW]); with SW = RT these are the plain tile copies above.
+template <int SW>
+__device__ __forceinline__ void subtile_to_staging(const cx<float>* __restrict__ tile, cx<float>* stg,
+                                                   int h2, int r0) {
+  for (int i = threadIdx.x; i < h2 * SW; i += blockDim.x)
+    stg[pad8(i)] = tile[(i / SW) * RT + r0 + i % SW];
+}
+template <int SW>
+__device__ __forceinline__ void staging_to_subtile(cx<float>* __restrict__ tile, const cx<float>* stg,
+                                                   int h2, int r0) {
+  for (int i = threadIdx.x; i < h2 * SW; i += blockDim.x)
+    tile[(i / SW) * RT + r0 + i % SW] = stg[pad8(i)];
+}
+
 // From the staged half spectra of rows a = 2g, b = 2g + 1 of the tile, build
 // the full spectrum Z[k] = A[k] + i B[k] (Hermitian extension of A and B), in
 // the group register order (slot q holds k = t + T q).
-template <int N2, int PPT>
+template <int N2, int PPT, int SW = RT>
 __device__ __forceinline__ void staging_to_pair(cx<float>* v, const cx<float>* stg, int g,
                                                 int t) {
   constexpr int T = N2 / PPT;
@@ -107,7 +123,7 @@ __device__ __forceinline__ void staging_to_pair(cx<float>* v, const cx<float>* s
     int k = t + T * q;
     int kk = k <= N2 / 2 ? k : N2 - k;
     float sg = k <= N2 / 2 ? 1.f : -1.f;
-    int i = kk * RT + 2 * g;
+    int i = kk * SW + 2 * g;
     cx<float> A = stg[pad8(i)], B = stg[pad8(i + 1)];
     A.y *= sg;
     B.y *= sg;
@@ -120,7 +136,7 @@ __device__ __forceinline__ void staging_to_pair(cx<float>* v, const cx<float>* s
 // k = 0..N/2, and write them to the staging arrays as rows 2g, 2g + 1. `v`
 // holds Z in group register order on entry. The group scratch cb may
 // alias the staging arrays.
-template <int N2, int PPT>
+template <int N2, int PPT, int SW = RT>
 __device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<float>* stg, int g,
                                                 int t) {
   constexpr int T = N2 / PPT;
@@ -146,7 +162,7 @@ __device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<
   for (int q = 0; q < QH; ++q) {
     int k = t + T * q;
     if (k <= N2 / 2) {
-      int i = k * RT + 2 * g;
+      int i = k * SW + 2 * g;
       stg[pad8(i)] = A[q];
       stg[pad8(i + 1)] = B[q];
     }
@@ -423,14 +439,14 @@ __device__ __forceinline__ float clip_f(float v, float k) { return fminf(fmaxf(v
 
 enum RowMode { ROW_FIRST = 0, ROW_FULL = 1, ROW_FINAL = 2 };
 
-// Row pass of one ADMM iteration (DCT prior), one work-group per (plane, row
-// tile): inverse row FFT of the column-pass output (x^l in the column-DCT /
+// Row pass of one ADMM iteration (DCT prior), one work-group per (plane, NP
+// row pairs of a row tile): inverse row FFT of the column-pass output (x^l in the column-DCT /
 // row-frequency domain) -> row DCT gives w = T x^l -> prox + dual update of v
 // -> inverse row DCT of t - u -> forward row FFT -> RT output for the next
 // column pass. ROW_FINAL stops after the inverse row FFT and writes x.
 // LDS: [twiddles N2][DCT table E N2][work region].
-template <int N2>
-__global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()), 2)
+template <int N2, int NP>
+__global__ void __launch_bounds__(NP * (N2 / ppt_row<N2>()), 2)
 k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
                float* __restrict__ vstate, int N1, const cx<float>* __restrict__ twg,
                const cx<float>* __restrict__ ewg, float kappa, int mode,
@@ -438,6 +454,8 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
+  constexpr int SW = 2 * NP;         // tile rows of this work-group
+  constexpr int PARTS = RT / SW;     // work-groups per tile
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
   cx<float>* ew = tw + N2;
@@ -445,13 +463,14 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = b / tiles, row0 = (b % tiles) * RT;
-  const int ra = row0 + 2 * g;
+  const int s = b / (tiles * PARTS), rem = b % (tiles * PARTS);
+  const int row0 = (rem / PARTS) * RT, r0 = (rem % PARTS) * SW;
+  const int ra = row0 + r0 + 2 * g;
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   lds_load_table(tw, twg, N2);
   if (mode != ROW_FINAL) lds_load_table(ew, ewg, N2);
-  tile_to_staging(Yin + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
+  subtile_to_staging<SW>(Yin + rt_tile_base(s, row0, N1, H2), stg, H2, r0);
   // prefetch the state of rows a, b (latency overlaps the two FFTs below)
   float* va = vstate + ((size_t)s * N1 + ra) * N2;
   float* vb = va + N2;
@@ -468,7 +487,7 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   }
   __syncthreads();
   cx<float> v[PPT];
-  staging_to_pair<N2, PPT>(v, stg, g, t);
+  staging_to_pair<N2, PPT, SW>(v, stg, g, t);
   __syncthreads();   // staging aliases the group scratch
   fft_group<N2, PPT, -1>(v, cb, t, tw);
   if (mode == ROW_FINAL) {
@@ -494,9 +513,9 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   }
   dct_inv_group<N2, PPT>(v, cb, t, tw, ew);
   fft_group<N2, PPT, +1>(v, cb, t, tw);
-  pair_to_staging<N2, PPT>(v, cb, stg, g, t);
+  pair_to_staging<N2, PPT, SW>(v, cb, stg, g, t);
   __syncthreads();
-  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
+  staging_to_subtile<SW>(Gout + rt_tile_base(s, row0, N1, H2), stg, H2, r0);
 }
 
 // Row pass of one ADMM iteration for the anisotropic TV prior on every plane
@@ -842,14 +861,13 @@ __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
 //   X(w) = xh0(w) + A(w) g(w)    (A = rho Psi^+ / (N1 N2), packed Hermitian)
 // -> inverse column FFT -> [column DCT] -> RT output.
 // DCT = true for the DCT prior (T acts on both axes), false for TV priors.
-// For S <= COL_PF_MAX_S the solve tables of this thread's frequencies are
-// loaded at kernel start so that their latency overlaps the first
-// transforms; for more planes that would not fit in registers and they are
-// loaded in the solve itself.
+// The solve tables are read inside the solve, not prefetched at kernel start:
+// a prefetch of the Psi^+ row costs about 2 S PPT registers, which lowers the
+// number of resident waves below what a 1024^2 problem needs (measured:
+// 34.6 us with the prefetch, 28.0 us without, K = S = 3).
 // LDS: [twiddles N1][DCT table E N1, when it fits][S x padded N1 complex];
 // when the E table does not fit (N1 = 2048 with many planes) it is read
 // from global memory.
-constexpr int COL_PF_MAX_S = 4;
 constexpr int LDS_BYTES_MAX = 160 * 1024;
 template <int N1, int S> constexpr bool col_e_in_lds() {
   return (4 * N1 + S * 2 * padded_len(N1)) * 4 <= LDS_BYTES_MAX;
@@ -867,9 +885,6 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   constexpr int PPT = ppt_col<N1>();
   constexpr int T = N1 / PPT;
   constexpr int PL = padded_len(N1);
-  constexpr bool PF = S <= COL_PF_MAX_S;
-  constexpr int SO = PF && S > 1 ? S - 1 : 1;
-  constexpr int PQ = PF ? PPT : 1;
   constexpr bool ELDS = DCT && col_e_in_lds<N1, S>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
@@ -884,13 +899,8 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * PL;
   const size_t F = (size_t)N1 * H2;
   const size_t f0 = (size_t)k2 * N1 + t;
-  // solve tables: x_hat0 of plane g, row g of A
-  cx<float> pxh[PPT], pao[SO][PQ];
-  float pdg[PQ];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) pxh[q] = xh0[(size_t)g * F + f0 + T * q];
-  // without prefetch: offset of A[g][j] (packed upper triangle) and the sign
-  // of its imaginary part (conjugate below the diagonal), per j != g
+  // offset of A[g][j] (packed upper triangle) and the sign of its imaginary
+  // part (conjugate below the diagonal), per j != g
   size_t arow[S > 1 ? S - 1 : 1];
   float asgn[S > 1 ? S - 1 : 1];
 #pragma unroll
@@ -898,22 +908,6 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
     const int j = jj < g ? jj : jj + 1;
     arow[jj] = (size_t)(g < j ? pair_index(g, j, S) : pair_index(j, g, S)) * F;
     asgn[jj] = g < j ? 1.f : -1.f;
-  }
-  if (PF && !zero_in) {
-#pragma unroll
-    for (int q = 0; q < PQ; ++q) pdg[q] = Adiag[(size_t)g * F + f0 + T * q];
-#pragma unroll
-    for (int jj = 0; jj < SO; ++jj) {
-      if (jj >= S - 1) break;
-      const int j = jj < g ? jj : jj + 1;
-      const int e = g < j ? pair_index(g, j, S) : pair_index(j, g, S);
-      const cx<float>* src = Aoff + (size_t)e * F + f0;
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        cx<float> a = src[T * q];
-        pao[jj][q] = g < j ? a : conjx(a);
-      }
-    }
   }
   lds_load_table(tw, twg, N1);
   if (ELDS) lds_load_table(ewl, ewg, N1);
@@ -932,30 +926,26 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int k1 = t + T * q;
+      const cx<float> xh = xh0[(size_t)g * F + f0 + T * q];
+      const float dg = Adiag[(size_t)g * F + f0 + T * q];
       cx<float> gg = ldc(cb, k1);
-      const float dg = PF ? pdg[q % PQ] : Adiag[(size_t)g * F + f0 + T * q];
-      cx<float> acc = {pxh[q].x + dg * gg.x, pxh[q].y + dg * gg.y};
+      cx<float> acc = {xh.x + dg * gg.x, xh.y + dg * gg.y};
 #pragma unroll
       for (int jj = 0; jj < S - 1; ++jj) {
         const int j = jj < g ? jj : jj + 1;
-        cx<float> a;
-        if constexpr (PF) {
-          a = pao[jj % SO][q % PQ];
-        } else {
-          a = Aoff[arow[jj] + f0 + T * q];
-          a.y *= asgn[jj];
-        }
+        cx<float> a = Aoff[arow[jj] + f0 + T * q];
+        a.y *= asgn[jj];
         acc = acc + cmul(a, ldc(reinterpret_cast<const cx<float>*>(lds) + j * PL, k1));
       }
       v[q] = acc;
-      // without prefetch, keep the table loads of one frequency at a time
-      // (otherwise the scheduler hoists all of them and spills)
-      if constexpr (!PF) __builtin_amdgcn_sched_barrier(0);
+      // keep the table loads of one frequency at a time (otherwise the
+      // scheduler hoists all of them and runs out of registers)
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();   // every plane's scratch was read by the solve
   } else {
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) v[q] = pxh[q];
+    for (int q = 0; q < PPT; ++q) v[q] = xh0[(size_t)g * F + f0 + T * q];
   }
   fft_group<N1, PPT, -1>(v, cb, t, tw);
   if constexpr (DCT) {
