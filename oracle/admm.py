@@ -180,7 +180,9 @@ def sherman_morrison(theta, c, rho):
     M-vector v, where a = conj(theta) collects the filter spectra at that
     frequency (so that Theta^H Theta = a a^H):
         v = rho^-1 (c - a (a^H c) / (rho + a^H a)).
-    theta: (M, ...) complex; c: (M, ...) complex."""
+    theta: (M, ...) complex; c: (M, ...) complex; rho: scalar, or an array
+    broadcasting over the frequency axes (a diagonal that varies with the
+    frequency, as with the Tikhonov term)."""
     a = np.conj(theta)
     ahc = np.sum(np.conj(a) * c, axis=0)
     aha = np.sum(np.abs(a) ** 2, axis=0)
@@ -189,9 +191,12 @@ def sherman_morrison(theta, c, rho):
 
 class ConvADMM:
     """Algorithm 2 with a common 2D convolutional dictionary for every band
-    (P = I, c_P = 1). Codes z, t, u have shape (M, S, N1, N2)."""
+    (P = I, c_P = 1). Codes z, t, u have shape (M, S, N1, N2). mu > 0 adds
+    the gradient (Tikhonov) term of Eq. DL_PriorHP_conv; the z-update normal
+    equation then gains mu sum_i R_i^H R_i on its left-hand side (stated
+    below Eq. solz), diagonal in frequency with symbol psi(w)."""
 
-    def __init__(self, psf, filters, lam, rho, beta, tier="auto"):
+    def __init__(self, psf, filters, lam, rho, beta, tier="auto", mu=0.0):
         K, S, N1, N2 = psf.shape
         self.psf = psf
         self.S, self.N1, self.N2 = S, N1, N2
@@ -204,6 +209,8 @@ class ConvADMM:
         else:
             self.solver = xupdate.FreqSolver(psf, beta, 1.0, np.ones((N1, N2)))
         self.theta = self.cd.spectra()                           # (M, N1, N2)
+        self.mu = float(mu)
+        self.psi = priors.tikhonov_symbol(N1, N2)                # (N1, N2)
 
     def synth(self, z):
         if self.tier == "dense":
@@ -220,11 +227,12 @@ class ConvADMM:
 
     def z_update(self, x, t, u):
         """Eq. solz_DFT: c = Theta^H F x + rho F (t - u), then Sherman-Morrison
-        per frequency and per band, then inverse DFT."""
+        per frequency and per band (diagonal rho + mu psi(w)), then inverse
+        DFT."""
         xh = np.fft.fft2(x, axes=(-2, -1))                       # (S, N1, N2)
         gh = np.fft.fft2(t - u, axes=(-2, -1))                   # (M, S, N1, N2)
         c = np.conj(self.theta)[:, None] * xh[None] + self.rho * gh
-        v = sherman_morrison(self.theta[:, None], c, self.rho)
+        v = sherman_morrison(self.theta[:, None], c, self.rho + self.mu * self.psi)
         return np.ascontiguousarray(np.real(np.fft.ifft2(v, axes=(-2, -1))))
 
     def run(self, y, iters, callback=None):

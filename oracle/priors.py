@@ -13,7 +13,9 @@
   patch_based), extracted circularly at a fixed stride.
 * Convolutional dictionary synthesis for 2D correlations: each band is
   sum_m d_m * z_{m,s} with a common set of L x L filters (the 2D-correlation
-  variant of Eq. conv_dic, Section III-B.2).
+  variant of Eq. conv_dic, Section III-B.2), optionally with gradient
+  (Tikhonov) regularisation of the codes (Eq. DL_PriorHP_conv, 2D case:
+  gradients along the first and second image axes).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
@@ -220,3 +222,21 @@ class ConvDict2D:
     def spectra(self) -> np.ndarray:
         """theta_m = 2D DFT of the grid-placed filters, shape (M, N1, N2)."""
         return np.fft.fft2(self.h)
+
+
+def gradient_filters_2d(N1: int, N2: int):
+    """r_1, r_2 of Eq. DL_PriorHP_conv for 2D correlations, as kernels on the
+    N1 x N2 torus: circular forward differences, (r_i * z)[n] = z[n + e_i] - z[n]
+    (tap -1 at offset 0, +1 at offset -e_i)."""
+    r1 = np.zeros((N1, N2))
+    r2 = np.zeros((N1, N2))
+    r1[0, 0] = r2[0, 0] = -1.0
+    r1[-1 % N1, 0] = 1.0
+    r2[0, -1 % N2] = 1.0
+    return r1, r2
+
+
+def tikhonov_symbol(N1: int, N2: int) -> np.ndarray:
+    """Per-frequency symbol of sum_i R_i^H R_i: sum_i |DFT(r_i)|^2."""
+    r1, r2 = gradient_filters_2d(N1, N2)
+    return np.abs(np.fft.fft2(r1)) ** 2 + np.abs(np.fft.fft2(r2)) ** 2

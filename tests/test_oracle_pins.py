@@ -442,3 +442,63 @@ def test_conv_admm_tiers_agree_and_converge():
     assert admm.rel_l2(b[0], a[0]) < 1e-10
     x, z, t, u = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq").run(y, 2000)
     assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
+
+
+def test_tikhonov_symbol_closed_form():
+    """sum_i |DFT(r_i)|^2 of the two circular forward differences is
+    (2 - 2 cos w1) + (2 - 2 cos w2)."""
+    N1, N2 = 6, 10
+    w1 = 2 * np.pi * np.arange(N1)[:, None] / N1
+    w2 = 2 * np.pi * np.arange(N2)[None, :] / N2
+    ref = (2 - 2 * np.cos(w1)) + (2 - 2 * np.cos(w2))
+    assert np.allclose(priors.tikhonov_symbol(N1, N2), ref, atol=1e-13)
+    # the kernels are forward differences: r_1 * z = z[n1 + 1] - z[n1]
+    z = _rng(60).standard_normal((N1, N2))
+    r1, r2 = priors.gradient_filters_2d(N1, N2)
+    assert np.allclose(model.conv_circ(z, r1), np.roll(z, -1, axis=0) - z, atol=1e-12)
+    assert np.allclose(model.conv_circ(z, r2), np.roll(z, -1, axis=1) - z, atol=1e-12)
+
+
+def test_sherman_morrison_frequency_dependent_diagonal():
+    """(c(w) I + a a^H) v = rhs with a diagonal that varies with frequency."""
+    rng = _rng(61)
+    M = 5
+    theta = rng.standard_normal((M, 6)) + 1j * rng.standard_normal((M, 6))
+    rhs = rng.standard_normal((M, 6)) + 1j * rng.standard_normal((M, 6))
+    cdiag = rng.uniform(1e-4, 3.0, 6)
+    v = admm.sherman_morrison(theta, rhs, cdiag)
+    for f in range(6):
+        a = np.conj(theta[:, f])
+        A = cdiag[f] * np.eye(M) + np.outer(a, np.conj(a))
+        assert np.allclose(v[:, f], np.linalg.solve(A, rhs[:, f]), rtol=1e-9, atol=1e-12)
+
+
+def test_conv_tikhonov_z_update_is_subproblem_minimiser():
+    """With the gradient regulariser the z-update minimises
+    1/2 ||D~ z - x||^2 + mu/2 sum_i ||r_i * z||^2 + rho/2 ||z - t + u||^2:
+    the gradient D~^T (D~ z - x) + mu sum_i R_i^T R_i z + rho (z - t + u)
+    vanishes (R_i^T R_i z = 2 z - z[n - e_i] - z[n + e_i], spatial)."""
+    S, N, M = 2, 12, 3
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=13)
+    filt = synth.random_unit_filters(_rng(62), M, 5)
+    mu, rho = 0.3, 0.2
+    alg = admm.ConvADMM(psf, filt, lam=1e-3, rho=rho, beta=5.0, tier="freq", mu=mu)
+    t = _rng(63).standard_normal((M, S, N, N))
+    u = _rng(64).standard_normal((M, S, N, N))
+    z = alg.z_update(x0, t, u)
+    lap = sum(2 * z - np.roll(z, 1, axis=ax) - np.roll(z, -1, axis=ax) for ax in (2, 3))
+    g = alg.cd.analysis(alg.cd.synth(z) - x0) + mu * lap + rho * (z - t + u)
+    assert np.max(np.abs(g)) < 1e-10
+    # and it differs from the unregularised update
+    z0 = admm.ConvADMM(psf, filt, lam=1e-3, rho=rho, beta=5.0, tier="freq").z_update(x0, t, u)
+    assert np.linalg.norm(z - z0) > 1e-2 * np.linalg.norm(z0)
+
+
+def test_conv_tikhonov_admm_converges():
+    """Algorithm 2 with the gradient regulariser reaches z = t."""
+    S, N, M = 2, 8, 3
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=14)
+    y = model.forward(x0, psf) + 0.01 * _rng(65).standard_normal((2, N, N))
+    filt = synth.random_unit_filters(_rng(66), M, 3)
+    x, z, t, u = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", mu=0.1).run(y, 2000)
+    assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
