@@ -89,6 +89,9 @@ typedef struct {
                            cip_plan_create only.                              */
   int n_filters;        /* M: 1 .. 32                                          */
   int filt_l;           /* L: 1 .. min(N1, N2)                                 */
+  double mu;            /* gradient (Tikhonov) weight on the codes, Eq.
+                           DL_PriorHP_conv for 2D correlations (forward
+                           differences along both axes); 0 = none, >= 0     */
 } cip_prior_desc;
 
 typedef struct cip_plan_s* cip_plan_t;

@@ -37,11 +37,11 @@ class _PriorDesc(ctypes.Structure):
                 ("dict", ctypes.c_void_p), ("n_atoms", ctypes.c_int),
                 ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int),
                 ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
-                ("filt_l", ctypes.c_int)]
+                ("filt_l", ctypes.c_int), ("mu", ctypes.c_double)]
 
 
-def _desc(prior, beta, dictionary=None, filters=None):
-    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0)
+def _desc(prior, beta, dictionary=None, filters=None, mu=0.0):
+    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu))
     if dictionary is not None:
         d.dict = ctypes.c_void_p(dictionary.data_ptr())
         d.n_atoms = int(dictionary.shape[1])
@@ -143,10 +143,10 @@ class Plan:
     dictionary: for prior="patch", float32 CUDA tensor [64 S, A] (atoms as
     columns, row s*64 + a*8 + b = pixel (a, b) of plane s).
     filters: for prior="conv2d", float32 CUDA tensor [M, L, L] (tap (a, b) at
-    offset (a - L//2, b - L//2))."""
+    offset (a - L//2, b - L//2)); mu: gradient (Tikhonov) weight on the codes."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
-                 filters=None, stream=None):
+                 filters=None, stream=None, mu=0.0):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
@@ -158,7 +158,7 @@ class Plan:
             if filters is None:
                 raise ValueError("the conv2d prior needs filters")
             _dev_f32(filters, tuple(filters.shape), "filters")
-        desc = _desc(prior, beta, dictionary, filters)
+        desc = _desc(prior, beta, dictionary, filters, mu)
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
                                  desc.n_atoms, desc.n_filters, desc.filt_l)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)

@@ -63,7 +63,7 @@ struct Layout {
   size_t state;                         // ADMM state
   size_t lam64, rt64, pl64;             // plan-time FP64 scratch
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
-  size_t th32, gam, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
+  size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t tables;                        // bytes of the table region
   size_t state_bytes;                   // bytes of the state region
   size_t total;                         // tables + state_bytes
@@ -130,6 +130,7 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     const size_t M = (size_t)prior->n_filters;
     L.th32 = tab(M * F * 8);
     L.gam = tab(F * 4);
+    L.eta = tab(F * 4);
     L.gv = sta(M * S * F * 8);
     L.dhat = sta((size_t)S * F * 8);
     L.xhat = sta((size_t)S * F * 8);
@@ -166,6 +167,7 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       return fail(CIP_EUNSUPPORTED, "conv prior: 1 to 32 filters");
     if (prior->filt_l < 1 || prior->filt_l > N1 || prior->filt_l > N2)
       return fail(CIP_EINVAL, "conv prior: filter size must be in [1, min(N1, N2)]");
+    if (!(prior->mu >= 0.0)) return fail(CIP_EINVAL, "conv prior: mu must be >= 0");
   }
   return CIP_OK;
 }
@@ -339,7 +341,8 @@ hipError_t conv_iter(cip_plan_t p, int l, int last, hipStream_t st) {
   hipError_t e = conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
                            p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
                            p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
-                           p->at<const float>(L.gam), p->n_filters, p->S, F, l == 1, l == 1,
+                           p->at<const float>(L.gam), p->at<const float>(L.eta), p->n_filters, p->S,
+                           F, l == 1, l == 1,
                            last ? 0 : 1, st);
   if (e != hipSuccess || last) return e;
   e = conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1, p->H2,
@@ -603,7 +606,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
                                         st)));
     }
     PLAN_HIP(conv_tables(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
-                         p->at<float>(L.gam), M, (size_t)N1 * p->H2, rho, st));
+                         p->at<float>(L.gam), p->at<float>(L.eta), M, (size_t)N1 * p->H2, rho,
+                         prior->mu, N1, N2, st));
   }
   if (p->kind == CIP_PRIOR_PATCH) {
     // M1 = D^T (rho I + D D^T)^-1 in FP64 on the host; D and M1 stored as BF16
@@ -867,7 +871,8 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
         HIP_TRY(conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
                           p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
                           p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
-                          p->at<const float>(L.gam), p->n_filters, p->S, F, 0, 0, 1, st));
+                          p->at<const float>(L.gam), p->at<const float>(L.eta), p->n_filters, p->S,
+                          F, 0, 0, 1, st));
       continue;
     }
     if (which == 0) HIP_TRY(admm_row(p, 2 + (r & 1), st));

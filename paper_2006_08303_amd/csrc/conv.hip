@@ -11,9 +11,10 @@ hipError_t conv_place_filter(const float* filt, double* dst, int L, int N1, int 
   return launch(k_place_filter, (int)((n + 255) / 256), 256, 0, st, filt, dst, L, N1, N2);
 }
 
-hipError_t conv_tables(const cx<double>* th64, cx<float>* th32, float* gam, int M, size_t F,
-                       double rho, hipStream_t st) {
-  return launch(k_conv_tables, (int)((F + 255) / 256), 256, 0, st, th64, th32, gam, M, F, rho);
+hipError_t conv_tables(const cx<double>* th64, cx<float>* th32, float* gam, float* eta, int M,
+                       size_t F, double rho, double mu, int N1, int N2, hipStream_t st) {
+  return launch(k_conv_tables, (int)((F + 255) / 256), 256, 0, st, th64, th32, gam, eta, M, F, rho,
+                mu, N1, N2);
 }
 
 hipError_t conv_col_fft(int dir, const cx<float>* in, cx<float>* out, int P, int N1, int H2,
@@ -30,10 +31,10 @@ hipError_t conv_col_fft(int dir, const cx<float>* in, cx<float>* out, int P, int
 
 hipError_t conv_freq(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<float>* xh0,
                      const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
-                     const float* gam, int M, int S, size_t F, int first, int zero_g, int do_z,
-                     hipStream_t st) {
+                     const float* gam, const float* eta, int M, int S, size_t F, int first,
+                     int zero_g, int do_z, hipStream_t st) {
   return launch(k_conv_freq, (int)((F + 127) / 128), 128, 0, st, gv, dhat, xhat, xh0, Adiag, Aoff,
-                th, gam, M, S, F, first, zero_g, do_z);
+                th, gam, eta, M, S, F, first, zero_g, do_z);
 }
 
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,

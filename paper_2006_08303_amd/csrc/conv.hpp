@@ -32,9 +32,14 @@ __global__ void k_place_filter(const float* __restrict__ filt, double* __restric
   dst[i] = (a < L && b < L) ? (double)filt[a * L + b] : 0.0;
 }
 
-// theta (FP32) and gamma = 1 / (rho + sum_m |theta_m|^2) (formed in FP64).
+// theta (FP32) and, formed in FP64 at FL frequency f = k2 N1 + k1, with the
+// code-gradient (Tikhonov) weight mu and the symbol of sum_i R_i^H R_i
+// (circular forward differences along both axes),
+//   psi = (2 - 2 cos w1) + (2 - 2 cos w2),  c = rho + mu psi,
+//   gamma = 1 / (c + sum_m |theta_m|^2),     eta = rho / c.
 __global__ void k_conv_tables(const cx<double>* __restrict__ th64, cx<float>* __restrict__ th32,
-                              float* __restrict__ gam, int M, size_t F, double rho) {
+                              float* __restrict__ gam, float* __restrict__ eta, int M, size_t F,
+                              double rho, double mu, int N1, int N2) {
   const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   double s = 0.0;
@@ -43,7 +48,15 @@ __global__ void k_conv_tables(const cx<double>* __restrict__ th64, cx<float>* __
     s += t.x * t.x + t.y * t.y;
     th32[(size_t)m * F + f] = cx<float>{(float)t.x, (float)t.y};
   }
-  gam[f] = (float)(1.0 / (rho + s));
+  double c = rho;
+  if (mu > 0.0) {
+    const int k2 = (int)(f / N1), k1 = (int)(f % N1);
+    const double w1 = 2.0 * kPi * (double)k1 / (double)N1;
+    const double w2 = 2.0 * kPi * (double)k2 / (double)N2;
+    c += mu * ((2.0 - 2.0 * cos(w1)) + (2.0 - 2.0 * cos(w2)));
+  }
+  gam[f] = (float)(1.0 / (c + s));
+  eta[f] = (float)(rho / c);
 }
 
 constexpr int CONV_PC = 4;   // planes per work-group in the batched column FFT
@@ -88,14 +101,18 @@ __global__ void k_col_fft_batch(const cx<float>* __restrict__ in, cx<float>* __r
 // Frequency pass, one thread per frequency f (FL order):
 //   x^ = xh0 + A d^ (S x S, packed Hermitian A = Psi^+), stored to xhat;
 //   if do_z: per plane s the stable Sherman-Morrison update of the M codes
-//   (v overwrites g^ in gv) and the new d^_s = sum_m theta_m v_m.
+//   (v overwrites g^ in gv) and the new d^_s = sum_m theta_m v_m. With the
+//   Tikhonov term the diagonal is c = rho + mu psi(w) instead of rho, and
+//   v = eta g^ + a (x^_s - a^H eta g^) gamma with eta = rho / c (eta = 1
+//   without it).
 // first: d^ = 0 (z = 0); zero_g: g^ = 0 (t = u = 0).
 constexpr int CONV_MMAX = 32;   // filters per dictionary (at most)
 
 __global__ void k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat,
                             cx<float>* __restrict__ xhat, const cx<float>* __restrict__ xh0,
                             const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
-                            const cx<float>* __restrict__ th, const float* __restrict__ gam, int M,
+                            const cx<float>* __restrict__ th, const float* __restrict__ gam,
+                            const float* __restrict__ eta, int M,
                             int S, size_t F, int first, int zero_g, int do_z) {
   const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
@@ -120,14 +137,19 @@ __global__ void k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ 
 #pragma unroll
   for (int m = 0; m < CONV_MMAX; ++m)
     if (m < M) t[m] = th[(size_t)m * F + f];
-  const float gm = gam[f];
+  const float gm = gam[f], et = eta[f];
   for (int s = 0; s < S; ++s) {
     cx<float> g[CONV_MMAX];
     cx<float> ag = {0.f, 0.f};   // a^H g = sum_m theta_m g_m
 #pragma unroll
     for (int m = 0; m < CONV_MMAX; ++m) {
       if (m >= M) break;
-      g[m] = zero_g ? cx<float>{0.f, 0.f} : gv[((size_t)m * S + s) * F + f];
+      if (zero_g) {
+        g[m] = cx<float>{0.f, 0.f};
+      } else {
+        const cx<float> gg = gv[((size_t)m * S + s) * F + f];
+        g[m] = cx<float>{et * gg.x, et * gg.y};
+      }
       ag = ag + cmul(t[m], g[m]);
     }
     const cx<float> r = {(xs[s].x - ag.x) * gm, (xs[s].y - ag.y) * gm};

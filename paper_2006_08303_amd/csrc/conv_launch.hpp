@@ -8,14 +8,14 @@
 namespace cip {
 
 hipError_t conv_place_filter(const float* filt, double* dst, int L, int N1, int N2, hipStream_t st);
-hipError_t conv_tables(const cx<double>* th64, cx<float>* th32, float* gam, int M, size_t F,
-                       double rho, hipStream_t st);
+hipError_t conv_tables(const cx<double>* th64, cx<float>* th32, float* gam, float* eta, int M,
+                       size_t F, double rho, double mu, int N1, int N2, hipStream_t st);
 hipError_t conv_col_fft(int dir, const cx<float>* in, cx<float>* out, int P, int N1, int H2,
                         const cx<float>* tw, hipStream_t st);
 hipError_t conv_freq(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<float>* xh0,
                      const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
-                     const float* gam, int M, int S, size_t F, int first, int zero_g, int do_z,
-                     hipStream_t st);
+                     const float* gam, const float* eta, int M, int S, size_t F, int first,
+                     int zero_g, int do_z, hipStream_t st);
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
                     const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st);
 

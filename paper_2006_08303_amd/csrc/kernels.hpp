@@ -532,13 +532,14 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
 // the halo row of vin. Layout of each buffer: [component][S][N1][N2],
 // component 0 = vertical (n1) difference, 1 = horizontal (n2) difference
 // (2 = band difference for TV3D).
-// LDS: [twiddles N2][work: max(5 group scratches, staging 10 x H2, q arrays)].
+// LDS: [twiddles N2][work: max(5 group scratches, staging 10 x H2, q arrays)],
+// 76 KB at N2 = 1024 (two work-groups per CU).
 template <int N2> constexpr int tv_work_floats() {
   constexpr int H2 = N2 / 2 + 1;
   constexpr int fft = (PAIRS + 1) * 2 * padded_len(N2);
   constexpr int stg = 2 * pad8_len(H2 * (RT + 2));
   constexpr int xr = (RT + 2) * N2;
-  constexpr int qq = 2 * (RT + 1) * N2;   // QV and QH, RT + 1 rows each
+  constexpr int qq = (2 * RT + 1) * N2;   // QV (RT + 1 rows) and QH (RT rows)
   constexpr int a = fft > stg ? fft : stg;
   constexpr int b = xr > qq ? xr : qq;
   return a > b ? a : b;
@@ -677,8 +678,12 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
     }
   }
   __syncthreads();
-  float* QV = lds;                    // [RT + 1][N2], row 0 = halo
-  float* QH = lds + (RT + 1) * N2;    // [RT + 1][N2], row 0 unused
+  // QV [RT + 1][N2] (row 0 = halo); QH holds local rows 1 .. RT, stored
+  // right after QV (QH[e] for e >= N2 lands in [(RT + 1) N2, (2 RT + 1) N2)),
+  // so that the work region stays below half of the CU's LDS and two
+  // work-groups fit on a CU
+  float* QV = lds;
+  float* QH = lds + RT * N2;
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
     const unsigned e = threadIdx.x + it * G::NT;

@@ -55,3 +55,21 @@ def test_conv_full_size_1024():
     err = admm.rel_l2(got, ref)
     print(f"1024^2 conv 3 iters: rel_l2 = {err:.3e}", flush=True)
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("N,K,S,M,L,iters,mu", [(64, 3, 3, 8, 5, 12, 0.01), (128, 3, 3, 32, 11, 6, 0.01),
+                                                (384, 2, 2, 8, 7, 4, 0.1), (64, 2, 1, 4, 3, 1, 0.05)])
+def test_conv_tikhonov_matches_oracle(N, K, S, M, L, iters, mu):
+    """Convolutional dictionary with gradient (Tikhonov) regularisation of the
+    codes (mu = 0.01 is the paper's 2D setting)."""
+    print(f"conv+tikhonov N={N} K={K} S={S} M={M} L={L} iters={iters} mu={mu}", flush=True)
+    x, psf, y, filt = _conv_problem(N, K, S, M, L)
+    lam, rho, beta = 1.875e-6, 1e-4, 8.0
+    ref = admm.ConvADMM(psf, filt, lam, rho, beta, tier="freq", mu=mu).run(y, iters)[0]
+    plan = cip.Plan(_t(psf), "conv2d", rho, lam, beta, filters=_t(filt), mu=mu)
+    got = _np(plan.solve(_t(y), iters))
+    err = admm.rel_l2(got, ref)
+    plain = admm.ConvADMM(psf, filt, lam, rho, beta, tier="freq").run(y, iters)[0]
+    print(f"  rel_l2 = {err:.3e} (vs unregularised oracle {admm.rel_l2(got, plain):.3e})",
+          flush=True)
+    assert err < 1e-4
