@@ -50,18 +50,25 @@ class AnalysisADMM:
     def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto"):
         K, S, N1, N2 = psf.shape
         self.psf = psf
+        self.kind = kind
         self.K, self.S, self.N1, self.N2 = K, S, N1, N2
-        self.lam, self.rho, self.beta = float(lam), float(rho), float(beta)
+        self.lam, self.beta = float(lam), float(beta)
         self.T = priors.make_transform(kind, S, N1, N2)
         self.tier = _tier(S, N1, N2, tier)
+        self.set_rho(rho)
+
+    def set_rho(self, rho):
+        """(Re)build the x-update for penalty rho (Psi depends on rho)."""
+        self.rho = float(rho)
+        S, N1, N2 = self.S, self.N1, self.N2
         if self.tier == "dense":
-            reg = rho * xupdate.dense_TtT(self.T, S, N1, N2)
+            reg = self.rho * xupdate.dense_TtT(self.T, S, N1, N2)
             self.solver = xupdate.DenseSolver(
-                psf, beta, reg, annihilates_constants=(kind == "tv2d"))
+                self.psf, self.beta, reg, annihilates_constants=(self.kind == "tv2d"))
         else:
-            band_lap = self.T.band_laplacian() if kind == "tv3d" else None
+            band_lap = self.T.band_laplacian() if self.kind == "tv3d" else None
             self.solver = xupdate.FreqSolver(
-                psf, beta, rho, self.T.gram_symbol(N1, N2), band_lap)
+                self.psf, self.beta, self.rho, self.T.gram_symbol(N1, N2), band_lap)
 
     def x_update(self, data, t, u):
         extra = self.rho * self.T.Tt(t - u)
@@ -89,6 +96,56 @@ class AnalysisADMM:
             if callback is not None:
                 callback(it, x, t, u)
         return x, t, u
+
+    def run_adaptive(self, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-4):
+        """Algorithm 1 with the penalty update and stopping rule of Section
+        IV-C (Eq. paramS). At every `every`-th iteration l, after the t- and
+        u-updates:
+          r = ||T x^l - t^l||,  s = rho ||t^l - t^{l-1}||;
+          stop (returning x^l) if ||x^l - x^{l-1}|| / ||x^{l-1}|| < tol;
+          rho <- tau rho if r > mu s, rho / tau if s > mu r;
+          on a change the scaled dual is rescaled, u <- u rho_old / rho_new,
+          and the x-update is rebuilt for the new rho.
+        Returns (x, info) with info = dict(iters, rho, rhos, rel_change, r, s)."""
+        rho0 = self.rho
+        data = self.solver.data_term(y)
+        t = np.zeros(self.T.shape)
+        u = np.zeros(self.T.shape)
+        x_prev = None
+        rhos = [self.rho]
+        info = {"rel_change": None, "r": None, "s": None}
+        it = 0
+        x = None
+        for it in range(1, max_iters + 1):
+            x = self.x_update(data, t, u)
+            w = self.T.T(x)
+            kappa = self.lam / self.rho
+            t_new = priors.soft(w + u, kappa)
+            u_new = u + w - t_new
+            if it % every == 0:
+                r = float(np.linalg.norm(w - t_new))
+                s_ = self.rho * float(np.linalg.norm(t_new - t))
+                info["r"], info["s"] = r, s_
+                if x_prev is not None:
+                    rel = float(np.linalg.norm(x - x_prev) / np.linalg.norm(x_prev))
+                    info["rel_change"] = rel
+                    if rel < tol:
+                        break
+                new = self.rho
+                if r > mu * s_:
+                    new = tau * self.rho
+                elif s_ > mu * r:
+                    new = self.rho / tau
+                if new != self.rho:
+                    u_new = u_new * (self.rho / new)
+                    self.set_rho(new)
+                    data = self.solver.data_term(y)
+                rhos.append(self.rho)
+            t, u = t_new, u_new
+            x_prev = x
+        info.update(iters=it, rho=self.rho, rhos=rhos)
+        self.set_rho(rho0)
+        return x, info
 
     def kkt(self, y, x, t, u):
         """Relative KKT residuals of the split problem at (x, t, u):

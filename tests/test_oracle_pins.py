@@ -502,3 +502,63 @@ def test_conv_tikhonov_admm_converges():
     filt = synth.random_unit_filters(_rng(66), M, 3)
     x, z, t, u = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", mu=0.1).run(y, 2000)
     assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
+
+
+# ---------------------------------------------------------------- adaptive rho (Eq. paramS)
+def test_adaptive_without_changes_equals_run():
+    """With the balance factor so large that rho never changes and no
+    stopping, the adaptive run is Algorithm 1 with fixed rho."""
+    x0, psf = _small_problem(K=2, S=2, N1=8, N2=8, seed=40)
+    y = model.forward(x0, psf) + 0.01 * _rng(70).standard_normal((2, 8, 8))
+    for kind in ("dct2d", "tv2d", "tv3d"):
+        alg = admm.AnalysisADMM(psf, kind, 1e-2, 0.1, 1.0, tier="freq")
+        xa, info = alg.run_adaptive(y, 30, mu=1e30, every=1, tol=0.0)
+        xr = admm.AnalysisADMM(psf, kind, 1e-2, 0.1, 1.0, tier="freq").run(y, 30)[0]
+        assert info["iters"] == 30 and info["rhos"] == [0.1] * 31
+        assert np.array_equal(xa, xr)
+
+
+def test_adaptive_rescaling_keeps_the_fixed_point():
+    """At a fixed point of Algorithm 1 with penalty rho, switching to rho' with
+    u rescaled by rho / rho' leaves the iterate where it is (the scaled dual
+    of rho' is u rho / rho'); the opposite rescaling moves it."""
+    x0, psf = _small_problem(K=2, S=2, N1=8, N2=8, seed=41)
+    y = model.forward(x0, psf) + 0.01 * _rng(71).standard_normal((2, 8, 8))
+    lam, rho = 1e-2, 0.5
+    x, t, u = admm.AnalysisADMM(psf, "dct2d", lam, rho, 1.0, tier="freq").run(y, 3000)
+    rho2 = 2.0 * rho
+    nxt = admm.AnalysisADMM(psf, "dct2d", lam, rho2, 1.0, tier="freq")
+    x_ok = nxt.run(y, 1, state=(t, u * rho / rho2))[0]
+    x_bad = nxt.run(y, 1, state=(t, u * rho2 / rho))[0]
+    assert np.linalg.norm(x_ok - x) < 1e-9 * np.linalg.norm(x)
+    assert np.linalg.norm(x_bad - x) > 1e-4 * np.linalg.norm(x)
+
+
+def test_adaptive_reaches_the_minimiser_and_moves_rho():
+    """From a poor starting penalty the adaptive run changes rho and stops
+    at the DCT-l1 minimiser (unique), the same point fixed-rho ADMM reaches."""
+    x0, psf = _small_problem(K=2, S=2, N1=8, N2=8, seed=42)
+    y = model.forward(x0, psf) + 0.01 * _rng(72).standard_normal((2, 8, 8))
+    lam = 1e-2
+    ref = admm.AnalysisADMM(psf, "dct2d", lam, 0.1, 1.0, tier="freq").run(y, 20000)[0]
+    for rho0, first in ((1e-5, "up"), (1e3, "down")):
+        alg = admm.AnalysisADMM(psf, "dct2d", lam, rho0, 1.0, tier="freq")
+        x, info = alg.run_adaptive(y, 20000, every=1, tol=1e-11)
+        assert info["iters"] < 20000
+        changes = [b / a for a, b in zip(info["rhos"], info["rhos"][1:]) if b != a]
+        assert changes and changes[0] == (2.0 if first == "up" else 0.5)
+        assert np.linalg.norm(x - ref) < 1e-6 * np.linalg.norm(ref)
+        assert alg.rho == rho0          # the object is left with its own rho
+
+
+def test_adaptive_stops_at_first_check_below_tolerance():
+    x0, psf = _small_problem(K=2, S=2, N1=8, N2=8, seed=43)
+    y = model.forward(x0, psf) + 0.01 * _rng(73).standard_normal((2, 8, 8))
+    alg = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq")
+    x, info = alg.run_adaptive(y, 5000, every=5, tol=1e-3)
+    assert info["iters"] % 5 == 0 and info["iters"] < 5000
+    assert info["rel_change"] < 1e-3
+    # one check earlier the change was still above the tolerance
+    x2, info2 = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq").run_adaptive(
+        y, info["iters"] - 5, every=5, tol=0.0)
+    assert info2["rel_change"] >= 1e-3
