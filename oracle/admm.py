@@ -99,8 +99,9 @@ class AnalysisADMM:
 
     def run_adaptive(self, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-4):
         """Algorithm 1 with the penalty update and stopping rule of Section
-        IV-C (Eq. paramS). At every `every`-th iteration l, after the t- and
-        u-updates:
+        IV-C (Eq. paramS). At every `every`-th iteration l < max_iters (the
+        paper does not say when to check; the last iterate is returned
+        either way), after the t- and u-updates:
           r = ||T x^l - t^l||,  s = rho ||t^l - t^{l-1}||;
           stop (returning x^l) if ||x^l - x^{l-1}|| / ||x^{l-1}|| < tol;
           rho <- tau rho if r > mu s, rho / tau if s > mu r;
@@ -122,7 +123,7 @@ class AnalysisADMM:
             kappa = self.lam / self.rho
             t_new = priors.soft(w + u, kappa)
             u_new = u + w - t_new
-            if it % every == 0:
+            if it % every == 0 and it < max_iters:   # the last iterate is returned anyway
                 r = float(np.linalg.norm(w - t_new))
                 s_ = self.rho * float(np.linalg.norm(t_new - t))
                 info["r"], info["s"] = r, s_

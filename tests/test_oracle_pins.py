@@ -514,7 +514,7 @@ def test_adaptive_without_changes_equals_run():
         alg = admm.AnalysisADMM(psf, kind, 1e-2, 0.1, 1.0, tier="freq")
         xa, info = alg.run_adaptive(y, 30, mu=1e30, every=1, tol=0.0)
         xr = admm.AnalysisADMM(psf, kind, 1e-2, 0.1, 1.0, tier="freq").run(y, 30)[0]
-        assert info["iters"] == 30 and info["rhos"] == [0.1] * 31
+        assert info["iters"] == 30 and info["rhos"] == [0.1] * 30   # checks at 1 .. 29
         assert np.array_equal(xa, xr)
 
 
@@ -560,5 +560,5 @@ def test_adaptive_stops_at_first_check_below_tolerance():
     assert info["rel_change"] < 1e-3
     # one check earlier the change was still above the tolerance
     x2, info2 = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq").run_adaptive(
-        y, info["iters"] - 5, every=5, tol=0.0)
+        y, info["iters"] - 4, every=5, tol=0.0)   # its last check is at iters - 5
     assert info2["rel_change"] >= 1e-3
