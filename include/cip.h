@@ -92,7 +92,13 @@ typedef struct {
   double mu;            /* gradient (Tikhonov) weight on the codes, Eq.
                            DL_PriorHP_conv for 2D correlations (forward
                            differences along both axes); 0 = none, >= 0     */
+  /* All priors:                                                             */
+  int flags;            /* CIP_PLAN_ADAPTIVE: keep the FP64 kernel spectra
+                           resident (K*S*N1*(N2/2+1)*16 more bytes) so that
+                           cip_solve_adaptive can change the penalty         */
 } cip_prior_desc;
+
+enum { CIP_PLAN_ADAPTIVE = 1 };
 
 typedef struct cip_plan_s* cip_plan_t;
 
@@ -147,6 +153,37 @@ int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* st
 
 /* Release the host-side plan object (the workspace stays the caller's). */
 int cip_plan_destroy(cip_plan_t plan);
+
+/* ---- adaptive penalty and stopping rule (Section IV-C, Eq. paramS) --------
+ * Algorithm 1 (analysis priors) from t = u = 0 where every `every`-th
+ * iteration l < max_iters, after the t- and u-updates, measures
+ *   r = ||T x^l - t^l||,  s = rho ||t^l - t^(l-1)||,
+ *   c = ||x^l - x^(l-1)|| / ||x^(l-1)||   (from the second iteration on);
+ * stops with x^l when c < tol; otherwise sets rho <- tau rho if r > mu s,
+ * rho <- rho / tau if s > mu r, rescales the scaled dual u by the inverse
+ * factor and recomputes the FP64 per-frequency inverses for the new rho
+ * before the next x-update. The plan must have been created with
+ * CIP_PLAN_ADAPTIVE and must not be an attached plan; its tables are back at
+ * its own rho when the call returns. Synchronous: waits on `stream` at every
+ * check and returns when x is in d_x. The norms are accumulated in FP32 per
+ * work-group and summed in FP64 on the host. */
+typedef struct {
+  int max_iters;   /* iteration cap (>= 1)                                     */
+  int every;       /* check and adapt every this many iterations (>= 1)       */
+  double tau;      /* penalty factor (> 1; the paper uses 2)                  */
+  double mu;       /* residual balance (> 1; the paper uses 10)               */
+  double tol;      /* stopping tolerance on c (>= 0; the paper uses 1e-4)     */
+} cip_adaptive_params;
+typedef struct {
+  int iters;        /* iterations run                                         */
+  int rho_changes;  /* number of penalty changes                              */
+  double rho;       /* penalty of the last iteration                          */
+  double rel_change;/* last measured c (-1 if none)                           */
+  double r_norm;    /* last measured r                                         */
+  double s_norm;    /* last measured s                                         */
+} cip_solve_info;
+int cip_solve_adaptive(cip_plan_t plan, const float* d_y, const cip_adaptive_params* params,
+                       float* d_x, void* stream, cip_solve_info* info);
 
 /* ---- shared tables, separate solve state ---------------------------------
  * A plan's workspace holds read-only tables (Alg. 1/2 step 2: spectra,

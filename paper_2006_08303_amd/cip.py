@@ -37,11 +37,25 @@ class _PriorDesc(ctypes.Structure):
                 ("dict", ctypes.c_void_p), ("n_atoms", ctypes.c_int),
                 ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int),
                 ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
-                ("filt_l", ctypes.c_int), ("mu", ctypes.c_double)]
+                ("filt_l", ctypes.c_int), ("mu", ctypes.c_double), ("flags", ctypes.c_int)]
 
 
-def _desc(prior, beta, dictionary=None, filters=None, mu=0.0):
-    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu))
+class _AdaptiveParams(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int), ("every", ctypes.c_int), ("tau", ctypes.c_double),
+                ("mu", ctypes.c_double), ("tol", ctypes.c_double)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rho_changes", ctypes.c_int), ("rho", ctypes.c_double),
+                ("rel_change", ctypes.c_double), ("r_norm", ctypes.c_double),
+                ("s_norm", ctypes.c_double)]
+
+
+CIP_PLAN_ADAPTIVE = 1
+
+
+def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0):
+    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu), int(flags))
     if dictionary is not None:
         d.dict = ctypes.c_void_p(dictionary.data_ptr())
         d.n_atoms = int(dictionary.shape[1])
@@ -97,12 +111,14 @@ def lib():
         L.cip_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(d)]
         L.cip_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(d), ctypes.POINTER(d)]
         L.cip_server_destroy.argtypes = [vp]
+        L.cip_solve_adaptive.argtypes = [vp, vp, ctypes.POINTER(_AdaptiveParams), vp, vp,
+                                         ctypes.POINTER(_SolveInfo)]
         for name in ("cip_plan_workspace_bytes", "cip_plan_create", "cip_forward", "cip_adjoint",
                      "cip_solve", "cip_plan_destroy", "cip_time_kernel", "cip_batch_create",
                      "cip_batch_launch", "cip_batch_destroy", "cip_plan_state_bytes",
                      "cip_plan_attach", "cip_server_create", "cip_server_add_operator",
                      "cip_server_submit", "cip_server_poll", "cip_server_wait",
-                     "cip_server_destroy"):
+                     "cip_server_destroy", "cip_solve_adaptive"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -126,8 +142,9 @@ def _dev_f32(t, shape, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0, n_filters=0, filt_l=0):
-    desc = _desc(prior, beta)
+def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0, n_filters=0, filt_l=0,
+                    flags=0):
+    desc = _desc(prior, beta, flags=flags)
     desc.n_atoms = int(n_atoms)
     desc.n_filters = int(n_filters)
     desc.filt_l = int(filt_l)
@@ -146,7 +163,7 @@ class Plan:
     offset (a - L//2, b - L//2)); mu: gradient (Tikhonov) weight on the codes."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
-                 filters=None, stream=None, mu=0.0):
+                 filters=None, stream=None, mu=0.0, adaptive=False):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
@@ -158,9 +175,9 @@ class Plan:
             if filters is None:
                 raise ValueError("the conv2d prior needs filters")
             _dev_f32(filters, tuple(filters.shape), "filters")
-        desc = _desc(prior, beta, dictionary, filters, mu)
+        desc = _desc(prior, beta, dictionary, filters, mu, CIP_PLAN_ADAPTIVE if adaptive else 0)
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
-                                 desc.n_atoms, desc.n_filters, desc.filt_l)
+                                 desc.n_atoms, desc.n_filters, desc.filt_l, desc.flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
         h = ctypes.c_void_p()
         _check(lib().cip_plan_create(self.K, self.S, self.N1, self.N2,
@@ -189,6 +206,19 @@ class Plan:
         _check(lib().cip_solve(self._h, _dev_f32(y, (self.K, self.N1, self.N2), "y"), int(iters),
                                _dev_f32(x, (self.S, self.N1, self.N2), "x"), _stream_ptr(stream)))
         return x
+
+    def solve_adaptive(self, y, max_iters, every=1, tau=2.0, mu=10.0, tol=1e-4, out=None,
+                       stream=None):
+        """cip_solve_adaptive; returns (x, info dict)."""
+        x = out if out is not None else torch.empty((self.S, self.N1, self.N2),
+                                                    dtype=torch.float32, device=y.device)
+        prm = _AdaptiveParams(int(max_iters), int(every), float(tau), float(mu), float(tol))
+        info = _SolveInfo()
+        _check(lib().cip_solve_adaptive(self._h, _dev_f32(y, (self.K, self.N1, self.N2), "y"),
+                                        ctypes.byref(prm),
+                                        _dev_f32(x, (self.S, self.N1, self.N2), "x"),
+                                        _stream_ptr(stream), ctypes.byref(info)))
+        return x, {f: getattr(info, f) for f, _ in _SolveInfo._fields_}
 
     def attach(self):
         """A plan sharing this plan's tables with a solve state of its own

@@ -16,6 +16,7 @@
 #include "col_pass.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "norms.hpp"
 #include "patch_launch.hpp"
 #include "conv_launch.hpp"
 #include "errors.hpp"
@@ -61,7 +62,8 @@ struct Layout {
   size_t lam32, Adiag, Aoff, Mm, xh0;   // per-frequency tables (x_hat0 per solve)
   size_t bufA, bufB;                    // RT staging (max(K,S) planes)
   size_t state;                         // ADMM state
-  size_t lam64, rt64, pl64;             // plan-time FP64 scratch
+  size_t lam64, rt64, pl64;             // plan-time FP64 scratch (lam64 resident if adaptive)
+  size_t xbuf, sums;                    // adaptive solves: iterates, norm partial sums
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
   size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t tables;                        // bytes of the table region
@@ -114,7 +116,13 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   L.bufA = sta(P * F * 8);
   L.bufB = sta(P * F * 8);
   L.state = sta((size_t)state_floats_per_voxel(kind) * S * N1 * N2 * 4);
-  L.lam64 = scr((size_t)K * S * F * 16);
+  const bool adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
+  // the FP64 spectra stay resident when the penalty may change during a solve
+  L.lam64 = adaptive ? tab((size_t)K * S * F * 16) : scr((size_t)K * S * F * 16);
+  if (adaptive) {
+    L.xbuf = sta((size_t)2 * S * N1 * N2 * 4);      // x^(l-1), x^l of the checks
+    L.sums = sta((size_t)S * (N1 / 8) * 4 * 4);     // norm-pass partial sums
+  }
   L.rt64 = scr(F * 16);
   L.pl64 = scr((size_t)N1 * N2 * 8);
   if (kind == CIP_PRIOR_PATCH) {
@@ -182,6 +190,7 @@ struct cip_plan_s {
   Layout L;
   bool solved_once;
   bool attached;        // shares another plan's tables
+  bool adaptive;        // FP64 spectra resident: the penalty may change in a solve
   template <typename T> T* at(size_t off) const {
     return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
   }
@@ -230,9 +239,13 @@ hipError_t col_op(const cx<Re>* in, void* out, int Pin, int Pout, int N1, int H2
   return hipSuccess;
 }
 
-hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
+// rho: penalty of the current iteration (the plan's unless the adaptive solve
+// changed it); sc = rho / rho_next when the penalty changes after this pass
+// (the state is then re-expressed for rho_next), else 1.
+hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout, double rho = 0.0,
+                        float sc = 1.f) {
   const Layout& L = p->L;
-  float kappa = (float)(p->lambda / p->rho);
+  float kappa = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
 #ifndef CIP_ROW_DCT_NP
 #define CIP_ROW_DCT_NP 4
 #endif
@@ -243,16 +256,16 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout) {
     return launch(k_admm_row_dct<NN, NP>, p->S * (p->N1 / RT) * (PAIRS / NP), NP * T, lds, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), p->at<float>(L.state),
                   p->N1, p->at<const cx<float>>(L.twN2f), p->at<const cx<float>>(L.ew2), kappa,
-                  mode, xout);
+                  mode, xout, sc);
   });
   return hipSuccess;
 }
 
 // Row pass of the TV priors; pass number l >= 1 of the solve (state buffers
 // alternate so that halo rows of the previous state stay readable).
-hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st) {
+hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
   const Layout& L = p->L;
-  float kappa = (float)(p->lambda / p->rho);
+  float kappa = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
   const bool band = p->kind == CIP_PRIOR_TV3D;
   const size_t buf = (size_t)(band ? 3 : 2) * p->S * p->N1 * p->N2;
   const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
@@ -263,17 +276,57 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st) {
     if (band)
       return launch(k_admm_row_tv3<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
                     p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
-                    p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0);
+                    p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0, sc);
     return launch(k_admm_row_tv<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
-                  p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0);
+                  p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0, sc);
   });
   return hipSuccess;
 }
 
-hipError_t admm_row(cip_plan_t p, int l, hipStream_t st) {
-  if (p->kind == CIP_PRIOR_DCT2D) return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr);
-  return admm_row_tv(p, l, st);
+hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
+  if (p->kind == CIP_PRIOR_DCT2D)
+    return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr, rho, sc);
+  return admm_row_tv(p, l, st, rho, sc);
+}
+
+// Norm pass of a checked iteration l (see norms.hpp): partial sums to
+// L.sums, one float4 per work-group; returns the number of work-groups.
+hipError_t norm_pass(cip_plan_t p, int l, double rho, float* xcur, const float* xprev,
+                     hipStream_t st, int* groups) {
+  const Layout& L = p->L;
+  const float kappa = (float)(p->lambda / rho);
+  const int first = l == 1 ? 1 : 0;
+  const int grid = p->S * (p->N1 / RT);
+  *groups = grid;
+  if (p->kind == CIP_PRIOR_DCT2D) {
+    DISPATCH_N(p->N2, {
+      const int T = NN / ppt_row<NN>();
+      size_t lds = (size_t)(4 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
+      return launch(k_norm_dct<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB),
+                    p->at<const float>(L.state), p->N1, p->at<const cx<float>>(L.twN2f),
+                    p->at<const cx<float>>(L.ew2), kappa, first, xcur, xprev,
+                    p->at<float>(L.sums));
+    });
+    return hipSuccess;
+  }
+  const bool band = p->kind == CIP_PRIOR_TV3D;
+  const size_t buf = (size_t)(band ? 3 : 2) * p->S * p->N1 * p->N2;
+  const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
+  DISPATCH_N(p->N2, {
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(2 * NN + tv_work_floats<NN>()) * 4;
+    if (band)
+      return launch(k_norm_tv<NN, true>, grid, (PAIRS + 1) * T, lds, st,
+                    p->at<const cx<float>>(L.bufB), vin, p->S, p->N1,
+                    p->at<const cx<float>>(L.twN2f), kappa, first, xcur, xprev,
+                    p->at<float>(L.sums));
+    return launch(k_norm_tv<NN, false>, grid, (PAIRS + 1) * T, lds, st,
+                  p->at<const cx<float>>(L.bufB), vin, p->S, p->N1,
+                  p->at<const cx<float>>(L.twN2f), kappa, first, xcur, xprev,
+                  p->at<float>(L.sums));
+  });
+  return hipSuccess;
 }
 
 hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
@@ -369,7 +422,8 @@ hipError_t solve_conv(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
                  (float)(1.0 / ((double)p->N1 * p->N2)), p->at<const cx<float>>(L.twN2f), st);
 }
 
-hipError_t gram(cip_plan_t p, hipStream_t st) {
+hipError_t gram(cip_plan_t p, hipStream_t st, double rho = 0.0) {
+  if (rho <= 0.0) rho = p->rho;
   GramArgs a;
   a.K = p->K;
   a.N1 = p->N1;
@@ -383,8 +437,8 @@ hipError_t gram(cip_plan_t p, hipStream_t st) {
   // patch synthesis: Psi = c_P I + beta L^H L with c_P = (Q / st)^2 = 4, rhs = b + g;
   // conv synthesis: c_P = 1, and the tables are unnormalised (the frequency
   // pass works with unnormalised spectra throughout)
-  a.wgt = patch ? 4.0 : (conv ? 1.0 : p->rho);
-  a.coefA = (patch || conv) ? 1.0 : p->rho;
+  a.wgt = patch ? 4.0 : (conv ? 1.0 : rho);
+  a.coefA = (patch || conv) ? 1.0 : rho;
   if (conv) a.scale = 1.0;
   a.tv_symbol = (p->kind == CIP_PRIOR_TV2D || p->kind == CIP_PRIOR_TV3D) ? 1 : 0;
   a.band_lap = p->kind == CIP_PRIOR_TV3D ? 1 : 0;
@@ -549,6 +603,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->L = L;
   p->solved_once = false;
   p->attached = false;
+  p->adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
 
   auto cleanup_fail = [&](int code, const std::string& m) {
     delete p;
@@ -687,6 +742,104 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
 int cip_plan_destroy(cip_plan_t p) {
   delete p;
   return CIP_OK;
+}
+
+int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params* prm, float* d_x,
+                       void* stream, cip_solve_info* info) {
+  if (!p || !d_y || !d_x || !prm) return fail(CIP_EINVAL, "NULL argument");
+  if (!p->adaptive) return fail(CIP_EINVAL, "plan was not created with CIP_PLAN_ADAPTIVE");
+  if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
+    return fail(CIP_EUNSUPPORTED, "adaptive penalty: analysis priors only");
+  if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
+      !(prm->tol >= 0.0))
+    return fail(CIP_EINVAL, "need max_iters >= 1, every >= 1, tau > 1, mu > 1, tol >= 0");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const Layout& L = p->L;
+  const int iters = prm->max_iters, every = prm->every;
+  const double rho0 = p->rho;
+  double rho = rho0;
+  cip_solve_info out{};
+  out.rel_change = -1.0;
+  std::vector<float> sums;
+  float* xb0 = p->at<float>(L.xbuf);
+  float* xb1 = xb0 + (size_t)p->S * p->N1 * p->N2;
+  auto xbuf = [&](int l) { return (l & 1) ? xb1 : xb0; };
+  auto xhat0 = [&]() -> hipError_t {
+    // Alg. 1 step 2 with the current tables: x_hat0 = Psi^+ beta Lambda^H F y / (N1 N2)
+    hipError_t e = row_r2c<float>(d_y, p->at<cx<float>>(L.bufB), p->K, p->N1, p->N2,
+                                  p->at<const cx<float>>(L.twN2f), st);
+    if (e != hipSuccess) return e;
+    return col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufB), p->at<void>(L.xh0), p->K, p->S,
+                                   p->N1, p->H2, p->at<const cx<float>>(L.twN1f),
+                                   p->at<const cx<float>>(L.Mm), 0, st);
+  };
+  int rc = CIP_OK;
+  auto body = [&]() -> int {
+    HIP_TRY(xhat0());
+    HIP_TRY(admm_col(p, 1, iters > 1 ? 1 : 0, st));   // x^1 (t = u = 0)
+    for (int l = 1;; ++l) {
+      const bool check = l % every == 0 && l < iters;   // the last iterate is returned anyway
+      const bool store = (l + 1) % every == 0 && l < iters;   // keep x^l for the next check
+      double next = rho;
+      bool stop = false;
+      if (check || store) {
+        int groups = 0;
+        HIP_TRY(norm_pass(p, l, rho, store ? xbuf(l) : nullptr,
+                          check && l > 1 ? xbuf(l - 1) : nullptr, st, &groups));
+        if (check) {
+          sums.resize((size_t)groups * 4);
+          HIP_TRY(hipMemcpyAsync(sums.data(), p->at<float>(L.sums), sums.size() * 4,
+                                 hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipStreamSynchronize(st));
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int b = 0; b < groups; ++b)
+            for (int i = 0; i < 4; ++i) acc[i] += (double)sums[(size_t)b * 4 + i];
+          const double r = std::sqrt(acc[0]), sres = rho * std::sqrt(acc[1]);
+          out.r_norm = r;
+          out.s_norm = sres;
+          if (l > 1) {
+            out.rel_change = acc[3] > 0.0 ? std::sqrt(acc[2] / acc[3]) : 0.0;
+            stop = out.rel_change < prm->tol;
+          }
+          if (!stop) {
+            if (r > prm->mu * sres) next = prm->tau * rho;
+            else if (sres > prm->mu * r) next = rho / prm->tau;
+          }
+        }
+      }
+      if (stop || l == iters) {
+        out.iters = l;
+        if (stop && p->kind == CIP_PRIOR_DCT2D && l < iters) {
+          // the column pass of this iteration applied the column DCT for the
+          // next row pass: redo it without (its input, bufA, is intact)
+          HIP_TRY(admm_col(p, 0, 0, st));
+        }
+        HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
+        break;
+      }
+      HIP_TRY(admm_row(p, l, st, rho, (float)(rho / next)));
+      if (next != rho) {
+        HIP_TRY(gram(p, st, next));
+        HIP_TRY(xhat0());
+        rho = next;
+        ++out.rho_changes;
+      }
+      HIP_TRY(admm_col(p, 0, l + 1 < iters ? 1 : 0, st));
+    }
+    return CIP_OK;
+  };
+  rc = body();
+  out.rho = rho;
+  if (rho != rho0) {   // leave the plan's tables at its own penalty
+    hipError_t e = gram(p, st, rho0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess && rc == CIP_OK)
+      rc = fail(CIP_EHIP, std::string("restoring the tables: ") + hipGetErrorString(e));
+  }
+  p->solved_once = true;
+  if (info) *info = out;
+  return rc;
 }
 
 int cip_plan_state_bytes(cip_plan_t p, size_t* bytes) {

@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(NP * (N2 / ppt_row<N2>()), 2)
 k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
                float* __restrict__ vstate, int N1, const cx<float>* __restrict__ twg,
                const cx<float>* __restrict__ ewg, float kappa, int mode,
-               float* __restrict__ xout) {
+               float* __restrict__ xout, float sc) {
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
@@ -502,14 +502,30 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     return;
   }
   dct_fwd_group<N2, PPT, false>(v, cb, t, tw, ew);
+  if (sc == 1.f) {
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    int k = t + T * q;
-    float na = v[q].x + clip_f(oa[q], kappa);
-    float nb = v[q].y + clip_f(ob[q], kappa);
-    va[k] = na;
-    vb[k] = nb;
-    v[q] = cx<float>{2.f * soft_f(na, kappa) - na, 2.f * soft_f(nb, kappa) - nb};
+    for (int q = 0; q < PPT; ++q) {
+      int k = t + T * q;
+      float na = v[q].x + clip_f(oa[q], kappa);
+      float nb = v[q].y + clip_f(ob[q], kappa);
+      va[k] = na;
+      vb[k] = nb;
+      v[q] = cx<float>{2.f * soft_f(na, kappa) - na, 2.f * soft_f(nb, kappa) - nb};
+    }
+  } else {
+    // penalty change after this iteration: u is rescaled by sc = rho / rho'
+    // and the state is re-expressed for rho' (v' = t + sc u)
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      int k = t + T * q;
+      const float na = v[q].x + clip_f(oa[q], kappa);
+      const float nb = v[q].y + clip_f(ob[q], kappa);
+      const float ta = soft_f(na, kappa), tb = soft_f(nb, kappa);
+      const float ua = sc * (na - ta), ub = sc * (nb - tb);
+      va[k] = ta + ua;
+      vb[k] = tb + ub;
+      v[q] = cx<float>{ta - ua, tb - ub};
+    }
   }
   dct_inv_group<N2, PPT>(v, cb, t, tw, ew);
   fft_group<N2, PPT, +1>(v, cb, t, tw);
@@ -650,7 +666,7 @@ template <int N2>
 __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<N2>::PER],
                                            const float (&poh)[TvGeo<N2>::PER],
                                            float* __restrict__ vout, unsigned s, int row0, int N1,
-                                           unsigned cstride, float kappa, int g, int t,
+                                           unsigned cstride, float kappa, float sc, int g, int t,
                                            cx<float> (&v)[TvGeo<N2>::PPT]) {
   using G = TvGeo<N2>;
   constexpr int PPT = G::PPT, T = G::T, PER = G::PER;
@@ -667,13 +683,27 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
       const float wv = X[e + N2] - x0;
       const unsigned o = s * plane + n1 * N2 + n2;
       const float nv = wv + clip_f(pov[it], kappa);
-      qv[it] = 2.f * soft_f(nv, kappa) - nv;
+      float sv = nv;   // state written (re-expressed for rho' when sc != 1)
+      if (sc == 1.f) {
+        qv[it] = 2.f * soft_f(nv, kappa) - nv;
+      } else {
+        const float tv = soft_f(nv, kappa), uv = sc * (nv - tv);
+        qv[it] = tv - uv;
+        sv = tv + uv;
+      }
       if (lr > 0) {
         const float wh = X[lr * N2 + (n2 + 1 == N2 ? 0 : n2 + 1)] - x0;
         const float nh = wh + clip_f(poh[it], kappa);
-        qh[it] = 2.f * soft_f(nh, kappa) - nh;
-        st_off(vout, o, nv);
-        st_off(vout, cstride + o, nh);
+        float sh = nh;
+        if (sc == 1.f) {
+          qh[it] = 2.f * soft_f(nh, kappa) - nh;
+        } else {
+          const float th = soft_f(nh, kappa), uh = sc * (nh - th);
+          qh[it] = th - uh;
+          sh = th + uh;
+        }
+        st_off(vout, o, sv);
+        st_off(vout, cstride + o, sh);
       }
     }
   }
@@ -757,7 +787,7 @@ template <int N2>
 __global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
 k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
               const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
-              const cx<float>* __restrict__ twg, float kappa, int first) {
+              const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
   using G = TvGeo<N2>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
@@ -775,7 +805,7 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   tv_prefetch<N2>(vin, pov, poh, s, row0, N1, cstride, first);
   tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
   cx<float> v[G::PPT];
-  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, g, t, v);
+  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
   tv_forward_rows<N2>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
 }
 
@@ -792,7 +822,7 @@ template <int N2>
 __global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
 k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
                const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
-               const cx<float>* __restrict__ twg, float kappa, int first) {
+               const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
   using G = TvGeo<N2>;
   constexpr int PPT = G::PPT, T = G::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -824,7 +854,7 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     xb[q] = active ? Xb[T * q] : 0.f;
   }
   cx<float> v[PPT];
-  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, g, t, v);
+  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
   // band terms: first + q_b[s-1] (from plane s-1), then - q_b[s] (plane s+1)
   for (int d = 0; d < 2; ++d) {
     const int sn = d == 0 ? s - 1 : s + 1;   // neighbouring plane
@@ -841,13 +871,23 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
         const float wb = d == 0 ? xb[q] - Xb[T * q] : Xb[T * q] - xb[q];
         const float na = wa + clip_f(pa, kappa);
         const float nb = wb + clip_f(pb, kappa);
-        const float qa = 2.f * soft_f(na, kappa) - na;
-        const float qb = 2.f * soft_f(nb, kappa) - nb;
+        float qa, qb, sa = na, sb = nb;
+        if (sc == 1.f) {
+          qa = 2.f * soft_f(na, kappa) - na;
+          qb = 2.f * soft_f(nb, kappa) - nb;
+        } else {
+          const float ta = soft_f(na, kappa), ua = sc * (na - ta);
+          const float tb = soft_f(nb, kappa), ub = sc * (nb - tb);
+          qa = ta - ua;
+          qb = tb - ub;
+          sa = ta + ua;
+          sb = tb + ub;
+        }
         if (d == 0) {
           v[q] = cx<float>{v[q].x + qa, v[q].y + qb};
         } else {
-          st_off(vout, bo + T * q, na);
-          st_off(vout, bo + N2 + T * q, nb);
+          st_off(vout, bo + T * q, sa);
+          st_off(vout, bo + N2 + T * q, sb);
           v[q] = cx<float>{v[q].x - qa, v[q].y - qb};
         }
       }

@@ -1,0 +1,93 @@
+"""GPU tests of the adaptive penalty and stopping rule (Section IV-C,
+Eq. paramS; cip_solve_adaptive) against the FP64 oracle's run_adaptive: the
+same number of iterations, the same final penalty and number of changes, and
+x within the FP32 tolerance (1e-4 relative l2)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm, model
+from paper_2006_08303_amd import cip, synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().double().numpy()
+
+
+def _problem(N, K, S, cfg):
+    x, psf, noise = synth.problem("smooth_disk", N, K, S, seed_config=cfg)
+    hx = model.forward(x, psf)
+    y = (hx + model.snr_noise_scale(hx, 30.0)[:, None, None] * noise)
+    return x, psf, y.astype(np.float32).astype(np.float64)
+
+
+# rho0 far from balanced so that the rule acts; lambda as in the fixed-rho tests
+@pytest.mark.parametrize("prior,N,K,S,lam,rho0,every,tol,maxit", [
+    ("dct2d", 64, 3, 3, 1e-2, 1e-3, 1, 1e-4, 300),      # 9 changes, runs to the cap
+    ("dct2d", 256, 3, 3, 1e-2, 10.0, 5, 1e-3, 200),     # 4 changes, stops at 35
+    ("tv2d", 128, 2, 3, 1e-3, 0.1, 2, 1e-4, 200),       # 1 change, stops at 60
+    ("tv2d", 128, 2, 3, 1e-3, 10.0, 2, 1e-4, 200),      # 4 changes, runs to the cap
+    ("tv3d", 128, 3, 3, 1e-3, 1e-5, 5, 1e-4, 200),      # 13 changes, stops at 70
+    ("tv3d", 384, 3, 3, 1e-3, 3.0, 5, 1e-4, 100),
+])
+def test_adaptive_matches_oracle(prior, N, K, S, lam, rho0, every, tol, maxit):
+    print(f"adaptive {prior} N={N} K={K} S={S} rho0={rho0} every={every} tol={tol}", flush=True)
+    x, psf, y = _problem(N, K, S, 9)
+    ref, rinfo = admm.AnalysisADMM(psf, prior, lam, rho0, 1.0, tier="freq").run_adaptive(
+        y, maxit, every=every, tol=tol)
+    plan = cip.Plan(_t(psf), prior, rho0, lam, 1.0, adaptive=True)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=every, tol=tol)
+    got = _np(got)
+    changes = sum(1 for a, b in zip(rinfo["rhos"], rinfo["rhos"][1:]) if a != b)
+    err = admm.rel_l2(got, ref)
+    print(f"  oracle: iters {rinfo['iters']} rho {rinfo['rho']:.3g} changes {changes}; "
+          f"gpu: iters {ginfo['iters']} rho {ginfo['rho']:.3g} changes {ginfo['rho_changes']}; "
+          f"rel_l2 {err:.3e}", flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == changes
+    assert err < 1e-4
+
+
+def test_adaptive_without_changes_equals_plain_solve():
+    """No penalty change and no stop: the same kernels as cip_solve, bit for
+    bit (the norm passes only read the solver state)."""
+    x, psf, y = _problem(128, 3, 3, 9)
+    for prior in ("dct2d", "tv2d", "tv3d"):
+        plan = cip.Plan(_t(psf), prior, 0.05, 1e-3, 1.0, adaptive=True)
+        a, info = plan.solve_adaptive(_t(y), 25, every=1, mu=1e30, tol=0.0)
+        b = plan.solve(_t(y), 25)
+        torch.cuda.synchronize()
+        assert info["rho_changes"] == 0 and info["iters"] == 25
+        assert torch.equal(a, b), prior
+
+
+def test_adaptive_leaves_tables_at_plan_rho():
+    x, psf, y = _problem(128, 3, 3, 9)
+    plan = cip.Plan(_t(psf), "dct2d", 1e-3, 1e-2, 1.0, adaptive=True)
+    before = plan.solve(_t(y), 10).clone()
+    _, info = plan.solve_adaptive(_t(y), 100, every=1, tol=1e-4)
+    assert info["rho_changes"] > 0
+    after = plan.solve(_t(y), 10)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+
+
+def test_adaptive_argument_errors():
+    x, psf, y = _problem(64, 2, 2, 9)
+    plain = cip.Plan(_t(psf), "dct2d", 0.1, 1e-2, 1.0)
+    with pytest.raises(cip.CipError):
+        plain.solve_adaptive(_t(y), 10)
+    ad = cip.Plan(_t(psf), "tv2d", 0.1, 1e-2, 1.0, adaptive=True)
+    with pytest.raises(cip.CipError):
+        ad.solve_adaptive(_t(y), 10, tau=1.0)
+    with pytest.raises(cip.CipError):
+        ad.attach().solve_adaptive(_t(y), 10)
