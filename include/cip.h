@@ -259,6 +259,27 @@ int cip_server_wait(cip_server_t server, uint64_t ticket, double* latency_s, dou
 /* Finish every queued request, stop the workers, release the arena. */
 int cip_server_destroy(cip_server_t server);
 
+/* ---- autotuning -------------------------------------------------------
+ * Times the available shapes of the analysis row pass on this plan's own
+ * data and keeps the fastest for all later solves of the plan: the number of
+ * row pairs per work-group (4 or 2; DCT prior) and the points per thread of
+ * the row transforms (the default radix sequence, or 8 points per thread,
+ * i.e. radices 8, 8, ..., for power-of-two N2), `reps` launches each with HIP
+ * events on `stream`. The plan must have run cip_solve once; the solve state
+ * is left undefined (the next solve starts from scratch anyway). Analysis
+ * priors only (CIP_EUNSUPPORTED otherwise). Blocks until done. */
+typedef struct {
+  int row_np;         /* row pairs per work-group chosen                       */
+  int row_ppt;        /* points per thread chosen                              */
+  int candidates;     /* shapes timed                                          */
+  double row_us;      /* average time of the chosen shape                      */
+  double default_us;  /* average time of the default shape                     */
+} cip_tuning;
+int cip_plan_autotune(cip_plan_t plan, int reps, void* stream, cip_tuning* out);
+/* Set the row-pass shape directly (values as chosen by cip_plan_autotune:
+ * row_np 4, or 2 for the DCT prior; row_ppt the default or 8). */
+int cip_plan_set_tuning(cip_plan_t plan, int row_np, int row_ppt);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* cip_last_error(void);
 

@@ -54,6 +54,11 @@ class _SolveInfo(ctypes.Structure):
 CIP_PLAN_ADAPTIVE = 1
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("row_np", ctypes.c_int), ("row_ppt", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("row_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+
+
 def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0):
     d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu), int(flags))
     if dictionary is not None:
@@ -113,12 +118,15 @@ def lib():
         L.cip_server_destroy.argtypes = [vp]
         L.cip_solve_adaptive.argtypes = [vp, vp, ctypes.POINTER(_AdaptiveParams), vp, vp,
                                          ctypes.POINTER(_SolveInfo)]
+        L.cip_plan_autotune.argtypes = [vp, i, vp, ctypes.POINTER(_Tuning)]
+        L.cip_plan_set_tuning.argtypes = [vp, i, i]
         for name in ("cip_plan_workspace_bytes", "cip_plan_create", "cip_forward", "cip_adjoint",
                      "cip_solve", "cip_plan_destroy", "cip_time_kernel", "cip_batch_create",
                      "cip_batch_launch", "cip_batch_destroy", "cip_plan_state_bytes",
                      "cip_plan_attach", "cip_server_create", "cip_server_add_operator",
                      "cip_server_submit", "cip_server_poll", "cip_server_wait",
-                     "cip_server_destroy", "cip_solve_adaptive"):
+                     "cip_server_destroy", "cip_solve_adaptive", "cip_plan_autotune",
+                     "cip_plan_set_tuning"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -219,6 +227,15 @@ class Plan:
                                         _dev_f32(x, (self.S, self.N1, self.N2), "x"),
                                         _stream_ptr(stream), ctypes.byref(info)))
         return x, {f: getattr(info, f) for f, _ in _SolveInfo._fields_}
+
+    def autotune(self, reps=20, stream=None):
+        """cip_plan_autotune: returns the chosen row-pass shape and timings."""
+        tu = _Tuning()
+        _check(lib().cip_plan_autotune(self._h, int(reps), _stream_ptr(stream), ctypes.byref(tu)))
+        return {f: getattr(tu, f) for f, _ in _Tuning._fields_}
+
+    def set_tuning(self, row_np, row_ppt):
+        _check(lib().cip_plan_set_tuning(self._h, int(row_np), int(row_ppt)))
 
     def attach(self):
         """A plan sharing this plan's tables with a solve state of its own

@@ -58,6 +58,7 @@ constexpr size_t STATE_BIT = size_t(1) << 62;
 
 struct Layout {
   size_t twN1f, twN2f, twN1d, twN2d;  // FFT twiddles
+  size_t twN2f8;                        // row twiddles, 8 points per thread (tuning variant)
   size_t ew1, ew2;                      // DCT tables exp(-i pi k / 2N) (N1 and N2)
   size_t lam32, Adiag, Aoff, Mm, xh0;   // per-frequency tables (x_hat0 per solve)
   size_t bufA, bufB;                    // RT staging (max(K,S) planes)
@@ -104,6 +105,7 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   };
   L.twN1f = tab(N1 * 8);
   L.twN2f = tab(N2 * 8);
+  L.twN2f8 = is_pow2(N2) ? tab(N2 * 8) : 0;   // row twiddles for 8 points per thread
   L.twN1d = tab(N1 * 16);
   L.twN2d = tab(N2 * 16);
   L.ew1 = tab(N1 * 8);
@@ -191,6 +193,8 @@ struct cip_plan_s {
   bool solved_once;
   bool attached;        // shares another plan's tables
   bool adaptive;        // FP64 spectra resident: the penalty may change in a solve
+  int row_np;           // row pairs per work-group of the DCT row pass (2 or 4)
+  int row_ppt;          // points per thread of the analysis row passes (default or 8)
   template <typename T> T* at(size_t off) const {
     return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
   }
@@ -246,17 +250,23 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout, dou
                         float sc = 1.f) {
   const Layout& L = p->L;
   float kappa = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
-#ifndef CIP_ROW_DCT_NP
-#define CIP_ROW_DCT_NP 4
-#endif
-  constexpr int NP = CIP_ROW_DCT_NP;
+  auto run = [&](auto kern, int NN, int np, int ppt, size_t work_floats) {
+    return launch(kern, p->S * (p->N1 / RT) * (PAIRS / np), np * (NN / ppt),
+                  (size_t)(4 * NN + work_floats) * 4, st, p->at<const cx<float>>(L.bufB),
+                  p->at<cx<float>>(L.bufA), p->at<float>(L.state), p->N1,
+                  p->at<const cx<float>>(ppt == ppt_row_n(NN) ? L.twN2f : L.twN2f8),
+                  p->at<const cx<float>>(L.ew2), kappa, mode, xout, sc);
+  };
   DISPATCH_N(p->N2, {
-    const int T = NN / ppt_row<NN>();
-    size_t lds = (size_t)(4 * NN + row_work_floats<NN, float>(NP, true)) * 4;
-    return launch(k_admm_row_dct<NN, NP>, p->S * (p->N1 / RT) * (PAIRS / NP), NP * T, lds, st,
-                  p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), p->at<float>(L.state),
-                  p->N1, p->at<const cx<float>>(L.twN2f), p->at<const cx<float>>(L.ew2), kappa,
-                  mode, xout, sc);
+    constexpr int PD = ppt_row<NN>();
+    constexpr int P8 = ((NN & (NN - 1)) == 0 && NN >= 16) ? 8 : PD;
+    const bool alt = p->row_ppt == 8 && P8 != PD;   // tuning variant
+    if (alt && p->row_np == 2)
+      return run(k_admm_row_dct<NN, 2, P8>, NN, 2, P8, row_work_floats<NN, float>(2, true));
+    if (alt) return run(k_admm_row_dct<NN, 4, P8>, NN, 4, P8, row_work_floats<NN, float>(4, true));
+    if (p->row_np == 2)
+      return run(k_admm_row_dct<NN, 2, PD>, NN, 2, PD, row_work_floats<NN, float>(2, true));
+    return run(k_admm_row_dct<NN, 4, PD>, NN, 4, PD, row_work_floats<NN, float>(4, true));
   });
   return hipSuccess;
 }
@@ -270,16 +280,23 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
   const size_t buf = (size_t)(band ? 3 : 2) * p->S * p->N1 * p->N2;
   const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
   float* vout = p->at<float>(L.state) + (size_t)(l & 1) * buf;
-  DISPATCH_N(p->N2, {
-    const int T = NN / ppt_row<NN>();
-    size_t lds = (size_t)(2 * NN + tv_work_floats<NN>()) * 4;
-    if (band)
-      return launch(k_admm_row_tv3<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
-                    p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
-                    p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0, sc);
-    return launch(k_admm_row_tv<NN>, p->S * (p->N1 / RT), (PAIRS + 1) * T, lds, st,
+  auto run = [&](auto kern, int threads, size_t work_floats, bool use8) {
+    return launch(kern, p->S * (p->N1 / RT), threads, (size_t)(2 * p->N2 + work_floats) * 4, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
-                  p->N1, p->at<const cx<float>>(L.twN2f), kappa, l == 1 ? 1 : 0, sc);
+                  p->N1, p->at<const cx<float>>(use8 ? L.twN2f8 : L.twN2f), kappa,
+                  l == 1 ? 1 : 0, sc);
+  };
+  DISPATCH_N(p->N2, {
+    constexpr int PD = ppt_row<NN>();
+    // 8 points per thread only where the work-group stays within 1024 threads
+    constexpr int P8 = ((NN & (NN - 1)) == 0 && NN >= 16 && NN <= 1024) ? 8 : PD;
+    const bool use8 = p->row_ppt == 8 && P8 != PD;   // tuning variant
+    const int threads = (PAIRS + 1) * (NN / (use8 ? P8 : PD));
+    if (band)
+      return use8 ? run(k_admm_row_tv3<NN, P8>, threads, tv_work_floats<NN>(), true)
+                  : run(k_admm_row_tv3<NN, PD>, threads, tv_work_floats<NN>(), false);
+    return use8 ? run(k_admm_row_tv<NN, P8>, threads, tv_work_floats<NN>(), true)
+                : run(k_admm_row_tv<NN, PD>, threads, tv_work_floats<NN>(), false);
   });
   return hipSuccess;
 }
@@ -604,6 +621,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->solved_once = false;
   p->attached = false;
   p->adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
+  p->row_np = PAIRS;
+  p->row_ppt = ppt_row_n(N2);
 
   auto cleanup_fail = [&](int code, const std::string& m) {
     delete p;
@@ -620,6 +639,13 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   std::vector<cx<double>> t1d, t2d;
   twiddles(N1, ppt_col_n(N1), t1f, t1d);   // column transforms (length N1)
   twiddles(N2, ppt_row_n(N2), t2f, t2d);   // row transforms (length N2)
+  if (L.twN2f8) {
+    std::vector<cx<float>> t8f;
+    std::vector<cx<double>> t8d;
+    twiddles(N2, 8, t8f, t8d);
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN2f8), t8f.data(), N2 * 8, hipMemcpyHostToDevice, st));
+    PLAN_HIP(hipStreamSynchronize(st));
+  }
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN1f), t1f.data(), N1 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN2f), t2f.data(), N2 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN1d), t1d.data(), N1 * 16, hipMemcpyHostToDevice, st));
@@ -992,6 +1018,74 @@ int cip_batch_launch(cip_batch_t b, void* stream) {
 
 int cip_batch_destroy(cip_batch_t b) {
   if (b) batch_free(b);
+  return CIP_OK;
+}
+
+int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
+  if (!p || reps < 1) return fail(CIP_EINVAL, "bad argument");
+  if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
+    return fail(CIP_EUNSUPPORTED, "autotuning covers the analysis row passes");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool dct = p->kind == CIP_PRIOR_DCT2D;
+  const int pd = ppt_row_n(p->N2);
+  const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
+  struct Cand { int np, ppt; };
+  std::vector<Cand> cands = {{PAIRS, pd}};
+  if (has8) cands.push_back({PAIRS, 8});
+  if (dct) {
+    cands.push_back({2, pd});
+    if (has8) cands.push_back({2, 8});
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = 1e300, first = 0.0;
+  Cand pick = cands[0];
+  for (size_t c = 0; c < cands.size(); ++c) {
+    p->row_np = cands[c].np;
+    p->row_ppt = cands[c].ppt;
+    for (int r = 0; r < 2; ++r) HIP_TRY(admm_row(p, 2 + (r & 1), st));   // warm-up
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) HIP_TRY(admm_row(p, 2 + (r & 1), st));
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    const double us = 1e3 * ms / reps;
+    if (c == 0) first = us;
+    if (us < best) {
+      best = us;
+      pick = cands[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->row_np = pick.np;
+  p->row_ppt = pick.ppt;
+  if (out) {
+    out->row_np = pick.np;
+    out->row_ppt = pick.ppt;
+    out->row_us = best;
+    out->default_us = first;
+    out->candidates = (int)cands.size();
+  }
+  return CIP_OK;
+}
+
+int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
+  if (!p) return fail(CIP_EINVAL, "NULL plan");
+  const bool dct = p->kind == CIP_PRIOR_DCT2D;
+  const int pd = ppt_row_n(p->N2);
+  const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
+    return fail(CIP_EUNSUPPORTED, "tuning covers the analysis row passes");
+  if (!(row_np == PAIRS || (dct && row_np == 2)))
+    return fail(CIP_EINVAL, "row_np must be 4 (or 2 for the DCT prior)");
+  if (!(row_ppt == pd || (has8 && row_ppt == 8)))
+    return fail(CIP_EINVAL, "row_ppt must be the default or 8 (power-of-two N2)");
+  p->row_np = row_np;
+  p->row_ppt = row_ppt;
   return CIP_OK;
 }
 

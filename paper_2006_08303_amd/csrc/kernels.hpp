@@ -440,18 +440,19 @@ __device__ __forceinline__ float clip_f(float v, float k) { return fminf(fmaxf(v
 enum RowMode { ROW_FIRST = 0, ROW_FULL = 1, ROW_FINAL = 2 };
 
 // Row pass of one ADMM iteration (DCT prior), one work-group per (plane, NP
-// row pairs of a row tile): inverse row FFT of the column-pass output (x^l in the column-DCT /
+// row pairs of a row tile), PPT_ points per thread in the row transforms (the
+// twiddle table must be the one built for PPT_): inverse row FFT of the column-pass output (x^l in the column-DCT /
 // row-frequency domain) -> row DCT gives w = T x^l -> prox + dual update of v
 // -> inverse row DCT of t - u -> forward row FFT -> RT output for the next
 // column pass. ROW_FINAL stops after the inverse row FFT and writes x.
 // LDS: [twiddles N2][DCT table E N2][work region].
-template <int N2, int NP>
-__global__ void __launch_bounds__(NP * (N2 / ppt_row<N2>()), 2)
+template <int N2, int NP, int PPT_ = ppt_row<N2>()>
+__global__ void __launch_bounds__(NP * (N2 / PPT_), 2)
 k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
                float* __restrict__ vstate, int N1, const cx<float>* __restrict__ twg,
                const cx<float>* __restrict__ ewg, float kappa, int mode,
                float* __restrict__ xout, float sc) {
-  constexpr int PPT = ppt_row<N2>();
+  constexpr int PPT = PPT_;
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
   constexpr int SW = 2 * NP;         // tile rows of this work-group
@@ -575,8 +576,8 @@ __device__ __forceinline__ void st_off(float* __restrict__ base, unsigned off, f
 // tile starting at row0. Group g < PAIRS owns rows row0 + 2g, row0 + 2g + 1
 // (local rows 1 + 2g, 2 + 2g of the LDS row block, whose row 0 is the halo
 // row r0 - 1); group PAIRS only transforms the halo pair.
-template <int N2> struct TvGeo {
-  static constexpr int PPT = ppt_row<N2>();
+template <int N2, int PPT_ = ppt_row<N2>()> struct TvGeo {
+  static constexpr int PPT = PPT_;
   static constexpr int T = N2 / PPT;
   static constexpr int H2 = N2 / 2 + 1;
   static constexpr int NR = RT + 2;                // rows in LDS: halo, RT own rows, halo
@@ -587,10 +588,10 @@ template <int N2> struct TvGeo {
 
 // Stage rows r0-1 .. r0+RT of plane s ([k2][NR] order); own rows come from
 // one tile, the two halo rows from the neighbouring tiles.
-template <int N2>
+template <int N2, int PPT_ = ppt_row<N2>()>
 __device__ __forceinline__ void tv_stage_rows(const cx<float>* __restrict__ Yin, cx<float>* stg,
                                               int s, int row0, int N1) {
-  using G = TvGeo<N2>;
+  using G = TvGeo<N2, PPT_>;
   constexpr int H2 = G::H2, NR = G::NR;
   const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
   for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
@@ -607,11 +608,11 @@ __device__ __forceinline__ void tv_stage_rows(const cx<float>* __restrict__ Yin,
 
 // Load the vertical / horizontal state this thread updates in tv_spatial
 // (issued early so that the latency overlaps the transforms).
-template <int N2>
-__device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float (&pov)[TvGeo<N2>::PER],
-                                            float (&poh)[TvGeo<N2>::PER], unsigned s, int row0,
+template <int N2, int PPT_ = ppt_row<N2>()>
+__device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float (&pov)[TvGeo<N2, PPT_>::PER],
+                                            float (&poh)[TvGeo<N2, PPT_>::PER], unsigned s, int row0,
                                             int N1, unsigned cstride, int first) {
-  using G = TvGeo<N2>;
+  using G = TvGeo<N2, PPT_>;
   const unsigned plane = (unsigned)N1 * N2;
 #pragma unroll
   for (int it = 0; it < G::PER; ++it) {
@@ -630,10 +631,10 @@ __device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float
 
 // Inverse row FFTs of the staged rows (two rows per group); x rows -> X =
 // lds [NR][N2]. Begins after the staging writes and ends with a barrier.
-template <int N2>
+template <int N2, int PPT_ = ppt_row<N2>()>
 __device__ __forceinline__ void tv_inverse_rows(const cx<float>* stg, cx<float>* cb,
                                                 const cx<float>* tw, float* X, int g, int t) {
-  using G = TvGeo<N2>;
+  using G = TvGeo<N2, PPT_>;
   constexpr int PPT = G::PPT, T = G::T, NR = G::NR;
   __syncthreads();
   cx<float> v[PPT];
@@ -662,13 +663,13 @@ __device__ __forceinline__ void tv_inverse_rows(const cx<float>* stg, cx<float>*
 // row (vertical only, not stored) and the own rows, q = 2 soft(v) - v, and
 // the spatial part of T^T q for the own rows into v (two rows per group,
 // zero for group PAIRS). Overwrites X; ends with a barrier.
-template <int N2>
-__device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<N2>::PER],
-                                           const float (&poh)[TvGeo<N2>::PER],
+template <int N2, int PPT_ = ppt_row<N2>()>
+__device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<N2, PPT_>::PER],
+                                           const float (&poh)[TvGeo<N2, PPT_>::PER],
                                            float* __restrict__ vout, unsigned s, int row0, int N1,
                                            unsigned cstride, float kappa, float sc, int g, int t,
-                                           cx<float> (&v)[TvGeo<N2>::PPT]) {
-  using G = TvGeo<N2>;
+                                           cx<float> (&v)[PPT_]) {
+  using G = TvGeo<N2, PPT_>;
   constexpr int PPT = G::PPT, T = G::T, PER = G::PER;
   const unsigned plane = (unsigned)N1 * N2;
   const float* X = lds;
@@ -741,11 +742,11 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
 
 // Forward row FFT of v (two rows per group), split into the half spectra of
 // the two rows, staged and written as the RT tile at `tile`.
-template <int N2>
-__device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[TvGeo<N2>::PPT], float* lds,
+template <int N2, int PPT_ = ppt_row<N2>()>
+__device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[PPT_], float* lds,
                                                 cx<float>* cb, const cx<float>* tw,
                                                 cx<float>* __restrict__ tile, int g, int t) {
-  using G = TvGeo<N2>;
+  using G = TvGeo<N2, PPT_>;
   constexpr int PPT = G::PPT, T = G::T, H2 = G::H2;
   fft_group<N2, PPT, +1>(v, cb, t, tw);
   cx<float>* ostg = reinterpret_cast<cx<float>*>(lds);
@@ -783,12 +784,12 @@ __device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[TvGeo<N2>::PPT], 
   staging_to_tile(tile, ostg, H2 * RT);
 }
 
-template <int N2>
-__global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
+template <int N2, int PPT_ = ppt_row<N2>()>
+__global__ void __launch_bounds__((PAIRS + 1) * (N2 / PPT_))
 k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
               const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
               const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
-  using G = TvGeo<N2>;
+  using G = TvGeo<N2, PPT_>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
   float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
@@ -800,13 +801,13 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   const unsigned cstride = (unsigned)S * N1 * N2;   // component stride within a buffer
   lds_load_table(tw, twg, N2);
-  tv_stage_rows<N2>(Yin, stg, s, row0, N1);
+  tv_stage_rows<N2, PPT_>(Yin, stg, s, row0, N1);
   float pov[G::PER], poh[G::PER];
-  tv_prefetch<N2>(vin, pov, poh, s, row0, N1, cstride, first);
-  tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+  tv_prefetch<N2, PPT_>(vin, pov, poh, s, row0, N1, cstride, first);
+  tv_inverse_rows<N2, PPT_>(stg, cb, tw, lds, g, t);
   cx<float> v[G::PPT];
-  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
-  tv_forward_rows<N2>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
+  tv_spatial<N2, PPT_>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
+  tv_forward_rows<N2, PPT_>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
 }
 
 // Row pass of the TV3D prior: T adds the band difference w_b[s] = x[s+1] -
@@ -818,12 +819,12 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
 // by the work-groups of planes s and s + 1 (same inputs, same arithmetic);
 // only the former stores the band state of plane s.
 // State buffer layout [3][S][N1][N2] (vertical, horizontal, band).
-template <int N2>
-__global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
+template <int N2, int PPT_ = ppt_row<N2>()>
+__global__ void __launch_bounds__((PAIRS + 1) * (N2 / PPT_))
 k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
                const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
                const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
-  using G = TvGeo<N2>;
+  using G = TvGeo<N2, PPT_>;
   constexpr int PPT = G::PPT, T = G::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
@@ -843,10 +844,10 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   const float* Xa = lds + (1 + 2 * g) * N2 + t;
   const float* Xb = Xa + N2;
   lds_load_table(tw, twg, N2);
-  tv_stage_rows<N2>(Yin, stg, s, row0, N1);
+  tv_stage_rows<N2, PPT_>(Yin, stg, s, row0, N1);
   float pov[G::PER], poh[G::PER];
-  tv_prefetch<N2>(vin, pov, poh, s, row0, N1, cstride, first);
-  tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+  tv_prefetch<N2, PPT_>(vin, pov, poh, s, row0, N1, cstride, first);
+  tv_inverse_rows<N2, PPT_>(stg, cb, tw, lds, g, t);
   float xa[PPT], xb[PPT];   // x of plane s, own elements
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -854,13 +855,13 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     xb[q] = active ? Xb[T * q] : 0.f;
   }
   cx<float> v[PPT];
-  tv_spatial<N2>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
+  tv_spatial<N2, PPT_>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
   // band terms: first + q_b[s-1] (from plane s-1), then - q_b[s] (plane s+1)
   for (int d = 0; d < 2; ++d) {
     const int sn = d == 0 ? s - 1 : s + 1;   // neighbouring plane
     if (sn < 0 || sn >= S) continue;         // uniform over the work-group
-    tv_stage_rows<N2>(Yin, stg, sn, row0, N1);
-    tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+    tv_stage_rows<N2, PPT_>(Yin, stg, sn, row0, N1);
+    tv_inverse_rows<N2, PPT_>(stg, cb, tw, lds, g, t);
     const unsigned bo = 2 * cstride + (unsigned)(d == 0 ? s - 1 : s) * plane + oa;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -894,7 +895,7 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     }
     __syncthreads();   // X is read above; the next staging overwrites it
   }
-  tv_forward_rows<N2>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
+  tv_forward_rows<N2, PPT_>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j

@@ -1,0 +1,77 @@
+"""GPU tests of the row-pass shapes the autotuner chooses between (row pairs
+per work-group, points per thread / radix sequence): every shape matches the
+FP64 oracle to the FP32 tolerance, and autotuning keeps results within FP32
+rounding of the default shape."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm, model
+from paper_2006_08303_amd import cip, synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().double().numpy()
+
+
+def _problem(N, K, S, cfg=10):
+    x, psf, noise = synth.problem("smooth_disk", N, K, S, seed_config=cfg)
+    hx = model.forward(x, psf)
+    y = (hx + model.snr_noise_scale(hx, 30.0)[:, None, None] * noise)
+    return x, psf, y.astype(np.float32).astype(np.float64)
+
+
+PARAMS = {"dct2d": (1e-2, 0.1), "tv2d": (1e-3, 1e-2), "tv3d": (1e-3, 1e-2)}
+
+
+@pytest.mark.parametrize("prior,N,shapes", [
+    ("dct2d", 128, [(4, 16), (4, 8), (2, 16), (2, 8)]),
+    ("dct2d", 384, [(4, 12), (2, 12)]),
+    ("tv2d", 256, [(4, 16), (4, 8)]),
+    ("tv3d", 128, [(4, 16), (4, 8)]),
+])
+def test_every_shape_matches_oracle(prior, N, shapes):
+    K, S = 3, 3
+    x, psf, y = _problem(N, K, S)
+    lam, rho = PARAMS[prior]
+    ref = admm.AnalysisADMM(psf, prior, lam, rho, 1.0, tier="freq").run(y, 12)[0]
+    plan = cip.Plan(_t(psf), prior, rho, lam, 1.0)
+    for np_, ppt in shapes:
+        plan.set_tuning(np_, ppt)
+        err = admm.rel_l2(_np(plan.solve(_t(y), 12)), ref)
+        print(f"{prior} N={N} shape np={np_} ppt={ppt}: rel_l2 {err:.3e}", flush=True)
+        assert err < 1e-4
+
+
+@pytest.mark.parametrize("prior,N,S", [("dct2d", 1024, 3), ("tv2d", 1024, 3), ("tv3d", 512, 5),
+                                       ("dct2d", 2048, 3)])
+def test_autotune_keeps_results(prior, N, S):
+    x, psf, y = _problem(N, 3, S)
+    lam, rho = PARAMS[prior]
+    plan = cip.Plan(_t(psf), prior, rho, lam, 1.0)
+    yt = _t(y)
+    base = plan.solve(yt, 5).clone()
+    tu = plan.autotune(reps=10)
+    print(f"{prior} N={N}: {tu}", flush=True)
+    got = plan.solve(yt, 5)
+    torch.cuda.synchronize()
+    assert tu["row_us"] <= tu["default_us"]
+    d = float(torch.linalg.vector_norm(got - base) / torch.linalg.vector_norm(base))
+    assert d < 1e-5
+
+
+def test_set_tuning_rejects_bad_shapes():
+    x, psf, y = _problem(64, 2, 2)
+    tv = cip.Plan(_t(psf), "tv2d", 1e-2, 1e-3, 1.0)
+    with pytest.raises(cip.CipError):
+        tv.set_tuning(2, 16)            # row pairs are fixed for TV
+    with pytest.raises(cip.CipError):
+        tv.set_tuning(4, 4)
