@@ -130,6 +130,9 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     out = torch.empty_like(x_t)
     print(f"[bench] {prior}: N={N} K=S={S} iters={args.iters} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
+    plan.solve(y_t, 2, out=out)
+    tuning = plan.autotune(reps=20) if not args.no_autotune else None
+    print(f"[bench] {prior}: row-pass shape {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.solve(y_t, args.iters, out=out)
     torch.cuda.synchronize()
@@ -148,10 +151,10 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
              1: f"column pass + per-frequency solve (k_admm_col)"}
     print(f"[bench] {prior}: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
           flush=True)
-    return plan, y_t, lam, rho, beta, value, ms_step, times, names
+    return plan, y_t, lam, rho, beta, value, ms_step, times, names, tuning
 
 
-def run_concurrent(args, dev, psf_t, y_t):
+def run_concurrent(args, dev, psf_t, y_t, tuning):
     """The same K=S=3 1024^2 DCT problem, `args.concurrent` independent copies
     solved together (one captured batch over as many streams): the working
     set then exceeds the 256 MB Infinity Cache, and the GPU is filled with
@@ -160,6 +163,9 @@ def run_concurrent(args, dev, psf_t, y_t):
     lam, rho, beta = PRIOR_PARAMS["dct2d"]
     plans = [cip.Plan(psf_t, "dct2d", rho, lam, beta) for _ in range(n)]
     xs = [torch.empty((plans[0].S, plans[0].N1, plans[0].N2), device=dev) for _ in range(n)]
+    if tuning:
+        for pl in plans:
+            pl.set_tuning(tuning["row_np"], tuning["row_ppt"])
     b = cip.Batch([(plans[i], y_t, args.iters, xs[i]) for i in range(n)], n_streams=n, graph=True)
     b.launch()
     torch.cuda.synchronize()
@@ -197,6 +203,9 @@ def run_batch(args, dev):
         plan = cip.Plan(torch.tensor(psf, dtype=torch.float32, device=dev), prior, rho, lam, beta)
         y = torch.randn((K, N, N), device=dev)
         x = torch.empty((S, N, N), device=dev)
+        if not args.no_autotune:
+            plan.solve(y, 2, out=x)
+            plan.autotune(reps=5)
         probs.append((plan, y, args.iters, x))
         vox += S * N * N
     torch.cuda.synchronize()
@@ -236,7 +245,7 @@ def run_serving(args, dev, n_slots):
     rng = np.random.default_rng(5000)
     sizes = [n for n in (256, 384, 512, 768, 1024, 1536, 2048) if n in cip.SUPPORTED_N]
     kinds = [(N, B) for N in sizes for B in (3, 5, 8)]
-    srv = cip.Server(args.serve_budget_gb << 30, n_slots=n_slots)
+    srv = cip.Server(args.serve_budget_gb << 30, n_slots=n_slots, autotune=not args.no_autotune)
     ops, ys, pools = [], [], []
     for j, (N, B) in enumerate(kinds):
         psf = synth.disk_psfs(B, B, N, N)
@@ -316,6 +325,8 @@ def main():
     ap.add_argument("--batch", type=int, default=96, help="problems in the batch run (0: skip)")
     ap.add_argument("--concurrent", type=int, default=8,
                     help="copies of the headline problem solved together (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default row-pass shapes (no cip_plan_autotune)")
     ap.add_argument("--quick", action="store_true",
                     help="headline DCT solve and kernel timings only (for profiler runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -335,7 +346,7 @@ def main():
     dev = torch.device("cuda:0")
     N, K, S = args.N, args.bands, args.bands
     x, psf, noise, psf_t, x_t, noise_t = make_workload(N, K, S, dev)
-    plan, y_t, lam, rho, beta, value, ms_step, times, names = run_prior(
+    plan, y_t, lam, rho, beta, value, ms_step, times, names, tuning = run_prior(
         "dct2d", N, K, S, args, psf_t, x_t, noise_t)
     dom = max(times, key=times.get)
     byt = algorithmic_bytes(dom, S, N, N, "dct2d")
@@ -350,10 +361,10 @@ def main():
                                  algorithmic_bytes(1 - dom, S, N, N, "dct2d")}}
     tv = None
     if not args.no_tv:
-        _, _, _, _, _, tv_value, tv_ms, tv_times, tv_names = run_prior(
+        _, _, _, _, _, tv_value, tv_ms, tv_times, tv_names, tv_tuning = run_prior(
             "tv2d", N, K, S, args, psf_t, x_t, noise_t)
         tv = {"prior": "tv2d (lambda=1e-3, rho=1e-2, beta=1)", "value": round(tv_value, 1),
-              "ms_per_step": round(tv_ms, 4),
+              "ms_per_step": round(tv_ms, 4), "row_shape": tv_tuning,
               "kernels_avg_us": {tv_names[w]: round(tv_times[w], 3) for w in tv_times},
               "algorithmic_bytes_per_launch": {tv_names[w]: algorithmic_bytes(w, S, N, N, "tv2d")
                                                for w in tv_times}}
@@ -363,7 +374,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    conc = run_concurrent(args, dev, psf_t, y_t) if args.concurrent > 1 else None
+    conc = run_concurrent(args, dev, psf_t, y_t, tuning) if args.concurrent > 1 else None
     batch = run_batch(args, dev) if args.batch > 0 else None
     serving = None
     if args.serve_seconds > 0:
@@ -399,7 +410,8 @@ def main():
         "config": {"workload": f"ADMM DCT-l1 reconstruction, K=S={S}, {N}x{N}, defocus-disk "
                                f"kernels, 30 dB, {args.iters} iterations per solve",
                    "K": K, "S": S, "N1": N, "N2": N, "iters_per_step": args.iters,
-                   "prior": "dct2d", "lambda": lam, "rho": rho, "beta": beta},
+                   "prior": "dct2d", "lambda": lam, "rho": rho, "beta": beta,
+                   "row_shape": tuning},
         "roofline": roof,
         "cpu_baseline": cpu,
         "tv2d": tv,

@@ -236,6 +236,8 @@ typedef struct cip_server_s* cip_server_t;
 typedef struct {
   size_t hbm_budget_bytes;   /* device memory for operators and requests    */
   int n_slots;               /* concurrent solves, 1 .. 16                  */
+  int autotune;              /* nonzero: tune each operator's row pass when
+                                it is registered (cip_plan_autotune)        */
 } cip_server_config;
 typedef struct {
   int op;                    /* operator id from cip_server_add_operator    */

@@ -72,7 +72,8 @@ def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0):
 
 
 class _ServerConfig(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int)]
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -314,8 +315,8 @@ class Server:
     """Request server (cip_server_*): operators registered once, requests
     with host numpy buffers, continuous batching over n_slots streams."""
 
-    def __init__(self, hbm_budget_bytes, n_slots=4):
-        cfg = _ServerConfig(int(hbm_budget_bytes), int(n_slots))
+    def __init__(self, hbm_budget_bytes, n_slots=4, autotune=False):
+        cfg = _ServerConfig(int(hbm_budget_bytes), int(n_slots), int(bool(autotune)))
         h = ctypes.c_void_p()
         _check(lib().cip_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -106,6 +106,7 @@ struct Request {
 
 struct cip_server_s {
   int device = 0;
+  bool autotune = false;
   void* base = nullptr;
   std::unique_ptr<Arena> arena;
   size_t reserved_ops = 0;   // bytes held by operators
@@ -197,6 +198,7 @@ int cip_server_create(const cip_server_config* cfg, cip_server_t* out) {
   if (hipMalloc(&s->base, cap) != hipSuccess)
     return fail(CIP_EHIP, "hipMalloc of the server arena failed");
   s->arena = std::make_unique<Arena>(cap);
+  s->autotune = cfg->autotune != 0;
   for (int i = 0; i < cfg->n_slots; ++i) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -233,6 +235,28 @@ int cip_server_add_operator(cip_server_t s, int K, int S, int N1, int N2, const 
     s->arena->release(off, ws);
     s->reserved_ops -= round_up(ws);
     return rc;
+  }
+  if (s->autotune && prior->kind != CIP_PRIOR_PATCH && prior->kind != CIP_PRIOR_CONV2D) {
+    // one short solve on zero measurements (the tuner times the row pass on
+    // the plan's own buffers), with y and x carved from the arena meanwhile
+    const size_t yb = round_up((size_t)K * N1 * N2 * 4), xb = (size_t)S * N1 * N2 * 4;
+    const size_t toff = s->arena->alloc(yb + xb);
+    if (toff != SIZE_MAX) {
+      unsigned char* t = static_cast<unsigned char*>(s->base) + toff;
+      hipStream_t st = s->streams[0];
+      int trc = hipMemsetAsync(t, 0, yb, st) == hipSuccess ? CIP_OK : CIP_EHIP;
+      if (!trc) trc = cip_solve(plan, reinterpret_cast<float*>(t), 2,
+                                reinterpret_cast<float*>(t + yb), st);
+      if (!trc) trc = cip_plan_autotune(plan, 10, st, nullptr);
+      if (!trc && hipStreamSynchronize(st) != hipSuccess) trc = CIP_EHIP;
+      s->arena->release(toff, yb + xb);
+      if (trc) {
+        s->arena->release(off, ws);
+        s->reserved_ops -= round_up(ws);
+        cip_plan_destroy(plan);
+        return fail(trc, "operator autotuning failed: " + cip::g_last_error);
+      }
+    }
   }
   Operator op;
   op.plan = plan;
