@@ -45,7 +45,7 @@ def analysis_objective(x, y, psf, transform, lam, beta):
 
 
 class AnalysisADMM:
-    """Algorithm 1 for T in {dct2d, tv2d, tv3d} and Phi = l1."""
+    """Algorithm 1 for T in {dct2d, dct3d, tv2d, tv3d} and Phi = l1."""
 
     def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto"):
         K, S, N1, N2 = psf.shape

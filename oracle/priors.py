@@ -2,7 +2,8 @@
 
 * Analysis prior R(x) = lambda * ||T x||_1 (Eq. analysis with Phi = l1):
   - T = orthonormal 2D DCT-II applied to each slice (a unitary transform, so
-    T^H T = I as assumed below Eq. solx_Trans);
+    T^H T = I as assumed below Eq. solx_Trans), or the same followed by the
+    orthonormal DCT-II along the band axis (one 3D transform);
   - T = anisotropic discrete gradient on each slice (circular forward
     differences along both image axes; "multidimensional discrete derivative
     operators" of Section III-A);
@@ -70,6 +71,27 @@ class DCT2D:
         return np.ones((N1, N2))
 
 
+class DCT3D(DCT2D):
+    """A single 3D transform over the cube (Section III-A: a 3D transform when
+    the data are correlated along all three dimensions): the orthonormal
+    DCT-II along the band axis applied to the 2D DCT of every slice,
+    T x = C_S (C_{N1} x_s C_{N2}^T) with C_S acting on the slice index."""
+
+    name = "dct3d"
+
+    def __init__(self, S: int, N1: int, N2: int):
+        super().__init__(S, N1, N2)
+        self.CS = dct_matrix(S)
+
+    def T(self, x):
+        w2 = self.C1 @ x @ self.C2.T                        # (S, N1, N2)
+        return np.tensordot(self.CS, w2, axes=(1, 0))[None]
+
+    def Tt(self, w):
+        w2 = np.tensordot(self.CS.T, w[0], axes=(1, 0))
+        return self.C1.T @ w2 @ self.C2
+
+
 class TV2D:
     """Anisotropic gradient per slice, circular forward differences:
     w[0] = x[n1 + 1, n2] - x[n1, n2],  w[1] = x[n1, n2 + 1] - x[n1, n2]."""
@@ -134,7 +156,7 @@ class TV3D(TV2D):
 
 
 def make_transform(kind: str, S: int, N1: int, N2: int):
-    return {"dct2d": DCT2D, "tv2d": TV2D, "tv3d": TV3D}[kind](S, N1, N2)
+    return {"dct2d": DCT2D, "dct3d": DCT3D, "tv2d": TV2D, "tv3d": TV3D}[kind](S, N1, N2)
 
 
 # ---------------------------------------------------------------- patches

@@ -102,7 +102,7 @@ def test_dct_matrix_matches_scipy_and_is_orthonormal():
         assert np.allclose(C @ v, scipy.fft.dct(v, type=2, norm="ortho"), atol=1e-13)
 
 
-@pytest.mark.parametrize("kind", ["dct2d", "tv2d", "tv3d"])
+@pytest.mark.parametrize("kind", ["dct2d", "dct3d", "tv2d", "tv3d"])
 def test_transform_adjoint(kind):
     T = priors.make_transform(kind, 3, 8, 6)
     x = _rng(6).standard_normal((3, 8, 6))
@@ -562,3 +562,42 @@ def test_adaptive_stops_at_first_check_below_tolerance():
     x2, info2 = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq").run_adaptive(
         y, info["iters"] - 4, every=5, tol=0.0)   # its last check is at iters - 5
     assert info2["rel_change"] >= 1e-3
+
+
+# ---------------------------------------------------------------- 3D DCT prior
+def test_dct3d_matches_scipy_dctn_and_is_orthonormal():
+    """T of the 3D DCT prior is scipy's orthonormal DCT-II over all three axes."""
+    S, N1, N2 = 5, 6, 4
+    T = priors.DCT3D(S, N1, N2)
+    x = _rng(80).standard_normal((S, N1, N2))
+    assert np.allclose(T.T(x)[0], scipy.fft.dctn(x, type=2, norm="ortho"), atol=1e-12)
+    assert np.allclose(T.Tt(T.T(x)), x, atol=1e-12)
+    assert np.isclose(np.linalg.norm(T.T(x)), np.linalg.norm(x), rtol=1e-13)
+
+
+def test_dct3d_identity_blur_closed_form():
+    """With H = I the DCT3D-l1 problem is orthonormal-basis denoising: the
+    minimiser is T^T soft(T y, lambda / beta), which differs from the
+    per-slice (2D) answer when S > 1."""
+    S, N = 3, 8
+    psf = np.zeros((S, S, N, N))
+    for s in range(S):
+        psf[s, s, 0, 0] = 1.0
+    y = _rng(81).standard_normal((S, N, N))
+    lam, beta, rho = 0.3, 1.0, 0.7
+    x, _, _ = admm.AnalysisADMM(psf, "dct3d", lam, rho, beta, tier="freq").run(y, 400)
+    T = priors.DCT3D(S, N, N)
+    ref = T.Tt(priors.soft(T.T(y), lam / beta))
+    assert np.allclose(x, ref, atol=1e-9)
+    x2 = priors.DCT2D(S, N, N)
+    ref2 = x2.Tt(priors.soft(x2.T(y), lam / beta))
+    assert np.linalg.norm(ref - ref2) > 1e-2 * np.linalg.norm(ref)
+
+
+def test_dct3d_admm_kkt():
+    x0, psf = _small_problem(K=3, S=3, N1=8, N2=8, seed=44)
+    y = model.forward(x0, psf) + 0.01 * _rng(82).standard_normal((3, 8, 8))
+    alg = admm.AnalysisADMM(psf, "dct3d", 1e-2, 0.2, 1.0, tier="freq")
+    x, t, u = alg.run(y, 3000)
+    r1, r2, r3 = alg.kkt(y, x, t, u)
+    assert r1 < 1e-8 and r2 < 1e-8 and r3 < 1e-8
