@@ -71,6 +71,10 @@ typedef enum {
    * Algorithm 2 with the frequency-domain sparse-code update of
    * Eqs. solz_DFT / solz_DFT_SM. */
   CIP_PRIOR_CONV2D = 4,
+  /* Analysis prior with T = one 3D transform (Section III-A, data correlated
+   * along all three dimensions): the orthonormal 2D DCT-II of every plane
+   * followed by the orthonormal DCT-II along the plane (band) axis. */
+  CIP_PRIOR_DCT3D = 5,
 } cip_prior_kind;
 
 typedef struct {

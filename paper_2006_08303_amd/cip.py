@@ -22,8 +22,9 @@ CIP_PRIOR_TV3D = 1
 CIP_PRIOR_DCT2D = 2
 CIP_PRIOR_PATCH = 3
 CIP_PRIOR_CONV2D = 4
+CIP_PRIOR_DCT3D = 5
 PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
-          "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D}
+          "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D, "dct3d": CIP_PRIOR_DCT3D}
 
 
 class CipError(RuntimeError):

@@ -61,6 +61,7 @@ struct Layout {
   size_t twN2f8;                        // row twiddles, 8 points per thread (tuning variant)
   size_t ew1, ew2;                      // DCT tables exp(-i pi k / 2N) (N1 and N2)
   size_t lam32, Adiag, Aoff, Mm, xh0;   // per-frequency tables (x_hat0 per solve)
+  size_t band;                          // DCT3D: band DCT-II matrix [S][S]
   size_t bufA, bufB;                    // RT staging (max(K,S) planes)
   size_t state;                         // ADMM state
   size_t lam64, rt64, pl64;             // plan-time FP64 scratch (lam64 resident if adaptive)
@@ -75,6 +76,7 @@ struct Layout {
 int state_floats_per_voxel(int kind) {
   switch (kind) {
     case CIP_PRIOR_DCT2D: return 1;
+    case CIP_PRIOR_DCT3D: return 1;
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
@@ -114,6 +116,7 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   L.Adiag = tab((size_t)S * F * 4);
   L.Aoff = tab((size_t)(S * (S - 1) / 2) * F * 8 + 8);
   L.Mm = tab((size_t)S * K * F * 8);
+  L.band = kind == CIP_PRIOR_DCT3D ? tab((size_t)S * S * 4) : 0;   // band DCT matrix C_S
   L.xh0 = sta((size_t)S * F * 8);
   L.bufA = sta(P * F * 8);
   L.bufB = sta(P * F * 8);
@@ -199,6 +202,10 @@ struct cip_plan_s {
     return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
   }
 };
+
+bool is_dct(const cip_plan_s* p) {
+  return p->kind == CIP_PRIOR_DCT2D || p->kind == CIP_PRIOR_DCT3D;
+}
 
 // ---------------------------------------------------------------- launch helpers
 namespace {
@@ -302,7 +309,7 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
 }
 
 hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
-  if (p->kind == CIP_PRIOR_DCT2D)
+  if (is_dct(p))
     return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr, rho, sc);
   return admm_row_tv(p, l, st, rho, sc);
 }
@@ -316,7 +323,7 @@ hipError_t norm_pass(cip_plan_t p, int l, double rho, float* xcur, const float* 
   const int first = l == 1 ? 1 : 0;
   const int grid = p->S * (p->N1 / RT);
   *groups = grid;
-  if (p->kind == CIP_PRIOR_DCT2D) {
+  if (is_dct(p)) {
     DISPATCH_N(p->N2, {
       const int T = NN / ppt_row<NN>();
       size_t lds = (size_t)(4 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
@@ -348,14 +355,15 @@ hipError_t norm_pass(cip_plan_t p, int l, double rho, float* xcur, const float* 
 
 hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
   const Layout& L = p->L;
-  const bool dct = p->kind == CIP_PRIOR_DCT2D;
+  const bool dct = is_dct(p);
 #define CIP_COL_CASE(NN)                                                                        \
   case NN:                                                                                      \
     return admm_col_launch_##NN(p->S, dct, p->at<const cx<float>>(L.bufA),                      \
                                 p->at<cx<float>>(L.bufB), p->H2, p->at<const float>(L.Adiag),    \
                                 p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.xh0),   \
                                 p->at<const cx<float>>(L.twN1f), p->at<const cx<float>>(L.ew1),  \
-                                zero_in, dct_out, st);
+                                L.band ? p->at<const float>(L.band) : nullptr, zero_in,          \
+                                dct_out, st);
   switch (p->N1) {
     CIP_FOR_EACH_SIZE(CIP_COL_CASE)
   }
@@ -651,6 +659,16 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN1d), t1d.data(), N1 * 16, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN2d), t2d.data(), N2 * 16, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipStreamSynchronize(st));
+  if (L.band) {   // orthonormal DCT-II along the band axis, C[k][s] = a_k cos(pi (2s+1) k / 2S)
+    std::vector<float> cs((size_t)S * S);
+    for (int k = 0; k < S; ++k)
+      for (int j = 0; j < S; ++j)
+        cs[(size_t)k * S + j] = (float)((k == 0 ? std::sqrt(1.0 / S) : std::sqrt(2.0 / S)) *
+                                        std::cos(M_PI * (2.0 * j + 1.0) * k / (2.0 * S)));
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.band), cs.data(), cs.size() * 4, hipMemcpyHostToDevice,
+                            st));
+    PLAN_HIP(hipStreamSynchronize(st));
+  }
   dct_table(N1, fw);
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.ew1), fw.data(), N1 * 8, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipStreamSynchronize(st));
@@ -836,7 +854,7 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
       }
       if (stop || l == iters) {
         out.iters = l;
-        if (stop && p->kind == CIP_PRIOR_DCT2D && l < iters) {
+        if (stop && is_dct(p) && l < iters) {
           // the column pass of this iteration applied the column DCT for the
           // next row pass: redo it without (its input, bufA, is intact)
           HIP_TRY(admm_col(p, 0, 0, st));
@@ -1027,7 +1045,7 @@ int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
     return fail(CIP_EUNSUPPORTED, "autotuning covers the analysis row passes");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool dct = p->kind == CIP_PRIOR_DCT2D;
+  const bool dct = is_dct(p);
   const int pd = ppt_row_n(p->N2);
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
   struct Cand { int np, ppt; };
@@ -1075,7 +1093,7 @@ int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
 
 int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   if (!p) return fail(CIP_EINVAL, "NULL plan");
-  const bool dct = p->kind == CIP_PRIOR_DCT2D;
+  const bool dct = is_dct(p);
   const int pd = ppt_row_n(p->N2);
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)

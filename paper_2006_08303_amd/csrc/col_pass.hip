@@ -16,11 +16,12 @@ namespace cip {
 template <int NN, bool DCT>
 static hipError_t col_n(int S, const cx<float>* Gin, cx<float>* Yout, int H2, const float* Adiag,
                         const cx<float>* Aoff, const cx<float>* xh0, const cx<float>* tw,
-                        const cx<float>* ew, int zero_in, int dct_out, hipStream_t st) {
+                        const cx<float>* ew, const float* band, int zero_in, int dct_out,
+                        hipStream_t st) {
   const int T = NN / ppt_col<NN>();
   auto run = [&](auto kern, size_t lds_floats) {
     return launch(kern, H2, S * T, lds_floats * 4, st, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew,
-                  zero_in, dct_out);
+                  band, zero_in, dct_out);
   };
   switch (S) {
     case 1: return run(k_admm_col<NN, DCT, 1>, col_lds_floats<NN, DCT, 1>());
@@ -39,9 +40,12 @@ hipError_t CIP_CAT(admm_col_launch_, CIP_COL_N)(int S, bool dct, const cx<float>
                                                  cx<float>* Yout, int H2, const float* Adiag,
                                                  const cx<float>* Aoff, const cx<float>* xh0,
                                                  const cx<float>* tw, const cx<float>* ew,
-                                                 int zero_in, int dct_out, hipStream_t st) {
-  return dct ? col_n<CIP_COL_N, true>(S, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew, zero_in, dct_out, st)
-             : col_n<CIP_COL_N, false>(S, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew, zero_in, dct_out, st);
+                                                 const float* band, int zero_in, int dct_out,
+                                                 hipStream_t st) {
+  return dct ? col_n<CIP_COL_N, true>(S, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew, band, zero_in,
+                                      dct_out, st)
+             : col_n<CIP_COL_N, false>(S, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew, nullptr, zero_in,
+                                       dct_out, st);
 }
 
 }  // namespace cip

@@ -12,7 +12,8 @@ namespace cip {
   hipError_t admm_col_launch_##NN(int S, bool dct, const cx<float>* Gin, cx<float>* Yout,      \
                                   int H2, const float* Adiag, const cx<float>* Aoff,           \
                                   const cx<float>* xh0, const cx<float>* tw,                   \
-                                  const cx<float>* ew, int zero_in, int dct_out, hipStream_t st);
+                                  const cx<float>* ew, const float* band, int zero_in,         \
+                                  int dct_out, hipStream_t st);
 CIP_FOR_EACH_SIZE(CIP_DECLARE_COL)
 #undef CIP_DECLARE_COL
 

@@ -902,11 +902,44 @@ __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
   return i * S - i * (i + 1) / 2 + (j - i - 1);
 }
 
+// Mix the S planes of a column pass work-group at every element with the
+// band matrix C (S x S, row-major): plane g receives sum_j C[g][j] v_j
+// (TRANS: sum_j C[j][g] v_j). Group g holds plane g's elements t + T q in
+// v; buf is the LDS array of S padded planes. Barriers before and after.
+template <int N1, int PPT, int S, bool TRANS>
+__device__ __forceinline__ void band_mix(cx<float>* v, cx<float>* buf, const float* __restrict__ C,
+                                         int g, int t) {
+  constexpr int T = N1 / PPT;
+  constexpr int PL = padded_len(N1);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) stc(buf + g * PL, t + T * q, v[q]);
+  __syncthreads();
+  float c[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) c[j] = TRANS ? C[j * S + g] : C[g * S + j];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    cx<float> acc = {0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const cx<float> w = ldc(buf + j * PL, t + T * q);
+      acc.x += c[j] * w.x;
+      acc.y += c[j] * w.y;
+    }
+    v[q] = acc;
+  }
+  __syncthreads();
+}
+
 // Column pass of one ADMM iteration, one work-group per column k2 holding all
 // S planes: [inverse column DCT] -> column FFT -> per-frequency solve
 //   X(w) = xh0(w) + A(w) g(w)    (A = rho Psi^+ / (N1 N2), packed Hermitian)
 // -> inverse column FFT -> [column DCT] -> RT output.
-// DCT = true for the DCT prior (T acts on both axes), false for TV priors.
+// DCT = true for the DCT priors (T acts on both axes), false for TV priors;
+// band != NULL (3D DCT): the band DCT C_S is applied across the planes after
+// the column DCT of the output and its transpose before the inverse column
+// DCT of the input (it commutes with the per-plane transforms).
 // The solve tables are read inside the solve, not prefetched at kernel start:
 // a prefetch of the Psi^+ row costs about 2 S PPT registers, which lowers the
 // number of resident waves below what a 1024^2 problem needs (measured:
@@ -927,7 +960,8 @@ __global__ void __launch_bounds__(S * (N1 / ppt_col<N1>()))
 k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int H2,
            const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
            const cx<float>* __restrict__ xh0, const cx<float>* __restrict__ twg,
-           const cx<float>* __restrict__ ewg, int zero_in, int dct_out) {
+           const cx<float>* __restrict__ ewg, const float* __restrict__ band, int zero_in,
+           int dct_out) {
   constexpr int PPT = ppt_col<N1>();
   constexpr int T = N1 / PPT;
   constexpr int PL = padded_len(N1);
@@ -964,7 +998,10 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   }
   __syncthreads();
   if (!zero_in) {
-    if constexpr (DCT) dct_inv_group<N1, PPT, false>(v, cb, t, tw, ew);
+    if constexpr (DCT) {
+      if (band) band_mix<N1, PPT, S, true>(v, reinterpret_cast<cx<float>*>(lds), band, g, t);
+      dct_inv_group<N1, PPT, false>(v, cb, t, tw, ew);
+    }
     fft_group<N1, PPT, +1>(v, cb, t, tw);
 #pragma unroll
     for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
@@ -995,7 +1032,10 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   }
   fft_group<N1, PPT, -1>(v, cb, t, tw);
   if constexpr (DCT) {
-    if (dct_out) dct_fwd_group<N1, PPT, false>(v, cb, t, tw, ew);
+    if (dct_out) {
+      dct_fwd_group<N1, PPT, false>(v, cb, t, tw, ew);
+      if (band) band_mix<N1, PPT, S, false>(v, reinterpret_cast<cx<float>*>(lds), band, g, t);
+    }
   }
 #pragma unroll
   for (int q = 0; q < PPT; ++q) Yout[rt_idx(g, t + T * q, k2, N1, H2)] = v[q];

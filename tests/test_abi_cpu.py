@@ -59,3 +59,43 @@ def test_create_rejects_bad_workspace(L):
     rc = L.cip_plan_create(2, 2, 64, 64, None, ctypes.byref(desc), 0.1, 0.01,
                            ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(h))
     assert rc == -1
+
+
+def test_workspace_grows_with_adaptive_flag_and_dct3d(L):
+    """The adaptive flag keeps the FP64 spectra (K S F 16 bytes, which
+    otherwise share memory with the solve state) and adds the iterate
+    buffers; the 3D DCT adds its S x S band matrix."""
+    from paper_2006_08303_amd import cip
+    K, S, N = 3, 3, 256
+    F = N * (N // 2 + 1)
+    base = cip.workspace_bytes(K, S, N, N, "dct2d")
+    ad = cip.workspace_bytes(K, S, N, N, "dct2d", flags=cip.CIP_PLAN_ADAPTIVE)
+    assert ad >= K * S * F * 16 + 2 * S * N * N * 4 and ad > base
+    assert cip.workspace_bytes(K, S, N, N, "dct3d") >= base
+    for n in (384, 768, 1536):
+        assert cip.workspace_bytes(2, 2, n, n, "tv3d") > 0
+    with pytest.raises(cip.CipError) as e:
+        cip.workspace_bytes(2, 2, 640, 640, "dct2d")   # 5 * 2^7 is not served
+    assert e.value.code == -2
+
+
+def test_new_entry_points_validate_before_device_work(L):
+    """Argument errors are reported without touching the device."""
+    from paper_2006_08303_amd import cip
+    info = cip._SolveInfo()
+    prm = cip._AdaptiveParams(10, 1, 2.0, 10.0, 1e-4)
+    assert L.cip_solve_adaptive(None, None, ctypes.byref(prm), None, None, ctypes.byref(info)) == -1
+    assert L.cip_plan_set_tuning(None, 4, 16) == -1
+    assert L.cip_plan_autotune(None, 10, None, None) == -1
+    h = ctypes.c_void_p()
+    cfg = cip._ServerConfig(1 << 30, 0, 0)          # no slots
+    assert L.cip_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    cfg = cip._ServerConfig(1 << 30, 17, 0)         # too many slots
+    assert L.cip_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    cfg = cip._ServerConfig(1024, 2, 0)             # budget below 1 MiB
+    assert L.cip_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert L.cip_batch_create(0, None, None, None, None, 4, 1, ctypes.byref(h)) == -1
+    desc = cip._desc("conv2d", 1.0)
+    desc.n_filters, desc.filt_l, desc.mu = 4, 3, -1.0   # negative Tikhonov weight
+    n = ctypes.c_size_t()
+    assert L.cip_plan_workspace_bytes(2, 2, 64, 64, ctypes.byref(desc), ctypes.byref(n)) == -1
