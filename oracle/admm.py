@@ -45,9 +45,12 @@ def analysis_objective(x, y, psf, transform, lam, beta):
 
 
 class AnalysisADMM:
-    """Algorithm 1 for T in {dct2d, dct3d, tv2d, tv3d} and Phi = l1."""
+    """Algorithm 1 for T in {dct2d, dct3d, tv2d, tv3d} and Phi = l1, and for
+    isotropic TV ("itv2d": T = I, Phi = TV, t-update by Chambolle's
+    algorithm with `inner` iterations per ADMM iteration, warm-started from
+    the previous dual p, step 1/8)."""
 
-    def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto"):
+    def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto", inner=20):
         K, S, N1, N2 = psf.shape
         self.psf = psf
         self.kind = kind
@@ -55,7 +58,19 @@ class AnalysisADMM:
         self.lam, self.beta = float(lam), float(beta)
         self.T = priors.make_transform(kind, S, N1, N2)
         self.tier = _tier(S, N1, N2, tier)
+        self.inner = int(inner)
         self.set_rho(rho)
+
+    def t_update(self, v, kappa, p):
+        """Eq. solt_trans for Phi = l1 (soft threshold of v = Tx + u); for
+        isotropic TV the TV proximal map of v by Chambolle's algorithm.
+        Returns (t, p) (p: the TV dual, None for l1)."""
+        if self.kind == "itv2d":
+            if p is None:
+                p = np.zeros((2,) + v.shape[1:])
+            t, p = priors.chambolle(v[0], kappa, p, self.inner)
+            return t[None], p
+        return priors.soft(v, kappa), None
 
     def set_rho(self, rho):
         """(Re)build the x-update for penalty rho (Psi depends on rho)."""
@@ -87,10 +102,11 @@ class AnalysisADMM:
             t, u = (a.copy() for a in state)
         x = None
         kappa = self.lam / self.rho
+        p = None
         for it in range(iters):
             x = self.x_update(data, t, u)
             w = self.T.T(x)
-            t_new = priors.soft(w + u, kappa)
+            t_new, p = self.t_update(w + u, kappa, p)
             u = u + w - t_new
             t = t_new
             if callback is not None:
@@ -117,11 +133,12 @@ class AnalysisADMM:
         info = {"rel_change": None, "r": None, "s": None}
         it = 0
         x = None
+        p = None
         for it in range(1, max_iters + 1):
             x = self.x_update(data, t, u)
             w = self.T.T(x)
             kappa = self.lam / self.rho
-            t_new = priors.soft(w + u, kappa)
+            t_new, p = self.t_update(w + u, kappa, p)
             u_new = u + w - t_new
             if it % every == 0 and it < max_iters:   # the last iterate is returned anyway
                 r = float(np.linalg.norm(w - t_new))

@@ -155,8 +155,61 @@ class TV3D(TV2D):
         return L
 
 
+class Identity:
+    """T = I: the analysis split used with isotropic TV (Phi(Tx) = TV(x) with
+    T = I, Section III-A); the t-update is then the TV proximal map."""
+
+    name = "itv2d"
+
+    def __init__(self, S: int, N1: int, N2: int):
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.shape = (1, S, N1, N2)
+
+    def T(self, x):
+        return x[None].copy()
+
+    def Tt(self, w):
+        return w[0].copy()
+
+    def gram_symbol(self, N1, N2):
+        return np.ones((N1, N2))
+
+
 def make_transform(kind: str, S: int, N1: int, N2: int):
-    return {"dct2d": DCT2D, "dct3d": DCT3D, "tv2d": TV2D, "tv3d": TV3D}[kind](S, N1, N2)
+    return {"dct2d": DCT2D, "dct3d": DCT3D, "tv2d": TV2D, "tv3d": TV3D,
+            "itv2d": Identity}[kind](S, N1, N2)
+
+
+# ---------------------------------------------------------------- isotropic TV
+def grad2(x: np.ndarray) -> np.ndarray:
+    """Circular forward differences of every slice, shape (2,) + x.shape."""
+    return np.stack([np.roll(x, -1, axis=-2) - x, np.roll(x, -1, axis=-1) - x])
+
+
+def div2(p: np.ndarray) -> np.ndarray:
+    """Discrete divergence, the negative adjoint of grad2:
+    div p = (p0[n1] - p0[n1 - 1]) + (p1[n2] - p1[n2 - 1])."""
+    return (p[0] - np.roll(p[0], 1, axis=-2)) + (p[1] - np.roll(p[1], 1, axis=-1))
+
+
+def tv_iso(x: np.ndarray) -> float:
+    """Isotropic TV, sum over pixels and slices of |grad x| (Euclidean)."""
+    g = grad2(x)
+    return float(np.sum(np.sqrt(g[0] ** 2 + g[1] ** 2)))
+
+
+def chambolle(f: np.ndarray, mu: float, p: np.ndarray, iters: int, tau: float = 0.125):
+    """Chambolle's projection algorithm for the isotropic-TV proximal map
+    argmin_t 1/2 ||t - f||^2 + mu TV(t), every slice separately:
+        p <- (p + tau grad(div p - f / mu)) / (1 + tau |grad(div p - f / mu)|),
+    t = f - mu div p; tau <= 1/8 guarantees convergence. Starts from the dual
+    p given (shape (2,) + f.shape) and returns (t, p)."""
+    p = p.copy()
+    for _ in range(iters):
+        g = grad2(div2(p) - f / mu)
+        nrm = np.sqrt(g[0] ** 2 + g[1] ** 2)
+        p = (p + tau * g) / (1.0 + tau * nrm)
+    return f - mu * div2(p), p
 
 
 # ---------------------------------------------------------------- patches

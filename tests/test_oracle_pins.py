@@ -601,3 +601,57 @@ def test_dct3d_admm_kkt():
     x, t, u = alg.run(y, 3000)
     r1, r2, r3 = alg.kkt(y, x, t, u)
     assert r1 < 1e-8 and r2 < 1e-8 and r3 < 1e-8
+
+
+# ---------------------------------------------------------------- isotropic TV (T = I, Chambolle)
+def test_div_is_negative_adjoint_of_grad():
+    x = _rng(90).standard_normal((2, 6, 5))
+    p = _rng(91).standard_normal((2, 2, 6, 5))
+    assert np.isclose(np.vdot(priors.grad2(x), p), -np.vdot(x, priors.div2(p)), rtol=1e-12)
+
+
+def test_chambolle_meets_the_tv_prox_optimality_conditions():
+    """At convergence t = f - mu div p with |p| <= 1 everywhere and
+    p . grad t = -|grad t| where grad t != 0: exactly the optimality
+    conditions of argmin 1/2 ||t - f||^2 + mu TV_iso(t) (checked directly,
+    independently of the iteration's formula). Also TV(t) < TV(f)."""
+    f = _rng(92).standard_normal((2, 8, 8))
+    mu = 0.3
+    t, p = priors.chambolle(f, mu, np.zeros((2, 2, 8, 8)), 20000)
+    assert np.allclose(t, f - mu * priors.div2(p), atol=1e-14)
+    g = priors.grad2(t)
+    ng = np.sqrt(g[0] ** 2 + g[1] ** 2)
+    assert np.max(np.sqrt(p[0] ** 2 + p[1] ** 2)) <= 1.0 + 1e-12
+    on = ng > 1e-4
+    assert np.max(np.abs(p[0] * g[0] + p[1] * g[1] + ng)[on]) < 1e-8
+    assert priors.tv_iso(t) < priors.tv_iso(f)
+    # the objective is lower than at perturbed points
+    obj = lambda z: 0.5 * np.sum((z - f) ** 2) + mu * priors.tv_iso(z)
+    for k in range(5):
+        assert obj(t) <= obj(t + 1e-3 * _rng(93 + k).standard_normal(t.shape))
+
+
+def test_chambolle_large_weight_gives_slice_means():
+    """With a weight far above the total variation the prox is the constant
+    slice mean."""
+    f = _rng(98).standard_normal((1, 6, 6))
+    t, _ = priors.chambolle(f, 100.0, np.zeros((2, 1, 6, 6)), 20000)
+    assert np.allclose(t, f.mean(), atol=1e-6)
+
+
+def test_itv_admm_with_identity_blur_is_the_tv_prox():
+    """With H = I (K = S, delta kernels) the isotropic-TV problem is TV
+    denoising of y with weight lambda / beta; ADMM (T = I, Chambolle t-update)
+    reaches it."""
+    S, N = 2, 8
+    psf = np.zeros((S, S, N, N))
+    for s in range(S):
+        psf[s, s, 0, 0] = 1.0
+    y = _rng(99).standard_normal((S, N, N))
+    lam, beta, rho = 0.2, 1.0, 0.5
+    x, _, _ = admm.AnalysisADMM(psf, "itv2d", lam, rho, beta, tier="freq", inner=50).run(y, 600)
+    ref, _ = priors.chambolle(y, lam / beta, np.zeros((2, S, N, N)), 20000)
+    assert np.allclose(x, ref, atol=1e-6)
+    # isotropic and anisotropic TV give different answers here
+    xa = admm.AnalysisADMM(psf, "tv2d", lam, rho, beta, tier="freq").run(y, 600)[0]
+    assert np.linalg.norm(xa - x) > 1e-3 * np.linalg.norm(x)
