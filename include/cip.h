@@ -75,6 +75,12 @@ typedef enum {
    * along all three dimensions): the orthonormal 2D DCT-II of every plane
    * followed by the orthonormal DCT-II along the plane (band) axis. */
   CIP_PRIOR_DCT3D = 5,
+  /* Isotropic TV of every plane as stated in Section III-A (Phi(Tx) = TV(x)
+   * with T = I): the t-update is the TV proximal map, computed with
+   * Chambolle's projection algorithm (circular forward differences, step
+   * 1/8, `tv_inner` iterations per ADMM iteration, dual warm-started from the
+   * previous ADMM iteration). */
+  CIP_PRIOR_ITV2D = 6,
 } cip_prior_kind;
 
 typedef struct {
@@ -96,6 +102,8 @@ typedef struct {
   double mu;            /* gradient (Tikhonov) weight on the codes, Eq.
                            DL_PriorHP_conv for 2D correlations (forward
                            differences along both axes); 0 = none, >= 0     */
+  /* CIP_PRIOR_ITV2D only:                                                    */
+  int tv_inner;         /* Chambolle iterations per ADMM iteration (0: 20)    */
   /* All priors:                                                             */
   int flags;            /* CIP_PLAN_ADAPTIVE: keep the FP64 kernel spectra
                            resident (K*S*N1*(N2/2+1)*16 more bytes) so that

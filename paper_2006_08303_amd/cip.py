@@ -23,8 +23,10 @@ CIP_PRIOR_DCT2D = 2
 CIP_PRIOR_PATCH = 3
 CIP_PRIOR_CONV2D = 4
 CIP_PRIOR_DCT3D = 5
+CIP_PRIOR_ITV2D = 6
 PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
-          "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D, "dct3d": CIP_PRIOR_DCT3D}
+          "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D, "dct3d": CIP_PRIOR_DCT3D,
+          "itv2d": CIP_PRIOR_ITV2D}
 
 
 class CipError(RuntimeError):
@@ -38,7 +40,8 @@ class _PriorDesc(ctypes.Structure):
                 ("dict", ctypes.c_void_p), ("n_atoms", ctypes.c_int),
                 ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int),
                 ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
-                ("filt_l", ctypes.c_int), ("mu", ctypes.c_double), ("flags", ctypes.c_int)]
+                ("filt_l", ctypes.c_int), ("mu", ctypes.c_double), ("tv_inner", ctypes.c_int),
+                ("flags", ctypes.c_int)]
 
 
 class _AdaptiveParams(ctypes.Structure):
@@ -60,8 +63,9 @@ class _Tuning(ctypes.Structure):
                 ("row_us", ctypes.c_double), ("default_us", ctypes.c_double)]
 
 
-def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0):
-    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu), int(flags))
+def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0, tv_inner=0):
+    d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu),
+                   int(tv_inner), int(flags))
     if dictionary is not None:
         d.dict = ctypes.c_void_p(dictionary.data_ptr())
         d.n_atoms = int(dictionary.shape[1])
@@ -173,7 +177,7 @@ class Plan:
     offset (a - L//2, b - L//2)); mu: gradient (Tikhonov) weight on the codes."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
-                 filters=None, stream=None, mu=0.0, adaptive=False):
+                 filters=None, stream=None, mu=0.0, adaptive=False, tv_inner=0):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
@@ -185,7 +189,8 @@ class Plan:
             if filters is None:
                 raise ValueError("the conv2d prior needs filters")
             _dev_f32(filters, tuple(filters.shape), "filters")
-        desc = _desc(prior, beta, dictionary, filters, mu, CIP_PLAN_ADAPTIVE if adaptive else 0)
+        desc = _desc(prior, beta, dictionary, filters, mu, CIP_PLAN_ADAPTIVE if adaptive else 0,
+                     tv_inner)
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
                                  desc.n_atoms, desc.n_filters, desc.filt_l, desc.flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)

@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 #include "norms.hpp"
+#include "itv.hpp"
 #include "patch_launch.hpp"
 #include "conv_launch.hpp"
 #include "errors.hpp"
@@ -77,6 +78,7 @@ int state_floats_per_voxel(int kind) {
   switch (kind) {
     case CIP_PRIOR_DCT2D: return 1;
     case CIP_PRIOR_DCT3D: return 1;
+    case CIP_PRIOR_ITV2D: return 5;  // u, dual p (2), f, q
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
@@ -166,6 +168,8 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (state_floats_per_voxel(prior->kind) < 0)
     return fail(CIP_EUNSUPPORTED, "unsupported prior kind");
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
+  if (prior->kind == CIP_PRIOR_ITV2D && (prior->tv_inner < 0 || prior->tv_inner > 10000))
+    return fail(CIP_EINVAL, "tv_inner must be in [0, 10000]");
   if (prior->kind == CIP_PRIOR_PATCH) {
     if (!is_pow2(N1) || !is_pow2(N2))
       return fail(CIP_EUNSUPPORTED, "patch prior: power-of-two grids only");
@@ -198,6 +202,7 @@ struct cip_plan_s {
   bool adaptive;        // FP64 spectra resident: the penalty may change in a solve
   int row_np;           // row pairs per work-group of the DCT row pass (2 or 4)
   int row_ppt;          // points per thread of the analysis row passes (default or 8)
+  int tv_inner;         // isotropic TV: Chambolle iterations per ADMM iteration
   template <typename T> T* at(size_t off) const {
     return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
   }
@@ -308,7 +313,43 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
   return hipSuccess;
 }
 
+// Isotropic TV t-update and dual update of pass l (see itv.hpp).
+hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
+  const Layout& L = p->L;
+  const float mu = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
+  const size_t n = (size_t)p->S * p->N1 * p->N2;
+  float* u = p->at<float>(L.state);
+  float* p0 = u + n;
+  float* p1 = p0 + n;
+  float* f = p1 + n;
+  float* q = f + n;
+  const int grid = p->S * (p->N1 / RT);
+  hipError_t e = hipSuccess;
+  DISPATCH_N(p->N2, {
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
+    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), u, f, p0,
+               p1, p->N1, p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
+  });
+  if (e != hipSuccess) return e;
+  const int blocks = (int)((n + 255) / 256);
+  for (int k = 0; k < p->tv_inner; ++k) {
+    e = launch(k_itv_q, blocks, 256, 0, st, p0, p1, f, q, p->N1, p->N2, n, 1.f / mu);
+    if (e != hipSuccess) return e;
+    e = launch(k_itv_p, blocks, 256, 0, st, q, p0, p1, p->N1, p->N2, n, 0.125f);
+    if (e != hipSuccess) return e;
+  }
+  DISPATCH_N(p->N2, {
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
+    return launch(k_itv_finish<NN>, grid, PAIRS * T, lds, st, f, p0, p1, u,
+                  p->at<cx<float>>(L.bufA), p->N1, p->at<const cx<float>>(L.twN2f), mu);
+  });
+  return hipSuccess;
+}
+
 hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
+  if (p->kind == CIP_PRIOR_ITV2D) return itv_row(p, l, st, rho);
   if (is_dct(p))
     return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr, rho, sc);
   return admm_row_tv(p, l, st, rho, sc);
@@ -631,6 +672,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
   p->row_np = PAIRS;
   p->row_ppt = ppt_row_n(N2);
+  p->tv_inner = prior->kind == CIP_PRIOR_ITV2D ? (prior->tv_inner > 0 ? prior->tv_inner : 20) : 0;
 
   auto cleanup_fail = [&](int code, const std::string& m) {
     delete p;
@@ -793,8 +835,8 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (!p || !d_y || !d_x || !prm) return fail(CIP_EINVAL, "NULL argument");
   if (!p->adaptive) return fail(CIP_EINVAL, "plan was not created with CIP_PLAN_ADAPTIVE");
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
-    return fail(CIP_EUNSUPPORTED, "adaptive penalty: analysis priors only");
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
+    return fail(CIP_EUNSUPPORTED, "adaptive penalty: l1 analysis priors only");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
       !(prm->tol >= 0.0))
     return fail(CIP_EINVAL, "need max_iters >= 1, every >= 1, tau > 1, mu > 1, tol >= 0");
@@ -1042,8 +1084,8 @@ int cip_batch_destroy(cip_batch_t b) {
 int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   if (!p || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
-    return fail(CIP_EUNSUPPORTED, "autotuning covers the analysis row passes");
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
+    return fail(CIP_EUNSUPPORTED, "autotuning covers the l1 analysis row passes");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool dct = is_dct(p);
   const int pd = ppt_row_n(p->N2);
@@ -1096,8 +1138,8 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   const bool dct = is_dct(p);
   const int pd = ppt_row_n(p->N2);
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D)
-    return fail(CIP_EUNSUPPORTED, "tuning covers the analysis row passes");
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
+    return fail(CIP_EUNSUPPORTED, "tuning covers the l1 analysis row passes");
   if (!(row_np == PAIRS || (dct && row_np == 2)))
     return fail(CIP_EINVAL, "row_np must be 4 (or 2 for the DCT prior)");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))

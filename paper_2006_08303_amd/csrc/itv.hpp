@@ -1,0 +1,136 @@
+// Isotropic TV prior (Section III-A: Phi(Tx) = TV(x) with T = I, one 2D TV
+// per plane). The x-update is that of a unitary T (tau = 1); the t-update is
+// the TV proximal map of f = x + u with weight mu = lambda / rho, computed with
+// Chambolle's projection algorithm (circular forward differences, step 1/8),
+// whose dual p is kept in the state and warm-starts the next ADMM iteration:
+//   q = div p - f / mu,   p <- (p + tau grad q) / (1 + tau |grad q|),
+//   t = f - mu div p,     u <- u + x - t = f - t,
+// with div p = (p0[n1] - p0[n1-1]) + (p1[n2] - p1[n2-1]) (the negative adjoint
+// of the forward differences). Per ADMM iteration: k_itv_prep (inverse row
+// FFT, f = x + u), `inner` x (k_itv_q, k_itv_p), k_itv_finish (t, u, forward
+// row FFT of t - u for the next column pass).
+// State planes [S][N1][N2] each: u, p0, p1, f, q.
+#pragma once
+#include "kernels.hpp"
+
+namespace cip {
+
+// Inverse row FFT of the column-pass output (x rows), f = x + u; on the
+// first iteration u = 0 and the dual starts at p = 0.
+template <int N2>
+__global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
+k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float* __restrict__ f,
+           float* __restrict__ p0, float* __restrict__ p1, int N1,
+           const cx<float>* __restrict__ twg, int first) {
+  constexpr int PPT = ppt_row<N2>();
+  constexpr int T = N2 / PPT;
+  constexpr int H2 = N2 / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int tiles = N1 / RT;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b / tiles, row0 = (b % tiles) * RT;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+  lds_load_table(tw, twg, N2);
+  tile_to_staging(Yin + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
+  __syncthreads();
+  cx<float> v[PPT];
+  staging_to_pair<N2, PPT>(v, stg, g, t);
+  __syncthreads();
+  fft_group<N2, PPT, -1>(v, cb, t, tw);
+  const size_t oa = ((size_t)s * N1 + row0 + 2 * g) * N2, ob = oa + N2;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = t + T * q;
+    f[oa + n] = v[q].x + (first ? 0.f : u[oa + n]);
+    f[ob + n] = v[q].y + (first ? 0.f : u[ob + n]);
+    if (first) {
+      p0[oa + n] = p0[ob + n] = 0.f;
+      p1[oa + n] = p1[ob + n] = 0.f;
+    }
+  }
+}
+
+// q = div p - f / mu, one thread per pixel of the S planes.
+__global__ void k_itv_q(const float* __restrict__ p0, const float* __restrict__ p1,
+                        const float* __restrict__ f, float* __restrict__ q, int N1, int N2,
+                        size_t n, float inv_mu) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t plane = (size_t)N1 * N2;
+  const size_t base = i - i % plane;
+  const int n1 = (int)((i % plane) / N2), n2 = (int)(i % N2);
+  const size_t up = base + (size_t)(n1 == 0 ? N1 - 1 : n1 - 1) * N2 + n2;
+  const size_t lf = i - n2 + (n2 == 0 ? N2 - 1 : n2 - 1);
+  q[i] = (p0[i] - p0[up]) + (p1[i] - p1[lf]) - f[i] * inv_mu;
+}
+
+// p <- (p + tau grad q) / (1 + tau |grad q|), one thread per pixel.
+__global__ void k_itv_p(const float* __restrict__ q, float* __restrict__ p0,
+                        float* __restrict__ p1, int N1, int N2, size_t n, float tau) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t plane = (size_t)N1 * N2;
+  const size_t base = i - i % plane;
+  const int n1 = (int)((i % plane) / N2), n2 = (int)(i % N2);
+  const size_t dn = base + (size_t)(n1 == N1 - 1 ? 0 : n1 + 1) * N2 + n2;
+  const size_t rt = i - n2 + (n2 == N2 - 1 ? 0 : n2 + 1);
+  const float qc = q[i];
+  const float g0 = q[dn] - qc, g1 = q[rt] - qc;
+  const float inv = 1.f / (1.f + tau * __builtin_sqrtf(g0 * g0 + g1 * g1));
+  p0[i] = (p0[i] + tau * g0) * inv;
+  p1[i] = (p1[i] + tau * g1) * inv;
+}
+
+// t = f - mu div p, u = f - t, and the forward row FFT of t - u (two rows
+// per group) -> RT tile of the next column pass.
+template <int N2>
+__global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
+k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
+             const float* __restrict__ p1, float* __restrict__ u, cx<float>* __restrict__ Gout,
+             int N1, const cx<float>* __restrict__ twg, float mu) {
+  constexpr int PPT = ppt_row<N2>();
+  constexpr int T = N2 / PPT;
+  constexpr int H2 = N2 / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
+  float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int tiles = N1 / RT;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b / tiles, row0 = (b % tiles) * RT;
+  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
+  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+  lds_load_table(tw, twg, N2);
+  const int ra = row0 + 2 * g;
+  const size_t pl = (size_t)s * N1 * N2;
+  cx<float> v[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = t + T * q, nl = n == 0 ? N2 - 1 : n - 1;
+    float o[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int n1 = ra + r, nu = n1 == 0 ? N1 - 1 : n1 - 1;
+      const size_t i = pl + (size_t)n1 * N2 + n;
+      const float dv = (p0[i] - p0[pl + (size_t)nu * N2 + n]) +
+                       (p1[i] - p1[pl + (size_t)n1 * N2 + nl]);
+      const float fi = f[i];
+      const float ti = fi - mu * dv;
+      const float ui = fi - ti;
+      u[i] = ui;
+      o[r] = ti - ui;
+    }
+    v[q] = cx<float>{o[0], o[1]};
+  }
+  __syncthreads();   // twiddle table ready
+  fft_group<N2, PPT, +1>(v, cb, t, tw);
+  pair_to_staging<N2, PPT>(v, cb, stg, g, t);
+  __syncthreads();
+  staging_to_tile(Gout + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
+}
+
+}  // namespace cip

@@ -247,7 +247,10 @@ int cip_server_add_operator(cip_server_t s, int K, int S, int N1, int N2, const 
       int trc = hipMemsetAsync(t, 0, yb, st) == hipSuccess ? CIP_OK : CIP_EHIP;
       if (!trc) trc = cip_solve(plan, reinterpret_cast<float*>(t), 2,
                                 reinterpret_cast<float*>(t + yb), st);
-      if (!trc) trc = cip_plan_autotune(plan, 10, st, nullptr);
+      if (!trc) {
+        trc = cip_plan_autotune(plan, 10, st, nullptr);
+        if (trc == CIP_EUNSUPPORTED) trc = CIP_OK;   // this prior has one row-pass shape
+      }
       if (!trc && hipStreamSynchronize(st) != hipSuccess) trc = CIP_EHIP;
       s->arena->release(toff, yb + xb);
       if (trc) {
