@@ -940,10 +940,13 @@ __device__ __forceinline__ void band_mix(cx<float>* v, cx<float>* buf, const flo
 // band != NULL (3D DCT): the band DCT C_S is applied across the planes after
 // the column DCT of the output and its transpose before the inverse column
 // DCT of the input (it commutes with the per-plane transforms).
-// The solve tables are read inside the solve, not prefetched at kernel start:
-// a prefetch of the Psi^+ row costs about 2 S PPT registers, which lowers the
-// number of resident waves below what a 1024^2 problem needs (measured:
-// 34.6 us with the prefetch, 28.0 us without, K = S = 3).
+// The solve tables (x_hat0, the diagonal and the S - 1 off-diagonal entries
+// of plane g's Psi^+ row) go through a software pipeline of col_depth<S>()
+// frequencies: the first loads are issued with the input loads and ride
+// under the column transforms, and solving frequency q issues the loads of
+// frequency q + depth. A prefetch of all PPT frequencies costs about 2 S PPT
+// registers and lowers the number of resident waves (measured: 34.6 us with
+// it, 28.0 us reading each frequency's tables inside the solve, K = S = 3).
 // LDS: [twiddles N1][DCT table E N1, when it fits][S x padded N1 complex];
 // when the E table does not fit (N1 = 2048 with many planes) it is read
 // from global memory.
@@ -953,6 +956,29 @@ template <int N1, int S> constexpr bool col_e_in_lds() {
 }
 template <int N1, bool DCT, int S> constexpr int col_lds_floats() {
   return 2 * N1 + (DCT && col_e_in_lds<N1, S>() ? 2 * N1 : 0) + S * 2 * padded_len(N1);
+}
+
+// Solve tables of one frequency for plane g.
+template <int S> struct ColTab {
+  cx<float> xh;
+  float dg;
+  cx<float> a[S > 1 ? S - 1 : 1];
+};
+// Frequencies in flight in the table pipeline: about 56 registers' worth,
+// at least 2, at most PPT.
+template <int S, int PPT> constexpr int col_depth() {
+  constexpr int d = 56 / (3 + 2 * (S - 1));
+  return d < 2 ? 2 : (d > PPT ? PPT : d);
+}
+template <int S>
+__device__ __forceinline__ void col_tab_load(ColTab<S>& c, const cx<float>* __restrict__ xh0,
+                                             const float* __restrict__ Adiag,
+                                             const cx<float>* __restrict__ Aoff, size_t gi,
+                                             const size_t (&arow)[S > 1 ? S - 1 : 1], size_t fi) {
+  c.xh = xh0[gi];
+  c.dg = Adiag[gi];
+#pragma unroll
+  for (int jj = 0; jj < S - 1; ++jj) c.a[jj] = Aoff[arow[jj] + fi];
 }
 
 template <int N1, bool DCT, int S>
@@ -989,12 +1015,17 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
     arow[jj] = (size_t)(g < j ? pair_index(g, j, S) : pair_index(j, g, S)) * F;
     asgn[jj] = g < j ? 1.f : -1.f;
   }
+  constexpr int D = col_depth<S, PPT>();
   lds_load_table(tw, twg, N1);
   if (ELDS) lds_load_table(ewl, ewg, N1);
   cx<float> v[PPT];
+  ColTab<S> tb[D];
   if (!zero_in) {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) v[q] = Gin[rt_idx(g, t + T * q, k2, N1, H2)];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      col_tab_load<S>(tb[q], xh0, Adiag, Aoff, (size_t)g * F + f0 + T * q, arow, f0 + T * q);
   }
   __syncthreads();
   if (!zero_in) {
@@ -1009,20 +1040,22 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int k1 = t + T * q;
-      const cx<float> xh = xh0[(size_t)g * F + f0 + T * q];
-      const float dg = Adiag[(size_t)g * F + f0 + T * q];
+      const ColTab<S> c = tb[q % D];
+      if (q + D < PPT)
+        col_tab_load<S>(tb[q % D], xh0, Adiag, Aoff, (size_t)g * F + f0 + T * (q + D), arow,
+                        f0 + T * (q + D));
       cx<float> gg = ldc(cb, k1);
-      cx<float> acc = {xh.x + dg * gg.x, xh.y + dg * gg.y};
+      cx<float> acc = {c.xh.x + c.dg * gg.x, c.xh.y + c.dg * gg.y};
 #pragma unroll
       for (int jj = 0; jj < S - 1; ++jj) {
         const int j = jj < g ? jj : jj + 1;
-        cx<float> a = Aoff[arow[jj] + f0 + T * q];
+        cx<float> a = c.a[jj];
         a.y *= asgn[jj];
         acc = acc + cmul(a, ldc(reinterpret_cast<const cx<float>*>(lds) + j * PL, k1));
       }
       v[q] = acc;
-      // keep the table loads of one frequency at a time (otherwise the
-      // scheduler hoists all of them and runs out of registers)
+      // keep the pipeline depth as written (otherwise the scheduler hoists
+      // every table load and runs out of registers)
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();   // every plane's scratch was read by the solve
