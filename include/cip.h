@@ -134,8 +134,10 @@ int cip_plan_workspace_bytes(int K, int S, int N1, int N2, const cip_prior_desc*
  * as zero (minimum-norm x-update where Psi is singular, e.g. the DC block with
  * unit-sum kernels and TV). Results are stored in FP32 in the workspace.
  *   d_psf      : [K][S][N1][N2] float32 device array, read during the call only.
- *   rho, lambda: ADMM penalty (> 0) and regularisation weight (>= 0); the
- *                soft threshold is lambda / rho (Eq. solt_trans).
+ *   rho, lambda: ADMM penalty (> 0) and regularisation weight (>= 0; > 0
+ *                for CIP_PRIOR_ITV2D); the soft threshold is lambda / rho
+ *                (Eq. solt_trans), the TV proximal weight of CIP_PRIOR_ITV2D
+ *                likewise.
  *   d_workspace: device buffer of at least cip_plan_workspace_bytes bytes,
  *                256-byte aligned, owned by the caller, kept by the plan until
  *                cip_plan_destroy and not touched by the caller meanwhile.

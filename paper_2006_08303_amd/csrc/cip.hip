@@ -78,7 +78,7 @@ int state_floats_per_voxel(int kind) {
   switch (kind) {
     case CIP_PRIOR_DCT2D: return 1;
     case CIP_PRIOR_DCT3D: return 1;
-    case CIP_PRIOR_ITV2D: return 5;  // u, dual p (2), f, q
+    case CIP_PRIOR_ITV2D: return 6;  // u, dual p (2 components, double-buffered), f
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
@@ -313,36 +313,46 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
   return hipSuccess;
 }
 
-// Isotropic TV t-update and dual update of pass l (see itv.hpp).
+// Isotropic TV t-update and dual update of pass l (see itv.hpp). The dual
+// alternates between buffers A and B over the Chambolle launches; pass l
+// starts from the buffer where pass l - 1 left it (A for l = 1, zeroed by the
+// prep kernel).
+constexpr int ITV_KB = 4;   // Chambolle iterations per launch (tile halo)
 hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
   const Layout& L = p->L;
   const float mu = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
   const size_t n = (size_t)p->S * p->N1 * p->N2;
   float* u = p->at<float>(L.state);
-  float* p0 = u + n;
-  float* p1 = p0 + n;
-  float* f = p1 + n;
-  float* q = f + n;
+  float* pd[2][2] = {{u + n, u + 2 * n}, {u + 3 * n, u + 4 * n}};
+  float* f = u + 5 * n;
+  const int nl = (p->tv_inner + ITV_KB - 1) / ITV_KB;
+  const int start = (int)(((long long)(l - 1) * nl) & 1);
   const int grid = p->S * (p->N1 / RT);
   hipError_t e = hipSuccess;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), u, f, p0,
-               p1, p->N1, p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
+    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), u, f,
+               pd[start][0], pd[start][1], p->N1, p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
   });
   if (e != hipSuccess) return e;
-  const int blocks = (int)((n + 255) / 256);
-  for (int k = 0; k < p->tv_inner; ++k) {
-    e = launch(k_itv_q, blocks, 256, 0, st, p0, p1, f, q, p->N1, p->N2, n, 1.f / mu);
-    if (e != hipSuccess) return e;
-    e = launch(k_itv_p, blocks, 256, 0, st, q, p0, p1, p->N1, p->N2, n, 0.125f);
+  const bool t32 = p->N1 % 32 == 0 && p->N2 % 32 == 0;
+  const int ts = t32 ? 32 : 16;
+  const int cgrid = p->S * (p->N1 / ts) * (p->N2 / ts);
+  for (int j = 0; j < nl; ++j) {
+    const int in = (start + j) & 1, out = in ^ 1;
+    const int m = std::min(ITV_KB, p->tv_inner - j * ITV_KB);
+    e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
+                     pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f)
+            : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
+                     pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f);
     if (e != hipSuccess) return e;
   }
+  const int fin = (start + nl) & 1;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    return launch(k_itv_finish<NN>, grid, PAIRS * T, lds, st, f, p0, p1, u,
+    return launch(k_itv_finish<NN>, grid, PAIRS * T, lds, st, f, pd[fin][0], pd[fin][1], u,
                   p->at<cx<float>>(L.bufA), p->N1, p->at<const cx<float>>(L.twN2f), mu);
   });
   return hipSuccess;
@@ -642,6 +652,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   if (rc) return rc;
   if (!d_psf || !d_workspace || !out) return fail(CIP_EINVAL, "NULL pointer argument");
   if (!(rho > 0.0) || !(lambda >= 0.0)) return fail(CIP_EINVAL, "need rho > 0 and lambda >= 0");
+  if (prior->kind == CIP_PRIOR_ITV2D && !(lambda > 0.0))
+    return fail(CIP_EINVAL, "isotropic TV: lambda must be > 0");
   if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
     return fail(CIP_EINVAL, "workspace must be 256-byte aligned");
   if (prior->kind == CIP_PRIOR_PATCH && !prior->dict)

@@ -7,9 +7,11 @@
 //   t = f - mu div p,     u <- u + x - t = f - t,
 // with div p = (p0[n1] - p0[n1-1]) + (p1[n2] - p1[n2-1]) (the negative adjoint
 // of the forward differences). Per ADMM iteration: k_itv_prep (inverse row
-// FFT, f = x + u), `inner` x (k_itv_q, k_itv_p), k_itv_finish (t, u, forward
-// row FFT of t - u for the next column pass).
-// State planes [S][N1][N2] each: u, p0, p1, f, q.
+// FFT, f = x + u), ceil(inner / KB) launches of k_itv_chambolle (up to KB
+// iterations each, in LDS), k_itv_finish (t, u, forward row FFT of t - u for
+// the next column pass).
+// State planes [S][N1][N2] each: u, dual buffer A (p0, p1), dual buffer B
+// (p0, p1), f.
 #pragma once
 #include "kernels.hpp"
 
@@ -54,35 +56,66 @@ k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float
   }
 }
 
-// q = div p - f / mu, one thread per pixel of the S planes.
-__global__ void k_itv_q(const float* __restrict__ p0, const float* __restrict__ p1,
-                        const float* __restrict__ f, float* __restrict__ q, int N1, int N2,
-                        size_t n, float inv_mu) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const size_t plane = (size_t)N1 * N2;
-  const size_t base = i - i % plane;
-  const int n1 = (int)((i % plane) / N2), n2 = (int)(i % N2);
-  const size_t up = base + (size_t)(n1 == 0 ? N1 - 1 : n1 - 1) * N2 + n2;
-  const size_t lf = i - n2 + (n2 == 0 ? N2 - 1 : n2 - 1);
-  q[i] = (p0[i] - p0[up]) + (p1[i] - p1[lf]) - f[i] * inv_mu;
-}
-
-// p <- (p + tau grad q) / (1 + tau |grad q|), one thread per pixel.
-__global__ void k_itv_p(const float* __restrict__ q, float* __restrict__ p0,
-                        float* __restrict__ p1, int N1, int N2, size_t n, float tau) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const size_t plane = (size_t)N1 * N2;
-  const size_t base = i - i % plane;
-  const int n1 = (int)((i % plane) / N2), n2 = (int)(i % N2);
-  const size_t dn = base + (size_t)(n1 == N1 - 1 ? 0 : n1 + 1) * N2 + n2;
-  const size_t rt = i - n2 + (n2 == N2 - 1 ? 0 : n2 + 1);
-  const float qc = q[i];
-  const float g0 = q[dn] - qc, g1 = q[rt] - qc;
-  const float inv = 1.f / (1.f + tau * __builtin_sqrtf(g0 * g0 + g1 * g1));
-  p0[i] = (p0[i] + tau * g0) * inv;
-  p1[i] = (p1[i] + tau * g1) * inv;
+// Up to KB Chambolle iterations on one TS x TS tile of one plane, in LDS
+// (temporal blocking). The tile is loaded with a halo of KB pixels on every
+// side (circular wrap): one iteration makes p at a pixel depend on p within
+// one pixel in each direction, so after m <= KB iterations only the cells
+// within m pixels of the region border are stale, and the TS x TS interior
+// equals what m global iterations give. Reads the dual from
+// (pi0, pi1) and writes the interior to (po0, po1): two buffers, because
+// neighbouring tiles read the halo of the input. Per iteration:
+//   q = div p - f / mu                 at region rows, cols >= 1
+//   p <- (p + tau grad q) / (1 + tau |grad q|)   at rows, cols in [1, W - 2]
+// (no cell reads outside the region; the cells left out never reach the
+// interior). One work-group per (plane, tile).
+template <int TS, int KB>
+__global__ void __launch_bounds__(256)
+k_itv_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
+                const float* __restrict__ pi1, float* __restrict__ po0, float* __restrict__ po1,
+                int N1, int N2, int iters, float inv_mu, float tau) {
+  constexpr int W = TS + 2 * KB;
+  constexpr int R = W * W;
+  __shared__ float P0[R], P1[R], Fv[R], Q[R];
+  const int tx = N2 / TS, ty = N1 / TS;
+  const int s = blockIdx.x / (tx * ty), rem = blockIdx.x % (tx * ty);
+  const int r0 = (rem / tx) * TS - KB, c0 = (rem % tx) * TS - KB;
+  const size_t pl = (size_t)s * N1 * N2;
+  for (int e = threadIdx.x; e < R; e += 256) {
+    const int a = e / W, c = e % W;
+    int gr = (r0 + a) % N1, gc = (c0 + c) % N2;
+    gr += gr < 0 ? N1 : 0;
+    gc += gc < 0 ? N2 : 0;
+    const size_t i = pl + (size_t)gr * N2 + gc;
+    P0[e] = pi0[i];
+    P1[e] = pi1[i];
+    Fv[e] = f[i];
+  }
+  for (int it = 0; it < iters; ++it) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < R; e += 256) {
+      const int a = e / W, c = e % W;
+      if (a >= 1 && c >= 1) Q[e] = (P0[e] - P0[e - W]) + (P1[e] - P1[e - 1]) - Fv[e] * inv_mu;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R; e += 256) {
+      const int a = e / W, c = e % W;
+      if (a >= 1 && c >= 1 && a <= W - 2 && c <= W - 2) {
+        const float qc = Q[e];
+        const float g0 = Q[e + W] - qc, g1 = Q[e + 1] - qc;
+        const float inv = 1.f / (1.f + tau * __builtin_sqrtf(g0 * g0 + g1 * g1));
+        P0[e] = (P0[e] + tau * g0) * inv;
+        P1[e] = (P1[e] + tau * g1) * inv;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TS * TS; e += 256) {
+    const int a = e / TS, c = e % TS;
+    const int l = (a + KB) * W + c + KB;
+    const size_t i = pl + (size_t)(r0 + KB + a) * N2 + (c0 + KB + c);
+    po0[i] = P0[l];
+    po1[i] = P1[l];
+  }
 }
 
 // t = f - mu div p, u = f - t, and the forward row FFT of t - u (two rows

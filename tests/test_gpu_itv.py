@@ -33,7 +33,9 @@ def _problem(kind, N, K, S, cfg=12):
                                                     ("smooth_disk", 128, 3, 3, 8, 10),
                                                     ("rects_gauss", 256, 2, 3, 5, 20),
                                                     ("smooth_disk", 384, 3, 3, 4, 15),
-                                                    ("smooth_disk", 64, 3, 3, 1, 20)])
+                                                    ("smooth_disk", 64, 3, 3, 1, 20),
+                                                    ("rects_gauss", 16, 2, 2, 6, 3),
+                                                    ("smooth_disk", 32, 2, 2, 5, 1)])
 def test_itv_solve_matches_oracle(kind, N, K, S, iters, inner):
     print(f"itv2d {kind} N={N} K={K} S={S} iters={iters} inner={inner}", flush=True)
     x, psf, y = _problem(kind, N, K, S)
@@ -54,3 +56,24 @@ def test_itv_differs_from_anisotropic():
     ga = _np(cip.Plan(_t(psf), "tv2d", rho, lam, 1.0).solve(_t(y), 30))
     assert admm.rel_l2(gi, ref) < 1e-4
     assert admm.rel_l2(ga, gi) > 1e-3
+
+
+def test_itv_repeat_solve_and_odd_launch_count():
+    """inner = 3 takes one Chambolle launch per ADMM iteration, so the dual
+    changes buffer from one iteration to the next; a second solve on the same
+    plan restarts from p = 0 and gives the same x."""
+    x, psf, y = _problem("smooth_disk", 64, 2, 2)
+    lam, rho = 1e-3, 1e-2
+    ref = admm.AnalysisADMM(psf, "itv2d", lam, rho, 1.0, tier="freq", inner=3).run(y, 7)[0]
+    plan = cip.Plan(_t(psf), "itv2d", rho, lam, 1.0, tv_inner=3)
+    a = _np(plan.solve(_t(y), 7))
+    b = _np(plan.solve(_t(y), 7))
+    assert admm.rel_l2(a, ref) < 1e-4
+    assert np.array_equal(a, b)
+
+
+def test_itv_rejects_zero_lambda():
+    psf = np.zeros((1, 1, 32, 32))
+    psf[0, 0, 0, 0] = 1.0
+    with pytest.raises(RuntimeError):
+        cip.Plan(_t(psf), "itv2d", 1e-2, 0.0, 1.0)
