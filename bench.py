@@ -117,12 +117,14 @@ def cpu_baseline(psf, y, lam, rho, beta, n_iter):
                       f"per-solve setup excluded; {dt:.1f} s"}
 
 
-PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0)}
+PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0), "itv2d": (1e-3, 1e-2, 1.0)}
+ITV_INNER = 20   # Chambolle iterations per ADMM iteration (isotropic TV)
 
 
 def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     lam, rho, beta = PRIOR_PARAMS[prior]
-    plan = cip.Plan(psf_t, prior, rho, lam, beta)
+    plan = cip.Plan(psf_t, prior, rho, lam, beta,
+                    **({"tv_inner": ITV_INNER} if prior == "itv2d" else {}))
     # measurements: y = H x + w, H applied by the library, sigma_k for 30 dB
     hx = plan.forward(x_t)
     sig = hx.pow(2).mean(dim=(1, 2)).sqrt() * 10 ** (-30.0 / 20.0)
@@ -131,7 +133,7 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     print(f"[bench] {prior}: N={N} K=S={S} iters={args.iters} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
     plan.solve(y_t, 2, out=out)
-    tuning = plan.autotune(reps=20) if not args.no_autotune else None
+    tuning = plan.autotune(reps=20) if not (args.no_autotune or prior == "itv2d") else None
     print(f"[bench] {prior}: row-pass shape {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.solve(y_t, args.iters, out=out)
@@ -147,8 +149,10 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
           flush=True)
     # per-kernel device time (HIP events recorded on the launch stream)
     times = {w: plan.time_kernel(w, args.kernel_reps) for w in (0, 1)}
-    names = {0: f"row pass ({'k_admm_row_dct' if prior == 'dct2d' else 'k_admm_row_tv'})",
-             1: f"column pass + per-frequency solve (k_admm_col)"}
+    row_name = {"dct2d": "row pass (k_admm_row_dct)", "tv2d": "row pass (k_admm_row_tv)",
+                "itv2d": f"row passes + {ITV_INNER} Chambolle iterations (k_itv_prep, "
+                         f"k_itv_chambolle x {(ITV_INNER + 3) // 4}, k_itv_finish)"}[prior]
+    names = {0: row_name, 1: "column pass + per-frequency solve (k_admm_col)"}
     print(f"[bench] {prior}: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
           flush=True)
     return plan, y_t, lam, rho, beta, value, ms_step, times, names, tuning
@@ -391,6 +395,14 @@ def main():
               "kernels_avg_us": {tv_names[w]: round(tv_times[w], 3) for w in tv_times},
               "algorithmic_bytes_per_launch": {tv_names[w]: algorithmic_bytes(w, S, N, N, "tv2d")
                                                for w in tv_times}}
+    itv = None
+    if not args.no_tv:
+        _, _, _, _, _, itv_value, itv_ms, itv_times, itv_names, _ = run_prior(
+            "itv2d", N, K, S, args, psf_t, x_t, noise_t)
+        itv = {"prior": f"isotropic tv (lambda=1e-3, rho=1e-2, beta=1, {ITV_INNER} Chambolle "
+                        f"iterations per ADMM iteration)", "value": round(itv_value, 1),
+               "ms_per_step": round(itv_ms, 4),
+               "kernels_avg_us": {itv_names[w]: round(itv_times[w], 3) for w in itv_times}}
     if args.copy_calib:
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -439,6 +451,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "tv2d": tv,
+        "itv2d": itv,
         "concurrent_1024": conc,
         "adaptive": adaptive,
         "batch": batch,

@@ -941,7 +941,7 @@ __device__ __forceinline__ void band_mix(cx<float>* v, cx<float>* buf, const flo
 // the column DCT of the output and its transpose before the inverse column
 // DCT of the input (it commutes with the per-plane transforms).
 // The solve tables (x_hat0, the diagonal and the S - 1 off-diagonal entries
-// of plane g's Psi^+ row) go through a software pipeline of col_depth<S>()
+// of plane g's Psi^+ row) go through a software pipeline of col_depth()
 // frequencies: the first loads are issued with the input loads and ride
 // under the column transforms, and solving frequency q issues the loads of
 // frequency q + depth. A prefetch of all PPT frequencies costs about 2 S PPT
@@ -964,11 +964,15 @@ template <int S> struct ColTab {
   float dg;
   cx<float> a[S > 1 ? S - 1 : 1];
 };
-// Frequencies in flight in the table pipeline: about 56 registers' worth,
-// at least 2, at most PPT.
+// Frequencies in flight in the table pipeline (0: each frequency's tables
+// are loaded where they are used). Measured at 1024^2, K = S = 3: 28.4 us
+// with depth 0, 26.5 with 1, 26.2 with 2 or 4, 33.8 with 8 (the prologue
+// loads then delay the first transform).
+#ifndef CIP_COL_DEPTH
+#define CIP_COL_DEPTH 2
+#endif
 template <int S, int PPT> constexpr int col_depth() {
-  constexpr int d = 56 / (3 + 2 * (S - 1));
-  return d < 2 ? 2 : (d > PPT ? PPT : d);
+  return CIP_COL_DEPTH < PPT ? CIP_COL_DEPTH : PPT;
 }
 template <int S>
 __device__ __forceinline__ void col_tab_load(ColTab<S>& c, const cx<float>* __restrict__ xh0,
@@ -1019,7 +1023,7 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   lds_load_table(tw, twg, N1);
   if (ELDS) lds_load_table(ewl, ewg, N1);
   cx<float> v[PPT];
-  ColTab<S> tb[D];
+  ColTab<S> tb[D > 0 ? D : 1];
   if (!zero_in) {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) v[q] = Gin[rt_idx(g, t + T * q, k2, N1, H2)];
@@ -1040,10 +1044,15 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int k1 = t + T * q;
-      const ColTab<S> c = tb[q % D];
-      if (q + D < PPT)
-        col_tab_load<S>(tb[q % D], xh0, Adiag, Aoff, (size_t)g * F + f0 + T * (q + D), arow,
-                        f0 + T * (q + D));
+      ColTab<S> c;
+      if constexpr (D == 0) {
+        col_tab_load<S>(c, xh0, Adiag, Aoff, (size_t)g * F + f0 + T * q, arow, f0 + T * q);
+      } else {
+        c = tb[q % D];
+        if (q + D < PPT)
+          col_tab_load<S>(tb[q % D], xh0, Adiag, Aoff, (size_t)g * F + f0 + T * (q + D), arow,
+                          f0 + T * (q + D));
+      }
       cx<float> gg = ldc(cb, k1);
       cx<float> acc = {c.xh.x + c.dg * gg.x, c.xh.y + c.dg * gg.y};
 #pragma unroll
