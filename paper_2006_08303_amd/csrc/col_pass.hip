@@ -20,8 +20,9 @@ static hipError_t col_n(int S, const cx<float>* Gin, cx<float>* Yout, int H2, co
                         hipStream_t st) {
   const int T = NN / ppt_col<NN>();
   auto run = [&](auto kern, size_t lds_floats) {
-    return launch(kern, H2, S * T, lds_floats * 4, st, Gin, Yout, H2, Adiag, Aoff, xh0, tw, ew,
-                  band, zero_in, dct_out);
+    // H2 - 1 work-groups: columns 0 and N2/2 share one (pair mode)
+    return launch(kern, H2 - 1, S * T, lds_floats * 4, st, Gin, Yout, H2, Adiag, Aoff, xh0, tw,
+                  ew, band, zero_in, dct_out);
   };
   switch (S) {
     case 1: return run(k_admm_col<NN, DCT, 1>, col_lds_floats<NN, DCT, 1>());

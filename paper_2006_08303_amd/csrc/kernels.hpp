@@ -985,13 +985,121 @@ __device__ __forceinline__ void col_tab_load(ColTab<S>& c, const cx<float>* __re
   for (int jj = 0; jj < S - 1; ++jj) c.a[jj] = Aoff[arow[jj] + fi];
 }
 
-template <int N1, bool DCT, int S>
-__global__ void __launch_bounds__(S * (N1 / ppt_col<N1>()))
-k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int H2,
-           const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
-           const cx<float>* __restrict__ xh0, const cx<float>* __restrict__ twg,
-           const cx<float>* __restrict__ ewg, const float* __restrict__ band, int zero_in,
-           int dct_out) {
+// Pair mode of the column pass. The row transforms of real rows are real at
+// k2 = 0 and k2 = N2/2, so those two columns travel as one complex column
+// z = a + i b (one work-group instead of two: H2 - 1 = N2/2 work-groups in
+// all, two per compute unit at N2 = 1024, none left over). After the column
+// transform Z = A + i B with A, B the (Hermitian) spectra of a and b:
+//   A[m] = (Z[m] + conj Z[N-m]) / 2,   B[m] = (Z[m] - conj Z[N-m]) / (2i).
+// The solved spectra XA (column 0 tables) and XB (column N2/2 tables) are
+// Hermitian too, so only m <= N/2 of each is solved: the thread holding
+// frequency m < N/2 solves XA[m], the one holding m >= N/2 solves XB[N-m],
+// and XB[0], XA[N/2] (needed by the thread holding m = 0 and m = N/2, t = 0)
+// are solved by every thread alike.
+// Each thread then takes the missing half from its partner (the thread
+// holding N - m, through LDS) and forms Z'[m] = XA[m] + i XB[m], whose
+// inverse column transform is xa + i xb.
+// In: Z of every plane in LDS (planes p at lds + p PL). Out: v[q] = Z'[t + T q].
+// Ends after the barrier that follows its LDS reads.
+template <int N1, int PPT, int S, int D>
+__device__ __forceinline__ void col_pair_solve(cx<float>* v, const cx<float>* Z, int g, int t,
+                                               size_t F, size_t fb, const cx<float>* __restrict__ xh0,
+                                               const float* __restrict__ Adiag,
+                                               const cx<float>* __restrict__ Aoff,
+                                               const size_t (&arow)[S > 1 ? S - 1 : 1],
+                                               const float (&asgn)[S > 1 ? S - 1 : 1],
+                                               cx<float>* cb, ColTab<S> (&tb)[D > 0 ? D : 1]) {
+  constexpr int T = N1 / PPT;
+  constexpr int PL = padded_len(N1);
+  // table index of slot q: slot q < PPT/2 holds m < N/2 (XA[m], column 0
+  // tables); slot q >= PPT/2 holds m >= N/2 (XB[N - m], column N2/2 tables;
+  // at m = N/2 that is XB[N/2]). tb holds the tables of slots 0 .. D-1
+  // (loaded with the input), as for the other columns.
+  auto fidx = [&](int q) -> size_t {
+    const int m = t + T * q;
+    return 2 * q < PPT ? (size_t)m : fb + (size_t)(m == 0 ? 0 : N1 - m);
+  };
+  // one solve from separated inputs: HALF_A picks (Z[m] + conj Z[r]) / 2,
+  // otherwise (Z[m] - conj Z[r]) / (2i)
+  auto solve = [&](const ColTab<S>& c, int m, int r, bool half_a) {
+    auto sep = [&](int p) {
+      const cx<float> a = ldc(Z + p * PL, m), b = ldc(Z + p * PL, r);
+      if (half_a) return cx<float>{0.5f * (a.x + b.x), 0.5f * (a.y - b.y)};
+      return cx<float>{0.5f * (a.y + b.y), -0.5f * (a.x - b.x)};
+    };
+    const cx<float> u = sep(g);
+    cx<float> acc = {c.xh.x + c.dg * u.x, c.xh.y + c.dg * u.y};
+#pragma unroll
+    for (int jj = 0; jj < S - 1; ++jj) {
+      const int j = jj < g ? jj : jj + 1;
+      cx<float> a = c.a[jj];
+      a.y *= asgn[jj];
+      acc = acc + cmul(a, sep(j));
+    }
+    return acc;
+  };
+  // XB[0] and XA[N/2], needed by thread 0: computed by every lane alike
+  // (uniform addresses)
+  ColTab<S> e0, eh;
+  col_tab_load<S>(e0, xh0, Adiag, Aoff, (size_t)g * F + fb, arow, fb);
+  col_tab_load<S>(eh, xh0, Adiag, Aoff, (size_t)g * F + N1 / 2, arow, (size_t)(N1 / 2));
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int m = t + T * q;
+    const int mr = m == 0 ? 0 : N1 - m;
+    ColTab<S> c;
+    if constexpr (D == 0) {
+      col_tab_load<S>(c, xh0, Adiag, Aoff, (size_t)g * F + fidx(q), arow, fidx(q));
+    } else {
+      c = tb[q % D];
+      if (q + D < PPT)
+        col_tab_load<S>(tb[q % D], xh0, Adiag, Aoff, (size_t)g * F + fidx(q + D), arow,
+                        fidx(q + D));
+    }
+    if (2 * q < PPT) v[q] = solve(c, m, mr, true);   // XA[m]
+    else v[q] = solve(c, mr, m, false);               // XB[N - m]
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const cx<float> xb0 = solve(e0, 0, 0, false);
+  const cx<float> xah = solve(eh, N1 / 2, N1 / 2, true);
+  __syncthreads();   // every plane's Z was read
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int m = t + T * q;
+    const cx<float> P = ldc(cb, m == 0 ? 0 : N1 - m);
+  cx<float> xa, xb;
+    if (q == 0 && t == 0) {
+      xa = v[q];
+      xb = xb0;
+    } else if (2 * q == PPT && t == 0) {
+      xa = xah;
+      xb = v[q];
+    } else if (2 * q < PPT) {
+      xa = v[q];
+      xb = P;
+    } else {
+      xa = conjx(P);
+      xb = conjx(v[q]);
+    }
+    v[q] = cx<float>{xa.x - xb.y, xa.y + xb.x};
+  }
+  __syncthreads();   // partners' values were read before cb is reused
+}
+
+// Body of the column pass for column k2 (PAIR: columns 0 and N2/2 together).
+template <int N1, bool DCT, int S, bool PAIR>
+__device__ __forceinline__ void col_body(const cx<float>* __restrict__ Gin,
+                                         cx<float>* __restrict__ Yout, int H2,
+                                         const float* __restrict__ Adiag,
+                                         const cx<float>* __restrict__ Aoff,
+                                         const cx<float>* __restrict__ xh0,
+                                         const cx<float>* __restrict__ twg,
+                                         const cx<float>* __restrict__ ewg,
+                                         const float* __restrict__ band, int zero_in, int dct_out,
+                                         int k2) {
   constexpr int PPT = ppt_col<N1>();
   constexpr int T = N1 / PPT;
   constexpr int PL = padded_len(N1);
@@ -1001,7 +1109,7 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   cx<float>* ewl = tw + N1;
   const cx<float>* ew = ELDS ? ewl : ewg;
   float* lds = reinterpret_cast<float*>(smem_raw) + (ELDS ? 4 : 2) * N1;
-  const int k2 = xcd_remap(blockIdx.x, gridDim.x);
+  const int kn = H2 - 1;
   // plane index; uniform across a wavefront when a group spans whole waves
   const int g = (T % 64 == 0) ? __builtin_amdgcn_readfirstlane(threadIdx.x / T)
                               : (int)(threadIdx.x / T);
@@ -1025,8 +1133,17 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
   cx<float> v[PPT];
   ColTab<S> tb[D > 0 ? D : 1];
   if (!zero_in) {
+    if constexpr (PAIR) {
+      // columns 0 and N2/2 of a real row transform are real: z = a + i b
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) v[q] = Gin[rt_idx(g, t + T * q, k2, N1, H2)];
+      for (int q = 0; q < PPT; ++q)
+        v[q] = cx<float>{Gin[rt_idx(g, t + T * q, 0, N1, H2)].x,
+                         Gin[rt_idx(g, t + T * q, kn, N1, H2)].x};
+    } else {
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) v[q] = Gin[rt_idx(g, t + T * q, k2, N1, H2)];
+    }
+    // (in pair mode the first D slots also use the column 0 tables)
 #pragma unroll
     for (int q = 0; q < D; ++q)
       col_tab_load<S>(tb[q], xh0, Adiag, Aoff, (size_t)g * F + f0 + T * q, arow, f0 + T * q);
@@ -1041,6 +1158,11 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
 #pragma unroll
     for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
     __syncthreads();
+    if constexpr (PAIR) {
+      static_assert(2 * D <= PPT, "pair mode: the prefetched slots must hold m < N/2");
+      col_pair_solve<N1, PPT, S, D>(v, reinterpret_cast<const cx<float>*>(lds), g, t, F,
+                                    (size_t)kn * N1, xh0, Adiag, Aoff, arow, asgn, cb, tb);
+    } else {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int k1 = t + T * q;
@@ -1068,6 +1190,15 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();   // every plane's scratch was read by the solve
+    }
+  } else if constexpr (PAIR) {
+    const size_t fb = (size_t)kn * N1;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const cx<float> xa = xh0[(size_t)g * F + f0 + T * q];
+      const cx<float> xb = xh0[(size_t)g * F + fb + t + T * q];
+      v[q] = cx<float>{xa.x - xb.y, xa.y + xb.x};
+    }
   } else {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) v[q] = xh0[(size_t)g * F + f0 + T * q];
@@ -1079,8 +1210,35 @@ k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int 
       if (band) band_mix<N1, PPT, S, false>(v, reinterpret_cast<cx<float>*>(lds), band, g, t);
     }
   }
+  if constexpr (PAIR) {
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) Yout[rt_idx(g, t + T * q, k2, N1, H2)] = v[q];
+    for (int q = 0; q < PPT; ++q) {
+      Yout[rt_idx(g, t + T * q, 0, N1, H2)] = cx<float>{v[q].x, 0.f};
+      Yout[rt_idx(g, t + T * q, kn, N1, H2)] = cx<float>{v[q].y, 0.f};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) Yout[rt_idx(g, t + T * q, k2, N1, H2)] = v[q];
+  }
+}
+
+// One work-group per column k2 < N2/2 (H2 - 1 work-groups); the one given
+// k2 = 0 also carries the Nyquist column (col_pair_solve). The two bodies are
+// separate instances so that neither's register allocation sees the other.
+template <int N1, bool DCT, int S>
+__global__ void __launch_bounds__(S * (N1 / ppt_col<N1>()))
+k_admm_col(const cx<float>* __restrict__ Gin, cx<float>* __restrict__ Yout, int H2,
+           const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
+           const cx<float>* __restrict__ xh0, const cx<float>* __restrict__ twg,
+           const cx<float>* __restrict__ ewg, const float* __restrict__ band, int zero_in,
+           int dct_out) {
+  const int k2 = xcd_remap(blockIdx.x, gridDim.x);
+  if (k2 == 0)
+    col_body<N1, DCT, S, true>(Gin, Yout, H2, Adiag, Aoff, xh0, twg, ewg, band, zero_in, dct_out,
+                               0);
+  else
+    col_body<N1, DCT, S, false>(Gin, Yout, H2, Adiag, Aoff, xh0, twg, ewg, band, zero_in, dct_out,
+                                k2);
 }
 
 }  // namespace cip
