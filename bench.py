@@ -151,7 +151,7 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     times = {w: plan.time_kernel(w, args.kernel_reps) for w in (0, 1)}
     row_name = {"dct2d": "row pass (k_admm_row_dct)", "tv2d": "row pass (k_admm_row_tv)",
                 "itv2d": f"row passes + {ITV_INNER} Chambolle iterations (k_itv_prep, "
-                         f"k_itv_chambolle x {(ITV_INNER + 3) // 4}, k_itv_finish)"}[prior]
+                         f"k_itv_chambolle x {(ITV_INNER + 4) // 5}, k_itv_finish)"}[prior]
     names = {0: row_name, 1: "column pass + per-frequency solve (k_admm_col)"}
     print(f"[bench] {prior}: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
           flush=True)

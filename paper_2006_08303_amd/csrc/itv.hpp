@@ -75,36 +75,62 @@ k_itv_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
                 int N1, int N2, int iters, float inv_mu, float tau) {
   constexpr int W = TS + 2 * KB;
   constexpr int R = W * W;
-  __shared__ float P0[R], P1[R], Fv[R], Q[R];
+  // every cell's own values stay in registers (slot k of this thread holds
+  // cell e = threadIdx.x + 256 k); LDS carries what the neighbours read
+  constexpr int NSLOT = (R + 255) / 256;
+  __shared__ float P0[R], P1[R], Q[R];
   const int tx = N2 / TS, ty = N1 / TS;
   const int s = blockIdx.x / (tx * ty), rem = blockIdx.x % (tx * ty);
   const int r0 = (rem / tx) * TS - KB, c0 = (rem % tx) * TS - KB;
   const size_t pl = (size_t)s * N1 * N2;
-  for (int e = threadIdx.x; e < R; e += 256) {
+  float rp0[NSLOT], rp1[NSLOT], rf[NSLOT], rq[NSLOT];
+  // which cells take part in the q and p updates
+  unsigned qm = 0, pm = 0;
+#pragma unroll
+  for (int k = 0; k < NSLOT; ++k) {
+    const int e = threadIdx.x + 256 * k;
     const int a = e / W, c = e % W;
-    int gr = (r0 + a) % N1, gc = (c0 + c) % N2;
-    gr += gr < 0 ? N1 : 0;
-    gc += gc < 0 ? N2 : 0;
-    const size_t i = pl + (size_t)gr * N2 + gc;
-    P0[e] = pi0[i];
-    P1[e] = pi1[i];
-    Fv[e] = f[i];
+    rp0[k] = rp1[k] = rf[k] = rq[k] = 0.f;
+    if (e < R) {
+      // r0 + a lies in [-KB, N1 + KB) and KB < N1 (likewise for columns)
+      int gr = r0 + a, gc = c0 + c;
+      gr += gr < 0 ? N1 : (gr >= N1 ? -N1 : 0);
+      gc += gc < 0 ? N2 : (gc >= N2 ? -N2 : 0);
+      const size_t i = pl + (size_t)gr * N2 + gc;
+      rp0[k] = pi0[i];
+      rp1[k] = pi1[i];
+      rf[k] = f[i];
+      P0[e] = rp0[k];
+      P1[e] = rp1[k];
+      if (a >= 1 && c >= 1) {
+        qm |= 1u << k;
+        if (a <= W - 2 && c <= W - 2) pm |= 1u << k;
+      }
+    }
   }
   for (int it = 0; it < iters; ++it) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < R; e += 256) {
-      const int a = e / W, c = e % W;
-      if (a >= 1 && c >= 1) Q[e] = (P0[e] - P0[e - W]) + (P1[e] - P1[e - 1]) - Fv[e] * inv_mu;
+    __syncthreads();   // P0, P1 hold the current dual
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if ((qm >> k) & 1u) {
+        rq[k] = (rp0[k] - P0[e - W]) + (rp1[k] - P1[e - 1]) - rf[k] * inv_mu;
+        Q[e] = rq[k];
+      }
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < R; e += 256) {
-      const int a = e / W, c = e % W;
-      if (a >= 1 && c >= 1 && a <= W - 2 && c <= W - 2) {
-        const float qc = Q[e];
-        const float g0 = Q[e + W] - qc, g1 = Q[e + 1] - qc;
-        const float inv = 1.f / (1.f + tau * __builtin_sqrtf(g0 * g0 + g1 * g1));
-        P0[e] = (P0[e] + tau * g0) * inv;
-        P1[e] = (P1[e] + tau * g1) * inv;
+    __syncthreads();   // Q complete; P0, P1 no longer read this iteration
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if ((pm >> k) & 1u) {
+        const float g0 = Q[e + W] - rq[k], g1 = Q[e + 1] - rq[k];
+        // hardware square root and reciprocal (about 1 ulp each)
+        const float inv = __builtin_amdgcn_rcpf(
+            1.f + tau * __builtin_amdgcn_sqrtf(g0 * g0 + g1 * g1));
+        rp0[k] = (rp0[k] + tau * g0) * inv;
+        rp1[k] = (rp1[k] + tau * g1) * inv;
+        P0[e] = rp0[k];
+        P1[e] = rp1[k];
       }
     }
   }

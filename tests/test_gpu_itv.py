@@ -35,7 +35,8 @@ def _problem(kind, N, K, S, cfg=12):
                                                     ("smooth_disk", 384, 3, 3, 4, 15),
                                                     ("smooth_disk", 64, 3, 3, 1, 20),
                                                     ("rects_gauss", 16, 2, 2, 6, 3),
-                                                    ("smooth_disk", 32, 2, 2, 5, 1)])
+                                                    ("smooth_disk", 32, 2, 2, 5, 1),
+                                                    ("rects_gauss", 64, 2, 2, 6, 7)])
 def test_itv_solve_matches_oracle(kind, N, K, S, iters, inner):
     print(f"itv2d {kind} N={N} K={K} S={S} iters={iters} inner={inner}", flush=True)
     x, psf, y = _problem(kind, N, K, S)
