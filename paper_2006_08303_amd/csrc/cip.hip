@@ -292,8 +292,9 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
   const size_t buf = (size_t)(band ? 3 : 2) * p->S * p->N1 * p->N2;
   const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
   float* vout = p->at<float>(L.state) + (size_t)(l & 1) * buf;
-  auto run = [&](auto kern, int threads, size_t work_floats, bool use8) {
-    return launch(kern, p->S * (p->N1 / RT), threads, (size_t)(2 * p->N2 + work_floats) * 4, st,
+  auto run = [&](auto kern, int threads, size_t work_floats, bool use8, int parts = 1) {
+    return launch(kern, p->S * (p->N1 / RT) * parts, threads,
+                  (size_t)(2 * p->N2 + work_floats) * 4, st,
                   p->at<const cx<float>>(L.bufB), p->at<cx<float>>(L.bufA), vin, vout, p->S,
                   p->N1, p->at<const cx<float>>(use8 ? L.twN2f8 : L.twN2f), kappa,
                   l == 1 ? 1 : 0, sc);
@@ -307,6 +308,11 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
     if (band)
       return use8 ? run(k_admm_row_tv3<NN, P8>, threads, tv_work_floats<NN>(), true)
                   : run(k_admm_row_tv3<NN, PD>, threads, tv_work_floats<NN>(), false);
+    if (p->row_np == 2) {   // half tiles: 2 own row pairs per work-group
+      const int th2 = 3 * (NN / (use8 ? P8 : PD));
+      return use8 ? run(k_admm_row_tv<NN, P8, 2>, th2, tv_work_floats<NN, 2>(), true, RT / 4)
+                  : run(k_admm_row_tv<NN, PD, 2>, th2, tv_work_floats<NN, 2>(), false, RT / 4);
+    }
     return use8 ? run(k_admm_row_tv<NN, P8>, threads, tv_work_floats<NN>(), true)
                 : run(k_admm_row_tv<NN, PD>, threads, tv_work_floats<NN>(), false);
   });
@@ -1108,7 +1114,7 @@ int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   struct Cand { int np, ppt; };
   std::vector<Cand> cands = {{PAIRS, pd}};
   if (has8) cands.push_back({PAIRS, 8});
-  if (dct) {
+  if (dct || p->kind == CIP_PRIOR_TV2D) {
     cands.push_back({2, pd});
     if (has8) cands.push_back({2, 8});
   }
@@ -1155,8 +1161,8 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
     return fail(CIP_EUNSUPPORTED, "tuning covers the l1 analysis row passes");
-  if (!(row_np == PAIRS || (dct && row_np == 2)))
-    return fail(CIP_EINVAL, "row_np must be 4 (or 2 for the DCT prior)");
+  if (!(row_np == PAIRS || ((dct || p->kind == CIP_PRIOR_TV2D) && row_np == 2)))
+    return fail(CIP_EINVAL, "row_np must be 4 (or 2 for the DCT and TV2D priors)");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))
     return fail(CIP_EINVAL, "row_ppt must be the default or 8 (power-of-two N2)");
   p->row_np = row_np;

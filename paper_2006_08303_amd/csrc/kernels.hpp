@@ -549,14 +549,16 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
 // the halo row of vin. Layout of each buffer: [component][S][N1][N2],
 // component 0 = vertical (n1) difference, 1 = horizontal (n2) difference
 // (2 = band difference for TV3D).
-// LDS: [twiddles N2][work: max(5 group scratches, staging 10 x H2, q arrays)],
-// 76 KB at N2 = 1024 (two work-groups per CU).
-template <int N2> constexpr int tv_work_floats() {
+// LDS: [twiddles N2][work: max(NP + 1 group scratches, staging (2 NP + 2) x
+// H2, q arrays)], 76 KB at N2 = 1024 with NP = 4 (two work-groups per CU),
+// 45 KB with NP = 2 (three).
+template <int N2, int NP = PAIRS> constexpr int tv_work_floats() {
   constexpr int H2 = N2 / 2 + 1;
-  constexpr int fft = (PAIRS + 1) * 2 * padded_len(N2);
-  constexpr int stg = 2 * pad8_len(H2 * (RT + 2));
-  constexpr int xr = (RT + 2) * N2;
-  constexpr int qq = (2 * RT + 1) * N2;   // QV (RT + 1 rows) and QH (RT rows)
+  constexpr int SW = 2 * NP;
+  constexpr int fft = (NP + 1) * 2 * padded_len(N2);
+  constexpr int stg = 2 * pad8_len(H2 * (SW + 2));
+  constexpr int xr = (SW + 2) * N2;
+  constexpr int qq = (2 * SW + 1) * N2;   // QV (SW + 1 rows) and QH (SW rows)
   constexpr int a = fft > stg ? fft : stg;
   constexpr int b = xr > qq ? xr : qq;
   return a > b ? a : b;
@@ -572,33 +574,37 @@ __device__ __forceinline__ void st_off(float* __restrict__ base, unsigned off, f
   *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (off << 2)) = v;
 }
 
-// Steps shared by the TV row passes (TV2D and TV3D), for plane s and the row
-// tile starting at row0. Group g < PAIRS owns rows row0 + 2g, row0 + 2g + 1
-// (local rows 1 + 2g, 2 + 2g of the LDS row block, whose row 0 is the halo
-// row r0 - 1); group PAIRS only transforms the halo pair.
-template <int N2, int PPT_ = ppt_row<N2>()> struct TvGeo {
+// Steps shared by the TV row passes (TV2D and TV3D), for plane s and the SW =
+// 2 NP own rows starting at rb (rows r0 .. r0 + SW - 1 of the RT-row tile at
+// row0, rb = row0 + r0). Group g < NP owns rows rb + 2g, rb + 2g + 1 (local
+// rows 1 + 2g, 2 + 2g of the LDS row block, whose row 0 is the halo row
+// rb - 1); group NP only transforms the halo pair.
+template <int N2, int PPT_ = ppt_row<N2>(), int NP_ = PAIRS> struct TvGeo {
   static constexpr int PPT = PPT_;
+  static constexpr int NP = NP_;
+  static constexpr int SW = 2 * NP;
   static constexpr int T = N2 / PPT;
   static constexpr int H2 = N2 / 2 + 1;
-  static constexpr int NR = RT + 2;                // rows in LDS: halo, RT own rows, halo
-  static constexpr unsigned NT = (PAIRS + 1) * T;  // threads per work-group
-  static constexpr int NE = (RT + 1) * N2;         // state elements: halo row + own rows
+  static constexpr int NR = SW + 2;                // rows in LDS: halo, SW own rows, halo
+  static constexpr unsigned NT = (NP + 1) * T;     // threads per work-group
+  static constexpr int NE = (SW + 1) * N2;         // state elements: halo row + own rows
   static constexpr int PER = (NE + NT - 1) / NT;
 };
 
-// Stage rows r0-1 .. r0+RT of plane s ([k2][NR] order); own rows come from
-// one tile, the two halo rows from the neighbouring tiles.
-template <int N2, int PPT_ = ppt_row<N2>()>
+// Stage rows rb-1 .. rb+SW of plane s ([k2][NR] order), rb = row0 + r0; own
+// rows come from the tile at row0, the two halo rows from wherever they lie.
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
 __device__ __forceinline__ void tv_stage_rows(const cx<float>* __restrict__ Yin, cx<float>* stg,
-                                              int s, int row0, int N1) {
-  using G = TvGeo<N2, PPT_>;
-  constexpr int H2 = G::H2, NR = G::NR;
+                                              int s, int row0, int N1, int r0 = 0) {
+  using G = TvGeo<N2, PPT_, NP>;
+  constexpr int H2 = G::H2, NR = G::NR, SW = G::SW;
   const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
-  for (int i = threadIdx.x; i < H2 * RT; i += blockDim.x) {
-    const int k2 = i / RT, r = i % RT;
-    stg[pad8(k2 * NR + r + 1)] = tile[i];
+  for (int i = threadIdx.x; i < H2 * SW; i += blockDim.x) {
+    const int k2 = i / SW, r = i % SW;
+    stg[pad8(k2 * NR + r + 1)] = tile[k2 * RT + r0 + r];
   }
-  const int lo = (row0 - 1 + N1) % N1, hi = (row0 + RT) % N1;
+  const int rb = row0 + r0;
+  const int lo = (rb - 1 + N1) % N1, hi = (rb + SW) % N1;
   for (int i = threadIdx.x; i < 2 * H2; i += blockDim.x) {
     const int k2 = i % H2, h = i / H2;
     const int r = h ? NR - 1 : 0;
@@ -608,11 +614,12 @@ __device__ __forceinline__ void tv_stage_rows(const cx<float>* __restrict__ Yin,
 
 // Load the vertical / horizontal state this thread updates in tv_spatial
 // (issued early so that the latency overlaps the transforms).
-template <int N2, int PPT_ = ppt_row<N2>()>
-__device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float (&pov)[TvGeo<N2, PPT_>::PER],
-                                            float (&poh)[TvGeo<N2, PPT_>::PER], unsigned s, int row0,
-                                            int N1, unsigned cstride, int first) {
-  using G = TvGeo<N2, PPT_>;
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
+__device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin,
+                                            float (&pov)[TvGeo<N2, PPT_, NP>::PER],
+                                            float (&poh)[TvGeo<N2, PPT_, NP>::PER], unsigned s,
+                                            int row0, int N1, unsigned cstride, int first) {
+  using G = TvGeo<N2, PPT_, NP>;
   const unsigned plane = (unsigned)N1 * N2;
 #pragma unroll
   for (int it = 0; it < G::PER; ++it) {
@@ -631,10 +638,10 @@ __device__ __forceinline__ void tv_prefetch(const float* __restrict__ vin, float
 
 // Inverse row FFTs of the staged rows (two rows per group); x rows -> X =
 // lds [NR][N2]. Begins after the staging writes and ends with a barrier.
-template <int N2, int PPT_ = ppt_row<N2>()>
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
 __device__ __forceinline__ void tv_inverse_rows(const cx<float>* stg, cx<float>* cb,
                                                 const cx<float>* tw, float* X, int g, int t) {
-  using G = TvGeo<N2, PPT_>;
+  using G = TvGeo<N2, PPT_, NP>;
   constexpr int PPT = G::PPT, T = G::T, NR = G::NR;
   __syncthreads();
   cx<float> v[PPT];
@@ -662,14 +669,14 @@ __device__ __forceinline__ void tv_inverse_rows(const cx<float>* stg, cx<float>*
 // From X: state update of the vertical / horizontal components for the halo
 // row (vertical only, not stored) and the own rows, q = 2 soft(v) - v, and
 // the spatial part of T^T q for the own rows into v (two rows per group,
-// zero for group PAIRS). Overwrites X; ends with a barrier.
-template <int N2, int PPT_ = ppt_row<N2>()>
-__device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<N2, PPT_>::PER],
-                                           const float (&poh)[TvGeo<N2, PPT_>::PER],
+// zero for group NP). Overwrites X; ends with a barrier.
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
+__device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<N2, PPT_, NP>::PER],
+                                           const float (&poh)[TvGeo<N2, PPT_, NP>::PER],
                                            float* __restrict__ vout, unsigned s, int row0, int N1,
                                            unsigned cstride, float kappa, float sc, int g, int t,
                                            cx<float> (&v)[PPT_]) {
-  using G = TvGeo<N2, PPT_>;
+  using G = TvGeo<N2, PPT_, NP>;
   constexpr int PPT = G::PPT, T = G::T, PER = G::PER;
   const unsigned plane = (unsigned)N1 * N2;
   const float* X = lds;
@@ -709,12 +716,12 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
     }
   }
   __syncthreads();
-  // QV [RT + 1][N2] (row 0 = halo); QH holds local rows 1 .. RT, stored
-  // right after QV (QH[e] for e >= N2 lands in [(RT + 1) N2, (2 RT + 1) N2)),
+  // QV [SW + 1][N2] (row 0 = halo); QH holds local rows 1 .. SW, stored
+  // right after QV (QH[e] for e >= N2 lands in [(SW + 1) N2, (2 SW + 1) N2)),
   // so that the work region stays below half of the CU's LDS and two
   // work-groups fit on a CU
   float* QV = lds;
-  float* QH = lds + RT * N2;
+  float* QH = lds + G::SW * N2;
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
     const unsigned e = threadIdx.x + it * G::NT;
@@ -724,7 +731,7 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
     }
   }
   __syncthreads();
-  const bool active = g < PAIRS;
+  const bool active = g < NP;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int n2 = t + T * q;
@@ -741,13 +748,15 @@ __device__ __forceinline__ void tv_spatial(float* lds, const float (&pov)[TvGeo<
 }
 
 // Forward row FFT of v (two rows per group), split into the half spectra of
-// the two rows, staged and written as the RT tile at `tile`.
-template <int N2, int PPT_ = ppt_row<N2>()>
+// the two rows, staged and written as rows r0 .. r0 + SW - 1 of the RT tile
+// at `tile`.
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
 __device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[PPT_], float* lds,
                                                 cx<float>* cb, const cx<float>* tw,
-                                                cx<float>* __restrict__ tile, int g, int t) {
-  using G = TvGeo<N2, PPT_>;
-  constexpr int PPT = G::PPT, T = G::T, H2 = G::H2;
+                                                cx<float>* __restrict__ tile, int g, int t,
+                                                int r0 = 0) {
+  using G = TvGeo<N2, PPT_, NP>;
+  constexpr int PPT = G::PPT, T = G::T, H2 = G::H2, SW = G::SW;
   fft_group<N2, PPT, +1>(v, cb, t, tw);
   cx<float>* ostg = reinterpret_cast<cx<float>*>(lds);
   {
@@ -768,12 +777,12 @@ __device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[PPT_], float* lds
       }
     }
     __syncthreads();
-    if (g < PAIRS) {
+    if (g < NP) {
 #pragma unroll
       for (int q = 0; q < QH2; ++q) {
         int k = t + T * q;
         if (k <= N2 / 2) {
-          int i = k * RT + 2 * g;
+          int i = k * SW + 2 * g;
           ostg[pad8(i)] = A[q];
           ostg[pad8(i + 1)] = B[q];
         }
@@ -781,33 +790,39 @@ __device__ __forceinline__ void tv_forward_rows(cx<float> (&v)[PPT_], float* lds
     }
   }
   __syncthreads();
-  staging_to_tile(tile, ostg, H2 * RT);
+  staging_to_subtile<SW>(tile, ostg, H2, r0);
 }
 
-template <int N2, int PPT_ = ppt_row<N2>()>
-__global__ void __launch_bounds__((PAIRS + 1) * (N2 / PPT_))
+// NP own row pairs per work-group (4: whole RT-row tiles; 2: half tiles,
+// twice the work-groups, which spreads a 1024^2 x 3 problem evenly over the
+// compute units at the cost of more halo rows).
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
+__global__ void __launch_bounds__((NP + 1) * (N2 / PPT_))
 k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
               const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
               const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
-  using G = TvGeo<N2, PPT_>;
+  using G = TvGeo<N2, PPT_, NP>;
+  constexpr int PARTS = RT / G::SW;   // work-groups per RT-row tile
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
   float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
   const int g = threadIdx.x / G::T, t = threadIdx.x % G::T;
   const int tiles = N1 / RT;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = b / tiles, row0 = (b % tiles) * RT;
+  const int s = b / (tiles * PARTS), rem = b % (tiles * PARTS);
+  const int row0 = (rem / PARTS) * RT, r0 = (rem % PARTS) * G::SW;
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   const unsigned cstride = (unsigned)S * N1 * N2;   // component stride within a buffer
   lds_load_table(tw, twg, N2);
-  tv_stage_rows<N2, PPT_>(Yin, stg, s, row0, N1);
+  tv_stage_rows<N2, PPT_, NP>(Yin, stg, s, row0, N1, r0);
   float pov[G::PER], poh[G::PER];
-  tv_prefetch<N2, PPT_>(vin, pov, poh, s, row0, N1, cstride, first);
-  tv_inverse_rows<N2, PPT_>(stg, cb, tw, lds, g, t);
+  tv_prefetch<N2, PPT_, NP>(vin, pov, poh, s, row0 + r0, N1, cstride, first);
+  tv_inverse_rows<N2, PPT_, NP>(stg, cb, tw, lds, g, t);
   cx<float> v[G::PPT];
-  tv_spatial<N2, PPT_>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
-  tv_forward_rows<N2, PPT_>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
+  tv_spatial<N2, PPT_, NP>(lds, pov, poh, vout, s, row0 + r0, N1, cstride, kappa, sc, g, t, v);
+  tv_forward_rows<N2, PPT_, NP>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t,
+                                r0);
 }
 
 // Row pass of the TV3D prior: T adds the band difference w_b[s] = x[s+1] -

@@ -162,6 +162,9 @@ def test_rectangular_grid(prior):
         plan = cip.Plan(_t(psf), prior, rho, lam, 1.0)
         got = _np(plan.solve(_t(y), 12))
         assert admm.rel_l2(got, ref) < 1e-4, (N1, N2)
+        plan.set_tuning(2, 16)   # half-tile row pass
+        got = _np(plan.solve(_t(y), 12))
+        assert admm.rel_l2(got, ref) < 1e-4, (N1, N2, "np=2")
 
 
 def test_tv2d_full_size_1024():
