@@ -278,7 +278,7 @@ int cip_server_destroy(cip_server_t server);
 /* ---- autotuning -------------------------------------------------------
  * Times the available shapes of the analysis row pass on this plan's own
  * data and keeps the fastest for all later solves of the plan: the number of
- * row pairs per work-group (4 or 2; DCT and TV2D priors) and the points per thread of
+ * row pairs per work-group (4 or 2) and the points per thread of
  * the row transforms (the default radix sequence, or 8 points per thread,
  * i.e. radices 8, 8, ..., for power-of-two N2), `reps` launches each with HIP
  * events on `stream`. The plan must have run cip_solve once; the solve state
@@ -293,7 +293,7 @@ typedef struct {
 } cip_tuning;
 int cip_plan_autotune(cip_plan_t plan, int reps, void* stream, cip_tuning* out);
 /* Set the row-pass shape directly (values as chosen by cip_plan_autotune:
- * row_np 4, or 2 for the DCT and TV2D priors; row_ppt the default or 8). */
+ * row_np 4 or 2; row_ppt the default or 8). */
 int cip_plan_set_tuning(cip_plan_t plan, int row_np, int row_ppt);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -305,14 +305,17 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
     constexpr int P8 = ((NN & (NN - 1)) == 0 && NN >= 16 && NN <= 1024) ? 8 : PD;
     const bool use8 = p->row_ppt == 8 && P8 != PD;   // tuning variant
     const int threads = (PAIRS + 1) * (NN / (use8 ? P8 : PD));
-    if (band)
-      return use8 ? run(k_admm_row_tv3<NN, P8>, threads, tv_work_floats<NN>(), true)
-                  : run(k_admm_row_tv3<NN, PD>, threads, tv_work_floats<NN>(), false);
     if (p->row_np == 2) {   // half tiles: 2 own row pairs per work-group
       const int th2 = 3 * (NN / (use8 ? P8 : PD));
+      if (band)
+        return use8 ? run(k_admm_row_tv3<NN, P8, 2>, th2, tv_work_floats<NN, 2>(), true, RT / 4)
+                    : run(k_admm_row_tv3<NN, PD, 2>, th2, tv_work_floats<NN, 2>(), false, RT / 4);
       return use8 ? run(k_admm_row_tv<NN, P8, 2>, th2, tv_work_floats<NN, 2>(), true, RT / 4)
                   : run(k_admm_row_tv<NN, PD, 2>, th2, tv_work_floats<NN, 2>(), false, RT / 4);
     }
+    if (band)
+      return use8 ? run(k_admm_row_tv3<NN, P8>, threads, tv_work_floats<NN>(), true)
+                  : run(k_admm_row_tv3<NN, PD>, threads, tv_work_floats<NN>(), false);
     return use8 ? run(k_admm_row_tv<NN, P8>, threads, tv_work_floats<NN>(), true)
                 : run(k_admm_row_tv<NN, PD>, threads, tv_work_floats<NN>(), false);
   });
@@ -1114,7 +1117,7 @@ int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   struct Cand { int np, ppt; };
   std::vector<Cand> cands = {{PAIRS, pd}};
   if (has8) cands.push_back({PAIRS, 8});
-  if (dct || p->kind == CIP_PRIOR_TV2D) {
+  {   // half-tile row passes (all l1 analysis priors)
     cands.push_back({2, pd});
     if (has8) cands.push_back({2, 8});
   }
@@ -1161,8 +1164,7 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
     return fail(CIP_EUNSUPPORTED, "tuning covers the l1 analysis row passes");
-  if (!(row_np == PAIRS || ((dct || p->kind == CIP_PRIOR_TV2D) && row_np == 2)))
-    return fail(CIP_EINVAL, "row_np must be 4 (or 2 for the DCT and TV2D priors)");
+  if (!(row_np == PAIRS || row_np == 2)) return fail(CIP_EINVAL, "row_np must be 4 or 2");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))
     return fail(CIP_EINVAL, "row_ppt must be the default or 8 (power-of-two N2)");
   p->row_np = row_np;

@@ -834,35 +834,37 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
 // by the work-groups of planes s and s + 1 (same inputs, same arithmetic);
 // only the former stores the band state of plane s.
 // State buffer layout [3][S][N1][N2] (vertical, horizontal, band).
-template <int N2, int PPT_ = ppt_row<N2>()>
-__global__ void __launch_bounds__((PAIRS + 1) * (N2 / PPT_))
+template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
+__global__ void __launch_bounds__((NP + 1) * (N2 / PPT_))
 k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
                const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
                const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
-  using G = TvGeo<N2, PPT_>;
+  using G = TvGeo<N2, PPT_, NP>;
   constexpr int PPT = G::PPT, T = G::T;
+  constexpr int PARTS = RT / G::SW;   // work-groups per RT-row tile
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
   float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tiles = N1 / RT;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = b / tiles, row0 = (b % tiles) * RT;
+  const int s = b / (tiles * PARTS), rem = b % (tiles * PARTS);
+  const int row0 = (rem / PARTS) * RT, r0 = (rem % PARTS) * G::SW, rb = row0 + r0;
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   const unsigned plane = (unsigned)N1 * N2;
   const unsigned cstride = (unsigned)S * plane;
-  const bool active = g < PAIRS;
-  // own elements of this thread: rows row0 + 2g, row0 + 2g + 1 at columns
+  const bool active = g < NP;
+  // own elements of this thread: rows rb + 2g, rb + 2g + 1 at columns
   // t + T q (local LDS rows 1 + 2g, 2 + 2g)
-  const unsigned oa = (unsigned)(row0 + 2 * g) * N2 + t;
+  const unsigned oa = (unsigned)(rb + 2 * g) * N2 + t;
   const float* Xa = lds + (1 + 2 * g) * N2 + t;
   const float* Xb = Xa + N2;
   lds_load_table(tw, twg, N2);
-  tv_stage_rows<N2, PPT_>(Yin, stg, s, row0, N1);
+  tv_stage_rows<N2, PPT_, NP>(Yin, stg, s, row0, N1, r0);
   float pov[G::PER], poh[G::PER];
-  tv_prefetch<N2, PPT_>(vin, pov, poh, s, row0, N1, cstride, first);
-  tv_inverse_rows<N2, PPT_>(stg, cb, tw, lds, g, t);
+  tv_prefetch<N2, PPT_, NP>(vin, pov, poh, s, rb, N1, cstride, first);
+  tv_inverse_rows<N2, PPT_, NP>(stg, cb, tw, lds, g, t);
   float xa[PPT], xb[PPT];   // x of plane s, own elements
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -870,13 +872,13 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     xb[q] = active ? Xb[T * q] : 0.f;
   }
   cx<float> v[PPT];
-  tv_spatial<N2, PPT_>(lds, pov, poh, vout, s, row0, N1, cstride, kappa, sc, g, t, v);
+  tv_spatial<N2, PPT_, NP>(lds, pov, poh, vout, s, rb, N1, cstride, kappa, sc, g, t, v);
   // band terms: first + q_b[s-1] (from plane s-1), then - q_b[s] (plane s+1)
   for (int d = 0; d < 2; ++d) {
     const int sn = d == 0 ? s - 1 : s + 1;   // neighbouring plane
     if (sn < 0 || sn >= S) continue;         // uniform over the work-group
-    tv_stage_rows<N2, PPT_>(Yin, stg, sn, row0, N1);
-    tv_inverse_rows<N2, PPT_>(stg, cb, tw, lds, g, t);
+    tv_stage_rows<N2, PPT_, NP>(Yin, stg, sn, row0, N1, r0);
+    tv_inverse_rows<N2, PPT_, NP>(stg, cb, tw, lds, g, t);
     const unsigned bo = 2 * cstride + (unsigned)(d == 0 ? s - 1 : s) * plane + oa;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -910,7 +912,8 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     }
     __syncthreads();   // X is read above; the next staging overwrites it
   }
-  tv_forward_rows<N2, PPT_>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t);
+  tv_forward_rows<N2, PPT_, NP>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t,
+                                r0);
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j

@@ -38,7 +38,8 @@ PARAMS = {"dct2d": (1e-2, 0.1), "tv2d": (1e-3, 1e-2), "tv3d": (1e-3, 1e-2)}
     ("tv2d", 256, [(4, 16), (4, 8), (2, 16), (2, 8)]),
     ("tv2d", 16, [(4, 16), (2, 16), (2, 8)]),
     ("tv2d", 384, [(4, 12), (2, 12)]),
-    ("tv3d", 128, [(4, 16), (4, 8)]),
+    ("tv3d", 128, [(4, 16), (4, 8), (2, 16), (2, 8)]),
+    ("tv3d", 16, [(2, 16)]),
 ])
 def test_every_shape_matches_oracle(prior, N, shapes):
     K, S = 3, 3
@@ -73,9 +74,6 @@ def test_autotune_keeps_results(prior, N, S):
 def test_set_tuning_rejects_bad_shapes():
     x, psf, y = _problem(64, 2, 2)
     tv = cip.Plan(_t(psf), "tv2d", 1e-2, 1e-3, 1.0)
-    tv3 = cip.Plan(_t(psf), "tv3d", 1e-2, 1e-3, 1.0)
-    with pytest.raises(cip.CipError):
-        tv3.set_tuning(2, 16)           # row pairs are fixed for TV3D
     with pytest.raises(cip.CipError):
         tv.set_tuning(3, 16)
     with pytest.raises(cip.CipError):
