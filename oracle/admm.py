@@ -266,16 +266,24 @@ def sherman_morrison(theta, c, rho):
 
 class ConvADMM:
     """Algorithm 2 with a common 2D convolutional dictionary for every band
-    (P = I, c_P = 1). Codes z, t, u have shape (M, S, N1, N2). mu > 0 adds
+    (P = I, c_P = 1), or with 3D filters and codes (dims=3). Codes z, t, u
+    have shape (M, S, N1, N2). mu > 0 adds
     the gradient (Tikhonov) term of Eq. DL_PriorHP_conv; the z-update normal
     equation then gains mu sum_i R_i^H R_i on its left-hand side (stated
     below Eq. solz), diagonal in frequency with symbol psi(w)."""
 
-    def __init__(self, psf, filters, lam, rho, beta, tier="auto", mu=0.0):
+    def __init__(self, psf, filters, lam, rho, beta, tier="auto", mu=0.0, dims=2):
         K, S, N1, N2 = psf.shape
         self.psf = psf
         self.S, self.N1, self.N2 = S, N1, N2
-        self.cd = priors.ConvDict2D(np.asarray(filters, dtype=np.float64), S, N1, N2)
+        self.dims = int(dims)
+        if self.dims == 3:
+            # 3D filters (M, S, L, L) and codes: every operator is diagonal
+            # in the 3D DFT over (band, n1, n2)
+            assert mu == 0.0, "the gradient term is defined here for 2D codes only"
+            self.cd = priors.ConvDict3D(np.asarray(filters, dtype=np.float64), S, N1, N2)
+        else:
+            self.cd = priors.ConvDict2D(np.asarray(filters, dtype=np.float64), S, N1, N2)
         self.M = self.cd.M
         self.lam, self.rho, self.beta = float(lam), float(rho), float(beta)
         self.tier = _tier(S, N1, N2, tier)
@@ -290,6 +298,10 @@ class ConvADMM:
     def synth(self, z):
         if self.tier == "dense":
             return self.cd.synth(z)
+        if self.dims == 3:
+            zh = np.fft.fftn(z, axes=(1, 2, 3))
+            return np.ascontiguousarray(np.real(np.fft.ifftn(
+                np.einsum("msab,msab->sab", self.theta, zh), axes=(0, 1, 2))))
         zh = np.fft.fft2(z, axes=(-2, -1))
         return np.ascontiguousarray(np.real(np.fft.ifft2(
             np.einsum("mab,msab->sab", self.theta, zh), axes=(-2, -1))))
@@ -304,6 +316,13 @@ class ConvADMM:
         """Eq. solz_DFT: c = Theta^H F x + rho F (t - u), then Sherman-Morrison
         per frequency and per band (diagonal rho + mu psi(w)), then inverse
         DFT."""
+        if self.dims == 3:
+            # the same Sherman-Morrison solve at every 3D frequency
+            xh = np.fft.fftn(x, axes=(0, 1, 2))                  # (S, N1, N2)
+            gh = np.fft.fftn(t - u, axes=(1, 2, 3))              # (M, S, N1, N2)
+            c = np.conj(self.theta) * xh[None] + self.rho * gh
+            v = sherman_morrison(self.theta, c, self.rho)
+            return np.ascontiguousarray(np.real(np.fft.ifftn(v, axes=(1, 2, 3))))
         xh = np.fft.fft2(x, axes=(-2, -1))                       # (S, N1, N2)
         gh = np.fft.fft2(t - u, axes=(-2, -1))                   # (M, S, N1, N2)
         c = np.conj(self.theta)[:, None] * xh[None] + self.rho * gh

@@ -16,7 +16,8 @@
   sum_m d_m * z_{m,s} with a common set of L x L filters (the 2D-correlation
   variant of Eq. conv_dic, Section III-B.2), optionally with gradient
   (Tikhonov) regularisation of the codes (Eq. DL_PriorHP_conv, 2D case:
-  gradients along the first and second image axes).
+  gradients along the first and second image axes); and with 3D filters and
+  codes (circular along the bands too, diagonal in the 3D DFT).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
@@ -297,6 +298,47 @@ class ConvDict2D:
     def spectra(self) -> np.ndarray:
         """theta_m = 2D DFT of the grid-placed filters, shape (M, N1, N2)."""
         return np.fft.fft2(self.h)
+
+
+class ConvDict3D:
+    """Convolutional dictionary with 3D filters for data correlated along the
+    bands too (Eq. conv_dic with 3D signals; Section IV-B writes each filter's
+    convolution matrix as diagonal in the 3D DFT): x = sum_m d_m (*) z_m, a
+    circular 3D convolution over (band, n1, n2) of the S x N1 x N2 code z_m
+    with the S x L x L filter d_m. Band tap s' sits at band offset s' and
+    spatial tap (a, b) at offset (a - L//2, b - L//2); P = I."""
+
+    def __init__(self, filters: np.ndarray, S: int, N1: int, N2: int):
+        M, Sf = filters.shape[:2]
+        assert Sf == S, "3D filters span the S bands"
+        self.M = M
+        self.S, self.N1, self.N2 = S, N1, N2
+        self.h = np.stack([np.stack([filter_on_grid(filters[m, sp], N1, N2) for sp in range(S)])
+                           for m in range(M)])                   # (M, S, N1, N2)
+
+    def synth(self, z: np.ndarray) -> np.ndarray:
+        """D~ z, z of shape (M, S, N1, N2) -> (S, N1, N2), spatial convolutions:
+        x[s] = sum_m sum_s' h_m[s'] * z_m[(s - s') mod S]."""
+        out = np.zeros((self.S, self.N1, self.N2))
+        for m in range(self.M):
+            for s in range(self.S):
+                for sp in range(self.S):
+                    out[s] += conv_circ(z[m, (s - sp) % self.S], self.h[m, sp])
+        return out
+
+    def analysis(self, x: np.ndarray) -> np.ndarray:
+        """D~^T x -> (M, S, N1, N2): z_m[s] = sum_s' corr(x[(s + s') mod S], h_m[s'])."""
+        z = np.zeros((self.M, self.S, self.N1, self.N2))
+        for m in range(self.M):
+            for s in range(self.S):
+                for sp in range(self.S):
+                    z[m, s] += corr_circ(x[(s + sp) % self.S], self.h[m, sp])
+        return z
+
+    def spectra(self) -> np.ndarray:
+        """theta_m = 3D DFT of the grid-placed filters, shape (M, S, N1, N2)
+        (band frequency first)."""
+        return np.fft.fftn(self.h, axes=(1, 2, 3))
 
 
 def gradient_filters_2d(N1: int, N2: int):

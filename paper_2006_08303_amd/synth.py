@@ -36,6 +36,7 @@ __all__ = [
     "unit_noise",
     "random_unit_atoms",
     "random_unit_filters",
+    "random_unit_filters_3d",
     "problem",
 ]
 
@@ -174,6 +175,13 @@ def random_unit_filters(rng: np.random.Generator, M: int, L: int) -> np.ndarray:
     f = rng.standard_normal((M, L, L))
     f /= np.linalg.norm(f.reshape(M, -1), axis=1)[:, None, None]
     return f
+
+def random_unit_filters_3d(rng: np.random.Generator, M: int, S: int, L: int) -> np.ndarray:
+    """M random S x L x L filters (standard normal taps), each scaled to unit
+    l2 norm; float32-representable values as float64."""
+    f = rng.standard_normal((M, S, L, L))
+    f /= np.linalg.norm(f.reshape(M, -1), axis=1)[:, None, None, None]
+    return f.astype(np.float32).astype(np.float64)
 
 
 def problem(kind: str, N: int, K: int, S: int, seed_config: int,

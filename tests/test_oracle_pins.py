@@ -444,6 +444,69 @@ def test_conv_admm_tiers_agree_and_converge():
     assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
 
 
+def _filters3(rng, M, S, L):
+    f = rng.standard_normal((M, S, L, L))
+    return f / np.linalg.norm(f.reshape(M, -1), axis=1)[:, None, None, None]
+
+
+def test_conv3d_synthesis_theorem_and_adjoint():
+    """3D dictionary: the spatial 3D circular convolutions equal the 3D-DFT
+    products (convolution theorem along the bands too), and the correlation
+    is their adjoint."""
+    S, N, M, L = 3, 8, 2, 3
+    cd = priors.ConvDict3D(_filters3(_rng(70), M, S, L), S, N, N)
+    z = _rng(71).standard_normal((M, S, N, N))
+    y = _rng(72).standard_normal((S, N, N))
+    ref = cd.synth(z)
+    via_fft = np.real(np.fft.ifftn(np.sum(cd.spectra() * np.fft.fftn(z, axes=(1, 2, 3)), axis=0)))
+    assert np.max(np.abs(via_fft - ref)) < 1e-12
+    # a single tap at band offset 1 shifts the bands by one (circularly)
+    f = np.zeros((1, S, 1, 1))
+    f[0, 1, 0, 0] = 1.0
+    shift = priors.ConvDict3D(f, S, N, N).synth(z[:1])
+    assert np.allclose(shift, np.roll(z[0], 1, axis=0), atol=1e-14)
+    assert abs(np.vdot(ref, y) - np.vdot(z, cd.analysis(y))) < 1e-10 * abs(np.vdot(ref, y))
+
+
+def test_conv3d_z_update_is_subproblem_minimiser():
+    """3D codes: the gradient D~^T (D~ z - x) + rho (z - t + u) vanishes at
+    the frequency-domain z-update (spatial-domain operators)."""
+    S, N, M = 3, 10, 2
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=13)
+    alg = admm.ConvADMM(psf, _filters3(_rng(73), M, S, 3), lam=1e-3, rho=0.2, beta=5.0,
+                        tier="freq", dims=3)
+    t = _rng(74).standard_normal((M, S, N, N))
+    u = _rng(75).standard_normal((M, S, N, N))
+    z = alg.z_update(x0, t, u)
+    g = alg.cd.analysis(alg.cd.synth(z) - x0) + 0.2 * (z - t + u)
+    assert np.max(np.abs(g)) < 1e-10
+
+
+def test_conv3d_single_band_is_the_2d_dictionary():
+    """With S = 1 the 3D dictionary is the 2D one: the two runs coincide."""
+    N, M = 8, 3
+    x0, psf = _small_problem(K=1, S=1, N1=N, N2=N, seed=14)
+    y = model.forward(x0, psf) + 0.01 * _rng(76).standard_normal((1, N, N))
+    f2 = synth.random_unit_filters(_rng(77), M, 3)
+    a = admm.ConvADMM(psf, f2, 1e-3, 0.5, 10.0, tier="freq").run(y, 15)
+    b = admm.ConvADMM(psf, f2[:, None], 1e-3, 0.5, 10.0, tier="freq", dims=3).run(y, 15)
+    assert admm.rel_l2(b[0], a[0]) < 1e-12
+
+
+def test_conv3d_admm_tiers_agree_and_converge():
+    """Algorithm 2 with 3D filters: the spatial (dense) and frequency tiers
+    run the same iteration, and the iteration reaches z = t."""
+    S, N, M = 2, 8, 2
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=15)
+    y = model.forward(x0, psf) + 0.01 * _rng(78).standard_normal((2, N, N))
+    filt = _filters3(_rng(79), M, S, 3)
+    a = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="dense", dims=3).run(y, 20)
+    b = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", dims=3).run(y, 20)
+    assert admm.rel_l2(b[0], a[0]) < 1e-10
+    x, z, t, u = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", dims=3).run(y, 2000)
+    assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
+
+
 def test_tikhonov_symbol_closed_form():
     """sum_i |DFT(r_i)|^2 of the two circular forward differences is
     (2 - 2 cos w1) + (2 - 2 cos w2)."""
