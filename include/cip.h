@@ -81,6 +81,13 @@ typedef enum {
    * 1/8, `tv_inner` iterations per ADMM iteration, dual warm-started from the
    * previous ADMM iteration). */
   CIP_PRIOR_ITV2D = 6,
+  /* Convolutional dictionary with 3D filters and codes (Section IV-B, data
+   * correlated along the bands too): plane s is sum_m sum_s' d_m[s'] (*)
+   * z_m[(s - s') mod S], circular along the planes as in space; every
+   * operator is diagonal in the 3D DFT, and the code update is the
+   * Sherman-Morrison solve at every 3D frequency. `filters` holds M filters
+   * of S x L x L taps ([M][S][L][L]); no gradient term (mu = 0). */
+  CIP_PRIOR_CONV3D = 7,
 } cip_prior_kind;
 
 typedef struct {
@@ -93,15 +100,17 @@ typedef struct {
   int n_atoms;          /* A: 64, 128 or 256                                   */
   int patch_q;          /* Q: must be 8                                        */
   int patch_stride;     /* st: must be 4                                       */
-  /* CIP_PRIOR_CONV2D only (ignored otherwise):                               */
-  const float* filters; /* device [M][L][L] float32, row-major; tap (a, b) acts
-                           at offset (a - L/2, b - L/2). Read during
-                           cip_plan_create only.                              */
+  /* CIP_PRIOR_CONV2D and CIP_PRIOR_CONV3D only (ignored otherwise):         */
+  const float* filters; /* device [M][L][L] float32 (CONV3D: [M][S][L][L]),
+                           row-major; tap (a, b) acts at offset
+                           (a - L/2, b - L/2), band tap s' at band offset s'.
+                           Read during cip_plan_create only.                  */
   int n_filters;        /* M: 1 .. 32                                          */
   int filt_l;           /* L: 1 .. min(N1, N2)                                 */
   double mu;            /* gradient (Tikhonov) weight on the codes, Eq.
                            DL_PriorHP_conv for 2D correlations (forward
-                           differences along both axes); 0 = none, >= 0     */
+                           differences along both axes); 0 = none, >= 0;
+                           must be 0 for CIP_PRIOR_CONV3D                   */
   /* CIP_PRIOR_ITV2D only:                                                    */
   int tv_inner;         /* Chambolle iterations per ADMM iteration (0: 20)    */
   /* All priors:                                                             */

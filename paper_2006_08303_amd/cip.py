@@ -24,9 +24,10 @@ CIP_PRIOR_PATCH = 3
 CIP_PRIOR_CONV2D = 4
 CIP_PRIOR_DCT3D = 5
 CIP_PRIOR_ITV2D = 6
+CIP_PRIOR_CONV3D = 7
 PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
           "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D, "dct3d": CIP_PRIOR_DCT3D,
-          "itv2d": CIP_PRIOR_ITV2D}
+          "itv2d": CIP_PRIOR_ITV2D, "conv3d": CIP_PRIOR_CONV3D}
 
 
 class CipError(RuntimeError):
@@ -72,7 +73,7 @@ def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0, tv_inner=
     if filters is not None:
         d.filters = ctypes.c_void_p(filters.data_ptr())
         d.n_filters = int(filters.shape[0])
-        d.filt_l = int(filters.shape[1])
+        d.filt_l = int(filters.shape[-1])
     return d
 
 
@@ -174,7 +175,9 @@ class Plan:
     dictionary: for prior="patch", float32 CUDA tensor [64 S, A] (atoms as
     columns, row s*64 + a*8 + b = pixel (a, b) of plane s).
     filters: for prior="conv2d", float32 CUDA tensor [M, L, L] (tap (a, b) at
-    offset (a - L//2, b - L//2)); mu: gradient (Tikhonov) weight on the codes."""
+    offset (a - L//2, b - L//2)); for prior="conv3d", [M, S, L, L] (band tap
+    s' at band offset s'); mu: gradient (Tikhonov) weight on the codes
+    (conv2d only)."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
                  filters=None, stream=None, mu=0.0, adaptive=False, tv_inner=0):
@@ -185,9 +188,11 @@ class Plan:
             if dictionary is None:
                 raise ValueError("the patch prior needs a dictionary")
             _dev_f32(dictionary, (64 * self.S, dictionary.shape[1]), "dictionary")
-        if prior == "conv2d":
+        if prior in ("conv2d", "conv3d"):
             if filters is None:
-                raise ValueError("the conv2d prior needs filters")
+                raise ValueError(f"the {prior} prior needs filters")
+            if prior == "conv3d" and (filters.dim() != 4 or int(filters.shape[1]) != self.S):
+                raise ValueError("conv3d filters must have shape [M, S, L, L]")
             _dev_f32(filters, tuple(filters.shape), "filters")
         desc = _desc(prior, beta, dictionary, filters, mu, CIP_PLAN_ADAPTIVE if adaptive else 0,
                      tv_inner)

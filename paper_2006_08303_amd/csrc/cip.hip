@@ -69,6 +69,7 @@ struct Layout {
   size_t xbuf, sums;                    // adaptive solves: iterates, norm partial sums
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
   size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
+  size_t bw;                                                 // 3D conv: band DFT matrix
   size_t tables;                        // bytes of the table region
   size_t state_bytes;                   // bytes of the state region
   size_t total;                         // tables + state_bytes
@@ -83,6 +84,7 @@ int state_floats_per_voxel(int kind) {
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
     case CIP_PRIOR_CONV2D: return 0;
+    case CIP_PRIOR_CONV3D: return 0;
     default: return -1;
   }
 }
@@ -141,17 +143,19 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     L.tbuf = sta(patch_tile_buffer_floats(S, N1, N2) * 4);
     L.rimg = sta((size_t)S * N1 * N2 * 4);
   }
-  if (kind == CIP_PRIOR_CONV2D) {
+  if (kind == CIP_PRIOR_CONV2D || kind == CIP_PRIOR_CONV3D) {
     const size_t M = (size_t)prior->n_filters;
-    L.th32 = tab(M * F * 8);
-    L.gam = tab(F * 4);
+    const size_t B = kind == CIP_PRIOR_CONV3D ? (size_t)S : 1;   // band frequencies
+    L.th32 = tab(M * B * F * 8);
+    L.gam = tab(B * F * 4);
     L.eta = tab(F * 4);
+    L.bw = kind == CIP_PRIOR_CONV3D ? tab((size_t)S * S * 8) : 0;
     L.gv = sta(M * S * F * 8);
     L.dhat = sta((size_t)S * F * 8);
     L.xhat = sta((size_t)S * F * 8);
     L.rtc = sta(M * S * F * 8);
     L.vconv = sta(M * S * (size_t)N1 * N2 * 4);
-    L.th64 = scr(M * F * 16);
+    L.th64 = scr(M * B * F * 16);
   }
   L.tables = ot;
   L.state_bytes = os > oc ? os : oc;
@@ -179,12 +183,14 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       return fail(CIP_EUNSUPPORTED, "patch prior: needs S <= 4 and 64, 128 or 256 atoms");
     if (!patch_grid_ok(N1, N2)) return fail(CIP_EUNSUPPORTED, "patch prior: grid too small");
   }
-  if (prior->kind == CIP_PRIOR_CONV2D) {
+  if (prior->kind == CIP_PRIOR_CONV2D || prior->kind == CIP_PRIOR_CONV3D) {
     if (prior->n_filters < 1 || prior->n_filters > 32)
       return fail(CIP_EUNSUPPORTED, "conv prior: 1 to 32 filters");
     if (prior->filt_l < 1 || prior->filt_l > N1 || prior->filt_l > N2)
       return fail(CIP_EINVAL, "conv prior: filter size must be in [1, min(N1, N2)]");
     if (!(prior->mu >= 0.0)) return fail(CIP_EINVAL, "conv prior: mu must be >= 0");
+    if (prior->kind == CIP_PRIOR_CONV3D && prior->mu != 0.0)
+      return fail(CIP_EUNSUPPORTED, "3D conv prior: no gradient term (mu must be 0)");
   }
   return CIP_OK;
 }
@@ -469,6 +475,24 @@ hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
   return hipSuccess;
 }
 
+// Frequency pass of the conv prior (2D form, or the 3D form with its band
+// DFTs).
+hipError_t conv_freq_pass(cip_plan_t p, int first, int zero_g, int do_z, hipStream_t st) {
+  const Layout& L = p->L;
+  const size_t F = (size_t)p->N1 * p->H2;
+  if (p->kind == CIP_PRIOR_CONV3D)
+    return conv_freq3(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
+                      p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
+                      p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
+                      p->at<const float>(L.gam), p->at<const cx<float>>(L.bw), p->n_filters, p->S,
+                      F, first, zero_g, do_z, st);
+  return conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
+                   p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
+                   p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
+                   p->at<const float>(L.gam), p->at<const float>(L.eta), p->n_filters, p->S, F,
+                   first, zero_g, do_z, st);
+}
+
 // Algorithm 2 with the convolutional prior. Per iteration l = 1..L:
 //   frequency pass: x^l = Psi^+ (b^ + d^{l-1}); for l < L also the
 //   Sherman-Morrison code update v and d^l;
@@ -477,14 +501,8 @@ hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
 // Finally x^L: inverse column and row FFTs of x^L.
 hipError_t conv_iter(cip_plan_t p, int l, int last, hipStream_t st) {
   const Layout& L = p->L;
-  const size_t F = (size_t)p->N1 * p->H2;
   const int P = p->n_filters * p->S;
-  hipError_t e = conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
-                           p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
-                           p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
-                           p->at<const float>(L.gam), p->at<const float>(L.eta), p->n_filters, p->S,
-                           F, l == 1, l == 1,
-                           last ? 0 : 1, st);
+  hipError_t e = conv_freq_pass(p, l == 1, l == 1, last ? 0 : 1, st);
   if (e != hipSuccess || last) return e;
   e = conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1, p->H2,
                    p->at<const cx<float>>(L.twN1f), st);
@@ -520,7 +538,8 @@ hipError_t gram(cip_plan_t p, hipStream_t st, double rho = 0.0) {
   a.beta = p->beta;
   a.scale = 1.0 / ((double)p->N1 * (double)p->N2);
   a.rcond = 1e-12;
-  const bool patch = p->kind == CIP_PRIOR_PATCH, conv = p->kind == CIP_PRIOR_CONV2D;
+  const bool patch = p->kind == CIP_PRIOR_PATCH,
+             conv = p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D;
   // analysis: Psi = rho tau I + beta L^H L, rhs = b + rho g;
   // patch synthesis: Psi = c_P I + beta L^H L with c_P = (Q / st)^2 = 4, rhs = b + g;
   // conv synthesis: c_P = 1, and the tables are unnormalised (the frequency
@@ -670,7 +689,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     return fail(CIP_EINVAL, "workspace must be 256-byte aligned");
   if (prior->kind == CIP_PRIOR_PATCH && !prior->dict)
     return fail(CIP_EINVAL, "patch prior needs a dictionary");
-  if (prior->kind == CIP_PRIOR_CONV2D && !prior->filters)
+  if ((prior->kind == CIP_PRIOR_CONV2D || prior->kind == CIP_PRIOR_CONV3D) && !prior->filters)
     return fail(CIP_EINVAL, "conv prior needs filters");
   Layout L = make_layout(K, S, N1, N2, prior);
   if (ws_bytes < L.total) return fail(CIP_ENOSPC, "workspace too small");
@@ -684,7 +703,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->H2 = N2 / 2 + 1;
   p->kind = prior->kind;
   p->n_atoms = prior->kind == CIP_PRIOR_PATCH ? prior->n_atoms : 0;
-  p->n_filters = prior->kind == CIP_PRIOR_CONV2D ? prior->n_filters : 0;
+  p->n_filters =
+      (prior->kind == CIP_PRIOR_CONV2D || prior->kind == CIP_PRIOR_CONV3D) ? prior->n_filters : 0;
   p->beta = prior->beta;
   p->rho = rho;
   p->lambda = lambda;
@@ -774,6 +794,34 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
                          p->at<float>(L.gam), p->at<float>(L.eta), M, (size_t)N1 * p->H2, rho,
                          prior->mu, N1, N2, st));
   }
+  if (p->kind == CIP_PRIOR_CONV3D) {
+    // 2D spectra of every filter slice (m, s') in FP64 -> band DFT -> theta_m(w, k)
+    const int M = prior->n_filters, Lf = prior->filt_l;
+    double* d_pl = p->at<double>(L.pl64);
+    for (int m = 0; m < M; ++m) {
+      for (int sp = 0; sp < S; ++sp) {
+        PLAN_HIP(conv_place_filter(prior->filters + ((size_t)m * S + sp) * Lf * Lf, d_pl, Lf, N1,
+                                   N2, st));
+        PLAN_HIP(row_r2c<double>(d_pl, p->at<cx<double>>(L.rt64), 1, N1, N2,
+                                 p->at<const cx<double>>(L.twN2d), st));
+        PLAN_HIP((col_op<double, OP_SPEC>(p->at<const cx<double>>(L.rt64), p->at<void>(L.th64), 1,
+                                          1, N1, p->H2, p->at<const cx<double>>(L.twN1d), nullptr,
+                                          m * S + sp, st)));
+      }
+    }
+    PLAN_HIP(conv_tables3(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
+                          p->at<float>(L.gam), M, S, (size_t)N1 * p->H2, rho, st));
+    // band DFT matrix bw[k][s] = exp(-2 pi i k s / S), formed in FP64
+    std::vector<cx<float>> bw((size_t)S * S);
+    for (int k = 0; k < S; ++k)
+      for (int s2 = 0; s2 < S; ++s2) {
+        const double a = -2.0 * kPi * (double)((k * s2) % S) / (double)S;
+        bw[(size_t)k * S + s2] = cx<float>{(float)std::cos(a), (float)std::sin(a)};
+      }
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.bw), bw.data(), bw.size() * sizeof(cx<float>),
+                            hipMemcpyHostToDevice, st));
+    PLAN_HIP(hipStreamSynchronize(st));
+  }
   if (p->kind == CIP_PRIOR_PATCH) {
     // M1 = D^T (rho I + D D^T)^-1 in FP64 on the host; D and M1 stored as BF16
     const int nv = 64 * S, na = prior->n_atoms;
@@ -832,7 +880,7 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   HIP_TRY((col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufA), p->at<void>(L.xh0), p->K, p->S,
                                    p->N1, p->H2, p->at<const cx<float>>(L.twN1f),
                                    p->at<const cx<float>>(L.Mm), 0, st)));
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D) {
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D) {
     if (p->kind == CIP_PRIOR_PATCH) HIP_TRY(solve_patch(p, iters, d_x, st));
     else HIP_TRY(solve_conv(p, iters, d_x, st));
     p->solved_once = true;
@@ -859,7 +907,8 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (!p || !d_y || !d_x || !prm) return fail(CIP_EINVAL, "NULL argument");
   if (!p->adaptive) return fail(CIP_EINVAL, "plan was not created with CIP_PLAN_ADAPTIVE");
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
+      p->kind == CIP_PRIOR_ITV2D)
     return fail(CIP_EUNSUPPORTED, "adaptive penalty: l1 analysis priors only");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
       !(prm->tol >= 0.0))
@@ -1108,7 +1157,8 @@ int cip_batch_destroy(cip_batch_t b) {
 int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   if (!p || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
+      p->kind == CIP_PRIOR_ITV2D)
     return fail(CIP_EUNSUPPORTED, "autotuning covers the l1 analysis row passes");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool dct = is_dct(p);
@@ -1162,7 +1212,8 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   const bool dct = is_dct(p);
   const int pd = ppt_row_n(p->N2);
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_ITV2D)
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
+      p->kind == CIP_PRIOR_ITV2D)
     return fail(CIP_EUNSUPPORTED, "tuning covers the l1 analysis row passes");
   if (!(row_np == PAIRS || row_np == 2)) return fail(CIP_EINVAL, "row_np must be 4 or 2");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))
@@ -1176,7 +1227,8 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
   if (!p || !avg_us || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
   if (which < 0 || which > 2) return fail(CIP_EINVAL, "which must be 0, 1 or 2");
-  const bool conv = p->kind == CIP_PRIOR_CONV2D, patch = p->kind == CIP_PRIOR_PATCH;
+  const bool conv = p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D,
+             patch = p->kind == CIP_PRIOR_PATCH;
   if (which == 2 && !patch && !conv)
     return fail(CIP_EINVAL, "which = 2 needs the patch or convolutional prior");
   if (patch && which == 0) return fail(CIP_EINVAL, "the patch prior has no fused row pass");
@@ -1198,11 +1250,7 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
         HIP_TRY(conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gv), P, p->N1,
                              p->H2, p->at<const cx<float>>(L.twN1f), st));
       else
-        HIP_TRY(conv_freq(p->at<cx<float>>(L.gv), p->at<cx<float>>(L.dhat), p->at<cx<float>>(L.xhat),
-                          p->at<const cx<float>>(L.xh0), p->at<const float>(L.Adiag),
-                          p->at<const cx<float>>(L.Aoff), p->at<const cx<float>>(L.th32),
-                          p->at<const float>(L.gam), p->at<const float>(L.eta), p->n_filters, p->S,
-                          F, 0, 0, 1, st));
+        HIP_TRY(conv_freq_pass(p, 0, 0, 1, st));
       continue;
     }
     if (which == 0) HIP_TRY(admm_row(p, 2 + (r & 1), st));

@@ -37,6 +37,34 @@ hipError_t conv_freq(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<f
                 th, gam, eta, M, S, F, first, zero_g, do_z);
 }
 
+hipError_t conv_tables3(const cx<double>* th64, cx<float>* th32, float* gam, int M, int S,
+                        size_t F, double rho, hipStream_t st) {
+  return launch(k_conv_tables3, (int)((F + 255) / 256), 256, 0, st, th64, th32, gam, M, S, F, rho);
+}
+
+hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<float>* xh0,
+                      const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
+                      const float* gam, const cx<float>* bw, int M, int S, size_t F, int first,
+                      int zero_g, int do_z, hipStream_t st) {
+  const int grid = (int)((F + 127) / 128);
+#define CIP_CF3(SS)                                                                            \
+  case SS:                                                                                     \
+    return launch(k_conv_freq3<SS>, grid, 128, 0, st, gv, dhat, xhat, xh0, Adiag, Aoff, th, gam, \
+                  bw, M, F, first, zero_g, do_z);
+  switch (S) {
+    CIP_CF3(1)
+    CIP_CF3(2)
+    CIP_CF3(3)
+    CIP_CF3(4)
+    CIP_CF3(5)
+    CIP_CF3(6)
+    CIP_CF3(7)
+    CIP_CF3(8)
+  }
+#undef CIP_CF3
+  return hipErrorInvalidValue;
+}
+
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
                     const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st) {
   CIP_DISPATCH_N(N2, {

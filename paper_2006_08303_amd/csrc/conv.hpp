@@ -1,5 +1,6 @@
 // Convolutional-dictionary synthesis prior, 2D-correlation form (a common set
-// of M filters d_m for every plane: plane s ~ sum_m d_m * z_{m,s}; P = I).
+// of M filters d_m for every plane: plane s ~ sum_m d_m * z_{m,s}; P = I),
+// and the 3D form (k_conv_tables3, k_conv_freq3 below).
 //
 // One ADMM iteration of Algorithm 2, with all operators diagonal in the 2D
 // DFT domain (Section IV-B):
@@ -162,6 +163,133 @@ __global__ void k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ 
       dn = dn + cmul(t[m], vm);
     }
     dhat[(size_t)s * F + f] = dn;
+  }
+}
+
+// 3D form (filters and codes circular along the S planes too; every operator
+// is diagonal in the 3D DFT over (band, n1, n2)). theta_m(w, k) for band
+// frequency k = 1D DFT over the band taps of the 2D spectra of the filter
+// slices; formed in FP64 at plan time, stored [M][k][F] in FP32, with
+// gamma(w, k) = 1 / (rho + sum_m |theta_m(w, k)|^2) stored [k][F].
+__global__ void k_conv_tables3(const cx<double>* __restrict__ th64, cx<float>* __restrict__ th32,
+                               float* __restrict__ gam, int M, int S, size_t F, double rho) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  for (int k = 0; k < S; ++k) {
+    double sum = 0.0;
+    for (int m = 0; m < M; ++m) {
+      cx<double> acc = {0.0, 0.0};
+      for (int sp = 0; sp < S; ++sp) {
+        // exp(-2 pi i k s' / S)
+        double sn, cs;
+        sincospi(-2.0 * (double)((k * sp) % S) / (double)S, &sn, &cs);
+        acc = acc + cmul(th64[((size_t)m * S + sp) * F + f], cx<double>{cs, sn});
+      }
+      th32[((size_t)m * S + k) * F + f] = cx<float>{(float)acc.x, (float)acc.y};
+      sum += acc.x * acc.x + acc.y * acc.y;
+    }
+    gam[(size_t)k * F + f] = (float)(1.0 / (rho + sum));
+  }
+}
+
+// Frequency pass of the 3D form, one thread per 2D frequency f (FL order),
+// all S planes and M codes:
+//   x^ = xh0 + A d^ as in the 2D form (d^_s from the previous code update);
+//   band DFTs (unnormalised, bw[k][s] = exp(-2 pi i k s / S)):
+//     X(k) = sum_s x^_s bw[k][s],   G_m(k) = sum_s g^_{m,s} bw[k][s];
+//   Sherman-Morrison per band frequency k (Eq. solz_DFT_SM at every 3D
+//   frequency): r(k) = (X(k) - sum_m theta_m(k) G_m(k)) gamma(k),
+//     V_m(k) = G_m(k) + conj(theta_m(k)) r(k);
+//   v_{m,s} = (1/S) sum_k V_m(k) conj(bw[k][s])  (overwrites g^ in gv),
+//   d^_s = (1/S) sum_k (sum_m theta_m(k) V_m(k)) conj(bw[k][s]).
+// Two passes over the codes (first the r(k), then V) keep the registers to
+// O(S). first: d^ = 0; zero_g: g^ = 0.
+template <int S>
+__global__ void __launch_bounds__(128)
+k_conv_freq3(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat, cx<float>* __restrict__ xhat,
+             const cx<float>* __restrict__ xh0, const float* __restrict__ Adiag,
+             const cx<float>* __restrict__ Aoff, const cx<float>* __restrict__ th,
+             const float* __restrict__ gam, const cx<float>* __restrict__ bw, int M, size_t F,
+             int first, int zero_g, int do_z) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  cx<float> d[S], xs[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) d[s] = first ? cx<float>{0.f, 0.f} : dhat[(size_t)s * F + f];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    cx<float> acc = xh0[(size_t)s * F + f];
+    const float dg = Adiag[(size_t)s * F + f];
+    acc.x += dg * d[s].x;
+    acc.y += dg * d[s].y;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      if (j == s) continue;
+      const cx<float> a = s < j ? Aoff[(size_t)pair_index(s, j, S) * F + f]
+                                : conjx(Aoff[(size_t)pair_index(j, s, S) * F + f]);
+      acc = acc + cmul(a, d[j]);
+    }
+    xs[s] = acc;
+    xhat[(size_t)s * F + f] = acc;
+  }
+  if (!do_z) return;
+  cx<float> X[S], ag[S], r[S], dn[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    X[k] = cx<float>{0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < S; ++s) X[k] = X[k] + cmul(xs[s], bw[k * S + s]);
+    ag[k] = cx<float>{0.f, 0.f};
+    dn[k] = cx<float>{0.f, 0.f};
+  }
+  if (!zero_g) {
+    for (int m = 0; m < M; ++m) {
+      cx<float> g[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) g[s] = gv[((size_t)m * S + s) * F + f];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        cx<float> G = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) G = G + cmul(g[s], bw[k * S + s]);
+        ag[k] = ag[k] + cmul(th[((size_t)m * S + k) * F + f], G);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const float gm = gam[(size_t)k * F + f];
+    r[k] = cx<float>{(X[k].x - ag[k].x) * gm, (X[k].y - ag[k].y) * gm};
+  }
+  const float invS = 1.f / (float)S;
+  for (int m = 0; m < M; ++m) {
+    cx<float> g[S], V[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      g[s] = zero_g ? cx<float>{0.f, 0.f} : gv[((size_t)m * S + s) * F + f];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      cx<float> G = {0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < S; ++s) G = G + cmul(g[s], bw[k * S + s]);
+      const cx<float> t = th[((size_t)m * S + k) * F + f];
+      V[k] = G + cmulc(r[k], t);   // G + conj(theta) r
+      dn[k] = dn[k] + cmul(t, V[k]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      cx<float> acc = {0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc = acc + cmulc(V[k], bw[k * S + s]);
+      gv[((size_t)m * S + s) * F + f] = cx<float>{acc.x * invS, acc.y * invS};
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    cx<float> acc = {0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc = acc + cmulc(dn[k], bw[k * S + s]);
+    dhat[(size_t)s * F + f] = cx<float>{acc.x * invS, acc.y * invS};
   }
 }
 

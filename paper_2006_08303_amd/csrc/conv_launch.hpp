@@ -16,6 +16,12 @@ hipError_t conv_freq(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<f
                      const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
                      const float* gam, const float* eta, int M, int S, size_t F, int first,
                      int zero_g, int do_z, hipStream_t st);
+hipError_t conv_tables3(const cx<double>* th64, cx<float>* th32, float* gam, int M, int S,
+                        size_t F, double rho, hipStream_t st);
+hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<float>* xh0,
+                      const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
+                      const float* gam, const cx<float>* bw, int M, int S, size_t F, int first,
+                      int zero_g, int do_z, hipStream_t st);
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
                     const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st);
 

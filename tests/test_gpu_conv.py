@@ -73,3 +73,56 @@ def test_conv_tikhonov_matches_oracle(N, K, S, M, L, iters, mu):
     print(f"  rel_l2 = {err:.3e} (vs unregularised oracle {admm.rel_l2(got, plain):.3e})",
           flush=True)
     assert err < 1e-4
+
+
+def _conv3_problem(N, K, S, M, L, cfg=3):
+    x, psf, noise = synth.problem("smooth_disk", N, K, S, seed_config=cfg)
+    y = model.measure(x, psf, noise, 30.0).astype(np.float32).astype(np.float64)
+    filt = synth.random_unit_filters_3d(synth.rng_for(cfg, 6), M, S, L)
+    return x, psf, y, filt
+
+
+@pytest.mark.parametrize("N,K,S,M,L,iters", [(64, 3, 3, 8, 5, 1), (64, 3, 3, 8, 5, 12),
+                                             (128, 3, 3, 16, 7, 8), (32, 2, 2, 4, 3, 10),
+                                             (64, 5, 5, 8, 5, 6), (32, 8, 8, 4, 3, 4),
+                                             (384, 3, 3, 8, 5, 3)])
+def test_conv3d_solve_matches_oracle(N, K, S, M, L, iters):
+    """3D filters and codes: band DFTs inside the frequency pass."""
+    print(f"conv3d solve N={N} K={K} S={S} M={M} L={L} iters={iters}", flush=True)
+    x, psf, y, filt = _conv3_problem(N, K, S, M, L)
+    lam, rho, beta = 1.875e-6, 1e-4, 8.0
+    ref = admm.ConvADMM(psf, filt, lam, rho, beta, tier="freq", dims=3).run(y, iters)[0]
+    plan = cip.Plan(_t(psf), "conv3d", rho, lam, beta, filters=_t(filt))
+    got = _np(plan.solve(_t(y), iters))
+    err = admm.rel_l2(got, ref)
+    print(f"  rel_l2 = {err:.3e}  psnr gpu {admm.psnr(got, x):.2f} dB oracle "
+          f"{admm.psnr(ref, x):.2f} dB", flush=True)
+    assert err < 1e-4
+
+
+def test_conv3d_single_plane_equals_conv2d():
+    """S = 1: the 3D dictionary is the 2D one (same kernels up to the band
+    DFT of length 1)."""
+    x, psf, y, filt = _conv_problem(64, 2, 1, 8, 5)
+    a = _np(cip.Plan(_t(psf), "conv2d", 1e-4, 1.875e-6, 8.0, filters=_t(filt)).solve(_t(y), 10))
+    b = _np(cip.Plan(_t(psf), "conv3d", 1e-4, 1.875e-6, 8.0,
+                     filters=_t(filt[:, None])).solve(_t(y), 10))
+    assert admm.rel_l2(b, a) < 1e-6
+
+
+def test_conv3d_full_size_1024():
+    """K = S = 3, 1024 x 1024, 32 filters of 3 x 11 x 11, 3 iterations."""
+    x, psf, y, filt = _conv3_problem(1024, 3, 3, 32, 11)
+    ref = admm.ConvADMM(psf, filt, 1.875e-6, 1e-4, 8.0, tier="freq", dims=3).run(y, 3)[0]
+    plan = cip.Plan(_t(psf), "conv3d", 1e-4, 1.875e-6, 8.0, filters=_t(filt))
+    got = _np(plan.solve(_t(y), 3))
+    err = admm.rel_l2(got, ref)
+    print(f"1024^2 conv3d 3 iters: rel_l2 = {err:.3e}", flush=True)
+    assert err < 1e-4
+    assert plan.time_kernel(2, 5) > 0.0
+
+
+def test_conv3d_rejects_gradient_term():
+    x, psf, y, filt = _conv3_problem(32, 2, 2, 4, 3)
+    with pytest.raises(cip.CipError):
+        cip.Plan(_t(psf), "conv3d", 1e-4, 1.875e-6, 8.0, filters=_t(filt), mu=0.01)
