@@ -272,7 +272,8 @@ class ConvADMM:
     equation then gains mu sum_i R_i^H R_i on its left-hand side (stated
     below Eq. solz), diagonal in frequency with symbol psi(w)."""
 
-    def __init__(self, psf, filters, lam, rho, beta, tier="auto", mu=0.0, dims=2):
+    def __init__(self, psf, filters, lam, rho, beta, tier="auto", mu=0.0, dims=2,
+                 dict_update=False, sigma=10.0):
         K, S, N1, N2 = psf.shape
         self.psf = psf
         self.S, self.N1, self.N2 = S, N1, N2
@@ -292,6 +293,15 @@ class ConvADMM:
         else:
             self.solver = xupdate.FreqSolver(psf, beta, 1.0, np.ones((N1, N2)))
         self.theta = self.cd.spectra()                           # (M, N1, N2)
+        self.dict_update = bool(dict_update)
+        if self.dict_update:
+            # online update of the 3D dictionary (Eqs. d_admm, g_admm, h_admm)
+            assert self.dims == 3, "the dictionary update is built for the 3D form"
+            L = np.asarray(filters).shape[-1]
+            self.sigma = float(sigma)
+            self.support = priors.filter_on_grid(np.ones((L, L)), N1, N2) > 0   # (N1, N2)
+            self.g = self.cd.h.copy()                            # feasible dictionary
+            self.e = np.zeros_like(self.g)                       # scaled dual
         self.mu = float(mu)
         self.psi = priors.tikhonov_symbol(N1, N2)                # (N1, N2)
 
@@ -329,6 +339,29 @@ class ConvADMM:
         v = sherman_morrison(self.theta[:, None], c, self.rho + self.mu * self.psi)
         return np.ascontiguousarray(np.real(np.fft.ifft2(v, axes=(-2, -1))))
 
+    def d_update(self, x, z):
+        """Eq. sold_3D: (sigma I + Z^H Z) d = Z^H x + sigma (g - e), Z_m the
+        3D convolution by code z_m, diagonal in the 3D DFT (rank one per
+        frequency plus sigma I): Sherman-Morrison at every 3D frequency.
+        d is full size (M, S, N1, N2)."""
+        xh = np.fft.fftn(x, axes=(0, 1, 2))
+        zh = np.fft.fftn(z, axes=(1, 2, 3))
+        c = np.conj(zh) * xh[None] + self.sigma * np.fft.fftn(self.g - self.e, axes=(1, 2, 3))
+        dh = sherman_morrison(zh, c, self.sigma)
+        return np.ascontiguousarray(np.real(np.fft.ifftn(dh, axes=(1, 2, 3))))
+
+    def g_update(self, d):
+        """Eq. g_admm (with e^l, the readable form of the garbled index):
+        crop d + e to the L x L x S filter support and scale every filter to
+        unit l2 norm (projection onto the constraint set C_d)."""
+        w = (d + self.e) * self.support[None, None]
+        n = np.sqrt(np.sum(w * w, axis=(1, 2, 3)))
+        return w / n[:, None, None, None]
+
+    def set_dictionary(self, g):
+        self.cd.h = g
+        self.theta = self.cd.spectra()
+
     def run(self, y, iters, callback=None):
         data = self.solver.data_term(y)
         z = np.zeros((self.M, self.S, self.N1, self.N2))
@@ -342,6 +375,14 @@ class ConvADMM:
             t_new = priors.soft(z + u, kappa)
             u = u + z - t_new
             t = t_new
+            if self.dict_update:
+                # one d, g, e step per outer iteration; the next x- and
+                # z-updates use the feasible dictionary g
+                d = self.d_update(x, z)
+                g = self.g_update(d)
+                self.e = self.e + g - d
+                self.g = g
+                self.set_dictionary(g)
             if callback is not None:
                 callback(it, x, z, t, u)
         return x, z, t, u

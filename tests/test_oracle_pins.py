@@ -507,6 +507,79 @@ def test_conv3d_admm_tiers_agree_and_converge():
     assert np.linalg.norm(z - t) < 2e-6 * np.linalg.norm(z)
 
 
+def _conv3_brute(z, h):
+    """sum over the nonzero taps of h of h[s', a, b] z[s - s', n1 - a, n2 - b]
+    (circular), by shifts: no FFT."""
+    out = np.zeros_like(z)
+    for (sp, a, b) in zip(*np.nonzero(h)):
+        out += h[sp, a, b] * np.roll(z, (sp, a, b), axis=(0, 1, 2))
+    return out
+
+
+def _corr3_brute(y, h):
+    out = np.zeros_like(y)
+    for (sp, a, b) in zip(*np.nonzero(h)):
+        out += h[sp, a, b] * np.roll(y, (-sp, -a, -b), axis=(0, 1, 2))
+    return out
+
+
+def test_conv3d_dictionary_d_update_solves_its_normal_equation():
+    """Eq. sold_3D: (sigma I + Z^H Z) d = Z^H x + sigma (g - e), with Z_m the
+    3D circular convolution by the code z_m (brute-force shifts)."""
+    S, N, M = 2, 6, 2
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=16)
+    alg = admm.ConvADMM(psf, _filters3(_rng(80), M, S, 3), 1e-3, 0.5, 10.0, tier="freq",
+                        dims=3, dict_update=True, sigma=0.7)
+    alg.e = 0.1 * _rng(81).standard_normal(alg.e.shape)
+    z = _rng(82).standard_normal((M, S, N, N))
+    d = alg.d_update(x0, z)
+    zd = sum(_conv3_brute(d[m], z[m]) for m in range(M))
+    for m in range(M):
+        res = 0.7 * d[m] + _corr3_brute(zd - x0, z[m]) - 0.7 * (alg.g[m] - alg.e[m])
+        assert np.max(np.abs(res)) < 1e-10
+
+
+def test_conv3d_dictionary_g_update_is_the_projection():
+    """Eq. g_admm: g_m is d_m + e_m cropped to the L x L x S support and
+    scaled to unit norm (the nearest point of C_d)."""
+    S, N, M, L = 2, 8, 3, 3
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=17)
+    alg = admm.ConvADMM(psf, _filters3(_rng(83), M, S, L), 1e-3, 0.5, 10.0, tier="freq",
+                        dims=3, dict_update=True)
+    d = _rng(84).standard_normal((M, S, N, N))
+    alg.e = _rng(85).standard_normal((M, S, N, N))
+    g = alg.g_update(d)
+    mask = np.zeros((N, N), bool)
+    for a in range(L):
+        for b in range(L):
+            mask[(a - L // 2) % N, (b - L // 2) % N] = True
+    for m in range(M):
+        assert abs(np.linalg.norm(g[m]) - 1.0) < 1e-12
+        assert np.all(g[m][:, ~mask] == 0.0)
+        w = (d[m] + alg.e[m])[:, mask]
+        assert np.allclose(g[m][:, mask], w / np.linalg.norm(w), atol=1e-14)
+
+
+def test_conv3d_dictionary_update_with_huge_sigma_keeps_the_dictionary():
+    """sigma -> infinity pins d to g - e = g, so the run equals the
+    fixed-dictionary run (the updated filters feed the next x- and
+    z-updates)."""
+    S, N, M = 2, 8, 2
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=18)
+    y = model.forward(x0, psf) + 0.01 * _rng(86).standard_normal((2, N, N))
+    filt = _filters3(_rng(87), M, S, 3)
+    a = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", dims=3).run(y, 10)
+    alg = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", dims=3, dict_update=True,
+                        sigma=1e12)
+    b = alg.run(y, 10)
+    assert admm.rel_l2(b[0], a[0]) < 1e-8
+    alg2 = admm.ConvADMM(psf, filt, 1e-3, 0.5, 10.0, tier="freq", dims=3, dict_update=True,
+                         sigma=1.0)
+    c = alg2.run(y, 10)
+    assert admm.rel_l2(c[0], a[0]) > 1e-4          # a finite sigma does move the dictionary
+    assert np.allclose(np.linalg.norm(alg2.g.reshape(M, -1), axis=1), 1.0, atol=1e-12)
+
+
 def test_tikhonov_symbol_closed_form():
     """sum_i |DFT(r_i)|^2 of the two circular forward differences is
     (2 - 2 cos w1) + (2 - 2 cos w2)."""
