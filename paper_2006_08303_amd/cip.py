@@ -42,7 +42,7 @@ class _PriorDesc(ctypes.Structure):
                 ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int),
                 ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
                 ("filt_l", ctypes.c_int), ("mu", ctypes.c_double), ("tv_inner", ctypes.c_int),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("sigma", ctypes.c_double)]
 
 
 class _AdaptiveParams(ctypes.Structure):
@@ -57,6 +57,7 @@ class _SolveInfo(ctypes.Structure):
 
 
 CIP_PLAN_ADAPTIVE = 1
+CIP_PLAN_DICT_UPDATE = 2
 
 
 class _Tuning(ctypes.Structure):
@@ -64,9 +65,9 @@ class _Tuning(ctypes.Structure):
                 ("row_us", ctypes.c_double), ("default_us", ctypes.c_double)]
 
 
-def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0, tv_inner=0):
+def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0, tv_inner=0, sigma=0.0):
     d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu),
-                   int(tv_inner), int(flags))
+                   int(tv_inner), int(flags), float(sigma))
     if dictionary is not None:
         d.dict = ctypes.c_void_p(dictionary.data_ptr())
         d.n_atoms = int(dictionary.shape[1])
@@ -105,6 +106,7 @@ def lib():
         L.cip_forward.argtypes = [vp, vp, vp, vp]
         L.cip_adjoint.argtypes = [vp, vp, vp, vp]
         L.cip_solve.argtypes = [vp, vp, i, vp, vp]
+        L.cip_plan_dictionary.argtypes = [vp, vp, vp]
         L.cip_plan_destroy.argtypes = [vp]
         L.cip_last_error.restype = ctypes.c_char_p
         L.cip_time_kernel.argtypes = [vp, i, i, vp, ctypes.POINTER(d)]
@@ -177,10 +179,12 @@ class Plan:
     filters: for prior="conv2d", float32 CUDA tensor [M, L, L] (tap (a, b) at
     offset (a - L//2, b - L//2)); for prior="conv3d", [M, S, L, L] (band tap
     s' at band offset s'); mu: gradient (Tikhonov) weight on the codes
-    (conv2d only)."""
+    (conv2d only). dict_update (conv3d): learn the dictionary online in every
+    solve with penalty sigma (0: 10); dictionary() returns the learned filters."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
-                 filters=None, stream=None, mu=0.0, adaptive=False, tv_inner=0):
+                 filters=None, stream=None, mu=0.0, adaptive=False, tv_inner=0,
+                 dict_update=False, sigma=0.0):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
@@ -194,8 +198,9 @@ class Plan:
             if prior == "conv3d" and (filters.dim() != 4 or int(filters.shape[1]) != self.S):
                 raise ValueError("conv3d filters must have shape [M, S, L, L]")
             _dev_f32(filters, tuple(filters.shape), "filters")
-        desc = _desc(prior, beta, dictionary, filters, mu, CIP_PLAN_ADAPTIVE if adaptive else 0,
-                     tv_inner)
+        flags = (CIP_PLAN_ADAPTIVE if adaptive else 0) | (CIP_PLAN_DICT_UPDATE if dict_update else 0)
+        desc = _desc(prior, beta, dictionary, filters, mu, flags, tv_inner, sigma)
+        self.filters_shape = tuple(filters.shape) if filters is not None else None
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
                                  desc.n_atoms, desc.n_filters, desc.filt_l, desc.flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
@@ -253,6 +258,13 @@ class Plan:
         """A plan sharing this plan's tables with a solve state of its own
         (cip_plan_attach); the state buffer is allocated here."""
         return AttachedPlan(self)
+
+    def dictionary(self, stream=None):
+        """The filters learned in the last solve (dict_update plans), [M, S, L, L]."""
+        out = torch.empty(self.filters_shape, dtype=torch.float32, device=self.workspace.device)
+        _check(lib().cip_plan_dictionary(self._h, ctypes.c_void_p(out.data_ptr()),
+                                         _stream_ptr(stream)))
+        return out
 
     def time_kernel(self, which, reps, stream=None):
         us = ctypes.c_double()

@@ -70,6 +70,7 @@ struct Layout {
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
   size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t bw;                                                 // 3D conv: band DFT matrix
+  size_t filt0, gtap, gehat, dsp, ecdl, dpl;                 // 3D dictionary update
   size_t tables;                        // bytes of the table region
   size_t state_bytes;                   // bytes of the state region
   size_t total;                         // tables + state_bytes
@@ -146,8 +147,20 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (kind == CIP_PRIOR_CONV2D || kind == CIP_PRIOR_CONV3D) {
     const size_t M = (size_t)prior->n_filters;
     const size_t B = kind == CIP_PRIOR_CONV3D ? (size_t)S : 1;   // band frequencies
-    L.th32 = tab(M * B * F * 8);
-    L.gam = tab(B * F * 4);
+    // a learned dictionary changes the filter tables during a solve: they
+    // then belong to the solve state
+    const bool learn = kind == CIP_PRIOR_CONV3D && (prior->flags & CIP_PLAN_DICT_UPDATE);
+    L.th32 = learn ? sta(M * B * F * 8) : tab(M * B * F * 8);
+    L.gam = learn ? sta(B * F * 4) : tab(B * F * 4);
+    if (learn) {
+      const size_t taps = M * S * (size_t)prior->filt_l * prior->filt_l;
+      L.filt0 = tab(taps * 4);
+      L.gtap = sta(taps * 4);
+      L.gehat = sta(M * S * F * 8);
+      L.dsp = sta(M * S * F * 8);
+      L.ecdl = sta(M * S * (size_t)N1 * N2 * 4);
+      L.dpl = sta(M * S * (size_t)N1 * N2 * 4);
+    }
     L.eta = tab(F * 4);
     L.bw = kind == CIP_PRIOR_CONV3D ? tab((size_t)S * S * 8) : 0;
     L.gv = sta(M * S * F * 8);
@@ -192,6 +205,11 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     if (prior->kind == CIP_PRIOR_CONV3D && prior->mu != 0.0)
       return fail(CIP_EUNSUPPORTED, "3D conv prior: no gradient term (mu must be 0)");
   }
+  if (prior->flags & CIP_PLAN_DICT_UPDATE) {
+    if (prior->kind != CIP_PRIOR_CONV3D)
+      return fail(CIP_EUNSUPPORTED, "dictionary learning: 3D conv prior only");
+    if (!(prior->sigma >= 0.0)) return fail(CIP_EINVAL, "sigma must be >= 0");
+  }
   return CIP_OK;
 }
 
@@ -206,6 +224,9 @@ struct cip_plan_s {
   bool solved_once;
   bool attached;        // shares another plan's tables
   bool adaptive;        // FP64 spectra resident: the penalty may change in a solve
+  bool learn;           // 3D conv: the dictionary is learned during every solve
+  double sigma;         // penalty of the dictionary ADMM
+  int filt_l;           // conv priors: filter side L
   int row_np;           // row pairs per work-group of the DCT row pass (2 or 4)
   int row_ppt;          // points per thread of the analysis row passes (default or 8)
   int tv_inner;         // isotropic TV: Chambolle iterations per ADMM iteration
@@ -493,6 +514,77 @@ hipError_t conv_freq_pass(cip_plan_t p, int first, int zero_g, int do_z, hipStre
                    first, zero_g, do_z, st);
 }
 
+// Online dictionary learning for the 3D conv prior (see conv.hpp).
+// Start of a solve: g = the plan's filters, e = 0, the spectra of g - e = g
+// and the filter tables from g.
+hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
+  const Layout& L = p->L;
+  const int M = p->n_filters, S = p->S, P = M * S, Lf = p->filt_l;
+  const size_t F = (size_t)p->N1 * p->H2;
+  hipError_t e = hipMemcpyAsync(p->at<void>(L.gtap), p->at<const void>(L.filt0),
+                                (size_t)P * Lf * Lf * 4, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  if ((e = cdl_dual(p->at<float>(L.ecdl), p->at<float>(L.dpl), p->at<const float>(L.gtap), M, S,
+                    p->N1, p->N2, Lf, 1, st)) != hipSuccess)
+    return e;
+  if ((e = row_r2c<float>(p->at<const float>(L.dpl), p->at<cx<float>>(L.rtc), P, p->N1, p->N2,
+                          p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
+    return e;
+  if ((e = conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gehat), P, p->N1,
+                        p->H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
+    return e;
+  return conv_tables3f(p->at<const cx<float>>(L.gehat), p->at<cx<float>>(L.th32),
+                       p->at<float>(L.gam), p->at<const cx<float>>(L.bw), M, S, F, (float)p->rho,
+                       st);
+}
+
+// One step of the dictionary ADMM after the code update of an outer
+// iteration (gv holds the new codes' plane spectra, xhat those of x):
+// d (Sherman-Morrison per 3D frequency) -> space; g = projection of d + e;
+// e += g - d and the spectra of g - e; filter tables from g; d^ = D(g) z for
+// the next x-update.
+hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
+  const Layout& L = p->L;
+  const int M = p->n_filters, S = p->S, P = M * S, Lf = p->filt_l;
+  const int N1 = p->N1, N2 = p->N2, H2 = p->H2;
+  const size_t F = (size_t)N1 * H2;
+  const cx<float>* bw = p->at<const cx<float>>(L.bw);
+  cx<float>* rtc = p->at<cx<float>>(L.rtc);
+  cx<float>* dsp = p->at<cx<float>>(L.dsp);
+  float* dpl = p->at<float>(L.dpl);
+  hipError_t e;
+  if ((e = cdl_dfreq(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
+                     p->at<const cx<float>>(L.gehat), dsp, bw, M, S, F, (float)p->sigma, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = conv_col_fft(-1, dsp, rtc, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
+    return e;
+  if ((e = row_c2r(rtc, dpl, P, N1, N2, (float)(1.0 / ((double)N1 * N2)),
+                   p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
+    return e;
+  if ((e = cdl_project(dpl, p->at<const float>(L.ecdl), p->at<float>(L.gtap), M, S, N1, N2, Lf,
+                       st)) != hipSuccess)
+    return e;
+  if ((e = cdl_dual(p->at<float>(L.ecdl), dpl, p->at<const float>(L.gtap), M, S, N1, N2, Lf, 0,
+                    st)) != hipSuccess)
+    return e;
+  if ((e = row_r2c<float>(dpl, rtc, P, N1, N2, p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
+    return e;
+  if ((e = conv_col_fft(1, rtc, p->at<cx<float>>(L.gehat), P, N1, H2,
+                        p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
+    return e;
+  if ((e = cdl_place(p->at<const float>(L.gtap), dpl, M, S, N1, N2, Lf, st)) != hipSuccess) return e;
+  if ((e = row_r2c<float>(dpl, rtc, P, N1, N2, p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
+    return e;
+  if ((e = conv_col_fft(1, rtc, dsp, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
+    return e;
+  if ((e = conv_tables3f(dsp, p->at<cx<float>>(L.th32), p->at<float>(L.gam), bw, M, S, F,
+                         (float)p->rho, st)) != hipSuccess)
+    return e;
+  return conv_dhat3(p->at<const cx<float>>(L.gv), p->at<const cx<float>>(L.th32),
+                    p->at<cx<float>>(L.dhat), bw, M, S, F, st);
+}
+
 // Algorithm 2 with the convolutional prior. Per iteration l = 1..L:
 //   frequency pass: x^l = Psi^+ (b^ + d^{l-1}); for l < L also the
 //   Sherman-Morrison code update v and d^l;
@@ -504,6 +596,7 @@ hipError_t conv_iter(cip_plan_t p, int l, int last, hipStream_t st) {
   const int P = p->n_filters * p->S;
   hipError_t e = conv_freq_pass(p, l == 1, l == 1, last ? 0 : 1, st);
   if (e != hipSuccess || last) return e;
+  if (p->learn && (e = cdl_step(p, st)) != hipSuccess) return e;
   e = conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1, p->H2,
                    p->at<const cx<float>>(L.twN1f), st);
   if (e != hipSuccess) return e;
@@ -519,6 +612,7 @@ hipError_t conv_iter(cip_plan_t p, int l, int last, hipStream_t st) {
 hipError_t solve_conv(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
   const Layout& L = p->L;
   hipError_t e;
+  if (p->learn && (e = cdl_start(p, st)) != hipSuccess) return e;
   for (int l = 1; l <= iters; ++l)
     if ((e = conv_iter(p, l, l == iters, st)) != hipSuccess) return e;
   e = conv_col_fft(-1, p->at<const cx<float>>(L.xhat), p->at<cx<float>>(L.bufB), p->S, p->N1, p->H2,
@@ -714,6 +808,9 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->solved_once = false;
   p->attached = false;
   p->adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
+  p->learn = prior->kind == CIP_PRIOR_CONV3D && (prior->flags & CIP_PLAN_DICT_UPDATE) != 0;
+  p->sigma = prior->sigma > 0.0 ? prior->sigma : 10.0;
+  p->filt_l = prior->filt_l;
   p->row_np = PAIRS;
   p->row_ppt = ppt_row_n(N2);
   p->tv_inner = prior->kind == CIP_PRIOR_ITV2D ? (prior->tv_inner > 0 ? prior->tv_inner : 20) : 0;
@@ -795,6 +892,24 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
                          prior->mu, N1, N2, st));
   }
   if (p->kind == CIP_PRIOR_CONV3D) {
+    // band DFT matrix bw[k][s] = exp(-2 pi i k s / S), formed in FP64
+    std::vector<cx<float>> bw((size_t)S * S);
+    for (int k = 0; k < S; ++k)
+      for (int s2 = 0; s2 < S; ++s2) {
+        const double a = -2.0 * kPi * (double)((k * s2) % S) / (double)S;
+        bw[(size_t)k * S + s2] = cx<float>{(float)std::cos(a), (float)std::sin(a)};
+      }
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.bw), bw.data(), bw.size() * sizeof(cx<float>),
+                            hipMemcpyHostToDevice, st));
+    PLAN_HIP(hipStreamSynchronize(st));   // bw is a host temporary
+  }
+  if (p->kind == CIP_PRIOR_CONV3D && p->learn) {
+    // the tables are formed from these filters at the start of every solve
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.filt0), prior->filters,
+                            (size_t)prior->n_filters * S * prior->filt_l * prior->filt_l * 4,
+                            hipMemcpyDeviceToDevice, st));
+  }
+  if (p->kind == CIP_PRIOR_CONV3D && !p->learn) {
     // 2D spectra of every filter slice (m, s') in FP64 -> band DFT -> theta_m(w, k)
     const int M = prior->n_filters, Lf = prior->filt_l;
     double* d_pl = p->at<double>(L.pl64);
@@ -811,15 +926,6 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     }
     PLAN_HIP(conv_tables3(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
                           p->at<float>(L.gam), M, S, (size_t)N1 * p->H2, rho, st));
-    // band DFT matrix bw[k][s] = exp(-2 pi i k s / S), formed in FP64
-    std::vector<cx<float>> bw((size_t)S * S);
-    for (int k = 0; k < S; ++k)
-      for (int s2 = 0; s2 < S; ++s2) {
-        const double a = -2.0 * kPi * (double)((k * s2) % S) / (double)S;
-        bw[(size_t)k * S + s2] = cx<float>{(float)std::cos(a), (float)std::sin(a)};
-      }
-    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.bw), bw.data(), bw.size() * sizeof(cx<float>),
-                            hipMemcpyHostToDevice, st));
     PLAN_HIP(hipStreamSynchronize(st));
   }
   if (p->kind == CIP_PRIOR_PATCH) {
@@ -894,6 +1000,16 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   }
   HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
   p->solved_once = true;
+  return CIP_OK;
+}
+
+int cip_plan_dictionary(cip_plan_t p, float* d_filters, void* stream) {
+  if (!p || !d_filters) return fail(CIP_EINVAL, "NULL argument");
+  if (!p->learn) return fail(CIP_EINVAL, "the plan does not learn its dictionary");
+  if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
+  const size_t bytes = (size_t)p->n_filters * p->S * p->filt_l * p->filt_l * 4;
+  HIP_TRY(hipMemcpyAsync(d_filters, p->at<const void>(p->L.gtap), bytes, hipMemcpyDeviceToDevice,
+                         reinterpret_cast<hipStream_t>(stream)));
   return CIP_OK;
 }
 

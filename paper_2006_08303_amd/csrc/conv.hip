@@ -65,6 +65,72 @@ hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<
   return hipErrorInvalidValue;
 }
 
+#define CIP_S_SWITCH(CASE) \
+  switch (S) {             \
+    CASE(1)                \
+    CASE(2)                \
+    CASE(3)                \
+    CASE(4)                \
+    CASE(5)                \
+    CASE(6)                \
+    CASE(7)                \
+    CASE(8)                \
+  }
+
+hipError_t cdl_dfreq(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
+                     cx<float>* dsp, const cx<float>* bw, int M, int S, size_t F, float sigma,
+                     hipStream_t st) {
+  const int grid = (int)((F + 127) / 128);
+#define CIP_DF(SS)                                                                              \
+  case SS:                                                                                      \
+    return launch(k_cdl_dfreq<SS>, grid, 128, 0, st, xhat, zh, gehat, dsp, bw, M, F, sigma);
+  CIP_S_SWITCH(CIP_DF)
+#undef CIP_DF
+  return hipErrorInvalidValue;
+}
+
+hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int S, int N1, int N2,
+                       int L, hipStream_t st) {
+  return launch(k_cdl_project, M, 256, 0, st, dpl, e, gtap, S, N1, N2, L);
+}
+
+hipError_t cdl_dual(float* e, float* dge, const float* gtap, int M, int S, int N1, int N2, int L,
+                    int init, hipStream_t st) {
+  const size_t n = (size_t)M * S * N1 * N2;
+  return launch(k_cdl_dual, (int)((n + 255) / 256), 256, 0, st, e, dge, gtap, S, N1, N2, L, n,
+                init);
+}
+
+hipError_t cdl_place(const float* gtap, float* out, int M, int S, int N1, int N2, int L,
+                     hipStream_t st) {
+  const size_t n = (size_t)M * S * N1 * N2;
+  return launch(k_cdl_place, (int)((n + 255) / 256), 256, 0, st, gtap, out, N1, N2, L, n);
+}
+
+hipError_t conv_tables3f(const cx<float>* th2, cx<float>* th32, float* gam, const cx<float>* bw,
+                         int M, int S, size_t F, float rho, hipStream_t st) {
+  const int grid = (int)((F + 127) / 128);
+#define CIP_TF(SS)                                                                    \
+  case SS:                                                                            \
+    return launch(k_conv_tables3f<SS>, grid, 128, 0, st, th2, th32, gam, bw, M, F, rho);
+  CIP_S_SWITCH(CIP_TF)
+#undef CIP_TF
+  return hipErrorInvalidValue;
+}
+
+hipError_t conv_dhat3(const cx<float>* zh, const cx<float>* th, cx<float>* dhat,
+                      const cx<float>* bw, int M, int S, size_t F, hipStream_t st) {
+  const int grid = (int)((F + 127) / 128);
+#define CIP_DH(SS)                                                                   \
+  case SS:                                                                           \
+    return launch(k_conv_dhat3<SS>, grid, 128, 0, st, zh, th, dhat, bw, M, F);
+  CIP_S_SWITCH(CIP_DH)
+#undef CIP_DH
+  return hipErrorInvalidValue;
+}
+
+#undef CIP_S_SWITCH
+
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
                     const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st) {
   CIP_DISPATCH_N(N2, {

@@ -293,6 +293,227 @@ k_conv_freq3(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat, cx<float>
   }
 }
 
+// ---------------------------------------------------------------- 3D dictionary update
+// Online update of the 3D dictionary (Eqs. d_admm, sold_3D, g_admm, h_admm),
+// one d, g, e step per outer iteration after the code update. d and e are
+// full-size (M codes of S planes, N1 x N2), g lives on the L x L x S filter
+// support (taps gtap [M][S][L][L]); spectra are unnormalised 2D DFTs per
+// plane (FL order), the band axis transformed inside the kernels.
+
+// d-update, one thread per 2D frequency: with Z_m(k), X(k), GE_m(k) the 3D
+// spectra of the codes, of x and of g - e, Eq. sold_3D at every 3D frequency
+// is (sigma I + a a^H) d = a X + sigma GE with a = conj(Z) (rank one plus
+// sigma I); Sherman-Morrison in the form without 1/sigma (as for the codes),
+//   r = (X - sum_m Z_m GE_m) / (sigma + sum_m |Z_m|^2),   d_m = GE_m + conj(Z_m) r,
+// returned as plane spectra (inverse band DFT) in dsp [M][S][F].
+template <int S>
+__global__ void __launch_bounds__(128)
+k_cdl_dfreq(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh,
+            const cx<float>* __restrict__ gehat, cx<float>* __restrict__ dsp,
+            const cx<float>* __restrict__ bw, int M, size_t F, float sigma) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  cx<float> xs[S], X[S], ag[S];
+  float aa[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) xs[s] = xhat[(size_t)s * F + f];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    X[k] = cx<float>{0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < S; ++s) X[k] = X[k] + cmul(xs[s], bw[k * S + s]);
+    ag[k] = cx<float>{0.f, 0.f};
+    aa[k] = 0.f;
+  }
+  for (int m = 0; m < M; ++m) {
+    cx<float> z[S], ge[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      z[s] = zh[((size_t)m * S + s) * F + f];
+      ge[s] = gehat[((size_t)m * S + s) * F + f];
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      cx<float> Z = {0.f, 0.f}, G = {0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        Z = Z + cmul(z[s], bw[k * S + s]);
+        G = G + cmul(ge[s], bw[k * S + s]);
+      }
+      ag[k] = ag[k] + cmul(Z, G);
+      aa[k] += Z.x * Z.x + Z.y * Z.y;
+    }
+  }
+  cx<float> r[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const float w = 1.f / (sigma + aa[k]);
+    r[k] = cx<float>{(X[k].x - ag[k].x) * w, (X[k].y - ag[k].y) * w};
+  }
+  const float invS = 1.f / (float)S;
+  for (int m = 0; m < M; ++m) {
+    cx<float> z[S], ge[S], D[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      z[s] = zh[((size_t)m * S + s) * F + f];
+      ge[s] = gehat[((size_t)m * S + s) * F + f];
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      cx<float> Z = {0.f, 0.f}, G = {0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        Z = Z + cmul(z[s], bw[k * S + s]);
+        G = G + cmul(ge[s], bw[k * S + s]);
+      }
+      D[k] = G + cmul(conjx(Z), r[k]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      cx<float> acc = {0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc = acc + cmulc(D[k], bw[k * S + s]);
+      dsp[((size_t)m * S + s) * F + f] = cx<float>{acc.x * invS, acc.y * invS};
+    }
+  }
+}
+
+// Support test of the filter grid placement: pixel (n1, n2) carries tap
+// (a, b) = ((n1 + L/2) mod N1, (n2 + L/2) mod N2) when a, b < L.
+__device__ __forceinline__ bool cdl_tap(int n1, int n2, int N1, int N2, int L, int& a, int& b) {
+  a = (n1 + L / 2) % N1;
+  b = (n2 + L / 2) % N2;
+  return a < L && b < L;
+}
+
+// g-update: per filter m (one work-group each), w = d + e on the support,
+// gtap = w / ||w||. dpl, e: [M][S][N1][N2].
+__global__ void __launch_bounds__(256)
+k_cdl_project(const float* __restrict__ dpl, const float* __restrict__ e, float* __restrict__ gtap,
+              int S, int N1, int N2, int L) {
+  const int m = blockIdx.x;
+  const int taps = S * L * L;
+  const size_t plane = (size_t)N1 * N2;
+  __shared__ float red[256];
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < taps; i += blockDim.x) {
+    const int sp = i / (L * L), a = (i / L) % L, b = i % L;
+    const int n1 = (a - L / 2 + N1) % N1, n2 = (b - L / 2 + N2) % N2;
+    const size_t o = ((size_t)m * S + sp) * plane + (size_t)n1 * N2 + n2;
+    const float w = dpl[o] + e[o];
+    acc += w * w;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const float inv = red[0] > 0.f ? 1.f / __builtin_sqrtf(red[0]) : 0.f;
+  for (int i = threadIdx.x; i < taps; i += blockDim.x) {
+    const int sp = i / (L * L), a = (i / L) % L, b = i % L;
+    const int n1 = (a - L / 2 + N1) % N1, n2 = (b - L / 2 + N2) % N2;
+    const size_t o = ((size_t)m * S + sp) * plane + (size_t)n1 * N2 + n2;
+    gtap[(size_t)m * taps + i] = (dpl[o] + e[o]) * inv;
+  }
+}
+
+// Dual update and the next right-hand side, elementwise over [M][S][N1][N2]:
+//   e <- e + g - d,   dge <- g - e  (dge holds d on entry).
+// With init set: e <- 0 and dge <- g (start of a solve, g from gtap).
+__global__ void k_cdl_dual(float* __restrict__ e, float* __restrict__ dge,
+                           const float* __restrict__ gtap, int S, int N1, int N2, int L,
+                           size_t n, int init) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t plane = (size_t)N1 * N2;
+  const size_t p = i / plane, r = i % plane;
+  const int n1 = (int)(r / N2), n2 = (int)(r % N2);
+  int a, b;
+  const float g = cdl_tap(n1, n2, N1, N2, L, a, b) ? gtap[(p * L + a) * L + b] : 0.f;
+  if (init) {
+    e[i] = 0.f;
+    dge[i] = g;
+    return;
+  }
+  const float en = e[i] + g - dge[i];
+  e[i] = en;
+  dge[i] = g - en;
+}
+
+// Grid placement of the taps gtap [M][S][L][L] -> planes [M][S][N1][N2].
+__global__ void k_cdl_place(const float* __restrict__ gtap, float* __restrict__ out, int N1, int N2,
+                            int L, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t plane = (size_t)N1 * N2;
+  const size_t p = i / plane, r = i % plane;
+  int a, b;
+  out[i] = cdl_tap((int)(r / N2), (int)(r % N2), N1, N2, L, a, b) ? gtap[(p * L + a) * L + b] : 0.f;
+}
+
+// Filter tables from the plane spectra th2 [M][S][F] of the placed taps
+// (FP32 form of k_conv_tables3): theta_m(k) = sum_s' th2_{m,s'} bw[k][s'],
+// gamma(k) = 1 / (rho + sum_m |theta_m(k)|^2).
+template <int S>
+__global__ void k_conv_tables3f(const cx<float>* __restrict__ th2, cx<float>* __restrict__ th32,
+                                float* __restrict__ gam, const cx<float>* __restrict__ bw, int M,
+                                size_t F, float rho) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  float sum[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) sum[k] = 0.f;
+  for (int m = 0; m < M; ++m) {
+    cx<float> t[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) t[s] = th2[((size_t)m * S + s) * F + f];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      cx<float> acc = {0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc = acc + cmul(t[s], bw[k * S + s]);
+      th32[((size_t)m * S + k) * F + f] = acc;
+      sum[k] += acc.x * acc.x + acc.y * acc.y;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < S; ++k) gam[(size_t)k * F + f] = 1.f / (rho + sum[k]);
+}
+
+// d^_s = sum_m theta_m z^_m per 3D frequency, back to plane spectra (after a
+// dictionary change, for the next x-update).
+template <int S>
+__global__ void k_conv_dhat3(const cx<float>* __restrict__ zh, const cx<float>* __restrict__ th,
+                             cx<float>* __restrict__ dhat, const cx<float>* __restrict__ bw, int M,
+                             size_t F) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  cx<float> dn[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) dn[k] = cx<float>{0.f, 0.f};
+  for (int m = 0; m < M; ++m) {
+    cx<float> z[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) z[s] = zh[((size_t)m * S + s) * F + f];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      cx<float> Z = {0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < S; ++s) Z = Z + cmul(z[s], bw[k * S + s]);
+      dn[k] = dn[k] + cmul(th[((size_t)m * S + k) * F + f], Z);
+    }
+  }
+  const float invS = 1.f / (float)S;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    cx<float> acc = {0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc = acc + cmulc(dn[k], bw[k * S + s]);
+    dhat[(size_t)s * F + f] = cx<float>{acc.x * invS, acc.y * invS};
+  }
+}
+
 // Row pass of the conv prior (pairs of rows of one code plane per group):
 // inverse row FFT of v (z = scale * result), state update V = z + clip(V),
 // w = 2 soft(V) - V, forward row FFT of w -> RT. first: V_prev = 0.

@@ -22,6 +22,20 @@ hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<
                       const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
                       const float* gam, const cx<float>* bw, int M, int S, size_t F, int first,
                       int zero_g, int do_z, hipStream_t st);
+// 3D dictionary update (see conv.hpp)
+hipError_t cdl_dfreq(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
+                     cx<float>* dsp, const cx<float>* bw, int M, int S, size_t F, float sigma,
+                     hipStream_t st);
+hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int S, int N1, int N2,
+                       int L, hipStream_t st);
+hipError_t cdl_dual(float* e, float* dge, const float* gtap, int M, int S, int N1, int N2, int L,
+                    int init, hipStream_t st);
+hipError_t cdl_place(const float* gtap, float* out, int M, int S, int N1, int N2, int L,
+                     hipStream_t st);
+hipError_t conv_tables3f(const cx<float>* th2, cx<float>* th32, float* gam, const cx<float>* bw,
+                         int M, int S, size_t F, float rho, hipStream_t st);
+hipError_t conv_dhat3(const cx<float>* zh, const cx<float>* th, cx<float>* dhat,
+                      const cx<float>* bw, int M, int S, size_t F, hipStream_t st);
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
                     const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st);
 

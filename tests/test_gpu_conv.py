@@ -126,3 +126,66 @@ def test_conv3d_rejects_gradient_term():
     x, psf, y, filt = _conv3_problem(32, 2, 2, 4, 3)
     with pytest.raises(cip.CipError):
         cip.Plan(_t(psf), "conv3d", 1e-4, 1.875e-6, 8.0, filters=_t(filt), mu=0.01)
+
+
+def _taps(g, L):
+    """Grid-placed filters (M, S, N1, N2) -> taps (M, S, L, L)."""
+    N1, N2 = g.shape[-2:]
+    ia = (np.arange(L) - L // 2) % N1
+    ib = (np.arange(L) - L // 2) % N2
+    return g[:, :, ia][:, :, :, ib]
+
+
+@pytest.mark.parametrize("N,K,S,M,L,iters,sigma", [(32, 2, 2, 4, 3, 6, 10.0), (64, 3, 3, 8, 5, 8, 10.0),
+                                                   (64, 3, 3, 8, 5, 8, 1.0), (32, 4, 4, 4, 3, 5, 10.0),
+                                                   (128, 3, 3, 16, 7, 4, 10.0), (64, 3, 3, 8, 5, 1, 10.0)])
+def test_conv3d_dictionary_learning_matches_oracle(N, K, S, M, L, iters, sigma):
+    """Online update of the 3D dictionary (one d, g, e step per outer
+    iteration): x and the learned filters against the FP64 oracle."""
+    print(f"conv3d dictionary learning N={N} K={K} S={S} M={M} L={L} iters={iters} "
+          f"sigma={sigma}", flush=True)
+    x, psf, y, filt = _conv3_problem(N, K, S, M, L)
+    lam, rho, beta = 1e-3, 1.0, 8.0
+    alg = admm.ConvADMM(psf, filt, lam, rho, beta, tier="freq", dims=3, dict_update=True,
+                        sigma=sigma)
+    gs = []
+    ref = alg.run(y, iters, callback=lambda it, *a: gs.append(alg.g.copy()))[0]
+    plan = cip.Plan(_t(psf), "conv3d", rho, lam, beta, filters=_t(filt), dict_update=True,
+                    sigma=sigma)
+    got = _np(plan.solve(_t(y), iters))
+    err = admm.rel_l2(got, ref)
+    g_ref = _taps(gs[iters - 2], L) if iters > 1 else filt
+    g_got = _np(plan.dictionary())
+    gerr = admm.rel_l2(g_got, g_ref)
+    moved = admm.rel_l2(g_ref, filt)
+    print(f"  x rel_l2 = {err:.3e}, filters rel_l2 = {gerr:.3e} (moved {moved:.3e} from the "
+          f"start)", flush=True)
+    assert err < 1e-4
+    assert gerr < 1e-4
+    # a second solve restarts from the plan's filters
+    again = _np(plan.solve(_t(y), iters))
+    assert np.array_equal(again, got)
+
+
+def test_conv3d_dictionary_learning_full_size_1024():
+    """K = S = 3, 1024 x 1024, 32 filters of 3 x 11 x 11, 3 iterations with
+    the dictionary update."""
+    x, psf, y, filt = _conv3_problem(1024, 3, 3, 32, 11)
+    alg = admm.ConvADMM(psf, filt, 1e-3, 1.0, 8.0, tier="freq", dims=3, dict_update=True)
+    ref = alg.run(y, 3)[0]
+    plan = cip.Plan(_t(psf), "conv3d", 1.0, 1e-3, 8.0, filters=_t(filt), dict_update=True)
+    got = _np(plan.solve(_t(y), 3))
+    err = admm.rel_l2(got, ref)
+    print(f"1024^2 conv3d + dictionary update, 3 iters: rel_l2 = {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
+def test_dictionary_learning_needs_conv3d():
+    x, psf, y, filt = _conv_problem(32, 2, 2, 4, 3)
+    with pytest.raises(cip.CipError):
+        cip.Plan(_t(psf), "conv2d", 1e-4, 1.875e-6, 8.0, filters=_t(filt), dict_update=True)
+    x, psf, y, f3 = _conv3_problem(32, 2, 2, 4, 3)
+    plan = cip.Plan(_t(psf), "conv3d", 1e-4, 1.875e-6, 8.0, filters=_t(f3))
+    plan.solve(_t(y), 2)
+    with pytest.raises(cip.CipError):
+        plan.dictionary()          # this plan does not learn its dictionary
