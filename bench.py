@@ -158,6 +158,54 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     return plan, y_t, lam, rho, beta, value, ms_step, times, names, tuning
 
 
+def run_other_priors(args, dev, psf_t, y_t):
+    """The other priors at the precision-workload shape (K = S = 3, 1024^2),
+    one solve of `iters_other` iterations each after a warm-up solve:
+    DCT3D, patch dictionary (A = 256), convolutional dictionary (32 filters
+    11 x 11; with the gradient term; 3D filters 3 x 11 x 11; 3D with online
+    dictionary learning). Parameters as in the parity tests."""
+    N, S = args.N, args.bands
+    it = args.iters_other
+    rng = synth.rng_for(3, 4)
+    D = torch.tensor(synth.random_unit_atoms(rng, 64 * S, 256), dtype=torch.float32, device=dev)
+    f2 = torch.tensor(synth.random_unit_filters(synth.rng_for(3, 5), 32, 11), dtype=torch.float32,
+                      device=dev)
+    f3 = torch.tensor(synth.random_unit_filters_3d(synth.rng_for(3, 6), 32, S, 11),
+                      dtype=torch.float32, device=dev)
+    cases = [
+        ("dct3d", dict(prior="dct3d", rho=0.1, lam=1e-2, beta=1.0), None),
+        ("patch (A = 256)", dict(prior="patch", rho=1e-4, lam=5e-6, beta=500.0, dictionary=D), 2),
+        ("conv2d (M = 32, L = 11)", dict(prior="conv2d", rho=1e-4, lam=1.875e-6, beta=8.0,
+                                         filters=f2), 2),
+        ("conv2d + gradient term (mu = 0.01)", dict(prior="conv2d", rho=1e-4, lam=1.875e-6,
+                                                    beta=8.0, filters=f2, mu=0.01), 2),
+        ("conv3d (M = 32, 3 x 11 x 11)", dict(prior="conv3d", rho=1e-4, lam=1.875e-6, beta=8.0,
+                                              filters=f3), 2),
+        ("conv3d + online dictionary update (sigma = 10)",
+         dict(prior="conv3d", rho=1.0, lam=1e-3, beta=8.0, filters=f3, dict_update=True), 2),
+    ]
+    out = {}
+    for name, kw, which in cases:
+        kw = dict(kw)
+        prior = kw.pop("prior")
+        rho, lam, beta = kw.pop("rho"), kw.pop("lam"), kw.pop("beta")
+        plan = cip.Plan(psf_t, prior, rho, lam, beta, **kw)
+        x = plan.solve(y_t, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(y_t, it, out=x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"iters": it, "ms_per_iter": round(dt * 1e3 / it, 4),
+               "Mpixel_iter_per_s": round(N * N * it / dt / 1e6, 1)}
+        if which is not None:
+            rec["sparse_code_kernel_avg_us"] = round(plan.time_kernel(which, 20), 2)
+        print(f"[bench] {name}: {rec}", file=sys.stderr, flush=True)
+        out[name] = rec
+        del plan
+    return out
+
+
 def run_concurrent(args, dev, psf_t, y_t, tuning):
     """The same K=S=3 1024^2 DCT problem, `args.concurrent` independent copies
     solved together (one captured batch over as many streams): the working
@@ -347,6 +395,8 @@ def main():
     ap.add_argument("--bands", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--iters-other", type=int, default=20,
+                    help="iterations per solve for the other priors (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--batch", type=int, default=96, help="problems in the batch run (0: skip)")
@@ -366,6 +416,7 @@ def main():
     if args.quick:
         args.no_cpu, args.no_tv, args.batch, args.serve_seconds, args.concurrent = \
             True, True, 0, 0.0, 0
+        args.iters_other = 0
     if args.gpus != 1:
         print("bench.py measures one GPU: one reconstruction runs on a single device "
               "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
@@ -411,6 +462,7 @@ def main():
         torch.cuda.synchronize()
     conc = run_concurrent(args, dev, psf_t, y_t, tuning) if args.concurrent > 1 else None
     adaptive = run_adaptive(args, dev, psf_t, y_t, tuning) if not args.quick else None
+    others = run_other_priors(args, dev, psf_t, y_t) if args.iters_other > 0 else None
     batch = run_batch(args, dev) if args.batch > 0 else None
     serving = None
     if args.serve_seconds > 0:
@@ -454,6 +506,7 @@ def main():
         "itv2d": itv,
         "concurrent_1024": conc,
         "adaptive": adaptive,
+        "other_priors": others,
         "batch": batch,
         "serving": serving,
         "latency_p50_ms": serving["continuous_batching"]["p50_ms"] if serving else None,

@@ -33,8 +33,23 @@ hipError_t conv_freq(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<f
                      const float* Adiag, const cx<float>* Aoff, const cx<float>* th,
                      const float* gam, const float* eta, int M, int S, size_t F, int first,
                      int zero_g, int do_z, hipStream_t st) {
-  return launch(k_conv_freq, (int)((F + 127) / 128), 128, 0, st, gv, dhat, xhat, xh0, Adiag, Aoff,
-                th, gam, eta, M, S, F, first, zero_g, do_z);
+  const int grid = (int)((F + 127) / 128);
+#define CIP_CF(SS)                                                                              \
+  case SS:                                                                                      \
+    return launch(k_conv_freq<SS>, grid, 128, 0, st, gv, dhat, xhat, xh0, Adiag, Aoff, th, gam, \
+                  eta, M, F, first, zero_g, do_z);
+  switch (S) {
+    CIP_CF(1)
+    CIP_CF(2)
+    CIP_CF(3)
+    CIP_CF(4)
+    CIP_CF(5)
+    CIP_CF(6)
+    CIP_CF(7)
+    CIP_CF(8)
+  }
+#undef CIP_CF
+  return hipErrorInvalidValue;
 }
 
 hipError_t conv_tables3(const cx<double>* th64, cx<float>* th32, float* gam, int M, int S,

@@ -109,21 +109,26 @@ __global__ void k_col_fft_batch(const cx<float>* __restrict__ in, cx<float>* __r
 // first: d^ = 0 (z = 0); zero_g: g^ = 0 (t = u = 0).
 constexpr int CONV_MMAX = 32;   // filters per dictionary (at most)
 
-__global__ void k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat,
-                            cx<float>* __restrict__ xhat, const cx<float>* __restrict__ xh0,
-                            const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
-                            const cx<float>* __restrict__ th, const float* __restrict__ gam,
-                            const float* __restrict__ eta, int M,
-                            int S, size_t F, int first, int zero_g, int do_z) {
+// (S is a template parameter so that the per-plane arrays stay in registers.)
+template <int S>
+__global__ void __launch_bounds__(128)
+k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat,
+            cx<float>* __restrict__ xhat, const cx<float>* __restrict__ xh0,
+            const float* __restrict__ Adiag, const cx<float>* __restrict__ Aoff,
+            const cx<float>* __restrict__ th, const float* __restrict__ gam,
+            const float* __restrict__ eta, int M, size_t F, int first, int zero_g, int do_z) {
   const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
-  cx<float> d[8], xs[8];
+  cx<float> d[S], xs[S];
+#pragma unroll
   for (int s = 0; s < S; ++s) d[s] = first ? cx<float>{0.f, 0.f} : dhat[(size_t)s * F + f];
+#pragma unroll
   for (int s = 0; s < S; ++s) {
     cx<float> acc = xh0[(size_t)s * F + f];
     const float dg = Adiag[(size_t)s * F + f];
     acc.x += dg * d[s].x;
     acc.y += dg * d[s].y;
+#pragma unroll
     for (int j = 0; j < S; ++j) {
       if (j == s) continue;
       const cx<float> a = s < j ? Aoff[(size_t)pair_index(s, j, S) * F + f]
@@ -136,31 +141,30 @@ __global__ void k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ 
   if (!do_z) return;
   cx<float> t[CONV_MMAX];
 #pragma unroll
-  for (int m = 0; m < CONV_MMAX; ++m)
-    if (m < M) t[m] = th[(size_t)m * F + f];
+  for (int m = 0; m < CONV_MMAX; ++m) t[m] = m < M ? th[(size_t)m * F + f] : cx<float>{0.f, 0.f};
   const float gm = gam[f], et = eta[f];
+#pragma unroll
   for (int s = 0; s < S; ++s) {
     cx<float> g[CONV_MMAX];
     cx<float> ag = {0.f, 0.f};   // a^H g = sum_m theta_m g_m
 #pragma unroll
     for (int m = 0; m < CONV_MMAX; ++m) {
-      if (m >= M) break;
-      if (zero_g) {
-        g[m] = cx<float>{0.f, 0.f};
-      } else {
+      g[m] = cx<float>{0.f, 0.f};
+      if (m < M && !zero_g) {
         const cx<float> gg = gv[((size_t)m * S + s) * F + f];
         g[m] = cx<float>{et * gg.x, et * gg.y};
       }
-      ag = ag + cmul(t[m], g[m]);
+      if (m < M) ag = ag + cmul(t[m], g[m]);
     }
     const cx<float> r = {(xs[s].x - ag.x) * gm, (xs[s].y - ag.y) * gm};
     cx<float> dn = {0.f, 0.f};
 #pragma unroll
     for (int m = 0; m < CONV_MMAX; ++m) {
-      if (m >= M) break;
-      const cx<float> vm = g[m] + cmulc(r, t[m]);   // g + conj(theta) r
-      gv[((size_t)m * S + s) * F + f] = vm;
-      dn = dn + cmul(t[m], vm);
+      if (m < M) {
+        const cx<float> vm = g[m] + cmulc(r, t[m]);   // g + conj(theta) r
+        gv[((size_t)m * S + s) * F + f] = vm;
+        dn = dn + cmul(t[m], vm);
+      }
     }
     dhat[(size_t)s * F + f] = dn;
   }
