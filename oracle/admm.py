@@ -295,8 +295,7 @@ class ConvADMM:
         self.theta = self.cd.spectra()                           # (M, N1, N2)
         self.dict_update = bool(dict_update)
         if self.dict_update:
-            # online update of the 3D dictionary (Eqs. d_admm, g_admm, h_admm)
-            assert self.dims == 3, "the dictionary update is built for the 3D form"
+            # online dictionary update (Eqs. d_admm, g_admm, h_admm)
             L = np.asarray(filters).shape[-1]
             self.sigma = float(sigma)
             self.support = priors.filter_on_grid(np.ones((L, L)), N1, N2) > 0   # (N1, N2)
@@ -343,7 +342,20 @@ class ConvADMM:
         """Eq. sold_3D: (sigma I + Z^H Z) d = Z^H x + sigma (g - e), Z_m the
         3D convolution by code z_m, diagonal in the 3D DFT (rank one per
         frequency plus sigma I): Sherman-Morrison at every 3D frequency.
-        d is full size (M, S, N1, N2)."""
+        d is full size (M, S, N1, N2). 2D form (common filters, the sum over
+        the planes of Section IV-B's remark): per 2D frequency the M x M
+        system sigma I + sum_s conj(Z_s) Z_s^T (rank S plus sigma I), solved
+        directly; d has shape (M, N1, N2)."""
+        if self.dims == 2:
+            xh = np.fft.fft2(x, axes=(-2, -1))                   # (S, N1, N2)
+            zh = np.fft.fft2(z, axes=(-2, -1))                   # (M, S, N1, N2)
+            geh = np.fft.fft2(self.g - self.e, axes=(-2, -1))    # (M, N1, N2)
+            rhs = np.einsum("msab,sab->mab", np.conj(zh), xh) + self.sigma * geh
+            mat = np.einsum("msab,nsab->abmn", np.conj(zh), zh)
+            mat = mat + self.sigma * np.eye(self.M)[None, None]
+            dh = np.linalg.solve(mat, np.moveaxis(rhs, 0, -1)[..., None])[..., 0]
+            return np.ascontiguousarray(np.real(np.fft.ifft2(np.moveaxis(dh, -1, 0),
+                                                             axes=(-2, -1))))
         xh = np.fft.fftn(x, axes=(0, 1, 2))
         zh = np.fft.fftn(z, axes=(1, 2, 3))
         c = np.conj(zh) * xh[None] + self.sigma * np.fft.fftn(self.g - self.e, axes=(1, 2, 3))
@@ -354,9 +366,10 @@ class ConvADMM:
         """Eq. g_admm (with e^l, the readable form of the garbled index):
         crop d + e to the L x L x S filter support and scale every filter to
         unit l2 norm (projection onto the constraint set C_d)."""
-        w = (d + self.e) * self.support[None, None]
-        n = np.sqrt(np.sum(w * w, axis=(1, 2, 3)))
-        return w / n[:, None, None, None]
+        mask = self.support if self.dims == 2 else self.support[None]
+        w = (d + self.e) * mask[None]
+        n = np.sqrt(np.sum(w.reshape(self.M, -1) ** 2, axis=1))
+        return w / n.reshape((self.M,) + (1,) * (w.ndim - 1))
 
     def set_dictionary(self, g):
         self.cd.h = g

@@ -580,6 +580,38 @@ def test_conv3d_dictionary_update_with_huge_sigma_keeps_the_dictionary():
     assert np.allclose(np.linalg.norm(alg2.g.reshape(M, -1), axis=1), 1.0, atol=1e-12)
 
 
+def test_conv2d_dictionary_d_update_solves_its_normal_equation():
+    """2D form (common filters): (sigma I + sum_s Z_s^H Z_s) d = sum_s
+    Z_s^H x_s + sigma (g - e), Z_{m,s} the 2D circular convolution by the
+    code z_{m,s} (shifts, no FFT)."""
+    S, N, M = 3, 6, 2
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=19)
+    alg = admm.ConvADMM(psf, synth.random_unit_filters(_rng(88), M, 3), 1e-3, 0.5, 10.0,
+                        tier="freq", dict_update=True, sigma=0.7)
+    alg.e = 0.1 * _rng(89).standard_normal(alg.e.shape)
+    z = _rng(90).standard_normal((M, S, N, N))
+    d = alg.d_update(x0, z)
+    resid = [sum(model.conv_circ(d[m], z[m, s]) for m in range(M)) - x0[s] for s in range(S)]
+    for m in range(M):
+        g = 0.7 * (d[m] - alg.g[m] + alg.e[m])
+        g = g + sum(model.corr_circ(resid[s], z[m, s]) for s in range(S))
+        assert np.max(np.abs(g)) < 1e-10
+
+
+def test_dictionary_learning_single_plane_3d_equals_2d():
+    """With S = 1 the 3D and 2D dictionary updates coincide."""
+    N, M = 8, 3
+    x0, psf = _small_problem(K=1, S=1, N1=N, N2=N, seed=20)
+    y = model.forward(x0, psf) + 0.01 * _rng(91).standard_normal((1, N, N))
+    f2 = synth.random_unit_filters(_rng(92), M, 3)
+    a = admm.ConvADMM(psf, f2, 1e-3, 0.5, 10.0, tier="freq", dict_update=True, sigma=2.0)
+    b = admm.ConvADMM(psf, f2[:, None], 1e-3, 0.5, 10.0, tier="freq", dims=3,
+                      dict_update=True, sigma=2.0)
+    ra, rb = a.run(y, 12), b.run(y, 12)
+    assert admm.rel_l2(rb[0], ra[0]) < 1e-12
+    assert np.max(np.abs(b.g[:, 0] - a.g)) < 1e-12
+
+
 def test_tikhonov_symbol_closed_form():
     """sum_i |DFT(r_i)|^2 of the two circular forward differences is
     (2 - 2 cos w1) + (2 - 2 cos w2)."""
