@@ -179,6 +179,8 @@ def run_other_priors(args, dev, psf_t, y_t):
                                          filters=f2), 2),
         ("conv2d + gradient term (mu = 0.01)", dict(prior="conv2d", rho=1e-4, lam=1.875e-6,
                                                     beta=8.0, filters=f2, mu=0.01), 2),
+        ("conv2d + online dictionary update (sigma = 10)",
+         dict(prior="conv2d", rho=1.0, lam=1e-3, beta=8.0, filters=f2, dict_update=True), 2),
         ("conv3d (M = 32, 3 x 11 x 11)", dict(prior="conv3d", rho=1e-4, lam=1.875e-6, beta=8.0,
                                               filters=f3), 2),
         ("conv3d + online dictionary update (sigma = 10)",

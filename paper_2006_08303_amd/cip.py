@@ -179,7 +179,7 @@ class Plan:
     filters: for prior="conv2d", float32 CUDA tensor [M, L, L] (tap (a, b) at
     offset (a - L//2, b - L//2)); for prior="conv3d", [M, S, L, L] (band tap
     s' at band offset s'); mu: gradient (Tikhonov) weight on the codes
-    (conv2d only). dict_update (conv3d): learn the dictionary online in every
+    (conv2d only). dict_update (conv priors): learn the dictionary online in every
     solve with penalty sigma (0: 10); dictionary() returns the learned filters."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,

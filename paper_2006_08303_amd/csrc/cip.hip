@@ -149,19 +149,21 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     const size_t B = kind == CIP_PRIOR_CONV3D ? (size_t)S : 1;   // band frequencies
     // a learned dictionary changes the filter tables during a solve: they
     // then belong to the solve state
-    const bool learn = kind == CIP_PRIOR_CONV3D && (prior->flags & CIP_PLAN_DICT_UPDATE);
+    const bool learn = (prior->flags & CIP_PLAN_DICT_UPDATE) != 0;
     L.th32 = learn ? sta(M * B * F * 8) : tab(M * B * F * 8);
     L.gam = learn ? sta(B * F * 4) : tab(B * F * 4);
     if (learn) {
-      const size_t taps = M * S * (size_t)prior->filt_l * prior->filt_l;
+      // filter planes: M S (3D) or M (2D, common filters)
+      const size_t P = M * B;
+      const size_t taps = P * (size_t)prior->filt_l * prior->filt_l;
       L.filt0 = tab(taps * 4);
       L.gtap = sta(taps * 4);
-      L.gehat = sta(M * S * F * 8);
-      L.dsp = sta(M * S * F * 8);
-      L.ecdl = sta(M * S * (size_t)N1 * N2 * 4);
-      L.dpl = sta(M * S * (size_t)N1 * N2 * 4);
+      L.gehat = sta(P * F * 8);
+      L.dsp = sta(P * F * 8);
+      L.ecdl = sta(P * (size_t)N1 * N2 * 4);
+      L.dpl = sta(P * (size_t)N1 * N2 * 4);
     }
-    L.eta = tab(F * 4);
+    L.eta = learn ? sta(F * 4) : tab(F * 4);
     L.bw = kind == CIP_PRIOR_CONV3D ? tab((size_t)S * S * 8) : 0;
     L.gv = sta(M * S * F * 8);
     L.dhat = sta((size_t)S * F * 8);
@@ -206,8 +208,8 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       return fail(CIP_EUNSUPPORTED, "3D conv prior: no gradient term (mu must be 0)");
   }
   if (prior->flags & CIP_PLAN_DICT_UPDATE) {
-    if (prior->kind != CIP_PRIOR_CONV3D)
-      return fail(CIP_EUNSUPPORTED, "dictionary learning: 3D conv prior only");
+    if (prior->kind != CIP_PRIOR_CONV3D && prior->kind != CIP_PRIOR_CONV2D)
+      return fail(CIP_EUNSUPPORTED, "dictionary learning: convolutional priors only");
     if (!(prior->sigma >= 0.0)) return fail(CIP_EINVAL, "sigma must be >= 0");
   }
   return CIP_OK;
@@ -226,6 +228,7 @@ struct cip_plan_s {
   bool adaptive;        // FP64 spectra resident: the penalty may change in a solve
   bool learn;           // 3D conv: the dictionary is learned during every solve
   double sigma;         // penalty of the dictionary ADMM
+  double mu;            // conv prior: gradient (Tikhonov) weight
   int filt_l;           // conv priors: filter side L
   int row_np;           // row pairs per work-group of the DCT row pass (2 or 4)
   int row_ppt;          // points per thread of the analysis row passes (default or 8)
@@ -514,17 +517,29 @@ hipError_t conv_freq_pass(cip_plan_t p, int first, int zero_g, int do_z, hipStre
                    first, zero_g, do_z, st);
 }
 
-// Online dictionary learning for the 3D conv prior (see conv.hpp).
-// Start of a solve: g = the plan's filters, e = 0, the spectra of g - e = g
-// and the filter tables from g.
+// Online dictionary learning for the conv priors (see conv.hpp). Filter
+// planes P = M S (3D) or M (2D, common filters); filter tables from g in
+// FP32. Start of a solve: g = the plan's filters, e = 0, the spectra of
+// g - e = g, and the tables from g.
+hipError_t cdl_tables(cip_plan_t p, const cx<float>* gspec, hipStream_t st) {
+  const Layout& L = p->L;
+  const size_t F = (size_t)p->N1 * p->H2;
+  if (p->kind == CIP_PRIOR_CONV3D)
+    return conv_tables3f(gspec, p->at<cx<float>>(L.th32), p->at<float>(L.gam),
+                         p->at<const cx<float>>(L.bw), p->n_filters, p->S, F, (float)p->rho, st);
+  return conv_tables2f(p->at<const cx<float>>(L.th32), p->at<float>(L.gam), p->at<float>(L.eta),
+                       p->n_filters, F, p->rho, p->mu, p->N1, p->N2, st);
+}
+
 hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
   const Layout& L = p->L;
-  const int M = p->n_filters, S = p->S, P = M * S, Lf = p->filt_l;
+  const bool d3 = p->kind == CIP_PRIOR_CONV3D;
+  const int M = p->n_filters, per = d3 ? p->S : 1, P = M * per, Lf = p->filt_l;
   const size_t F = (size_t)p->N1 * p->H2;
   hipError_t e = hipMemcpyAsync(p->at<void>(L.gtap), p->at<const void>(L.filt0),
                                 (size_t)P * Lf * Lf * 4, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;
-  if ((e = cdl_dual(p->at<float>(L.ecdl), p->at<float>(L.dpl), p->at<const float>(L.gtap), M, S,
+  if ((e = cdl_dual(p->at<float>(L.ecdl), p->at<float>(L.dpl), p->at<const float>(L.gtap), M, per,
                     p->N1, p->N2, Lf, 1, st)) != hipSuccess)
     return e;
   if ((e = row_r2c<float>(p->at<const float>(L.dpl), p->at<cx<float>>(L.rtc), P, p->N1, p->N2,
@@ -533,39 +548,44 @@ hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
   if ((e = conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gehat), P, p->N1,
                         p->H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
-  return conv_tables3f(p->at<const cx<float>>(L.gehat), p->at<cx<float>>(L.th32),
-                       p->at<float>(L.gam), p->at<const cx<float>>(L.bw), M, S, F, (float)p->rho,
-                       st);
+  if (!d3 && (e = hipMemcpyAsync(p->at<void>(L.th32), p->at<const void>(L.gehat), (size_t)P * F * 8,
+                                 hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return e;
+  return cdl_tables(p, p->at<const cx<float>>(L.gehat), st);
 }
 
 // One step of the dictionary ADMM after the code update of an outer
 // iteration (gv holds the new codes' plane spectra, xhat those of x):
-// d (Sherman-Morrison per 3D frequency) -> space; g = projection of d + e;
-// e += g - d and the spectra of g - e; filter tables from g; d^ = D(g) z for
-// the next x-update.
+// d (3D: Sherman-Morrison per 3D frequency; 2D: Woodbury with an S x S
+// Cholesky per frequency) -> space; g = projection of d + e; e += g - d and
+// the spectra of g - e; filter tables from g; d^ = D(g) z for the next
+// x-update.
 hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
   const Layout& L = p->L;
-  const int M = p->n_filters, S = p->S, P = M * S, Lf = p->filt_l;
+  const bool d3 = p->kind == CIP_PRIOR_CONV3D;
+  const int M = p->n_filters, S = p->S, per = d3 ? S : 1, P = M * per, Lf = p->filt_l;
   const int N1 = p->N1, N2 = p->N2, H2 = p->H2;
   const size_t F = (size_t)N1 * H2;
-  const cx<float>* bw = p->at<const cx<float>>(L.bw);
+  const cx<float>* bw = d3 ? p->at<const cx<float>>(L.bw) : nullptr;
   cx<float>* rtc = p->at<cx<float>>(L.rtc);
   cx<float>* dsp = p->at<cx<float>>(L.dsp);
   float* dpl = p->at<float>(L.dpl);
-  hipError_t e;
-  if ((e = cdl_dfreq(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
-                     p->at<const cx<float>>(L.gehat), dsp, bw, M, S, F, (float)p->sigma, st)) !=
-      hipSuccess)
-    return e;
+  hipError_t e = d3 ? cdl_dfreq(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
+                                p->at<const cx<float>>(L.gehat), dsp, bw, M, S, F, (float)p->sigma,
+                                st)
+                    : cdl_dfreq2(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
+                                 p->at<const cx<float>>(L.gehat), dsp, M, S, F, (float)p->sigma,
+                                 st);
+  if (e != hipSuccess) return e;
   if ((e = conv_col_fft(-1, dsp, rtc, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
   if ((e = row_c2r(rtc, dpl, P, N1, N2, (float)(1.0 / ((double)N1 * N2)),
                    p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
     return e;
-  if ((e = cdl_project(dpl, p->at<const float>(L.ecdl), p->at<float>(L.gtap), M, S, N1, N2, Lf,
+  if ((e = cdl_project(dpl, p->at<const float>(L.ecdl), p->at<float>(L.gtap), M, per, N1, N2, Lf,
                        st)) != hipSuccess)
     return e;
-  if ((e = cdl_dual(p->at<float>(L.ecdl), dpl, p->at<const float>(L.gtap), M, S, N1, N2, Lf, 0,
+  if ((e = cdl_dual(p->at<float>(L.ecdl), dpl, p->at<const float>(L.gtap), M, per, N1, N2, Lf, 0,
                     st)) != hipSuccess)
     return e;
   if ((e = row_r2c<float>(dpl, rtc, P, N1, N2, p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
@@ -573,16 +593,21 @@ hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
   if ((e = conv_col_fft(1, rtc, p->at<cx<float>>(L.gehat), P, N1, H2,
                         p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
-  if ((e = cdl_place(p->at<const float>(L.gtap), dpl, M, S, N1, N2, Lf, st)) != hipSuccess) return e;
+  if ((e = cdl_place(p->at<const float>(L.gtap), dpl, M, per, N1, N2, Lf, st)) != hipSuccess)
+    return e;
   if ((e = row_r2c<float>(dpl, rtc, P, N1, N2, p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
     return e;
-  if ((e = conv_col_fft(1, rtc, dsp, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
+  // 3D: plane spectra to dsp, then the band DFT into the tables; 2D: the
+  // spectra are the tables
+  cx<float>* gspec = d3 ? dsp : p->at<cx<float>>(L.th32);
+  if ((e = conv_col_fft(1, rtc, gspec, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
-  if ((e = conv_tables3f(dsp, p->at<cx<float>>(L.th32), p->at<float>(L.gam), bw, M, S, F,
-                         (float)p->rho, st)) != hipSuccess)
-    return e;
-  return conv_dhat3(p->at<const cx<float>>(L.gv), p->at<const cx<float>>(L.th32),
-                    p->at<cx<float>>(L.dhat), bw, M, S, F, st);
+  if ((e = cdl_tables(p, gspec, st)) != hipSuccess) return e;
+  if (d3)
+    return conv_dhat3(p->at<const cx<float>>(L.gv), p->at<const cx<float>>(L.th32),
+                      p->at<cx<float>>(L.dhat), bw, M, S, F, st);
+  return conv_dhat2(p->at<const cx<float>>(L.gv), p->at<const cx<float>>(L.th32),
+                    p->at<cx<float>>(L.dhat), M, S, F, st);
 }
 
 // Algorithm 2 with the convolutional prior. Per iteration l = 1..L:
@@ -808,7 +833,9 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->solved_once = false;
   p->attached = false;
   p->adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
-  p->learn = prior->kind == CIP_PRIOR_CONV3D && (prior->flags & CIP_PLAN_DICT_UPDATE) != 0;
+  p->learn = (prior->kind == CIP_PRIOR_CONV3D || prior->kind == CIP_PRIOR_CONV2D) &&
+             (prior->flags & CIP_PLAN_DICT_UPDATE) != 0;
+  p->mu = prior->mu;
   p->sigma = prior->sigma > 0.0 ? prior->sigma : 10.0;
   p->filt_l = prior->filt_l;
   p->row_np = PAIRS;
@@ -875,7 +902,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     }
   }
   PLAN_HIP(gram(p, st));
-  if (p->kind == CIP_PRIOR_CONV2D) {
+  if (p->kind == CIP_PRIOR_CONV2D && !p->learn) {
     // filter spectra theta_m in FP64 (same transform path as the kernels)
     const int M = prior->n_filters, Lf = prior->filt_l;
     double* d_pl = p->at<double>(L.pl64);
@@ -903,11 +930,12 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
                             hipMemcpyHostToDevice, st));
     PLAN_HIP(hipStreamSynchronize(st));   // bw is a host temporary
   }
-  if (p->kind == CIP_PRIOR_CONV3D && p->learn) {
+  if (p->learn) {
     // the tables are formed from these filters at the start of every solve
+    const size_t planes = (size_t)prior->n_filters * (p->kind == CIP_PRIOR_CONV3D ? S : 1);
     PLAN_HIP(hipMemcpyAsync(p->at<void>(L.filt0), prior->filters,
-                            (size_t)prior->n_filters * S * prior->filt_l * prior->filt_l * 4,
-                            hipMemcpyDeviceToDevice, st));
+                            planes * prior->filt_l * prior->filt_l * 4, hipMemcpyDeviceToDevice,
+                            st));
   }
   if (p->kind == CIP_PRIOR_CONV3D && !p->learn) {
     // 2D spectra of every filter slice (m, s') in FP64 -> band DFT -> theta_m(w, k)
@@ -1007,7 +1035,8 @@ int cip_plan_dictionary(cip_plan_t p, float* d_filters, void* stream) {
   if (!p || !d_filters) return fail(CIP_EINVAL, "NULL argument");
   if (!p->learn) return fail(CIP_EINVAL, "the plan does not learn its dictionary");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
-  const size_t bytes = (size_t)p->n_filters * p->S * p->filt_l * p->filt_l * 4;
+  const size_t planes = (size_t)p->n_filters * (p->kind == CIP_PRIOR_CONV3D ? p->S : 1);
+  const size_t bytes = planes * p->filt_l * p->filt_l * 4;
   HIP_TRY(hipMemcpyAsync(d_filters, p->at<const void>(p->L.gtap), bytes, hipMemcpyDeviceToDevice,
                          reinterpret_cast<hipStream_t>(stream)));
   return CIP_OK;

@@ -104,6 +104,28 @@ hipError_t cdl_dfreq(const cx<float>* xhat, const cx<float>* zh, const cx<float>
   return hipErrorInvalidValue;
 }
 
+hipError_t cdl_dfreq2(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
+                      cx<float>* dsp, int M, int S, size_t F, float sigma, hipStream_t st) {
+  const int grid = (int)((F + 127) / 128);
+#define CIP_DF2(SS)                                                                          \
+  case SS:                                                                                   \
+    return launch(k_cdl_dfreq2<SS>, grid, 128, 0, st, xhat, zh, gehat, dsp, M, F, sigma);
+  CIP_S_SWITCH(CIP_DF2)
+#undef CIP_DF2
+  return hipErrorInvalidValue;
+}
+
+hipError_t conv_tables2f(const cx<float>* th, float* gam, float* eta, int M, size_t F, double rho,
+                         double mu, int N1, int N2, hipStream_t st) {
+  return launch(k_conv_tables2f, (int)((F + 255) / 256), 256, 0, st, th, gam, eta, M, F, rho, mu,
+                N1, N2);
+}
+
+hipError_t conv_dhat2(const cx<float>* zh, const cx<float>* th, cx<float>* dhat, int M, int S,
+                      size_t F, hipStream_t st) {
+  return launch(k_conv_dhat2, (int)((F + 255) / 256), 256, 0, st, zh, th, dhat, M, S, F);
+}
+
 hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int S, int N1, int N2,
                        int L, hipStream_t st) {
   return launch(k_cdl_project, M, 256, 0, st, dpl, e, gtap, S, N1, N2, L);

@@ -382,6 +382,114 @@ k_cdl_dfreq(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh
   }
 }
 
+// d-update of the 2D form (common filters): per 2D frequency the normal
+// equation (sigma I + A A^H) d = A X + sigma GE with A = [a_1 .. a_S],
+// a_s = conj(Z_{.,s}) (rank S plus sigma I; the sum over the planes noted in
+// Section IV-B). Solved through the Woodbury identity in the form without
+// 1/sigma,  d = GE + A y,  (sigma I_S + A^H A) y = X - A^H GE,
+// with an S x S complex Cholesky factorisation per frequency.
+// zh [M][S][F] (codes), xhat [S][F], gehat and dsp [M][F].
+template <int S>
+__global__ void __launch_bounds__(128)
+k_cdl_dfreq2(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh,
+             const cx<float>* __restrict__ gehat, cx<float>* __restrict__ dsp, int M, size_t F,
+             float sigma) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  cx<float> B[S][S], w[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    w[s] = xhat[(size_t)s * F + f];
+#pragma unroll
+    for (int t = 0; t < S; ++t) B[s][t] = cx<float>{0.f, 0.f};
+  }
+  for (int m = 0; m < M; ++m) {
+    cx<float> z[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) z[s] = zh[((size_t)m * S + s) * F + f];
+    const cx<float> ge = gehat[(size_t)m * F + f];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      w[s] = w[s] - cmul(z[s], ge);                                  // X - A^H GE
+#pragma unroll
+      for (int t = s; t < S; ++t) B[s][t] = B[s][t] + cmulc(z[s], z[t]);   // (A^H A)_{s,t}
+    }
+  }
+  // Cholesky B = L L^H (B[s][t], t >= s, holds the upper triangle); L in the
+  // lower triangle of B
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    float djj = B[j][j].x + sigma;
+#pragma unroll
+    for (int k = 0; k < j; ++k) djj -= B[j][k].x * B[j][k].x + B[j][k].y * B[j][k].y;
+    const float ljj = __builtin_sqrtf(djj), il = 1.f / ljj;
+    B[j][j] = cx<float>{ljj, 0.f};
+#pragma unroll
+    for (int i = j + 1; i < S; ++i) {
+      cx<float> a = conjx(B[j][i]);   // B[i][j] = conj(B[j][i])
+#pragma unroll
+      for (int k = 0; k < j; ++k) a = a - cmulc(B[i][k], B[j][k]);
+      B[i][j] = cx<float>{a.x * il, a.y * il};
+    }
+  }
+  // L u = w, then L^H y = u
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    cx<float> a = w[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) a = a - cmul(B[i][k], w[k]);
+    w[i] = cx<float>{a.x / B[i][i].x, a.y / B[i][i].x};
+  }
+#pragma unroll
+  for (int i = S - 1; i >= 0; --i) {
+    cx<float> a = w[i];
+#pragma unroll
+    for (int k = i + 1; k < S; ++k) a = a - cmul(conjx(B[k][i]), w[k]);
+    w[i] = cx<float>{a.x / B[i][i].x, a.y / B[i][i].x};
+  }
+  for (int m = 0; m < M; ++m) {
+    cx<float> d = gehat[(size_t)m * F + f];
+#pragma unroll
+    for (int s = 0; s < S; ++s) d = d + cmul(conjx(zh[((size_t)m * S + s) * F + f]), w[s]);
+    dsp[(size_t)m * F + f] = d;
+  }
+}
+
+// Filter tables of the 2D form from FP32 spectra (theta already in th):
+// gamma = 1 / (c + sum_m |theta_m|^2), eta = rho / c, c = rho + mu psi(w).
+__global__ void k_conv_tables2f(const cx<float>* __restrict__ th, float* __restrict__ gam,
+                                float* __restrict__ eta, int M, size_t F, double rho, double mu,
+                                int N1, int N2) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  float sum = 0.f;
+  for (int m = 0; m < M; ++m) {
+    const cx<float> t = th[(size_t)m * F + f];
+    sum += t.x * t.x + t.y * t.y;
+  }
+  double c = rho;
+  if (mu > 0.0) {
+    const int k2 = (int)(f / N1), k1 = (int)(f % N1);
+    c += mu * ((2.0 - 2.0 * cospi(2.0 * (double)k1 / (double)N1)) +
+               (2.0 - 2.0 * cospi(2.0 * (double)k2 / (double)N2)));
+  }
+  gam[f] = (float)(1.0 / (c + (double)sum));
+  eta[f] = (float)(rho / c);
+}
+
+// d^_s = sum_m theta_m z^_{m,s} (2D form), after a dictionary change.
+__global__ void k_conv_dhat2(const cx<float>* __restrict__ zh, const cx<float>* __restrict__ th,
+                             cx<float>* __restrict__ dhat, int M, int S, size_t F) {
+  const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  for (int s = 0; s < S; ++s) {
+    cx<float> acc = {0.f, 0.f};
+    for (int m = 0; m < M; ++m)
+      acc = acc + cmul(th[(size_t)m * F + f], zh[((size_t)m * S + s) * F + f]);
+    dhat[(size_t)s * F + f] = acc;
+  }
+}
+
 // Support test of the filter grid placement: pixel (n1, n2) carries tap
 // (a, b) = ((n1 + L/2) mod N1, (n2 + L/2) mod N2) when a, b < L.
 __device__ __forceinline__ bool cdl_tap(int n1, int n2, int N1, int N2, int L, int& a, int& b) {

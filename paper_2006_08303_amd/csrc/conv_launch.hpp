@@ -26,6 +26,12 @@ hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<
 hipError_t cdl_dfreq(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
                      cx<float>* dsp, const cx<float>* bw, int M, int S, size_t F, float sigma,
                      hipStream_t st);
+hipError_t cdl_dfreq2(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
+                      cx<float>* dsp, int M, int S, size_t F, float sigma, hipStream_t st);
+hipError_t conv_tables2f(const cx<float>* th, float* gam, float* eta, int M, size_t F, double rho,
+                         double mu, int N1, int N2, hipStream_t st);
+hipError_t conv_dhat2(const cx<float>* zh, const cx<float>* th, cx<float>* dhat, int M, int S,
+                      size_t F, hipStream_t st);
 hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int S, int N1, int N2,
                        int L, hipStream_t st);
 hipError_t cdl_dual(float* e, float* dge, const float* gtap, int M, int S, int N1, int N2, int L,

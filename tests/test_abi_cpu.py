@@ -102,9 +102,9 @@ def test_new_entry_points_validate_before_device_work(L):
 
 
 def test_conv3d_and_dictionary_learning_validation(L):
-    """3D conv prior: workspace holds the band tables; dictionary learning is
-    refused for other priors and with a negative sigma, and grows the solve
-    state (d, e and the g - e spectra are full size)."""
+    """3D conv prior: workspace holds the band tables; dictionary learning
+    (conv priors only) is refused for other priors and with a negative sigma,
+    and grows the solve state (d, e and the g - e spectra are full size)."""
     from paper_2006_08303_amd import cip
     K, S, N, M, Lf = 3, 3, 64, 4, 5
     base = cip.workspace_bytes(K, S, N, N, "conv3d", n_filters=M, filt_l=Lf)
@@ -113,9 +113,12 @@ def test_conv3d_and_dictionary_learning_validation(L):
     F = N * (N // 2 + 1)
     assert learn >= base + 2 * M * S * F * 8 + 2 * M * S * N * N * 4
     with pytest.raises(cip.CipError) as e:
-        cip.workspace_bytes(K, S, N, N, "conv2d", n_filters=M, filt_l=Lf,
-                            flags=cip.CIP_PLAN_DICT_UPDATE)
+        cip.workspace_bytes(K, S, N, N, "dct2d", flags=cip.CIP_PLAN_DICT_UPDATE)
     assert e.value.code == -2
+    b2 = cip.workspace_bytes(K, S, N, N, "conv2d", n_filters=M, filt_l=Lf)
+    l2 = cip.workspace_bytes(K, S, N, N, "conv2d", n_filters=M, filt_l=Lf,
+                             flags=cip.CIP_PLAN_DICT_UPDATE)
+    assert l2 >= b2 + 2 * M * F * 8 + 2 * M * N * N * 4
     desc = cip._desc("conv3d", 1.0, flags=cip.CIP_PLAN_DICT_UPDATE, sigma=-1.0)
     desc.n_filters, desc.filt_l = M, Lf
     n = ctypes.c_size_t()
