@@ -193,9 +193,17 @@ class PatchADMM:
     """Algorithm 2 with the patch-based dictionary prior.
 
     D has shape (n, A) with n = Q*Q*S (column a = atom a, element layout as in
-    ``priors.Patches``); codes z, t, u have shape (A, J)."""
+    ``priors.Patches``); codes z, t, u have shape (A, J).
 
-    def __init__(self, psf, D, Q, stride, lam, rho, beta, tier="auto"):
+    dict_update: learn the dictionary online (Section IV-B, patch-based
+    dictionary update): after the code update of each outer iteration one
+    step of the dictionary ADMM, Eqs. ADMM0 (closed form Eq. sold_patch),
+    ADMM1 (projection onto ||G||_F = 1, the constraint of Eq.
+    patch_based_dic) and subh, starting from G = D, E = 0; the next x- and
+    z-updates use G."""
+
+    def __init__(self, psf, D, Q, stride, lam, rho, beta, tier="auto", dict_update=False,
+                 sigma=1.0):
         K, S, N1, N2 = psf.shape
         self.psf = psf
         self.S, self.N1, self.N2 = S, N1, N2
@@ -209,8 +217,35 @@ class PatchADMM:
             self.solver = xupdate.DenseSolver(psf, beta, cP * np.eye(S * N1 * N2))
         else:
             self.solver = xupdate.FreqSolver(psf, beta, cP, np.ones((N1, N2)))
+        self.dict_update, self.sigma = bool(dict_update), float(sigma)
+        self.g = self.D.copy()
+        self.e = np.zeros_like(self.D)
+        self.set_dictionary(self.D)
+
+    def set_dictionary(self, D):
+        """Use dictionary D in the following x- and z-updates."""
+        self.D = np.array(D, dtype=np.float64)
         A = self.D.shape[1]
-        self.zgram = rho * np.eye(A) + self.D.T @ self.D     # rho I + D^T D
+        self.zgram = self.rho * np.eye(A) + self.D.T @ self.D     # rho I + D^T D
+
+    def d_update_patches(self, X, z):
+        """Eq. sold_patch: D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1
+        for patch matrix X (n x J) and codes Z (A x J); the system matrix
+        is symmetric, so D^T solves (Z Z^T + sigma I) D^T = (X Z^T +
+        sigma (G - E))^T."""
+        A = z.shape[0]
+        rhs = X @ z.T + self.sigma * (self.g - self.e)
+        return np.linalg.solve(z @ z.T + self.sigma * np.eye(A), rhs.T).T
+
+    def d_update(self, x, z):
+        """Eq. ADMM0 with X = [P_1 x | ... | P_J x]."""
+        return self.d_update_patches(self.P.extract(x), z)
+
+    def g_update(self, d):
+        """Eq. ADMM1: the point of the unit Frobenius sphere nearest to
+        D + E, i.e. (D + E) / ||D + E||_F."""
+        w = d + self.e
+        return w / np.linalg.norm(w)
 
     def x_update(self, data, z):
         extra = self.P.adjoint(self.D @ z)                    # P^H D~ z
@@ -237,6 +272,14 @@ class PatchADMM:
             t_new = priors.soft(z + u, kappa)
             u = u + z - t_new
             t = t_new
+            if self.dict_update:
+                # one D, G, E step per outer iteration (Eqs. ADMM0, ADMM1,
+                # subh); the next x- and z-updates use the feasible G
+                d = self.d_update(x, z)
+                g = self.g_update(d)
+                self.e = self.e + g - d
+                self.g = g
+                self.set_dictionary(g)
             if callback is not None:
                 callback(it, x, z, t, u)
         return x, z, t, u

@@ -402,6 +402,103 @@ def test_patch_admm_kkt():
     assert np.linalg.norm(t - priors.soft(t + u, lam / rho)) < 1e-6 * np.linalg.norm(t)
 
 
+def _patch_dl(seed, S=2, N=8, A=24, sigma=0.7):
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=seed)
+    D = synth.random_unit_atoms(_rng(seed + 200), 4 * 4 * S, A)
+    D = D / np.linalg.norm(D)
+    alg = admm.PatchADMM(psf, D, Q=4, stride=2, lam=1e-3, rho=0.3, beta=10.0,
+                         dict_update=True, sigma=sigma)
+    return x0, psf, alg
+
+
+def test_patch_dictionary_d_update_minimises_its_objective():
+    """Eq. ADMM0: the D-update minimises 1/2 ||D Z - X||_F^2 + sigma/2
+    ||D - G + E||_F^2 (checked against a least-squares solve of the stacked
+    system [Z^T; sqrt(sigma) I] D^T = [X^T; sqrt(sigma) (G - E)^T] and by
+    random perturbations)."""
+    x0, psf, alg = _patch_dl(30)
+    A, n = alg.D.shape[1], alg.D.shape[0]
+    alg.g = _rng(31).standard_normal((n, A))
+    alg.e = 0.3 * _rng(32).standard_normal((n, A))
+    X = _rng(33).standard_normal((n, 50))
+    Z = _rng(34).standard_normal((A, 50))
+    D = alg.d_update_patches(X, Z)
+    sq = math.sqrt(alg.sigma)
+    lhs = np.vstack([Z.T, sq * np.eye(A)])
+    rhs = np.vstack([X.T, sq * (alg.g - alg.e).T])
+    ref = np.linalg.lstsq(lhs, rhs, rcond=None)[0].T
+    assert np.max(np.abs(D - ref)) < 1e-10
+
+    def f(Dm):
+        return 0.5 * np.sum((Dm @ Z - X) ** 2) + 0.5 * alg.sigma * np.sum((Dm - alg.g + alg.e) ** 2)
+    f0 = f(D)
+    for i in range(5):
+        assert f(D + 1e-3 * _rng(35 + i).standard_normal(D.shape)) > f0
+
+
+def test_patch_dictionary_d_update_recovers_a_consistent_dictionary():
+    """With X = D* Z exactly and a vanishing sigma, Eq. sold_patch returns
+    D* (Z has full row rank)."""
+    x0, psf, alg = _patch_dl(40, sigma=1e-12)
+    n, A = alg.D.shape
+    Dstar = _rng(41).standard_normal((n, A))
+    Z = _rng(42).standard_normal((A, 200))
+    D = alg.d_update_patches(Dstar @ Z, Z)
+    assert np.max(np.abs(D - Dstar)) < 1e-8
+
+
+def test_patch_dictionary_g_update_is_the_projection():
+    """Eq. ADMM1: G is the point of the unit Frobenius sphere nearest to
+    D + E: unit norm, a positive multiple of D + E, and no random unit
+    matrix is closer."""
+    x0, psf, alg = _patch_dl(50)
+    n, A = alg.D.shape
+    d = _rng(51).standard_normal((n, A))
+    alg.e = _rng(52).standard_normal((n, A))
+    g = alg.g_update(d)
+    w = d + alg.e
+    assert abs(np.linalg.norm(g) - 1.0) < 1e-12
+    c = np.sum(g * w) / np.sum(w * w)
+    assert c > 0 and np.max(np.abs(g - c * w)) < 1e-14
+    dist = np.linalg.norm(g - w)
+    for i in range(20):
+        q = _rng(53 + i).standard_normal((n, A))
+        assert np.linalg.norm(q / np.linalg.norm(q) - w) > dist
+
+
+def test_patch_dictionary_update_with_huge_sigma_keeps_the_dictionary():
+    """sigma -> infinity pins D to G - E = G; with ||G||_F = 1 the
+    projection keeps it, so the run equals the fixed-dictionary run; a
+    finite sigma moves the dictionary and keeps ||G||_F = 1."""
+    S, N = 2, 8
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=60)
+    y = model.forward(x0, psf) + 0.01 * _rng(61).standard_normal((2, N, N))
+    D = synth.random_unit_atoms(_rng(62), 4 * 4 * S, 24)
+    D = D / np.linalg.norm(D)
+    kw = dict(Q=4, stride=2, lam=1e-3, rho=0.3, beta=10.0)
+    a = admm.PatchADMM(psf, D, **kw).run(y, 10)
+    b = admm.PatchADMM(psf, D, dict_update=True, sigma=1e12, **kw).run(y, 10)
+    assert admm.rel_l2(b[0], a[0]) < 1e-8
+    alg = admm.PatchADMM(psf, D, dict_update=True, sigma=1.0, **kw)
+    c = alg.run(y, 10)
+    assert admm.rel_l2(c[0], a[0]) > 1e-4
+    assert abs(np.linalg.norm(alg.g) - 1.0) < 1e-12
+    assert np.max(np.abs(alg.D - alg.g)) == 0.0
+
+
+def test_patch_dictionary_learning_lowers_the_patch_fit():
+    """With E = 0, Eq. ADMM0 minimises fit(D) + sigma/2 ||D - G||_F^2 with
+    fit(D) = 1/2 ||D Z - X||_F^2, whose value at D = G is fit(G): the D-step
+    satisfies fit(D) + sigma/2 ||D - G||_F^2 <= fit(G)."""
+    x0, psf, alg = _patch_dl(70, sigma=0.05)
+    n, A = alg.D.shape
+    X = alg.P.extract(x0)
+    Z = _rng(71).standard_normal((A, alg.P.J)) * 0.1
+    D = alg.d_update_patches(X, Z)
+    fit = lambda Dm: 0.5 * np.sum((Dm @ Z - X) ** 2)
+    assert fit(D) + 0.5 * alg.sigma * np.sum((D - alg.g) ** 2) <= fit(alg.g) + 1e-12
+
+
 def test_sherman_morrison_equals_dense_solve():
     """Eq. solz_DFT_SM equals a dense solve of (rho I + Theta^H Theta) v = c."""
     rng = _rng(30)
