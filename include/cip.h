@@ -117,12 +117,14 @@ typedef struct {
   int flags;            /* CIP_PLAN_ADAPTIVE: keep the FP64 kernel spectra
                            resident (K*S*N1*(N2/2+1)*16 more bytes) so that
                            cip_solve_adaptive can change the penalty;
-                           CIP_PLAN_DICT_UPDATE (CIP_PRIOR_CONV2D and
-                           CIP_PRIOR_CONV3D): learn the dictionary online
-                           during every solve                              */
+                           CIP_PLAN_DICT_UPDATE (CIP_PRIOR_PATCH,
+                           CIP_PRIOR_CONV2D and CIP_PRIOR_CONV3D): learn
+                           the dictionary online during every solve         */
   /* CIP_PLAN_DICT_UPDATE only:                                               */
-  double sigma;         /* penalty of the dictionary ADMM (Eq. d_admm);
-                           0: 10 (the paper's 3D setting), > 0              */
+  double sigma;         /* penalty of the dictionary ADMM (Eqs. ADMM0 and
+                           d_admm), > 0; 0 selects the paper's settings: 1
+                           for the patch dictionary, 10 for the
+                           convolutional one                               */
 } cip_prior_desc;
 
 enum { CIP_PLAN_ADAPTIVE = 1, CIP_PLAN_DICT_UPDATE = 2 };
@@ -180,18 +182,26 @@ int cip_adjoint(cip_plan_t plan, const float* d_y, float* d_x, void* stream);
  * call. A plan runs one solve at a time (its state lives in the workspace). */
 int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* stream);
 
-/* Online dictionary learning (conv priors with CIP_PLAN_DICT_UPDATE, the
- * dictionary update of Section IV-B: Eqs. d_admm, sold_3D, g_admm, h_admm).
- * Every cip_solve then starts from the plan's filters and, after the code
- * update of each outer iteration l < iters, takes one step of the
- * dictionary ADMM: d full size (3D: Sherman-Morrison at every 3D frequency;
- * 2D: the rank-S system of the common filters per 2D frequency, by the
- * Woodbury identity), g = d + e cropped to the filter support and scaled to
- * unit norm per filter, e <- e + g - d; the next x- and code updates use g.
- * This call copies g of the last solve (the filters' layout: [M][L][L] or
- * [M][S][L][L] float32) to the device buffer d_filters, asynchronously on
- * `stream`. CIP_EINVAL if the plan does not learn its dictionary or has not
- * solved yet. */
+/* Online dictionary learning (plans created with CIP_PLAN_DICT_UPDATE, the
+ * dictionary update of Section IV-B). Every cip_solve then starts from the
+ * plan's dictionary and, after the code update of each outer iteration
+ * l < iters, takes one step of the dictionary ADMM; the next x- and code
+ * updates use the new dictionary g.
+ *   Convolutional priors (Eqs. d_admm, sold_3D, g_admm, h_admm): d full
+ *   size (3D: Sherman-Morrison at every 3D frequency; 2D: the rank-S system
+ *   of the common filters per 2D frequency, by the Woodbury identity),
+ *   g = d + e cropped to the filter support and scaled to unit norm per
+ *   filter, e <- e + g - d.
+ *   Patch prior (Eqs. ADMM0, sold_patch, ADMM1, subh): with the patch matrix
+ *   X = [P_1 x | ... | P_J x] and the codes Z of the iteration,
+ *   D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1, G = (D + E) / ||D + E||_F
+ *   (the constraint ||D||_F = 1 of Eq. patch_based_dic), E <- E + G - D;
+ *   the code update's tables (G and M1 = G^T (rho I + G G^T)^-1, BF16) are
+ *   rebuilt from G on the GPU (FP32 products and Cholesky factors).
+ * This call copies g of the last solve (the layout of the plan's dictionary:
+ * [n][A], [M][L][L] or [M][S][L][L] float32) to the device buffer d_filters,
+ * asynchronously on `stream`. CIP_EINVAL if the plan does not learn its
+ * dictionary or has not solved yet. */
 int cip_plan_dictionary(cip_plan_t plan, float* d_filters, void* stream);
 
 /* Release the host-side plan object (the workspace stays the caller's). */

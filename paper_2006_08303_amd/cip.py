@@ -160,8 +160,8 @@ def _dev_f32(t, shape, name):
 
 
 def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0, n_filters=0, filt_l=0,
-                    flags=0):
-    desc = _desc(prior, beta, flags=flags)
+                    flags=0, sigma=0.0):
+    desc = _desc(prior, beta, flags=flags, sigma=sigma)
     desc.n_atoms = int(n_atoms)
     desc.n_filters = int(n_filters)
     desc.filt_l = int(filt_l)
@@ -179,8 +179,9 @@ class Plan:
     filters: for prior="conv2d", float32 CUDA tensor [M, L, L] (tap (a, b) at
     offset (a - L//2, b - L//2)); for prior="conv3d", [M, S, L, L] (band tap
     s' at band offset s'); mu: gradient (Tikhonov) weight on the codes
-    (conv2d only). dict_update (conv priors): learn the dictionary online in every
-    solve with penalty sigma (0: 10); dictionary() returns the learned filters."""
+    (conv2d only). dict_update (patch and conv priors): learn the dictionary
+    online in every solve with penalty sigma (0: 1 for the patch prior, 10 for
+    the conv priors); dictionary() returns the learned dictionary or filters."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
                  filters=None, stream=None, mu=0.0, adaptive=False, tv_inner=0,
@@ -200,7 +201,8 @@ class Plan:
             _dev_f32(filters, tuple(filters.shape), "filters")
         flags = (CIP_PLAN_ADAPTIVE if adaptive else 0) | (CIP_PLAN_DICT_UPDATE if dict_update else 0)
         desc = _desc(prior, beta, dictionary, filters, mu, flags, tv_inner, sigma)
-        self.filters_shape = tuple(filters.shape) if filters is not None else None
+        self.filters_shape = (tuple(filters.shape) if filters is not None else
+                              tuple(dictionary.shape) if dictionary is not None else None)
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
                                  desc.n_atoms, desc.n_filters, desc.filt_l, desc.flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
@@ -260,7 +262,8 @@ class Plan:
         return AttachedPlan(self)
 
     def dictionary(self, stream=None):
-        """The filters learned in the last solve (dict_update plans), [M, S, L, L]."""
+        """The dictionary learned in the last solve (dict_update plans): the
+        filters' shape, or [64 S, A] for the patch prior."""
         out = torch.empty(self.filters_shape, dtype=torch.float32, device=self.workspace.device)
         _check(lib().cip_plan_dictionary(self._h, ctypes.c_void_p(out.data_ptr()),
                                          _stream_ptr(stream)))

@@ -68,6 +68,7 @@ struct Layout {
   size_t lam64, rt64, pl64;             // plan-time FP64 scratch (lam64 resident if adaptive)
   size_t xbuf, sums;                    // adaptive solves: iterates, norm partial sums
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
+  size_t dbf0, m1bf0, pd0, pzf, ppart, pbm, pd, pcm, plt, pg, pe;  // patch dictionary learning
   size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t bw;                                                 // 3D conv: band DFT matrix
   size_t filt0, gtap, gehat, dsp, ecdl, dpl;                 // 3D dictionary update
@@ -138,8 +139,25 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (kind == CIP_PRIOR_PATCH) {
     const size_t nv = (size_t)64 * S, na = (size_t)prior->n_atoms;
     const size_t J = (size_t)(N1 / 4) * (N2 / 4);
-    L.dbf = tab(nv * na * 2);
-    L.m1bf = tab(na * nv * 2);
+    // a learned dictionary changes D and M1 during a solve: they then belong
+    // to the solve state, and the plan keeps the tables of its initial one
+    const bool learn = (prior->flags & CIP_PLAN_DICT_UPDATE) != 0;
+    L.dbf = learn ? sta(nv * na * 2) : tab(nv * na * 2);
+    L.m1bf = learn ? sta(na * nv * 2) : tab(na * nv * 2);
+    if (learn) {
+      const size_t KS = (size_t)patch_dict_splits(N1, N2);
+      L.dbf0 = tab(nv * na * 2);
+      L.m1bf0 = tab(na * nv * 2);
+      L.pd0 = tab(nv * na * 4);
+      L.pzf = sta(na * J * 4);
+      L.ppart = sta(KS * (nv + na) * na * 4);
+      L.pbm = sta(nv * na * 4);
+      L.pd = sta(nv * na * 4);
+      L.pcm = sta((size_t)256 * 256 * 4);
+      L.plt = sta((size_t)256 * 256 * 4);
+      L.pg = sta(nv * na * 4);
+      L.pe = sta(nv * na * 4);
+    }
     L.vpatch = sta(na * J * 4);
     L.tbuf = sta(patch_tile_buffer_floats(S, N1, N2) * 4);
     L.rimg = sta((size_t)S * N1 * N2 * 4);
@@ -208,8 +226,9 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       return fail(CIP_EUNSUPPORTED, "3D conv prior: no gradient term (mu must be 0)");
   }
   if (prior->flags & CIP_PLAN_DICT_UPDATE) {
-    if (prior->kind != CIP_PRIOR_CONV3D && prior->kind != CIP_PRIOR_CONV2D)
-      return fail(CIP_EUNSUPPORTED, "dictionary learning: convolutional priors only");
+    if (prior->kind != CIP_PRIOR_CONV3D && prior->kind != CIP_PRIOR_CONV2D &&
+        prior->kind != CIP_PRIOR_PATCH)
+      return fail(CIP_EUNSUPPORTED, "dictionary learning: patch and convolutional priors only");
     if (!(prior->sigma >= 0.0)) return fail(CIP_EINVAL, "sigma must be >= 0");
   }
   return CIP_OK;
@@ -226,7 +245,7 @@ struct cip_plan_s {
   bool solved_once;
   bool attached;        // shares another plan's tables
   bool adaptive;        // FP64 spectra resident: the penalty may change in a solve
-  bool learn;           // 3D conv: the dictionary is learned during every solve
+  bool learn;           // the dictionary is learned during every solve
   double sigma;         // penalty of the dictionary ADMM
   double mu;            // conv prior: gradient (Tikhonov) weight
   int filt_l;           // conv priors: filter side L
@@ -470,20 +489,66 @@ hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
 //   row FFT -> x^l (written to d_x);
 //   for l < L: sparse-code update, soft threshold and dual update on MFMA
 //   (k_patch_z), then r = P^T D~ z^l (k_patch_assemble).
+//   With a learned dictionary the code update writes z in FP32 and skips
+//   D z; one step of the dictionary ADMM follows (D, G, E and the BF16
+//   tables of G), then D z with the new G.
+PatchDictBufs patch_dict_bufs(cip_plan_t p) {
+  const Layout& L = p->L;
+  PatchDictBufs b;
+  b.zf = p->at<float>(L.pzf);
+  b.part = p->at<float>(L.ppart);
+  b.bm = p->at<float>(L.pbm);
+  b.d = p->at<float>(L.pd);
+  b.cm = p->at<float>(L.pcm);
+  b.lt = p->at<float>(L.plt);
+  b.g = p->at<float>(L.pg);
+  b.e = p->at<float>(L.pe);
+  b.dbf = p->at<uint16_t>(L.dbf);
+  b.m1bf = p->at<uint16_t>(L.m1bf);
+  return b;
+}
+
 hipError_t patch_step(cip_plan_t p, const float* x, int first, hipStream_t st) {
   const Layout& L = p->L;
   const float kappa = (float)(p->lambda / p->rho);
-  hipError_t e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf),
-                                p->at<const uint16_t>(L.dbf), p->at<const uint16_t>(L.m1bf), p->N1,
-                                p->N2, kappa, first, st);
+  hipError_t e;
+  if (p->learn) {
+    const PatchDictBufs b = patch_dict_bufs(p);
+    e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), b.dbf,
+                       b.m1bf, p->N1, p->N2, kappa, first, st, PZ_MODE_CODES, b.zf);
+    if (e != hipSuccess) return e;
+    e = patch_dict_step(x, b, p->S, p->n_atoms, p->N1, p->N2, (float)p->sigma, (float)p->rho, st);
+    if (e != hipSuccess) return e;
+    e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), b.dbf,
+                       b.m1bf, p->N1, p->N2, kappa, first, st, PZ_MODE_SYNTH, b.zf);
+  } else {
+    e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf),
+                       p->at<const uint16_t>(L.dbf), p->at<const uint16_t>(L.m1bf), p->N1, p->N2,
+                       kappa, first, st);
+  }
   if (e != hipSuccess) return e;
   return patch_assemble_launch(p->S, p->at<const float>(L.tbuf), p->at<float>(L.rimg), p->N1, p->N2,
                                st);
 }
 
+// Start of a solve with a learned dictionary: G = the plan's dictionary,
+// E = 0, and its BF16 tables.
+hipError_t patch_dict_begin(cip_plan_t p, hipStream_t st) {
+  const Layout& L = p->L;
+  const int nv = 64 * p->S, na = p->n_atoms;
+  hipError_t e = hipMemcpyAsync(p->at<void>(L.dbf), p->at<const void>(L.dbf0), (size_t)nv * na * 2,
+                                hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(p->at<void>(L.m1bf), p->at<const void>(L.m1bf0), (size_t)nv * na * 2,
+                     hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  return patch_dict_start(p->at<const float>(L.pd0), patch_dict_bufs(p), nv, na, st);
+}
+
 hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
   const Layout& L = p->L;
   hipError_t e;
+  if (p->learn && (e = patch_dict_begin(p, st)) != hipSuccess) return e;
   for (int l = 1; l <= iters; ++l) {
     if (l > 1) {
       e = row_r2c<float>(p->at<const float>(L.rimg), p->at<cx<float>>(L.bufA), p->S, p->N1, p->N2,
@@ -833,10 +898,13 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->solved_once = false;
   p->attached = false;
   p->adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
-  p->learn = (prior->kind == CIP_PRIOR_CONV3D || prior->kind == CIP_PRIOR_CONV2D) &&
+  p->learn = (prior->kind == CIP_PRIOR_CONV3D || prior->kind == CIP_PRIOR_CONV2D ||
+              prior->kind == CIP_PRIOR_PATCH) &&
              (prior->flags & CIP_PLAN_DICT_UPDATE) != 0;
   p->mu = prior->mu;
-  p->sigma = prior->sigma > 0.0 ? prior->sigma : 10.0;
+  // default sigma: the paper's settings (1 for the patch dictionary, 10 for
+  // the convolutional one)
+  p->sigma = prior->sigma > 0.0 ? prior->sigma : (prior->kind == CIP_PRIOR_PATCH ? 1.0 : 10.0);
   p->filt_l = prior->filt_l;
   p->row_np = PAIRS;
   p->row_ppt = ppt_row_n(N2);
@@ -964,8 +1032,13 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     PLAN_HIP(hipStreamSynchronize(st));
     std::vector<uint16_t> dbf, m1bf;
     patch_dictionary_tables(D, nv, na, rho, dbf, m1bf);
-    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.dbf), dbf.data(), dbf.size() * 2, hipMemcpyHostToDevice, st));
-    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.m1bf), m1bf.data(), m1bf.size() * 2, hipMemcpyHostToDevice, st));
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(p->learn ? L.dbf0 : L.dbf), dbf.data(), dbf.size() * 2,
+                            hipMemcpyHostToDevice, st));
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(p->learn ? L.m1bf0 : L.m1bf), m1bf.data(),
+                            m1bf.size() * 2, hipMemcpyHostToDevice, st));
+    if (p->learn)
+      PLAN_HIP(hipMemcpyAsync(p->at<void>(L.pd0), D.data(), D.size() * 4, hipMemcpyHostToDevice,
+                              st));
   }
   PLAN_HIP(hipStreamSynchronize(st));
   *out = p;
@@ -1035,6 +1108,12 @@ int cip_plan_dictionary(cip_plan_t p, float* d_filters, void* stream) {
   if (!p || !d_filters) return fail(CIP_EINVAL, "NULL argument");
   if (!p->learn) return fail(CIP_EINVAL, "the plan does not learn its dictionary");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
+  if (p->kind == CIP_PRIOR_PATCH) {
+    HIP_TRY(hipMemcpyAsync(d_filters, p->at<const void>(p->L.pg),
+                           (size_t)64 * p->S * p->n_atoms * 4, hipMemcpyDeviceToDevice,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return CIP_OK;
+  }
   const size_t planes = (size_t)p->n_filters * (p->kind == CIP_PRIOR_CONV3D ? p->S : 1);
   const size_t bytes = planes * p->filt_l * p->filt_l * 4;
   HIP_TRY(hipMemcpyAsync(d_filters, p->at<const void>(p->L.gtap), bytes, hipMemcpyDeviceToDevice,

@@ -1,6 +1,7 @@
 // Launchers of the patch-dictionary kernels (separate translation unit).
 #include "launch.hpp"
 #include "patch.hpp"
+#include "patch_dl.hpp"
 #include "patch_launch.hpp"
 
 namespace cip {
@@ -11,18 +12,26 @@ bool patch_supported(int S, int NA) {
 
 hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, const uint16_t* D,
                           const uint16_t* M1, int N1, int N2, float kappa, int first,
-                          hipStream_t st) {
+                          hipStream_t st, int mode, float* zf) {
   const PatchGeo G = patch_geo(N1, N2);
   const int tiles = (G.J1 / G.TPR) * G.ntc;
-#define CIP_PATCH_CASE(SS, AA)                                                           \
-  if (S == SS && NA == AA)                                                               \
-    return launch(k_patch_z<SS, AA>, tiles, 256, (size_t)patch_lds_bytes<SS, AA>(), st, x, v, \
-                  tb, D, M1, G, kappa, first);
+  static_assert(PZ_MODE_FULL == PZ_FULL && PZ_MODE_CODES == PZ_CODES && PZ_MODE_SYNTH == PZ_SYNTH,
+                "launcher and kernel modes agree");
+  if (mode != PZ_FULL && !zf) return hipErrorInvalidValue;
+#define CIP_PATCH_MODE(SS, AA, MM)                                                            \
+  launch(k_patch_z<SS, AA, MM>, tiles, 256, (size_t)patch_lds_bytes<SS, AA>(), st, x, v, tb, D, \
+         M1, G, kappa, first, zf)
+#define CIP_PATCH_CASE(SS, AA)                                                  \
+  if (S == SS && NA == AA)                                                      \
+    return mode == PZ_FULL    ? CIP_PATCH_MODE(SS, AA, PZ_FULL)                 \
+           : mode == PZ_CODES ? CIP_PATCH_MODE(SS, AA, PZ_CODES)                \
+                              : CIP_PATCH_MODE(SS, AA, PZ_SYNTH);
   CIP_PATCH_CASE(1, 64) CIP_PATCH_CASE(1, 128) CIP_PATCH_CASE(1, 256)
   CIP_PATCH_CASE(2, 64) CIP_PATCH_CASE(2, 128) CIP_PATCH_CASE(2, 256)
   CIP_PATCH_CASE(3, 64) CIP_PATCH_CASE(3, 128) CIP_PATCH_CASE(3, 256)
   CIP_PATCH_CASE(4, 64) CIP_PATCH_CASE(4, 128) CIP_PATCH_CASE(4, 256)
 #undef CIP_PATCH_CASE
+#undef CIP_PATCH_MODE
   return hipErrorInvalidValue;
 }
 
@@ -35,6 +44,55 @@ hipError_t patch_assemble_launch(int S, const float* tb, float* r, int N1, int N
 size_t patch_tile_buffer_floats(int S, int N1, int N2) {
   const PatchGeo G = patch_geo(N1, N2);
   return (size_t)(G.J1 / G.TPR) * G.ntc * S * G.RR * G.RC;
+}
+
+int patch_dict_splits(int N1, int N2) {
+  const size_t J = (size_t)(N1 / PATCH_ST) * (N2 / PATCH_ST);
+  const size_t ks = J / PDL_KSTEP;
+  return (int)(ks < 16 ? ks : 16);
+}
+
+hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int NA,
+                            hipStream_t st) {
+  const int count = nv * NA;
+  return launch(k_pdl_start, (count + 255) / 256, 256, 0, st, d0, b.g, b.e, count);
+}
+
+// One step of the dictionary ADMM and the new code tables (see patch_dl.hpp).
+hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
+                           float sigma, float rho, hipStream_t st) {
+  const PatchGeo G = patch_geo(N1, N2);
+  const int nv = 64 * S, rows = nv + NA;
+  const int KS = patch_dict_splits(N1, N2);
+  const int chunk = (int)(((size_t)G.J1 * G.J2) / KS);
+  if (nv > PDL_MAXM || NA > PDL_MAXM || chunk % PDL_KSTEP) return hipErrorInvalidValue;
+  hipError_t e;
+  hipLaunchKernelGGL(k_pdl_gemm, dim3(rows / 64, NA / 64, KS), dim3(256), 0, st, x, b.zf, b.part,
+                     G, S, NA, chunk);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t nr = (size_t)rows * NA;
+  if ((e = launch(k_pdl_reduce, (int)((nr + 255) / 256), 256, 0, st, (const float*)b.part,
+                  (const float*)b.g, (const float*)b.e, b.bm, b.cm, nv, NA, KS, sigma)) != hipSuccess)
+    return e;
+  // D = B (Z Z^T + sigma I)^-1
+  if ((e = launch(k_pdl_chol, 1, 1024, 0, st, (const float*)b.cm, PDL_MAXM, NA, b.lt)) != hipSuccess)
+    return e;
+  if ((e = launch(k_pdl_trsolve, (nv + 3) / 4, 256, (size_t)pdl_trsolve_lds_floats(NA) * 4, st,
+                  (const float*)b.lt, NA, (const float*)b.bm, NA, 1, nv, b.d,
+                  (uint16_t*)nullptr)) != hipSuccess)
+    return e;
+  // G, E and the BF16 dictionary
+  if ((e = launch(k_pdl_project, 1, 1024, 0, st, (const float*)b.d, b.g, b.e, b.dbf, nv * NA)) !=
+      hipSuccess)
+    return e;
+  // M1 = G^T (rho I + G G^T)^-1 in BF16
+  hipLaunchKernelGGL(k_pdl_gram, dim3(nv / 16, nv / 16), dim3(256), 0, st, (const float*)b.g, NA,
+                     rho, b.cm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch(k_pdl_chol, 1, 1024, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
+    return e;
+  return launch(k_pdl_trsolve, (NA + 3) / 4, 256, (size_t)pdl_trsolve_lds_floats(nv) * 4, st,
+                (const float*)b.lt, nv, (const float*)b.g, 1, NA, NA, (float*)nullptr, b.m1bf);
 }
 
 bool patch_grid_ok(int N1, int N2) {

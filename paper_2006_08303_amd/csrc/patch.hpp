@@ -71,16 +71,22 @@ template <int S, int NA> constexpr int patch_lds_bytes() {
   return wb + eb > dz ? wb + eb : dz;
 }
 
+// What k_patch_z runs: the whole update (codes, state, D z), only the codes
+// and state (z also written in FP32 to zf), or only D z from the codes in zf
+// (after a dictionary change).
+enum { PZ_FULL = 0, PZ_CODES = 1, PZ_SYNTH = 2 };
+
 // Sparse-code update for one tile of 64 patches per work-group (4 waves).
 //   x   [S][N1][N2]  current image x^{l+1}
 //   v   [NA][J]      state, updated in place (first: treated as 0)
 //   tb  per-tile overlap-added D z, [tile][S][RR][RC]
 //   Dg  [NV][NA] bf16, M1g [NA][NV] bf16 (row-major)
-template <int S, int NA>
+//   zf  [NA][J]      codes z in FP32 (PZ_CODES: written; PZ_SYNTH: read)
+template <int S, int NA, int MODE>
 __global__ void __launch_bounds__(256)
 k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict__ tb,
           const uint16_t* __restrict__ Dg, const uint16_t* __restrict__ M1g, PatchGeo G,
-          float kappa, int first) {
+          float kappa, int first, float* __restrict__ zf) {
   constexpr int NV = 64 * S;
   constexpr int WS = NA + 8;   // LDS row stride of W / Z (bf16)
   constexpr int ES = NV + 8;   // LDS row stride of E (bf16)
@@ -98,89 +104,100 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
     return (size_t)(tr * G.TPR + jl / G.TPC) * G.J2 + tc * G.TPC + jl % G.TPC;
   };
 
-  // 0. w = t - u = 2 soft(v) - v, as bf16 rows WB[patch][atom]
-  for (int idx = threadIdx.x; idx < NA * PATCH_NP; idx += 256) {
-    const int a = idx / PATCH_NP, jl = idx % PATCH_NP;
-    const float vv = first ? 0.f : v[(size_t)a * J + jglob(jl)];
-    WB[jl * WS + a] = f2bf(2.f * soft_f(vv, kappa) - vv);
-  }
-  __syncthreads();
-
-  // 1. GEMM1: acc = D w; epilogue e = P x - D w -> EB[patch][i]
-  if (wave < NV / 64) {
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
-    const uint16_t* Da = Dg + (size_t)(64 * wave + l32) * NA + 8 * lhi;
-#pragma unroll 4
-    for (int ks = 0; ks < NA / 16; ++ks) {
-      bf16x8 a0 = ld_bf16x8(Da + 16 * ks);
-      bf16x8 a1 = ld_bf16x8(Da + 32 * NA + 16 * ks);
-      bf16x8 b0 = ld_bf16x8(WB + l32 * WS + 16 * ks + 8 * lhi);
-      bf16x8 b1 = ld_bf16x8(WB + (32 + l32) * WS + 16 * ks + 8 * lhi);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+  if constexpr (MODE == PZ_SYNTH) {
+    // codes from zf, as bf16 rows WB[patch][atom]
+    for (int idx = threadIdx.x; idx < NA * PATCH_NP; idx += 256) {
+      const int a = idx / PATCH_NP, jl = idx % PATCH_NP;
+      WB[jl * WS + a] = f2bf(zf[(size_t)a * J + jglob(jl)]);
     }
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int jl = 32 * n + l32;
-        const int pr0 = (tr * G.TPR + jl / G.TPC) * PATCH_ST;
-        const int pc0 = (tc * G.TPC + jl % G.TPC) * PATCH_ST;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-          const int s = row >> 6, a = (row >> 3) & 7, b = row & 7;
-          const int pr = (pr0 + a) & (G.N1 - 1), pc = (pc0 + b) & (G.N2 - 1);
-          const float p = x[((size_t)s * G.N1 + pr) * G.N2 + pc];
-          EB[jl * ES + row] = f2bf(p - acc[m][n][i]);
-        }
-      }
-  }
-  __syncthreads();
-
-  // 2. GEMM2: acc = M1 e; z = w + acc; v <- z + clip(v); z -> WB (bf16)
-  for (int wb = wave; wb < NA / 64; wb += 4) {
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
-    const uint16_t* Ma = M1g + (size_t)(64 * wb + l32) * NV + 8 * lhi;
-#pragma unroll 4
-    for (int ks = 0; ks < NV / 16; ++ks) {
-      bf16x8 a0 = ld_bf16x8(Ma + 16 * ks);
-      bf16x8 a1 = ld_bf16x8(Ma + 32 * NV + 16 * ks);
-      bf16x8 b0 = ld_bf16x8(EB + l32 * ES + 16 * ks + 8 * lhi);
-      bf16x8 b1 = ld_bf16x8(EB + (32 + l32) * ES + 16 * ks + 8 * lhi);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    __syncthreads();
+  } else {
+    // 0. w = t - u = 2 soft(v) - v, as bf16 rows WB[patch][atom]
+    for (int idx = threadIdx.x; idx < NA * PATCH_NP; idx += 256) {
+      const int a = idx / PATCH_NP, jl = idx % PATCH_NP;
+      const float vv = first ? 0.f : v[(size_t)a * J + jglob(jl)];
+      WB[jl * WS + a] = f2bf(2.f * soft_f(vv, kappa) - vv);
     }
+    __syncthreads();
+
+    // 1. GEMM1: acc = D w; epilogue e = P x - D w -> EB[patch][i]
+    if (wave < NV / 64) {
+      f32x16 acc[2][2];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int jl = 32 * n + l32;
-        const size_t jg = jglob(jl);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int atom = 64 * wb + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-          float* vp = v + (size_t)atom * J + jg;
-          const float vv = first ? 0.f : *vp;
-          const float z = (2.f * soft_f(vv, kappa) - vv) + acc[m][n][i];
-          *vp = z + clip_f(vv, kappa);
-          WB[jl * WS + atom] = f2bf(z);
-        }
+        for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
+      const uint16_t* Da = Dg + (size_t)(64 * wave + l32) * NA + 8 * lhi;
+#pragma unroll 4
+      for (int ks = 0; ks < NA / 16; ++ks) {
+        bf16x8 a0 = ld_bf16x8(Da + 16 * ks);
+        bf16x8 a1 = ld_bf16x8(Da + 32 * NA + 16 * ks);
+        bf16x8 b0 = ld_bf16x8(WB + l32 * WS + 16 * ks + 8 * lhi);
+        bf16x8 b1 = ld_bf16x8(WB + (32 + l32) * WS + 16 * ks + 8 * lhi);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
       }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const int jl = 32 * n + l32;
+          const int pr0 = (tr * G.TPR + jl / G.TPC) * PATCH_ST;
+          const int pc0 = (tc * G.TPC + jl % G.TPC) * PATCH_ST;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
+            const int s = row >> 6, a = (row >> 3) & 7, b = row & 7;
+            const int pr = (pr0 + a) & (G.N1 - 1), pc = (pc0 + b) & (G.N2 - 1);
+            const float p = x[((size_t)s * G.N1 + pr) * G.N2 + pc];
+            EB[jl * ES + row] = f2bf(p - acc[m][n][i]);
+          }
+        }
+    }
+    __syncthreads();
+
+    // 2. GEMM2: acc = M1 e; z = w + acc; v <- z + clip(v); z -> WB (bf16)
+    for (int wb = wave; wb < NA / 64; wb += 4) {
+      f32x16 acc[2][2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
+      const uint16_t* Ma = M1g + (size_t)(64 * wb + l32) * NV + 8 * lhi;
+#pragma unroll 4
+      for (int ks = 0; ks < NV / 16; ++ks) {
+        bf16x8 a0 = ld_bf16x8(Ma + 16 * ks);
+        bf16x8 a1 = ld_bf16x8(Ma + 32 * NV + 16 * ks);
+        bf16x8 b0 = ld_bf16x8(EB + l32 * ES + 16 * ks + 8 * lhi);
+        bf16x8 b1 = ld_bf16x8(EB + (32 + l32) * ES + 16 * ks + 8 * lhi);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const int jl = 32 * n + l32;
+          const size_t jg = jglob(jl);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int atom = 64 * wb + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
+            float* vp = v + (size_t)atom * J + jg;
+            const float vv = first ? 0.f : *vp;
+            const float z = (2.f * soft_f(vv, kappa) - vv) + acc[m][n][i];
+            *vp = z + clip_f(vv, kappa);
+            WB[jl * WS + atom] = f2bf(z);
+            if constexpr (MODE == PZ_CODES) zf[(size_t)atom * J + jg] = z;
+          }
+        }
+    }
+    if constexpr (MODE == PZ_CODES) return;
+    __syncthreads();
   }
-  __syncthreads();
 
   // 3. GEMM3: D z, then overlap-add inside the tile
   f32x16 acc3[2][2];

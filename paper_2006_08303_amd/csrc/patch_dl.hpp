@@ -1,0 +1,329 @@
+// Online update of the patch dictionary (Section IV-B, patch-based
+// dictionary update): one step of the dictionary ADMM per outer iteration,
+// taken after the sparse-code update with the image x and the codes Z:
+//   D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1     Eq. sold_patch
+//   G = (D + E) / ||D + E||_F                              Eq. ADMM1
+//   E = E + G - D                                          Eq. subh
+// with X = [P_1 x | ... | P_J x] (n x J, n = 64 S) and Z (A x J). The next x-
+// and code updates use G: its BF16 copy and M1 = G^T (rho I + G G^T)^-1.
+//
+// Arithmetic is FP32 throughout:
+//   k_pdl_gemm     the products X Z^T and Z Z^T on FP32 MFMA
+//                  (v_mfma_f32_32x32x2f32), split over the patches, every
+//                  split written to its own slice (no atomics);
+//   k_pdl_reduce   fixed-order sum of the slices, + sigma (G - E) and sigma I;
+//   k_pdl_chol     Cholesky factor of an SPD matrix of order m <= 256 in one
+//                  work-group: the matrix (padded with the identity to
+//                  256 x 256) lives in registers, 8 x 8 per thread, and the
+//                  pivot column is broadcast through LDS (one barrier per
+//                  column);
+//   k_pdl_trsolve  rows of B M^-1 = B L^-T L^-1, one row per wave, L packed
+//                  in LDS;
+//   k_pdl_project  the Frobenius projection and the dual update (one
+//                  work-group, FP64 norm);
+//   k_pdl_gram     rho I + G G^T.
+#pragma once
+#include "patch.hpp"
+
+namespace cip {
+
+constexpr int PDL_MAXM = 256;    // largest system order (A or n = 64 S)
+constexpr int PDL_KSTEP = 32;    // patches per LDS stage of k_pdl_gemm
+
+// Split-K products W Z^T with W = [X; Z] ((n + A) x J). Work-group
+// (rb, cb, ks) computes the 64 x 64 block (rb, cb) over the patches
+// [ks * chunk, (ks + 1) * chunk) and writes it to part[ks] ((n + A) x A,
+// row-major). Rows rb < S are the patch rows of plane s = rb (row
+// 64 s + 8 a + b, patch j = pi J2 + pj: pixel x[s][4 pi + a][4 pj + b],
+// circular); blocks of Z Z^T above the diagonal are skipped.
+// Requires chunk % 32 == 0, J % chunk == 0, J2 a power of two.
+__global__ void __launch_bounds__(256)
+k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __restrict__ part,
+           PatchGeo G, int S, int NA, int chunk) {
+  __shared__ float As[64][PDL_KSTEP + 1];
+  __shared__ float Bs[64][PDL_KSTEP + 1];
+  const int rb = blockIdx.x, cb = blockIdx.y, ks = blockIdx.z;
+  if (rb >= S && cb > rb - S) return;
+  const int rows = 64 * S + NA;
+  const size_t J = (size_t)G.J1 * G.J2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = threadIdx.x >> 2, lk = (threadIdx.x & 3) * 8;   // staging: row, 8 patches
+  const int pa = lr >> 3, pb = lr & 7;
+  const int jsh = __builtin_ctz((unsigned)G.J2);
+  const float* zb = zf + (size_t)(64 * cb + lr) * J;
+  const float* za = zf + (size_t)(64 * (rb >= S ? rb - S : 0) + lr) * J;
+  const float* xs = x + (size_t)(rb < S ? rb : 0) * G.N1 * G.N2;
+  f32x16 acc = f32x16{};
+  const size_t jend = (size_t)(ks + 1) * chunk;
+  for (size_t j0 = (size_t)ks * chunk; j0 < jend; j0 += PDL_KSTEP) {
+    float av[8], bv[8];
+    const float4* bp = reinterpret_cast<const float4*>(zb + j0 + lk);
+    const float4 b0 = bp[0], b1 = bp[1];
+    bv[0] = b0.x; bv[1] = b0.y; bv[2] = b0.z; bv[3] = b0.w;
+    bv[4] = b1.x; bv[5] = b1.y; bv[6] = b1.z; bv[7] = b1.w;
+    if (rb >= S) {
+      const float4* ap = reinterpret_cast<const float4*>(za + j0 + lk);
+      const float4 a0 = ap[0], a1 = ap[1];
+      av[0] = a0.x; av[1] = a0.y; av[2] = a0.z; av[3] = a0.w;
+      av[4] = a1.x; av[5] = a1.y; av[6] = a1.z; av[7] = a1.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const size_t j = j0 + lk + q;
+        const int pi = (int)(j >> jsh), pj = (int)(j & (size_t)(G.J2 - 1));
+        const int r = (PATCH_ST * pi + pa) & (G.N1 - 1), c = (PATCH_ST * pj + pb) & (G.N2 - 1);
+        av[q] = xs[(size_t)r * G.N2 + c];
+      }
+    }
+    __syncthreads();   // the previous stage has been consumed
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[lr][lk + q] = av[q];
+      Bs[lr][lk + q] = bv[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < PDL_KSTEP / 2; ++kk)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[32 * wr + l32][2 * kk + lhi],
+                                                 Bs[32 * wc + l32][2 * kk + lhi], acc, 0, 0, 0);
+  }
+  float* out = part + ((size_t)ks * rows + 64 * rb + 32 * wr) * NA + 64 * cb + 32 * wc + l32;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[(size_t)(8 * (i / 4) + 4 * lhi + (i % 4)) * NA] = acc[i];
+}
+
+// Sum of the KS slices in a fixed order. Rows r < n: B = X Z^T + sigma (G - E)
+// (n x A, row-major); rows n + i: C = Z Z^T + sigma I into cm (leading
+// dimension 256; the blocks on and below the diagonal only).
+__global__ void k_pdl_reduce(const float* __restrict__ part, const float* __restrict__ g,
+                             const float* __restrict__ e, float* __restrict__ bm,
+                             float* __restrict__ cm, int nv, int NA, int KS, float sigma) {
+  const int rows = nv + NA;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)rows * NA) return;
+  const int r = (int)(idx / NA), c = (int)(idx % NA);
+  if (r >= nv && (c >> 6) > ((r - nv) >> 6)) return;
+  float s = 0.f;
+  for (int k = 0; k < KS; ++k) s += part[(size_t)k * rows * NA + idx];
+  if (r < nv) {
+    bm[idx] = s + sigma * (g[idx] - e[idx]);
+  } else {
+    const int i = r - nv;
+    cm[(size_t)i * PDL_MAXM + c] = s + (i == c ? sigma : 0.f);
+  }
+}
+
+// Cholesky factor L (M = L L^T) of the SPD matrix M of order m <= 256 whose
+// lower triangle is a[i * lda + k] (i >= k). Output lt[k * 256 + i] = L[i][k]
+// for i >= k (row k of lt is column k of L); orders above m are padded with
+// the identity. One work-group of 1024 threads: wave w holds the 64 x 64
+// block (w / 4, w % 4) of the padded matrix, lane the 8 x 8 tile
+// (lane / 8, lane % 8) of it, in registers; waves above the block diagonal
+// idle. Step j eliminates column j (Gaussian elimination on the symmetric
+// matrix, P[i][k] -= P[i][j] P[k][j] / P[j][j] for i, k > j); the pivot
+// column travels through a double-buffered LDS column, so one barrier per
+// step suffices. At the end L[i][k] = P[i][k] / sqrt(P[k][k]).
+__global__ void __launch_bounds__(1024)
+k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) {
+  __shared__ float colb[2][PDL_MAXM];
+  __shared__ float piv[PDL_MAXM];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bi = w >> 2, bk = w & 3;
+  const int ti = 8 * bi + (lane >> 3), tk = 8 * bk + (lane & 7);
+  const bool act = bi >= bk;
+  float P[8][8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = 8 * ti + r, k = 8 * tk + c;
+      float v = i == k ? 1.f : 0.f;
+      if (act && i < m && k < m) v = i >= k ? a[(size_t)i * lda + k] : a[(size_t)k * lda + i];
+      P[r][c] = v;
+    }
+  for (int j = 0; j < PDL_MAXM; ++j) {
+    float* cb = colb[j & 1];
+    if (act && tk == (j >> 3)) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c == (j & 7)) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) cb[8 * ti + r] = P[r][c];
+        }
+    }
+    __syncthreads();
+    if (act && 8 * ti + 7 > j && 8 * tk + 7 > j) {
+      const float inv = 1.f / cb[j];
+      float cr[8], cc[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) cr[r] = cb[8 * ti + r];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) cc[c] = cb[8 * tk + c] * inv;
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (8 * ti + r > j && 8 * tk + c > j) P[r][c] = fmaf(-cr[r], cc[c], P[r][c]);
+    }
+  }
+  if (act && ti == tk) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) piv[8 * ti + r] = sqrtf(P[r][r]);
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int k = 8 * tk + c;
+      const float s = 1.f / piv[k];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = 8 * ti + r;
+        if (i >= k) lt[(size_t)k * PDL_MAXM + i] = P[r][c] * s;
+      }
+    }
+  }
+}
+
+// LDS floats of k_pdl_trsolve for order m: packed columns of L and 1 / L[k][k]
+__host__ __device__ constexpr int pdl_trsolve_lds_floats(int m) { return m * (m + 1) / 2 + m; }
+
+// Rows of X = B M^-1 with M = L L^T (lt from k_pdl_chol, order m): for every
+// row b of B, x solves M x^T = b^T (M symmetric): L y = b^T (forward), then
+// L^T x = y (backward), both column by column. One wave per row (lane holds
+// entries lane + 64 r), four rows per work-group; L is staged in LDS as
+// packed columns (column k at offset k m - k (k - 1) / 2, entries k..m-1).
+// B entry (row, col) is b[row * bsr + col * bsc]; X is written row-major
+// (q x m) to xo (FP32) and/or xbf (BF16) when those are not null.
+__global__ void __launch_bounds__(256)
+k_pdl_trsolve(const float* __restrict__ lt, int m, const float* __restrict__ b, int bsr, int bsc,
+              int q, float* __restrict__ xo, uint16_t* __restrict__ xbf) {
+  extern __shared__ float Lp[];
+  float* rd = Lp + m * (m + 1) / 2;
+  const int mm = m * m;
+  for (int base = 0; base < mm; base += 256 * 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * 256 + threadIdx.x;
+      const int k = idx / m, i = idx - k * m;
+      v[u] = (idx < mm && i >= k) ? lt[(size_t)k * PDL_MAXM + i] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * 256 + threadIdx.x;
+      const int k = idx / m, i = idx - k * m;
+      if (idx < mm && i >= k) Lp[k * m - k * (k - 1) / 2 + (i - k)] = v[u];
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < m; k += 256) rd[k] = 1.f / Lp[k * m - k * (k - 1) / 2];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= q) return;
+  float y[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int c = lane + 64 * r;
+    y[r] = c < m ? b[(size_t)row * bsr + (size_t)c * bsc] : 0.f;
+  }
+  auto pick = [&](int k) -> float {
+    const int r = k >> 6;
+    const float v = r == 0 ? y[0] : (r == 1 ? y[1] : (r == 2 ? y[2] : y[3]));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k & 63));
+  };
+  // forward: L y = b
+  for (int k = 0; k < m; ++k) {
+    const float yk = pick(k) * rd[k];
+    const float* col = Lp + k * m - k * (k - 1) / 2 - k;   // col[i] = L[i][k], i >= k
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lane + 64 * r;
+      if (i == k) y[r] = yk;
+      else if (i > k && i < m) y[r] = fmaf(-col[i], yk, y[r]);
+    }
+  }
+  // backward: L^T x = y
+  for (int k = m - 1; k >= 0; --k) {
+    const float xk = pick(k) * rd[k];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lane + 64 * r;
+      if (i == k) y[r] = xk;
+      else if (i < k) y[r] = fmaf(-Lp[i * m - i * (i - 1) / 2 + (k - i)], xk, y[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int c = lane + 64 * r;
+    if (c < m) {
+      if (xo) xo[(size_t)row * m + c] = y[r];
+      if (xbf) xbf[(size_t)row * m + c] = f2bf(y[r]);
+    }
+  }
+}
+
+// G = (D + E) / ||D + E||_F, E <- E + G - D, and G in BF16 (count = n A
+// entries, one work-group of 1024 threads; the squared norm is summed in
+// FP64 in a fixed order).
+__global__ void __launch_bounds__(1024)
+k_pdl_project(const float* __restrict__ d, float* __restrict__ g, float* __restrict__ e,
+              uint16_t* __restrict__ gbf, int count) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 1024) {
+    const double w = (double)d[i] + (double)e[i];
+    s += w * w;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tot += red[k];
+  const float inv = (float)(1.0 / sqrt(tot));
+  for (int i = threadIdx.x; i < count; i += 1024) {
+    const float dv = d[i], ev = e[i];
+    const float gv = (dv + ev) * inv;
+    g[i] = gv;
+    e[i] = ev + gv - dv;
+    gbf[i] = f2bf(gv);
+  }
+}
+
+// cm[i * 256 + k] = rho [i == k] + sum_a G[i][a] G[k][a] for i >= k
+// (G: n x A row-major); 16 x 16 output tiles, grid (n / 16, n / 16).
+__global__ void __launch_bounds__(256)
+k_pdl_gram(const float* __restrict__ g, int NA, float rho, float* __restrict__ cm) {
+  __shared__ float Ga[16][17], Gb[16][17];
+  const int bi = blockIdx.y, bk = blockIdx.x;
+  if (bk > bi) return;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  float acc = 0.f;
+  for (int a0 = 0; a0 < NA; a0 += 16) {
+    Ga[ty][tx] = g[(size_t)(16 * bi + ty) * NA + a0 + tx];
+    Gb[ty][tx] = g[(size_t)(16 * bk + ty) * NA + a0 + tx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc = fmaf(Ga[ty][q], Gb[tx][q], acc);
+    __syncthreads();
+  }
+  const int i = 16 * bi + ty, k = 16 * bk + tx;
+  if (i >= k) cm[(size_t)i * PDL_MAXM + k] = acc + (i == k ? rho : 0.f);
+}
+
+// Start of a solve: G = D0, E = 0 (count entries).
+__global__ void k_pdl_start(const float* __restrict__ d0, float* __restrict__ g,
+                            float* __restrict__ e, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    g[i] = d0[i];
+    e[i] = 0.f;
+  }
+}
+
+}  // namespace cip

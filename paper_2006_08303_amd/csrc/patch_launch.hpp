@@ -9,9 +9,26 @@ namespace cip {
 bool patch_supported(int S, int NA);
 bool patch_grid_ok(int N1, int N2);
 size_t patch_tile_buffer_floats(int S, int N1, int N2);
+// mode: full update, codes and state only (z to zf in FP32), or D z only
+// from the codes in zf
+enum { PZ_MODE_FULL = 0, PZ_MODE_CODES = 1, PZ_MODE_SYNTH = 2 };
 hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, const uint16_t* D,
                           const uint16_t* M1, int N1, int N2, float kappa, int first,
-                          hipStream_t st);
+                          hipStream_t st, int mode = 0, float* zf = nullptr);
+
+// Device buffers of the online patch-dictionary update (patch_dl.hpp):
+//   zf [A][J] codes, part [KS][n + A][A] split products, bm / d [n][A]
+//   right-hand side and D, cm / lt [256][256] system and its factor,
+//   g / e [n][A] dictionary and dual, dbf [n][A] / m1bf [A][n] BF16 tables.
+struct PatchDictBufs {
+  float *zf, *part, *bm, *d, *cm, *lt, *g, *e;
+  uint16_t *dbf, *m1bf;
+};
+int patch_dict_splits(int N1, int N2);
+hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int NA,
+                            hipStream_t st);
+hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
+                           float sigma, float rho, hipStream_t st);
 hipError_t patch_assemble_launch(int S, const float* tb, float* r, int N1, int N2, hipStream_t st);
 
 }  // namespace cip

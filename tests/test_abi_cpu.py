@@ -103,8 +103,10 @@ def test_new_entry_points_validate_before_device_work(L):
 
 def test_conv3d_and_dictionary_learning_validation(L):
     """3D conv prior: workspace holds the band tables; dictionary learning
-    (conv priors only) is refused for other priors and with a negative sigma,
-    and grows the solve state (d, e and the g - e spectra are full size)."""
+    (patch and conv priors only) is refused for other priors and with a
+    negative sigma, and grows the solve state (conv: d, e and the g - e
+    spectra are full size; patch: the FP32 codes, the split products and the
+    two 256 x 256 systems)."""
     from paper_2006_08303_amd import cip
     K, S, N, M, Lf = 3, 3, 64, 4, 5
     base = cip.workspace_bytes(K, S, N, N, "conv3d", n_filters=M, filt_l=Lf)
@@ -119,6 +121,15 @@ def test_conv3d_and_dictionary_learning_validation(L):
     l2 = cip.workspace_bytes(K, S, N, N, "conv2d", n_filters=M, filt_l=Lf,
                              flags=cip.CIP_PLAN_DICT_UPDATE)
     assert l2 >= b2 + 2 * M * F * 8 + 2 * M * N * N * 4
+    A, J = 256, (N // 4) ** 2
+    pb = cip.workspace_bytes(K, S, N, N, "patch", n_atoms=A)
+    pl = cip.workspace_bytes(K, S, N, N, "patch", n_atoms=A, flags=cip.CIP_PLAN_DICT_UPDATE)
+    KS = min(16, J // 32)
+    assert pl >= pb + A * J * 4 + KS * (64 * S + A) * A * 4 + 2 * 256 * 256 * 4
+    with pytest.raises(cip.CipError) as e:
+        cip.workspace_bytes(K, S, N, N, "patch", n_atoms=A, flags=cip.CIP_PLAN_DICT_UPDATE,
+                            sigma=-1.0)
+    assert e.value.code == -1
     desc = cip._desc("conv3d", 1.0, flags=cip.CIP_PLAN_DICT_UPDATE, sigma=-1.0)
     desc.n_filters, desc.filt_l = M, Lf
     n = ctypes.c_size_t()
