@@ -75,9 +75,9 @@ hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA
                   (const float*)b.g, (const float*)b.e, b.bm, b.cm, nv, NA, KS, sigma)) != hipSuccess)
     return e;
   // D = B (Z Z^T + sigma I)^-1
-  if ((e = launch(k_pdl_chol, 1, 1024, 0, st, (const float*)b.cm, PDL_MAXM, NA, b.lt)) != hipSuccess)
+  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, NA, b.lt)) != hipSuccess)
     return e;
-  if ((e = launch(k_pdl_trsolve, (nv + 3) / 4, 256, (size_t)pdl_trsolve_lds_floats(NA) * 4, st,
+  if ((e = launch(k_pdl_trsolve, (nv + 4 * PDL_TR_ROWS - 1) / (4 * PDL_TR_ROWS), 256, (size_t)pdl_trsolve_lds_floats(NA) * 4, st,
                   (const float*)b.lt, NA, (const float*)b.bm, NA, 1, nv, b.d,
                   (uint16_t*)nullptr)) != hipSuccess)
     return e;
@@ -89,9 +89,9 @@ hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA
   hipLaunchKernelGGL(k_pdl_gram, dim3(nv / 16, nv / 16), dim3(256), 0, st, (const float*)b.g, NA,
                      rho, b.cm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch(k_pdl_chol, 1, 1024, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
+  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
     return e;
-  return launch(k_pdl_trsolve, (NA + 3) / 4, 256, (size_t)pdl_trsolve_lds_floats(nv) * 4, st,
+  return launch(k_pdl_trsolve, (NA + 4 * PDL_TR_ROWS - 1) / (4 * PDL_TR_ROWS), 256, (size_t)pdl_trsolve_lds_floats(nv) * 4, st,
                 (const float*)b.lt, nv, (const float*)b.g, 1, NA, NA, (float*)nullptr, b.m1bf);
 }
 

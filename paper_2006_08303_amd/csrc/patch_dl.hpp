@@ -13,10 +13,10 @@
 //                  split written to its own slice (no atomics);
 //   k_pdl_reduce   fixed-order sum of the slices, + sigma (G - E) and sigma I;
 //   k_pdl_chol     Cholesky factor of an SPD matrix of order m <= 256 in one
-//                  work-group: the matrix (padded with the identity to
-//                  256 x 256) lives in registers, 8 x 8 per thread, and the
-//                  pivot column is broadcast through LDS (one barrier per
-//                  column);
+//                  work-group: the lower half of the matrix (padded with the
+//                  identity to 256 x 256) lives in registers, 8 x 8 per
+//                  thread, and the pivot column is broadcast through LDS
+//                  (one barrier per column);
 //   k_pdl_trsolve  rows of B M^-1 = B L^-T L^-1, one row per wave, L packed
 //                  in LDS;
 //   k_pdl_project  the Frobenius projection and the dual update (one
@@ -118,21 +118,31 @@ __global__ void k_pdl_reduce(const float* __restrict__ part, const float* __rest
 // Cholesky factor L (M = L L^T) of the SPD matrix M of order m <= 256 whose
 // lower triangle is a[i * lda + k] (i >= k). Output lt[k * 256 + i] = L[i][k]
 // for i >= k (row k of lt is column k of L); orders above m are padded with
-// the identity. One work-group of 1024 threads: wave w holds the 64 x 64
-// block (w / 4, w % 4) of the padded matrix, lane the 8 x 8 tile
-// (lane / 8, lane % 8) of it, in registers; waves above the block diagonal
-// idle. Step j eliminates column j (Gaussian elimination on the symmetric
-// matrix, P[i][k] -= P[i][j] P[k][j] / P[j][j] for i, k > j); the pivot
-// column travels through a double-buffered LDS column, so one barrier per
-// step suffices. At the end L[i][k] = P[i][k] / sqrt(P[k][k]).
-__global__ void __launch_bounds__(1024)
+// the identity. One work-group of 640 threads: each of its 10 waves holds one
+// 64 x 64 block on or below the diagonal of the padded matrix, each lane an
+// 8 x 8 tile (lane / 8, lane % 8) of it, in registers. Step j eliminates
+// column j (Gaussian elimination on the symmetric matrix,
+// P[i][k] -= P[i][j] P[k][j] / P[j][j] for i, k > j): the owners of column j
+// publish it in LDS with its entries i <= j set to zero, and the pivot apart,
+// so that every tile applies the same unmasked rank-1 update; the buffers
+// alternate between steps, so one barrier per step suffices. At the end
+// L[i][k] = P[i][k] / sqrt(P[k][k]).
+// The block of wave w is chosen so that, with waves placed on the four SIMDs
+// round-robin, the blocks still active at step j (those with block column
+// >= j / 64) spread evenly: 3, 2, 1 and 1 per SIMD for the four column
+// blocks.
+constexpr int PDL_CHOL_THREADS = 640;
+
+__global__ void __launch_bounds__(PDL_CHOL_THREADS)
 k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) {
-  __shared__ float colb[2][PDL_MAXM];
+  __shared__ __align__(16) float colb[2][PDL_MAXM];
+  __shared__ float pivb[2];
   __shared__ float piv[PDL_MAXM];
+  constexpr int kBi[10] = {3, 2, 3, 3, 1, 2, 2, 3, 0, 1};
+  constexpr int kBk[10] = {3, 2, 2, 1, 1, 1, 0, 0, 0, 0};
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int bi = w >> 2, bk = w & 3;
+  const int bi = kBi[w], bk = kBk[w];
   const int ti = 8 * bi + (lane >> 3), tk = 8 * bk + (lane & 7);
-  const bool act = bi >= bk;
   float P[8][8];
 #pragma unroll
   for (int r = 0; r < 8; ++r)
@@ -140,61 +150,69 @@ k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) 
     for (int c = 0; c < 8; ++c) {
       const int i = 8 * ti + r, k = 8 * tk + c;
       float v = i == k ? 1.f : 0.f;
-      if (act && i < m && k < m) v = i >= k ? a[(size_t)i * lda + k] : a[(size_t)k * lda + i];
+      if (i < m && k < m) v = i >= k ? a[(size_t)i * lda + k] : a[(size_t)k * lda + i];
       P[r][c] = v;
     }
-  for (int j = 0; j < PDL_MAXM; ++j) {
+  // orders above m are the identity: their elimination steps change nothing
+  for (int j = 0; j < m; ++j) {
     float* cb = colb[j & 1];
-    if (act && tk == (j >> 3)) {
+    if (tk == (j >> 3)) {
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c == (j & 7)) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) cb[8 * ti + r] = P[r][c];
+          for (int r = 0; r < 8; ++r) {
+            const int i = 8 * ti + r;
+            cb[i] = i > j ? P[r][c] : 0.f;
+            if (i == j) pivb[j & 1] = P[r][c];
+          }
         }
     }
     __syncthreads();
-    if (act && 8 * ti + 7 > j && 8 * tk + 7 > j) {
-      const float inv = 1.f / cb[j];
-      float cr[8], cc[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) cr[r] = cb[8 * ti + r];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) cc[c] = cb[8 * tk + c] * inv;
+    if (8 * ti + 7 > j && 8 * tk + 7 > j) {
+      const float inv = 1.f / pivb[j & 1];
+      const float4* cq = reinterpret_cast<const float4*>(cb);
+      const float4 r0 = cq[2 * ti], r1 = cq[2 * ti + 1];
+      const float4 c0 = cq[2 * tk], c1 = cq[2 * tk + 1];
+      const float cr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+      const float cc[8] = {c0.x * inv, c0.y * inv, c0.z * inv, c0.w * inv,
+                           c1.x * inv, c1.y * inv, c1.z * inv, c1.w * inv};
 #pragma unroll
       for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (8 * ti + r > j && 8 * tk + c > j) P[r][c] = fmaf(-cr[r], cc[c], P[r][c]);
+        for (int c = 0; c < 8; ++c) P[r][c] = fmaf(-cr[r], cc[c], P[r][c]);
     }
   }
-  if (act && ti == tk) {
+  if (ti == tk) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) piv[8 * ti + r] = sqrtf(P[r][r]);
   }
   __syncthreads();
-  if (act) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int k = 8 * tk + c;
-      const float s = 1.f / piv[k];
+  for (int c = 0; c < 8; ++c) {
+    const int k = 8 * tk + c;
+    const float s = 1.f / piv[k];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int i = 8 * ti + r;
-        if (i >= k) lt[(size_t)k * PDL_MAXM + i] = P[r][c] * s;
-      }
+    for (int r = 0; r < 8; ++r) {
+      const int i = 8 * ti + r;
+      if (i >= k) lt[(size_t)k * PDL_MAXM + i] = P[r][c] * s;
     }
   }
 }
+
+// Rows of B per wave in k_pdl_trsolve (the solve is bound by instruction
+// issue: more rows per wave lengthen every step as much as they save)
+constexpr int PDL_TR_ROWS = 1;
 
 // LDS floats of k_pdl_trsolve for order m: packed columns of L and 1 / L[k][k]
 __host__ __device__ constexpr int pdl_trsolve_lds_floats(int m) { return m * (m + 1) / 2 + m; }
 
 // Rows of X = B M^-1 with M = L L^T (lt from k_pdl_chol, order m): for every
 // row b of B, x solves M x^T = b^T (M symmetric): L y = b^T (forward), then
-// L^T x = y (backward), both column by column. One wave per row (lane holds
-// entries lane + 64 r), four rows per work-group; L is staged in LDS as
-// packed columns (column k at offset k m - k (k - 1) / 2, entries k..m-1).
+// L^T x = y (backward), both column by column. PDL_TR_ROWS rows per wave
+// (lane holds entries lane + 64 r), four waves per work-group; L is staged
+// in LDS as packed columns (column k at offset k m - k (k - 1) / 2, entries
+// k..m-1).
 // B entry (row, col) is b[row * bsr + col * bsc]; X is written row-major
 // (q x m) to xo (FP32) and/or xbf (BF16) when those are not null.
 __global__ void __launch_bounds__(256)
@@ -222,48 +240,88 @@ k_pdl_trsolve(const float* __restrict__ lt, int m, const float* __restrict__ b, 
   for (int k = threadIdx.x; k < m; k += 256) rd[k] = 1.f / Lp[k * m - k * (k - 1) / 2];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= q) return;
-  float y[4];
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * PDL_TR_ROWS;
+  if (row0 >= q) return;
+  float y[PDL_TR_ROWS][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int c = lane + 64 * r;
-    y[r] = c < m ? b[(size_t)row * bsr + (size_t)c * bsc] : 0.f;
-  }
-  auto pick = [&](int k) -> float {
+  for (int t = 0; t < PDL_TR_ROWS; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = lane + 64 * r;
+      y[t][r] = (c < m && row0 + t < q) ? b[(size_t)(row0 + t) * bsr + (size_t)c * bsc] : 0.f;
+    }
+  auto pick = [&](int t, int k) -> float {
     const int r = k >> 6;
-    const float v = r == 0 ? y[0] : (r == 1 ? y[1] : (r == 2 ? y[2] : y[3]));
+    const float v = r == 0 ? y[t][0] : (r == 1 ? y[t][1] : (r == 2 ? y[t][2] : y[t][3]));
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k & 63));
   };
-  // forward: L y = b
+  // The LDS operands of step k + 1 are loaded before step k's dependent
+  // arithmetic, so that their latency overlaps it; the rows of a wave share
+  // them.
+  // forward: L y = b; column k of L at col(k)[i], i >= k
+  auto colv = [&](int k, float (&v)[4], float& rk) {
+    const float* col = Lp + k * m - k * (k - 1) / 2 - k;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lane + 64 * r;
+      v[r] = (i > k && i < m) ? col[i] : 0.f;
+    }
+    rk = rd[k];
+  };
+  float cv[4], rk;
+  colv(0, cv, rk);
   for (int k = 0; k < m; ++k) {
-    const float yk = pick(k) * rd[k];
-    const float* col = Lp + k * m - k * (k - 1) / 2 - k;   // col[i] = L[i][k], i >= k
+    float nv[4], nr = 0.f;
+    if (k + 1 < m) colv(k + 1, nv, nr);
+#pragma unroll
+    for (int t = 0; t < PDL_TR_ROWS; ++t) {
+      const float yk = pick(t, k) * rk;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = lane + 64 * r;
+        y[t][r] = i == k ? yk : fmaf(-cv[r], yk, y[t][r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cv[r] = nv[r];
+    rk = nr;
+  }
+  // backward: L^T x = y; row k of L (entries i < k) at Lp[i m - i (i - 1) / 2 + k - i]
+  auto rowv = [&](int k, float (&v)[4], float& rkk) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = lane + 64 * r;
-      if (i == k) y[r] = yk;
-      else if (i > k && i < m) y[r] = fmaf(-col[i], yk, y[r]);
+      v[r] = i < k ? Lp[i * m - i * (i - 1) / 2 + (k - i)] : 0.f;
     }
-  }
-  // backward: L^T x = y
+    rkk = rd[k];
+  };
+  rowv(m - 1, cv, rk);
   for (int k = m - 1; k >= 0; --k) {
-    const float xk = pick(k) * rd[k];
+    float nv[4], nr = 0.f;
+    if (k > 0) rowv(k - 1, nv, nr);
+#pragma unroll
+    for (int t = 0; t < PDL_TR_ROWS; ++t) {
+      const float xk = pick(t, k) * rk;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = lane + 64 * r;
+        y[t][r] = i == k ? xk : fmaf(-cv[r], xk, y[t][r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cv[r] = nv[r];
+    rk = nr;
+  }
+#pragma unroll
+  for (int t = 0; t < PDL_TR_ROWS; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = lane + 64 * r;
-      if (i == k) y[r] = xk;
-      else if (i < k) y[r] = fmaf(-Lp[i * m - i * (i - 1) / 2 + (k - i)], xk, y[r]);
+      const int c = lane + 64 * r;
+      if (c < m && row0 + t < q) {
+        if (xo) xo[(size_t)(row0 + t) * m + c] = y[t][r];
+        if (xbf) xbf[(size_t)(row0 + t) * m + c] = f2bf(y[t][r]);
+      }
     }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int c = lane + 64 * r;
-    if (c < m) {
-      if (xo) xo[(size_t)row * m + c] = y[r];
-      if (xbf) xbf[(size_t)row * m + c] = f2bf(y[r]);
-    }
-  }
 }
 
 // G = (D + E) / ||D + E||_F, E <- E + G - D, and G in BF16 (count = n A

@@ -2,9 +2,10 @@
 ADMM0 / sold_patch, ADMM1, subh) against the FP64 oracle. The code update
 runs on BF16 MFMA as in the fixed-dictionary path; the dictionary step uses
 FP32 MFMA products, FP32 Cholesky factors and FP32 triangular solves. x must
-meet the BF16 path's 2e-3 relative l2; the learned dictionary G is compared
-in relative Frobenius norm with the tolerance given per case (the D-step
-amplifies the BF16 code error by the conditioning of Z Z^T + sigma I)."""
+meet the BF16 path's 2e-3 relative l2, and so must the learned dictionary G
+in relative Frobenius norm; the dictionary step alone, on the same BF16
+codes, must match FP64 to 1e-4 (FP32 arithmetic of a well-conditioned
+step)."""
 import numpy as np
 import pytest
 import torch
