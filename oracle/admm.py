@@ -45,18 +45,20 @@ def analysis_objective(x, y, psf, transform, lam, beta):
 
 
 class AnalysisADMM:
-    """Algorithm 1 for T in {dct2d, dct3d, tv2d, tv3d} and Phi = l1, and for
+    """Algorithm 1 for T in {dct2d, dct3d, tv2d, tv3d, wdct3d (Symmlet-8
+    wavelet per slice, `levels` levels, then DCT along the bands)} and
+    Phi = l1, and for
     isotropic TV ("itv2d": T = I, Phi = TV, t-update by Chambolle's
     algorithm with `inner` iterations per ADMM iteration, warm-started from
     the previous dual p, step 1/8)."""
 
-    def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto", inner=20):
+    def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto", inner=20, levels=3):
         K, S, N1, N2 = psf.shape
         self.psf = psf
         self.kind = kind
         self.K, self.S, self.N1, self.N2 = K, S, N1, N2
         self.lam, self.beta = float(lam), float(beta)
-        self.T = priors.make_transform(kind, S, N1, N2)
+        self.T = priors.make_transform(kind, S, N1, N2, levels)
         self.tier = _tier(S, N1, N2, tier)
         self.inner = int(inner)
         self.set_rho(rho)

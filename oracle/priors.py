@@ -8,7 +8,10 @@
     differences along both image axes; "multidimensional discrete derivative
     operators" of Section III-A);
   - T = the same plus a forward difference along the band axis (3D case,
-    non-circular, no term after the last band).
+    non-circular, no term after the last band);
+  - T = 2D Symmlet-8 wavelet transform of each slice followed by the
+    orthonormal DCT-II along the band axis (the Kronecker basis used for the
+    analysis prior in Section V-A).
 * Soft thresholding, the l1 proximal map (Eq. solt_trans), sign(0) = -1.
 * Patch extraction P_j for Q x Q x T patches spanning all bands (Eq.
   patch_based), extracted circularly at a fixed stride.
@@ -91,6 +94,94 @@ class DCT3D(DCT2D):
     def Tt(self, w):
         w2 = np.tensordot(self.CS.T, w[0], axes=(1, 0))
         return self.C1.T @ w2 @ self.C2
+
+
+# ---------------------------------------------------------------- wavelet (x) DCT
+# Symmlet-8 scaling filter (Daubechies' least-asymmetric orthonormal wavelet
+# with 8 vanishing moments; 16 taps, sum sqrt(2), unit energy).
+SYM8 = np.array([
+    -0.0033824159510061256, -0.0005421323317911481, 0.03169508781149298,
+    0.007607487324917605, -0.1432942383508097, -0.061273359067658524,
+    0.4813596512583722, 0.7771857517005235, 0.3644418948353314,
+    -0.05194583810770904, -0.027219029917056003, 0.049137179673607506,
+    0.003808752013890615, -0.01495225833704823, -0.0003029205147213668,
+    0.0018899503327594609])
+
+
+def qmf_highpass(h: np.ndarray) -> np.ndarray:
+    """Wavelet filter of an orthonormal scaling filter: g[t] = (-1)^t h[L-1-t]."""
+    L = len(h)
+    return np.array([(-1.0) ** t * h[L - 1 - t] for t in range(L)])
+
+
+def dwt1(x: np.ndarray, h: np.ndarray, axis: int) -> np.ndarray:
+    """One level of the periodized orthonormal DWT along `axis`:
+    a[k] = sum_t h[t] x[(2k + t) mod N], d[k] = sum_t g[t] x[(2k + t) mod N];
+    the output holds [a | d] along the axis."""
+    g = qmf_highpass(h)
+    xa = np.moveaxis(x, axis, -1)
+    a = sum(h[t] * np.roll(xa, -t, axis=-1)[..., ::2] for t in range(len(h)))
+    d = sum(g[t] * np.roll(xa, -t, axis=-1)[..., ::2] for t in range(len(h)))
+    return np.moveaxis(np.concatenate([a, d], axis=-1), -1, axis)
+
+
+def idwt1(c: np.ndarray, h: np.ndarray, axis: int) -> np.ndarray:
+    """Adjoint (= inverse) of dwt1: x[n] = sum_k a[k] h[n - 2k] + d[k] g[n - 2k]
+    (indices mod N)."""
+    g = qmf_highpass(h)
+    ca = np.moveaxis(c, axis, -1)
+    n = ca.shape[-1]
+    ua = np.zeros_like(ca)
+    ud = np.zeros_like(ca)
+    ua[..., ::2] = ca[..., : n // 2]
+    ud[..., ::2] = ca[..., n // 2:]
+    x = sum(h[t] * np.roll(ua, t, axis=-1) + g[t] * np.roll(ud, t, axis=-1)
+            for t in range(len(h)))
+    return np.moveaxis(x, -1, axis)
+
+
+class WaveletDCT:
+    """The Kronecker transform of Section V-A for the analysis prior: the 2D
+    Symmlet-8 wavelet transform of every slice (periodized, `levels` levels,
+    Mallat layout: each level transforms the low-pass corner of the previous
+    one along both image axes) followed by the orthonormal DCT-II along the
+    band axis. Orthonormal, so T^H T = I."""
+
+    name = "wdct3d"
+
+    def __init__(self, S: int, N1: int, N2: int, levels: int = 3):
+        assert N1 % (1 << levels) == 0 and N2 % (1 << levels) == 0
+        self.S, self.N1, self.N2, self.levels = S, N1, N2, levels
+        self.h = SYM8
+        self.CS = dct_matrix(S)
+        self.shape = (1, S, N1, N2)
+
+    def wavelet2(self, x):
+        """2D DWT of every slice of x (S, N1, N2)."""
+        c = np.array(x, dtype=np.float64, copy=True)
+        r, q = self.N1, self.N2
+        for _ in range(self.levels):
+            blk = dwt1(dwt1(c[:, :r, :q], self.h, axis=2), self.h, axis=1)
+            c[:, :r, :q] = blk
+            r, q = r // 2, q // 2
+        return c
+
+    def iwavelet2(self, c):
+        x = np.array(c, dtype=np.float64, copy=True)
+        sizes = [(self.N1 >> l, self.N2 >> l) for l in range(self.levels)]
+        for r, q in reversed(sizes):
+            x[:, :r, :q] = idwt1(idwt1(x[:, :r, :q], self.h, axis=1), self.h, axis=2)
+        return x
+
+    def T(self, x):
+        return np.tensordot(self.CS, self.wavelet2(x), axes=(1, 0))[None]
+
+    def Tt(self, w):
+        return self.iwavelet2(np.tensordot(self.CS.T, w[0], axes=(1, 0)))
+
+    def gram_symbol(self, N1, N2):
+        """T^H T = I: the per-frequency symbol is 1."""
+        return np.ones((N1, N2))
 
 
 class TV2D:
@@ -176,7 +267,9 @@ class Identity:
         return np.ones((N1, N2))
 
 
-def make_transform(kind: str, S: int, N1: int, N2: int):
+def make_transform(kind: str, S: int, N1: int, N2: int, levels: int = 3):
+    if kind == "wdct3d":
+        return WaveletDCT(S, N1, N2, levels)
     return {"dct2d": DCT2D, "dct3d": DCT3D, "tv2d": TV2D, "tv3d": TV3D,
             "itv2d": Identity}[kind](S, N1, N2)
 

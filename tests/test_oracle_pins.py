@@ -869,6 +869,132 @@ def test_dct3d_admm_kkt():
 
 
 # ---------------------------------------------------------------- isotropic TV (T = I, Chambolle)
+def test_symmlet8_filter_is_orthonormal_with_eight_vanishing_moments():
+    """The Symmlet-8 scaling filter (Section V-A's wavelet): sum sqrt(2), unit
+    energy, orthogonal to its even shifts; its wavelet filter annihilates
+    polynomials of degree < 8 and not degree 8; the filter is not the
+    minimum-phase one (zeros on both sides of the unit circle: the
+    least-asymmetric choice of the family)."""
+    h = priors.SYM8
+    assert len(h) == 16
+    assert abs(h.sum() - math.sqrt(2.0)) < 1e-12
+    assert abs(np.dot(h, h) - 1.0) < 1e-12
+    for m in range(1, 8):
+        assert abs(np.dot(h[:-2 * m], h[2 * m:])) < 1e-12
+    g = priors.qmf_highpass(h)
+    t = np.arange(16.0)
+    for p in range(8):
+        assert abs(np.sum(g * t ** p)) < 1e-8 * np.sum(np.abs(g) * t ** p)
+    assert abs(np.sum(g * t ** 8)) > 1e3
+    r = np.abs(np.roots(h))
+    assert np.any(r < 0.9) and np.any(r > 1.1)
+
+
+def test_dwt1_equals_the_explicit_analysis_matrix():
+    """One periodized DWT level equals the product with the matrix whose row k
+    holds h[t] at column (2k + t) mod N (low-pass half) and g[t] likewise
+    (high-pass half), built entry by entry; that matrix is orthogonal."""
+    N = 32
+    h = priors.SYM8
+    g = priors.qmf_highpass(h)
+    W = np.zeros((N, N))
+    for k in range(N // 2):
+        for t in range(16):
+            W[k, (2 * k + t) % N] += h[t]
+            W[N // 2 + k, (2 * k + t) % N] += g[t]
+    assert np.allclose(W @ W.T, np.eye(N), atol=1e-12)
+    x = _rng(120).standard_normal((3, N))
+    assert np.allclose(priors.dwt1(x, h, axis=1), x @ W.T, atol=1e-13)
+    assert np.allclose(priors.idwt1(x @ W.T, h, axis=1), x, atol=1e-12)
+    # N smaller than the filter: the taps wrap around more than once
+    N = 8
+    W = np.zeros((N, N))
+    for k in range(N // 2):
+        for t in range(16):
+            W[k, (2 * k + t) % N] += h[t]
+            W[N // 2 + k, (2 * k + t) % N] += g[t]
+    x = _rng(121).standard_normal((2, N))
+    assert np.allclose(priors.dwt1(x, h, axis=1), x @ W.T, atol=1e-13)
+
+
+def test_wavelet_dct_is_orthonormal_and_maps_constants_to_one_coefficient():
+    """T = (2D Symmlet-8, 3 levels per slice) then DCT along the bands is
+    orthonormal (T^T T = I, T T^T = I on random data); a constant cube c
+    goes to the single coefficient sqrt(S) c 2^levels at the first band-DCT
+    index and the top-left corner (sum h = sqrt(2) per axis and level, zero
+    wavelet moment)."""
+    S, N1, N2 = 3, 32, 16
+    T = priors.WaveletDCT(S, N1, N2, levels=3)
+    x = _rng(122).standard_normal((S, N1, N2))
+    w = T.T(x)
+    assert abs(np.linalg.norm(w) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+    assert np.allclose(T.Tt(w), x, atol=1e-12)
+    c = _rng(123).standard_normal((1, S, N1, N2))
+    assert np.allclose(T.T(T.Tt(c)), c, atol=1e-12)
+    wc = T.T(np.full((S, N1, N2), 0.7))[0]
+    ref = np.zeros_like(wc)
+    ref[0, :N1 // 8, :N2 // 8] = math.sqrt(S) * 0.7 * 8.0
+    assert np.allclose(wc, ref, atol=1e-10)    # the tabulated taps' zero moment is ~2e-12
+    # the same transform as a product of dense per-level operators on one
+    # slice: level l applies W_R (x) W_C to the top-left R x C corner only
+    # (Mallat's pyramid), W the explicit analysis matrices of the 1D level
+    def w1(N):
+        g = priors.qmf_highpass(priors.SYM8)
+        W = np.zeros((N, N))
+        for k in range(N // 2):
+            for t in range(16):
+                W[k, (2 * k + t) % N] += priors.SYM8[t]
+                W[N // 2 + k, (2 * k + t) % N] += g[t]
+        return W
+    op = np.eye(N1 * N2)
+    R, C = N1, N2
+    for _ in range(3):
+        M = np.eye(N1 * N2)
+        idx = (np.arange(R)[:, None] * N2 + np.arange(C)[None, :]).ravel()
+        M[np.ix_(idx, idx)] = np.kron(w1(R), w1(C))
+        op = M @ op
+        R, C = R // 2, C // 2
+    per_slice = np.stack([(op @ x[s].ravel()).reshape(N1, N2) for s in range(S)])
+    ref = np.tensordot(priors.dct_matrix(S), per_slice, axes=(1, 0))
+    assert np.allclose(w[0], ref, atol=1e-12)
+
+
+def test_wavelet_dct_identity_blur_closed_form():
+    """With H = I the wavelet (x) DCT l1 problem is orthonormal-basis
+    denoising: ADMM reaches T^T soft(T y, lambda / beta), in both tiers."""
+    S, N = 2, 16
+    psf = np.zeros((S, S, N, N))
+    for s in range(S):
+        psf[s, s, 0, 0] = 1.0
+    y = _rng(124).standard_normal((S, N, N))
+    lam, beta, rho = 0.3, 1.0, 0.7
+    T = priors.WaveletDCT(S, N, N, levels=2)
+    ref = T.Tt(priors.soft(T.T(y), lam / beta))
+    for tier in ("freq", "dense"):
+        x, _, _ = admm.AnalysisADMM(psf, "wdct3d", lam, rho, beta, tier=tier,
+                                    levels=2).run(y, 400)
+        assert np.allclose(x, ref, atol=1e-9)
+
+
+def test_wavelet_dct_admm_kkt():
+    """Algorithm 1 with the wavelet (x) DCT prior reaches a KKT point of
+    beta/2 ||y - Hx||^2 + lambda ||T x||_1: beta H^T (Hx - y) + T^T s = 0 with
+    s in lambda d||t||_1 at t = T x."""
+    x0, psf = _small_problem(K=3, S=3, N1=16, N2=16, seed=45)
+    y = model.forward(x0, psf) + 0.01 * _rng(125).standard_normal((3, 16, 16))
+    lam, rho, beta = 1e-2, 0.2, 1.0
+    alg = admm.AnalysisADMM(psf, "wdct3d", lam, rho, beta, tier="freq", levels=2)
+    x, t, u = alg.run(y, 3000)
+    w = alg.T.T(x)
+    assert np.linalg.norm(w - t) < 1e-7 * np.linalg.norm(w)
+    s = rho * u                                   # the scaled dual: s = rho u
+    assert np.max(np.abs(s)) <= lam * (1 + 1e-6)
+    on = np.abs(t) > 1e-9
+    assert np.allclose(s[on], lam * np.sign(t[on]), atol=1e-6 * lam)
+    g = beta * model.adjoint(model.forward(x, psf) - y, psf) + alg.T.Tt(s)
+    assert np.max(np.abs(g)) < 1e-6 * np.max(np.abs(beta * model.adjoint(y, psf)))
+
+
 def test_div_is_negative_adjoint_of_grad():
     x = _rng(90).standard_normal((2, 6, 5))
     p = _rng(91).standard_normal((2, 2, 6, 5))
