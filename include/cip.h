@@ -88,6 +88,15 @@ typedef enum {
    * Sherman-Morrison solve at every 3D frequency. `filters` holds M filters
    * of S x L x L taps ([M][S][L][L]); no gradient term (mu = 0). */
   CIP_PRIOR_CONV3D = 7,
+  /* Wavelet (x) DCT analysis prior (Section V-A's Kronecker basis for the
+   * analysis case): T = C_S (x) W, W the 2D Symmlet-8 wavelet transform of
+   * every plane (periodized orthonormal DWT, Mallat's pyramid of
+   * `wt_levels` levels: each level transforms the low-pass corner of the
+   * previous one along both image axes), C_S the orthonormal DCT-II along
+   * the planes. T is orthonormal, so the x-update is that of the DCT priors
+   * (Psi = rho I + beta Lambda^H Lambda); Phi = l1. N1 and N2 must be
+   * multiples of 2^wt_levels. */
+  CIP_PRIOR_WDCT3D = 8,
 } cip_prior_kind;
 
 typedef struct {
@@ -125,6 +134,8 @@ typedef struct {
                            d_admm), > 0; 0 selects the paper's settings: 1
                            for the patch dictionary, 10 for the
                            convolutional one                               */
+  /* CIP_PRIOR_WDCT3D only:                                                   */
+  int wt_levels;        /* wavelet levels, 1 .. 10 (0: 3)                     */
 } cip_prior_desc;
 
 enum { CIP_PLAN_ADAPTIVE = 1, CIP_PLAN_DICT_UPDATE = 2 };

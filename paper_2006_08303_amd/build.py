@@ -1,9 +1,10 @@
 """Compile the HIP library for gfx950 (hipcc, in-tree).
 
 Translation units: csrc/cip.hip (C ABI, plan, operators, row passes),
-csrc/patch.hip (patch-dictionary MFMA kernels), csrc/conv.hip
-(convolutional-dictionary kernels), csrc/server.hip (request server on
-the plan API) and one csrc/col_pass.hip
+csrc/patch.hip (patch-dictionary MFMA kernels and their dictionary
+learning), csrc/conv.hip (convolutional-dictionary kernels),
+csrc/wavelet.hip (wavelet (x) DCT prior), csrc/server.hip (request server
+on the plan API) and one csrc/col_pass.hip
 instance per supported column length. They are compiled in
 parallel and linked into paper_2006_08303_amd/libcip.so.
 """
@@ -33,7 +34,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     jobs = [(os.path.join(CSRC, "cip.hip"), os.path.join(tmpdir, "cip.o"), []),
             (os.path.join(CSRC, "patch.hip"), os.path.join(tmpdir, "patch.o"), []),
             (os.path.join(CSRC, "conv.hip"), os.path.join(tmpdir, "conv.o"), []),
-            (os.path.join(CSRC, "server.hip"), os.path.join(tmpdir, "server.o"), [])]
+            (os.path.join(CSRC, "server.hip"), os.path.join(tmpdir, "server.o"), []),
+            (os.path.join(CSRC, "wavelet.hip"), os.path.join(tmpdir, "wavelet.o"), [])]
     for n in SIZES:
         jobs.append((os.path.join(CSRC, "col_pass.hip"), os.path.join(tmpdir, f"col_{n}.o"),
                      [f"-DCIP_COL_N={n}"]))

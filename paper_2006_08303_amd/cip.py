@@ -25,9 +25,10 @@ CIP_PRIOR_CONV2D = 4
 CIP_PRIOR_DCT3D = 5
 CIP_PRIOR_ITV2D = 6
 CIP_PRIOR_CONV3D = 7
+CIP_PRIOR_WDCT3D = 8
 PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
           "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D, "dct3d": CIP_PRIOR_DCT3D,
-          "itv2d": CIP_PRIOR_ITV2D, "conv3d": CIP_PRIOR_CONV3D}
+          "itv2d": CIP_PRIOR_ITV2D, "conv3d": CIP_PRIOR_CONV3D, "wdct3d": CIP_PRIOR_WDCT3D}
 
 
 class CipError(RuntimeError):
@@ -42,7 +43,8 @@ class _PriorDesc(ctypes.Structure):
                 ("patch_q", ctypes.c_int), ("patch_stride", ctypes.c_int),
                 ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
                 ("filt_l", ctypes.c_int), ("mu", ctypes.c_double), ("tv_inner", ctypes.c_int),
-                ("flags", ctypes.c_int), ("sigma", ctypes.c_double)]
+                ("flags", ctypes.c_int), ("sigma", ctypes.c_double),
+                ("wt_levels", ctypes.c_int)]
 
 
 class _AdaptiveParams(ctypes.Structure):
@@ -65,9 +67,10 @@ class _Tuning(ctypes.Structure):
                 ("row_us", ctypes.c_double), ("default_us", ctypes.c_double)]
 
 
-def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0, tv_inner=0, sigma=0.0):
+def _desc(prior, beta, dictionary=None, filters=None, mu=0.0, flags=0, tv_inner=0, sigma=0.0,
+          wt_levels=0):
     d = _PriorDesc(PRIORS[prior], float(beta), None, 0, 8, 4, None, 0, 0, float(mu),
-                   int(tv_inner), int(flags), float(sigma))
+                   int(tv_inner), int(flags), float(sigma), int(wt_levels))
     if dictionary is not None:
         d.dict = ctypes.c_void_p(dictionary.data_ptr())
         d.n_atoms = int(dictionary.shape[1])
@@ -160,8 +163,8 @@ def _dev_f32(t, shape, name):
 
 
 def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0, n_filters=0, filt_l=0,
-                    flags=0, sigma=0.0):
-    desc = _desc(prior, beta, flags=flags, sigma=sigma)
+                    flags=0, sigma=0.0, wt_levels=0):
+    desc = _desc(prior, beta, flags=flags, sigma=sigma, wt_levels=wt_levels)
     desc.n_atoms = int(n_atoms)
     desc.n_filters = int(n_filters)
     desc.filt_l = int(filt_l)
@@ -181,11 +184,12 @@ class Plan:
     s' at band offset s'); mu: gradient (Tikhonov) weight on the codes
     (conv2d only). dict_update (patch and conv priors): learn the dictionary
     online in every solve with penalty sigma (0: 1 for the patch prior, 10 for
-    the conv priors); dictionary() returns the learned dictionary or filters."""
+    the conv priors); dictionary() returns the learned dictionary or filters.
+    wt_levels: wavelet levels of prior="wdct3d" (0: 3)."""
 
     def __init__(self, psf, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
                  filters=None, stream=None, mu=0.0, adaptive=False, tv_inner=0,
-                 dict_update=False, sigma=0.0):
+                 dict_update=False, sigma=0.0, wt_levels=0):
         K, S, N1, N2 = psf.shape
         self.K, self.S, self.N1, self.N2 = int(K), int(S), int(N1), int(N2)
         self.prior, self.rho, self.lam, self.beta = prior, float(rho), float(lam), float(beta)
@@ -200,11 +204,12 @@ class Plan:
                 raise ValueError("conv3d filters must have shape [M, S, L, L]")
             _dev_f32(filters, tuple(filters.shape), "filters")
         flags = (CIP_PLAN_ADAPTIVE if adaptive else 0) | (CIP_PLAN_DICT_UPDATE if dict_update else 0)
-        desc = _desc(prior, beta, dictionary, filters, mu, flags, tv_inner, sigma)
+        desc = _desc(prior, beta, dictionary, filters, mu, flags, tv_inner, sigma, wt_levels)
         self.filters_shape = (tuple(filters.shape) if filters is not None else
                               tuple(dictionary.shape) if dictionary is not None else None)
         nbytes = workspace_bytes(self.K, self.S, self.N1, self.N2, prior, beta,
-                                 desc.n_atoms, desc.n_filters, desc.filt_l, desc.flags)
+                                 desc.n_atoms, desc.n_filters, desc.filt_l, desc.flags,
+                                 desc.sigma, desc.wt_levels)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=psf.device)
         h = ctypes.c_void_p()
         _check(lib().cip_plan_create(self.K, self.S, self.N1, self.N2,

@@ -19,6 +19,7 @@
 #include "norms.hpp"
 #include "itv.hpp"
 #include "patch_launch.hpp"
+#include "wavelet_launch.hpp"
 #include "conv_launch.hpp"
 #include "errors.hpp"
 #include "sizes.hpp"
@@ -71,6 +72,7 @@ struct Layout {
   size_t dbf0, m1bf0, pd0, pzf, ppart, pbm, pd, pcm, plt, pg, pe;  // patch dictionary learning
   size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t bw;                                                 // 3D conv: band DFT matrix
+  size_t wband, wcoef, wtmp;            // wavelet (x) DCT: band DCT, coefficients, staging
   size_t filt0, gtap, gehat, dsp, ecdl, dpl;                 // 3D dictionary update
   size_t tables;                        // bytes of the table region
   size_t state_bytes;                   // bytes of the state region
@@ -87,6 +89,7 @@ int state_floats_per_voxel(int kind) {
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
     case CIP_PRIOR_CONV2D: return 0;
     case CIP_PRIOR_CONV3D: return 0;
+    case CIP_PRIOR_WDCT3D: return 1;  // v = T x + u
     default: return -1;
   }
 }
@@ -136,6 +139,12 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   }
   L.rt64 = scr(F * 16);
   L.pl64 = scr((size_t)N1 * N2 * 8);
+  if (kind == CIP_PRIOR_WDCT3D) {
+    L.wband = tab((size_t)S * S * 4);
+    L.wcoef = sta((size_t)S * N1 * N2 * 4);
+    L.wtmp = sta((size_t)S * N1 * N2 * 4);
+    L.rimg = sta((size_t)S * N1 * N2 * 4);
+  }
   if (kind == CIP_PRIOR_PATCH) {
     const size_t nv = (size_t)64 * S, na = (size_t)prior->n_atoms;
     const size_t J = (size_t)(N1 / 4) * (N2 / 4);
@@ -207,6 +216,12 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
   if (prior->kind == CIP_PRIOR_ITV2D && (prior->tv_inner < 0 || prior->tv_inner > 10000))
     return fail(CIP_EINVAL, "tv_inner must be in [0, 10000]");
+  if (prior->kind == CIP_PRIOR_WDCT3D) {
+    const int lv = prior->wt_levels > 0 ? prior->wt_levels : 3;
+    if (prior->wt_levels < 0 || lv > 10) return fail(CIP_EINVAL, "wt_levels must be in [0, 10]");
+    if (N1 % (1 << lv) || N2 % (1 << lv))
+      return fail(CIP_EUNSUPPORTED, "wavelet prior: N1 and N2 must be multiples of 2^wt_levels");
+  }
   if (prior->kind == CIP_PRIOR_PATCH) {
     if (!is_pow2(N1) || !is_pow2(N2))
       return fail(CIP_EUNSUPPORTED, "patch prior: power-of-two grids only");
@@ -252,6 +267,7 @@ struct cip_plan_s {
   int row_np;           // row pairs per work-group of the DCT row pass (2 or 4)
   int row_ppt;          // points per thread of the analysis row passes (default or 8)
   int tv_inner;         // isotropic TV: Chambolle iterations per ADMM iteration
+  int wt_levels;        // wavelet (x) DCT: levels of the 2D wavelet transform
   template <typename T> T* at(size_t off) const {
     return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
   }
@@ -560,6 +576,39 @@ hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
                 p->at<const cx<float>>(L.twN2f), st);
     if (e != hipSuccess) return e;
     if (l < iters && (e = patch_step(p, d_x, l == 1 ? 1 : 0, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Algorithm 1 with the wavelet (x) DCT prior. Per iteration l = 1..L:
+//   x-update (Eq. solx_Trans_DFT, T^T T = I): row FFT of r = T^T (t - u)
+//   (r = 0 for l = 1), column FFT + per-frequency solve (rhs b + rho r^) +
+//   inverse column FFT, inverse row FFT -> x^l (written to d_x);
+//   for l < L: forward wavelet levels of x^l, band DCT, soft threshold and
+//   dual update in v-form (Eqs. solt_trans, subu_trans), inverse band DCT and
+//   wavelet levels of t - u -> r.
+hipError_t solve_wdct(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
+  const Layout& L = p->L;
+  const int S = p->S, N1 = p->N1, N2 = p->N2, lv = p->wt_levels;
+  const float kappa = (float)(p->lambda / p->rho);
+  float* coef = p->at<float>(L.wcoef);
+  float* tmp = p->at<float>(L.wtmp);
+  float* r = p->at<float>(L.rimg);
+  hipError_t e;
+  for (int l = 1; l <= iters; ++l) {
+    if (l > 1 && (e = row_r2c<float>(r, p->at<cx<float>>(L.bufA), S, N1, N2,
+                                     p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
+      return e;
+    if ((e = admm_col(p, l == 1 ? 1 : 0, 0, st)) != hipSuccess) return e;
+    if ((e = row_c2r(p->at<const cx<float>>(L.bufB), d_x, S, N1, N2, 1.0f,
+                     p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
+      return e;
+    if (l == iters) break;
+    if ((e = wavelet_forward(d_x, coef, tmp, S, N1, N2, lv, st)) != hipSuccess) return e;
+    if ((e = wavelet_state(coef, p->at<float>(L.state), p->at<const float>(L.wband), S, N1, N2,
+                           kappa, l == 1 ? 1 : 0, st)) != hipSuccess)
+      return e;
+    if ((e = wavelet_inverse(coef, r, tmp, S, N1, N2, lv, st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -909,6 +958,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->row_np = PAIRS;
   p->row_ppt = ppt_row_n(N2);
   p->tv_inner = prior->kind == CIP_PRIOR_ITV2D ? (prior->tv_inner > 0 ? prior->tv_inner : 20) : 0;
+  p->wt_levels =
+      prior->kind == CIP_PRIOR_WDCT3D ? (prior->wt_levels > 0 ? prior->wt_levels : 3) : 0;
 
   auto cleanup_fail = [&](int code, const std::string& m) {
     delete p;
@@ -937,14 +988,14 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN1d), t1d.data(), N1 * 16, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipMemcpyAsync(p->at<void>(L.twN2d), t2d.data(), N2 * 16, hipMemcpyHostToDevice, st));
   PLAN_HIP(hipStreamSynchronize(st));
-  if (L.band) {   // orthonormal DCT-II along the band axis, C[k][s] = a_k cos(pi (2s+1) k / 2S)
+  if (L.band || L.wband) {   // orthonormal DCT-II along the bands, C[k][s] = a_k cos(pi (2s+1) k / 2S)
     std::vector<float> cs((size_t)S * S);
     for (int k = 0; k < S; ++k)
       for (int j = 0; j < S; ++j)
         cs[(size_t)k * S + j] = (float)((k == 0 ? std::sqrt(1.0 / S) : std::sqrt(2.0 / S)) *
                                         std::cos(M_PI * (2.0 * j + 1.0) * k / (2.0 * S)));
-    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.band), cs.data(), cs.size() * 4, hipMemcpyHostToDevice,
-                            st));
+    PLAN_HIP(hipMemcpyAsync(p->at<void>(L.band ? L.band : L.wband), cs.data(), cs.size() * 4,
+                            hipMemcpyHostToDevice, st));
     PLAN_HIP(hipStreamSynchronize(st));
   }
   dct_table(N1, fw);
@@ -1087,8 +1138,10 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   HIP_TRY((col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufA), p->at<void>(L.xh0), p->K, p->S,
                                    p->N1, p->H2, p->at<const cx<float>>(L.twN1f),
                                    p->at<const cx<float>>(L.Mm), 0, st)));
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D) {
+  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
+      p->kind == CIP_PRIOR_WDCT3D) {
     if (p->kind == CIP_PRIOR_PATCH) HIP_TRY(solve_patch(p, iters, d_x, st));
+    else if (p->kind == CIP_PRIOR_WDCT3D) HIP_TRY(solve_wdct(p, iters, d_x, st));
     else HIP_TRY(solve_conv(p, iters, d_x, st));
     p->solved_once = true;
     return CIP_OK;
@@ -1132,7 +1185,7 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (!p->adaptive) return fail(CIP_EINVAL, "plan was not created with CIP_PLAN_ADAPTIVE");
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
-      p->kind == CIP_PRIOR_ITV2D)
+      p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED, "adaptive penalty: l1 analysis priors only");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
       !(prm->tol >= 0.0))
@@ -1382,7 +1435,7 @@ int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   if (!p || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
-      p->kind == CIP_PRIOR_ITV2D)
+      p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED, "autotuning covers the l1 analysis row passes");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool dct = is_dct(p);
@@ -1437,7 +1490,7 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   const int pd = ppt_row_n(p->N2);
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
-      p->kind == CIP_PRIOR_ITV2D)
+      p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED, "tuning covers the l1 analysis row passes");
   if (!(row_np == PAIRS || row_np == 2)) return fail(CIP_EINVAL, "row_np must be 4 or 2");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))
@@ -1455,7 +1508,8 @@ int cip_time_kernel(cip_plan_t p, int which, int reps, void* stream, double* avg
              patch = p->kind == CIP_PRIOR_PATCH;
   if (which == 2 && !patch && !conv)
     return fail(CIP_EINVAL, "which = 2 needs the patch or convolutional prior");
-  if (patch && which == 0) return fail(CIP_EINVAL, "the patch prior has no fused row pass");
+  if ((patch || p->kind == CIP_PRIOR_WDCT3D) && which == 0)
+    return fail(CIP_EINVAL, "this prior has no fused row pass");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

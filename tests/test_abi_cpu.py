@@ -138,3 +138,23 @@ def test_conv3d_and_dictionary_learning_validation(L):
     desc.n_filters, desc.filt_l = M, Lf
     assert L.cip_plan_workspace_bytes(K, S, N, N, ctypes.byref(desc), ctypes.byref(n)) == -2
     assert L.cip_plan_dictionary(None, None, None) == -1
+
+
+def test_wavelet_prior_validation(L):
+    """Wavelet (x) DCT prior: grids must be multiples of 2^wt_levels, levels
+    in [0, 10] (0: 3); the state is v plus coefficient, staging and image
+    buffers."""
+    from paper_2006_08303_amd import cip
+    K, S = 3, 3
+    n3 = cip.workspace_bytes(K, S, 64, 64, "wdct3d")
+    assert n3 >= 4 * S * 64 * 64 * 4
+    assert cip.workspace_bytes(K, S, 384, 384, "wdct3d", wt_levels=7) > 0
+    with pytest.raises(cip.CipError) as e:
+        cip.workspace_bytes(K, S, 384, 384, "wdct3d", wt_levels=8)
+    assert e.value.code == -2
+    with pytest.raises(cip.CipError) as e:
+        cip.workspace_bytes(K, S, 64, 64, "wdct3d", wt_levels=11)
+    assert e.value.code == -1
+    with pytest.raises(cip.CipError) as e:
+        cip.workspace_bytes(K, S, 64, 64, "wdct3d", wt_levels=-1)
+    assert e.value.code == -1
