@@ -161,7 +161,8 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
 def run_other_priors(args, dev, psf_t, y_t):
     """The other priors at the precision-workload shape (K = S = 3, 1024^2),
     one solve of `iters_other` iterations each after a warm-up solve:
-    DCT3D, patch dictionary (A = 256; with online dictionary learning),
+    DCT3D, wavelet (x) DCT (Symmlet-8, 3 levels), patch dictionary (A = 256;
+    with online dictionary learning),
     convolutional dictionary (32 filters 11 x 11; with the gradient term; 3D
     filters 3 x 11 x 11; 2D and 3D with online dictionary learning).
     Parameters as in the parity tests."""
@@ -178,6 +179,8 @@ def run_other_priors(args, dev, psf_t, y_t):
                       dtype=torch.float32, device=dev)
     cases = [
         ("dct3d", dict(prior="dct3d", rho=0.1, lam=1e-2, beta=1.0), None),
+        ("wavelet (x) DCT (Symmlet-8, 3 levels)", dict(prior="wdct3d", rho=0.1, lam=1e-2,
+                                                     beta=1.0), None),
         ("patch (A = 256)", dict(prior="patch", rho=1e-4, lam=5e-6, beta=500.0, dictionary=D), 2),
         ("patch + online dictionary update (A = 256, sigma = 1000 J)",
          dict(prior="patch", rho=1e-4, lam=5e-5, beta=500.0, dictionary=D1, dict_update=True,
