@@ -7,38 +7,58 @@ namespace cip {
 
 namespace {
 int blocks(size_t n) { return (int)((n + 255) / 256); }
+
+// work-groups of a level with T x T coefficient tiles per band
+dim3 tile_grid(int R, int C, int planes, int T) {
+  return dim3((C / 2 + T - 1) / T, (R / 2 + T - 1) / T, planes);
+}
+
+// 32 x 32 tiles (less halo per coefficient) when they still give two
+// work-groups per compute unit, else 16 x 16
+bool big_tiles(int R, int C, int planes) {
+  const dim3 g = tile_grid(R, C, planes, 32);
+  return (size_t)g.x * g.y * g.z >= 512;
+}
 }  // namespace
 
+// Staging areas of the low-low bands: the top-left and bottom-right
+// quadrants of tmp (every level after the first fits in a quadrant).
 hipError_t wavelet_forward(const float* x, float* coef, float* tmp, int planes, int N1, int N2,
                            int levels, hipStream_t st) {
-  int R = N1, C = N2;
-  hipError_t e;
+  float* area[2] = {tmp, tmp + (size_t)(N1 / 2) * N2 + N2 / 2};
+  const float* src = x;
   for (int l = 0; l < levels; ++l) {
-    const float* src = l == 0 ? x : coef;
-    if ((e = launch(k_dwt_rows, blocks((size_t)planes * R * (C / 2)), 256, 0, st, src, tmp, planes,
-                    N1, N2, R, C)) != hipSuccess)
-      return e;
-    if ((e = launch(k_dwt_cols, blocks((size_t)planes * (R / 2) * C), 256, 0, st,
-                    (const float*)tmp, coef, planes, N1, N2, R, C)) != hipSuccess)
-      return e;
-    R /= 2;
-    C /= 2;
+    const int R = N1 >> l, C = N2 >> l;
+    float* ll = l == levels - 1 ? coef : area[l & 1];
+    if (big_tiles(R, C, planes))
+      hipLaunchKernelGGL(k_dwt2<32>, tile_grid(R, C, planes, 32), dim3(256), 0, st, src, ll, coef,
+                         N1, N2, R, C);
+    else
+      hipLaunchKernelGGL(k_dwt2<16>, tile_grid(R, C, planes, 16), dim3(256), 0, st, src, ll, coef,
+                         N1, N2, R, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = ll;
   }
   return hipSuccess;
 }
 
 hipError_t wavelet_inverse(float* coef, float* x, float* tmp, int planes, int N1, int N2,
                            int levels, hipStream_t st) {
-  hipError_t e;
+  float* area[2] = {tmp, tmp + (size_t)(N1 / 2) * N2 + N2 / 2};
+  const float* ll = coef;
   for (int l = levels - 1; l >= 0; --l) {
     const int R = N1 >> l, C = N2 >> l;
-    float* dst = l == 0 ? x : coef;
-    if ((e = launch(k_idwt_cols, blocks((size_t)planes * (R / 2) * C), 256, 0, st,
-                    (const float*)coef, tmp, planes, N1, N2, R, C)) != hipSuccess)
-      return e;
-    if ((e = launch(k_idwt_rows, blocks((size_t)planes * R * (C / 2)), 256, 0, st,
-                    (const float*)tmp, dst, planes, N1, N2, R, C)) != hipSuccess)
-      return e;
+    float* dst = l == 0 ? x : area[l & 1];
+    if (big_tiles(R, C, planes))
+      hipLaunchKernelGGL(k_idwt2<32>, tile_grid(R, C, planes, 32), dim3(256), 0, st, ll,
+                         (const float*)coef, dst, N1, N2, R, C);
+    else
+      hipLaunchKernelGGL(k_idwt2<16>, tile_grid(R, C, planes, 16), dim3(256), 0, st, ll,
+                         (const float*)coef, dst, N1, N2, R, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ll = dst;
   }
   return hipSuccess;
 }

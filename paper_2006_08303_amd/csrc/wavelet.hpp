@@ -9,10 +9,12 @@
 // with g[t] = (-1)^t h[15 - t], stored as [a | d]. The inverse is the
 // transpose: x[2m + e] = sum_j a[(m - j) mod n/2] h[e + 2j]
 //                                + d[(m - j) mod n/2] g[e + 2j].
-// The transform runs out of place, one launch per axis and level, between
-// a coefficient buffer and a staging buffer; the band DCT, the soft
-// threshold and the dual update (v-form state, as in the other analysis
-// priors) are one pointwise kernel over the coefficients.
+// One launch per level does both axes through an LDS tile. The detail
+// bands go to the coefficient buffer and the low-low band of a level to one
+// of two staging areas (quadrants of a staging buffer), which the next level
+// reads; the inverse mirrors this. The band DCT, the soft threshold and the
+// dual update (v-form state, as in the other analysis priors) are one
+// pointwise kernel over the coefficients.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -32,102 +34,162 @@ __device__ __forceinline__ float sym8_g(int t) {   // wavelet filter
   return (t & 1) ? -kSym8[15 - t] : kSym8[15 - t];
 }
 
-// Forward level along the rows (contiguous axis) of the R x C corner of
-// every plane (leading dimension N2, plane stride N1 N2): in -> out.
-// Thread (p, r, k), k < C / 2, forms a[k] and d[k].
-__global__ void k_dwt_rows(const float* __restrict__ in, float* __restrict__ out, int planes,
-                           int N1, int N2, int R, int C) {
-  const int h = C >> 1;
-  const size_t n = (size_t)planes * R * h;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int k = (int)(idx % h);
-  const int r = (int)((idx / h) % R);
-  const int p = (int)(idx / ((size_t)h * R));
-  const float* row = in + ((size_t)p * N1 + r) * N2;
-  float a = 0.f, d = 0.f;
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const float v = row[(2 * k + t) % C];
-    a = fmaf(kSym8[t], v, a);
-    d = fmaf(sym8_g(t), v, d);
-  }
-  float* o = out + ((size_t)p * N1 + r) * N2;
-  o[k] = a;
-  o[h + k] = d;
+// i mod n for i in [-n, n + 78) without an integer division (levels whose
+// side is below a tile's reach wrap several times)
+__device__ __forceinline__ int wrap_idx(int i, int n) {
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
 }
 
-// Forward level along the columns of the R x C corner: thread (p, k, c),
-// k < R / 2 (consecutive threads take consecutive columns).
-__global__ void k_dwt_cols(const float* __restrict__ in, float* __restrict__ out, int planes,
-                           int N1, int N2, int R, int C) {
-  const int h = R >> 1;
-  const size_t n = (size_t)planes * h * C;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int c = (int)(idx % C);
-  const int k = (int)((idx / C) % h);
-  const int p = (int)(idx / ((size_t)C * h));
-  const float* col = in + (size_t)p * N1 * N2 + c;
-  float a = 0.f, d = 0.f;
+// One forward level on the R x C corner (both axes fused through LDS). A
+// work-group produces the coefficients k1 in [K1, K1 + T), k2 in
+// [K2, K2 + T) of the four bands of one plane from the (2T + 14)^2 input
+// samples they read (indices mod R and mod C): the transform along the rows
+// first (a | d along the columns), then along the columns (a ; d along the
+// rows). The low-low band goes to ll (another buffer, or the coefficient
+// corner at the last level), the three others to coef. src and ll have the
+// coefficient array's layout (leading dimension N2, plane stride N1 N2).
+// DWT_T output coefficients per tile and axis (32, or 16 on the small
+// levels, whose grids would otherwise not fill the GPU); DWT_IN input
+// samples per tile and axis.
+template <int DWT_T>
+__global__ void __launch_bounds__(256)
+k_dwt2(const float* __restrict__ src, float* __restrict__ ll, float* __restrict__ coef, int N1,
+       int N2, int R, int C) {
+  constexpr int DWT_IN = 2 * DWT_T + 14;
+  __shared__ float X[DWT_IN][DWT_IN + 1];
+  __shared__ float RA[DWT_IN][DWT_T + 1], RD[DWT_IN][DWT_T + 1];
+  const int h1 = R >> 1, h2 = C >> 1;
+  const int K1 = blockIdx.y * DWT_T, K2 = blockIdx.x * DWT_T;
+  const size_t po = (size_t)blockIdx.z * N1 * N2;
+  const float* in = src + po;
+  // all of a thread's loads are issued before its LDS stores (latency overlap)
+  constexpr int NL = (DWT_IN * DWT_IN + 255) / 256;
+  float val[NL];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const float v = col[(size_t)((2 * k + t) % R) * N2];
-    a = fmaf(kSym8[t], v, a);
-    d = fmaf(sym8_g(t), v, d);
+  for (int q = 0; q < NL; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < DWT_IN * DWT_IN) {
+      const int u = e / DWT_IN, v = e % DWT_IN;
+      val[q] = in[(size_t)wrap_idx(2 * K1 + u, R) * N2 + wrap_idx(2 * K2 + v, C)];
+    }
   }
-  float* o = out + (size_t)p * N1 * N2 + c;
-  o[(size_t)k * N2] = a;
-  o[(size_t)(h + k) * N2] = d;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < DWT_IN * DWT_IN) X[e / DWT_IN][e % DWT_IN] = val[q];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < DWT_IN * DWT_T; e += 256) {
+    const int u = e / DWT_T, k = e % DWT_T;
+    float a = 0.f, d = 0.f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const float v = X[u][2 * k + t];
+      a = fmaf(kSym8[t], v, a);
+      d = fmaf(sym8_g(t), v, d);
+    }
+    RA[u][k] = a;
+    RD[u][k] = d;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < DWT_T * DWT_T; e += 256) {
+    const int i = e / DWT_T, k = e % DWT_T;
+    const int k1 = K1 + i, k2 = K2 + k;
+    if (k1 >= h1 || k2 >= h2) continue;
+    float aa = 0.f, ad = 0.f, da = 0.f, dd = 0.f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const float ra = RA[2 * i + t][k], rd = RD[2 * i + t][k];
+      aa = fmaf(kSym8[t], ra, aa);
+      ad = fmaf(kSym8[t], rd, ad);
+      da = fmaf(sym8_g(t), ra, da);
+      dd = fmaf(sym8_g(t), rd, dd);
+    }
+    ll[po + (size_t)k1 * N2 + k2] = aa;
+    coef[po + (size_t)k1 * N2 + h2 + k2] = ad;
+    coef[po + (size_t)(h1 + k1) * N2 + k2] = da;
+    coef[po + (size_t)(h1 + k1) * N2 + h2 + k2] = dd;
+  }
 }
 
-// Inverse level along the rows: thread (p, r, m), m < C / 2, forms x[2m]
-// and x[2m + 1] from a = in[0 .. C/2) and d = in[C/2 .. C).
-__global__ void k_idwt_rows(const float* __restrict__ in, float* __restrict__ out, int planes,
-                            int N1, int N2, int R, int C) {
-  const int h = C >> 1;
-  const size_t n = (size_t)planes * R * h;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int m = (int)(idx % h);
-  const int r = (int)((idx / h) % R);
-  const int p = (int)(idx / ((size_t)h * R));
-  const float* row = in + ((size_t)p * N1 + r) * N2;
-  float x0 = 0.f, x1 = 0.f;
+// One inverse level: the R x C corner from its four bands (low-low at ll,
+// the others in coef), written to dst. A work-group produces the samples
+// 2 m + e, m in [M, M + T) along both axes, from the band coefficients
+// (m - j) mod (R/2, C/2), j < 8 (T + 7 per axis): inverse along the rows
+// first, then along the columns.
+template <int DWT_T>
+__global__ void __launch_bounds__(256)
+k_idwt2(const float* __restrict__ ll, const float* __restrict__ coef, float* __restrict__ dst,
+        int N1, int N2, int R, int C) {
+  constexpr int IDWT_IN = DWT_T + 7;
+  __shared__ float B[4][IDWT_IN][IDWT_IN + 1];
+  __shared__ float YL[IDWT_IN][2 * DWT_T + 1], YH[IDWT_IN][2 * DWT_T + 1];
+  const int h1 = R >> 1, h2 = C >> 1;
+  const int M1 = blockIdx.y * DWT_T, M2 = blockIdx.x * DWT_T;
+  const size_t po = (size_t)blockIdx.z * N1 * N2;
+  // band b: 0 low-low, 1 low rows / high columns, 2 high rows / low columns, 3 high-high
+  // all of a thread's loads are issued before its LDS stores (latency overlap)
+  constexpr int NB = IDWT_IN * IDWT_IN, NL = (4 * NB + 255) / 256;
+  float val[NL];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int k = ((m - j) % h + h) % h;
-    const float a = row[k], d = row[h + k];
-    x0 = fmaf(kSym8[2 * j], a, fmaf(sym8_g(2 * j), d, x0));
-    x1 = fmaf(kSym8[2 * j + 1], a, fmaf(sym8_g(2 * j + 1), d, x1));
+  for (int q = 0; q < NL; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < 4 * NB) {
+      const int b = e / NB, r = e % NB;
+      const int u = r / IDWT_IN, v = r % IDWT_IN;
+      const int k1 = wrap_idx(M1 - 7 + u, h1), k2 = wrap_idx(M2 - 7 + v, h2);
+      const float* base =
+          b == 0 ? ll + po : coef + po + (size_t)((b >> 1) * h1) * N2 + (b & 1) * h2;
+      val[q] = base[(size_t)k1 * N2 + k2];
+    }
   }
-  float* o = out + ((size_t)p * N1 + r) * N2;
-  o[2 * m] = x0;
-  o[2 * m + 1] = x1;
-}
-
-// Inverse level along the columns: thread (p, m, c), m < R / 2.
-__global__ void k_idwt_cols(const float* __restrict__ in, float* __restrict__ out, int planes,
-                            int N1, int N2, int R, int C) {
-  const int h = R >> 1;
-  const size_t n = (size_t)planes * h * C;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int c = (int)(idx % C);
-  const int m = (int)((idx / C) % h);
-  const int p = (int)(idx / ((size_t)C * h));
-  const float* col = in + (size_t)p * N1 * N2 + c;
-  float x0 = 0.f, x1 = 0.f;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int k = ((m - j) % h + h) % h;
-    const float a = col[(size_t)k * N2], d = col[(size_t)(h + k) * N2];
-    x0 = fmaf(kSym8[2 * j], a, fmaf(sym8_g(2 * j), d, x0));
-    x1 = fmaf(kSym8[2 * j + 1], a, fmaf(sym8_g(2 * j + 1), d, x1));
+  for (int q = 0; q < NL; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < 4 * NB) {
+      const int r = e % NB;
+      B[e / NB][r / IDWT_IN][r % IDWT_IN] = val[q];
+    }
   }
-  float* o = out + (size_t)p * N1 * N2 + c;
-  o[(size_t)(2 * m) * N2] = x0;
-  o[(size_t)(2 * m + 1) * N2] = x1;
+  __syncthreads();
+  // along the rows: Y[u][2 m + e] for the low and the high row families
+  for (int e = threadIdx.x; e < IDWT_IN * DWT_T; e += 256) {
+    const int u = e / DWT_T, m = e % DWT_T;
+    float l0 = 0.f, l1 = 0.f, g0 = 0.f, g1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int v = m - j + 7;
+      const float a = B[0][u][v], d = B[1][u][v], a2 = B[2][u][v], d2 = B[3][u][v];
+      l0 = fmaf(kSym8[2 * j], a, fmaf(sym8_g(2 * j), d, l0));
+      l1 = fmaf(kSym8[2 * j + 1], a, fmaf(sym8_g(2 * j + 1), d, l1));
+      g0 = fmaf(kSym8[2 * j], a2, fmaf(sym8_g(2 * j), d2, g0));
+      g1 = fmaf(kSym8[2 * j + 1], a2, fmaf(sym8_g(2 * j + 1), d2, g1));
+    }
+    YL[u][2 * m] = l0;
+    YL[u][2 * m + 1] = l1;
+    YH[u][2 * m] = g0;
+    YH[u][2 * m + 1] = g1;
+  }
+  __syncthreads();
+  // along the columns: out[2 m + e][n]
+  float* out = dst + po;
+  for (int e = threadIdx.x; e < DWT_T * 2 * DWT_T; e += 256) {
+    const int m = e / (2 * DWT_T), n = e % (2 * DWT_T);
+    if (M1 + m >= h1 || M2 + (n >> 1) >= h2) continue;
+    float x0 = 0.f, x1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int u = m - j + 7;
+      const float a = YL[u][n], d = YH[u][n];
+      x0 = fmaf(kSym8[2 * j], a, fmaf(sym8_g(2 * j), d, x0));
+      x1 = fmaf(kSym8[2 * j + 1], a, fmaf(sym8_g(2 * j + 1), d, x1));
+    }
+    const size_t col = (size_t)2 * M2 + n;
+    out[(size_t)(2 * (M1 + m)) * N2 + col] = x0;
+    out[(size_t)(2 * (M1 + m) + 1) * N2 + col] = x1;
+  }
 }
 
 // Band DCT, soft threshold and dual update at every coefficient position
