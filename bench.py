@@ -160,7 +160,8 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
 
 def run_other_priors(args, dev, psf_t, y_t):
     """The other priors at the precision-workload shape (K = S = 3, 1024^2),
-    one solve of `iters_other` iterations each after a warm-up solve:
+    the median of three solves of `iters_other` iterations each after a
+    warm-up solve:
     DCT3D, wavelet (x) DCT (Symmlet-8, 3 levels), patch dictionary (A = 256;
     with online dictionary learning),
     convolutional dictionary (32 filters 11 x 11; with the gradient term; 3D
@@ -204,12 +205,17 @@ def run_other_priors(args, dev, psf_t, y_t):
         plan = cip.Plan(psf_t, prior, rho, lam, beta, **kw)
         x = plan.solve(y_t, 2)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.solve(y_t, it, out=x)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        # median of three timed solves (the priors with many short kernels per
+        # iteration are exposed to host launch jitter)
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            plan.solve(y_t, it, out=x)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = sorted(times)[1]
         rec = {"iters": it, "ms_per_iter": round(dt * 1e3 / it, 4),
-               "Mpixel_iter_per_s": round(N * N * it / dt / 1e6, 1)}
+               "Mpixel_iter_per_s": round(N * N * it / dt / 1e6, 1), "timed_solves": 3}
         if which is not None:
             rec["sparse_code_kernel_avg_us"] = round(plan.time_kernel(which, 20), 2)
         print(f"[bench] {name}: {rec}", file=sys.stderr, flush=True)
