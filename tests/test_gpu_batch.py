@@ -26,7 +26,7 @@ def _problems():
     spec = [("dct2d", 256, 3, 3, 12), ("tv2d", 128, 2, 4, 9), ("dct2d", 512, 3, 2, 5),
             ("tv2d", 64, 4, 1, 17), ("conv2d", 64, 3, 3, 6), ("patch", 64, 3, 3, 7),
             ("dct2d", 1024, 3, 3, 3), ("tv2d", 256, 6, 5, 4), ("tv2d", 384, 3, 2, 6),
-            ("dct2d", 768, 2, 5, 3)]
+            ("dct2d", 768, 2, 5, 3), ("wdct3d", 128, 3, 3, 8)]
     out = []
     for j, (prior, N, K, S, iters) in enumerate(spec):
         x, psf, noise = synth.problem("rects_gauss", N, K, S, seed_config=4) \

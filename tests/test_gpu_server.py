@@ -46,7 +46,8 @@ def test_attached_plans_run_concurrently():
     assert torch.equal(xa, ref0) and torch.equal(xb, ref1)
 
 
-SPEC = [("tv3d", 256, 3, 3), ("tv3d", 128, 5, 5), ("dct2d", 512, 3, 3), ("tv3d", 64, 8, 8)]
+SPEC = [("tv3d", 256, 3, 3), ("tv3d", 128, 5, 5), ("dct2d", 512, 3, 3), ("tv3d", 64, 8, 8),
+        ("wdct3d", 128, 3, 3)]
 
 
 def _server_with_ops(budget, slots):
