@@ -58,6 +58,20 @@ hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int
   return launch(k_pdl_start, (count + 255) / 256, 256, 0, st, d0, b.g, b.e, count);
 }
 
+// Rows of B M^-1 (k_pdl_trsolve, one row per wave) for order m <= 256.
+static hipError_t trsolve(const float* lt, int m, const float* b, int bsr, int bsc, int q, float* xo,
+                   uint16_t* xbf, hipStream_t st) {
+  const int grid = (q + 3) / 4;
+  const size_t lds = (size_t)pdl_trsolve_lds_floats(m) * 4;
+  switch ((m + 63) / 64) {
+    case 1: return launch(k_pdl_trsolve<1>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
+    case 2: return launch(k_pdl_trsolve<2>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
+    case 3: return launch(k_pdl_trsolve<3>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
+    case 4: return launch(k_pdl_trsolve<4>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
+  }
+  return hipErrorInvalidValue;
+}
+
 // One step of the dictionary ADMM and the new code tables (see patch_dl.hpp).
 hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
                            float sigma, float rho, hipStream_t st) {
@@ -77,10 +91,7 @@ hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA
   // D = B (Z Z^T + sigma I)^-1
   if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, NA, b.lt)) != hipSuccess)
     return e;
-  if ((e = launch(k_pdl_trsolve, (nv + 4 * PDL_TR_ROWS - 1) / (4 * PDL_TR_ROWS), 256, (size_t)pdl_trsolve_lds_floats(NA) * 4, st,
-                  (const float*)b.lt, NA, (const float*)b.bm, NA, 1, nv, b.d,
-                  (uint16_t*)nullptr)) != hipSuccess)
-    return e;
+  if ((e = trsolve(b.lt, NA, b.bm, NA, 1, nv, b.d, nullptr, st)) != hipSuccess) return e;
   // G, E and the BF16 dictionary
   if ((e = launch(k_pdl_project, 1, 1024, 0, st, (const float*)b.d, b.g, b.e, b.dbf, nv * NA)) !=
       hipSuccess)
@@ -91,8 +102,7 @@ hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
     return e;
-  return launch(k_pdl_trsolve, (NA + 4 * PDL_TR_ROWS - 1) / (4 * PDL_TR_ROWS), 256, (size_t)pdl_trsolve_lds_floats(nv) * 4, st,
-                (const float*)b.lt, nv, (const float*)b.g, 1, NA, NA, (float*)nullptr, b.m1bf);
+  return trsolve(b.lt, nv, b.g, 1, NA, NA, nullptr, b.m1bf, st);
 }
 
 bool patch_grid_ok(int N1, int N2) {

@@ -56,9 +56,9 @@ k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __r
   const float* za = zf + (size_t)(64 * (rb >= S ? rb - S : 0) + lr) * J;
   const float* xs = x + (size_t)(rb < S ? rb : 0) * G.N1 * G.N2;
   f32x16 acc = f32x16{};
-  const size_t jend = (size_t)(ks + 1) * chunk;
-  for (size_t j0 = (size_t)ks * chunk; j0 < jend; j0 += PDL_KSTEP) {
-    float av[8], bv[8];
+  // stage j0's operands are loaded into registers while stage j0 - 32
+  // runs on the MFMA units (software pipelining over the patches)
+  auto load = [&](size_t j0, float (&av)[8], float (&bv)[8]) {
     const float4* bp = reinterpret_cast<const float4*>(zb + j0 + lk);
     const float4 b0 = bp[0], b1 = bp[1];
     bv[0] = b0.x; bv[1] = b0.y; bv[2] = b0.z; bv[3] = b0.w;
@@ -77,6 +77,11 @@ k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __r
         av[q] = xs[(size_t)r * G.N2 + c];
       }
     }
+  };
+  const size_t jbeg = (size_t)ks * chunk, jend = jbeg + chunk;
+  float av[8], bv[8];
+  load(jbeg, av, bv);
+  for (size_t j0 = jbeg; j0 < jend; j0 += PDL_KSTEP) {
     __syncthreads();   // the previous stage has been consumed
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -84,6 +89,7 @@ k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __r
       Bs[lr][lk + q] = bv[q];
     }
     __syncthreads();
+    if (j0 + PDL_KSTEP < jend) load(j0 + PDL_KSTEP, av, bv);
 #pragma unroll
     for (int kk = 0; kk < PDL_KSTEP / 2; ++kk)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[32 * wr + l32][2 * kk + lhi],
@@ -200,21 +206,22 @@ k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) 
   }
 }
 
-// Rows of B per wave in k_pdl_trsolve (the solve is bound by instruction
-// issue: more rows per wave lengthen every step as much as they save)
-constexpr int PDL_TR_ROWS = 1;
-
 // LDS floats of k_pdl_trsolve for order m: packed columns of L and 1 / L[k][k]
 __host__ __device__ constexpr int pdl_trsolve_lds_floats(int m) { return m * (m + 1) / 2 + m; }
 
 // Rows of X = B M^-1 with M = L L^T (lt from k_pdl_chol, order m): for every
 // row b of B, x solves M x^T = b^T (M symmetric): L y = b^T (forward), then
-// L^T x = y (backward), both column by column. PDL_TR_ROWS rows per wave
-// (lane holds entries lane + 64 r), four waves per work-group; L is staged
-// in LDS as packed columns (column k at offset k m - k (k - 1) / 2, entries
-// k..m-1).
-// B entry (row, col) is b[row * bsr + col * bsc]; X is written row-major
-// (q x m) to xo (FP32) and/or xbf (BF16) when those are not null.
+// L^T x = y (backward), both column by column. One row per wave (lane holds
+// entries lane + 64 r, r < NR = ceil(m / 64)), four waves per work-group; L
+// is staged in LDS as packed columns (column k at offset k m - k (k - 1) / 2,
+// entries k..m-1). In each sweep the division by L[k][k] of the entry that
+// step k finishes is applied to the broadcast value only, and to the entries
+// themselves once at the end (an entry is not read again after its step).
+// The solve is bound by instruction issue (one dependent chain per wave):
+// the next step's LDS operands are loaded before the current step's
+// arithmetic. B entry (row, col) is b[row * bsr + col * bsc]; X is written
+// row-major (q x m) to xo (FP32) and/or xbf (BF16) when those are not null.
+template <int NR>
 __global__ void __launch_bounds__(256)
 k_pdl_trsolve(const float* __restrict__ lt, int m, const float* __restrict__ b, int bsr, int bsc,
               int q, float* __restrict__ xo, uint16_t* __restrict__ xbf) {
@@ -240,88 +247,86 @@ k_pdl_trsolve(const float* __restrict__ lt, int m, const float* __restrict__ b, 
   for (int k = threadIdx.x; k < m; k += 256) rd[k] = 1.f / Lp[k * m - k * (k - 1) / 2];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * PDL_TR_ROWS;
-  if (row0 >= q) return;
-  float y[PDL_TR_ROWS][4];
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= q) return;
+  float y[NR];
 #pragma unroll
-  for (int t = 0; t < PDL_TR_ROWS; ++t)
+  for (int r = 0; r < NR; ++r) {
+    const int c = lane + 64 * r;
+    y[r] = c < m ? b[(size_t)row * bsr + (size_t)c * bsc] : 0.f;
+  }
+  // entry k lives in slot k / 64 of lane k % 64: the sweeps run over the
+  // 64-entry blocks with the slot a compile-time index (a runtime slot index
+  // would put y in scratch memory)
+  auto scale = [&]() {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = lane + 64 * r;
-      y[t][r] = (c < m && row0 + t < q) ? b[(size_t)(row0 + t) * bsr + (size_t)c * bsc] : 0.f;
+    for (int r = 0; r < NR; ++r) {
+      const int i = lane + 64 * r;
+      if (i < m) y[r] *= rd[i];
     }
-  auto pick = [&](int t, int k) -> float {
-    const int r = k >> 6;
-    const float v = r == 0 ? y[t][0] : (r == 1 ? y[t][1] : (r == 2 ? y[t][2] : y[t][3]));
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k & 63));
   };
-  // The LDS operands of step k + 1 are loaded before step k's dependent
-  // arithmetic, so that their latency overlaps it; the rows of a wave share
-  // them.
-  // forward: L y = b; column k of L at col(k)[i], i >= k
-  auto colv = [&](int k, float (&v)[4], float& rk) {
+  // forward: L y = b; column k of L at col(k)[i], i >= k (zero for i <= k)
+  auto colv = [&](int k, float (&v)[NR], float& rk) {
     const float* col = Lp + k * m - k * (k - 1) / 2 - k;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NR; ++r) {
       const int i = lane + 64 * r;
       v[r] = (i > k && i < m) ? col[i] : 0.f;
     }
     rk = rd[k];
   };
-  float cv[4], rk;
+  float cv[NR], rk;
   colv(0, cv, rk);
-  for (int k = 0; k < m; ++k) {
-    float nv[4], nr = 0.f;
-    if (k + 1 < m) colv(k + 1, nv, nr);
 #pragma unroll
-    for (int t = 0; t < PDL_TR_ROWS; ++t) {
-      const float yk = pick(t, k) * rk;
+  for (int rb = 0; rb < NR; ++rb) {
+    const int kend = m < 64 * (rb + 1) ? m : 64 * (rb + 1);
+    for (int k = 64 * rb; k < kend; ++k) {
+      float nv[NR], nr = 0.f;
+      if (k + 1 < m) colv(k + 1, nv, nr);
+      const float yk =
+          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[rb]), k & 63)) * rk;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = lane + 64 * r;
-        y[t][r] = i == k ? yk : fmaf(-cv[r], yk, y[t][r]);
-      }
+      for (int r = 0; r < NR; ++r) y[r] = fmaf(-cv[r], yk, y[r]);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cv[r] = nv[r];
+      rk = nr;
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) cv[r] = nv[r];
-    rk = nr;
   }
+  scale();
   // backward: L^T x = y; row k of L (entries i < k) at Lp[i m - i (i - 1) / 2 + k - i]
-  auto rowv = [&](int k, float (&v)[4], float& rkk) {
+  auto rowv = [&](int k, float (&v)[NR], float& rkk) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NR; ++r) {
       const int i = lane + 64 * r;
       v[r] = i < k ? Lp[i * m - i * (i - 1) / 2 + (k - i)] : 0.f;
     }
     rkk = rd[k];
   };
   rowv(m - 1, cv, rk);
-  for (int k = m - 1; k >= 0; --k) {
-    float nv[4], nr = 0.f;
-    if (k > 0) rowv(k - 1, nv, nr);
 #pragma unroll
-    for (int t = 0; t < PDL_TR_ROWS; ++t) {
-      const float xk = pick(t, k) * rk;
+  for (int rb = NR - 1; rb >= 0; --rb) {
+    const int kbeg = m - 1 < 64 * rb + 63 ? m - 1 : 64 * rb + 63;
+    for (int k = kbeg; k >= 64 * rb; --k) {
+      float nv[NR], nr = 0.f;
+      if (k > 0) rowv(k - 1, nv, nr);
+      const float xk =
+          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[rb]), k & 63)) * rk;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = lane + 64 * r;
-        y[t][r] = i == k ? xk : fmaf(-cv[r], xk, y[t][r]);
-      }
+      for (int r = 0; r < NR; ++r) y[r] = fmaf(-cv[r], xk, y[r]);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cv[r] = nv[r];
+      rk = nr;
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) cv[r] = nv[r];
-    rk = nr;
   }
+  scale();
 #pragma unroll
-  for (int t = 0; t < PDL_TR_ROWS; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = lane + 64 * r;
-      if (c < m && row0 + t < q) {
-        if (xo) xo[(size_t)(row0 + t) * m + c] = y[t][r];
-        if (xbf) xbf[(size_t)(row0 + t) * m + c] = f2bf(y[t][r]);
-      }
+  for (int r = 0; r < NR; ++r) {
+    const int c = lane + 64 * r;
+    if (c < m) {
+      if (xo) xo[(size_t)row * m + c] = y[r];
+      if (xbf) xbf[(size_t)row * m + c] = f2bf(y[r]);
     }
+  }
 }
 
 // G = (D + E) / ||D + E||_F, E <- E + G - D, and G in BF16 (count = n A
