@@ -273,7 +273,9 @@ int cip_plan_attach(cip_plan_t base, void* d_state, size_t bytes, cip_plan_t* ou
  * cip_batch_destroy; every launch recomputes all solves from t = u = 0.
  * Each result equals that of a lone cip_solve on the same plan (the solves
  * share no memory). Creating a batch allocates host objects, streams and
- * events, never device memory. */
+ * events, never device memory. Plans that learn their dictionary
+ * (CIP_PLAN_DICT_UPDATE) run in direct batches only: with use_graph the call
+ * returns CIP_EUNSUPPORTED before any capture. */
 typedef struct cip_batch_s* cip_batch_t;
 int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
                      float* const* d_x, int n_streams, int use_graph, cip_batch_t* out);

@@ -1355,6 +1355,10 @@ int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, co
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) return fail(CIP_EINVAL, "a plan may appear once per batch");
   }
+  if (use_graph)
+    for (int i = 0; i < n; ++i)
+      if (plans[i]->learn)
+        return fail(CIP_EUNSUPPORTED, "dictionary-learning plans are not captured into a graph");
   cip_batch_s* b = new cip_batch_s();
   b->plans.assign(plans, plans + n);
   b->y.assign(d_y, d_y + n);

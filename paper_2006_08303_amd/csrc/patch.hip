@@ -59,17 +59,38 @@ hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int
 }
 
 // Rows of B M^-1 (k_pdl_trsolve, one row per wave) for order m <= 256.
+// The LDS limit of the four instances is raised once per process (not on
+// every launch, so that solves captured into a graph issue kernels only).
+static hipError_t trsolve_lds_limit() {
+  static hipError_t status = [] {
+    const int lds = pdl_trsolve_lds_floats(PDL_MAXM) * 4;
+    const void* k[4] = {reinterpret_cast<const void*>(k_pdl_trsolve<1>),
+                        reinterpret_cast<const void*>(k_pdl_trsolve<2>),
+                        reinterpret_cast<const void*>(k_pdl_trsolve<3>),
+                        reinterpret_cast<const void*>(k_pdl_trsolve<4>)};
+    for (const void* f : k) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }();
+  return status;
+}
+
 static hipError_t trsolve(const float* lt, int m, const float* b, int bsr, int bsc, int q, float* xo,
-                   uint16_t* xbf, hipStream_t st) {
-  const int grid = (q + 3) / 4;
+                          uint16_t* xbf, hipStream_t st) {
+  hipError_t e = trsolve_lds_limit();
+  if (e != hipSuccess) return e;
+  const dim3 grid((q + 3) / 4), block(256);
   const size_t lds = (size_t)pdl_trsolve_lds_floats(m) * 4;
   switch ((m + 63) / 64) {
-    case 1: return launch(k_pdl_trsolve<1>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
-    case 2: return launch(k_pdl_trsolve<2>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
-    case 3: return launch(k_pdl_trsolve<3>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
-    case 4: return launch(k_pdl_trsolve<4>, grid, 256, lds, st, lt, m, b, bsr, bsc, q, xo, xbf);
+    case 1: hipLaunchKernelGGL(k_pdl_trsolve<1>, grid, block, lds, st, lt, m, b, bsr, bsc, q, xo, xbf); break;
+    case 2: hipLaunchKernelGGL(k_pdl_trsolve<2>, grid, block, lds, st, lt, m, b, bsr, bsc, q, xo, xbf); break;
+    case 3: hipLaunchKernelGGL(k_pdl_trsolve<3>, grid, block, lds, st, lt, m, b, bsr, bsc, q, xo, xbf); break;
+    case 4: hipLaunchKernelGGL(k_pdl_trsolve<4>, grid, block, lds, st, lt, m, b, bsr, bsc, q, xo, xbf); break;
+    default: return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // One step of the dictionary ADMM and the new code tables (see patch_dl.hpp).

@@ -177,3 +177,45 @@ def test_patch_dictionary_solves_restart_from_the_plan_dictionary():
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert torch.equal(ga, gb)
+
+
+@pytest.mark.skip(reason="capturing a learning patch plan into a graph ended in a host "
+                  "segmentation fault inside batch creation, in a variant that rebuilt M1 on a "
+                  "side stream (since taken out); the cause was not found, and graph capture of "
+                  "dictionary-learning plans is refused (next test)")
+def test_patch_dictionary_learning_in_a_captured_batch():
+    """A captured and replayed batch of a learning plan (eager work between
+    the replays) equals the lone solve bit for bit."""
+    x, psf, y, D = _problem(64, 2, 2, 64)
+    plan = cip.Plan(_t(psf), "patch", RHO, LAM, BETA, dictionary=_t(D), dict_update=True,
+                    sigma=_sigma(64))
+    yt = _t(y)
+    ref = plan.solve(yt, 6).clone()
+    torch.cuda.synchronize()
+    xs = torch.full_like(ref, float("nan"))
+    b = cip.Batch([(plan, yt, 6, xs)], n_streams=1, graph=True)
+    for rep in range(3):
+        xs.fill_(float("nan"))
+        b.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(xs, ref), rep
+
+
+def test_dictionary_learning_plans_are_not_captured():
+    """Graph capture of dictionary-learning plans is refused before any
+    capture starts (CIP_EUNSUPPORTED); a direct batch still runs them and
+    equals the lone solve."""
+    x, psf, y, D = _problem(64, 2, 2, 64)
+    plan = cip.Plan(_t(psf), "patch", RHO, LAM, BETA, dictionary=_t(D), dict_update=True,
+                    sigma=_sigma(64))
+    yt = _t(y)
+    ref = plan.solve(yt, 6).clone()
+    torch.cuda.synchronize()
+    xs = torch.full_like(ref, float("nan"))
+    with pytest.raises(cip.CipError) as e:
+        cip.Batch([(plan, yt, 6, xs)], n_streams=1, graph=True)
+    assert e.value.code == -2
+    b = cip.Batch([(plan, yt, 6, xs)], n_streams=1, graph=False)
+    b.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(xs, ref)
