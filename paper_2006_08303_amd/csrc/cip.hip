@@ -187,7 +187,7 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       L.gtap = sta(taps * 4);
       L.gehat = sta(P * F * 8);
       L.dsp = sta(P * F * 8);
-      L.ecdl = sta(P * (size_t)N1 * N2 * 4);
+      L.ecdl = sta(P * F * 8);   // the dual as plane spectra
       L.dpl = sta(P * (size_t)N1 * N2 * 4);
     }
     L.eta = learn ? sta(F * 4) : tab(F * 4);
@@ -653,8 +653,9 @@ hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(p->at<void>(L.gtap), p->at<const void>(L.filt0),
                                 (size_t)P * Lf * Lf * 4, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;
-  if ((e = cdl_dual(p->at<float>(L.ecdl), p->at<float>(L.dpl), p->at<const float>(L.gtap), M, per,
-                    p->N1, p->N2, Lf, 1, st)) != hipSuccess)
+  if ((e = cdl_fzero(p->at<cx<float>>(L.ecdl), (size_t)P * F, st)) != hipSuccess) return e;
+  if ((e = cdl_place(p->at<const float>(L.gtap), p->at<float>(L.dpl), M, per, p->N1, p->N2, Lf,
+                     st)) != hipSuccess)
     return e;
   if ((e = row_r2c<float>(p->at<const float>(L.dpl), p->at<cx<float>>(L.rtc), P, p->N1, p->N2,
                           p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
@@ -670,10 +671,12 @@ hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
 
 // One step of the dictionary ADMM after the code update of an outer
 // iteration (gv holds the new codes' plane spectra, xhat those of x):
-// d (3D: Sherman-Morrison per 3D frequency; 2D: Woodbury with an S x S
-// Cholesky per frequency) -> space; g = projection of d + e; e += g - d and
-// the spectra of g - e; filter tables from g; d^ = D(g) z for the next
-// x-update.
+// d^ (3D: Sherman-Morrison per 3D frequency; 2D: Woodbury with an S x S
+// Cholesky per frequency), returned as d^ + e^ (the dual is kept as plane
+// spectra); d + e to space; g = projection of d + e; the spectra g^ of
+// the placed g; e^ += g^ - d^ and the spectra of g - e; filter tables from
+// g^; d^ = D(g) z for the next x-update. Two batched 2D FFTs of the filter
+// planes per step.
 hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
   const Layout& L = p->L;
   const bool d3 = p->kind == CIP_PRIOR_CONV3D;
@@ -683,39 +686,34 @@ hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
   const cx<float>* bw = d3 ? p->at<const cx<float>>(L.bw) : nullptr;
   cx<float>* rtc = p->at<cx<float>>(L.rtc);
   cx<float>* dsp = p->at<cx<float>>(L.dsp);
+  cx<float>* gehat = p->at<cx<float>>(L.gehat);
+  cx<float>* ehat = p->at<cx<float>>(L.ecdl);
   float* dpl = p->at<float>(L.dpl);
+  // dsp <- d^ + e^
   hipError_t e = d3 ? cdl_dfreq(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
-                                p->at<const cx<float>>(L.gehat), dsp, bw, M, S, F, (float)p->sigma,
-                                st)
+                                gehat, ehat, dsp, bw, M, S, F, (float)p->sigma, st)
                     : cdl_dfreq2(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
-                                 p->at<const cx<float>>(L.gehat), dsp, M, S, F, (float)p->sigma,
-                                 st);
+                                 gehat, ehat, dsp, M, S, F, (float)p->sigma, st);
   if (e != hipSuccess) return e;
+  // d + e in space
   if ((e = conv_col_fft(-1, dsp, rtc, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
   if ((e = row_c2r(rtc, dpl, P, N1, N2, (float)(1.0 / ((double)N1 * N2)),
                    p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
     return e;
-  if ((e = cdl_project(dpl, p->at<const float>(L.ecdl), p->at<float>(L.gtap), M, per, N1, N2, Lf,
-                       st)) != hipSuccess)
+  if ((e = cdl_project(dpl, nullptr, p->at<float>(L.gtap), M, per, N1, N2, Lf, st)) != hipSuccess)
     return e;
-  if ((e = cdl_dual(p->at<float>(L.ecdl), dpl, p->at<const float>(L.gtap), M, per, N1, N2, Lf, 0,
-                    st)) != hipSuccess)
-    return e;
-  if ((e = row_r2c<float>(dpl, rtc, P, N1, N2, p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
-    return e;
-  if ((e = conv_col_fft(1, rtc, p->at<cx<float>>(L.gehat), P, N1, H2,
-                        p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
-    return e;
+  // g^ of the placed taps, into gehat
   if ((e = cdl_place(p->at<const float>(L.gtap), dpl, M, per, N1, N2, Lf, st)) != hipSuccess)
     return e;
   if ((e = row_r2c<float>(dpl, rtc, P, N1, N2, p->at<const cx<float>>(L.twN2f), st)) != hipSuccess)
     return e;
-  // 3D: plane spectra to dsp, then the band DFT into the tables; 2D: the
-  // spectra are the tables
-  cx<float>* gspec = d3 ? dsp : p->at<cx<float>>(L.th32);
-  if ((e = conv_col_fft(1, rtc, gspec, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
+  if ((e = conv_col_fft(1, rtc, gehat, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
+  // 3D: g^ to dsp (d^ + e^ is read first), then the band DFT into the
+  // tables; 2D: g^ are the tables
+  cx<float>* gspec = d3 ? dsp : p->at<cx<float>>(L.th32);
+  if ((e = cdl_fdual(ehat, gehat, dsp, gspec, (size_t)P * F, st)) != hipSuccess) return e;
   if ((e = cdl_tables(p, gspec, st)) != hipSuccess) return e;
   if (d3)
     return conv_dhat3(p->at<const cx<float>>(L.gv), p->at<const cx<float>>(L.th32),

@@ -93,23 +93,25 @@ hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<
   }
 
 hipError_t cdl_dfreq(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
-                     cx<float>* dsp, const cx<float>* bw, int M, int S, size_t F, float sigma,
-                     hipStream_t st) {
+                     const cx<float>* ehat, cx<float>* dsp, const cx<float>* bw, int M, int S,
+                     size_t F, float sigma, hipStream_t st) {
   const int grid = (int)((F + 127) / 128);
-#define CIP_DF(SS)                                                                              \
-  case SS:                                                                                      \
-    return launch(k_cdl_dfreq<SS>, grid, 128, 0, st, xhat, zh, gehat, dsp, bw, M, F, sigma);
+#define CIP_DF(SS)                                                                           \
+  case SS:                                                                                   \
+    return launch(k_cdl_dfreq<SS>, grid, 128, 0, st, xhat, zh, gehat, ehat, dsp, bw, M, F, \
+                  sigma);
   CIP_S_SWITCH(CIP_DF)
 #undef CIP_DF
   return hipErrorInvalidValue;
 }
 
 hipError_t cdl_dfreq2(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
-                      cx<float>* dsp, int M, int S, size_t F, float sigma, hipStream_t st) {
+                      const cx<float>* ehat, cx<float>* dsp, int M, int S, size_t F, float sigma,
+                      hipStream_t st) {
   const int grid = (int)((F + 127) / 128);
-#define CIP_DF2(SS)                                                                          \
-  case SS:                                                                                   \
-    return launch(k_cdl_dfreq2<SS>, grid, 128, 0, st, xhat, zh, gehat, dsp, M, F, sigma);
+#define CIP_DF2(SS)                                                                             \
+  case SS:                                                                                      \
+    return launch(k_cdl_dfreq2<SS>, grid, 128, 0, st, xhat, zh, gehat, ehat, dsp, M, F, sigma);
   CIP_S_SWITCH(CIP_DF2)
 #undef CIP_DF2
   return hipErrorInvalidValue;
@@ -131,17 +133,20 @@ hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int
   return launch(k_cdl_project, M, 256, 0, st, dpl, e, gtap, S, N1, N2, L);
 }
 
-hipError_t cdl_dual(float* e, float* dge, const float* gtap, int M, int S, int N1, int N2, int L,
-                    int init, hipStream_t st) {
-  const size_t n = (size_t)M * S * N1 * N2;
-  return launch(k_cdl_dual, (int)((n + 255) / 256), 256, 0, st, e, dge, gtap, S, N1, N2, L, n,
-                init);
+hipError_t cdl_fdual(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs, size_t n,
+                     hipStream_t st) {
+  return launch(k_cdl_fdual, (int)((n + 255) / 256), 256, 0, st, e, ge, sd, gs, n);
+}
+
+hipError_t cdl_fzero(cx<float>* e, size_t n, hipStream_t st) {
+  return launch(k_cdl_fzero, (int)((n + 255) / 256), 256, 0, st, e, n);
 }
 
 hipError_t cdl_place(const float* gtap, float* out, int M, int S, int N1, int N2, int L,
                      hipStream_t st) {
-  const size_t n = (size_t)M * S * N1 * N2;
-  return launch(k_cdl_place, (int)((n + 255) / 256), 256, 0, st, gtap, out, N1, N2, L, n);
+  hipLaunchKernelGGL(k_cdl_place, dim3((N2 + 255) / 256, N1, M * S), dim3(256), 0, st, gtap, out,
+                     N1, N2, L);
+  return hipGetLastError();
 }
 
 hipError_t conv_tables3f(const cx<float>* th2, cx<float>* th32, float* gam, const cx<float>* bw,

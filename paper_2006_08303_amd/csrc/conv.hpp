@@ -309,12 +309,14 @@ k_conv_freq3(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat, cx<float>
 // is (sigma I + a a^H) d = a X + sigma GE with a = conj(Z) (rank one plus
 // sigma I); Sherman-Morrison in the form without 1/sigma (as for the codes),
 //   r = (X - sum_m Z_m GE_m) / (sigma + sum_m |Z_m|^2),   d_m = GE_m + conj(Z_m) r,
-// returned as plane spectra (inverse band DFT) in dsp [M][S][F].
+// returned as plane spectra (inverse band DFT) plus the dual's, d^ + e^, in
+// dsp [M][S][F] (what the projection needs; d^ itself is not kept).
 template <int S>
 __global__ void __launch_bounds__(128)
 k_cdl_dfreq(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh,
-            const cx<float>* __restrict__ gehat, cx<float>* __restrict__ dsp,
-            const cx<float>* __restrict__ bw, int M, size_t F, float sigma) {
+            const cx<float>* __restrict__ gehat, const cx<float>* __restrict__ ehat,
+            cx<float>* __restrict__ dsp, const cx<float>* __restrict__ bw, int M, size_t F,
+            float sigma) {
   const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   cx<float> xs[S], X[S], ag[S];
@@ -377,7 +379,8 @@ k_cdl_dfreq(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh
       cx<float> acc = {0.f, 0.f};
 #pragma unroll
       for (int k = 0; k < S; ++k) acc = acc + cmulc(D[k], bw[k * S + s]);
-      dsp[((size_t)m * S + s) * F + f] = cx<float>{acc.x * invS, acc.y * invS};
+      const size_t o = ((size_t)m * S + s) * F + f;
+      dsp[o] = cx<float>{acc.x * invS, acc.y * invS} + ehat[o];
     }
   }
 }
@@ -388,12 +391,13 @@ k_cdl_dfreq(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh
 // Section IV-B). Solved through the Woodbury identity in the form without
 // 1/sigma,  d = GE + A y,  (sigma I_S + A^H A) y = X - A^H GE,
 // with an S x S complex Cholesky factorisation per frequency.
-// zh [M][S][F] (codes), xhat [S][F], gehat and dsp [M][F].
+// zh [M][S][F] (codes), xhat [S][F], gehat, ehat and dsp [M][F]; dsp
+// receives d^ + e^.
 template <int S>
 __global__ void __launch_bounds__(128)
 k_cdl_dfreq2(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh,
-             const cx<float>* __restrict__ gehat, cx<float>* __restrict__ dsp, int M, size_t F,
-             float sigma) {
+             const cx<float>* __restrict__ gehat, const cx<float>* __restrict__ ehat,
+             cx<float>* __restrict__ dsp, int M, size_t F, float sigma) {
   const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   cx<float> B[S][S], w[S];
@@ -451,7 +455,7 @@ k_cdl_dfreq2(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ z
     cx<float> d = gehat[(size_t)m * F + f];
 #pragma unroll
     for (int s = 0; s < S; ++s) d = d + cmul(conjx(zh[((size_t)m * S + s) * F + f]), w[s]);
-    dsp[(size_t)m * F + f] = d;
+    dsp[(size_t)m * F + f] = d + ehat[(size_t)m * F + f];
   }
 }
 
@@ -499,7 +503,8 @@ __device__ __forceinline__ bool cdl_tap(int n1, int n2, int N1, int N2, int L, i
 }
 
 // g-update: per filter m (one work-group each), w = d + e on the support,
-// gtap = w / ||w||. dpl, e: [M][S][N1][N2].
+// gtap = w / ||w||. dpl, e: [M][S][N1][N2]; e may be null (dpl then holds
+// d + e).
 __global__ void __launch_bounds__(256)
 k_cdl_project(const float* __restrict__ dpl, const float* __restrict__ e, float* __restrict__ gtap,
               int S, int N1, int N2, int L) {
@@ -512,7 +517,7 @@ k_cdl_project(const float* __restrict__ dpl, const float* __restrict__ e, float*
     const int sp = i / (L * L), a = (i / L) % L, b = i % L;
     const int n1 = (a - L / 2 + N1) % N1, n2 = (b - L / 2 + N2) % N2;
     const size_t o = ((size_t)m * S + sp) * plane + (size_t)n1 * N2 + n2;
-    const float w = dpl[o] + e[o];
+    const float w = dpl[o] + (e ? e[o] : 0.f);
     acc += w * w;
   }
   red[threadIdx.x] = acc;
@@ -526,42 +531,43 @@ k_cdl_project(const float* __restrict__ dpl, const float* __restrict__ e, float*
     const int sp = i / (L * L), a = (i / L) % L, b = i % L;
     const int n1 = (a - L / 2 + N1) % N1, n2 = (b - L / 2 + N2) % N2;
     const size_t o = ((size_t)m * S + sp) * plane + (size_t)n1 * N2 + n2;
-    gtap[(size_t)m * taps + i] = (dpl[o] + e[o]) * inv;
+    gtap[(size_t)m * taps + i] = (dpl[o] + (e ? e[o] : 0.f)) * inv;
   }
 }
 
-// Dual update and the next right-hand side, elementwise over [M][S][N1][N2]:
-//   e <- e + g - d,   dge <- g - e  (dge holds d on entry).
-// With init set: e <- 0 and dge <- g (start of a solve, g from gtap).
-__global__ void k_cdl_dual(float* __restrict__ e, float* __restrict__ dge,
-                           const float* __restrict__ gtap, int S, int N1, int N2, int L,
-                           size_t n, int init) {
+// The dual e is kept as plane spectra (the transforms are linear): with
+// s = d^ + e^ (from the d-update) and g^ the spectra of the placed g,
+// elementwise over [P][F]:
+//   e^ <- e^ + g^ - d^ = g^ + 2 e^ - s,  ge <- g^ - e^ (the next right-hand
+//   side),  gs <- g^.
+// ge holds g^ on entry; gs may alias sd (s is read first).
+__global__ void k_cdl_fdual(cx<float>* __restrict__ e, cx<float>* ge, const cx<float>* sd,
+                            cx<float>* gs, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const size_t plane = (size_t)N1 * N2;
-  const size_t p = i / plane, r = i % plane;
-  const int n1 = (int)(r / N2), n2 = (int)(r % N2);
-  int a, b;
-  const float g = cdl_tap(n1, n2, N1, N2, L, a, b) ? gtap[(p * L + a) * L + b] : 0.f;
-  if (init) {
-    e[i] = 0.f;
-    dge[i] = g;
-    return;
-  }
-  const float en = e[i] + g - dge[i];
+  const cx<float> g = ge[i], sv = sd[i], eo = e[i];
+  const cx<float> en = g + eo + eo - sv;
   e[i] = en;
-  dge[i] = g - en;
+  ge[i] = g - en;
+  gs[i] = g;
 }
 
-// Grid placement of the taps gtap [M][S][L][L] -> planes [M][S][N1][N2].
-__global__ void k_cdl_place(const float* __restrict__ gtap, float* __restrict__ out, int N1, int N2,
-                            int L, size_t n) {
+// e^ = 0 (start of a solve)
+__global__ void k_cdl_fzero(cx<float>* __restrict__ e, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const size_t plane = (size_t)N1 * N2;
-  const size_t p = i / plane, r = i % plane;
+  if (i < n) e[i] = cx<float>{0.f, 0.f};
+}
+
+// Grid placement of the taps gtap [M][S][L][L] -> planes [M][S][N1][N2]:
+// thread (n2, n1, plane) of a 3D grid (no index division).
+__global__ void k_cdl_place(const float* __restrict__ gtap, float* __restrict__ out, int N1, int N2,
+                            int L) {
+  const int n2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n2 >= N2) return;
+  const int n1 = blockIdx.y;
+  const size_t p = blockIdx.z;
   int a, b;
-  out[i] = cdl_tap((int)(r / N2), (int)(r % N2), N1, N2, L, a, b) ? gtap[(p * L + a) * L + b] : 0.f;
+  out[(p * N1 + n1) * N2 + n2] = cdl_tap(n1, n2, N1, N2, L, a, b) ? gtap[(p * L + a) * L + b] : 0.f;
 }
 
 // Filter tables from the plane spectra th2 [M][S][F] of the placed taps

@@ -23,19 +23,24 @@ hipError_t conv_freq3(cx<float>* gv, cx<float>* dhat, cx<float>* xhat, const cx<
                       const float* gam, const cx<float>* bw, int M, int S, size_t F, int first,
                       int zero_g, int do_z, hipStream_t st);
 // 3D dictionary update (see conv.hpp)
+// d-updates (3D and 2D forms); dsp receives d^ + e^
 hipError_t cdl_dfreq(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
-                     cx<float>* dsp, const cx<float>* bw, int M, int S, size_t F, float sigma,
-                     hipStream_t st);
+                     const cx<float>* ehat, cx<float>* dsp, const cx<float>* bw, int M, int S,
+                     size_t F, float sigma, hipStream_t st);
 hipError_t cdl_dfreq2(const cx<float>* xhat, const cx<float>* zh, const cx<float>* gehat,
-                      cx<float>* dsp, int M, int S, size_t F, float sigma, hipStream_t st);
+                      const cx<float>* ehat, cx<float>* dsp, int M, int S, size_t F, float sigma,
+                      hipStream_t st);
 hipError_t conv_tables2f(const cx<float>* th, float* gam, float* eta, int M, size_t F, double rho,
                          double mu, int N1, int N2, hipStream_t st);
 hipError_t conv_dhat2(const cx<float>* zh, const cx<float>* th, cx<float>* dhat, int M, int S,
                       size_t F, hipStream_t st);
 hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int S, int N1, int N2,
                        int L, hipStream_t st);
-hipError_t cdl_dual(float* e, float* dge, const float* gtap, int M, int S, int N1, int N2, int L,
-                    int init, hipStream_t st);
+// frequency-domain dual (see conv.hpp): from s = d^ + e^ and g^,
+// e^ += g^ - d^, ge = g^ - e^, gs = g^
+hipError_t cdl_fdual(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs, size_t n,
+                     hipStream_t st);
+hipError_t cdl_fzero(cx<float>* e, size_t n, hipStream_t st);
 hipError_t cdl_place(const float* gtap, float* out, int M, int S, int N1, int N2, int L,
                      hipStream_t st);
 hipError_t conv_tables3f(const cx<float>* th2, cx<float>* th32, float* gam, const cx<float>* bw,
