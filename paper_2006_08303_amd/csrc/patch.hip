@@ -37,8 +37,9 @@ hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, co
 
 hipError_t patch_assemble_launch(int S, const float* tb, float* r, int N1, int N2, hipStream_t st) {
   const PatchGeo G = patch_geo(N1, N2);
-  const size_t n = (size_t)S * N1 * N2;
-  return launch(k_patch_assemble, (int)((n + 255) / 256), 256, 0, st, tb, r, S, G);
+  hipLaunchKernelGGL(k_patch_assemble, dim3((N2 + 255) / 256, N1, S), dim3(256), 0, st, tb, r, S,
+                     G);
+  return hipGetLastError();
 }
 
 size_t patch_tile_buffer_floats(int S, int N1, int N2) {

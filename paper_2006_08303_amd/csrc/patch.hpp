@@ -262,14 +262,13 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
 // r = P^T D~ z: every pixel sums the tiles whose regions cover it (its own
 // tile and, within Q - st pixels of a tile edge, the previous tile along that
 // axis, circularly), in a fixed order.
+// Thread (C, R, s) of a 3D grid (no index division).
 __global__ void k_patch_assemble(const float* __restrict__ tb, float* __restrict__ r, int S,
                                  PatchGeo G) {
-  const size_t n = (size_t)S * G.N1 * G.N2;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int C = (int)(idx % G.N2);
-  const int R = (int)((idx / G.N2) % G.N1);
-  const int s = (int)(idx / ((size_t)G.N2 * G.N1));
+  const int C = blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= G.N2) return;
+  const int R = blockIdx.y, s = blockIdx.z;
+  const size_t idx = ((size_t)s * G.N1 + R) * G.N2 + C;
   const int TH = PATCH_ST * G.TPR, TW = PATCH_ST * G.TPC;
   const int ntr = G.J1 / G.TPR;
   const int RA = G.RR * G.RC;
