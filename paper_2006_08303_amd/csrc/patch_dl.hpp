@@ -126,12 +126,12 @@ __global__ void k_pdl_reduce(const float* __restrict__ part, const float* __rest
 // for i >= k (row k of lt is column k of L); orders above m are padded with
 // the identity. One work-group of 640 threads: each of its 10 waves holds one
 // 64 x 64 block on or below the diagonal of the padded matrix, each lane an
-// 8 x 8 tile (lane / 8, lane % 8) of it, in registers. Step j eliminates
-// column j (Gaussian elimination on the symmetric matrix,
-// P[i][k] -= P[i][j] P[k][j] / P[j][j] for i, k > j): the owners of column j
-// publish it in LDS with its entries i <= j set to zero, and the pivot apart,
-// so that every tile applies the same unmasked rank-1 update; the buffers
-// alternate between steps, so one barrier per step suffices. At the end
+// 8 x 8 tile (lane / 8, lane % 8) of it, in registers. Gaussian elimination
+// on the symmetric matrix (P[i][k] -= P[i][j] P[k][j] / P[j][j] for
+// i, k > j), two columns per step: the owners publish them in LDS with their
+// eliminated entries set to zero, and the pivots apart, so that every tile
+// applies the same unmasked rank-2 update; the buffers alternate between
+// steps, so one barrier per two columns suffices. At the end
 // L[i][k] = P[i][k] / sqrt(P[k][k]).
 // The block of wave w is chosen so that, with waves placed on the four SIMDs
 // round-robin, the blocks still active at step j (those with block column
@@ -141,8 +141,8 @@ constexpr int PDL_CHOL_THREADS = 640;
 
 __global__ void __launch_bounds__(PDL_CHOL_THREADS)
 k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) {
-  __shared__ __align__(16) float colb[2][PDL_MAXM];
-  __shared__ float pivb[2];
+  __shared__ __align__(16) float colb[2][2][PDL_MAXM];
+  __shared__ float pivb[2][2];
   __shared__ float piv[PDL_MAXM];
   constexpr int kBi[10] = {3, 2, 3, 3, 1, 2, 2, 3, 0, 1};
   constexpr int kBk[10] = {3, 2, 2, 1, 1, 1, 0, 0, 0, 0};
@@ -159,34 +159,65 @@ k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) 
       if (i < m && k < m) v = i >= k ? a[(size_t)i * lda + k] : a[(size_t)k * lda + i];
       P[r][c] = v;
     }
-  // orders above m are the identity: their elimination steps change nothing
-  for (int j = 0; j < m; ++j) {
-    float* cb = colb[j & 1];
+  // Columns j and j + 1 per barrier (a rank-2 update; both lie in one tile
+  // column). The owners publish both raw columns, entries i <= j (column j)
+  // and i <= j + 1 (column j + 1) set to zero, and both diagonal entries;
+  // every thread then forms column j + 1 after column j's elimination for
+  // its own rows and columns, b = c1 - c0 c0[j + 1] / p0 (zero for
+  // i <= j + 1), p1 = P[j+1][j+1] - c0[j+1]^2 / p0, and applies
+  // P -= c0 c0^T / p0 + b b^T / p1. Orders above m are the identity.
+  for (int j = 0; j < m; j += 2) {
+    const int par = (j >> 1) & 1;
+    float* cb0 = colb[par][0];
+    float* cb1 = colb[par][1];
     if (tk == (j >> 3)) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
+      for (int c = 0; c < 8; c += 2)
         if (c == (j & 7)) {
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
             const int i = 8 * ti + r;
-            cb[i] = i > j ? P[r][c] : 0.f;
-            if (i == j) pivb[j & 1] = P[r][c];
+            cb0[i] = i > j ? P[r][c] : 0.f;
+            cb1[i] = i > j + 1 ? P[r][c + 1] : 0.f;
+            if (i == j) pivb[par][0] = P[r][c];
+            if (i == j + 1) pivb[par][1] = P[r][c + 1];
           }
         }
     }
     __syncthreads();
     if (8 * ti + 7 > j && 8 * tk + 7 > j) {
-      const float inv = 1.f / pivb[j & 1];
-      const float4* cq = reinterpret_cast<const float4*>(cb);
-      const float4 r0 = cq[2 * ti], r1 = cq[2 * ti + 1];
-      const float4 c0 = cq[2 * tk], c1 = cq[2 * tk + 1];
-      const float cr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-      const float cc[8] = {c0.x * inv, c0.y * inv, c0.z * inv, c0.w * inv,
-                           c1.x * inv, c1.y * inv, c1.z * inv, c1.w * inv};
+      const float p0 = pivb[par][0], q = cb0[j + 1];
+      const float inv0 = 1.f / p0, qi = q * inv0;
+      const float inv1 = 1.f / (pivb[par][1] - q * qi);
+      const float4* c0q = reinterpret_cast<const float4*>(cb0);
+      const float4* c1q = reinterpret_cast<const float4*>(cb1);
+      float ar[8], br[8], ac[8], bc[8];
+      {
+        const float4 x0 = c0q[2 * ti], x1 = c0q[2 * ti + 1];
+        const float4 y0 = c1q[2 * ti], y1 = c1q[2 * ti + 1];
+        const float xa[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const float ya[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          ar[r] = xa[r];
+          br[r] = 8 * ti + r > j + 1 ? fmaf(-xa[r], qi, ya[r]) : 0.f;
+        }
+      }
+      {
+        const float4 x0 = c0q[2 * tk], x1 = c0q[2 * tk + 1];
+        const float4 y0 = c1q[2 * tk], y1 = c1q[2 * tk + 1];
+        const float xa[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const float ya[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          ac[c] = xa[c] * inv0;
+          bc[c] = 8 * tk + c > j + 1 ? fmaf(-xa[c], qi, ya[c]) * inv1 : 0.f;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) P[r][c] = fmaf(-cr[r], cc[c], P[r][c]);
+        for (int c = 0; c < 8; ++c) P[r][c] = fmaf(-br[r], bc[c], fmaf(-ar[r], ac[c], P[r][c]));
     }
   }
   if (ti == tk) {
