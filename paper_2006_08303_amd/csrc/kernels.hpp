@@ -395,14 +395,21 @@ __global__ void k_col_op(const cx<Re>* __restrict__ in, void* __restrict__ outv,
 #pragma unroll
     for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
     __syncthreads();
-    // per-frequency map; each thread owns whole frequencies
+    // per-frequency map; each thread owns whole frequencies (the plane loops
+    // run to the static maximum of 8 with guards, so that xin stays in
+    // registers)
     for (int k1 = threadIdx.x; k1 < N1; k1 += blockDim.x) {
       cx<Re> xin[8];
-      for (int j = 0; j < Pin; ++j) xin[j] = ldc(reinterpret_cast<const cx<Re>*>(lds) + j * PL, k1);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        xin[j] = j < Pin ? ldc(reinterpret_cast<const cx<Re>*>(lds) + j * PL, k1)
+                         : cx<Re>{Re(0), Re(0)};
       const size_t f = (size_t)k2 * N1 + k1;
       for (int o = 0; o < Pout; ++o) {
         cx<Re> acc = {Re(0), Re(0)};
-        for (int j = 0; j < Pin; ++j) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (j >= Pin) break;
           cx<Re> m;
           if (OP == OP_ADJ) m = conjx(mat[(size_t)(j * Pout + o) * F + f]);
           else m = mat[(size_t)(o * Pin + j) * F + f];
