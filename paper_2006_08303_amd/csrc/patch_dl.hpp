@@ -7,9 +7,10 @@
 // with X = [P_1 x | ... | P_J x] (n x J, n = 64 S) and Z (A x J). The next x-
 // and code updates use G: its BF16 copy and M1 = G^T (rho I + G G^T)^-1.
 //
-// Arithmetic is FP32 throughout:
-//   k_pdl_gemm     the products X Z^T and Z Z^T on FP32 MFMA
-//                  (v_mfma_f32_32x32x2f32), split over the patches, every
+// Arithmetic is FP32 except where noted:
+//   k_pdl_gemm     the products X Z^T and Z Z^T on BF16 MFMA with split
+//                  operands (hi + lo, three products, FP32 accumulation:
+//                  about 16 significant bits), split over the patches, every
 //                  split written to its own slice (no atomics);
 //   k_pdl_reduce   fixed-order sum of the slices, + sigma (G - E) and sigma I;
 //   k_pdl_chol     Cholesky factor of an SPD matrix of order m <= 256 in one
@@ -40,8 +41,11 @@ constexpr int PDL_KSTEP = 32;    // patches per LDS stage of k_pdl_gemm
 __global__ void __launch_bounds__(256)
 k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __restrict__ part,
            PatchGeo G, int S, int NA, int chunk) {
-  __shared__ float As[64][PDL_KSTEP + 1];
-  __shared__ float Bs[64][PDL_KSTEP + 1];
+  // operands split as x = hi + lo, both BF16 (x - hi is exact in FP32, lo
+  // keeps its leading 8 bits): products hi*hi + hi*lo + lo*hi on BF16 MFMA
+  // with FP32 accumulation carry about 16 significant bits
+  constexpr int LS = PDL_KSTEP + 8;   // LDS row stride (bf16), rows 16-byte aligned
+  __shared__ __align__(16) uint16_t Ah[64][LS], Al[64][LS], Bh[64][LS], Bl[64][LS];
   const int rb = blockIdx.x, cb = blockIdx.y, ks = blockIdx.z;
   if (rb >= S && cb > rb - S) return;
   const int rows = 64 * S + NA;
@@ -83,17 +87,35 @@ k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __r
   load(jbeg, av, bv);
   for (size_t j0 = jbeg; j0 < jend; j0 += PDL_KSTEP) {
     __syncthreads();   // the previous stage has been consumed
+    {
+      uint16_t ah[8], al[8], bh[8], bl[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[lr][lk + q] = av[q];
-      Bs[lr][lk + q] = bv[q];
+      for (int q = 0; q < 8; ++q) {
+        ah[q] = f2bf(av[q]);
+        al[q] = f2bf(av[q] - __uint_as_float((uint32_t)ah[q] << 16));
+        bh[q] = f2bf(bv[q]);
+        bl[q] = f2bf(bv[q] - __uint_as_float((uint32_t)bh[q] << 16));
+      }
+      auto pack = [](const uint16_t (&h)[8]) {
+        return uint4{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                     h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16)};
+      };
+      *reinterpret_cast<uint4*>(&Ah[lr][lk]) = pack(ah);
+      *reinterpret_cast<uint4*>(&Al[lr][lk]) = pack(al);
+      *reinterpret_cast<uint4*>(&Bh[lr][lk]) = pack(bh);
+      *reinterpret_cast<uint4*>(&Bl[lr][lk]) = pack(bl);
     }
     __syncthreads();
     if (j0 + PDL_KSTEP < jend) load(j0 + PDL_KSTEP, av, bv);
 #pragma unroll
-    for (int kk = 0; kk < PDL_KSTEP / 2; ++kk)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[32 * wr + l32][2 * kk + lhi],
-                                                 Bs[32 * wc + l32][2 * kk + lhi], acc, 0, 0, 0);
+    for (int kk = 0; kk < PDL_KSTEP / 16; ++kk) {
+      const int ko = 16 * kk + 8 * lhi;
+      const bf16x8 a_h = ld_bf16x8(&Ah[32 * wr + l32][ko]), a_l = ld_bf16x8(&Al[32 * wr + l32][ko]);
+      const bf16x8 b_h = ld_bf16x8(&Bh[32 * wc + l32][ko]), b_l = ld_bf16x8(&Bl[32 * wc + l32][ko]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc, 0, 0, 0);
+    }
   }
   float* out = part + ((size_t)ks * rows + 64 * rb + 32 * wr) * NA + 64 * cb + 32 * wc + l32;
 #pragma unroll

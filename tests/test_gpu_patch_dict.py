@@ -1,7 +1,8 @@
 """GPU parity of the online patch-dictionary update (Section IV-B: Eqs.
 ADMM0 / sold_patch, ADMM1, subh) against the FP64 oracle. The code update
 runs on BF16 MFMA as in the fixed-dictionary path; the dictionary step uses
-FP32 MFMA products, FP32 Cholesky factors and FP32 triangular solves. x must
+split-BF16 MFMA products (FP32 accumulation), FP32 Cholesky factors and FP32
+triangular solves. x must
 meet the BF16 path's 2e-3 relative l2, and so must the learned dictionary G
 in relative Frobenius norm; the dictionary step alone, on the same BF16
 codes, must match FP64 to 1e-4 (FP32 arithmetic of a well-conditioned
@@ -124,7 +125,9 @@ def test_patch_dictionary_first_step_on_bf16_codes(N, K, S, A):
     two iterations the GPU takes one D, G, E step on z^1 = M1 e (w = 0,
     e = P x^1), whose operands M1 and e are BF16. The same step in FP64 on
     codes formed from BF16-rounded M1 and e (x^1 from the FP64 oracle) must
-    give the GPU's G to within the FP32 arithmetic of the step (1e-4)."""
+    give the GPU's G to within the step's own arithmetic (FP32 factorizations
+    and solves, products of split BF16 operands with about 16 significant
+    bits: 1e-4)."""
     sigma = _sigma(N)
     x, psf, y, D = _problem(N, K, S, A)
     alg = admm.PatchADMM(psf, D, 8, 4, LAM, RHO, BETA, tier="freq", dict_update=True,
