@@ -208,7 +208,9 @@ int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* st
  *   D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1, G = (D + E) / ||D + E||_F
  *   (the constraint ||D||_F = 1 of Eq. patch_based_dic), E <- E + G - D;
  *   the code update's tables (G and M1 = G^T (rho I + G G^T)^-1, BF16) are
- *   rebuilt from G on the GPU (FP32 products and Cholesky factors).
+ *   rebuilt from G on the GPU (X Z^T and Z Z^T from split BF16 operands with
+ *   FP32 accumulation, about 16 significant bits; FP32 Cholesky factors and
+ *   triangular solves).
  * This call copies g of the last solve (the layout of the plan's dictionary:
  * [n][A], [M][L][L] or [M][S][L][L] float32) to the device buffer d_filters,
  * asynchronously on `stream`. CIP_EINVAL if the plan does not learn its
