@@ -16,8 +16,8 @@
 //   k_pdl_chol     Cholesky factor of an SPD matrix of order m <= 256 in one
 //                  work-group: the lower half of the matrix (padded with the
 //                  identity to 256 x 256) lives in registers, 8 x 8 per
-//                  thread, and the pivot column is broadcast through LDS
-//                  (one barrier per column);
+//                  thread, and the pivot columns are broadcast through LDS
+//                  (one barrier per two columns);
 //   k_pdl_trsolve  rows of B M^-1 = B L^-T L^-1, one row per wave, L packed
 //                  in LDS;
 //   k_pdl_project  the Frobenius projection and the dual update (one

@@ -2,11 +2,10 @@
 ADMM0 / sold_patch, ADMM1, subh) against the FP64 oracle. The code update
 runs on BF16 MFMA as in the fixed-dictionary path; the dictionary step uses
 split-BF16 MFMA products (FP32 accumulation), FP32 Cholesky factors and FP32
-triangular solves. x must
-meet the BF16 path's 2e-3 relative l2, and so must the learned dictionary G
-in relative Frobenius norm; the dictionary step alone, on the same BF16
-codes, must match FP64 to 1e-4 (FP32 arithmetic of a well-conditioned
-step)."""
+triangular solves. x must meet the BF16 path's 2e-3 relative l2, and so
+must the learned dictionary G in relative Frobenius norm; the dictionary
+step alone, on the same BF16 codes, must match FP64 to 1e-4 (the step's own
+arithmetic on a well-conditioned system)."""
 import numpy as np
 import pytest
 import torch
@@ -62,7 +61,7 @@ def test_patch_dictionary_learning_matches_oracle(N, K, S, A, iters, gtol):
     """x meets the BF16 bar (2e-3); the learned G (after the iters - 1
     dictionary steps the solve takes: the oracle's G of the next-to-last
     iteration) agrees within gtol, the BF16 code error carried through the
-    dictionary steps (the D-step on identical codes agrees to ~5e-7, next
+    dictionary steps (the D-step on identical codes agrees to 3-7e-7, next
     test)."""
     sigma = _sigma(N)
     print(f"patch dictionary learning N={N} K={K} S={S} A={A} iters={iters} sigma={sigma}",
