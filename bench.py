@@ -412,7 +412,7 @@ def main():
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--bands", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=70)
     ap.add_argument("--iters-other", type=int, default=20,
                     help="iterations per solve for the other priors (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
