@@ -127,6 +127,23 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
+      // the patch samples of the epilogue are loaded first (latency overlaps the products)
+      float xp[2][2][16];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const int jl = 32 * n + l32;
+          const int pr0 = (tr * G.TPR + jl / G.TPC) * PATCH_ST;
+          const int pc0 = (tc * G.TPC + jl % G.TPC) * PATCH_ST;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
+            const int s = row >> 6, a = (row >> 3) & 7, b = row & 7;
+            const int pr = (pr0 + a) & (G.N1 - 1), pc = (pc0 + b) & (G.N2 - 1);
+            xp[m][n][i] = x[((size_t)s * G.N1 + pr) * G.N2 + pc];
+          }
+        }
       const uint16_t* Da = Dg + (size_t)(64 * wave + l32) * NA + 8 * lhi;
 #pragma unroll 4
       for (int ks = 0; ks < NA / 16; ++ks) {
@@ -144,15 +161,10 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
 #pragma unroll
         for (int n = 0; n < 2; ++n) {
           const int jl = 32 * n + l32;
-          const int pr0 = (tr * G.TPR + jl / G.TPC) * PATCH_ST;
-          const int pc0 = (tc * G.TPC + jl % G.TPC) * PATCH_ST;
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-            const int s = row >> 6, a = (row >> 3) & 7, b = row & 7;
-            const int pr = (pr0 + a) & (G.N1 - 1), pc = (pc0 + b) & (G.N2 - 1);
-            const float p = x[((size_t)s * G.N1 + pr) * G.N2 + pc];
-            EB[jl * ES + row] = f2bf(p - acc[m][n][i]);
+            EB[jl * ES + row] = f2bf(xp[m][n][i] - acc[m][n][i]);
           }
         }
     }
@@ -165,6 +177,19 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
+      // the state of the epilogue is loaded first (latency overlaps the products)
+      float vs[2][2][16];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const size_t jg = jglob(32 * n + l32);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int atom = 64 * wb + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
+            vs[m][n][i] = first ? 0.f : v[(size_t)atom * J + jg];
+          }
+        }
       const uint16_t* Ma = M1g + (size_t)(64 * wb + l32) * NV + 8 * lhi;
 #pragma unroll 4
       for (int ks = 0; ks < NV / 16; ++ks) {
@@ -186,10 +211,9 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int atom = 64 * wb + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-            float* vp = v + (size_t)atom * J + jg;
-            const float vv = first ? 0.f : *vp;
+            const float vv = vs[m][n][i];
             const float z = (2.f * soft_f(vv, kappa) - vv) + acc[m][n][i];
-            *vp = z + clip_f(vv, kappa);
+            v[(size_t)atom * J + jg] = z + clip_f(vv, kappa);
             WB[jl * WS + atom] = f2bf(z);
             if constexpr (MODE == PZ_CODES) zf[(size_t)atom * J + jg] = z;
           }
