@@ -183,14 +183,6 @@ class AnalysisADMM:
 
 
 # ================================================================ synthesis: patches
-def patch_objective(x, z, y, psf, patches, D, lam, beta):
-    """beta/2 ||y - Hx||^2 + 1/2 sum_j ||D z_j - P_j x||^2 + lambda ||z||_1
-    (Eq. rls with Eq. patch_based)."""
-    r = y - model.forward(x, psf)
-    q = D @ z - patches.extract(x)
-    return 0.5 * beta * np.sum(r * r) + 0.5 * np.sum(q * q) + lam * np.sum(np.abs(z))
-
-
 class PatchADMM:
     """Algorithm 2 with the patch-based dictionary prior.
 
@@ -288,13 +280,6 @@ class PatchADMM:
 
 
 # ================================================================ synthesis: conv dictionary
-def conv_objective(x, z, y, psf, cd, lam, beta):
-    """beta/2 ||y - Hx||^2 + 1/2 ||D~ z - x||^2 + lambda ||z||_1."""
-    r = y - model.forward(x, psf)
-    q = cd.synth(z) - x
-    return 0.5 * beta * np.sum(r * r) + 0.5 * np.sum(q * q) + lam * np.sum(np.abs(z))
-
-
 def sherman_morrison(theta, c, rho):
     """Eq. solz_DFT_SM at every frequency: solve (rho I + a a^H) v = c for the
     M-vector v, where a = conj(theta) collects the filter spectra at that

@@ -31,6 +31,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 from __future__ import annotations
 
 import numpy as np
+from scipy.linalg import solve_triangular
 
 from .model import dense_H
 
@@ -171,8 +172,9 @@ class DenseSolver:
         r = rhs_spatial.ravel()
         if self.PN is not None:
             r = r - self.PN @ r
-        z = np.linalg.solve(self.L, r)
-        x = np.linalg.solve(self.L.T, z)
+        # L L^T x = r by forward then backward substitution
+        z = solve_triangular(self.L, r, lower=True)
+        x = solve_triangular(self.L.T, z, lower=False)
         if self.PN is not None:
             x = x - self.PN @ x
         return x.reshape(self.S, self.N1, self.N2)

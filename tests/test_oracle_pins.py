@@ -1046,3 +1046,67 @@ def test_itv_admm_with_identity_blur_is_the_tv_prox():
     # isotropic and anisotropic TV give different answers here
     xa = admm.AnalysisADMM(psf, "tv2d", lam, rho, beta, tier="freq").run(y, 600)[0]
     assert np.linalg.norm(xa - x) > 1e-3 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------- pins added for the larger tiers
+@pytest.mark.slow
+@pytest.mark.parametrize("N,kind,iters", [(32, "tv2d", 20), (32, "dct2d", 20), (32, "tv3d", 10),
+                                          (64, "tv2d", 10)])
+def test_dense_and_freq_tiers_agree_at_32_and_64(N, kind, iters):
+    """Tier D (assembled normal matrix of Eq. solx_Trans, Cholesky, null-space
+    projector for the singular DC block) and tier F (per-frequency solve of
+    Eq. solx_Trans_DFT) run the same iteration at 32^2 and 64^2 (K = S = 2,
+    S N1 N2 up to 8192 unknowns)."""
+    x0, psf = _small_problem(K=2, S=2, N1=N, N2=N, seed=31)
+    y = model.forward(x0, psf) + 0.01 * _rng(32).standard_normal((2, N, N))
+    lam, rho = (1e-2, 0.1) if kind == "dct2d" else (1e-3, 1e-2)
+    a = admm.AnalysisADMM(psf, kind, lam, rho, 1.0, tier="dense").run(y, iters)[0]
+    b = admm.AnalysisADMM(psf, kind, lam, rho, 1.0, tier="freq").run(y, iters)[0]
+    assert admm.rel_l2(b, a) < 1e-10
+    assert np.max(np.abs(b - a)) < 1e-9 * np.max(np.abs(a))
+
+
+def test_symmlet8_is_the_least_asymmetric_daubechies_factor():
+    """The 16-tap filters with 8 vanishing moments are h = sqrt(2) (1 + z^-1)^8
+    Q(z) / (norm), with |Q(e^iw)|^2 = P(sin^2(w/2)), P(y) = sum_{k<8}
+    C(7+k, k) y^k (Daubechies' construction). Every real spectral factor Q
+    picks one zero from each reciprocal pair of P's zeros mapped to z
+    (3 complex-conjugate pairs and one real zero: 16 factors). The table
+    SYM8 must be the factor whose phase is closest to linear (the
+    least-asymmetric choice; measured on Q, the other factor has exactly
+    linear phase), and, of that factor and its mirror image (same phase
+    nonlinearity), the one whose largest tap is h[7]."""
+    import itertools
+    c = [math.comb(7 + k, k) for k in range(8)]
+    yr = np.roots(c[::-1])
+    groups, used = [], set()
+    for i, yv in enumerate(yr):
+        if i in used:
+            continue
+        b = 2.0 - 4.0 * yv                       # z + 1/z = 2 - 4 y
+        z = (b + np.sqrt(b * b - 4.0 + 0j)) / 2.0
+        if abs(yv.imag) < 1e-12:
+            groups.append([complex(z)])
+            used.add(i)
+        else:
+            j = [k for k in range(len(yr))
+                 if k not in used and k != i and abs(yr[k] - np.conj(yv)) < 1e-8][0]
+            used.update([i, j])
+            groups.append([z, np.conj(z)])
+    assert sorted(len(g) for g in groups) == [1, 2, 2, 2]
+    w = np.linspace(0.0, math.pi, 1025)
+    A = np.vstack([w, np.ones_like(w)]).T
+    found = []
+    for choice in itertools.product([0, 1], repeat=len(groups)):
+        zs = [(z if ch == 0 else 1.0 / z) for g, ch in zip(groups, choice) for z in g]
+        q = np.real(np.poly(zs))
+        ph = np.unwrap(np.angle(np.exp(-1j * np.outer(w, np.arange(len(q)))) @ q))
+        dev = float(np.max(np.abs(ph - A @ np.linalg.lstsq(A, ph, rcond=None)[0])))
+        h = np.convolve(q, [math.comb(8, k) for k in range(9)])
+        found.append((dev, h / h.sum() * math.sqrt(2.0)))
+    found.sort(key=lambda t: t[0])
+    best = [h for d, h in found if d < found[0][0] + 1e-9]
+    assert len(best) == 2                         # the factor and its mirror image
+    assert found[2][0] > found[0][0] + 0.03       # a clear margin to the next pair
+    assert any(np.max(np.abs(h - priors.SYM8)) < 1e-10 for h in best)
+    assert int(np.argmax(priors.SYM8)) == 7
