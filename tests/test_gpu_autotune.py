@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests import parity
 from oracle import admm, model
 from paper_2006_08303_amd import cip, synth
 
@@ -51,7 +52,7 @@ def test_every_shape_matches_oracle(prior, N, shapes):
         plan.set_tuning(np_, ppt)
         err = admm.rel_l2(_np(plan.solve(_t(y), 12)), ref)
         print(f"{prior} N={N} shape np={np_} ppt={ppt}: rel_l2 {err:.3e}", flush=True)
-        assert err < 1e-4
+        parity.check(_np(plan.solve(_t(y), 12)), ref, 1e-4)
 
 
 @pytest.mark.parametrize("prior,N,S", [("dct2d", 1024, 3), ("tv2d", 1024, 3), ("tv3d", 512, 5),

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests import parity
 from oracle import admm, model
 from paper_2006_08303_amd import cip, synth
 
@@ -40,7 +41,7 @@ def test_dct3d_solve_matches_oracle(N, K, S, iters):
     err = admm.rel_l2(got, ref)
     print(f"  rel_l2 = {err:.3e}  psnr gpu {admm.psnr(got, x):.2f} dB oracle "
           f"{admm.psnr(ref, x):.2f} dB", flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 def test_dct3d_single_plane_equals_dct2d():
@@ -48,7 +49,7 @@ def test_dct3d_single_plane_equals_dct2d():
     x, psf, y = _problem(128, 3, 1)
     a = _np(cip.Plan(_t(psf), "dct3d", 0.1, 1e-2, 1.0).solve(_t(y), 10))
     b = _np(cip.Plan(_t(psf), "dct2d", 0.1, 1e-2, 1.0).solve(_t(y), 10))
-    assert admm.rel_l2(a, b) < 1e-6
+    parity.check(a, b, 1e-6)
 
 
 def test_dct3d_adaptive_matches_oracle():
@@ -59,4 +60,4 @@ def test_dct3d_adaptive_matches_oracle():
     got, ginfo = plan.solve_adaptive(_t(y), 200, every=5, tol=1e-3)
     print(f"oracle {rinfo['iters']} {rinfo['rho']}; gpu {ginfo['iters']} {ginfo['rho']}", flush=True)
     assert ginfo["iters"] == rinfo["iters"] and ginfo["rho"] == pytest.approx(rinfo["rho"])
-    assert admm.rel_l2(_np(got), ref) < 1e-4
+    parity.check(_np(got), ref, 1e-4)

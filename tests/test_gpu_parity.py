@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests import parity
 from oracle import admm, model
 from paper_2006_08303_amd import cip, synth
 
@@ -43,8 +44,8 @@ def test_forward_adjoint_match_oracle(K, S, N1, N2):
     plan = cip.Plan(_t(psf), "dct2d", 0.1, 0.01, 1.0)
     yg = _np(plan.forward(_t(x)))
     xg = _np(plan.adjoint(_t(y)))
-    assert admm.rel_l2(yg, model.forward(x, psf)) < 1e-5
-    assert admm.rel_l2(xg, model.adjoint(y, psf)) < 1e-5
+    parity.check(yg, model.forward(x, psf), 1e-5)
+    parity.check(xg, model.adjoint(y, psf), 1e-5)
 
 
 def test_adjoint_identity_gpu():
@@ -81,7 +82,7 @@ def test_dct_solve_matches_oracle(N, K, S, iters):
     got = _np(plan.solve(_t(y), iters))
     err = admm.rel_l2(got, ref)
     print(f"  rel_l2 = {err:.3e}  psnr(gpu, truth) = {admm.psnr(got, x):.2f} dB", flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 def test_dct_solve_config2_256():
@@ -96,7 +97,7 @@ def test_dct_solve_config2_256():
     err = admm.rel_l2(got, ref)
     print(f"config-2 DCT: rel_l2 = {err:.3e}, psnr gpu {admm.psnr(got, x):.2f} dB, "
           f"oracle {admm.psnr(ref, x):.2f} dB", flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 def test_solve_is_repeatable_and_plan_reusable():
@@ -116,15 +117,15 @@ def test_full_size_1024_operators_and_solve():
     x, psf, noise = synth.problem("smooth_disk", N, K, S, seed_config=3)
     plan = cip.Plan(_t(psf), "dct2d", 0.1, 1e-2, 1.0)
     hx = model.forward(x, psf)
-    assert admm.rel_l2(_np(plan.forward(_t(x))), hx) < 1e-5
+    parity.check(_np(plan.forward(_t(x))), hx, 1e-5)
     y = (hx + model.snr_noise_scale(hx, 30.0)[:, None, None] * noise)
     y = y.astype(np.float32).astype(np.float64)
-    assert admm.rel_l2(_np(plan.adjoint(_t(y))), model.adjoint(y, psf)) < 1e-5
+    parity.check(_np(plan.adjoint(_t(y))), model.adjoint(y, psf), 1e-5)
     ref = admm.AnalysisADMM(psf, "dct2d", 1e-2, 0.1, 1.0, tier="freq").run(y, 3)[0]
     got = _np(plan.solve(_t(y), 3))
     err = admm.rel_l2(got, ref)
     print(f"1024^2 DCT 3 iters: rel_l2 = {err:.3e}", flush=True)
-    assert err < 1e-5
+    parity.check(got, ref, 1e-5)
 
 
 @pytest.mark.parametrize("N,K,S,iters,kind", [(64, 2, 2, 50, "rects_gauss"), (64, 3, 3, 1, "smooth_disk"),
@@ -143,7 +144,7 @@ def test_tv2d_solve_matches_oracle(N, K, S, iters, kind):
     err = admm.rel_l2(got, ref)
     print(f"  rel_l2 = {err:.3e}  psnr gpu {admm.psnr(got, x):.2f} dB oracle {admm.psnr(ref, x):.2f}",
           flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 @pytest.mark.parametrize("prior", ["dct2d", "tv2d"])
@@ -161,10 +162,10 @@ def test_rectangular_grid(prior):
         ref = admm.AnalysisADMM(psf, prior, lam, rho, 1.0, tier="freq").run(y, 12)[0]
         plan = cip.Plan(_t(psf), prior, rho, lam, 1.0)
         got = _np(plan.solve(_t(y), 12))
-        assert admm.rel_l2(got, ref) < 1e-4, (N1, N2)
+        parity.check(got, ref, 1e-4, label=str((N1, N2)))
         plan.set_tuning(2, 16)   # half-tile row pass
         got = _np(plan.solve(_t(y), 12))
-        assert admm.rel_l2(got, ref) < 1e-4, (N1, N2, "np=2")
+        parity.check(got, ref, 1e-4, label=str((N1, N2, "np=2")))
 
 
 def test_tv2d_full_size_1024():
@@ -179,4 +180,4 @@ def test_tv2d_full_size_1024():
     got = _np(plan.solve(_t(y), 3))
     err = admm.rel_l2(got, ref)
     print(f"1024^2 TV2D 3 iters: rel_l2 = {err:.3e}", flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests import parity
 from oracle import admm, model
 from paper_2006_08303_amd import cip, synth
 
@@ -83,8 +84,8 @@ def test_patch_dictionary_learning_matches_oracle(N, K, S, A, iters, gtol):
           f"{np.linalg.norm(g):.6f})", flush=True)
     assert moved > 1e-3                 # the dictionary does change
     assert abs(np.linalg.norm(g) - 1.0) < 1e-5
-    assert ex < 2e-3
-    assert eg < gtol
+    parity.check(got, ref, 2e-3, label="x")
+    parity.check(g, g_ref, gtol, label="G")
 
 
 def test_patch_dictionary_learning_full_size_1024():
@@ -106,8 +107,8 @@ def test_patch_dictionary_learning_full_size_1024():
     ex = admm.rel_l2(got, ref)
     eg = np.linalg.norm(g - gs[iters - 2]) / np.linalg.norm(gs[iters - 2])
     print(f"  x rel_l2 {ex:.3e}  G rel {eg:.3e}", flush=True)
-    assert ex < 2e-3
-    assert eg < 2e-3
+    parity.check(got, ref, 2e-3, label="x")
+    parity.check(g, gs[iters - 2], 2e-3, label="G")
 
 
 def _bf16(a):
@@ -144,7 +145,7 @@ def test_patch_dictionary_first_step_on_bf16_codes(N, K, S, A):
     eg = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     moved = np.linalg.norm(g_ref - D)
     print(f"first step N={N} S={S} A={A}: G rel {eg:.3e} (step {moved:.3e})", flush=True)
-    assert eg < 1e-4
+    parity.check(g, g_ref, 1e-4, label="G")
 
 
 def test_patch_dictionary_huge_sigma_is_the_fixed_dictionary_run():
@@ -160,7 +161,7 @@ def test_patch_dictionary_huge_sigma_is_the_fixed_dictionary_run():
     err = admm.rel_l2(b, a)
     dg = np.abs(_np(learn.dictionary()) - D).max()
     print(f"huge sigma: rel_l2 vs fixed {err:.3e}, max |G - D| {dg:.3e}", flush=True)
-    assert err < 2e-3
+    parity.check(b, a, 2e-3)
     assert dg < 1e-6
 
 

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests import parity
 from oracle import admm, model
 from paper_2006_08303_amd import cip, synth
 
@@ -33,8 +34,8 @@ def test_forward_adjoint_radix3(K, S, N1, N2):
     x = rng.uniform(0, 1, (S, N1, N2)).astype(np.float32).astype(np.float64)
     y = rng.standard_normal((K, N1, N2)).astype(np.float32).astype(np.float64)
     plan = cip.Plan(_t(psf), "dct2d", 0.1, 0.01, 1.0)
-    assert admm.rel_l2(_np(plan.forward(_t(x))), model.forward(x, psf)) < 1e-5
-    assert admm.rel_l2(_np(plan.adjoint(_t(y))), model.adjoint(y, psf)) < 1e-5
+    parity.check(_np(plan.forward(_t(x))), model.forward(x, psf), 1e-5)
+    parity.check(_np(plan.adjoint(_t(y))), model.adjoint(y, psf), 1e-5)
 
 
 def _problem(kind, N, K, S, cfg):
@@ -58,7 +59,7 @@ def test_solve_radix3(prior, N, K, S, iters):
     got = _np(cip.Plan(_t(psf), prior, rho, lam, 1.0).solve(_t(y), iters))
     err = admm.rel_l2(got, ref)
     print(f"  rel_l2 = {err:.3e}", flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 def test_rectangular_radix3_tv():
@@ -72,7 +73,7 @@ def test_rectangular_radix3_tv():
     y = y.astype(np.float32).astype(np.float64)
     ref = admm.AnalysisADMM(psf, "tv2d", 1e-3, 1e-2, 1.0, tier="freq").run(y, 10)[0]
     got = _np(cip.Plan(_t(psf), "tv2d", 1e-2, 1e-3, 1.0).solve(_t(y), 10))
-    assert admm.rel_l2(got, ref) < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 def test_conv_radix3():
@@ -85,7 +86,7 @@ def test_conv_radix3():
     got = _np(cip.Plan(_t(psf), "conv2d", rho, lam, beta, filters=_t(filt)).solve(_t(y), 4))
     err = admm.rel_l2(got, ref)
     print(f"  rel_l2 = {err:.3e}", flush=True)
-    assert err < 1e-4
+    parity.check(got, ref, 1e-4)
 
 
 def test_patch_rejects_radix3():

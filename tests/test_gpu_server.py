@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests import parity
 from oracle import admm, model
 from paper_2006_08303_amd import cip, synth
 
@@ -116,7 +117,7 @@ def test_server_result_matches_oracle():
                             tier="freq").run(y.astype(np.float64), 10)[0]
     err = admm.rel_l2(x.astype(np.float64), ref)
     print(f"  rel_l2 = {err:.3e}", flush=True)
-    assert err < 1e-4
+    parity.check(x.astype(np.float64), ref, 1e-4)
 
 
 def test_server_admission_by_footprint():
