@@ -350,6 +350,29 @@ int cip_plan_autotune(cip_plan_t plan, int reps, void* stream, cip_tuning* out);
  * row_np 4 or 2; row_ppt the default or 8). */
 int cip_plan_set_tuning(cip_plan_t plan, int row_np, int row_ppt);
 
+/* ---- reconstruction without device allocation ----------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the result of
+ * cip_plan_create + cip_solve + cip_plan_destroy, with the plan's workspace
+ * (tables and solve state) in a static buffer of CIP_STATIC_WORKSPACE_BYTES
+ * that the library holds on every GPU it runs on until the process ends,
+ * instead of caller memory. Arguments as for cip_plan_create (d_psf) and
+ * cip_solve (d_y, iters, d_x); nothing is allocated on the device and the
+ * caller passes only inputs and outputs. Limit: problems whose
+ * cip_plan_workspace_bytes exceeds CIP_STATIC_WORKSPACE_BYTES (64 MiB: for
+ * example the analysis priors up to 512 x 512 with K = S = 3) return
+ * CIP_ENOSPC before any GPU work. Every call on a GPU reuses that GPU's
+ * buffer, which keeps the last call's contents; each call rebuilds all it
+ * reads, so no part of it has to start at zero. Two calls overlapping on one
+ * GPU would race on the buffer: the library serialises the calls of a
+ * process, and each returns only after its work on `stream` has finished
+ * (so, unlike cip_solve, this call is synchronous). Errors as for
+ * cip_plan_create and cip_solve. */
+#define CIP_STATIC_WORKSPACE_BYTES (64u << 20)
+int cip_solve_static(int K, int S, int N1, int N2, const float* d_psf,
+                     const cip_prior_desc* prior, double rho, double lambda, const float* d_y,
+                     int iters, float* d_x, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* cip_last_error(void);
 

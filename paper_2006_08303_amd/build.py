@@ -4,7 +4,8 @@ Translation units: csrc/cip.hip (C ABI, plan, operators, row passes),
 csrc/patch.hip (patch-dictionary MFMA kernels and their dictionary
 learning), csrc/conv.hip (convolutional-dictionary kernels),
 csrc/wavelet.hip (wavelet (x) DCT prior), csrc/server.hip (request server
-on the plan API) and one csrc/col_pass.hip
+on the plan API), csrc/static_solve.hip (reconstruction in a static device
+buffer) and one csrc/col_pass.hip
 instance per supported column length. They are compiled in
 parallel and linked into paper_2006_08303_amd/libcip.so.
 """
@@ -35,7 +36,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
             (os.path.join(CSRC, "patch.hip"), os.path.join(tmpdir, "patch.o"), []),
             (os.path.join(CSRC, "conv.hip"), os.path.join(tmpdir, "conv.o"), []),
             (os.path.join(CSRC, "server.hip"), os.path.join(tmpdir, "server.o"), []),
-            (os.path.join(CSRC, "wavelet.hip"), os.path.join(tmpdir, "wavelet.o"), [])]
+            (os.path.join(CSRC, "wavelet.hip"), os.path.join(tmpdir, "wavelet.o"), []),
+            (os.path.join(CSRC, "static_solve.hip"), os.path.join(tmpdir, "static_solve.o"), [])]
     for n in SIZES:
         jobs.append((os.path.join(CSRC, "col_pass.hip"), os.path.join(tmpdir, f"col_{n}.o"),
                      [f"-DCIP_COL_N={n}"]))

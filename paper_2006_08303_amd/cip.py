@@ -132,13 +132,15 @@ def lib():
                                          ctypes.POINTER(_SolveInfo)]
         L.cip_plan_autotune.argtypes = [vp, i, vp, ctypes.POINTER(_Tuning)]
         L.cip_plan_set_tuning.argtypes = [vp, i, i]
+        L.cip_solve_static.argtypes = [i, i, i, i, vp, ctypes.POINTER(_PriorDesc), d, d, vp, i, vp,
+                                       vp]
         for name in ("cip_plan_workspace_bytes", "cip_plan_create", "cip_forward", "cip_adjoint",
                      "cip_solve", "cip_plan_destroy", "cip_time_kernel", "cip_batch_create",
                      "cip_batch_launch", "cip_batch_destroy", "cip_plan_state_bytes",
                      "cip_plan_attach", "cip_server_create", "cip_server_add_operator",
                      "cip_server_submit", "cip_server_poll", "cip_server_wait",
                      "cip_server_destroy", "cip_solve_adaptive", "cip_plan_autotune",
-                     "cip_plan_set_tuning"):
+                     "cip_plan_set_tuning", "cip_solve_static"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -285,6 +287,24 @@ class Plan:
         if h is not None and _lib is not None:
             _lib.cip_plan_destroy(h)
             self._h = None
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20   # CIP_STATIC_WORKSPACE_BYTES
+
+
+def solve_static(psf, y, iters, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dictionary=None,
+                 filters=None, mu=0.0, tv_inner=0, wt_levels=0, out=None, stream=None):
+    """cip_solve_static: a whole reconstruction (plan tables and solve state)
+    in the library's static device buffer; no device memory is allocated by
+    the library (out is allocated here unless given). Synchronous."""
+    K, S, N1, N2 = (int(v) for v in psf.shape)
+    desc = _desc(prior, beta, dictionary, filters, mu, 0, tv_inner, 0.0, wt_levels)
+    x = out if out is not None else torch.empty((S, N1, N2), dtype=torch.float32, device=y.device)
+    _check(lib().cip_solve_static(K, S, N1, N2, _dev_f32(psf, (K, S, N1, N2), "psf"),
+                                  ctypes.byref(desc), float(rho), float(lam),
+                                  _dev_f32(y, (K, N1, N2), "y"), int(iters),
+                                  _dev_f32(x, (S, N1, N2), "x"), _stream_ptr(stream)))
+    return x
 
 
 class Batch:

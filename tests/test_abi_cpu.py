@@ -158,3 +158,19 @@ def test_wavelet_prior_validation(L):
     with pytest.raises(cip.CipError) as e:
         cip.workspace_bytes(K, S, 64, 64, "wdct3d", wt_levels=-1)
     assert e.value.code == -1
+
+
+def test_solve_static_refuses_problems_beyond_its_buffer(L):
+    """cip_solve_static checks the workspace a problem needs against its
+    static buffer before touching the GPU (1024^2 x 3 needs about 178 MiB)."""
+    from paper_2006_08303_amd import cip
+    desc = cip._PriorDesc(cip.CIP_PRIOR_DCT2D, 1.0)
+    dummy = ctypes.c_void_p(256)     # never dereferenced: the call fails first
+    rc = L.cip_solve_static(3, 3, 1024, 1024, dummy, ctypes.byref(desc), 0.1, 0.01, dummy, 10,
+                            dummy, None)
+    assert rc == -3
+    assert b"static buffer" in L.cip_last_error()
+    assert cip.workspace_bytes(3, 3, 512, 512, "dct2d") <= cip.STATIC_WORKSPACE_BYTES
+    rc = L.cip_solve_static(3, 3, 64, 64, dummy, ctypes.byref(desc), 0.1, 0.01, dummy, 0,
+                            dummy, None)
+    assert rc == -1
