@@ -86,21 +86,27 @@ def make_workload(N, K, S, dev, snr_db=30.0, seed_config=3):
     return x, psf, noise, psf_t, x_t, noise_t
 
 
-def cpu_baseline(psf, y, lam, rho, beta, n_iter):
-    """FP64 oracle (frequency tier) on the same problem, bounded sample."""
-    from oracle import admm
+def cpu_baseline(x, psf, noise, lam, rho, beta, n_iter):
+    """FP64 oracle (frequency tier) on a bounded sample of the same workload.
+
+    The oracle forms its own measurements from the generated scene, kernels
+    and noise (y = H x + w in space, 30 dB, rounded to float32 so that the GPU
+    can be given exactly the same y), runs n_iter iterations of Algorithm 1
+    and returns (record, x after n_iter iterations, y)."""
+    from oracle import admm, model, priors
     try:
         from threadpoolctl import threadpool_info
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
+    y = model.measure(x, psf, noise, 30.0).astype(np.float32).astype(np.float64)
     alg = admm.AnalysisADMM(psf, "dct2d", lam, rho, beta, tier="freq")
     data = alg.solver.data_term(y)
     T = alg.T
     t_ = np.zeros(T.shape)
     u_ = np.zeros(T.shape)
     kappa = lam / rho
-    from oracle import priors
+    xx = None
     t0 = time.perf_counter()
     for _ in range(n_iter):
         xx = alg.x_update(data, t_, u_)
@@ -110,11 +116,45 @@ def cpu_baseline(psf, y, lam, rho, beta, n_iter):
         t_ = tn
     dt = time.perf_counter() - t0
     N1, N2 = psf.shape[-2:]
-    return {"value": N1 * N2 * n_iter / dt / 1e6, "unit": "Mpixel*ADMM-iter/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"{n_iter} ADMM iterations (x-update, prox, dual) of the same "
-                      f"{N1}x{N2} K=S={psf.shape[1]} DCT-l1 problem in FP64 NumPy, "
-                      f"per-solve setup excluded; {dt:.1f} s"}
+    rec = {"value": N1 * N2 * n_iter / dt / 1e6, "unit": "Mpixel*ADMM-iter/s", "cores": int(cores),
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{n_iter} ADMM iterations (x-update, prox, dual) of the same "
+                     f"{N1}x{N2} K=S={psf.shape[1]} DCT-l1 problem in FP64 NumPy on {cores} "
+                     f"threads, per-solve setup excluded; {dt:.1f} s"}
+    return rec, xx, y
+
+
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo) and logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count()}
+
+
+def parity_vs_oracle(plan, x_ref, y_ref, x_true, n_iter, dev):
+    """GPU solve of the oracle's own measurements for the same iteration
+    count: relative l2, max |x_gpu - x_ref| and PSNR of the difference
+    (peak max |x_ref|), plus both reconstructions' PSNR against the scene."""
+    yt = torch.tensor(y_ref, dtype=torch.float32, device=dev)
+    got = plan.solve(yt, n_iter)
+    torch.cuda.synchronize()
+    g = got.cpu().double().numpy()
+    d = g - x_ref
+    mse = float(np.mean(d * d))
+    peak = float(np.abs(x_ref).max())
+    return {"iters": n_iter, "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(x_ref)),
+            "max_abs": float(np.abs(d).max()), "max_abs_over_peak": float(np.abs(d).max()) / peak,
+            "psnr_diff_db": round(10 * np.log10(peak * peak / mse), 2) if mse > 0 else None,
+            "psnr_vs_scene_gpu_db": round(10 * np.log10(1.0 / float(np.mean((g - x_true) ** 2))), 3),
+            "psnr_vs_scene_oracle_db":
+                round(10 * np.log10(1.0 / float(np.mean((x_ref - x_true) ** 2))), 3)}
 
 
 PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0), "itv2d": (1e-3, 1e-2, 1.0)}
@@ -455,6 +495,17 @@ def main():
             "other_kernel": {"name": names[1 - dom], "avg_us": round(times[1 - dom], 3),
                              "algorithmic_bytes_per_launch":
                                  algorithmic_bytes(1 - dom, S, N, N, "dct2d")}}
+    # the whole iteration: both passes' bytes, and the compulsory minimum (state
+    # read and write, packed Psi^+ and x_hat0 read once), over the measured
+    # time per iteration of the timed solves
+    it_us = ms_step * 1e3 / args.iters
+    F = N * (N // 2 + 1)
+    two_pass = algorithmic_bytes(0, S, N, N, "dct2d") + algorithmic_bytes(1, S, N, N, "dct2d")
+    minimum = (2 * S * N * N + S * S * F + 2 * S * F) * 4
+    roof["iteration"] = {"us": round(it_us, 3), "bytes_two_passes": two_pass,
+                         "frac_two_passes": round(two_pass / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                         "bytes_minimum": minimum,
+                         "frac_minimum": round(minimum / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     tv = None
     if not args.no_tv:
         _, _, _, _, _, tv_value, tv_ms, tv_times, tv_names, tv_tuning = run_prior(
@@ -497,9 +548,11 @@ def main():
                    "throughput_speedup": round(srv4["Mvoxel_iter_per_s"] /
                                                max(seq["Mvoxel_iter_per_s"], 1e-9), 3)}
     cpu = None
+    parity = None
     if not args.no_cpu:
-        y = y_t.double().cpu().numpy()
-        cpu = cpu_baseline(psf, y, lam, rho, beta, args.cpu_iters)
+        cpu, x_ref, y_ref = cpu_baseline(x, psf, noise, lam, rho, beta, args.cpu_iters)
+        parity = parity_vs_oracle(plan, x_ref, y_ref, x, args.cpu_iters, dev)
+        print(f"[bench] parity vs oracle: {parity}", file=sys.stderr, flush=True)
     rec = {
         "metric": "Mpixel*ADMM-iter/s (3x3 bands, 1024^2)",
         "value": round(value, 1),
@@ -520,6 +573,7 @@ def main():
                    "row_shape": tuning},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "parity": parity,
         "tv2d": tv,
         "itv2d": itv,
         "concurrent_1024": conc,
