@@ -176,11 +176,23 @@ __device__ __forceinline__ void static_for_k(cx<R> (&sub)[F][MM], cx<R>* v) {
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
 
-// Synchronise the threads of one transform group. (A wave-level barrier is
-// not used: with one group per wavefront and several wavefronts per
-// work-group it produced wrong results on gfx950, so groups always use the
-// work-group barrier.)
-template <int T> __device__ __forceinline__ void group_sync() { __syncthreads(); }
+// Synchronise the threads of one transform group. WS (wave-scope sync) may be
+// set by kernels whose groups never share LDS with another group between
+// their own explicit work-group barriers; a group of at most 64 threads then
+// lies inside one wavefront (T divides 64), whose LDS operations are
+// performed in order, so ordering its LDS accesses needs only a wavefront-
+// scope release fence, the wave barrier and an acquire fence (the fences
+// keep the compiler from moving LDS accesses across the barrier, which the
+// bare wave barrier does not). Otherwise the work-group barrier is used.
+template <int T, bool WS = false> __device__ __forceinline__ void group_sync() {
+  if constexpr (WS && T <= 64 && 64 % T == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // ---------------------------------------------------------------- group FFT
 // Stockham radix sequence: PPT (first stage, from registers), then radices
@@ -233,7 +245,8 @@ template <int N, int PPT> struct fft_shape {
 
 // One Stockham stage with radix RS on the group's LDS array buf, after
 // radices with product NS have been applied.
-template <int N, int PPT, int RS, int NS, int TWOFF, int DIR, bool LASTSTAGE, typename R>
+template <int N, int PPT, int RS, int NS, int TWOFF, int DIR, bool LASTSTAGE, typename R,
+          bool WS = false>
 __device__ __forceinline__ void stage_lds(cx<R>* buf, int t, const cx<R>* tws, cx<R>* v) {
   constexpr int T = N / PPT;
   constexpr int NB = PPT / RS;   // butterflies per thread
@@ -269,7 +282,7 @@ __device__ __forceinline__ void stage_lds(cx<R>* buf, int t, const cx<R>* tws, c
     }
     dft<RS, DIR, R>(&v[b * RS]);
   }
-  group_sync<T>();
+  group_sync<T, WS>();
   if constexpr (!LASTSTAGE) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -291,17 +304,18 @@ __device__ __forceinline__ void stage_lds(cx<R>* buf, int t, const cx<R>* tws, c
         }
       }
     }
-    group_sync<T>();
+    group_sync<T, WS>();
   }
 }
 
-template <int N, int PPT, int DIR, typename R, int S>
+template <int N, int PPT, int DIR, typename R, int S, bool WS = false>
 __device__ __forceinline__ void later_stages(cx<R>* buf, int t, const cx<R>* tws, cx<R>* reg) {
   using SH = fft_shape<N, PPT>;
   if constexpr (S <= SH::NST) {
     constexpr bool last = S == SH::NST;
-    stage_lds<N, PPT, SH::radix(S), SH::ns(S), SH::stage_off(S), DIR, last, R>(buf, t, tws, reg);
-    later_stages<N, PPT, DIR, R, S + 1>(buf, t, tws, reg);
+    stage_lds<N, PPT, SH::radix(S), SH::ns(S), SH::stage_off(S), DIR, last, R, WS>(buf, t, tws,
+                                                                                  reg);
+    later_stages<N, PPT, DIR, R, S + 1, WS>(buf, t, tws, reg);
   }
 }
 
@@ -310,7 +324,8 @@ __device__ __forceinline__ void later_stages(cx<R>* buf, int t, const cx<R>* tws
 // stage twiddle table (LDS). The routine starts with a group barrier before
 // its first LDS write, so callers may still have been reading buf.
 // DIR = +1: forward (exp(-2 pi i jk/N)); DIR = -1: inverse, unnormalised.
-template <int N, int PPT, int DIR, typename R>
+// WS: wave-scope group synchronisation (see group_sync).
+template <int N, int PPT, int DIR, typename R, bool WS = false>
 __device__ __forceinline__ void fft_group(cx<R>* reg, cx<R>* buf, int t, const cx<R>* tws) {
   using SH = fft_shape<N, PPT>;
   constexpr int T = SH::T;
@@ -319,7 +334,7 @@ __device__ __forceinline__ void fft_group(cx<R>* reg, cx<R>* buf, int t, const c
   if constexpr (SH::NST == 0) {
     return;   // N == PPT
   } else {
-    group_sync<T>();
+    group_sync<T, WS>();
     if constexpr (16 % PPT == 0) {   // t * PPT + r stays within one padding block
       const int pb = pad(t * PPT);
 #pragma unroll
@@ -332,8 +347,8 @@ __device__ __forceinline__ void fft_group(cx<R>* reg, cx<R>* buf, int t, const c
         buf[pad(t * PPT + r)] = reg[r];
       }
     }
-    group_sync<T>();
-    later_stages<N, PPT, DIR, R, 1>(buf, t, tws, reg);
+    group_sync<T, WS>();
+    later_stages<N, PPT, DIR, R, 1, WS>(buf, t, tws, reg);
     // last stage: butterfly b, output r -> element t + T (b + r NB), where
     // registers hold [b][r]; reorder to reg[q] = X[t + T q]
     constexpr int RL = SH::radix(SH::NST);

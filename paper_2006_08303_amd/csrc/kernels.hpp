@@ -136,7 +136,7 @@ __device__ __forceinline__ void staging_to_pair(cx<float>* v, const cx<float>* s
 // k = 0..N/2, and write them to the staging arrays as rows 2g, 2g + 1. `v`
 // holds Z in group register order on entry. The group scratch cb may
 // alias the staging arrays.
-template <int N2, int PPT, int SW = RT>
+template <int N2, int PPT, int SW = RT, bool WS = false>
 __device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<float>* stg, int g,
                                                 int t) {
   constexpr int T = N2 / PPT;
@@ -144,7 +144,7 @@ __device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<
   // (called right after fft_group, which ends with a barrier)
 #pragma unroll
   for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
-  group_sync<T>();
+  group_sync<T, WS>();
   cx<float> A[QH], B[QH];
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
@@ -179,26 +179,26 @@ __device__ __forceinline__ void pair_to_staging(cx<float>* v, cx<float>* cb, cx<
 // `ew` is the LDS table E[0..N).
 // LEAD: synchronise before the first LDS write (not needed right after
 // fft_group, which ends with a barrier after its last LDS read).
-template <int N, int PPT, bool LEAD = true>
+template <int N, int PPT, bool LEAD = true, bool WS = false>
 __device__ __forceinline__ void dct_fwd_group(cx<float>* reg, cx<float>* cb, int t,
                                               const cx<float>* tw, const cx<float>* ew) {
   constexpr int T = N / PPT;
   const float a0 = __builtin_sqrtf(1.0f / N), a1 = __builtin_sqrtf(2.0f / N);
-  if constexpr (LEAD) group_sync<T>();
+  if constexpr (LEAD) group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int n = t + T * q;
     int p = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
     stc(cb, p, reg[q]);
   }
-  group_sync<T>();
+  group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) reg[q] = ldc(cb, t + T * q);
-  fft_group<N, PPT, +1>(reg, cb, t, tw);
-  group_sync<T>();
+  fft_group<N, PPT, +1, float, WS>(reg, cb, t, tw);
+  group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, reg[q]);
-  group_sync<T>();
+  group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
@@ -216,15 +216,15 @@ __device__ __forceinline__ void dct_fwd_group(cx<float>* reg, cx<float>* cb, int
 // Inverse (DCT-III, orthonormal) of a complex coefficient sequence Y:
 //   V[k] = conj(E[k]) / N * (Y[k] / a_k - i Y[N-k] / a_{N-k}),  V[0] = Y[0] / (N a_0),
 // then an inverse FFT and the inverse even/odd reordering.
-template <int N, int PPT, bool LEAD = true>
+template <int N, int PPT, bool LEAD = true, bool WS = false>
 __device__ __forceinline__ void dct_inv_group(cx<float>* reg, cx<float>* cb, int t,
                                               const cx<float>* tw, const cx<float>* ew) {
   constexpr int T = N / PPT;
   const float ia0 = __builtin_sqrtf((float)N) / N, ia1 = __builtin_sqrtf(0.5f * N) / N;
-  if constexpr (LEAD) group_sync<T>();
+  if constexpr (LEAD) group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, reg[q]);
-  group_sync<T>();
+  group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int k = t + T * q;
@@ -239,15 +239,15 @@ __device__ __forceinline__ void dct_inv_group(cx<float>* reg, cx<float>* cb, int
     cx<float> e = ew[k];
     reg[q] = cmulc(a, e);   // a * conj(E[k])
   }
-  fft_group<N, PPT, -1>(reg, cb, t, tw);
-  group_sync<T>();
+  fft_group<N, PPT, -1, float, WS>(reg, cb, t, tw);
+  group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     int m = t + T * q;
     int pos = (m < N / 2) ? 2 * m : 2 * N - 2 * m - 1;
     stc(cb, pos, reg[q]);
   }
-  group_sync<T>();
+  group_sync<T, WS>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) reg[q] = ldc(cb, t + T * q);
 }
@@ -497,7 +497,7 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   cx<float> v[PPT];
   staging_to_pair<N2, PPT, SW>(v, stg, g, t);
   __syncthreads();   // staging aliases the group scratch
-  fft_group<N2, PPT, -1>(v, cb, t, tw);
+  fft_group<N2, PPT, -1, float, true>(v, cb, t, tw);
   if (mode == ROW_FINAL) {
     float* xa = xout + ((size_t)s * N1 + ra) * N2;
     float* xb = xa + N2;
@@ -509,7 +509,7 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
     }
     return;
   }
-  dct_fwd_group<N2, PPT, false>(v, cb, t, tw, ew);
+  dct_fwd_group<N2, PPT, false, true>(v, cb, t, tw, ew);
   if (sc == 1.f) {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -535,9 +535,9 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
       v[q] = cx<float>{ta - ua, tb - ub};
     }
   }
-  dct_inv_group<N2, PPT>(v, cb, t, tw, ew);
-  fft_group<N2, PPT, +1>(v, cb, t, tw);
-  pair_to_staging<N2, PPT, SW>(v, cb, stg, g, t);
+  dct_inv_group<N2, PPT, true, true>(v, cb, t, tw, ew);
+  fft_group<N2, PPT, +1, float, true>(v, cb, t, tw);
+  pair_to_staging<N2, PPT, SW, true>(v, cb, stg, g, t);
   __syncthreads();
   staging_to_subtile<SW>(Gout + rt_tile_base(s, row0, N1, H2), stg, H2, r0);
 }
@@ -1177,9 +1177,9 @@ __device__ __forceinline__ void col_body(const cx<float>* __restrict__ Gin,
   if (!zero_in) {
     if constexpr (DCT) {
       if (band) band_mix<N1, PPT, S, true>(v, reinterpret_cast<cx<float>*>(lds), band, g, t);
-      dct_inv_group<N1, PPT, false>(v, cb, t, tw, ew);
+      dct_inv_group<N1, PPT, false, true>(v, cb, t, tw, ew);
     }
-    fft_group<N1, PPT, +1>(v, cb, t, tw);
+    fft_group<N1, PPT, +1, float, true>(v, cb, t, tw);
 #pragma unroll
     for (int q = 0; q < PPT; ++q) stc(cb, t + T * q, v[q]);
     __syncthreads();
@@ -1228,10 +1228,10 @@ __device__ __forceinline__ void col_body(const cx<float>* __restrict__ Gin,
 #pragma unroll
     for (int q = 0; q < PPT; ++q) v[q] = xh0[(size_t)g * F + f0 + T * q];
   }
-  fft_group<N1, PPT, -1>(v, cb, t, tw);
+  fft_group<N1, PPT, -1, float, true>(v, cb, t, tw);
   if constexpr (DCT) {
     if (dct_out) {
-      dct_fwd_group<N1, PPT, false>(v, cb, t, tw, ew);
+      dct_fwd_group<N1, PPT, false, true>(v, cb, t, tw, ew);
       if (band) band_mix<N1, PPT, S, false>(v, reinterpret_cast<cx<float>*>(lds), band, g, t);
     }
   }
