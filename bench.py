@@ -239,6 +239,8 @@ def run_other_priors(args, dev, psf_t, y_t):
     ]
     out = {}
     for name, kw, which in cases:
+        if args.others_only and args.others_only not in name:
+            continue
         kw = dict(kw)
         prior = kw.pop("prior")
         rho, lam, beta = kw.pop("rho"), kw.pop("lam"), kw.pop("beta")
@@ -379,6 +381,10 @@ def run_serving(args, dev, n_slots):
     sizes = [n for n in (256, 384, 512, 768, 1024, 1536, 2048) if n in cip.SUPPORTED_N]
     kinds = [(N, B) for N in sizes for B in (3, 5, 8)]
     srv = cip.Server(args.serve_budget_gb << 30, n_slots=n_slots, autotune=not args.no_autotune)
+    # results are not inspected here: every kind writes into a ring of
+    # n_slots + 1 host buffers (an overloaded trace queues thousands of
+    # requests; a buffer each would take ~100 GB of host memory)
+    ring = n_slots + 1
     ops, ys, pools = [], [], []
     for j, (N, B) in enumerate(kinds):
         psf = synth.disk_psfs(B, B, N, N)
@@ -386,7 +392,7 @@ def run_serving(args, dev, n_slots):
                                     1e-2, 1e-3, 1.0))
         ys.append(np.ascontiguousarray(
             synth.unit_noise(synth.rng_for(5, j), B, N, N).astype(np.float32)))
-        pools.append([])
+        pools.append([np.empty((B, N, N), np.float32) for _ in range(ring)])
     torch.cuda.synchronize()
     n_req = int(args.serve_seconds * args.serve_rate)
     gaps = rng.exponential(1.0 / args.serve_rate, n_req)
@@ -409,13 +415,15 @@ def run_serving(args, dev, n_slots):
                 time.sleep(0.001)
                 continue
             lat.append(srv.wait(t)[0])
-            with lock:
-                pools[j].append(xb)
             i += 1
+            if i % 500 == 0:
+                print(f"[bench] serving ({n_slots} slots): {i}/{n_req} done, "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
+    used = [0] * len(kinds)
+    t0 = time.perf_counter()
     th = threading.Thread(target=reaper)
     th.start()
-    t0 = time.perf_counter()
     due = t0
     for k in range(n_req):
         due += gaps[k]
@@ -423,9 +431,8 @@ def run_serving(args, dev, n_slots):
         if due > now:
             time.sleep(due - now)
         j = int(which[k])
-        N, B = kinds[j]
-        with lock:
-            xb = pools[j].pop() if pools[j] else np.empty((B, N, N), np.float32)
+        xb = pools[j][used[j] % ring]
+        used[j] += 1
         t = srv.submit(ops[j], ys[j], xb, args.iters)
         with lock:
             tickets.append((t, j, xb))
@@ -455,6 +462,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=70)
     ap.add_argument("--iters-other", type=int, default=20,
                     help="iterations per solve for the other priors (0: skip)")
+    ap.add_argument("--others-only", default="",
+                    help="run only the other priors whose name contains this text")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--batch", type=int, default=96, help="problems in the batch run (0: skip)")
@@ -464,7 +473,7 @@ def main():
                     help="keep the default row-pass shapes (no cip_plan_autotune)")
     ap.add_argument("--quick", action="store_true",
                     help="headline DCT solve and kernel timings only (for profiler runs)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the Poisson arrival trace (0: skip serving)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=int, default=96)
@@ -474,7 +483,8 @@ def main():
     if args.quick:
         args.no_cpu, args.no_tv, args.batch, args.serve_seconds, args.concurrent = \
             True, True, 0, 0.0, 0
-        args.iters_other = 0
+        if not args.others_only:
+            args.iters_other = 0
     if args.gpus != 1:
         print("bench.py measures one GPU: one reconstruction runs on a single device "
               "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)

@@ -136,6 +136,15 @@ typedef struct {
                            convolutional one                               */
   /* CIP_PRIOR_WDCT3D only:                                                   */
   int wt_levels;        /* wavelet levels, 1 .. 10 (0: 3)                     */
+  /* CIP_PRIOR_PATCH only:                                                    */
+  int patch_t;          /* patch depth T along the planes (Q x Q x T patches,
+                           Eq. patch_based): 0 or S (patches span every
+                           plane); other depths return CIP_EUNSUPPORTED    */
+  /* CIP_PRIOR_CONV2D only:                                                   */
+  int per_band;         /* 0: one common set of M filters for every plane
+                           (the 2D-correlation form of Section III-B);
+                           1: a separate set per plane, which this build does
+                           not serve (CIP_EUNSUPPORTED)                     */
 } cip_prior_desc;
 
 enum { CIP_PLAN_ADAPTIVE = 1, CIP_PLAN_DICT_UPDATE = 2 };
@@ -178,8 +187,11 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf,
  * FP32 FFTs; d_x and d_y must not overlap. */
 int cip_forward(cip_plan_t plan, const float* d_x, float* d_y, void* stream);
 
-/* x = H^T y (x_s = sum_k h_{k,s} correlated with y_k): d_y [K][N1][N2] ->
- * d_x [S][N1][N2]. FP32 FFTs; must not overlap. */
+/* x = H^T y, the transpose of the block matrix H of Eq. forwardModel (its
+ * (k, s) block is the circular convolution by h_{k,s}): x_s is the sum over k
+ * of y_k circularly correlated with h_{k,s}; in the frequency domain
+ * x_hat_s = sum_k conj(Lambda_{k,s}) y_hat_k (Section IV-A). d_y [K][N1][N2]
+ * -> d_x [S][N1][N2]. FP32 FFTs; d_x and d_y must not overlap. */
 int cip_adjoint(cip_plan_t plan, const float* d_y, float* d_x, void* stream);
 
 /* Run `iters` >= 1 ADMM iterations from t = u = 0 (and z = 0) on the
@@ -279,6 +291,15 @@ int cip_plan_attach(cip_plan_t base, void* d_state, size_t bytes, cip_plan_t* ou
  * (CIP_PLAN_DICT_UPDATE) run in direct batches only: with use_graph the call
  * returns CIP_EUNSUPPORTED before any capture. */
 typedef struct cip_batch_s* cip_batch_t;
+/* One-shot form: the n solves (distinct plans; d_y[i] [K][N1][N2] ->
+ * d_x[i] [S][N1][N2] after iters[i] iterations) launched directly over the
+ * library's internal streams (four per device, created at the first call and
+ * kept until the process ends), forked from and joined back to `stream`;
+ * asynchronous on `stream`, like cip_solve. Each result equals that of a
+ * lone cip_solve on the same plan. Calls from several host threads are
+ * enqueued one after the other. */
+int cip_batch_solve(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
+                    float* const* d_x, void* stream);
 int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
                      float* const* d_x, int n_streams, int use_graph, cip_batch_t* out);
 int cip_batch_launch(cip_batch_t batch, void* stream);
@@ -314,8 +335,12 @@ typedef struct {
   int iters;                 /* ADMM iterations (>= 1)                      */
 } cip_request;
 int cip_server_create(const cip_server_config* cfg, cip_server_t* out);
-/* d_psf: device [K][S][N1][N2], read during the call. CIP_ENOSPC when the
- * operator's workspace does not fit in the free part of the arena. */
+/* d_psf: device [K][S][N1][N2], read during the call on the server's own
+ * registration stream: the kernels (and the dictionary or filters of the
+ * prior) must already be written when the call is made (synchronise the
+ * stream that wrote them first). The plan is built and, with autotune,
+ * tuned on that stream while queued requests keep running. CIP_ENOSPC when
+ * the operator's workspace does not fit in the free part of the arena. */
 int cip_server_add_operator(cip_server_t server, int K, int S, int N1, int N2, const float* d_psf,
                             const cip_prior_desc* prior, double rho, double lambda, int* op_id);
 /* Queue a request; CIP_ENOSPC when it could never fit in the budget. */

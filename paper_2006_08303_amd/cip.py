@@ -44,7 +44,7 @@ class _PriorDesc(ctypes.Structure):
                 ("filters", ctypes.c_void_p), ("n_filters", ctypes.c_int),
                 ("filt_l", ctypes.c_int), ("mu", ctypes.c_double), ("tv_inner", ctypes.c_int),
                 ("flags", ctypes.c_int), ("sigma", ctypes.c_double),
-                ("wt_levels", ctypes.c_int)]
+                ("wt_levels", ctypes.c_int), ("patch_t", ctypes.c_int), ("per_band", ctypes.c_int)]
 
 
 class _AdaptiveParams(ctypes.Structure):
@@ -117,6 +117,8 @@ def lib():
                                        ctypes.POINTER(i), ctypes.POINTER(vp), i, i,
                                        ctypes.POINTER(vp)]
         L.cip_batch_launch.argtypes = [vp, vp]
+        L.cip_batch_solve.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i),
+                                      ctypes.POINTER(vp), vp]
         L.cip_batch_destroy.argtypes = [vp]
         L.cip_plan_state_bytes.argtypes = [vp, ctypes.POINTER(sz)]
         L.cip_plan_attach.argtypes = [vp, vp, sz, ctypes.POINTER(vp)]
@@ -140,7 +142,7 @@ def lib():
                      "cip_plan_attach", "cip_server_create", "cip_server_add_operator",
                      "cip_server_submit", "cip_server_poll", "cip_server_wait",
                      "cip_server_destroy", "cip_solve_adaptive", "cip_plan_autotune",
-                     "cip_plan_set_tuning", "cip_solve_static"):
+                     "cip_plan_set_tuning", "cip_solve_static", "cip_batch_solve"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -307,6 +309,23 @@ def solve_static(psf, y, iters, prior="dct2d", rho=0.1, lam=0.01, beta=1.0, dict
     return x
 
 
+def batch_solve(problems, stream=None):
+    """cip_batch_solve: problems is a list of (plan, y, iters, x) with
+    distinct plans; the solves run over the library's internal streams,
+    asynchronously on `stream`."""
+    n = len(problems)
+    if n == 0:
+        raise ValueError("empty batch")
+    vp = ctypes.c_void_p
+    plans, ys, xs, its = (vp * n)(), (vp * n)(), (vp * n)(), (ctypes.c_int * n)()
+    for j, (plan, y, iters, x) in enumerate(problems):
+        plans[j] = plan._h.value
+        ys[j] = _dev_f32(y, (plan.K, plan.N1, plan.N2), "y").value
+        xs[j] = _dev_f32(x, (plan.S, plan.N1, plan.N2), "x").value
+        its[j] = int(iters)
+    _check(lib().cip_batch_solve(n, plans, ys, its, xs, _stream_ptr(stream)))
+
+
 class Batch:
     """Independent solves run together (cip_batch_create / cip_batch_launch).
 
@@ -378,6 +397,8 @@ class Server:
                      filters=None):
         K, S, N1, N2 = (int(v) for v in psf.shape)
         desc = _desc(prior, beta, dictionary, filters)
+        # the library reads the kernels on its own stream: finish writing them
+        torch.cuda.current_stream(psf.device).synchronize()
         op = ctypes.c_int()
         _check(lib().cip_server_add_operator(self._h, K, S, N1, N2,
                                              _dev_f32(psf, (K, S, N1, N2), "psf"),

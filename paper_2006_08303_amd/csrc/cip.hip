@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -230,6 +231,13 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     if (!patch_supported(S, prior->n_atoms))
       return fail(CIP_EUNSUPPORTED, "patch prior: needs S <= 4 and 64, 128 or 256 atoms");
     if (!patch_grid_ok(N1, N2)) return fail(CIP_EUNSUPPORTED, "patch prior: grid too small");
+    if (prior->patch_t != 0 && prior->patch_t != S)
+      return fail(CIP_EUNSUPPORTED, "patch prior: patches must span every plane (patch_t 0 or S)");
+  }
+  if (prior->kind == CIP_PRIOR_CONV2D) {
+    if (prior->per_band == 1)
+      return fail(CIP_EUNSUPPORTED, "conv prior: only a common filter set for every plane");
+    if (prior->per_band != 0) return fail(CIP_EINVAL, "per_band must be 0 or 1");
   }
   if (prior->kind == CIP_PRIOR_CONV2D || prior->kind == CIP_PRIOR_CONV3D) {
     if (prior->n_filters < 1 || prior->n_filters > 32)
@@ -1317,19 +1325,74 @@ struct cip_batch_s {
 
 namespace {
 
-int batch_enqueue(cip_batch_s* b, hipStream_t origin) {
-  HIP_TRY(hipEventRecord(b->fork, origin));
-  for (size_t i = 0; i < b->streams.size(); ++i) {
-    HIP_TRY(hipStreamWaitEvent(b->streams[i], b->fork, 0));
-    for (int j : b->lanes[i]) {
-      int rc = cip_solve(b->plans[j], b->y[j], b->iters[j], b->x[j], b->streams[i]);
+// Fork / join of the solves over `streams`: lanes[i] lists the problems of
+// stream i.
+int fork_join(const std::vector<std::vector<int>>& lanes, const std::vector<hipStream_t>& streams,
+              hipEvent_t fork, const std::vector<hipEvent_t>& join, const cip_plan_t* plans,
+              const float* const* y, const int* iters, float* const* x, hipStream_t origin) {
+  HIP_TRY(hipEventRecord(fork, origin));
+  for (size_t i = 0; i < lanes.size(); ++i) {
+    HIP_TRY(hipStreamWaitEvent(streams[i], fork, 0));
+    for (int j : lanes[i]) {
+      int rc = cip_solve(plans[j], y[j], iters[j], x[j], streams[i]);
       if (rc) return rc;
     }
-    HIP_TRY(hipEventRecord(b->join[i], b->streams[i]));
-    HIP_TRY(hipStreamWaitEvent(origin, b->join[i], 0));
+    HIP_TRY(hipEventRecord(join[i], streams[i]));
+    HIP_TRY(hipStreamWaitEvent(origin, join[i], 0));
   }
   return CIP_OK;
 }
+
+int batch_enqueue(cip_batch_s* b, hipStream_t origin) {
+  return fork_join(b->lanes, b->streams, b->fork, b->join, b->plans.data(), b->y.data(),
+                   b->iters.data(), b->x.data(), origin);
+}
+
+// Problems spread largest-first (cost ~ N1 N2 (S + K) iters) onto the
+// least-loaded of ns lanes.
+std::vector<std::vector<int>> assign_lanes(int n, const cip_plan_t* plans, const int* iters,
+                                           int ns) {
+  std::vector<std::vector<int>> lanes(ns);
+  std::vector<double> load(ns, 0.0), cost(n);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    const cip_plan_t p = plans[i];
+    cost[i] = (double)p->N1 * p->N2 * (p->S + p->K) * iters[i];
+  }
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  for (int i : order) {
+    int best = 0;
+    for (int k = 1; k < ns; ++k)
+      if (load[k] < load[best]) best = k;
+    lanes[best].push_back(i);
+    load[best] += cost[i];
+  }
+  return lanes;
+}
+
+int check_batch_args(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
+                     float* const* d_x) {
+  if (n < 1 || !plans || !d_y || !iters || !d_x) return fail(CIP_EINVAL, "bad argument");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || !d_y[i] || !d_x[i] || iters[i] < 1) return fail(CIP_EINVAL, "bad problem entry");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(CIP_EINVAL, "a plan may appear once per batch");
+  }
+  return CIP_OK;
+}
+
+// Internal streams and events of cip_batch_solve, per device, created at the
+// first call on that device and kept until the process ends.
+constexpr int kPoolStreams = 4;
+struct StreamPool {
+  bool ready = false;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+};
+std::mutex g_pool_mu;
+StreamPool g_pool[64];
 
 void batch_free(cip_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1344,15 +1407,38 @@ void batch_free(cip_batch_s* b) {
 
 extern "C" {
 
+int cip_batch_solve(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
+                    float* const* d_x, void* stream) {
+  int rc = check_batch_args(n, plans, d_y, iters, d_x);
+  if (rc) return rc;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return fail(CIP_EHIP, "cip_batch_solve: no usable current device");
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  StreamPool& P = g_pool[dev];
+  if (!P.ready) {
+    P.streams.assign(kPoolStreams, nullptr);
+    P.join.assign(kPoolStreams, nullptr);
+    for (int k = 0; k < kPoolStreams; ++k) {
+      HIP_TRY(hipStreamCreateWithFlags(&P.streams[k], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&P.join[k], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
+    P.ready = true;
+  }
+  const int ns = n < kPoolStreams ? n : kPoolStreams;
+  const std::vector<hipStream_t> streams(P.streams.begin(), P.streams.begin() + ns);
+  const std::vector<hipEvent_t> join(P.join.begin(), P.join.begin() + ns);
+  return fork_join(assign_lanes(n, plans, iters, ns), streams, P.fork, join, plans, d_y, iters,
+                   d_x, reinterpret_cast<hipStream_t>(stream));
+}
+
 int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, const int* iters,
                      float* const* d_x, int n_streams, int use_graph, cip_batch_t* out) {
-  if (n < 1 || !plans || !d_y || !iters || !d_x || !out) return fail(CIP_EINVAL, "bad argument");
+  if (!out) return fail(CIP_EINVAL, "bad argument");
   if (n_streams < 1 || n_streams > 64) return fail(CIP_EINVAL, "n_streams must be in [1, 64]");
-  for (int i = 0; i < n; ++i) {
-    if (!plans[i] || !d_y[i] || !d_x[i] || iters[i] < 1) return fail(CIP_EINVAL, "bad problem entry");
-    for (int j = 0; j < i; ++j)
-      if (plans[j] == plans[i]) return fail(CIP_EINVAL, "a plan may appear once per batch");
-  }
+  int crc = check_batch_args(n, plans, d_y, iters, d_x);
+  if (crc) return crc;
   if (use_graph)
     for (int i = 0; i < n; ++i)
       if (plans[i]->learn)
@@ -1363,22 +1449,7 @@ int cip_batch_create(int n, const cip_plan_t* plans, const float* const* d_y, co
   b->x.assign(d_x, d_x + n);
   b->iters.assign(iters, iters + n);
   const int ns = n_streams < n ? n_streams : n;
-  b->lanes.resize(ns);
-  std::vector<double> load(ns, 0.0), cost(n);
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) {
-    order[i] = i;
-    const cip_plan_t p = plans[i];
-    cost[i] = (double)p->N1 * p->N2 * (p->S + p->K) * iters[i];
-  }
-  std::sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-  for (int i : order) {
-    int best = 0;
-    for (int k = 1; k < ns; ++k)
-      if (load[k] < load[best]) best = k;
-    b->lanes[best].push_back(i);
-    load[best] += cost[i];
-  }
+  b->lanes = assign_lanes(n, plans, iters, ns);
   auto bail = [&](int code, const std::string& m) {
     batch_free(b);
     return fail(code, m);

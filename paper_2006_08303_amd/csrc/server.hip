@@ -120,6 +120,8 @@ struct cip_server_s {
   std::condition_variable done_cv;   // a request finished
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  hipStream_t op_stream = nullptr;   // operator registration (plan build, autotuning)
+  std::mutex op_mu;                  // one registration at a time
 
   // Pick and reserve memory for the next admissible request (lock held).
   bool pick(uint64_t* ticket, size_t* off) {
@@ -138,8 +140,8 @@ struct cip_server_s {
     return false;
   }
 
-  int run(Request& r, size_t off, hipStream_t st) {
-    const Operator& op = ops[r.op];
+  // `op` is a copy taken under the lock (ops may grow meanwhile).
+  int run(const Request& r, const Operator& op, size_t off, hipStream_t st) {
     unsigned char* mem = static_cast<unsigned char*>(base) + off;
     float* dy = reinterpret_cast<float*>(mem + round_up(op.state_bytes));
     const size_t ybytes = (size_t)op.K * op.N1 * op.N2 * 4;
@@ -171,8 +173,9 @@ struct cip_server_s {
       Request& r = reqs[t];
       r.status = 2;
       r.start = Clock::now();
+      const Operator op = ops[r.op];
       lk.unlock();
-      const int rc = run(r, off, st);
+      const int rc = run(r, op, off, st);
       const std::string msg = rc ? cip::g_last_error : std::string();
       lk.lock();
       arena->release(off, r.bytes);
@@ -208,6 +211,11 @@ int cip_server_create(const cip_server_config* cfg, cip_server_t* out) {
     }
     s->streams.push_back(st);
   }
+  if (hipStreamCreateWithFlags(&s->op_stream, hipStreamNonBlocking) != hipSuccess) {
+    for (auto q : s->streams) (void)hipStreamDestroy(q);
+    (void)hipFree(s->base);
+    return fail(CIP_EHIP, "hipStreamCreate failed");
+  }
   cip_server_s* raw = s.get();
   for (int i = 0; i < cfg->n_slots; ++i) raw->workers.emplace_back([raw, i] { raw->worker(i); });
   *out = s.release();
@@ -220,6 +228,13 @@ int cip_server_add_operator(cip_server_t s, int K, int S, int N1, int N2, const 
   size_t ws = 0;
   int rc = cip_plan_workspace_bytes(K, S, N1, N2, prior, &ws);
   if (rc) return rc;
+  std::lock_guard<std::mutex> reg(s->op_mu);
+  auto release = [&](size_t off, size_t bytes, bool op_bytes) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->arena->release(off, bytes);
+    if (op_bytes) s->reserved_ops -= round_up(bytes);
+    s->work_cv.notify_all();   // a queued request may fit now
+  };
   size_t off;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -227,23 +242,26 @@ int cip_server_add_operator(cip_server_t s, int K, int S, int N1, int N2, const 
     if (off == SIZE_MAX) return fail(CIP_ENOSPC, "operator does not fit in the server budget");
     s->reserved_ops += round_up(ws);
   }
+  // plan build and autotuning on the registration stream, without the lock
+  hipStream_t st = s->op_stream;
   cip_plan_t plan = nullptr;
   rc = cip_plan_create(K, S, N1, N2, d_psf, prior, rho, lambda,
-                       static_cast<unsigned char*>(s->base) + off, ws, s->streams[0], &plan);
-  std::lock_guard<std::mutex> lk(s->mu);
+                       static_cast<unsigned char*>(s->base) + off, ws, st, &plan);
   if (rc) {
-    s->arena->release(off, ws);
-    s->reserved_ops -= round_up(ws);
+    release(off, ws, true);
     return rc;
   }
   if (s->autotune && prior->kind != CIP_PRIOR_PATCH && prior->kind != CIP_PRIOR_CONV2D) {
     // one short solve on zero measurements (the tuner times the row pass on
     // the plan's own buffers), with y and x carved from the arena meanwhile
     const size_t yb = round_up((size_t)K * N1 * N2 * 4), xb = (size_t)S * N1 * N2 * 4;
-    const size_t toff = s->arena->alloc(yb + xb);
+    size_t toff;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      toff = s->arena->alloc(yb + xb);
+    }
     if (toff != SIZE_MAX) {
       unsigned char* t = static_cast<unsigned char*>(s->base) + toff;
-      hipStream_t st = s->streams[0];
       int trc = hipMemsetAsync(t, 0, yb, st) == hipSuccess ? CIP_OK : CIP_EHIP;
       if (!trc) trc = cip_solve(plan, reinterpret_cast<float*>(t), 2,
                                 reinterpret_cast<float*>(t + yb), st);
@@ -252,12 +270,12 @@ int cip_server_add_operator(cip_server_t s, int K, int S, int N1, int N2, const 
         if (trc == CIP_EUNSUPPORTED) trc = CIP_OK;   // this prior has one row-pass shape
       }
       if (!trc && hipStreamSynchronize(st) != hipSuccess) trc = CIP_EHIP;
-      s->arena->release(toff, yb + xb);
+      release(toff, yb + xb, false);
       if (trc) {
-        s->arena->release(off, ws);
-        s->reserved_ops -= round_up(ws);
+        const std::string msg = cip::g_last_error;
         cip_plan_destroy(plan);
-        return fail(trc, "operator autotuning failed: " + cip::g_last_error);
+        release(off, ws, true);
+        return fail(trc, "operator autotuning failed: " + msg);
       }
     }
   }
@@ -270,6 +288,7 @@ int cip_server_add_operator(cip_server_t s, int K, int S, int N1, int N2, const 
   op.ws_off = off;
   op.ws_bytes = ws;
   cip_plan_state_bytes(plan, &op.state_bytes);
+  std::lock_guard<std::mutex> lk(s->mu);
   s->ops.push_back(op);
   *op_id = (int)s->ops.size() - 1;
   return CIP_OK;
@@ -339,6 +358,7 @@ int cip_server_destroy(cip_server_t s) {
   for (auto& w : s->workers) w.join();
   for (auto& op : s->ops) cip_plan_destroy(op.plan);
   for (auto st : s->streams) (void)hipStreamDestroy(st);
+  if (s->op_stream) (void)hipStreamDestroy(s->op_stream);
   (void)hipFree(s->base);
   delete s;
   return CIP_OK;

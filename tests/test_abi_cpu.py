@@ -174,3 +174,27 @@ def test_solve_static_refuses_problems_beyond_its_buffer(L):
     rc = L.cip_solve_static(3, 3, 64, 64, dummy, ctypes.byref(desc), 0.1, 0.01, dummy, 0,
                             dummy, None)
     assert rc == -1
+
+
+def test_batch_solve_and_descriptor_fields_are_checked_on_the_host(L):
+    """cip_batch_solve refuses empty batches and a plan listed twice before
+    any device work (the plan handles are not dereferenced); the descriptor
+    fields patch_t (patch depth) and per_band (conv filter sets) accept
+    the served values and refuse the others."""
+    from paper_2006_08303_amd import cip
+    vp = ctypes.c_void_p
+    plans = (vp * 2)(256, 256)
+    ptrs = (vp * 2)(256, 512)
+    its = (ctypes.c_int * 2)(3, 3)
+    assert L.cip_batch_solve(0, plans, ptrs, its, ptrs, None) == -1
+    assert L.cip_batch_solve(2, plans, ptrs, its, ptrs, None) == -1
+    assert b"once" in L.cip_last_error()
+    n = ctypes.c_size_t()
+    for pt, rc in ((0, 0), (3, 0), (1, -2), (2, -2)):
+        d = cip._PriorDesc(cip.CIP_PRIOR_PATCH, 500.0)
+        d.n_atoms, d.patch_q, d.patch_stride, d.patch_t = 256, 8, 4, pt
+        assert L.cip_plan_workspace_bytes(3, 3, 256, 256, ctypes.byref(d), ctypes.byref(n)) == rc
+    for pb, rc in ((0, 0), (1, -2), (2, -1)):
+        d = cip._PriorDesc(cip.CIP_PRIOR_CONV2D, 8.0)
+        d.n_filters, d.filt_l, d.per_band = 32, 11, pb
+        assert L.cip_plan_workspace_bytes(3, 3, 256, 256, ctypes.byref(d), ctypes.byref(n)) == rc

@@ -97,3 +97,16 @@ def test_batch_rejects_bad_arguments(batch_setup):
         cip.Batch([(plan, y, 0, x)])
     with pytest.raises(cip.CipError):
         cip.Batch([(plan, y, iters, x)], n_streams=0)
+
+
+def test_one_shot_batch_solve_equals_lone_solves(batch_setup):
+    """cip_batch_solve (internal stream pool, asynchronous on the caller's
+    stream): every result bitwise equal to the lone solve, twice in a row
+    (the pool is reused), the second time on a subset."""
+    probs, solo = batch_setup
+    for sel in (list(range(len(probs))), [0, 3, 6, 9]):
+        outs = [torch.full_like(solo[j], float("nan")) for j in sel]
+        cip.batch_solve([(probs[j][0], probs[j][1], probs[j][2], o) for j, o in zip(sel, outs)])
+        torch.cuda.synchronize()
+        for j, o in zip(sel, outs):
+            assert torch.equal(o, solo[j]), j
