@@ -1,11 +1,12 @@
 // Patch-dictionary synthesis prior (Eq. patch_based), sparse-code update of
-// Algorithm 2 on MFMA (gfx950 v_mfma_f32_32x32x16_bf16, FP32 accumulation).
+// Algorithm 2 on MFMA (gfx950 v_mfma_f32_16x16x32_bf16, FP32 accumulation).
 //
 // Geometry: Q x Q x S patches (Q = 8) spanning all planes, extracted
 // circularly at stride st = 4 (P^T P = 4 I). Patch vector element
 // s*64 + a*8 + b of patch (pi, pj) is x[s][4 pi + a][4 pj + b]; the patch
 // index is j = pi * J2 + pj with J1 = N1 / 4, J2 = N2 / 4. A work-group owns a
-// tile of 64 patches, TPR x TPC (TPC = min(64, J2)).
+// tile of 64 patches, TPR x TPC (TPC = min(64, J2)); with this ordering the
+// tile's patches are the 64 consecutive indices 64 tile .. 64 tile + 63.
 //
 // Per tile, with the ADMM state v = z + u_prev (t = soft(v), u = clip(v),
 // w = t - u = 2 soft(v) - v, all as in the analysis passes):
@@ -16,10 +17,16 @@
 // z = w + M1 (P x - D w) equals Eq. solz_patch2,
 // (rho I + D^T D)^-1 (D^T P x + rho w), by the push-through identity; it never
 // forms the badly conditioned (rho I + D^T D)^-1 and its correction term is
-// small, which suits BF16 operands. D z of the 64 patches is overlap-added
-// inside the tile (fixed summation order) and written to a per-tile buffer;
-// k_patch_assemble sums the (at most 4) tiles covering each pixel, giving
-// P^T D~ z for the next x-update (Eq. solx_synt) without atomics.
+// small, which suits BF16 operands. Each GEMM's rows are split evenly over
+// the 4 waves (16-row MFMA blocks), every wave covering all 64 patches. D z of
+// the 64 patches is overlap-added inside the tile (fixed summation order)
+// and written to a per-tile buffer; k_patch_assemble sums the (at most 4)
+// tiles covering each pixel, giving P^T D~ z for the next x-update
+// (Eq. solx_synt) without atomics.
+//
+// The state v is stored patch-major, [J][A] (the A codes of a patch are
+// contiguous), so a tile's state is one contiguous block and every thread
+// moves four codes of one patch at a time.
 #pragma once
 #include "kernels.hpp"
 
@@ -27,6 +34,8 @@ namespace cip {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int PATCH_Q = 8;
 constexpr int PATCH_ST = 4;
@@ -46,6 +55,7 @@ __device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t* p) {
 
 struct PatchGeo {
   int N1, N2, J1, J2, TPR, TPC, ntc, RR, RC;
+  int ltpc;   // log2(TPC)
 };
 
 __host__ __device__ inline PatchGeo patch_geo(int N1, int N2) {
@@ -59,15 +69,20 @@ __host__ __device__ inline PatchGeo patch_geo(int N1, int N2) {
   g.ntc = g.J2 / g.TPC;
   g.RR = PATCH_ST * g.TPR + (PATCH_Q - PATCH_ST);
   g.RC = PATCH_ST * g.TPC + (PATCH_Q - PATCH_ST);
+  g.ltpc = 0;
+  while ((1 << g.ltpc) < g.TPC) ++g.ltpc;
   return g;
 }
 
-// LDS bytes of k_patch_z
+// LDS of k_patch_z: WB [64][NA + 8] bf16 (w, then z) and EB [64][NV + 8]
+// bf16 (e), the B operands of the products (rows 16-byte aligned, the pad
+// spreads consecutive patches over the banks); after the last product both
+// are reused for DZ [64][NV + 4] float (D z of every patch).
 template <int S, int NA> constexpr int patch_lds_bytes() {
   constexpr int NV = 64 * S;
   constexpr int wb = PATCH_NP * (NA + 8) * 2;
   constexpr int eb = PATCH_NP * (NV + 8) * 2;
-  constexpr int dz = PATCH_NP * NV * 4;
+  constexpr int dz = PATCH_NP * (NV + 4) * 4;
   return wb + eb > dz ? wb + eb : dz;
 }
 
@@ -76,210 +91,223 @@ template <int S, int NA> constexpr int patch_lds_bytes() {
 // (after a dictionary change).
 enum { PZ_FULL = 0, PZ_CODES = 1, PZ_SYNTH = 2 };
 
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+  const bf16x4 h = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};   // round to nearest even
+  return __builtin_bit_cast(uint2, h);
+}
+
+// One product C (RB blocks of 16 rows of A, all 64 patches) += A B over K:
+// A rows from global memory (bf16, row stride K), B from LDS (patch rows of
+// stride BS, K contiguous). Lane l holds A row (l % 16) and B column (l % 16)
+// at k = 8 (l / 16) .. + 7 of every 32-wide k step; C block (rb, cb) holds
+// rows 4 (l / 16) + i (i < 4) of column l % 16.
+template <int RB, int K, int BS>
+__device__ __forceinline__ void patch_mfma(f32x4 (&acc)[RB][4], const uint16_t* __restrict__ A,
+                                           const uint16_t* B, int c16, int q4) {
+  const uint16_t* Ar = A + (size_t)c16 * K + 8 * q4;
+  const uint16_t* Br = B + c16 * BS + 8 * q4;
+#pragma unroll 2
+  for (int ks = 0; ks < K / 32; ++ks) {
+    bf16x8 a[RB], b[4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) a[rb] = ld_bf16x8(Ar + (size_t)rb * 16 * K + 32 * ks);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) b[cb] = ld_bf16x8(Br + cb * 16 * BS + 32 * ks);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+  }
+}
+
 // Sparse-code update for one tile of 64 patches per work-group (4 waves).
 //   x   [S][N1][N2]  current image x^{l+1}
-//   v   [NA][J]      state, updated in place (first: treated as 0)
+//   v   [J][NA]      state, updated in place (first: treated as 0)
 //   tb  per-tile overlap-added D z, [tile][S][RR][RC]
 //   Dg  [NV][NA] bf16, M1g [NA][NV] bf16 (row-major)
 //   zf  [NA][J]      codes z in FP32 (PZ_CODES: written; PZ_SYNTH: read)
 template <int S, int NA, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict__ tb,
           const uint16_t* __restrict__ Dg, const uint16_t* __restrict__ M1g, PatchGeo G,
           float kappa, int first, float* __restrict__ zf) {
   constexpr int NV = 64 * S;
   constexpr int WS = NA + 8;   // LDS row stride of W / Z (bf16)
   constexpr int ES = NV + 8;   // LDS row stride of E (bf16)
+  constexpr int DS = NV + 4;   // LDS row stride of DZ (float)
+  constexpr int RB1 = NV / 64;   // 16-row blocks per wave of the n x 64 products
+  constexpr int RB2 = NA / 64;   // 16-row blocks per wave of the A x 64 product
   static_assert(NA % 64 == 0, "atoms must be a multiple of 64");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint16_t* WB = reinterpret_cast<uint16_t*>(smem_raw);
   uint16_t* EB = WB + PATCH_NP * WS;
   float* DZ = reinterpret_cast<float*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l32 = lane & 31, lhi = lane >> 5;
+  const int c16 = lane & 15, q4 = lane >> 4;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tr = tile / G.ntc, tc = tile % G.ntc;
+  const int tr = tile / G.ntc, tc = tile - tr * G.ntc;
   const size_t J = (size_t)G.J1 * G.J2;
-  auto jglob = [&](int jl) -> size_t {
-    return (size_t)(tr * G.TPR + jl / G.TPC) * G.J2 + tc * G.TPC + jl % G.TPC;
-  };
+  const size_t j0 = (size_t)tile * PATCH_NP;   // first patch of the tile
+  float* vt = v + j0 * NA;                     // the tile's state block [64][NA]
 
   if constexpr (MODE == PZ_SYNTH) {
-    // codes from zf, as bf16 rows WB[patch][atom]
-    for (int idx = threadIdx.x; idx < NA * PATCH_NP; idx += 256) {
-      const int a = idx / PATCH_NP, jl = idx % PATCH_NP;
-      WB[jl * WS + a] = f2bf(zf[(size_t)a * J + jglob(jl)]);
+    // codes from zf, as bf16 rows WB[patch][atom] (lanes over patches: the
+    // zf reads are contiguous)
+    for (int it = threadIdx.x; it < PATCH_NP * NA / 4; it += 256) {
+      const int jl = it & (PATCH_NP - 1), a = 4 * (it >> 6);
+      const float* zp = zf + (size_t)a * J + j0 + jl;
+      *reinterpret_cast<uint2*>(WB + jl * WS + a) =
+          pack_bf16x4(zp[0], zp[J], zp[2 * J], zp[3 * J]);
     }
     __syncthreads();
   } else {
     // 0. w = t - u = 2 soft(v) - v, as bf16 rows WB[patch][atom]
-    for (int idx = threadIdx.x; idx < NA * PATCH_NP; idx += 256) {
-      const int a = idx / PATCH_NP, jl = idx % PATCH_NP;
-      const float vv = first ? 0.f : v[(size_t)a * J + jglob(jl)];
-      WB[jl * WS + a] = f2bf(2.f * soft_f(vv, kappa) - vv);
+    for (int it = threadIdx.x; it < PATCH_NP * NA / 4; it += 256) {
+      const int jl = it / (NA / 4), a = 4 * (it % (NA / 4));
+      float4 vv = first ? float4{0.f, 0.f, 0.f, 0.f}
+                        : *reinterpret_cast<const float4*>(vt + jl * NA + a);
+      *reinterpret_cast<uint2*>(WB + jl * WS + a) =
+          pack_bf16x4(2.f * soft_f(vv.x, kappa) - vv.x, 2.f * soft_f(vv.y, kappa) - vv.y,
+                      2.f * soft_f(vv.z, kappa) - vv.z, 2.f * soft_f(vv.w, kappa) - vv.w);
+    }
+    // the patch samples of the epilogue, issued before the products: rows
+    // r0 .. r0 + 3 of a block are pixels (s, a, b0 .. b0 + 3) of one patch row,
+    // four consecutive floats of x (b0 is 0 or 4, columns stay 16-byte aligned)
+    float4 xp[RB1][4];
+#pragma unroll
+    for (int rb = 0; rb < RB1; ++rb) {
+      const int r0 = 16 * (RB1 * wave + rb) + 4 * q4;
+      const int s = r0 >> 6, a = (r0 >> 3) & 7, b0 = r0 & 7;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int jl = 16 * cb + c16;
+        const int pr = (PATCH_ST * (tr * G.TPR + (jl >> G.ltpc)) + a) & (G.N1 - 1);
+        const int pc = (PATCH_ST * (tc * G.TPC + (jl & (G.TPC - 1))) + b0) & (G.N2 - 1);
+        xp[rb][cb] = *reinterpret_cast<const float4*>(x + ((size_t)s * G.N1 + pr) * G.N2 + pc);
+      }
     }
     __syncthreads();
 
-    // 1. GEMM1: acc = D w; epilogue e = P x - D w -> EB[patch][i]
-    if (wave < NV / 64) {
-      f32x16 acc[2][2];
+    // 1. GEMM1: acc = D w; epilogue e = P x - D w -> EB[patch][row]
+    {
+      f32x4 acc[RB1][4];
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int rb = 0; rb < RB1; ++rb)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
-      // the patch samples of the epilogue are loaded first (latency overlaps the products)
-      float xp[2][2][16];
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{};
+      patch_mfma<RB1, NA, WS>(acc, Dg + (size_t)16 * RB1 * wave * NA, WB, c16, q4);
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int rb = 0; rb < RB1; ++rb) {
+        const int r0 = 16 * (RB1 * wave + rb) + 4 * q4;
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          const int jl = 32 * n + l32;
-          const int pr0 = (tr * G.TPR + jl / G.TPC) * PATCH_ST;
-          const int pc0 = (tc * G.TPC + jl % G.TPC) * PATCH_ST;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-            const int s = row >> 6, a = (row >> 3) & 7, b = row & 7;
-            const int pr = (pr0 + a) & (G.N1 - 1), pc = (pc0 + b) & (G.N2 - 1);
-            xp[m][n][i] = x[((size_t)s * G.N1 + pr) * G.N2 + pc];
-          }
+        for (int cb = 0; cb < 4; ++cb) {
+          const int jl = 16 * cb + c16;
+          const float4 p = xp[rb][cb];
+          const f32x4 d = acc[rb][cb];
+          *reinterpret_cast<uint2*>(EB + jl * ES + r0) =
+              pack_bf16x4(p.x - d[0], p.y - d[1], p.z - d[2], p.w - d[3]);
         }
-      const uint16_t* Da = Dg + (size_t)(64 * wave + l32) * NA + 8 * lhi;
-#pragma unroll 4
-      for (int ks = 0; ks < NA / 16; ++ks) {
-        bf16x8 a0 = ld_bf16x8(Da + 16 * ks);
-        bf16x8 a1 = ld_bf16x8(Da + 32 * NA + 16 * ks);
-        bf16x8 b0 = ld_bf16x8(WB + l32 * WS + 16 * ks + 8 * lhi);
-        bf16x8 b1 = ld_bf16x8(WB + (32 + l32) * WS + 16 * ks + 8 * lhi);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
       }
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          const int jl = 32 * n + l32;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-            EB[jl * ES + row] = f2bf(xp[m][n][i] - acc[m][n][i]);
-          }
-        }
     }
     __syncthreads();
 
     // 2. GEMM2: acc = M1 e; z = w + acc; v <- z + clip(v); z -> WB (bf16)
-    for (int wb = wave; wb < NA / 64; wb += 4) {
-      f32x16 acc[2][2];
+    {
+      // the state of the epilogue, issued before the products
+      float4 vs[RB2][4];
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int rb = 0; rb < RB2; ++rb)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[m][n] = f32x16{};
-      // the state of the epilogue is loaded first (latency overlaps the products)
-      float vs[2][2][16];
+        for (int cb = 0; cb < 4; ++cb) {
+          const int a0 = 16 * (RB2 * wave + rb) + 4 * q4, jl = 16 * cb + c16;
+          vs[rb][cb] = first ? float4{0.f, 0.f, 0.f, 0.f}
+                             : *reinterpret_cast<const float4*>(vt + jl * NA + a0);
+        }
+      f32x4 acc[RB2][4];
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int rb = 0; rb < RB2; ++rb)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          const size_t jg = jglob(32 * n + l32);
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{};
+      patch_mfma<RB2, NV, ES>(acc, M1g + (size_t)16 * RB2 * wave * NV, EB, c16, q4);
+      // (WB may be overwritten: every wave finished GEMM1 before the barrier)
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int atom = 64 * wb + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-            vs[m][n][i] = first ? 0.f : v[(size_t)atom * J + jg];
+      for (int rb = 0; rb < RB2; ++rb) {
+        const int a0 = 16 * (RB2 * wave + rb) + 4 * q4;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const int jl = 16 * cb + c16;
+          const float4 vv = vs[rb][cb];
+          const f32x4 m = acc[rb][cb];
+          float4 z, vn;
+          z.x = (2.f * soft_f(vv.x, kappa) - vv.x) + m[0];
+          z.y = (2.f * soft_f(vv.y, kappa) - vv.y) + m[1];
+          z.z = (2.f * soft_f(vv.z, kappa) - vv.z) + m[2];
+          z.w = (2.f * soft_f(vv.w, kappa) - vv.w) + m[3];
+          vn.x = z.x + clip_f(vv.x, kappa);
+          vn.y = z.y + clip_f(vv.y, kappa);
+          vn.z = z.z + clip_f(vv.z, kappa);
+          vn.w = z.w + clip_f(vv.w, kappa);
+          *reinterpret_cast<float4*>(vt + jl * NA + a0) = vn;
+          *reinterpret_cast<uint2*>(WB + jl * WS + a0) = pack_bf16x4(z.x, z.y, z.z, z.w);
+          if constexpr (MODE == PZ_CODES) {
+            float* zp = zf + (size_t)a0 * J + j0 + jl;
+            zp[0] = z.x;
+            zp[J] = z.y;
+            zp[2 * J] = z.z;
+            zp[3 * J] = z.w;
           }
         }
-      const uint16_t* Ma = M1g + (size_t)(64 * wb + l32) * NV + 8 * lhi;
-#pragma unroll 4
-      for (int ks = 0; ks < NV / 16; ++ks) {
-        bf16x8 a0 = ld_bf16x8(Ma + 16 * ks);
-        bf16x8 a1 = ld_bf16x8(Ma + 32 * NV + 16 * ks);
-        bf16x8 b0 = ld_bf16x8(EB + l32 * ES + 16 * ks + 8 * lhi);
-        bf16x8 b1 = ld_bf16x8(EB + (32 + l32) * ES + 16 * ks + 8 * lhi);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
       }
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          const int jl = 32 * n + l32;
-          const size_t jg = jglob(jl);
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int atom = 64 * wb + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-            const float vv = vs[m][n][i];
-            const float z = (2.f * soft_f(vv, kappa) - vv) + acc[m][n][i];
-            v[(size_t)atom * J + jg] = z + clip_f(vv, kappa);
-            WB[jl * WS + atom] = f2bf(z);
-            if constexpr (MODE == PZ_CODES) zf[(size_t)atom * J + jg] = z;
-          }
-        }
     }
     if constexpr (MODE == PZ_CODES) return;
     __syncthreads();
   }
 
   // 3. GEMM3: D z, then overlap-add inside the tile
-  f32x16 acc3[2][2];
+  {
+    f32x4 acc[RB1][4];
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+    for (int rb = 0; rb < RB1; ++rb)
 #pragma unroll
-    for (int n = 0; n < 2; ++n) acc3[m][n] = f32x16{};
-  if (wave < NV / 64) {
-    const uint16_t* Da = Dg + (size_t)(64 * wave + l32) * NA + 8 * lhi;
-#pragma unroll 4
-    for (int ks = 0; ks < NA / 16; ++ks) {
-      bf16x8 a0 = ld_bf16x8(Da + 16 * ks);
-      bf16x8 a1 = ld_bf16x8(Da + 32 * NA + 16 * ks);
-      bf16x8 b0 = ld_bf16x8(WB + l32 * WS + 16 * ks + 8 * lhi);
-      bf16x8 b1 = ld_bf16x8(WB + (32 + l32) * WS + 16 * ks + 8 * lhi);
-      acc3[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc3[0][0], 0, 0, 0);
-      acc3[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc3[0][1], 0, 0, 0);
-      acc3[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc3[1][0], 0, 0, 0);
-      acc3[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc3[1][1], 0, 0, 0);
-    }
-  }
-  __syncthreads();   // WB / EB are reused as DZ below
-  if (wave < NV / 64) {
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{};
+    patch_mfma<RB1, NA, WS>(acc, Dg + (size_t)16 * RB1 * wave * NA, WB, c16, q4);
+    __syncthreads();   // WB / EB are reused as DZ below
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int rb = 0; rb < RB1; ++rb) {
+      const int r0 = 16 * (RB1 * wave + rb) + 4 * q4;
 #pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int jl = 32 * n + l32;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int row = 64 * wave + 32 * m + 8 * (i / 4) + 4 * lhi + (i % 4);
-          DZ[jl * NV + row] = acc3[m][n][i];
-        }
+      for (int cb = 0; cb < 4; ++cb) {
+        const int jl = 16 * cb + c16;
+        const f32x4 d = acc[rb][cb];
+        *reinterpret_cast<float4*>(DZ + jl * DS + r0) = float4{d[0], d[1], d[2], d[3]};
       }
+    }
   }
   __syncthreads();
-  // tile region S x RR x RC: every pixel sums its (<= 4) patches in a fixed order
-  const int RA = G.RR * G.RC;
-  float* out = tb + (size_t)tile * S * RA;
-  for (int idx = threadIdx.x; idx < S * RA; idx += 256) {
-    const int s = idx / RA, rem = idx % RA, rr = rem / G.RC, cc = rem % G.RC;
-    float sum = 0.f;
+  // tile region S x RR x RC: every pixel sums its (<= 4) patches in a fixed
+  // order; one region row per wave at a time, lanes along the row
+  const int RR = G.RR, RC = G.RC;
+  float* out = tb + (size_t)tile * S * RR * RC;
+  for (int row = wave; row < S * RR; row += 4) {
+    const int s = row / RR, rr = row - s * RR;
+    for (int cc = lane; cc < RC; cc += 64) {
+      float sum = 0.f;
 #pragma unroll
-    for (int da = 1; da >= 0; --da) {
-      const int ar = rr / PATCH_ST - da;
-      if (ar < 0 || ar >= G.TPR) continue;
-      const int a = rr - PATCH_ST * ar;
-      if (a >= PATCH_Q) continue;
+      for (int da = 1; da >= 0; --da) {
+        const int ar = (rr >> 2) - da;
+        const int a = rr - PATCH_ST * ar;
+        if (ar < 0 || ar >= G.TPR || a >= PATCH_Q) continue;
 #pragma unroll
-      for (int db = 1; db >= 0; --db) {
-        const int ac = cc / PATCH_ST - db;
-        if (ac < 0 || ac >= G.TPC) continue;
-        const int b = cc - PATCH_ST * ac;
-        if (b >= PATCH_Q) continue;
-        sum += DZ[(ar * G.TPC + ac) * NV + s * 64 + a * 8 + b];
+        for (int db = 1; db >= 0; --db) {
+          const int ac = (cc >> 2) - db;
+          const int b = cc - PATCH_ST * ac;
+          if (ac < 0 || ac >= G.TPC || b >= PATCH_Q) continue;
+          sum += DZ[(ar * G.TPC + ac) * DS + s * 64 + a * 8 + b];
+        }
       }
+      out[row * RC + cc] = sum;
     }
-    out[idx] = sum;
   }
 }
 
