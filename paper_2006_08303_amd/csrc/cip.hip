@@ -511,8 +511,8 @@ hipError_t admm_col(cip_plan_t p, int zero_in, int dct_out, hipStream_t st) {
 //   x-update (Eq. solx_synt_DFT): row FFT of r = P^T D~ z^{l-1} (r = 0 for
 //   l = 1), column FFT + per-frequency solve + inverse column FFT, inverse
 //   row FFT -> x^l (written to d_x);
-//   for l < L: sparse-code update, soft threshold and dual update on MFMA
-//   (k_patch_z), then r = P^T D~ z^l (k_patch_assemble).
+//   for l < L: sparse-code update, soft threshold, dual update and the
+//   tiles' D z on MFMA (k_patch_z), then r = P^T D~ z^l (k_patch_assemble).
 //   With a learned dictionary the code update writes z in FP32 and skips
 //   D z; one step of the dictionary ADMM follows (D, G, E and the BF16
 //   tables of G), then D z with the new G.

@@ -3,6 +3,7 @@
 #include "patch.hpp"
 #include "patch_dl.hpp"
 #include "patch_launch.hpp"
+#include "sizes.hpp"
 
 namespace cip {
 
@@ -37,7 +38,7 @@ hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, co
 
 hipError_t patch_assemble_launch(int S, const float* tb, float* r, int N1, int N2, hipStream_t st) {
   const PatchGeo G = patch_geo(N1, N2);
-  hipLaunchKernelGGL(k_patch_assemble, dim3((N2 + 255) / 256, N1, S), dim3(256), 0, st, tb, r, S,
+  hipLaunchKernelGGL(k_patch_assemble, dim3((N2 / 4 + 63) / 64, N1, S), dim3(64), 0, st, tb, r, S,
                      G);
   return hipGetLastError();
 }

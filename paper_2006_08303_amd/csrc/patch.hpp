@@ -74,16 +74,18 @@ __host__ __device__ inline PatchGeo patch_geo(int N1, int N2) {
   return g;
 }
 
-// LDS of k_patch_z: WB [64][NA + 8] bf16 (w, then z) and EB [64][NV + 8]
-// bf16 (e), the B operands of the products (rows 16-byte aligned, the pad
-// spreads consecutive patches over the banks); after the last product both
-// are reused for DZ [64][NV + 4] float (D z of every patch).
+// LDS of k_patch_z: one region holding in turn WB [64][NA + 8] bf16 (w),
+// EB [64][NV + 8] bf16 (e) and WB again (z), the B operands of the three
+// products (rows 16-byte aligned, the pad spreads consecutive patches over
+// the banks), and finally DZ [64][NV + 4] float (D z of every patch). At
+// S = 3, A = 256 that is 50 KB, three work-groups per CU.
 template <int S, int NA> constexpr int patch_lds_bytes() {
   constexpr int NV = 64 * S;
   constexpr int wb = PATCH_NP * (NA + 8) * 2;
   constexpr int eb = PATCH_NP * (NV + 8) * 2;
   constexpr int dz = PATCH_NP * (NV + 4) * 4;
-  return wb + eb > dz ? wb + eb : dz;
+  constexpr int m = wb > eb ? wb : eb;
+  return m > dz ? m : dz;
 }
 
 // What k_patch_z runs: the whole update (codes, state, D z), only the codes
@@ -97,27 +99,40 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
 }
 
 // One product C (RB blocks of 16 rows of A, all 64 patches) += A B over K:
-// A rows from global memory (bf16, row stride K), B from LDS (patch rows of
-// stride BS, K contiguous). Lane l holds A row (l % 16) and B column (l % 16)
-// at k = 8 (l / 16) .. + 7 of every 32-wide k step; C block (rb, cb) holds
-// rows 4 (l / 16) + i (i < 4) of column l % 16.
+// A rows from global memory (bf16, row stride K; the dictionary tables stay
+// in L2), B from LDS (patch rows of stride BS, K contiguous). Lane l holds A
+// row (l % 16) and B column (l % 16) at k = 8 (l / 16) .. + 7 of every
+// 32-wide k step; C block (rb, cb) holds rows 4 (l / 16) + i (i < 4) of
+// column l % 16. The A operands are loaded PF k steps ahead (a ring of
+// PF + 1 register sets) so that the L2 latency overlaps the products.
 template <int RB, int K, int BS>
 __device__ __forceinline__ void patch_mfma(f32x4 (&acc)[RB][4], const uint16_t* __restrict__ A,
                                            const uint16_t* B, int c16, int q4) {
+  constexpr int KS = K / 32;
+  constexpr int PF = KS < 2 ? KS : 2;
   const uint16_t* Ar = A + (size_t)c16 * K + 8 * q4;
   const uint16_t* Br = B + c16 * BS + 8 * q4;
-#pragma unroll 2
-  for (int ks = 0; ks < K / 32; ++ks) {
-    bf16x8 a[RB], b[4];
+  bf16x8 a[PF + 1][RB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a[rb] = ld_bf16x8(Ar + (size_t)rb * 16 * K + 32 * ks);
+  for (int p = 0; p < PF; ++p)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) a[p][rb] = ld_bf16x8(Ar + (size_t)rb * 16 * K + 32 * p);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks + PF < KS) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        a[(ks + PF) % (PF + 1)][rb] = ld_bf16x8(Ar + (size_t)rb * 16 * K + 32 * (ks + PF));
+    }
+    bf16x8 b[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) b[cb] = ld_bf16x8(Br + cb * 16 * BS + 32 * ks);
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks % (PF + 1)][rb], b[cb], acc[rb][cb], 0, 0, 0);
   }
 }
 
@@ -141,7 +156,7 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
   static_assert(NA % 64 == 0, "atoms must be a multiple of 64");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint16_t* WB = reinterpret_cast<uint16_t*>(smem_raw);
-  uint16_t* EB = WB + PATCH_NP * WS;
+  uint16_t* EB = WB;   // e replaces w once every wave has finished GEMM1
   float* DZ = reinterpret_cast<float*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c16 = lane & 15, q4 = lane >> 4;
@@ -197,6 +212,7 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{};
       patch_mfma<RB1, NA, WS>(acc, Dg + (size_t)16 * RB1 * wave * NA, WB, c16, q4);
+      __syncthreads();   // every wave has read w: e overwrites it
 #pragma unroll
       for (int rb = 0; rb < RB1; ++rb) {
         const int r0 = 16 * (RB1 * wave + rb) + 4 * q4;
@@ -230,7 +246,7 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{};
       patch_mfma<RB2, NV, ES>(acc, M1g + (size_t)16 * RB2 * wave * NV, EB, c16, q4);
-      // (WB may be overwritten: every wave finished GEMM1 before the barrier)
+      __syncthreads();   // every wave has read e: z overwrites it
 #pragma unroll
       for (int rb = 0; rb < RB2; ++rb) {
         const int a0 = 16 * (RB2 * wave + rb) + 4 * q4;
@@ -286,13 +302,17 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
   }
   __syncthreads();
   // tile region S x RR x RC: every pixel sums its (<= 4) patches in a fixed
-  // order; one region row per wave at a time, lanes along the row
+  // order (patch row rr / 4 - 1 before rr / 4, patch column cc / 4 - 1
+  // before cc / 4). One region row per wave at a time (the patch rows are
+  // then wave-uniform); each lane forms four consecutive pixels 4 c4 ..
+  // 4 c4 + 3, which share their patches: columns 4..7 of patch c4 - 1 and
+  // 0..3 of patch c4, one float4 each.
   const int RR = G.RR, RC = G.RC;
   float* out = tb + (size_t)tile * S * RR * RC;
   for (int row = wave; row < S * RR; row += 4) {
     const int s = row / RR, rr = row - s * RR;
-    for (int cc = lane; cc < RC; cc += 64) {
-      float sum = 0.f;
+    for (int c4 = lane; c4 < RC / 4; c4 += 64) {
+      float4 sum = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int da = 1; da >= 0; --da) {
         const int ar = (rr >> 2) - da;
@@ -300,33 +320,38 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
         if (ar < 0 || ar >= G.TPR || a >= PATCH_Q) continue;
 #pragma unroll
         for (int db = 1; db >= 0; --db) {
-          const int ac = (cc >> 2) - db;
-          const int b = cc - PATCH_ST * ac;
-          if (ac < 0 || ac >= G.TPC || b >= PATCH_Q) continue;
-          sum += DZ[(ar * G.TPC + ac) * DS + s * 64 + a * 8 + b];
+          const int ac = c4 - db;
+          if (ac < 0 || ac >= G.TPC) continue;
+          const float4 q = *reinterpret_cast<const float4*>(
+              DZ + (ar * G.TPC + ac) * DS + s * 64 + a * 8 + 4 * db);
+          sum.x += q.x;
+          sum.y += q.y;
+          sum.z += q.z;
+          sum.w += q.w;
         }
       }
-      out[row * RC + cc] = sum;
+      *reinterpret_cast<float4*>(out + row * RC + 4 * c4) = sum;
     }
   }
 }
 
 // r = P^T D~ z: every pixel sums the tiles whose regions cover it (its own
 // tile and, within Q - st pixels of a tile edge, the previous tile along that
-// axis, circularly), in a fixed order.
-// Thread (C, R, s) of a 3D grid (no index division).
+// axis, circularly), in a fixed order. Thread (C4, R, s) of a 3D grid handles
+// the four columns 4 C4 .. 4 C4 + 3, which always have the same covering
+// tiles (tile widths and region strides are multiples of 4), as float4.
 __global__ void k_patch_assemble(const float* __restrict__ tb, float* __restrict__ r, int S,
                                  PatchGeo G) {
-  const int C = blockIdx.x * blockDim.x + threadIdx.x;
-  if (C >= G.N2) return;
-  const int R = blockIdx.y, s = blockIdx.z;
+  const int C4 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (4 * C4 >= G.N2) return;
+  const int C = 4 * C4, R = blockIdx.y, s = blockIdx.z;
   const size_t idx = ((size_t)s * G.N1 + R) * G.N2 + C;
   const int TH = PATCH_ST * G.TPR, TW = PATCH_ST * G.TPC;
   const int ntr = G.J1 / G.TPR;
   const int RA = G.RR * G.RC;
   const int tr0 = R / TH, lr0 = R - tr0 * TH;
   const int tc0 = C / TW, lc0 = C - tc0 * TW;
-  float sum = 0.f;
+  float4 sum = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int dr = 0; dr < 2; ++dr) {
     if (dr == 1 && lr0 >= PATCH_Q - PATCH_ST) break;
@@ -338,10 +363,14 @@ __global__ void k_patch_assemble(const float* __restrict__ tb, float* __restrict
       const int tc = dc ? (tc0 + G.ntc - 1) % G.ntc : tc0;
       const int lc = dc ? lc0 + TW : lc0;
       const size_t t = (size_t)tr * G.ntc + tc;
-      sum += tb[(t * S + s) * RA + lr * G.RC + lc];
+      const float4 q = *reinterpret_cast<const float4*>(tb + (t * S + s) * RA + lr * G.RC + lc);
+      sum.x += q.x;
+      sum.y += q.y;
+      sum.z += q.z;
+      sum.w += q.w;
     }
   }
-  r[idx] = sum;
+  *reinterpret_cast<float4*>(r + idx) = sum;
 }
 
 }  // namespace cip
