@@ -276,6 +276,22 @@ struct cip_plan_s {
   int row_ppt;          // points per thread of the analysis row passes (default or 8)
   int tv_inner;         // isotropic TV: Chambolle iterations per ADMM iteration
   int wt_levels;        // wavelet (x) DCT: levels of the 2D wavelet transform
+  // analysis priors: the iteration loop of a solve (iterations 2 .. iters)
+  // captured into a hipGraph once the plan has been solved twice in a row
+  // with the same iteration count; rebuilt when that count or the row-pass
+  // shape changes
+  hipGraph_t loop_graph = nullptr;
+  hipGraphExec_t loop_exec = nullptr;
+  int loop_iters = 0;   // iteration count the graph was captured for (0: none)
+  int last_iters = 0;   // iteration count of the previous solve
+  void drop_loop_graph() {
+    if (loop_exec) (void)hipGraphExecDestroy(loop_exec);
+    if (loop_graph) (void)hipGraphDestroy(loop_graph);
+    loop_exec = nullptr;
+    loop_graph = nullptr;
+    loop_iters = 0;
+  }
+  ~cip_plan_s() { drop_loop_graph(); }
   template <typename T> T* at(size_t off) const {
     return reinterpret_cast<T*>((off & STATE_BIT) ? sws + (off & ~STATE_BIT) : ws + off);
   }
@@ -902,6 +918,64 @@ void patch_dictionary_tables(const std::vector<float>& D, int nv, int na, double
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
+namespace {
+
+// Iterations 2 .. iters of Algorithm 1 (row pass, column pass), all on the
+// plan's own buffers.
+hipError_t loop_kernels(cip_plan_t p, int iters, hipStream_t st) {
+  for (int l = 1; l < iters; ++l) {
+    hipError_t e = admm_row(p, l, st);
+    if (e != hipSuccess) return e;
+    e = admm_col(p, 0, l < iters - 1 ? 1 : 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The loop launched directly, or, from the second solve in a row with the
+// same iteration count, replayed from a hipGraph captured once (the loop's
+// kernels read and write only plan buffers, so the graph stays valid for
+// every later solve with that count). A stream that is itself being
+// captured (a batch graph) gets the kernels directly.
+int analysis_loop(cip_plan_t p, int iters, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cs));
+  const bool repeat = p->last_iters == iters;
+  p->last_iters = iters;
+  if (cs != hipStreamCaptureStatusNone || !repeat) {
+    HIP_TRY(loop_kernels(p, iters, st));
+    return CIP_OK;
+  }
+  if (p->loop_iters != iters) {
+    p->drop_loop_graph();
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    hipError_t e2 = e == hipSuccess ? loop_kernels(p, iters, cap) : hipSuccess;
+    hipGraph_t g = nullptr;
+    hipError_t e3 = e == hipSuccess ? hipStreamEndCapture(cap, &g) : hipSuccess;
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      HIP_TRY(loop_kernels(p, iters, st));   // fall back to direct launches
+      return CIP_OK;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      HIP_TRY(loop_kernels(p, iters, st));
+      return CIP_OK;
+    }
+    p->loop_graph = g;
+    p->loop_exec = x;
+    p->loop_iters = iters;
+  }
+  HIP_TRY(hipGraphLaunch(p->loop_exec, st));
+  return CIP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* cip_last_error(void) { return g_last_error.c_str(); }
@@ -1154,9 +1228,9 @@ int cip_solve(cip_plan_t p, const float* d_y, int iters, float* d_x, void* strea
   }
   // iteration 1 (t = u = 0): column pass only
   HIP_TRY(admm_col(p, 1, iters > 1 ? 1 : 0, st));
-  for (int l = 1; l < iters; ++l) {
-    HIP_TRY(admm_row(p, l, st));
-    HIP_TRY(admm_col(p, 0, l < iters - 1 ? 1 : 0, st));
+  if (iters > 1) {
+    int rc = analysis_loop(p, iters, st);
+    if (rc) return rc;
   }
   HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
   p->solved_once = true;
@@ -1296,6 +1370,12 @@ int cip_plan_attach(cip_plan_t base, void* d_state, size_t bytes, cip_plan_t* ou
     return fail(CIP_EINVAL, "state buffer must be 256-byte aligned");
   if (bytes < base->L.state_bytes) return fail(CIP_ENOSPC, "state buffer too small");
   cip_plan_s* p = new cip_plan_s(*base);
+  // the copy must not share the base plan's captured loop (it holds the
+  // base's state addresses)
+  p->loop_graph = nullptr;
+  p->loop_exec = nullptr;
+  p->loop_iters = 0;
+  p->last_iters = 0;
   p->sws = reinterpret_cast<unsigned char*>(d_state);
   p->solved_once = false;
   p->attached = true;
@@ -1568,6 +1648,7 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   if (!(row_np == PAIRS || row_np == 2)) return fail(CIP_EINVAL, "row_np must be 4 or 2");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))
     return fail(CIP_EINVAL, "row_ppt must be the default or 8 (power-of-two N2)");
+  if (p->row_np != row_np || p->row_ppt != row_ppt) p->drop_loop_graph();
   p->row_np = row_np;
   p->row_ppt = row_ppt;
   return CIP_OK;

@@ -181,3 +181,29 @@ def test_tv2d_full_size_1024():
     err = admm.rel_l2(got, ref)
     print(f"1024^2 TV2D 3 iters: rel_l2 = {err:.3e}", flush=True)
     parity.check(got, ref, 1e-4)
+
+
+@pytest.mark.parametrize("prior", ["dct2d", "tv2d", "tv3d"])
+def test_replayed_iteration_loop_equals_direct_solve(prior):
+    """From the second solve in a row with the same iteration count the
+    analysis loop is replayed from a captured graph: every replay (also after
+    a solve with another count and after a change of the row-pass shape) is
+    bitwise equal to the first, directly launched solve, and matches the
+    oracle."""
+    N, K, S = 128, 3, 3
+    x, psf, y = _problem("smooth_disk", N, K, S, 2)
+    lam, rho = (1e-2, 0.1) if prior == "dct2d" else (1e-3, 1e-2)
+    plan = cip.Plan(_t(psf), prior, rho, lam, 1.0)
+    yt = _t(y)
+    first = _np(plan.solve(yt, 15))
+    for it in (15, 15, 7, 15, 15):
+        got = _np(plan.solve(yt, it))
+        if it == 15:
+            assert np.array_equal(got, first)
+    plan.set_tuning(2, 16)
+    ref_shape = _np(plan.solve(yt, 15))
+    assert np.array_equal(_np(plan.solve(yt, 15)), ref_shape)
+    assert np.array_equal(_np(plan.solve(yt, 15)), ref_shape)
+    ref = admm.AnalysisADMM(psf, prior, lam, rho, 1.0, tier="freq").run(y, 15)[0]
+    parity.check(first, ref, 1e-4, label=f"{prior} direct")
+    parity.check(ref_shape, ref, 1e-4, label=f"{prior} half tiles, replayed")
