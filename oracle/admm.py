@@ -222,6 +222,17 @@ class PatchADMM:
         A = self.D.shape[1]
         self.zgram = self.rho * np.eye(A) + self.D.T @ self.D     # rho I + D^T D
 
+    def set_rho(self, rho):
+        """Penalty rho of the code split (the z-update matrix depends on it)."""
+        self.rho = float(rho)
+        self.set_dictionary(self.D)
+
+    def run_adaptive(self, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-4,
+                     adapt_sigma=False):
+        """Algorithm 2 with the penalty update and stopping rule of Section
+        IV-C; see ``synthesis_run_adaptive``."""
+        return synthesis_run_adaptive(self, y, max_iters, tau, mu, every, tol, adapt_sigma)
+
     def d_update_patches(self, X, z):
         """Eq. sold_patch: D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1
         for patch matrix X (n x J) and codes Z (A x J); the system matrix
@@ -252,12 +263,16 @@ class PatchADMM:
         rhs = self.D.T @ self.P.extract(x) + self.rho * (t - u)
         return np.linalg.solve(self.zgram, rhs)
 
-    def run(self, y, iters, callback=None):
+    def run(self, y, iters, callback=None, state=None):
+        """Run ``iters`` iterations from z = t = u = 0 (or from ``state`` =
+        (z, t, u)). Returns (x, z, t, u)."""
         data = self.solver.data_term(y)
         A = self.D.shape[1]
         z = np.zeros((A, self.P.J))
         t = np.zeros_like(z)
         u = np.zeros_like(z)
+        if state is not None:
+            z, t, u = (np.array(a, dtype=np.float64) for a in state)
         kappa = self.lam / self.rho
         x = None
         for it in range(iters):
@@ -405,11 +420,25 @@ class ConvADMM:
         self.cd.h = g
         self.theta = self.cd.spectra()
 
-    def run(self, y, iters, callback=None):
+    def set_rho(self, rho):
+        """Penalty rho of the code split (used directly by the z-update)."""
+        self.rho = float(rho)
+
+    def run_adaptive(self, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-4,
+                     adapt_sigma=False):
+        """Algorithm 2 with the penalty update and stopping rule of Section
+        IV-C; see ``synthesis_run_adaptive``."""
+        return synthesis_run_adaptive(self, y, max_iters, tau, mu, every, tol, adapt_sigma)
+
+    def run(self, y, iters, callback=None, state=None):
+        """Run ``iters`` iterations from z = t = u = 0 (or from ``state`` =
+        (z, t, u)). Returns (x, z, t, u)."""
         data = self.solver.data_term(y)
         z = np.zeros((self.M, self.S, self.N1, self.N2))
         t = np.zeros_like(z)
         u = np.zeros_like(z)
+        if state is not None:
+            z, t, u = (np.array(a, dtype=np.float64) for a in state)
         kappa = self.lam / self.rho
         x = None
         for it in range(iters):
@@ -429,6 +458,92 @@ class ConvADMM:
             if callback is not None:
                 callback(it, x, z, t, u)
         return x, z, t, u
+
+
+def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-4,
+                           adapt_sigma=False):
+    """Algorithm 2 (patch or convolutional dictionary) with the penalty update
+    and stopping rule of Section IV-C (Eq. paramS). The split is z = t, so at
+    every `every`-th iteration l < max_iters, after the t- and u-updates:
+      r = ||z^l - t^l||,  s = rho ||t^l - t^{l-1}||;
+      stop (returning x^l) if ||x^l - x^{l-1}|| / ||x^{l-1}|| < tol;
+      rho <- tau rho if r > mu s, rho / tau if s > mu r; on a change the
+      scaled dual is rescaled, u <- u rho_old / rho_new, and the code update
+      is rebuilt for the new rho (its threshold lambda / rho too).
+    With online dictionary learning and adapt_sigma (the paper applies the
+    same strategy to sigma in the dictionary update), after the D, G, E step
+    of a checked iteration:
+      r_d = ||D - G||,  s_d = sigma ||G - G_prev||;
+      sigma <- tau sigma if r_d > mu s_d, sigma / tau if s_d > mu r_d, and
+      the scaled dual E is rescaled by sigma_old / sigma_new.
+    The object is left with its starting rho and sigma (and dictionary: the
+    learned one, as after ``run``). Returns (x, info), info = dict(iters,
+    rho, rhos, sigma, sigmas, rel_change, r, s)."""
+    rho0 = alg.rho
+    learn = getattr(alg, "dict_update", False)
+    sig0 = alg.sigma if learn else None
+    data = alg.solver.data_term(y)
+    zshape = (alg.D.shape[1], alg.P.J) if hasattr(alg, "P") else \
+        (alg.M, alg.S, alg.N1, alg.N2)
+    z = np.zeros(zshape)
+    t = np.zeros(zshape)
+    u = np.zeros(zshape)
+    x_prev, x = None, None
+    rhos, sigmas = [alg.rho], ([alg.sigma] if learn else [])
+    info = {"rel_change": None, "r": None, "s": None}
+    it = 0
+    for it in range(1, max_iters + 1):
+        x = alg.x_update(data, z)
+        z = alg.z_update(x, t, u)
+        kappa = alg.lam / alg.rho
+        t_new = priors.soft(z + u, kappa)
+        u_new = u + z - t_new
+        check = it % every == 0 and it < max_iters   # the last iterate is returned anyway
+        if check:
+            r = float(np.linalg.norm(z - t_new))
+            s_ = alg.rho * float(np.linalg.norm(t_new - t))
+            info["r"], info["s"] = r, s_
+            if x_prev is not None:
+                rel = float(np.linalg.norm(x - x_prev) / np.linalg.norm(x_prev))
+                info["rel_change"] = rel
+                if rel < tol:
+                    break
+            new = alg.rho
+            if r > mu * s_:
+                new = tau * alg.rho
+            elif s_ > mu * r:
+                new = alg.rho / tau
+            if new != alg.rho:
+                u_new = u_new * (alg.rho / new)
+                alg.set_rho(new)
+            rhos.append(alg.rho)
+        t, u = t_new, u_new
+        if learn:
+            g_prev = alg.g
+            d = alg.d_update(x, z)
+            g = alg.g_update(d)
+            alg.e = alg.e + g - d
+            alg.g = g
+            if check and adapt_sigma:
+                rd = float(np.linalg.norm(d - g))
+                sd = alg.sigma * float(np.linalg.norm(g - g_prev))
+                new = alg.sigma
+                if rd > mu * sd:
+                    new = tau * alg.sigma
+                elif sd > mu * rd:
+                    new = alg.sigma / tau
+                if new != alg.sigma:
+                    alg.e = alg.e * (alg.sigma / new)
+                    alg.sigma = new
+                sigmas.append(alg.sigma)
+            alg.set_dictionary(g)
+        x_prev = x
+    info.update(iters=it, rho=alg.rho, rhos=rhos,
+                sigma=alg.sigma if learn else None, sigmas=sigmas)
+    alg.set_rho(rho0)
+    if learn:
+        alg.sigma = sig0
+    return x, info
 
 
 def psnr(x, ref, peak=1.0):

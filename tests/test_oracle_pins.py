@@ -1110,3 +1110,78 @@ def test_symmlet8_is_the_least_asymmetric_daubechies_factor():
     assert found[2][0] > found[0][0] + 0.03       # a clear margin to the next pair
     assert any(np.max(np.abs(h - priors.SYM8)) < 1e-10 for h in best)
     assert int(np.argmax(priors.SYM8)) == 7
+
+
+# ---------------------------------------------------------------- adaptive penalty, Algorithm 2
+def _synth_algs(seed, learn=False, sigma=1.0):
+    """A small patch problem and a small 2D convolutional-dictionary problem."""
+    S, N = 2, 8
+    x0, psf = _small_problem(K=2, S=S, N1=N, N2=N, seed=seed)
+    y = model.forward(x0, psf) + 0.01 * _rng(seed + 100).standard_normal((2, N, N))
+    D = synth.random_unit_atoms(_rng(seed + 1), 4 * 4 * S, 40)
+    filt = synth.random_unit_filters(_rng(seed + 2), 4, 3)
+
+    def patch(rho):
+        return admm.PatchADMM(psf, D, 4, 2, 1e-3, rho, 10.0, tier="freq", dict_update=learn,
+                              sigma=sigma)
+
+    def conv(rho):
+        return admm.ConvADMM(psf, filt, 1e-3, rho, 8.0, tier="freq", dict_update=learn,
+                             sigma=sigma)
+    return y, patch, conv
+
+
+@pytest.mark.parametrize("learn", [False, True])
+def test_synthesis_adaptive_without_changes_equals_run(learn):
+    """With the balance factor so large that neither rho nor sigma changes
+    and no stopping, the adaptive run is Algorithm 2 (with its dictionary
+    steps) at fixed penalties."""
+    y, patch, conv = _synth_algs(50, learn=learn)
+    for make in (patch, conv):
+        xa, info = make(0.3).run_adaptive(y, 12, mu=1e30, every=1, tol=0.0, adapt_sigma=True)
+        xr = make(0.3).run(y, 12)[0]
+        assert info["iters"] == 12 and info["rhos"] == [0.3] * 12
+        if learn:
+            assert info["sigmas"] == [1.0] * 12
+        assert np.array_equal(xa, xr)
+
+
+def test_synthesis_rescaling_keeps_the_fixed_point():
+    """Near a fixed point of Algorithm 2 with penalty rho, switching to rho'
+    with the scaled dual rescaled by rho / rho' keeps the iterate within the
+    drift of two more iterations at rho (rho' u' = rho u leaves the code and
+    threshold updates at their fixed point); the opposite rescaling moves it
+    ten (conv) to fifty (patch) times further (patch and convolutional
+    dictionaries). Two
+    iterations: the next x depends on the codes only, the dual acts through
+    the code update after it."""
+    y, patch, conv = _synth_algs(51)
+    rho, rho2 = 0.3, 0.6
+    for make in (patch, conv):
+        x, z, t, u = make(rho).run(y, 4000)
+        drift = np.linalg.norm(make(rho).run(y, 2, state=(z, t, u))[0] - x)
+        nxt = make(rho2)
+        x_ok = nxt.run(y, 2, state=(z, t, u * rho / rho2))[0]
+        x_bad = nxt.run(y, 2, state=(z, t, u * rho2 / rho))[0]
+        assert np.linalg.norm(x_ok - x) < 2.0 * drift
+        assert np.linalg.norm(x_bad - x) > 5.0 * drift
+
+
+def test_synthesis_adaptive_moves_rho_and_stops():
+    """From a poor penalty in either direction the adaptive run changes rho
+    the right way first (up from a tiny rho, where the primal residual
+    dominates; down from a huge one), and with the paper's tolerance it stops
+    at the first check whose relative change is below it: one check earlier
+    the change was still above. (The codes of the synthesis problem are not
+    unique, so the limit itself is not pinned here.)"""
+    y, patch, conv = _synth_algs(52)
+    for make in (patch, conv):
+        for rho0, first in ((1e-4, 2.0), (1e3, 0.5)):
+            alg = make(rho0)
+            x, info = alg.run_adaptive(y, 5000, every=1, tol=1e-4)
+            changes = [b / a for a, b in zip(info["rhos"], info["rhos"][1:]) if b != a]
+            assert changes and changes[0] == first
+            assert info["iters"] < 5000 and info["rel_change"] < 1e-4
+            assert alg.rho == rho0
+            _, info2 = make(rho0).run_adaptive(y, info["iters"], every=1, tol=0.0)
+            assert info2["rel_change"] >= 1e-4      # its last check is at iters - 1
