@@ -478,7 +478,8 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
       the scaled dual E is rescaled by sigma_old / sigma_new.
     The object is left with its starting rho and sigma (and dictionary: the
     learned one, as after ``run``). Returns (x, info), info = dict(iters,
-    rho, rhos, sigma, sigmas, rel_change, r, s)."""
+    rho, rhos, sigma, sigmas, rel_change, r, s, trace = [(l, r, s, c)] of the
+    checks)."""
     rho0 = alg.rho
     learn = getattr(alg, "dict_update", False)
     sig0 = alg.sigma if learn else None
@@ -490,7 +491,7 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
     u = np.zeros(zshape)
     x_prev, x = None, None
     rhos, sigmas = [alg.rho], ([alg.sigma] if learn else [])
-    info = {"rel_change": None, "r": None, "s": None}
+    info = {"rel_change": None, "r": None, "s": None, "trace": []}
     it = 0
     for it in range(1, max_iters + 1):
         x = alg.x_update(data, z)
@@ -503,11 +504,13 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
             r = float(np.linalg.norm(z - t_new))
             s_ = alg.rho * float(np.linalg.norm(t_new - t))
             info["r"], info["s"] = r, s_
+            rel = None
             if x_prev is not None:
                 rel = float(np.linalg.norm(x - x_prev) / np.linalg.norm(x_prev))
                 info["rel_change"] = rel
-                if rel < tol:
-                    break
+            info["trace"].append((it, r, s_, rel))
+            if rel is not None and rel < tol:
+                break
             new = alg.rho
             if r > mu * s_:
                 new = tau * alg.rho

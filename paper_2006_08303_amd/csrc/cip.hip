@@ -58,6 +58,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // Plans attached to a built plan (cip_plan_attach) share its tables and have
 // a state region of their own.
 constexpr size_t STATE_BIT = size_t(1) << 62;
+constexpr int XCHANGE_GROUPS = 256;   // work-groups of k_xchange
 
 struct Layout {
   size_t twN1f, twN2f, twN1d, twN2d;  // FFT twiddles
@@ -132,11 +133,19 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   L.bufB = sta(P * F * 8);
   L.state = sta((size_t)state_floats_per_voxel(kind) * S * N1 * N2 * 4);
   const bool adaptive = (prior->flags & CIP_PLAN_ADAPTIVE) != 0;
+  const bool synthesis = kind == CIP_PRIOR_PATCH || kind == CIP_PRIOR_CONV2D ||
+                         kind == CIP_PRIOR_CONV3D;
   // the FP64 spectra stay resident when the penalty may change during a solve
-  L.lam64 = adaptive ? tab((size_t)K * S * F * 16) : scr((size_t)K * S * F * 16);
+  // (analysis priors: Psi depends on rho; the synthesis x-update does not)
+  L.lam64 = adaptive && !synthesis ? tab((size_t)K * S * F * 16) : scr((size_t)K * S * F * 16);
   if (adaptive) {
     L.xbuf = sta((size_t)2 * S * N1 * N2 * 4);      // x^(l-1), x^l of the checks
-    L.sums = sta((size_t)S * (N1 / 8) * 4 * 4);     // norm-pass partial sums
+    size_t nsum = (size_t)S * (N1 / 8) * 4;         // norm-pass partial sums
+    if (kind == CIP_PRIOR_PATCH) {
+      const size_t ps = patch_z_residual_floats(N1, N2) + 2 * XCHANGE_GROUPS;
+      if (ps > nsum) nsum = ps;
+    }
+    L.sums = sta(nsum * 4);
   }
   L.rt64 = scr(F * 16);
   L.pl64 = scr((size_t)N1 * N2 * 8);
@@ -276,6 +285,7 @@ struct cip_plan_s {
   int row_ppt;          // points per thread of the analysis row passes (default or 8)
   int tv_inner;         // isotropic TV: Chambolle iterations per ADMM iteration
   int wt_levels;        // wavelet (x) DCT: levels of the 2D wavelet transform
+  std::vector<float> dict_host;   // patch prior with CIP_PLAN_ADAPTIVE: D, to rebuild M1
   // analysis priors: the iteration loop of a solve (iterations 2 .. iters)
   // captured into a hipGraph once the plan has been solved twice in a row
   // with the same iteration count; rebuilt when that count or the row-pass
@@ -602,6 +612,106 @@ hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
     if (l < iters && (e = patch_step(p, d_x, l == 1 ? 1 : 0, st)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Algorithm 2 with the patch prior and the penalty update and stopping rule
+// of Section IV-C (Eq. paramS), the split z = t: at every `every`-th
+// iteration l < max_iters, after the code, t and u updates,
+//   r = ||z^l - t^l||, s = rho ||t^l - t^(l-1)|| (summed by the code update),
+//   c = ||x^l - x^(l-1)|| / ||x^(l-1)|| (k_xchange; x^l is in d_x);
+// stop with x^l when c < tol, else change rho by tau when one residual
+// exceeds mu times the other: the state is re-expressed for the new penalty
+// (u scaled by rho / rho') and M1 = D^T (rho' I + D D^T)^-1 is rebuilt in FP64
+// on the host. The plan's tables are back at its own rho on return.
+void patch_dictionary_tables(const std::vector<float>& D, int nv, int na, double rho,
+                             std::vector<uint16_t>& dbf, std::vector<uint16_t>& m1bf);
+
+int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x, hipStream_t st,
+                         cip_solve_info& out) {
+  const Layout& L = p->L;
+  const int iters = prm->max_iters, every = prm->every;
+  const int nv = 64 * p->S, na = p->n_atoms;
+  const double rho0 = p->rho;
+  double rho = rho0;
+  const size_t nres = patch_z_residual_floats(p->N1, p->N2);
+  float* rs = p->at<float>(L.sums);
+  float* xs = rs + nres;
+  float* xprev = p->at<float>(L.xbuf);
+  const size_t nx = (size_t)p->S * p->N1 * p->N2;
+  const size_t ncode = (size_t)na * (p->N1 / 4) * (p->N2 / 4);
+  std::vector<float> hs(nres + 2 * XCHANGE_GROUPS);
+  auto set_m1 = [&](double r) -> int {
+    std::vector<uint16_t> dbf, m1bf;
+    patch_dictionary_tables(p->dict_host, nv, na, r, dbf, m1bf);
+    HIP_TRY(hipMemcpyAsync(p->at<void>(L.m1bf), m1bf.data(), m1bf.size() * 2,
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // m1bf is host memory of this scope
+    return CIP_OK;
+  };
+  int rc = CIP_OK;
+  for (int l = 1;; ++l) {
+    // x-update (Eq. solx_synt_DFT) -> x^l in d_x
+    if (l > 1)
+      HIP_TRY(row_r2c<float>(p->at<const float>(L.rimg), p->at<cx<float>>(L.bufA), p->S, p->N1,
+                             p->N2, p->at<const cx<float>>(L.twN2f), st));
+    HIP_TRY(admm_col(p, l == 1 ? 1 : 0, 0, st));
+    HIP_TRY(row_c2r(p->at<const cx<float>>(L.bufB), d_x, p->S, p->N1, p->N2, 1.0f,
+                    p->at<const cx<float>>(L.twN2f), st));
+    if (l == iters) {
+      out.iters = l;
+      break;
+    }
+    const bool check = l % every == 0;
+    const bool store = (l + 1) % every == 0;
+    const float kappa = (float)(p->lambda / rho);
+    HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf),
+                           p->at<const uint16_t>(L.dbf), p->at<const uint16_t>(L.m1bf), p->N1,
+                           p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_FULL, nullptr,
+                           check ? rs : nullptr));
+    HIP_TRY(patch_assemble_launch(p->S, p->at<const float>(L.tbuf), p->at<float>(L.rimg), p->N1,
+                                  p->N2, st));
+    if (check || store)
+      HIP_TRY(launch(k_xchange, XCHANGE_GROUPS, 256, 0, st, (const float*)d_x, xprev, xs, nx,
+                     check && l > 1 ? 1 : 0));
+    if (!check) continue;
+    HIP_TRY(hipMemcpyAsync(hs.data(), rs, hs.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double r2 = 0.0, s2 = 0.0, d2 = 0.0, p2 = 0.0;
+    for (size_t i = 0; i < nres; i += 2) {
+      r2 += hs[i];
+      s2 += hs[i + 1];
+    }
+    for (int b = 0; b < XCHANGE_GROUPS; ++b) {
+      d2 += hs[nres + 2 * b];
+      p2 += hs[nres + 2 * b + 1];
+    }
+    const double r = std::sqrt(r2), sres = rho * std::sqrt(s2);
+    out.r_norm = r;
+    out.s_norm = sres;
+    if (l > 1) {
+      out.rel_change = p2 > 0.0 ? std::sqrt(d2 / p2) : 0.0;
+      if (out.rel_change < prm->tol) {
+        out.iters = l;
+        break;
+      }
+    }
+    double next = rho;
+    if (r > prm->mu * sres) next = prm->tau * rho;
+    else if (sres > prm->mu * r) next = rho / prm->tau;
+    if (next != rho) {
+      HIP_TRY(launch(k_rescale_state, 1024, 256, 0, st, p->at<float>(L.vpatch), ncode, kappa,
+                     (float)(rho / next)));
+      if ((rc = set_m1(next)) != CIP_OK) break;
+      rho = next;
+      ++out.rho_changes;
+    }
+  }
+  out.rho = rho;
+  if (rho != rho0) {   // leave the plan's tables at its own penalty
+    const int rc2 = set_m1(rho0);
+    if (rc == CIP_OK) rc = rc2;
+  }
+  return rc;
 }
 
 // Algorithm 1 with the wavelet (x) DCT prior. Per iteration l = 1..L:
@@ -1170,6 +1280,8 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
     if (p->learn)
       PLAN_HIP(hipMemcpyAsync(p->at<void>(L.pd0), D.data(), D.size() * 4, hipMemcpyHostToDevice,
                               st));
+    PLAN_HIP(hipStreamSynchronize(st));
+    if (p->adaptive) p->dict_host = std::move(D);
   }
   PLAN_HIP(hipStreamSynchronize(st));
   *out = p;
@@ -1264,13 +1376,29 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (!p || !d_y || !d_x || !prm) return fail(CIP_EINVAL, "NULL argument");
   if (!p->adaptive) return fail(CIP_EINVAL, "plan was not created with CIP_PLAN_ADAPTIVE");
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
-  if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
-      p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
-    return fail(CIP_EUNSUPPORTED, "adaptive penalty: l1 analysis priors only");
+  if ((p->kind == CIP_PRIOR_PATCH && p->learn) || p->kind == CIP_PRIOR_CONV2D ||
+      p->kind == CIP_PRIOR_CONV3D || p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
+    return fail(CIP_EUNSUPPORTED,
+                "adaptive penalty: l1 analysis priors and the patch prior with a fixed dictionary");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
       !(prm->tol >= 0.0))
     return fail(CIP_EINVAL, "need max_iters >= 1, every >= 1, tau > 1, mu > 1, tol >= 0");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (p->kind == CIP_PRIOR_PATCH) {
+    // Alg. 2 step 2: x_hat0 = Psi^-1 beta Lambda^H F y / (N1 N2)
+    HIP_TRY(row_r2c<float>(d_y, p->at<cx<float>>(p->L.bufA), p->K, p->N1, p->N2,
+                           p->at<const cx<float>>(p->L.twN2f), st));
+    HIP_TRY((col_op<float, OP_XHAT0>(p->at<const cx<float>>(p->L.bufA), p->at<void>(p->L.xh0),
+                                     p->K, p->S, p->N1, p->H2,
+                                     p->at<const cx<float>>(p->L.twN1f),
+                                     p->at<const cx<float>>(p->L.Mm), 0, st)));
+    cip_solve_info out{};
+    out.rel_change = -1.0;
+    const int rc = solve_patch_adaptive(p, prm, d_x, st, out);
+    p->solved_once = true;
+    if (info) *info = out;
+    return rc;
+  }
   const Layout& L = p->L;
   const int iters = prm->max_iters, every = prm->every;
   const double rho0 = p->rho;

@@ -170,4 +170,49 @@ k_norm_tv(const cx<float>* __restrict__ Yin, const float* __restrict__ vin, int 
   block_sum4<NTP>(acc, lds, sums + 4 * blockIdx.x);
 }
 
+// Iterate change of the stopping rule for solvers that hold x in space
+// (synthesis priors): per work-group partial sums sums[2 b] = sum (x - xp)^2,
+// sums[2 b + 1] = sum xp^2 (when have_prev), then xp = x. Grid-stride over n
+// values, fixed summation order; 256 threads per work-group.
+__global__ void __launch_bounds__(256)
+k_xchange(const float* __restrict__ x, float* __restrict__ xp, float* __restrict__ sums, size_t n,
+          int have_prev) {
+  __shared__ float red[2][4];
+  float a = 0.f, b = 0.f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float xv = x[i];
+    if (have_prev) {
+      const float pv = xp[i];
+      a += (xv - pv) * (xv - pv);
+      b += pv * pv;
+    }
+    xp[i] = xv;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sums[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    sums[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// State of a threshold split re-expressed for a new penalty (v-form, as in
+// the analysis row passes): t = soft(v, kappa) stays, the scaled dual
+// u = clip(v, kappa) becomes sc u with sc = rho / rho'; v' = t + sc u.
+__global__ void k_rescale_state(float* __restrict__ v, size_t n, float kappa, float sc) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float vv = v[i];
+    v[i] = soft_f(vv, kappa) + sc * clip_f(vv, kappa);
+  }
+}
+
 }  // namespace cip

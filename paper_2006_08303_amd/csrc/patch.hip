@@ -11,9 +11,14 @@ bool patch_supported(int S, int NA) {
   return S >= 1 && S <= 4 && (NA == 64 || NA == 128 || NA == 256);
 }
 
+size_t patch_z_residual_floats(int N1, int N2) {
+  const PatchGeo G = patch_geo(N1, N2);
+  return (size_t)(G.J1 / G.TPR) * G.ntc * 4 * 2;
+}
+
 hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, const uint16_t* D,
                           const uint16_t* M1, int N1, int N2, float kappa, int first,
-                          hipStream_t st, int mode, float* zf) {
+                          hipStream_t st, int mode, float* zf, float* rs) {
   const PatchGeo G = patch_geo(N1, N2);
   const int tiles = (G.J1 / G.TPR) * G.ntc;
   static_assert(PZ_MODE_FULL == PZ_FULL && PZ_MODE_CODES == PZ_CODES && PZ_MODE_SYNTH == PZ_SYNTH,
@@ -21,7 +26,7 @@ hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, co
   if (mode != PZ_FULL && !zf) return hipErrorInvalidValue;
 #define CIP_PATCH_MODE(SS, AA, MM)                                                            \
   launch(k_patch_z<SS, AA, MM>, tiles, 256, (size_t)patch_lds_bytes<SS, AA>(), st, x, v, tb, D, \
-         M1, G, kappa, first, zf)
+         M1, G, kappa, first, zf, rs)
 #define CIP_PATCH_CASE(SS, AA)                                                  \
   if (S == SS && NA == AA)                                                      \
     return mode == PZ_FULL    ? CIP_PATCH_MODE(SS, AA, PZ_FULL)                 \

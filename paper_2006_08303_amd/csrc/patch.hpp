@@ -142,11 +142,14 @@ __device__ __forceinline__ void patch_mfma(f32x4 (&acc)[RB][4], const uint16_t* 
 //   tb  per-tile overlap-added D z, [tile][S][RR][RC]
 //   Dg  [NV][NA] bf16, M1g [NA][NV] bf16 (row-major)
 //   zf  [NA][J]      codes z in FP32 (PZ_CODES: written; PZ_SYNTH: read)
+//   rs  when not null (adaptive penalty, Section IV-C): every wave writes
+//       rs[2 (4 tile + wave)] = sum (z - t)^2 and rs[... + 1] =
+//       sum (t - t_prev)^2 over its codes, t = soft(v_new), t_prev = soft(v)
 template <int S, int NA, int MODE>
 __global__ void __launch_bounds__(256, 2)
 k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict__ tb,
           const uint16_t* __restrict__ Dg, const uint16_t* __restrict__ M1g, PatchGeo G,
-          float kappa, int first, float* __restrict__ zf) {
+          float kappa, int first, float* __restrict__ zf, float* __restrict__ rs) {
   constexpr int NV = 64 * S;
   constexpr int WS = NA + 8;   // LDS row stride of W / Z (bf16)
   constexpr int ES = NV + 8;   // LDS row stride of E (bf16)
@@ -247,6 +250,7 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{};
       patch_mfma<RB2, NV, ES>(acc, M1g + (size_t)16 * RB2 * wave * NV, EB, c16, q4);
       __syncthreads();   // every wave has read e: z overwrites it
+      float r2 = 0.f, s2 = 0.f;   // residual sums of the adaptive penalty
 #pragma unroll
       for (int rb = 0; rb < RB2; ++rb) {
         const int a0 = 16 * (RB2 * wave + rb) + 4 * q4;
@@ -266,6 +270,16 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
           vn.w = z.w + clip_f(vv.w, kappa);
           *reinterpret_cast<float4*>(vt + jl * NA + a0) = vn;
           *reinterpret_cast<uint2*>(WB + jl * WS + a0) = pack_bf16x4(z.x, z.y, z.z, z.w);
+          if (rs) {
+            const float zz[4] = {z.x, z.y, z.z, z.w}, nn[4] = {vn.x, vn.y, vn.z, vn.w},
+                        oo[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float tn = soft_f(nn[i], kappa), tp = soft_f(oo[i], kappa);
+              r2 += (zz[i] - tn) * (zz[i] - tn);
+              s2 += (tn - tp) * (tn - tp);
+            }
+          }
           if constexpr (MODE == PZ_CODES) {
             float* zp = zf + (size_t)a0 * J + j0 + jl;
             zp[0] = z.x;
@@ -273,6 +287,17 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
             zp[2 * J] = z.z;
             zp[3 * J] = z.w;
           }
+        }
+      }
+      if (rs) {   // wave sums in a fixed order, one pair per wave
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          r2 += __shfl_xor(r2, off, 64);
+          s2 += __shfl_xor(s2, off, 64);
+        }
+        if (lane == 0) {
+          rs[2 * (4 * tile + wave)] = r2;
+          rs[2 * (4 * tile + wave) + 1] = s2;
         }
       }
     }

@@ -12,9 +12,12 @@ size_t patch_tile_buffer_floats(int S, int N1, int N2);
 // mode: full update, codes and state only (z to zf in FP32), or D z only
 // from the codes in zf
 enum { PZ_MODE_FULL = 0, PZ_MODE_CODES = 1, PZ_MODE_SYNTH = 2 };
+// rs: when not null, residual partial sums of the adaptive penalty (two floats
+// per wave: patch_z_residual_floats of them).
 hipError_t patch_z_launch(int S, int NA, const float* x, float* v, float* tb, const uint16_t* D,
                           const uint16_t* M1, int N1, int N2, float kappa, int first,
-                          hipStream_t st, int mode = 0, float* zf = nullptr);
+                          hipStream_t st, int mode = 0, float* zf = nullptr, float* rs = nullptr);
+size_t patch_z_residual_floats(int N1, int N2);
 
 // Device buffers of the online patch-dictionary update (patch_dl.hpp):
 //   zf [A][J] codes, part [KS][n + A][A] split products, bm / d [n][A]

@@ -92,3 +92,62 @@ def test_adaptive_argument_errors():
         ad.solve_adaptive(_t(y), 10, tau=1.0)
     with pytest.raises(cip.CipError):
         ad.attach().solve_adaptive(_t(y), 10)
+
+
+def _patch_problem(N=64, K=3, S=3, A=256, cfg=9):
+    x, psf, y = _problem(N, K, S, cfg)
+    D = synth.random_unit_atoms(synth.rng_for(cfg, 4), 64 * S, A).astype(np.float32).astype(np.float64)
+    return x, psf, y, D
+
+
+# Settings whose penalty decisions are far from the balance point (oracle
+# traces: from rho0 = 1e-4 the checks up to iteration 25 have r > 4.4 mu s,
+# from rho0 = 3 the checks up to 35 have s > 2 mu r and the next ones
+# s < 0.4 mu r, from rho0 = 1e-2 no check comes within a factor 5 of a
+# change) and whose stopping check lies 23-31% from the tolerance on either
+# side. Penalties stay >= 1e-4: far below it the BF16 code update drifts from
+# the FP64 iteration (fixed rho = 1e-6: 0.18 after 60 iterations).
+@pytest.mark.parametrize("rho0,every,tol,maxit", [
+    (1e-4, 5, 1e-4, 30),      # 5 doublings, runs to the cap
+    (3.0, 5, 1e-4, 60),       # 7 halvings, runs to the cap
+    (3.0, 5, 4.5e-3, 60),     # 1 halving, stops at the check of iteration 10
+    (1e-2, 5, 1e-4, 40),      # no change
+])
+def test_patch_adaptive_matches_oracle(rho0, every, tol, maxit):
+    """Algorithm 2 with the adaptive penalty and stopping rule, patch prior
+    (fixed dictionary, A = 256): same iterations, penalty changes and final
+    penalty as the FP64 oracle, x within the BF16 bar (2e-3)."""
+    print(f"adaptive patch rho0={rho0} every={every} tol={tol} maxit={maxit}", flush=True)
+    x, psf, y, D = _patch_problem()
+    lam, beta = 5e-6, 500.0
+    ref, rinfo = admm.PatchADMM(psf, D, 8, 4, lam, rho0, beta, tier="freq").run_adaptive(
+        y, maxit, every=every, tol=tol)
+    plan = cip.Plan(_t(psf), "patch", rho0, lam, beta, dictionary=_t(D), adaptive=True)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=every, tol=tol)
+    got = _np(got)
+    changes = sum(1 for a, b in zip(rinfo["rhos"], rinfo["rhos"][1:]) if a != b)
+    print(f"  oracle: iters {rinfo['iters']} rho {rinfo['rho']:.4g} changes {changes}; "
+          f"gpu: iters {ginfo['iters']} rho {ginfo['rho']:.4g} changes {ginfo['rho_changes']}",
+          flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == changes
+    parity.check(got, ref, 2e-3, label="patch adaptive x")
+
+
+def test_patch_adaptive_without_change_equals_plain_solve_and_restores_tables():
+    """No penalty change: the adaptive solve is the plain solve (bitwise);
+    after a solve that changed the penalty, the plan's code tables are back at
+    its own rho (a plain solve is bitwise the same as before)."""
+    x, psf, y, D = _patch_problem()
+    plan = cip.Plan(_t(psf), "patch", 1e-2, 5e-6, 500.0, dictionary=_t(D), adaptive=True)
+    yt = _t(y)
+    plain = _np(plan.solve(yt, 30))
+    got, info = plan.solve_adaptive(yt, 30, every=5, tol=0.0)
+    assert info["rho_changes"] == 0 and info["iters"] == 30
+    assert np.array_equal(_np(got), plain)
+    low = cip.Plan(_t(psf), "patch", 1e-6, 5e-6, 500.0, dictionary=_t(D), adaptive=True)
+    before = _np(low.solve(yt, 20))
+    _, info = low.solve_adaptive(yt, 40, every=5, tol=0.0)
+    assert info["rho_changes"] > 0
+    assert np.array_equal(_np(low.solve(yt, 20)), before)
