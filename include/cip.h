@@ -123,9 +123,13 @@ typedef struct {
   /* CIP_PRIOR_ITV2D only:                                                    */
   int tv_inner;         /* Chambolle iterations per ADMM iteration (0: 20)    */
   /* All priors:                                                             */
-  int flags;            /* CIP_PLAN_ADAPTIVE: keep the FP64 kernel spectra
-                           resident (K*S*N1*(N2/2+1)*16 more bytes) so that
-                           cip_solve_adaptive can change the penalty;
+  int flags;            /* CIP_PLAN_ADAPTIVE: keep what cip_solve_adaptive
+                           needs to change the penalty: the FP64 kernel
+                           spectra for the analysis priors
+                           (K*S*N1*(N2/2+1)*16 more bytes), the FP64 filter
+                           spectra for the conv priors (M*N1*(N2/2+1)*16,
+                           times S for CONV3D), a host copy of D for the
+                           patch prior;
                            CIP_PLAN_DICT_UPDATE (CIP_PRIOR_PATCH,
                            CIP_PRIOR_CONV2D and CIP_PRIOR_CONV3D): learn
                            the dictionary online during every solve         */
@@ -240,11 +244,21 @@ int cip_plan_destroy(cip_plan_t plan);
  * stops with x^l when c < tol; otherwise sets rho <- tau rho if r > mu s,
  * rho <- rho / tau if s > mu r, rescales the scaled dual u by the inverse
  * factor and recomputes the FP64 per-frequency inverses for the new rho
- * before the next x-update. The plan must have been created with
- * CIP_PLAN_ADAPTIVE and must not be an attached plan; its tables are back at
- * its own rho when the call returns. Synchronous: waits on `stream` at every
- * check and returns when x is in d_x. The norms are accumulated in FP32 per
- * work-group and summed in FP64 on the host. */
+ * before the next x-update.
+ * Algorithm 2 (CIP_PRIOR_PATCH, CIP_PRIOR_CONV2D, CIP_PRIOR_CONV3D with a
+ * fixed dictionary) from z = t = u = 0, the split z = t: the same rule with
+ *   r = ||z^l - t^l||,  s = rho ||t^l - t^(l-1)||,
+ * and on a change u rescaled as above and the code update rebuilt for the new
+ * rho (its threshold lambda / rho; M1 = D^T (rho I + D D^T)^-1 in FP64 on the
+ * host for the patch prior; the per-frequency Sherman-Morrison tables in FP64
+ * from the resident filter spectra for the conv priors; the x-update does not
+ * depend on rho). CIP_EUNSUPPORTED for plans that learn their dictionary and
+ * for CIP_PRIOR_ITV2D and CIP_PRIOR_WDCT3D.
+ * The plan must have been created with CIP_PLAN_ADAPTIVE and must not be an
+ * attached plan; its tables are back at its own rho when the call returns.
+ * Synchronous: waits on `stream` at every check and returns when x is in
+ * d_x. The norms are accumulated in FP32 per work-group (per wave for the
+ * synthesis priors) and summed in FP64. */
 typedef struct {
   int max_iters;   /* iteration cap (>= 1)                                     */
   int every;       /* check and adapt every this many iterations (>= 1)       */

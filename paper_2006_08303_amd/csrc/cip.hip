@@ -145,6 +145,12 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       const size_t ps = patch_z_residual_floats(N1, N2) + 2 * XCHANGE_GROUPS;
       if (ps > nsum) nsum = ps;
     }
+    if (kind == CIP_PRIOR_CONV2D || kind == CIP_PRIOR_CONV3D) {
+      // row-pass residuals, k_xchange sums, two FP64 totals
+      const size_t cs = conv_row_residual_floats(prior->n_filters * S, N1, N2) +
+                        2 * XCHANGE_GROUPS + 4;
+      if (cs > nsum) nsum = cs;
+    }
     L.sums = sta(nsum * 4);
   }
   L.rt64 = scr(F * 16);
@@ -207,7 +213,9 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     L.xhat = sta((size_t)S * F * 8);
     L.rtc = sta(M * S * F * 8);
     L.vconv = sta(M * S * (size_t)N1 * N2 * 4);
-    L.th64 = scr(M * B * F * 16);
+    // the FP64 filter spectra stay resident when the penalty may change
+    // during a solve (the z-update tables are rebuilt from them)
+    L.th64 = adaptive && !learn ? tab(M * B * F * 16) : scr(M * B * F * 16);
   }
   L.tables = ot;
   L.state_bytes = os > oc ? os : oc;
@@ -893,6 +901,118 @@ hipError_t solve_conv(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
                  (float)(1.0 / ((double)p->N1 * p->N2)), p->at<const cx<float>>(L.twN2f), st);
 }
 
+// Algorithm 2 with a convolutional dictionary and the penalty update and
+// stopping rule of Section IV-C (Eq. paramS), split z = t: at every `every`-th
+// iteration l < max_iters,
+//   r = ||z^l - t^l||, s = rho ||t^l - t^(l-1)|| (summed by the row pass),
+//   c = ||x^l - x^(l-1)|| / ||x^(l-1)|| (x^l formed in d_x, k_xchange);
+// stop with x^l when c < tol, else change rho by tau when one residual
+// exceeds mu times the other. Only the z-update depends on rho: on a change
+// the state is re-expressed for the new penalty (u scaled by rho / rho'),
+// g^ = F(t - u') is formed again, and gamma, eta (and theta) are rebuilt in
+// FP64 from the resident filter spectra. The plan's tables are back at its
+// own rho on return.
+int solve_conv_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x, hipStream_t st,
+                        cip_solve_info& out) {
+  const Layout& L = p->L;
+  const int iters = prm->max_iters, every = prm->every;
+  const int M = p->n_filters, P = M * p->S;
+  const size_t F = (size_t)p->N1 * p->H2;
+  const double rho0 = p->rho;
+  double rho = rho0;
+  const size_t nres = conv_row_residual_floats(P, p->N1, p->N2);
+  float* rs = p->at<float>(L.sums);
+  float* xs = rs + nres;
+  double* tot = reinterpret_cast<double*>(xs + 2 * XCHANGE_GROUPS);
+  float* xprev = p->at<float>(L.xbuf);
+  const size_t nx = (size_t)p->S * p->N1 * p->N2;
+  const size_t ncode = (size_t)P * p->N1 * p->N2;
+  const float zscale = (float)(1.0 / ((double)p->N1 * p->N2));
+  std::vector<float> hs(2 * XCHANGE_GROUPS + 4);
+  auto set_tables = [&](double r) -> hipError_t {
+    if (p->kind == CIP_PRIOR_CONV3D)
+      return conv_tables3(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
+                          p->at<float>(L.gam), M, p->S, F, r, st);
+    return conv_tables(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
+                       p->at<float>(L.gam), p->at<float>(L.eta), M, F, r, p->mu, p->N1, p->N2,
+                       st);
+  };
+  auto x_out = [&]() -> hipError_t {   // x^l = F^-1 x^ -> d_x
+    hipError_t e = conv_col_fft(-1, p->at<const cx<float>>(L.xhat), p->at<cx<float>>(L.bufB),
+                                p->S, p->N1, p->H2, p->at<const cx<float>>(L.twN1f), st);
+    if (e != hipSuccess) return e;
+    return row_c2r(p->at<const cx<float>>(L.bufB), d_x, p->S, p->N1, p->N2, zscale,
+                   p->at<const cx<float>>(L.twN2f), st);
+  };
+  int rc = CIP_OK;
+  for (int l = 1;; ++l) {
+    const bool last = l == iters;
+    HIP_TRY(conv_freq_pass(p, l == 1, l == 1, last ? 0 : 1, st));
+    if (last) {
+      HIP_TRY(x_out());
+      out.iters = l;
+      break;
+    }
+    const bool check = l % every == 0;
+    const bool store = (l + 1) % every == 0;
+    const float kappa = (float)(p->lambda / rho);
+    HIP_TRY(conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1,
+                         p->H2, p->at<const cx<float>>(L.twN1f), st));
+    HIP_TRY(conv_row(p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.rtc), p->at<float>(L.vconv),
+                     P, p->N1, p->N2, p->at<const cx<float>>(L.twN2f), kappa, zscale, l == 1, st,
+                     check ? rs : nullptr));
+    HIP_TRY(conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gv), P, p->N1,
+                         p->H2, p->at<const cx<float>>(L.twN1f), st));
+    if (check || store) {
+      HIP_TRY(x_out());
+      HIP_TRY(launch(k_xchange, XCHANGE_GROUPS, 256, 0, st, (const float*)d_x, xprev, xs, nx,
+                     check && l > 1 ? 1 : 0));
+    }
+    if (!check) continue;
+    HIP_TRY(launch(k_sum_pairs, 1, 256, 0, st, (const float*)rs, nres / 2, tot));
+    HIP_TRY(hipMemcpyAsync(hs.data(), xs, hs.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double d2 = 0.0, p2 = 0.0, tt[2];
+    for (int b = 0; b < XCHANGE_GROUPS; ++b) {
+      d2 += hs[2 * b];
+      p2 += hs[2 * b + 1];
+    }
+    std::memcpy(tt, hs.data() + 2 * XCHANGE_GROUPS, sizeof tt);
+    const double r = std::sqrt(tt[0]), sres = rho * std::sqrt(tt[1]);
+    out.r_norm = r;
+    out.s_norm = sres;
+    if (l > 1) {
+      out.rel_change = p2 > 0.0 ? std::sqrt(d2 / p2) : 0.0;
+      if (out.rel_change < prm->tol) {
+        out.iters = l;   // x^l is in d_x
+        break;
+      }
+    }
+    double next = rho;
+    if (r > prm->mu * sres) next = prm->tau * rho;
+    else if (sres > prm->mu * r) next = rho / prm->tau;
+    if (next != rho) {
+      // V -> V', W = t - u' (in the memory of g^, which is formed again)
+      float* w = p->at<float>(L.gv);
+      HIP_TRY(conv_reemit(p->at<float>(L.vconv), w, ncode, kappa, (float)(p->lambda / next),
+                          (float)(rho / next), st));
+      HIP_TRY(row_r2c<float>(w, p->at<cx<float>>(L.rtc), P, p->N1, p->N2,
+                             p->at<const cx<float>>(L.twN2f), st));
+      HIP_TRY(conv_col_fft(1, p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.gv), P, p->N1,
+                           p->H2, p->at<const cx<float>>(L.twN1f), st));
+      HIP_TRY(set_tables(next));
+      rho = next;
+      ++out.rho_changes;
+    }
+  }
+  out.rho = rho;
+  if (rho != rho0) {   // leave the plan's tables at its own penalty
+    const hipError_t e = set_tables(rho0);
+    if (e != hipSuccess && rc == CIP_OK) rc = fail(CIP_EHIP, hipGetErrorString(e));
+  }
+  return rc;
+}
+
 hipError_t gram(cip_plan_t p, hipStream_t st, double rho = 0.0) {
   if (rho <= 0.0) rho = p->rho;
   GramArgs a;
@@ -1376,15 +1496,17 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (!p || !d_y || !d_x || !prm) return fail(CIP_EINVAL, "NULL argument");
   if (!p->adaptive) return fail(CIP_EINVAL, "plan was not created with CIP_PLAN_ADAPTIVE");
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
-  if ((p->kind == CIP_PRIOR_PATCH && p->learn) || p->kind == CIP_PRIOR_CONV2D ||
-      p->kind == CIP_PRIOR_CONV3D || p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
+  const bool synthesis = p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D ||
+                         p->kind == CIP_PRIOR_CONV3D;
+  if ((synthesis && p->learn) || p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED,
-                "adaptive penalty: l1 analysis priors and the patch prior with a fixed dictionary");
+                "adaptive penalty: l1 analysis priors and the synthesis priors with a fixed "
+                "dictionary");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
       !(prm->tol >= 0.0))
     return fail(CIP_EINVAL, "need max_iters >= 1, every >= 1, tau > 1, mu > 1, tol >= 0");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (p->kind == CIP_PRIOR_PATCH) {
+  if (synthesis) {
     // Alg. 2 step 2: x_hat0 = Psi^-1 beta Lambda^H F y / (N1 N2)
     HIP_TRY(row_r2c<float>(d_y, p->at<cx<float>>(p->L.bufA), p->K, p->N1, p->N2,
                            p->at<const cx<float>>(p->L.twN2f), st));
@@ -1394,7 +1516,8 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
                                      p->at<const cx<float>>(p->L.Mm), 0, st)));
     cip_solve_info out{};
     out.rel_change = -1.0;
-    const int rc = solve_patch_adaptive(p, prm, d_x, st, out);
+    const int rc = p->kind == CIP_PRIOR_PATCH ? solve_patch_adaptive(p, prm, d_x, st, out)
+                                              : solve_conv_adaptive(p, prm, d_x, st, out);
     p->solved_once = true;
     if (info) *info = out;
     return rc;

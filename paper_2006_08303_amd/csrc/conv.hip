@@ -174,14 +174,26 @@ hipError_t conv_dhat3(const cx<float>* zh, const cx<float>* th, cx<float>* dhat,
 #undef CIP_S_SWITCH
 
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
-                    const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st) {
+                    const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st,
+                    float* rs) {
   CIP_DISPATCH_N(N2, {
     const int T = NN / ppt_row<NN>();
     const size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
     return launch(k_conv_row<NN>, P * (N1 / RT), PAIRS * T, lds, st, Vin, Gout, V, N1, tw, kappa,
-                  zscale, first);
+                  zscale, first, rs);
   });
   return hipSuccess;
+}
+
+size_t conv_row_residual_floats(int P, int N1, int N2) {
+  const int nt = PAIRS * (N2 / ppt_row_n(N2));   // threads of a k_conv_row group
+  const size_t waves = nt < 64 ? 1 : (size_t)(nt / 64);
+  return 2 * waves * (size_t)P * (N1 / RT);
+}
+
+hipError_t conv_reemit(float* V, float* W, size_t n, float kappa, float kappa_new, float sc,
+                       hipStream_t st) {
+  return launch(k_conv_reemit, 2048, 256, 0, st, V, W, n, kappa, kappa_new, sc);
 }
 
 }  // namespace cip

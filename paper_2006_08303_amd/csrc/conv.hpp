@@ -635,13 +635,20 @@ __global__ void k_conv_dhat3(const cx<float>* __restrict__ zh, const cx<float>* 
 // Row pass of the conv prior (pairs of rows of one code plane per group):
 // inverse row FFT of v (z = scale * result), state update V = z + clip(V),
 // w = 2 soft(V) - V, forward row FFT of w -> RT. first: V_prev = 0.
+// rs (optional): the residuals of the split z = t, per wave of the group,
+//   rs[2 i] = sum (z - t)^2 = sum (clip(V) - clip(V_prev))^2,
+//   rs[2 i + 1] = sum (t - t_prev)^2 = sum (soft(V) - soft(V_prev))^2,
+// i = blockIdx.x * waves + wave (conv_row_residual_floats entries in all).
 template <int N2>
 __global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()), 2)
 k_conv_row(const cx<float>* __restrict__ Vin, cx<float>* __restrict__ Gout, float* __restrict__ V,
-           int N1, const cx<float>* __restrict__ twg, float kappa, float zscale, int first) {
+           int N1, const cx<float>* __restrict__ twg, float kappa, float zscale, int first,
+           float* __restrict__ rs) {
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
+  constexpr int NT = PAIRS * T;
+  static_assert(NT % 64 == 0 || 64 % NT == 0, "waves of the row pass must be whole or one");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
   float* lds = reinterpret_cast<float*>(smem_raw) + 2 * N2;
@@ -667,6 +674,7 @@ k_conv_row(const cx<float>* __restrict__ Vin, cx<float>* __restrict__ Gout, floa
   staging_to_pair<N2, PPT>(v, stg, g, t);
   __syncthreads();
   fft_group<N2, PPT, -1>(v, cb, t, tw);
+  float r2 = 0.f, s2 = 0.f;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int k = t + T * q;
@@ -674,12 +682,49 @@ k_conv_row(const cx<float>* __restrict__ Vin, cx<float>* __restrict__ Gout, floa
     const float nb = zscale * v[q].y + clip_f(ob[q], kappa);
     va[k] = na;
     vb[k] = nb;
-    v[q] = cx<float>{2.f * soft_f(na, kappa) - na, 2.f * soft_f(nb, kappa) - nb};
+    const float ta = soft_f(na, kappa), tb = soft_f(nb, kappa);
+    v[q] = cx<float>{2.f * ta - na, 2.f * tb - nb};
+    if (rs) {
+      const float ra = clip_f(na, kappa) - clip_f(oa[q], kappa);
+      const float rb = clip_f(nb, kappa) - clip_f(ob[q], kappa);
+      const float da = ta - soft_f(oa[q], kappa), db = tb - soft_f(ob[q], kappa);
+      r2 += ra * ra + rb * rb;
+      s2 += da * da + db * db;
+    }
+  }
+  if (rs) {   // fixed-order reduction over the lanes of each wave
+    constexpr int W = NT < 64 ? NT : 64;
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1) {
+      r2 += __shfl_xor(r2, off, W);
+      s2 += __shfl_xor(s2, off, W);
+    }
+    if ((threadIdx.x & (W - 1)) == 0) {
+      const int i = blockIdx.x * (NT / W) + threadIdx.x / W;
+      rs[2 * i] = r2;
+      rs[2 * i + 1] = s2;
+    }
   }
   fft_group<N2, PPT, +1>(v, cb, t, tw);
   pair_to_staging<N2, PPT>(v, cb, stg, g, t);
   __syncthreads();
   staging_to_tile(Gout + rt_tile_base(p, row0, N1, H2), stg, H2 * RT);
+}
+
+// A change of the penalty rho -> rho' between iterations (Section IV-C):
+// the state V (t = soft(V, kappa), u = clip(V, kappa)) is re-expressed as
+// V' = t + sc u with sc = rho / rho' (kappa' = lambda / rho' bounds sc u), and
+// W = t - sc u = 2 soft(V', kappa') - V' is written for the forward
+// transforms that rebuild g^ = F(t - u').
+__global__ void k_conv_reemit(float* __restrict__ V, float* __restrict__ W, size_t n, float kappa,
+                              float kappa_new, float sc) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float v = V[i];
+    const float vn = soft_f(v, kappa) + sc * clip_f(v, kappa);
+    V[i] = vn;
+    W[i] = 2.f * soft_f(vn, kappa_new) - vn;
+  }
 }
 
 }  // namespace cip

@@ -47,7 +47,14 @@ hipError_t conv_tables3f(const cx<float>* th2, cx<float>* th32, float* gam, cons
                          int M, int S, size_t F, float rho, hipStream_t st);
 hipError_t conv_dhat3(const cx<float>* zh, const cx<float>* th, cx<float>* dhat,
                       const cx<float>* bw, int M, int S, size_t F, hipStream_t st);
+// rs: optional residual sums of the split z = t (k_conv_row), sized by
+// conv_row_residual_floats
 hipError_t conv_row(const cx<float>* Vin, cx<float>* Gout, float* V, int P, int N1, int N2,
-                    const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st);
+                    const cx<float>* tw, float kappa, float zscale, int first, hipStream_t st,
+                    float* rs = nullptr);
+size_t conv_row_residual_floats(int P, int N1, int N2);
+// state V re-expressed for a new penalty, W = t - u' (k_conv_reemit)
+hipError_t conv_reemit(float* V, float* W, size_t n, float kappa, float kappa_new, float sc,
+                       hipStream_t st);
 
 }  // namespace cip

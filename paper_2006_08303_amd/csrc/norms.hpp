@@ -204,6 +204,32 @@ k_xchange(const float* __restrict__ x, float* __restrict__ xp, float* __restrict
   }
 }
 
+// out[0] = sum in[2 i], out[1] = sum in[2 i + 1] over i < npairs, in FP64 and
+// a fixed order; one work-group of 256 threads.
+__global__ void __launch_bounds__(256)
+k_sum_pairs(const float* __restrict__ in, size_t npairs, double* __restrict__ out) {
+  __shared__ double red[2][4];
+  double a = 0.0, b = 0.0;
+  for (size_t i = threadIdx.x; i < npairs; i += 256) {
+    a += (double)in[2 * i];
+    b += (double)in[2 * i + 1];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    out[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
 // State of a threshold split re-expressed for a new penalty (v-form, as in
 // the analysis row passes): t = soft(v, kappa) stays, the scaled dual
 // u = clip(v, kappa) becomes sc u with sc = rho / rho'; v' = t + sc u.

@@ -151,3 +151,70 @@ def test_patch_adaptive_without_change_equals_plain_solve_and_restores_tables():
     _, info = low.solve_adaptive(yt, 40, every=5, tol=0.0)
     assert info["rho_changes"] > 0
     assert np.array_equal(_np(low.solve(yt, 20)), before)
+
+
+def _conv_problem(N, K, S, M, L, dims, cfg=9):
+    x, psf, y = _problem(N, K, S, cfg)
+    if dims == 2:
+        filt = synth.random_unit_filters(synth.rng_for(cfg, 5), M, L)
+        filt = filt.astype(np.float32).astype(np.float64)
+    else:
+        filt = synth.random_unit_filters_3d(synth.rng_for(cfg, 6), M, S, L)
+    return x, psf, y, filt
+
+
+# Oracle traces (lambda = 1.875e-6, beta = 8): every decision lies at least a
+# factor 2.8 from the mu threshold, except the common one (1.0 and 1e6 from
+# it), and the stopping checks lie 5-12% from the tolerance on either side.
+@pytest.mark.parametrize("kind,N,M,L,rho0,every,tol,maxit,mu", [
+    ("conv2d", 64, 8, 5, 1e-6, 5, 1e-4, 60, 0.0),      # 11 doublings, to the cap
+    ("conv2d", 64, 8, 5, 100.0, 5, 1e-4, 60, 0.0),     # 11 halvings, to the cap
+    ("conv2d", 128, 32, 11, 100.0, 5, 1e-4, 50, 0.0),  # 9 halvings, to the cap
+    ("conv2d", 64, 8, 5, 1e-6, 5, 1.47e-3, 60, 0.01),  # gradient term: 4 changes, stops at 25
+    ("conv3d", 64, 8, 5, 10.0, 5, 1e-4, 36, 0.0),      # 7 halvings, to the cap
+    ("conv3d", 64, 8, 5, 1e-6, 5, 1.2e-3, 60, 0.0),    # 5 doublings, stops at 30
+])
+def test_conv_adaptive_matches_oracle(kind, N, M, L, rho0, every, tol, maxit, mu):
+    """Algorithm 2 with the adaptive penalty and stopping rule, convolutional
+    dictionaries (2D common filters, with and without the gradient term, and
+    3D filters): same iterations, penalty changes and final penalty as the
+    FP64 oracle, x within the FP32 bar (1e-4)."""
+    dims = 3 if kind == "conv3d" else 2
+    print(f"adaptive {kind} N={N} M={M} L={L} rho0={rho0} every={every} tol={tol} "
+          f"maxit={maxit} mu={mu}", flush=True)
+    x, psf, y, filt = _conv_problem(N, 3, 3, M, L, dims)
+    lam, beta = 1.875e-6, 8.0
+    ref, rinfo = admm.ConvADMM(psf, filt, lam, rho0, beta, tier="freq", dims=dims,
+                               mu=mu).run_adaptive(y, maxit, every=every, tol=tol)
+    plan = cip.Plan(_t(psf), kind, rho0, lam, beta, filters=_t(filt), mu=mu, adaptive=True)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=every, tol=tol)
+    got = _np(got)
+    changes = sum(1 for a, b in zip(rinfo["rhos"], rinfo["rhos"][1:]) if a != b)
+    print(f"  oracle: iters {rinfo['iters']} rho {rinfo['rho']:.4g} changes {changes}; "
+          f"gpu: iters {ginfo['iters']} rho {ginfo['rho']:.4g} changes {ginfo['rho_changes']}",
+          flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == changes
+    parity.check(got, ref, 1e-4, label=f"{kind} adaptive x")
+
+
+@pytest.mark.parametrize("kind", ["conv2d", "conv3d"])
+def test_conv_adaptive_without_change_equals_plain_solve_and_restores_tables(kind):
+    """No penalty change (rho = 1e-2: every check a factor 3 from a change):
+    the adaptive solve is the plain solve (bitwise); after a solve that changed
+    the penalty the plan's tables are back at its own rho."""
+    dims = 3 if kind == "conv3d" else 2
+    x, psf, y, filt = _conv_problem(64, 3, 3, 8, 5, dims)
+    lam, beta = 1.875e-6, 8.0
+    yt = _t(y)
+    plan = cip.Plan(_t(psf), kind, 1e-2, lam, beta, filters=_t(filt), adaptive=True)
+    plain = _np(plan.solve(yt, 30))
+    got, info = plan.solve_adaptive(yt, 30, every=5, tol=0.0)
+    assert info["rho_changes"] == 0 and info["iters"] == 30
+    assert np.array_equal(_np(got), plain)
+    low = cip.Plan(_t(psf), kind, 1e-6, lam, beta, filters=_t(filt), adaptive=True)
+    before = _np(low.solve(yt, 20))
+    _, info = low.solve_adaptive(yt, 40, every=5, tol=0.0)
+    assert info["rho_changes"] > 0
+    assert np.array_equal(_np(low.solve(yt, 20)), before)
