@@ -252,8 +252,16 @@ int cip_plan_destroy(cip_plan_t plan);
  * rho (its threshold lambda / rho; M1 = D^T (rho I + D D^T)^-1 in FP64 on the
  * host for the patch prior; the per-frequency Sherman-Morrison tables in FP64
  * from the resident filter spectra for the conv priors; the x-update does not
- * depend on rho). CIP_EUNSUPPORTED for plans that learn their dictionary and
- * for CIP_PRIOR_ITV2D and CIP_PRIOR_WDCT3D.
+ * depend on rho).
+ * With online dictionary learning (CIP_PLAN_DICT_UPDATE) the code update is
+ * rebuilt from the current dictionary G (on the GPU, FP32), and with
+ * adapt_sigma the rule also sets the dictionary penalty after the D, G, E
+ * step of every checked iteration:
+ *   r_d = ||D - G||,  s_d = sigma ||G - G_prev||,
+ *   sigma <- tau sigma if r_d > mu s_d, sigma / tau if s_d > mu r_d, and the
+ *   scaled dual E is rescaled by sigma_old / sigma_new.
+ * CIP_EUNSUPPORTED for CIP_PRIOR_ITV2D and CIP_PRIOR_WDCT3D, and for
+ * adapt_sigma on a plan that does not learn its dictionary.
  * The plan must have been created with CIP_PLAN_ADAPTIVE and must not be an
  * attached plan; its tables are back at its own rho when the call returns.
  * Synchronous: waits on `stream` at every check and returns when x is in
@@ -265,6 +273,7 @@ typedef struct {
   double tau;      /* penalty factor (> 1; the paper uses 2)                  */
   double mu;       /* residual balance (> 1; the paper uses 10)               */
   double tol;      /* stopping tolerance on c (>= 0; the paper uses 1e-4)     */
+  int adapt_sigma; /* also adapt the dictionary penalty sigma (learning plans) */
 } cip_adaptive_params;
 typedef struct {
   int iters;        /* iterations run                                         */
@@ -273,6 +282,8 @@ typedef struct {
   double rel_change;/* last measured c (-1 if none)                           */
   double r_norm;    /* last measured r                                         */
   double s_norm;    /* last measured s                                         */
+  double sigma;     /* dictionary penalty of the last step (learning plans)  */
+  int sigma_changes;/* number of sigma changes                                */
 } cip_solve_info;
 int cip_solve_adaptive(cip_plan_t plan, const float* d_y, const cip_adaptive_params* params,
                        float* d_x, void* stream, cip_solve_info* info);

@@ -479,7 +479,7 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
     The object is left with its starting rho and sigma (and dictionary: the
     learned one, as after ``run``). Returns (x, info), info = dict(iters,
     rho, rhos, sigma, sigmas, rel_change, r, s, trace = [(l, r, s, c)] of the
-    checks)."""
+    checks, trace_sigma = [(l, r_d, s_d)] of the sigma checks)."""
     rho0 = alg.rho
     learn = getattr(alg, "dict_update", False)
     sig0 = alg.sigma if learn else None
@@ -491,7 +491,7 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
     u = np.zeros(zshape)
     x_prev, x = None, None
     rhos, sigmas = [alg.rho], ([alg.sigma] if learn else [])
-    info = {"rel_change": None, "r": None, "s": None, "trace": []}
+    info = {"rel_change": None, "r": None, "s": None, "trace": [], "trace_sigma": []}
     it = 0
     for it in range(1, max_iters + 1):
         x = alg.x_update(data, z)
@@ -530,6 +530,7 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
             if check and adapt_sigma:
                 rd = float(np.linalg.norm(d - g))
                 sd = alg.sigma * float(np.linalg.norm(g - g_prev))
+                info["trace_sigma"].append((it, rd, sd))
                 new = alg.sigma
                 if rd > mu * sd:
                     new = tau * alg.sigma

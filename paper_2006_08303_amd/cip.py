@@ -49,13 +49,14 @@ class _PriorDesc(ctypes.Structure):
 
 class _AdaptiveParams(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int), ("every", ctypes.c_int), ("tau", ctypes.c_double),
-                ("mu", ctypes.c_double), ("tol", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("tol", ctypes.c_double), ("adapt_sigma", ctypes.c_int)]
 
 
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("rho_changes", ctypes.c_int), ("rho", ctypes.c_double),
                 ("rel_change", ctypes.c_double), ("r_norm", ctypes.c_double),
-                ("s_norm", ctypes.c_double)]
+                ("s_norm", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("sigma_changes", ctypes.c_int)]
 
 
 CIP_PLAN_ADAPTIVE = 1
@@ -244,11 +245,12 @@ class Plan:
         return x
 
     def solve_adaptive(self, y, max_iters, every=1, tau=2.0, mu=10.0, tol=1e-4, out=None,
-                       stream=None):
+                       stream=None, adapt_sigma=False):
         """cip_solve_adaptive; returns (x, info dict)."""
         x = out if out is not None else torch.empty((self.S, self.N1, self.N2),
                                                     dtype=torch.float32, device=y.device)
-        prm = _AdaptiveParams(int(max_iters), int(every), float(tau), float(mu), float(tol))
+        prm = _AdaptiveParams(int(max_iters), int(every), float(tau), float(mu), float(tol),
+                              1 if adapt_sigma else 0)
         info = _SolveInfo()
         _check(lib().cip_solve_adaptive(self._h, _dev_f32(y, (self.K, self.N1, self.N2), "y"),
                                         ctypes.byref(prm),

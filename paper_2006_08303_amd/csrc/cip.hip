@@ -76,6 +76,7 @@ struct Layout {
   size_t bw;                                                 // 3D conv: band DFT matrix
   size_t wband, wcoef, wtmp;            // wavelet (x) DCT: band DCT, coefficients, staging
   size_t filt0, gtap, gehat, dsp, ecdl, dpl;                 // 3D dictionary update
+  size_t gprev;                         // conv learning with adaptive penalties: G_prev taps
   size_t tables;                        // bytes of the table region
   size_t state_bytes;                   // bytes of the state region
   size_t total;                         // tables + state_bytes
@@ -142,13 +143,14 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     L.xbuf = sta((size_t)2 * S * N1 * N2 * 4);      // x^(l-1), x^l of the checks
     size_t nsum = (size_t)S * (N1 / 8) * 4;         // norm-pass partial sums
     if (kind == CIP_PRIOR_PATCH) {
-      const size_t ps = patch_z_residual_floats(N1, N2) + 2 * XCHANGE_GROUPS;
+      const size_t ps = patch_z_residual_floats(N1, N2) + 2 * XCHANGE_GROUPS + 4;
       if (ps > nsum) nsum = ps;
     }
     if (kind == CIP_PRIOR_CONV2D || kind == CIP_PRIOR_CONV3D) {
-      // row-pass residuals, k_xchange sums, two FP64 totals
+      // row-pass residuals, k_xchange sums, two FP64 totals, the dictionary
+      // residuals and their two FP64 totals
       const size_t cs = conv_row_residual_floats(prior->n_filters * S, N1, N2) +
-                        2 * XCHANGE_GROUPS + 4;
+                        2 * XCHANGE_GROUPS + 4 + 2 * CDL_RES_GROUPS + 4;
       if (cs > nsum) nsum = cs;
     }
     L.sums = sta(nsum * 4);
@@ -205,6 +207,7 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       L.dsp = sta(P * F * 8);
       L.ecdl = sta(P * F * 8);   // the dual as plane spectra
       L.dpl = sta(P * (size_t)N1 * N2 * 4);
+      if (adaptive) L.gprev = sta(taps * 4);
     }
     L.eta = learn ? sta(F * 4) : tab(F * 4);
     L.bw = kind == CIP_PRIOR_CONV3D ? tab((size_t)S * S * 8) : 0;
@@ -629,8 +632,12 @@ hipError_t solve_patch(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
 //   c = ||x^l - x^(l-1)|| / ||x^(l-1)|| (k_xchange; x^l is in d_x);
 // stop with x^l when c < tol, else change rho by tau when one residual
 // exceeds mu times the other: the state is re-expressed for the new penalty
-// (u scaled by rho / rho') and M1 = D^T (rho' I + D D^T)^-1 is rebuilt in FP64
-// on the host. The plan's tables are back at its own rho on return.
+// (u scaled by rho / rho') and M1 = D^T (rho' I + D D^T)^-1 is rebuilt: in
+// FP64 on the host for a fixed dictionary (the plan's tables are back at its
+// own rho on return), on the GPU from G with online dictionary learning.
+// With learning and adapt_sigma the D, G, E step of a checked iteration also
+// yields r_d = ||D - G|| and s_d = sigma ||G - G_prev||, and sigma changes
+// by the same rule, E rescaled by sigma / sigma'.
 void patch_dictionary_tables(const std::vector<float>& D, int nv, int na, double rho,
                              std::vector<uint16_t>& dbf, std::vector<uint16_t>& m1bf);
 
@@ -640,15 +647,22 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
   const int iters = prm->max_iters, every = prm->every;
   const int nv = 64 * p->S, na = p->n_atoms;
   const double rho0 = p->rho;
-  double rho = rho0;
+  double rho = rho0, sigma = p->sigma;
   const size_t nres = patch_z_residual_floats(p->N1, p->N2);
   float* rs = p->at<float>(L.sums);
   float* xs = rs + nres;
+  double* dres = reinterpret_cast<double*>(xs + 2 * XCHANGE_GROUPS);
   float* xprev = p->at<float>(L.xbuf);
   const size_t nx = (size_t)p->S * p->N1 * p->N2;
   const size_t ncode = (size_t)na * (p->N1 / 4) * (p->N2 / 4);
-  std::vector<float> hs(nres + 2 * XCHANGE_GROUPS);
+  // code-update sums, k_xchange sums, the dictionary residuals (2 doubles)
+  std::vector<float> hs(nres + 2 * XCHANGE_GROUPS + 4);
+  const PatchDictBufs db = p->learn ? patch_dict_bufs(p) : PatchDictBufs{};
   auto set_m1 = [&](double r) -> int {
+    if (p->learn) {
+      HIP_TRY(patch_dict_m1(db, p->S, na, (float)r, st));
+      return CIP_OK;
+    }
     std::vector<uint16_t> dbf, m1bf;
     patch_dictionary_tables(p->dict_host, nv, na, r, dbf, m1bf);
     HIP_TRY(hipMemcpyAsync(p->at<void>(L.m1bf), m1bf.data(), m1bf.size() * 2,
@@ -657,6 +671,7 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
     return CIP_OK;
   };
   int rc = CIP_OK;
+  if (p->learn) HIP_TRY(patch_dict_begin(p, st));
   for (int l = 1;; ++l) {
     // x-update (Eq. solx_synt_DFT) -> x^l in d_x
     if (l > 1)
@@ -671,11 +686,24 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
     }
     const bool check = l % every == 0;
     const bool store = (l + 1) % every == 0;
+    const bool check_sigma = check && p->learn && prm->adapt_sigma;
     const float kappa = (float)(p->lambda / rho);
-    HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf),
-                           p->at<const uint16_t>(L.dbf), p->at<const uint16_t>(L.m1bf), p->N1,
-                           p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_FULL, nullptr,
-                           check ? rs : nullptr));
+    if (p->learn) {
+      // codes in FP32, one D, G, E step, then D z with the new G
+      HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), db.dbf,
+                             db.m1bf, p->N1, p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_CODES,
+                             db.zf, check ? rs : nullptr));
+      HIP_TRY(patch_dict_step(d_x, db, p->S, na, p->N1, p->N2, (float)sigma, (float)rho, st,
+                              check_sigma ? dres : nullptr));
+      HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), db.dbf,
+                             db.m1bf, p->N1, p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_SYNTH,
+                             db.zf));
+    } else {
+      HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf),
+                             p->at<const uint16_t>(L.dbf), p->at<const uint16_t>(L.m1bf), p->N1,
+                             p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_FULL, nullptr,
+                             check ? rs : nullptr));
+    }
     HIP_TRY(patch_assemble_launch(p->S, p->at<const float>(L.tbuf), p->at<float>(L.rimg), p->N1,
                                   p->N2, st));
     if (check || store)
@@ -684,7 +712,7 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
     if (!check) continue;
     HIP_TRY(hipMemcpyAsync(hs.data(), rs, hs.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    double r2 = 0.0, s2 = 0.0, d2 = 0.0, p2 = 0.0;
+    double r2 = 0.0, s2 = 0.0, d2 = 0.0, p2 = 0.0, td[2];
     for (size_t i = 0; i < nres; i += 2) {
       r2 += hs[i];
       s2 += hs[i + 1];
@@ -693,6 +721,7 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
       d2 += hs[nres + 2 * b];
       p2 += hs[nres + 2 * b + 1];
     }
+    std::memcpy(td, hs.data() + nres + 2 * XCHANGE_GROUPS, sizeof td);
     const double r = std::sqrt(r2), sres = rho * std::sqrt(s2);
     out.r_norm = r;
     out.s_norm = sres;
@@ -713,9 +742,21 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
       rho = next;
       ++out.rho_changes;
     }
+    if (check_sigma) {
+      const double rd = std::sqrt(td[0]), sd = sigma * std::sqrt(td[1]);
+      double ns = sigma;
+      if (rd > prm->mu * sd) ns = prm->tau * sigma;
+      else if (sd > prm->mu * rd) ns = sigma / prm->tau;
+      if (ns != sigma) {
+        HIP_TRY(patch_dict_scale_dual(db, nv * na, (float)(sigma / ns), st));
+        sigma = ns;
+        ++out.sigma_changes;
+      }
+    }
   }
   out.rho = rho;
-  if (rho != rho0) {   // leave the plan's tables at its own penalty
+  out.sigma = p->learn ? sigma : 0.0;
+  if (rho != rho0 && !p->learn) {   // leave the plan's tables at its own penalty
     const int rc2 = set_m1(rho0);
     if (rc == CIP_OK) rc = rc2;
   }
@@ -777,14 +818,14 @@ hipError_t conv_freq_pass(cip_plan_t p, int first, int zero_g, int do_z, hipStre
 // planes P = M S (3D) or M (2D, common filters); filter tables from g in
 // FP32. Start of a solve: g = the plan's filters, e = 0, the spectra of
 // g - e = g, and the tables from g.
-hipError_t cdl_tables(cip_plan_t p, const cx<float>* gspec, hipStream_t st) {
+hipError_t cdl_tables(cip_plan_t p, const cx<float>* gspec, double rho, hipStream_t st) {
   const Layout& L = p->L;
   const size_t F = (size_t)p->N1 * p->H2;
   if (p->kind == CIP_PRIOR_CONV3D)
     return conv_tables3f(gspec, p->at<cx<float>>(L.th32), p->at<float>(L.gam),
-                         p->at<const cx<float>>(L.bw), p->n_filters, p->S, F, (float)p->rho, st);
+                         p->at<const cx<float>>(L.bw), p->n_filters, p->S, F, (float)rho, st);
   return conv_tables2f(p->at<const cx<float>>(L.th32), p->at<float>(L.gam), p->at<float>(L.eta),
-                       p->n_filters, F, p->rho, p->mu, p->N1, p->N2, st);
+                       p->n_filters, F, rho, p->mu, p->N1, p->N2, st);
 }
 
 hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
@@ -808,7 +849,7 @@ hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
   if (!d3 && (e = hipMemcpyAsync(p->at<void>(L.th32), p->at<const void>(L.gehat), (size_t)P * F * 8,
                                  hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return e;
-  return cdl_tables(p, p->at<const cx<float>>(L.gehat), st);
+  return cdl_tables(p, p->at<const cx<float>>(L.gehat), p->rho, st);
 }
 
 // One step of the dictionary ADMM after the code update of an outer
@@ -819,7 +860,11 @@ hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
 // the placed g; e^ += g^ - d^ and the spectra of g - e; filter tables from
 // g^; d^ = D(g) z for the next x-update. Two batched 2D FFTs of the filter
 // planes per step.
-hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
+// One D, G, E step with penalty sigma; the code tables for the next
+// iterations from G at penalty rho. part (optional, a check of sigma): the
+// partial sums of k_cdl_fdual_res, G_prev kept in L.gprev.
+hipError_t cdl_step(cip_plan_t p, hipStream_t st, double sigma, double rho,
+                    float* part = nullptr) {
   const Layout& L = p->L;
   const bool d3 = p->kind == CIP_PRIOR_CONV3D;
   const int M = p->n_filters, S = p->S, per = d3 ? S : 1, P = M * per, Lf = p->filt_l;
@@ -833,10 +878,14 @@ hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
   float* dpl = p->at<float>(L.dpl);
   // dsp <- d^ + e^
   hipError_t e = d3 ? cdl_dfreq(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
-                                gehat, ehat, dsp, bw, M, S, F, (float)p->sigma, st)
+                                gehat, ehat, dsp, bw, M, S, F, (float)sigma, st)
                     : cdl_dfreq2(p->at<const cx<float>>(L.xhat), p->at<const cx<float>>(L.gv),
-                                 gehat, ehat, dsp, M, S, F, (float)p->sigma, st);
+                                 gehat, ehat, dsp, M, S, F, (float)sigma, st);
   if (e != hipSuccess) return e;
+  const size_t ntaps = (size_t)P * Lf * Lf;
+  if (part && (e = hipMemcpyAsync(p->at<void>(L.gprev), p->at<const void>(L.gtap), ntaps * 4,
+                                  hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return e;
   // d + e in space
   if ((e = conv_col_fft(-1, dsp, rtc, P, N1, H2, p->at<const cx<float>>(L.twN1f), st)) != hipSuccess)
     return e;
@@ -855,8 +904,12 @@ hipError_t cdl_step(cip_plan_t p, hipStream_t st) {
   // 3D: g^ to dsp (d^ + e^ is read first), then the band DFT into the
   // tables; 2D: g^ are the tables
   cx<float>* gspec = d3 ? dsp : p->at<cx<float>>(L.th32);
-  if ((e = cdl_fdual(ehat, gehat, dsp, gspec, (size_t)P * F, st)) != hipSuccess) return e;
-  if ((e = cdl_tables(p, gspec, st)) != hipSuccess) return e;
+  e = part ? cdl_fdual_res(ehat, gehat, dsp, gspec, (size_t)P * F, F, N1, N2,
+                           p->at<const float>(L.gtap), p->at<const float>(L.gprev), ntaps, part,
+                           st)
+           : cdl_fdual(ehat, gehat, dsp, gspec, (size_t)P * F, st);
+  if (e != hipSuccess) return e;
+  if ((e = cdl_tables(p, gspec, rho, st)) != hipSuccess) return e;
   if (d3)
     return conv_dhat3(p->at<const cx<float>>(L.gv), p->at<const cx<float>>(L.th32),
                       p->at<cx<float>>(L.dhat), bw, M, S, F, st);
@@ -875,7 +928,7 @@ hipError_t conv_iter(cip_plan_t p, int l, int last, hipStream_t st) {
   const int P = p->n_filters * p->S;
   hipError_t e = conv_freq_pass(p, l == 1, l == 1, last ? 0 : 1, st);
   if (e != hipSuccess || last) return e;
-  if (p->learn && (e = cdl_step(p, st)) != hipSuccess) return e;
+  if (p->learn && (e = cdl_step(p, st, p->sigma, p->rho)) != hipSuccess) return e;
   e = conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1, p->H2,
                    p->at<const cx<float>>(L.twN1f), st);
   if (e != hipSuccess) return e;
@@ -909,28 +962,43 @@ hipError_t solve_conv(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
 // stop with x^l when c < tol, else change rho by tau when one residual
 // exceeds mu times the other. Only the z-update depends on rho: on a change
 // the state is re-expressed for the new penalty (u scaled by rho / rho'),
-// g^ = F(t - u') is formed again, and gamma, eta (and theta) are rebuilt in
-// FP64 from the resident filter spectra. The plan's tables are back at its
-// own rho on return.
+// g^ = F(t - u') is formed again, and gamma, eta (and theta) are rebuilt:
+// in FP64 from the resident filter spectra for a fixed dictionary (the
+// plan's tables are back at its own rho on return), in FP32 from the
+// spectra of G with online dictionary learning. With learning and
+// adapt_sigma the D, G, E step of a checked iteration also yields
+//   r_d = ||D - G|| (Parseval over the spectra of the dual's change),
+//   s_d = sigma ||G - G_prev|| (over the filter taps),
+// and sigma changes by the same rule, the scaled dual E rescaled by
+// sigma / sigma'.
 int solve_conv_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x, hipStream_t st,
                         cip_solve_info& out) {
   const Layout& L = p->L;
   const int iters = prm->max_iters, every = prm->every;
-  const int M = p->n_filters, P = M * p->S;
+  const bool d3 = p->kind == CIP_PRIOR_CONV3D;
+  const int M = p->n_filters, P = M * p->S, Pf = M * (d3 ? p->S : 1);
   const size_t F = (size_t)p->N1 * p->H2;
   const double rho0 = p->rho;
-  double rho = rho0;
+  double rho = rho0, sigma = p->sigma;
   const size_t nres = conv_row_residual_floats(P, p->N1, p->N2);
   float* rs = p->at<float>(L.sums);
   float* xs = rs + nres;
   double* tot = reinterpret_cast<double*>(xs + 2 * XCHANGE_GROUPS);
+  float* dpart = xs + 2 * XCHANGE_GROUPS + 4;
+  double* dtot = reinterpret_cast<double*>(dpart + 2 * CDL_RES_GROUPS);
   float* xprev = p->at<float>(L.xbuf);
   const size_t nx = (size_t)p->S * p->N1 * p->N2;
   const size_t ncode = (size_t)P * p->N1 * p->N2;
-  const float zscale = (float)(1.0 / ((double)p->N1 * p->N2));
-  std::vector<float> hs(2 * XCHANGE_GROUPS + 4);
+  const double nn = (double)p->N1 * p->N2;
+  const float zscale = (float)(1.0 / nn);
+  // xs .. dtot + 2: k_xchange sums, the totals, the dictionary partials and totals
+  std::vector<float> hs(2 * XCHANGE_GROUPS + 4 + 2 * CDL_RES_GROUPS + 4);
+  // the spectra of G (the tables' source with learning): the tables
+  // themselves for 2D, the last D, G, E step's g^ for 3D
+  cx<float>* gspec = d3 ? p->at<cx<float>>(L.dsp) : p->at<cx<float>>(L.th32);
   auto set_tables = [&](double r) -> hipError_t {
-    if (p->kind == CIP_PRIOR_CONV3D)
+    if (p->learn) return cdl_tables(p, gspec, r, st);
+    if (d3)
       return conv_tables3(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
                           p->at<float>(L.gam), M, p->S, F, r, st);
     return conv_tables(p->at<const cx<double>>(L.th64), p->at<cx<float>>(L.th32),
@@ -945,6 +1013,7 @@ int solve_conv_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x
                    p->at<const cx<float>>(L.twN2f), st);
   };
   int rc = CIP_OK;
+  if (p->learn) HIP_TRY(cdl_start(p, st));
   for (int l = 1;; ++l) {
     const bool last = l == iters;
     HIP_TRY(conv_freq_pass(p, l == 1, l == 1, last ? 0 : 1, st));
@@ -955,7 +1024,9 @@ int solve_conv_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x
     }
     const bool check = l % every == 0;
     const bool store = (l + 1) % every == 0;
+    const bool check_sigma = check && p->learn && prm->adapt_sigma;
     const float kappa = (float)(p->lambda / rho);
+    if (p->learn) HIP_TRY(cdl_step(p, st, sigma, rho, check_sigma ? dpart : nullptr));
     HIP_TRY(conv_col_fft(-1, p->at<const cx<float>>(L.gv), p->at<cx<float>>(L.rtc), P, p->N1,
                          p->H2, p->at<const cx<float>>(L.twN1f), st));
     HIP_TRY(conv_row(p->at<const cx<float>>(L.rtc), p->at<cx<float>>(L.rtc), p->at<float>(L.vconv),
@@ -970,14 +1041,18 @@ int solve_conv_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x
     }
     if (!check) continue;
     HIP_TRY(launch(k_sum_pairs, 1, 256, 0, st, (const float*)rs, nres / 2, tot));
+    if (check_sigma)
+      HIP_TRY(launch(k_sum_pairs, 1, 256, 0, st, (const float*)dpart, (size_t)CDL_RES_GROUPS,
+                     dtot));
     HIP_TRY(hipMemcpyAsync(hs.data(), xs, hs.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    double d2 = 0.0, p2 = 0.0, tt[2];
+    double d2 = 0.0, p2 = 0.0, tt[2], td[2];
     for (int b = 0; b < XCHANGE_GROUPS; ++b) {
       d2 += hs[2 * b];
       p2 += hs[2 * b + 1];
     }
     std::memcpy(tt, hs.data() + 2 * XCHANGE_GROUPS, sizeof tt);
+    std::memcpy(td, hs.data() + 2 * XCHANGE_GROUPS + 4 + 2 * CDL_RES_GROUPS, sizeof td);
     const double r = std::sqrt(tt[0]), sres = rho * std::sqrt(tt[1]);
     out.r_norm = r;
     out.s_norm = sres;
@@ -1004,9 +1079,22 @@ int solve_conv_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_x
       rho = next;
       ++out.rho_changes;
     }
+    if (check_sigma) {
+      const double rd = std::sqrt(td[0] / nn), sd = sigma * std::sqrt(td[1]);
+      double ns = sigma;
+      if (rd > prm->mu * sd) ns = prm->tau * sigma;
+      else if (sd > prm->mu * rd) ns = sigma / prm->tau;
+      if (ns != sigma) {
+        HIP_TRY(cdl_rescale_dual(p->at<cx<float>>(L.ecdl), p->at<cx<float>>(L.gehat), gspec,
+                                 (size_t)Pf * F, (float)(sigma / ns), st));
+        sigma = ns;
+        ++out.sigma_changes;
+      }
+    }
   }
   out.rho = rho;
-  if (rho != rho0) {   // leave the plan's tables at its own penalty
+  out.sigma = p->learn ? sigma : 0.0;
+  if (rho != rho0 && !p->learn) {   // leave the plan's tables at its own penalty
     const hipError_t e = set_tables(rho0);
     if (e != hipSuccess && rc == CIP_OK) rc = fail(CIP_EHIP, hipGetErrorString(e));
   }
@@ -1498,10 +1586,11 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
   const bool synthesis = p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D ||
                          p->kind == CIP_PRIOR_CONV3D;
-  if ((synthesis && p->learn) || p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
+  if (p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED,
-                "adaptive penalty: l1 analysis priors and the synthesis priors with a fixed "
-                "dictionary");
+                "adaptive penalty: l1 analysis priors and the synthesis priors");
+  if (prm->adapt_sigma && !p->learn)
+    return fail(CIP_EUNSUPPORTED, "adapt_sigma: the plan does not learn its dictionary");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
       !(prm->tol >= 0.0))
     return fail(CIP_EINVAL, "need max_iters >= 1, every >= 1, tau > 1, mu > 1, tol >= 0");

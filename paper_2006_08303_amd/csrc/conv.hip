@@ -133,6 +133,18 @@ hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int
   return launch(k_cdl_project, M, 256, 0, st, dpl, e, gtap, S, N1, N2, L);
 }
 
+hipError_t cdl_fdual_res(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs,
+                         size_t n, size_t F, int N1, int N2, const float* gtap,
+                         const float* gprev, size_t ntaps, float* part, hipStream_t st) {
+  return launch(k_cdl_fdual_res, CDL_RES_GROUPS, 256, 0, st, e, ge, sd, gs, n, F, N1, N2, gtap,
+                gprev, ntaps, part);
+}
+
+hipError_t cdl_rescale_dual(cx<float>* e, cx<float>* ge, const cx<float>* gs, size_t n, float c,
+                            hipStream_t st) {
+  return launch(k_cdl_rescale_dual, (int)((n + 255) / 256), 256, 0, st, e, ge, gs, n, c);
+}
+
 hipError_t cdl_fdual(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs, size_t n,
                      hipStream_t st) {
   return launch(k_cdl_fdual, (int)((n + 255) / 256), 256, 0, st, e, ge, sd, gs, n);

@@ -390,9 +390,19 @@ k_cdl_dfreq(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh
 // a_s = conj(Z_{.,s}) (rank S plus sigma I; the sum over the planes noted in
 // Section IV-B). Solved through the Woodbury identity in the form without
 // 1/sigma,  d = GE + A y,  (sigma I_S + A^H A) y = X - A^H GE,
-// with an S x S complex Cholesky factorisation per frequency.
+// with an S x S complex Cholesky factorisation per frequency. The condition
+// number of sigma I_S + A^H A is about ||A||^2 / sigma (1e5 .. 1e9 for small
+// sigma and strong codes), so the products, the factorisation and the solves
+// run in FP64 on the FP32 operands; only d^ + e^ is rounded to FP32.
 // zh [M][S][F] (codes), xhat [S][F], gehat, ehat and dsp [M][F]; dsp
-// receives d^ + e^.
+// receives d^ + e^. B holds the upper triangle of A^H A packed by rows,
+// element (s, t), t >= s, at tri(s, t); the factor L overwrites it in the
+// transposed position, L(i, j) at tri(j, i).
+template <int S>
+__device__ __forceinline__ constexpr int tri(int s, int t) {
+  return s * S - s * (s - 1) / 2 + (t - s);
+}
+
 template <int S>
 __global__ void __launch_bounds__(128)
 k_cdl_dfreq2(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ zh,
@@ -400,62 +410,81 @@ k_cdl_dfreq2(const cx<float>* __restrict__ xhat, const cx<float>* __restrict__ z
              cx<float>* __restrict__ dsp, int M, size_t F, float sigma) {
   const size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
-  cx<float> B[S][S], w[S];
+  constexpr int NT = S * (S + 1) / 2;
+  cx<double> B[NT], w[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    w[s] = xhat[(size_t)s * F + f];
-#pragma unroll
-    for (int t = 0; t < S; ++t) B[s][t] = cx<float>{0.f, 0.f};
+    const cx<float> xv = xhat[(size_t)s * F + f];
+    w[s] = cx<double>{(double)xv.x, (double)xv.y};
   }
-  for (int m = 0; m < M; ++m) {
-    cx<float> z[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) z[s] = zh[((size_t)m * S + s) * F + f];
-    const cx<float> ge = gehat[(size_t)m * F + f];
+  for (int i = 0; i < NT; ++i) B[i] = cx<double>{0.0, 0.0};
+  for (int m = 0; m < M; ++m) {
+    cx<double> z[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      w[s] = w[s] - cmul(z[s], ge);                                  // X - A^H GE
+      const cx<float> zv = zh[((size_t)m * S + s) * F + f];
+      z[s] = cx<double>{(double)zv.x, (double)zv.y};
+    }
+    const cx<float> gf = gehat[(size_t)m * F + f];
+    const cx<double> ge = {(double)gf.x, (double)gf.y};
 #pragma unroll
-      for (int t = s; t < S; ++t) B[s][t] = B[s][t] + cmulc(z[s], z[t]);   // (A^H A)_{s,t}
+    for (int s = 0; s < S; ++s) {
+      w[s] = w[s] - cmul(z[s], ge);                                       // X - A^H GE
+#pragma unroll
+      for (int t = s; t < S; ++t) B[tri<S>(s, t)] = B[tri<S>(s, t)] + cmulc(z[s], z[t]);
     }
   }
-  // Cholesky B = L L^H (B[s][t], t >= s, holds the upper triangle); L in the
-  // lower triangle of B
+  // Cholesky sigma I + A^H A = L L^H. Every pivot is at least sigma (a Schur
+  // complement of a PSD matrix plus sigma I): a smaller computed pivot is
+  // rounding and is raised to sigma.
+  const double sg = (double)sigma;
 #pragma unroll
   for (int j = 0; j < S; ++j) {
-    float djj = B[j][j].x + sigma;
+    double djj = B[tri<S>(j, j)].x + sg;
 #pragma unroll
-    for (int k = 0; k < j; ++k) djj -= B[j][k].x * B[j][k].x + B[j][k].y * B[j][k].y;
-    const float ljj = __builtin_sqrtf(djj), il = 1.f / ljj;
-    B[j][j] = cx<float>{ljj, 0.f};
+    for (int k = 0; k < j; ++k) {
+      const cx<double> l = B[tri<S>(k, j)];
+      djj -= l.x * l.x + l.y * l.y;
+    }
+    djj = djj > sg ? djj : sg;
+    const double ljj = sqrt(djj), il = 1.0 / ljj;
+    B[tri<S>(j, j)] = cx<double>{ljj, 0.0};
 #pragma unroll
     for (int i = j + 1; i < S; ++i) {
-      cx<float> a = conjx(B[j][i]);   // B[i][j] = conj(B[j][i])
+      cx<double> a = conjx(B[tri<S>(j, i)]);   // (A^H A)_{i,j} = conj((A^H A)_{j,i})
 #pragma unroll
-      for (int k = 0; k < j; ++k) a = a - cmulc(B[i][k], B[j][k]);
-      B[i][j] = cx<float>{a.x * il, a.y * il};
+      for (int k = 0; k < j; ++k) a = a - cmulc(B[tri<S>(k, i)], B[tri<S>(k, j)]);
+      B[tri<S>(j, i)] = cx<double>{a.x * il, a.y * il};
     }
   }
   // L u = w, then L^H y = u
 #pragma unroll
   for (int i = 0; i < S; ++i) {
-    cx<float> a = w[i];
+    cx<double> a = w[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) a = a - cmul(B[i][k], w[k]);
-    w[i] = cx<float>{a.x / B[i][i].x, a.y / B[i][i].x};
+    for (int k = 0; k < i; ++k) a = a - cmul(B[tri<S>(k, i)], w[k]);
+    const double d = B[tri<S>(i, i)].x;
+    w[i] = cx<double>{a.x / d, a.y / d};
   }
 #pragma unroll
   for (int i = S - 1; i >= 0; --i) {
-    cx<float> a = w[i];
+    cx<double> a = w[i];
 #pragma unroll
-    for (int k = i + 1; k < S; ++k) a = a - cmul(conjx(B[k][i]), w[k]);
-    w[i] = cx<float>{a.x / B[i][i].x, a.y / B[i][i].x};
+    for (int k = i + 1; k < S; ++k) a = a - cmul(conjx(B[tri<S>(i, k)]), w[k]);
+    const double d = B[tri<S>(i, i)].x;
+    w[i] = cx<double>{a.x / d, a.y / d};
   }
   for (int m = 0; m < M; ++m) {
-    cx<float> d = gehat[(size_t)m * F + f];
+    const cx<float> gf = gehat[(size_t)m * F + f];
+    cx<double> d = {(double)gf.x, (double)gf.y};
 #pragma unroll
-    for (int s = 0; s < S; ++s) d = d + cmul(conjx(zh[((size_t)m * S + s) * F + f]), w[s]);
-    dsp[(size_t)m * F + f] = d + ehat[(size_t)m * F + f];
+    for (int s = 0; s < S; ++s) {
+      const cx<float> zv = zh[((size_t)m * S + s) * F + f];
+      d = d + cmul(cx<double>{(double)zv.x, -(double)zv.y}, w[s]);
+    }
+    const cx<float> ev = ehat[(size_t)m * F + f];
+    dsp[(size_t)m * F + f] = cx<float>{(float)(d.x + (double)ev.x), (float)(d.y + (double)ev.y)};
   }
 }
 
@@ -550,6 +579,64 @@ __global__ void k_cdl_fdual(cx<float>* __restrict__ e, cx<float>* ge, const cx<f
   e[i] = en;
   ge[i] = g - en;
   gs[i] = g;
+}
+
+// k_cdl_fdual at a check of the dictionary penalty (the rule of Section IV-C
+// applied to sigma): the same updates, grid-stride over the work-groups, and
+// per work-group b
+//   part[2 b] = sum w |e^_new - e^_old|^2 = sum w |g^ - d^|^2, w = 1 on the
+//     half-spectrum columns k2 = 0 and N2 / 2 and 2 elsewhere, so that the
+//     total is N1 N2 ||D - G||^2 (Parseval, unnormalised transforms);
+//   part[2 b + 1] = sum (gtap - gprev)^2 over the ntaps filter taps
+//     (= ||G - G_prev||^2).
+__global__ void __launch_bounds__(256)
+k_cdl_fdual_res(cx<float>* __restrict__ e, cx<float>* ge, const cx<float>* sd, cx<float>* gs,
+                size_t n, size_t F, int N1, int N2, const float* __restrict__ gtap,
+                const float* __restrict__ gprev, size_t ntaps, float* __restrict__ part) {
+  __shared__ float red[2][4];
+  const size_t stride = (size_t)gridDim.x * 256;
+  float a = 0.f, b = 0.f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const cx<float> g = ge[i], sv = sd[i], eo = e[i];
+    const cx<float> en = g + eo + eo - sv;
+    e[i] = en;
+    ge[i] = g - en;
+    gs[i] = g;
+    const int k2 = (int)((i % F) / (size_t)N1);
+    const float w = (k2 == 0 || 2 * k2 == N2) ? 1.f : 2.f;
+    const float dx = en.x - eo.x, dy = en.y - eo.y;
+    a += w * (dx * dx + dy * dy);
+  }
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < ntaps; i += stride) {
+    const float d = gtap[i] - gprev[i];
+    b += d * d;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    part[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// A change sigma -> sigma' of the dictionary penalty: the scaled dual
+// e^ <- c e^ (c = sigma / sigma'), and the next right-hand side ge = g^ - e^
+// formed again from gs = g^.
+__global__ void k_cdl_rescale_dual(cx<float>* __restrict__ e, cx<float>* __restrict__ ge,
+                                   const cx<float>* __restrict__ gs, size_t n, float c) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const cx<float> en = cx<float>{c * e[i].x, c * e[i].y};
+  e[i] = en;
+  ge[i] = gs[i] - en;
 }
 
 // e^ = 0 (start of a solve)

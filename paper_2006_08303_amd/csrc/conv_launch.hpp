@@ -40,6 +40,15 @@ hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int
 // e^ += g^ - d^, ge = g^ - e^, gs = g^
 hipError_t cdl_fdual(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs, size_t n,
                      hipStream_t st);
+// the same at a check of sigma: partial sums of |g^ - d^|^2 (half-spectrum
+// weights) and of |gtap - gprev|^2, one pair per work-group (CDL_RES_GROUPS)
+constexpr int CDL_RES_GROUPS = 1024;
+hipError_t cdl_fdual_res(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs,
+                         size_t n, size_t F, int N1, int N2, const float* gtap,
+                         const float* gprev, size_t ntaps, float* part, hipStream_t st);
+// sigma -> sigma': e^ <- c e^, ge = gs - e^ (c = sigma / sigma')
+hipError_t cdl_rescale_dual(cx<float>* e, cx<float>* ge, const cx<float>* gs, size_t n, float c,
+                            hipStream_t st);
 hipError_t cdl_fzero(cx<float>* e, size_t n, hipStream_t st);
 hipError_t cdl_place(const float* gtap, float* out, int M, int S, int N1, int N2, int L,
                      hipStream_t st);

@@ -101,8 +101,23 @@ static hipError_t trsolve(const float* lt, int m, const float* b, int bsr, int b
 }
 
 // One step of the dictionary ADMM and the new code tables (see patch_dl.hpp).
+hipError_t patch_dict_m1(const PatchDictBufs& b, int S, int NA, float rho, hipStream_t st) {
+  const int nv = 64 * S;
+  hipError_t e;
+  hipLaunchKernelGGL(k_pdl_gram, dim3(nv / 16, nv / 16), dim3(256), 0, st, (const float*)b.g, NA,
+                     rho, b.cm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
+    return e;
+  return trsolve(b.lt, nv, b.g, 1, NA, NA, nullptr, b.m1bf, st);
+}
+
+hipError_t patch_dict_scale_dual(const PatchDictBufs& b, int count, float c, hipStream_t st) {
+  return launch(k_pdl_scale, (count + 255) / 256, 256, 0, st, b.e, count, c);
+}
+
 hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
-                           float sigma, float rho, hipStream_t st) {
+                           float sigma, float rho, hipStream_t st, double* res) {
   const PatchGeo G = patch_geo(N1, N2);
   const int nv = 64 * S, rows = nv + NA;
   const int KS = patch_dict_splits(N1, N2);
@@ -121,16 +136,11 @@ hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA
     return e;
   if ((e = trsolve(b.lt, NA, b.bm, NA, 1, nv, b.d, nullptr, st)) != hipSuccess) return e;
   // G, E and the BF16 dictionary
-  if ((e = launch(k_pdl_project, 1, 1024, 0, st, (const float*)b.d, b.g, b.e, b.dbf, nv * NA)) !=
-      hipSuccess)
+  if ((e = launch(k_pdl_project, 1, 1024, 0, st, (const float*)b.d, b.g, b.e, b.dbf, nv * NA,
+                  res)) != hipSuccess)
     return e;
   // M1 = G^T (rho I + G G^T)^-1 in BF16
-  hipLaunchKernelGGL(k_pdl_gram, dim3(nv / 16, nv / 16), dim3(256), 0, st, (const float*)b.g, NA,
-                     rho, b.cm);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
-    return e;
-  return trsolve(b.lt, nv, b.g, 1, NA, NA, nullptr, b.m1bf, st);
+  return patch_dict_m1(b, S, NA, rho, st);
 }
 
 bool patch_grid_ok(int N1, int N2) {

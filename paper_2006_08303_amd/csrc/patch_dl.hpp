@@ -384,11 +384,12 @@ k_pdl_trsolve(const float* __restrict__ lt, int m, const float* __restrict__ b, 
 
 // G = (D + E) / ||D + E||_F, E <- E + G - D, and G in BF16 (count = n A
 // entries, one work-group of 1024 threads; the squared norm is summed in
-// FP64 in a fixed order).
+// FP64 in a fixed order). res (optional, a check of the dictionary penalty):
+// res[0] = ||D - G||^2, res[1] = ||G - G_prev||^2 in FP64.
 __global__ void __launch_bounds__(1024)
 k_pdl_project(const float* __restrict__ d, float* __restrict__ g, float* __restrict__ e,
-              uint16_t* __restrict__ gbf, int count) {
-  __shared__ double red[16];
+              uint16_t* __restrict__ gbf, int count, double* __restrict__ res) {
+  __shared__ double red[16], red2[2][16];
   double s = 0.0;
   for (int i = threadIdx.x; i < count; i += 1024) {
     const double w = (double)d[i] + (double)e[i];
@@ -402,13 +403,48 @@ k_pdl_project(const float* __restrict__ d, float* __restrict__ g, float* __restr
 #pragma unroll
   for (int k = 0; k < 16; ++k) tot += red[k];
   const float inv = (float)(1.0 / sqrt(tot));
+  double rd = 0.0, sd = 0.0;
   for (int i = threadIdx.x; i < count; i += 1024) {
     const float dv = d[i], ev = e[i];
     const float gv = (dv + ev) * inv;
+    if (res) {
+      const double a = (double)gv - (double)dv, b = (double)gv - (double)g[i];
+      rd += a * a;
+      sd += b * b;
+    }
     g[i] = gv;
     e[i] = ev + gv - dv;
     gbf[i] = f2bf(gv);
   }
+  if (res) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      rd += __shfl_down(rd, off, 64);
+      sd += __shfl_down(sd, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red2[0][threadIdx.x >> 6] = rd;
+      red2[1][threadIdx.x >> 6] = sd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        a += red2[0][k];
+        b += red2[1][k];
+      }
+      res[0] = a;
+      res[1] = b;
+    }
+  }
+}
+
+// E <- c E (count entries): a change sigma -> sigma' of the dictionary
+// penalty rescales the scaled dual by c = sigma / sigma'.
+__global__ void k_pdl_scale(float* __restrict__ e, int count, float c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) e[i] *= c;
 }
 
 // cm[i * 256 + k] = rho [i == k] + sum_a G[i][a] G[k][a] for i >= k

@@ -30,8 +30,14 @@ struct PatchDictBufs {
 int patch_dict_splits(int N1, int N2);
 hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int NA,
                             hipStream_t st);
+// one D, G, E step and M1 of the new G; res (optional, device): ||D - G||^2,
+// ||G - G_prev||^2 in FP64
 hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
-                           float sigma, float rho, hipStream_t st);
+                           float sigma, float rho, hipStream_t st, double* res = nullptr);
+// M1 = G^T (rho I + G G^T)^-1 (BF16) of the current G
+hipError_t patch_dict_m1(const PatchDictBufs& b, int S, int NA, float rho, hipStream_t st);
+// E <- c E (count = n A entries)
+hipError_t patch_dict_scale_dual(const PatchDictBufs& b, int count, float c, hipStream_t st);
 hipError_t patch_assemble_launch(int S, const float* tb, float* r, int N1, int N2, hipStream_t st);
 
 }  // namespace cip

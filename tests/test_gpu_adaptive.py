@@ -218,3 +218,115 @@ def test_conv_adaptive_without_change_equals_plain_solve_and_restores_tables(kin
     _, info = low.solve_adaptive(yt, 40, every=5, tol=0.0)
     assert info["rho_changes"] > 0
     assert np.array_equal(_np(low.solve(yt, 20)), before)
+
+
+def _changes(seq):
+    return sum(1 for a, b in zip(seq, seq[1:]) if a != b)
+
+
+# Dictionary learning with the adaptive rule (oracle traces, lambda =
+# 1.875e-6, beta = 8): every rho and sigma decision at least a factor 2.1
+# from the mu threshold. Online learning amplifies perturbations of the
+# dictionary: rounding G to FP32 after every step moves the oracle's own x by
+# 1e-5 .. 4e-5 within 20 iterations at rho = 1e-4, and a 1e-6 relative change
+# of y moves it by 2e-4 .. 4e-3 within 40 iterations of these runs. The runs
+# stop where the FP32 rounding of G moves the oracle's x by at most 2.6e-6
+# (15 or 20 iterations), so FP32 can follow FP64.
+@pytest.mark.parametrize("kind,rho0,sigma0,maxit,adapt_sigma", [
+    ("conv2d", 100.0, 10.0, 20, True),     # 3 rho halvings, 2 sigma changes
+    ("conv2d", 1e-2, 1e-2, 20, True),      # no rho change, 3 sigma doublings
+    ("conv2d", 1e-4, 10.0, 15, False),     # 2 rho doublings, sigma fixed
+    ("conv3d", 10.0, 1e3, 20, True),       # 3 rho halvings, 2 sigma changes
+])
+def test_conv_learning_adaptive_matches_oracle(kind, rho0, sigma0, maxit, adapt_sigma):
+    """Online dictionary learning (M = 8 filters of 5 x 5) with the adaptive
+    penalty rho and, with adapt_sigma, the same rule for the dictionary
+    penalty sigma: the GPU takes the oracle's rho and sigma trajectories (the
+    counts of changes and the final values) and x stays within 1e-4."""
+    dims = 3 if kind == "conv3d" else 2
+    print(f"adaptive learning {kind} rho0={rho0} sigma0={sigma0} maxit={maxit} "
+          f"adapt_sigma={adapt_sigma}", flush=True)
+    x, psf, y, filt = _conv_problem(64, 3, 3, 8, 5, dims)
+    lam, beta = 1.875e-6, 8.0
+    alg = admm.ConvADMM(psf, filt, lam, rho0, beta, tier="freq", dims=dims, dict_update=True,
+                        sigma=sigma0)
+    ref, rinfo = alg.run_adaptive(y, maxit, every=5, tol=1e-4, adapt_sigma=adapt_sigma)
+    plan = cip.Plan(_t(psf), kind, rho0, lam, beta, filters=_t(filt), adaptive=True,
+                    dict_update=True, sigma=sigma0)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=5, tol=1e-4, adapt_sigma=adapt_sigma)
+    got = _np(got)
+    print(f"  oracle: rho {rinfo['rho']:.4g} ({_changes(rinfo['rhos'])}) sigma "
+          f"{rinfo['sigma']:.4g} ({_changes(rinfo['sigmas'])}); gpu: rho {ginfo['rho']:.4g} "
+          f"({ginfo['rho_changes']}) sigma {ginfo['sigma']:.4g} ({ginfo['sigma_changes']})",
+          flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == _changes(rinfo["rhos"])
+    assert ginfo["sigma"] == pytest.approx(rinfo["sigma"], rel=1e-12)
+    assert ginfo["sigma_changes"] == _changes(rinfo["sigmas"])
+    parity.check(got, ref, 1e-4, label=f"{kind} learning adaptive x")
+
+
+# Patch dictionary (A = 128, ||D||_F = 1, lambda = 5e-5, beta = 500, sigma
+# proportional to the patch count J as in the fixed-rho learning tests):
+# the caps keep every decision at least a factor 3.1 from the threshold.
+# Rounding G to FP32 after every step moves the oracle's x by 3.5e-7 and
+# 2.9e-4 in these runs (by 9.6e-4 from rho0 = 1e-4, sigma0 = 1000 J, where
+# sigma falls to 125 J: beyond what the FP32 dictionary step resolves).
+@pytest.mark.parametrize("rho0,sigma_per_patch,maxit", [
+    (1.0, 1000.0, 21),      # 4 rho halvings, 3 sigma changes
+    (1e-4, 1e5, 16),        # 3 rho doublings, 3 sigma halvings
+])
+def test_patch_learning_adaptive_matches_oracle(rho0, sigma_per_patch, maxit):
+    """Patch-dictionary learning with adaptive rho and sigma: the oracle's
+    trajectories, x within the BF16 bar (2e-3)."""
+    N, S, A = 64, 3, 128
+    sigma0 = sigma_per_patch * (N // 4) ** 2
+    print(f"adaptive learning patch rho0={rho0} sigma0={sigma0} maxit={maxit}", flush=True)
+    x, psf, y = _problem(N, 3, S, 9)
+    D = synth.random_unit_atoms(synth.rng_for(9, 4), 64 * S, A)
+    D = (D / np.linalg.norm(D)).astype(np.float32).astype(np.float64)
+    lam, beta = 5e-5, 500.0
+    alg = admm.PatchADMM(psf, D, 8, 4, lam, rho0, beta, tier="freq", dict_update=True,
+                         sigma=sigma0)
+    ref, rinfo = alg.run_adaptive(y, maxit, every=5, tol=1e-4, adapt_sigma=True)
+    plan = cip.Plan(_t(psf), "patch", rho0, lam, beta, dictionary=_t(D), adaptive=True,
+                    dict_update=True, sigma=sigma0)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=5, tol=1e-4, adapt_sigma=True)
+    got = _np(got)
+    print(f"  oracle: rho {rinfo['rho']:.4g} ({_changes(rinfo['rhos'])}) sigma "
+          f"{rinfo['sigma']:.4g} ({_changes(rinfo['sigmas'])}); gpu: rho {ginfo['rho']:.4g} "
+          f"({ginfo['rho_changes']}) sigma {ginfo['sigma']:.4g} ({ginfo['sigma_changes']})",
+          flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == _changes(rinfo["rhos"])
+    assert ginfo["sigma"] == pytest.approx(rinfo["sigma"], rel=1e-12)
+    assert ginfo["sigma_changes"] == _changes(rinfo["sigmas"])
+    parity.check(got, ref, 2e-3, label="patch learning adaptive x")
+
+
+def test_learning_adaptive_without_changes_equals_plain_solve():
+    """With tau so close to 1 that no residual ratio passes mu = 1e30, the
+    adaptive solve of a learning plan is its plain solve, bitwise (conv and
+    patch), and adapt_sigma on a fixed-dictionary plan is refused."""
+    x, psf, y, filt = _conv_problem(64, 3, 3, 8, 5, 2)
+    yt = _t(y)
+    plan = cip.Plan(_t(psf), "conv2d", 1e-4, 1.875e-6, 8.0, filters=_t(filt), adaptive=True,
+                    dict_update=True, sigma=10.0)
+    plain = _np(plan.solve(yt, 12))
+    got, info = plan.solve_adaptive(yt, 12, every=3, tol=0.0, mu=1e30, adapt_sigma=True)
+    assert info["rho_changes"] == 0 and info["sigma_changes"] == 0 and info["iters"] == 12
+    assert np.array_equal(_np(got), plain)
+    D = synth.random_unit_atoms(synth.rng_for(9, 4), 192, 128)
+    D = (D / np.linalg.norm(D)).astype(np.float32).astype(np.float64)
+    pp = cip.Plan(_t(psf), "patch", 1e-4, 5e-5, 500.0, dictionary=_t(D), adaptive=True,
+                  dict_update=True, sigma=2.56e5)
+    plain = _np(pp.solve(yt, 12))
+    got, info = pp.solve_adaptive(yt, 12, every=3, tol=0.0, mu=1e30, adapt_sigma=True)
+    assert info["rho_changes"] == 0 and info["sigma_changes"] == 0
+    assert np.array_equal(_np(got), plain)
+    fixed = cip.Plan(_t(psf), "conv2d", 1e-4, 1.875e-6, 8.0, filters=_t(filt), adaptive=True)
+    with pytest.raises(cip.CipError) as e:
+        fixed.solve_adaptive(yt, 10, adapt_sigma=True)
+    assert e.value.code == -2
