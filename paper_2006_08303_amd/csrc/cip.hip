@@ -72,6 +72,7 @@ struct Layout {
   size_t xbuf, sums;                    // adaptive solves: iterates, norm partial sums
   size_t dbf, m1bf, vpatch, tbuf, rimg;  // patch prior: D, M1 (bf16), codes, tiles, P^T D z
   size_t dbf0, m1bf0, pd0, pzf, ppart, pbm, pd, pcm, plt, pg, pe;  // patch dictionary learning
+  size_t pcm64, plt64;                  // FP64 matrix and factor of the D-step
   size_t th32, gam, eta, gv, dhat, xhat, rtc, vconv, th64;  // conv prior
   size_t bw;                                                 // 3D conv: band DFT matrix
   size_t wband, wcoef, wtmp;            // wavelet (x) DCT: band DCT, coefficients, staging
@@ -177,11 +178,13 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
       L.m1bf0 = tab(na * nv * 2);
       L.pd0 = tab(nv * na * 4);
       L.pzf = sta(na * J * 4);
-      L.ppart = sta(KS * (nv + na) * na * 4);
-      L.pbm = sta(nv * na * 4);
-      L.pd = sta(nv * na * 4);
+      L.ppart = sta(KS * (nv + na) * na * 8);
+      L.pbm = sta(nv * na * 8);
+      L.pd = sta(nv * na * 8);
       L.pcm = sta((size_t)256 * 256 * 4);
       L.plt = sta((size_t)256 * 256 * 4);
+      L.pcm64 = sta((size_t)256 * 256 * 8);
+      L.plt64 = sta((size_t)2 * 256 * 256 * 8);
       L.pg = sta(nv * na * 4);
       L.pe = sta(nv * na * 4);
     }
@@ -557,9 +560,11 @@ PatchDictBufs patch_dict_bufs(cip_plan_t p) {
   const Layout& L = p->L;
   PatchDictBufs b;
   b.zf = p->at<float>(L.pzf);
-  b.part = p->at<float>(L.ppart);
-  b.bm = p->at<float>(L.pbm);
-  b.d = p->at<float>(L.pd);
+  b.part = p->at<double>(L.ppart);
+  b.bm = p->at<double>(L.pbm);
+  b.d = p->at<double>(L.pd);
+  b.cm64 = p->at<double>(L.pcm64);
+  b.lt64 = p->at<double>(L.plt64);
   b.cm = p->at<float>(L.pcm);
   b.lt = p->at<float>(L.plt);
   b.g = p->at<float>(L.pg);
@@ -578,7 +583,7 @@ hipError_t patch_step(cip_plan_t p, const float* x, int first, hipStream_t st) {
     e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), b.dbf,
                        b.m1bf, p->N1, p->N2, kappa, first, st, PZ_MODE_CODES, b.zf);
     if (e != hipSuccess) return e;
-    e = patch_dict_step(x, b, p->S, p->n_atoms, p->N1, p->N2, (float)p->sigma, (float)p->rho, st);
+    e = patch_dict_step(x, b, p->S, p->n_atoms, p->N1, p->N2, p->sigma, (float)p->rho, st);
     if (e != hipSuccess) return e;
     e = patch_z_launch(p->S, p->n_atoms, x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), b.dbf,
                        b.m1bf, p->N1, p->N2, kappa, first, st, PZ_MODE_SYNTH, b.zf);
@@ -693,7 +698,7 @@ int solve_patch_adaptive(cip_plan_t p, const cip_adaptive_params* prm, float* d_
       HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), db.dbf,
                              db.m1bf, p->N1, p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_CODES,
                              db.zf, check ? rs : nullptr));
-      HIP_TRY(patch_dict_step(d_x, db, p->S, na, p->N1, p->N2, (float)sigma, (float)rho, st,
+      HIP_TRY(patch_dict_step(d_x, db, p->S, na, p->N1, p->N2, sigma, (float)rho, st,
                               check_sigma ? dres : nullptr));
       HIP_TRY(patch_z_launch(p->S, na, d_x, p->at<float>(L.vpatch), p->at<float>(L.tbuf), db.dbf,
                              db.m1bf, p->N1, p->N2, kappa, l == 1 ? 1 : 0, st, PZ_MODE_SYNTH,

@@ -56,7 +56,7 @@ size_t patch_tile_buffer_floats(int S, int N1, int N2) {
 int patch_dict_splits(int N1, int N2) {
   const size_t J = (size_t)(N1 / PATCH_ST) * (N2 / PATCH_ST);
   const size_t ks = J / PDL_KSTEP;
-  return (int)(ks < 16 ? ks : 16);
+  return (int)(ks < 64 ? ks : 64);
 }
 
 hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int NA,
@@ -107,7 +107,8 @@ hipError_t patch_dict_m1(const PatchDictBufs& b, int S, int NA, float rho, hipSt
   hipLaunchKernelGGL(k_pdl_gram, dim3(nv / 16, nv / 16), dim3(256), 0, st, (const float*)b.g, NA,
                      rho, b.cm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, nv, b.lt)) != hipSuccess)
+  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, nv,
+                  b.lt)) != hipSuccess)
     return e;
   return trsolve(b.lt, nv, b.g, 1, NA, NA, nullptr, b.m1bf, st);
 }
@@ -117,26 +118,37 @@ hipError_t patch_dict_scale_dual(const PatchDictBufs& b, int count, float c, hip
 }
 
 hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
-                           float sigma, float rho, hipStream_t st, double* res) {
+                           double sigma, float rho, hipStream_t st, double* res) {
   const PatchGeo G = patch_geo(N1, N2);
   const int nv = 64 * S, rows = nv + NA;
   const int KS = patch_dict_splits(N1, N2);
   const int chunk = (int)(((size_t)G.J1 * G.J2) / KS);
-  if (nv > PDL_MAXM || NA > PDL_MAXM || chunk % PDL_KSTEP) return hipErrorInvalidValue;
+  if (nv > PDL_MAXM || NA > PDL_MAXM || NA % 64 || chunk % PDL_KSTEP) return hipErrorInvalidValue;
   hipError_t e;
-  hipLaunchKernelGGL(k_pdl_gemm, dim3(rows / 64, NA / 64, KS), dim3(256), 0, st, x, b.zf, b.part,
-                     G, S, NA, chunk);
+  // X Z^T and Z Z^T in FP64
+  hipLaunchKernelGGL(k_pdl_gemm64, dim3(rows / 64, NA / 64, KS), dim3(256), 0, st, x, b.zf,
+                     b.part, G, S, NA, chunk);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t nr = (size_t)rows * NA;
-  if ((e = launch(k_pdl_reduce, (int)((nr + 255) / 256), 256, 0, st, (const float*)b.part,
-                  (const float*)b.g, (const float*)b.e, b.bm, b.cm, nv, NA, KS, sigma)) != hipSuccess)
+  if ((e = launch(k_pdl_reduce64, (int)((nr + 255) / 256), 256, 0, st, (const double*)b.part,
+                  (const float*)b.g, (const float*)b.e, b.bm, b.cm64, nv, NA, KS, sigma)) !=
+      hipSuccess)
     return e;
-  // D = B (Z Z^T + sigma I)^-1
-  if ((e = launch(k_pdl_chol, 1, PDL_CHOL_THREADS, 0, st, (const float*)b.cm, PDL_MAXM, NA, b.lt)) != hipSuccess)
+  // D = B (Z Z^T + sigma I)^-1 in FP64
+  double* lt2 = b.lt64 + (size_t)PDL_MAXM * PDL_MAXM;
+  if ((e = launch(k_pdl_chol64, 1, 256, 0, st, b.cm64, PDL_MAXM, NA, b.lt64, lt2)) != hipSuccess)
     return e;
-  if ((e = trsolve(b.lt, NA, b.bm, NA, 1, nv, b.d, nullptr, st)) != hipSuccess) return e;
+  const dim3 tg((nv + 3) / 4), tb(256);
+  switch (NA / 64) {
+    case 1: hipLaunchKernelGGL(k_pdl_trsolve64<1>, tg, tb, 0, st, b.lt64, lt2, NA, b.bm, nv, b.d); break;
+    case 2: hipLaunchKernelGGL(k_pdl_trsolve64<2>, tg, tb, 0, st, b.lt64, lt2, NA, b.bm, nv, b.d); break;
+    case 3: hipLaunchKernelGGL(k_pdl_trsolve64<3>, tg, tb, 0, st, b.lt64, lt2, NA, b.bm, nv, b.d); break;
+    case 4: hipLaunchKernelGGL(k_pdl_trsolve64<4>, tg, tb, 0, st, b.lt64, lt2, NA, b.bm, nv, b.d); break;
+    default: return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // G, E and the BF16 dictionary
-  if ((e = launch(k_pdl_project, 1, 1024, 0, st, (const float*)b.d, b.g, b.e, b.dbf, nv * NA,
+  if ((e = launch(k_pdl_project, 1, 1024, 0, st, (const double*)b.d, b.g, b.e, b.dbf, nv * NA,
                   res)) != hipSuccess)
     return e;
   // M1 = G^T (rho I + G G^T)^-1 in BF16

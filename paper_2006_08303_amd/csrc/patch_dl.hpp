@@ -7,22 +7,28 @@
 // with X = [P_1 x | ... | P_J x] (n x J, n = 64 S) and Z (A x J). The next x-
 // and code updates use G: its BF16 copy and M1 = G^T (rho I + G G^T)^-1.
 //
-// Arithmetic is FP32 except where noted:
-//   k_pdl_gemm     the products X Z^T and Z Z^T on BF16 MFMA with split
-//                  operands (hi + lo, three products, FP32 accumulation:
-//                  about 16 significant bits), split over the patches, every
-//                  split written to its own slice (no atomics);
-//   k_pdl_reduce   fixed-order sum of the slices, + sigma (G - E) and sigma I;
-//   k_pdl_chol     Cholesky factor of an SPD matrix of order m <= 256 in one
-//                  work-group: the lower half of the matrix (padded with the
-//                  identity to 256 x 256) lives in registers, 8 x 8 per
-//                  thread, and the pivot columns are broadcast through LDS
-//                  (one barrier per two columns);
-//   k_pdl_trsolve  rows of B M^-1 = B L^-T L^-1, one row per wave, L packed
-//                  in LDS;
-//   k_pdl_project  the Frobenius projection and the dual update (one
-//                  work-group, FP64 norm);
-//   k_pdl_gram     rho I + G G^T.
+// Z Z^T + sigma I is ill-conditioned at the paper's sigma = 1 (its largest
+// eigenvalue grows with the patch count: about 1e6 relative to sigma at
+// 1024^2), so the D-step runs in FP64 on the FP32 operands x and Z:
+//   k_pdl_gemm64   X Z^T and Z Z^T on FP64 MFMA (v_mfma_f64_16x16x4), the
+//                  products of FP32 operands exact, FP64 accumulation, split
+//                  over the patches, every split written to its own slice
+//                  (no atomics);
+//   k_pdl_reduce64 fixed-order sum of the slices, + sigma (G - E) and sigma I;
+//   k_pdl_chol64   Cholesky factor of Z Z^T + sigma I (order A <= 256),
+//                  blocked right-looking in one work-group: 16-column panels
+//                  factored by one wave in registers (readlane broadcasts, no
+//                  barriers), trailing updates by all waves in 8 x 8
+//                  register tiles from the panel in LDS;
+//   k_pdl_trsolve64  rows of B M^-1 = B L^-T L^-1 in FP64, one row per wave,
+//                  L read from global memory (L2) a few columns ahead;
+//   k_pdl_project  the Frobenius projection (FP64 norm) and the dual update
+//                  from the FP64 D; G and E kept in FP32.
+// M1 = G^T (rho I + G G^T)^-1 (well conditioned for the unit-norm G and the
+// rho of the code split) stays FP32: k_pdl_gram, k_pdl_chol (FP32, one
+// work-group, the matrix in registers, 8 x 8 per thread, pivot columns
+// broadcast through LDS) and k_pdl_trsolve (L packed in LDS), with the BF16
+// copy of M1 as output.
 #pragma once
 #include "patch.hpp"
 
@@ -31,27 +37,30 @@ namespace cip {
 constexpr int PDL_MAXM = 256;    // largest system order (A or n = 64 S)
 constexpr int PDL_KSTEP = 32;    // patches per LDS stage of k_pdl_gemm
 
-// Split-K products W Z^T with W = [X; Z] ((n + A) x J). Work-group
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Split-K products W Z^T with W = [X; Z] ((n + A) x J) in FP64. Work-group
 // (rb, cb, ks) computes the 64 x 64 block (rb, cb) over the patches
 // [ks * chunk, (ks + 1) * chunk) and writes it to part[ks] ((n + A) x A,
 // row-major). Rows rb < S are the patch rows of plane s = rb (row
 // 64 s + 8 a + b, patch j = pi J2 + pj: pixel x[s][4 pi + a][4 pj + b],
-// circular); blocks of Z Z^T above the diagonal are skipped.
+// circular); blocks of Z Z^T above the diagonal are skipped. Each stage of
+// 32 patches is staged in LDS as FP64 (the FP32 values convert exactly);
+// wave (wr, wc) computes the 32 x 32 quarter (wr, wc) as 2 x 2 tiles of
+// v_mfma_f64_16x16x4 (lane l: A[l % 16][l / 16], B[l / 16][l % 16]; result
+// register r: D[l / 16 + 4 r][l % 16]).
 // Requires chunk % 32 == 0, J % chunk == 0, J2 a power of two.
+constexpr int PDL_LS64 = PDL_KSTEP + 1;   // LDS row stride (doubles)
+
 __global__ void __launch_bounds__(256)
-k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __restrict__ part,
-           PatchGeo G, int S, int NA, int chunk) {
-  // operands split as x = hi + lo, both BF16 (x - hi is exact in FP32, lo
-  // keeps its leading 8 bits): products hi*hi + hi*lo + lo*hi on BF16 MFMA
-  // with FP32 accumulation carry about 16 significant bits
-  constexpr int LS = PDL_KSTEP + 8;   // LDS row stride (bf16), rows 16-byte aligned
-  __shared__ __align__(16) uint16_t Ah[64][LS], Al[64][LS], Bh[64][LS], Bl[64][LS];
+k_pdl_gemm64(const float* __restrict__ x, const float* __restrict__ zf, double* __restrict__ part,
+             PatchGeo G, int S, int NA, int chunk) {
+  __shared__ double As[64][PDL_LS64], Bs[64][PDL_LS64];
   const int rb = blockIdx.x, cb = blockIdx.y, ks = blockIdx.z;
   if (rb >= S && cb > rb - S) return;
   const int rows = 64 * S + NA;
   const size_t J = (size_t)G.J1 * G.J2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l32 = lane & 31, lhi = lane >> 5;
   const int wr = wave >> 1, wc = wave & 1;
   const int lr = threadIdx.x >> 2, lk = (threadIdx.x & 3) * 8;   // staging: row, 8 patches
   const int pa = lr >> 3, pb = lr & 7;
@@ -59,9 +68,13 @@ k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __r
   const float* zb = zf + (size_t)(64 * cb + lr) * J;
   const float* za = zf + (size_t)(64 * (rb >= S ? rb - S : 0) + lr) * J;
   const float* xs = x + (size_t)(rb < S ? rb : 0) * G.N1 * G.N2;
-  f32x16 acc = f32x16{};
-  // stage j0's operands are loaded into registers while stage j0 - 32
-  // runs on the MFMA units (software pipelining over the patches)
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // the next stage's operands are loaded into registers while the current
+  // stage runs on the MFMA units
   auto load = [&](size_t j0, float (&av)[8], float (&bv)[8]) {
     const float4* bp = reinterpret_cast<const float4*>(zb + j0 + lk);
     const float4 b0 = bp[0], b1 = bp[1];
@@ -83,63 +96,63 @@ k_pdl_gemm(const float* __restrict__ x, const float* __restrict__ zf, float* __r
     }
   };
   const size_t jbeg = (size_t)ks * chunk, jend = jbeg + chunk;
+  const int li = lane & 15, lq = lane >> 4;
   float av[8], bv[8];
   load(jbeg, av, bv);
   for (size_t j0 = jbeg; j0 < jend; j0 += PDL_KSTEP) {
     __syncthreads();   // the previous stage has been consumed
-    {
-      uint16_t ah[8], al[8], bh[8], bl[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        ah[q] = f2bf(av[q]);
-        al[q] = f2bf(av[q] - __uint_as_float((uint32_t)ah[q] << 16));
-        bh[q] = f2bf(bv[q]);
-        bl[q] = f2bf(bv[q] - __uint_as_float((uint32_t)bh[q] << 16));
-      }
-      auto pack = [](const uint16_t (&h)[8]) {
-        return uint4{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
-                     h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16)};
-      };
-      *reinterpret_cast<uint4*>(&Ah[lr][lk]) = pack(ah);
-      *reinterpret_cast<uint4*>(&Al[lr][lk]) = pack(al);
-      *reinterpret_cast<uint4*>(&Bh[lr][lk]) = pack(bh);
-      *reinterpret_cast<uint4*>(&Bl[lr][lk]) = pack(bl);
+    for (int q = 0; q < 8; ++q) {
+      As[lr][lk + q] = (double)av[q];
+      Bs[lr][lk + q] = (double)bv[q];
     }
     __syncthreads();
     if (j0 + PDL_KSTEP < jend) load(j0 + PDL_KSTEP, av, bv);
 #pragma unroll
-    for (int kk = 0; kk < PDL_KSTEP / 16; ++kk) {
-      const int ko = 16 * kk + 8 * lhi;
-      const bf16x8 a_h = ld_bf16x8(&Ah[32 * wr + l32][ko]), a_l = ld_bf16x8(&Al[32 * wr + l32][ko]);
-      const bf16x8 b_h = ld_bf16x8(&Bh[32 * wc + l32][ko]), b_l = ld_bf16x8(&Bl[32 * wc + l32][ko]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc, 0, 0, 0);
+    for (int kk = 0; kk < PDL_KSTEP / 4; ++kk) {
+      const int k = 4 * kk + lq;
+      double a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[32 * wr + 16 * t + li][k];
+        b[t] = Bs[32 * wc + 16 * t + li][k];
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
     }
   }
-  float* out = part + ((size_t)ks * rows + 64 * rb + 32 * wr) * NA + 64 * cb + 32 * wc + l32;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) out[(size_t)(8 * (i / 4) + 4 * lhi + (i % 4)) * NA] = acc[i];
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      double* out = part + ((size_t)ks * rows + 64 * rb + 32 * wr + 16 * t + lq) * NA + 64 * cb +
+                    32 * wc + 16 * u + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(size_t)(4 * r) * NA] = acc[t][u][r];
+    }
 }
 
-// Sum of the KS slices in a fixed order. Rows r < n: B = X Z^T + sigma (G - E)
-// (n x A, row-major); rows n + i: C = Z Z^T + sigma I into cm (leading
-// dimension 256; the blocks on and below the diagonal only).
-__global__ void k_pdl_reduce(const float* __restrict__ part, const float* __restrict__ g,
-                             const float* __restrict__ e, float* __restrict__ bm,
-                             float* __restrict__ cm, int nv, int NA, int KS, float sigma) {
+// Sum of the KS slices in a fixed order (FP64). Rows r < n: B = X Z^T +
+// sigma (G - E) (n x A, row-major); rows n + i: C = Z Z^T + sigma I into cm
+// (leading dimension 256; the blocks on and below the diagonal only).
+__global__ void k_pdl_reduce64(const double* __restrict__ part, const float* __restrict__ g,
+                               const float* __restrict__ e, double* __restrict__ bm,
+                               double* __restrict__ cm, int nv, int NA, int KS, double sigma) {
   const int rows = nv + NA;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)rows * NA) return;
   const int r = (int)(idx / NA), c = (int)(idx % NA);
   if (r >= nv && (c >> 6) > ((r - nv) >> 6)) return;
-  float s = 0.f;
+  double s = 0.0;
   for (int k = 0; k < KS; ++k) s += part[(size_t)k * rows * NA + idx];
   if (r < nv) {
-    bm[idx] = s + sigma * (g[idx] - e[idx]);
+    bm[idx] = s + sigma * ((double)g[idx] - (double)e[idx]);
   } else {
     const int i = r - nv;
-    cm[(size_t)i * PDL_MAXM + c] = s + (i == c ? sigma : 0.f);
+    cm[(size_t)i * PDL_MAXM + c] = s + (i == c ? sigma : 0.0);
   }
 }
 
@@ -256,6 +269,149 @@ k_pdl_chol(const float* __restrict__ a, int lda, int m, float* __restrict__ lt) 
       const int i = 8 * ti + r;
       if (i >= k) lt[(size_t)k * PDL_MAXM + i] = P[r][c] * s;
     }
+  }
+}
+
+// Cholesky factor (FP64) of the SPD matrix M of order m <= 256, m % 16 == 0,
+// lower triangle in a[i * lda + k] (i >= k), blocked right-looking in one
+// work-group of 256 threads; a is overwritten (it holds the trailing matrix
+// between panels). Output lt[k * 256 + i] = L[i][k] and lt2[i * 256 + k] =
+// L[i][k] for i >= k. For every panel of 16 columns starting at b0:
+//   factor: wave 0 alone, the panel (rows b0 .. m - 1) in registers, lane l
+//     holding rows b0 + l + 64 s (s < 4), all 16 columns; the pivot and the
+//     column entries of the diagonal block (rows < 16 live in slot 0 of
+//     lanes 0 .. 15) are broadcast with readlane, so the 16 steps need no
+//     barrier;
+//   trailing update: a[i][k] -= sum_c L[i][c] L[k][c] over the panel's
+//     columns for b0 + 16 <= k <= i < m, by all four waves in 8 x 8 tiles
+//     per thread, the panel read from LDS (column-major).
+// Two barriers per panel.
+constexpr int PDL_CHOL64_NB = 16;
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__global__ void __launch_bounds__(256)
+k_pdl_chol64(double* __restrict__ a, int lda, int m, double* __restrict__ lt,
+             double* __restrict__ lt2) {
+  constexpr int NB = PDL_CHOL64_NB;
+  constexpr int LDP = PDL_MAXM + 8;
+  __shared__ __align__(16) double pnT[NB][LDP];   // factored panel, pnT[c][row]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int b0 = 0; b0 < m; b0 += NB) {
+    const int nr = m - b0;
+    if (wave == 0) {
+      // whole rows of 16 entries (two-double vector loads, no per-entry
+      // branch); entries above the diagonal and rows beyond nr read as zero
+      double v[4][NB];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = lane + 64 * s;
+        const double2* src =
+            reinterpret_cast<const double2*>(a + (size_t)(b0 + (row < nr ? row : 0)) * lda + b0);
+#pragma unroll
+        for (int c = 0; c < NB; c += 2) {
+          const double2 w = src[c / 2];
+          v[s][c] = (row < nr && c <= row) ? w.x : 0.0;
+          v[s][c + 1] = (row < nr && c + 1 <= row) ? w.y : 0.0;
+        }
+      }
+      // Rows at or beyond nr hold zeros and stay zero. The updates also run
+      // over the diagonal block's upper triangle (row < k), whose entries
+      // are never read again (a step reads column j only below the pivot)
+      // and are not written out: no per-entry masks in the inner loop.
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const double d = sqrt(readlane_f64(v[0][j], j)), inv = 1.0 / d;
+        double lj[4];
+        lj[0] = lane > j ? v[0][j] * inv : (lane == j ? d : 0.0);
+#pragma unroll
+        for (int s = 1; s < 4; ++s) lj[s] = v[s][j] * inv;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s][j] = lj[s];
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) {
+          const double lkj = readlane_f64(lj[0], k);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) v[s][k] -= lj[s] * lkj;
+        }
+      }
+      // the panel with zeros above the diagonal: to LDS for the update, to
+      // lt by columns and lt2 by rows (the zeros land in entries the solves
+      // never read)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = lane + 64 * s;
+        if (row < nr) {
+          double2* dst2 = reinterpret_cast<double2*>(lt2 + (size_t)(b0 + row) * PDL_MAXM + b0);
+#pragma unroll
+          for (int c = 0; c < NB; c += 2) {
+            const double x0 = c <= row ? v[s][c] : 0.0, x1 = c + 1 <= row ? v[s][c + 1] : 0.0;
+            pnT[c][row] = x0;
+            pnT[c + 1][row] = x1;
+            lt[(size_t)(b0 + c) * PDL_MAXM + b0 + row] = x0;
+            lt[(size_t)(b0 + c + 1) * PDL_MAXM + b0 + row] = x1;
+            dst2[c / 2] = double2{x0, x1};
+          }
+        }
+      }
+    }
+    // the update reads the panel from LDS only: an LDS-scoped barrier (the
+    // stores of lt and lt2 need not have completed)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    // trailing update of rows and columns b0 + NB .. m - 1 (8 x 8 tiles on
+    // and below the diagonal, tile (ti, tk), tk <= ti, numbered row by row)
+    const int nt = (nr - NB) / 8;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t = tid; t < ntiles; t += 256) {
+      int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (ti * (ti + 1) / 2 > t) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      const int tk = t - ti * (ti + 1) / 2;
+      const int r0 = NB + 8 * ti, c0 = NB + 8 * tk;   // panel-relative rows
+      // the tile of the trailing matrix, loaded before the products (its
+      // latency overlaps them); acc starts from it
+      double acc[8][8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double2* src =
+            reinterpret_cast<const double2*>(a + (size_t)(b0 + r0 + r) * lda + b0 + c0);
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) {
+          const double2 w = src[c / 2];
+          acc[r][c] = w.x;
+          acc[r][c + 1] = w.y;
+        }
+      }
+#pragma unroll 2
+      for (int q = 0; q < NB; ++q) {
+        double x[8], y[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          x[r] = pnT[q][r0 + r];
+          y[r] = pnT[q][c0 + r];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+          for (int c = 0; c < 8; ++c) acc[r][c] -= x[r] * y[c];
+      }
+      // whole tile rows back (entries above the diagonal of a diagonal tile
+      // are never read again)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        double2* dst = reinterpret_cast<double2*>(a + (size_t)(b0 + r0 + r) * lda + b0 + c0);
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) dst[c / 2] = double2{acc[r][c], acc[r][c + 1]};
+      }
+    }
+    __syncthreads();   // the next panel reads the updated trailing matrix
   }
 }
 
@@ -382,12 +538,107 @@ k_pdl_trsolve(const float* __restrict__ lt, int m, const float* __restrict__ b, 
   }
 }
 
-// G = (D + E) / ||D + E||_F, E <- E + G - D, and G in BF16 (count = n A
-// entries, one work-group of 1024 threads; the squared norm is summed in
-// FP64 in a fixed order). res (optional, a check of the dictionary penalty):
+// Rows of X = B M^-1 with M = L L^T in FP64 (order m, a multiple of 64, at
+// most 256): lt holds L by columns (lt[k * 256 + i] = L[i][k]), lt2 by rows
+// (lt2[i * 256 + k] = L[i][k]), both from k_pdl_chol<double>. For every row
+// b of B (n x m, row-major), L y = b^T (forward, column by column), then
+// L^T x = y (backward, row by row of L). One row per wave, entry c in slot
+// c / 64 of lane c % 64; the column (row) of L that step k needs is read
+// from global memory, PF steps ahead of its use, through a ring of
+// registers, and y_k is broadcast from its lane by two readlanes.
+template <int NR>
+__global__ void __launch_bounds__(256)
+k_pdl_trsolve64(const double* __restrict__ lt, const double* __restrict__ lt2, int m,
+                const double* __restrict__ b, int q, double* __restrict__ xo) {
+  constexpr int PF = 8;
+  __shared__ double rd[PDL_MAXM];
+  for (int k = threadIdx.x; k < m; k += 256) rd[k] = 1.0 / lt[(size_t)k * PDL_MAXM + k];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= q) return;
+  double y[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int c = lane + 64 * r;
+    y[r] = c < m ? b[(size_t)row * m + c] : 0.0;
+  }
+  auto bcast = [&](double v, int l) {
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+  };
+  // forward: y_i -= L[i][k] y_k / L[k][k] for i > k, then y_k /= L[k][k]
+  // (the division of the finished entry is applied to the broadcast value
+  // only, and to the entries once at the end)
+  double ring[PF][NR];
+  auto colv = [&](int k, double (&v)[NR]) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = lane + 64 * r;
+      v[r] = (k < m && i > k && i < m) ? lt[(size_t)k * PDL_MAXM + i] : 0.0;
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) colv(u, ring[u]);
+#pragma unroll
+  for (int rb = 0; rb < NR; ++rb) {
+#pragma unroll 1
+    for (int k0 = 64 * rb; k0 < 64 * rb + 64 && k0 < m; k0 += PF) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int k = k0 + u;
+        const double yk = bcast(y[rb], k & 63) * rd[k];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) y[r] -= ring[u][r] * yk;
+        colv(k + PF, ring[u]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    if (i < m) y[r] *= rd[i];
+  }
+  // backward: x_i -= L[k][i] x_k / L[k][k] for i < k, k from m - 1 down
+  auto rowv = [&](int k, double (&v)[NR]) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = lane + 64 * r;
+      v[r] = (k >= 0 && i < k) ? lt2[(size_t)k * PDL_MAXM + i] : 0.0;
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) rowv(m - 1 - u, ring[u]);
+#pragma unroll
+  for (int rb = NR - 1; rb >= 0; --rb) {
+    if (64 * rb >= m) continue;
+#pragma unroll 1
+    for (int k0 = 64 * rb + 63; k0 >= 64 * rb; k0 -= PF) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int k = k0 - u;
+        const double xk = bcast(y[rb], k & 63) * rd[k];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) y[r] -= ring[u][r] * xk;
+        rowv(k - PF, ring[u]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int c = lane + 64 * r;
+    if (c < m) xo[(size_t)row * m + c] = y[r] * rd[c];
+  }
+}
+
+// G = (D + E) / ||D + E||_F, E <- E + G - D from the FP64 D, G and E stored
+// in FP32 and G in BF16 (count = n A entries, one work-group of 1024
+// threads; the squared norm is summed in FP64 in a fixed order). res (optional, a check of the dictionary penalty):
 // res[0] = ||D - G||^2, res[1] = ||G - G_prev||^2 in FP64.
 __global__ void __launch_bounds__(1024)
-k_pdl_project(const float* __restrict__ d, float* __restrict__ g, float* __restrict__ e,
+k_pdl_project(const double* __restrict__ d, float* __restrict__ g, float* __restrict__ e,
               uint16_t* __restrict__ gbf, int count, double* __restrict__ res) {
   __shared__ double red[16], red2[2][16];
   double s = 0.0;
@@ -402,18 +653,19 @@ k_pdl_project(const float* __restrict__ d, float* __restrict__ g, float* __restr
   double tot = 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) tot += red[k];
-  const float inv = (float)(1.0 / sqrt(tot));
+  const double inv = 1.0 / sqrt(tot);
   double rd = 0.0, sd = 0.0;
   for (int i = threadIdx.x; i < count; i += 1024) {
-    const float dv = d[i], ev = e[i];
-    const float gv = (dv + ev) * inv;
+    const double dv = (double)d[i], ev = (double)e[i];
+    const double gd = (dv + ev) * inv;
+    const float gv = (float)gd;
     if (res) {
-      const double a = (double)gv - (double)dv, b = (double)gv - (double)g[i];
+      const double a = gd - dv, b = gd - (double)g[i];
       rd += a * a;
       sd += b * b;
     }
     g[i] = gv;
-    e[i] = ev + gv - dv;
+    e[i] = (float)(ev + gd - dv);
     gbf[i] = f2bf(gv);
   }
   if (res) {

@@ -23,8 +23,14 @@ size_t patch_z_residual_floats(int N1, int N2);
 //   zf [A][J] codes, part [KS][n + A][A] split products, bm / d [n][A]
 //   right-hand side and D, cm / lt [256][256] system and its factor,
 //   g / e [n][A] dictionary and dual, dbf [n][A] / m1bf [A][n] BF16 tables.
+// Device buffers of the online patch-dictionary update: the FP32 codes zf
+// [A][J]; the FP64 D-step's product slices, right-hand side, matrix, factor
+// (by columns, then by rows) and D; the FP32 matrix and factor of M1; G, E
+// (FP32) and the BF16 tables of G and M1.
 struct PatchDictBufs {
-  float *zf, *part, *bm, *d, *cm, *lt, *g, *e;
+  float* zf;
+  double *part, *bm, *cm64, *lt64, *d;
+  float *cm, *lt, *g, *e;
   uint16_t *dbf, *m1bf;
 };
 int patch_dict_splits(int N1, int N2);
@@ -33,7 +39,7 @@ hipError_t patch_dict_start(const float* d0, const PatchDictBufs& b, int nv, int
 // one D, G, E step and M1 of the new G; res (optional, device): ||D - G||^2,
 // ||G - G_prev||^2 in FP64
 hipError_t patch_dict_step(const float* x, const PatchDictBufs& b, int S, int NA, int N1, int N2,
-                           float sigma, float rho, hipStream_t st, double* res = nullptr);
+                           double sigma, float rho, hipStream_t st, double* res = nullptr);
 // M1 = G^T (rho I + G G^T)^-1 (BF16) of the current G
 hipError_t patch_dict_m1(const PatchDictBufs& b, int S, int NA, float rho, hipStream_t st);
 // E <- c E (count = n A entries)

@@ -119,16 +119,24 @@ def _bf16(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("N,K,S,A", [(64, 2, 2, 64), (64, 3, 3, 256), (128, 3, 4, 128)])
-def test_patch_dictionary_first_step_on_bf16_codes(N, K, S, A):
+@pytest.mark.parametrize("N,K,S,A,sigma_kind,tol", [
+    (64, 2, 2, 64, "scaled", 1e-4), (64, 3, 3, 256, "scaled", 1e-4),
+    (128, 3, 4, 128, "scaled", 1e-4),
+    (64, 2, 2, 64, "paper", 2e-3), (64, 3, 3, 256, "paper", 2e-3), (128, 4, 4, 128, "paper", 2e-3)])
+def test_patch_dictionary_first_step_on_bf16_codes(N, K, S, A, sigma_kind, tol):
     """The first dictionary step, isolated from the BF16 code error: with
     two iterations the GPU takes one D, G, E step on z^1 = M1 e (w = 0,
     e = P x^1), whose operands M1 and e are BF16. The same step in FP64 on
     codes formed from BF16-rounded M1 and e (x^1 from the FP64 oracle) must
-    give the GPU's G to within the step's own arithmetic (FP32 factorizations
-    and solves, products of split BF16 operands with about 16 significant
-    bits: 1e-4)."""
-    sigma = _sigma(N)
+    give the GPU's G: the GPU's step runs in FP64 on its FP32 x and codes,
+    which differ from the oracle's by FP32 rounding and the FP32
+    accumulation of the code products. With sigma = 1000 J the step matches
+    to 1e-4. At the paper's sigma = 1, Z Z^T + sigma I has condition numbers
+    1e5 .. 6e6 here, and the FP32-level difference of x^1 (4e-7) flips the
+    BF16 rounding of a few patch samples: perturbing the oracle's own x^1 by
+    4e-7 moves its G by 3e-6 .. 1e-3 in these cases, so the bar is the BF16
+    path's 2e-3."""
+    sigma = _sigma(N) if sigma_kind == "scaled" else 1.0
     x, psf, y, D = _problem(N, K, S, A)
     alg = admm.PatchADMM(psf, D, 8, 4, LAM, RHO, BETA, tier="freq", dict_update=True,
                          sigma=sigma)
@@ -144,8 +152,27 @@ def test_patch_dictionary_first_step_on_bf16_codes(N, K, S, A):
     g = _np(plan.dictionary())
     eg = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     moved = np.linalg.norm(g_ref - D)
-    print(f"first step N={N} S={S} A={A}: G rel {eg:.3e} (step {moved:.3e})", flush=True)
-    parity.check(g, g_ref, 1e-4, label="G")
+    print(f"first step N={N} S={S} A={A} sigma={sigma:g}: G rel {eg:.3e} (step {moved:.3e})",
+          flush=True)
+    parity.check(g, g_ref, tol, label="G")
+
+
+@pytest.mark.parametrize("N,K,S,A", [(64, 3, 3, 128), (128, 3, 3, 256)])
+def test_patch_dictionary_learning_at_sigma_1(N, K, S, A):
+    """The paper's sigma = 1 (the library default), 3 iterations (two
+    dictionary steps of the FP64 D-step): x within the BF16 bar. Each step
+    moves G by 0.04 .. 0.9 at this sigma and amplifies the BF16 code error
+    (the learned G differs from the oracle's by 1e-2 .. 3e-2 after two steps,
+    x by 3e-4), so x is the compared result."""
+    x, psf, y, D = _problem(N, K, S, A)
+    alg = admm.PatchADMM(psf, D, 8, 4, LAM, RHO, BETA, tier="freq", dict_update=True,
+                         sigma=1.0)
+    ref = alg.run(y, 3)[0]
+    plan = cip.Plan(_t(psf), "patch", RHO, LAM, BETA, dictionary=_t(D), dict_update=True)
+    got = _np(plan.solve(_t(y), 3))
+    print(f"sigma = 1, N={N} S={S} A={A}: psnr gpu {admm.psnr(got, x):.2f} dB, oracle "
+          f"{admm.psnr(ref, x):.2f} dB", flush=True)
+    parity.check(got, ref, 2e-3, label="x")
 
 
 def test_patch_dictionary_huge_sigma_is_the_fixed_dictionary_run():
