@@ -200,8 +200,8 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
 
 def run_other_priors(args, dev, psf_t, y_t):
     """The other priors at the precision-workload shape (K = S = 3, 1024^2),
-    the median of three solves of `iters_other` iterations each after a
-    warm-up solve:
+    the median of three solves of `iters_other` iterations each (100 by
+    default, as in the precision workloads) after a warm-up solve:
     DCT3D, wavelet (x) DCT (Symmlet-8, 3 levels), patch dictionary (A = 256;
     with online dictionary learning),
     convolutional dictionary (32 filters 11 x 11; with the gradient term; 3D
@@ -460,8 +460,9 @@ def main():
     ap.add_argument("--bands", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=70)
-    ap.add_argument("--iters-other", type=int, default=20,
-                    help="iterations per solve for the other priors (0: skip)")
+    ap.add_argument("--iters-other", type=int, default=100,
+                    help="iterations per solve for the other priors (0: skip); 100 is the "
+                         "iteration count of the precision workloads")
     ap.add_argument("--others-only", default="",
                     help="run only the other priors whose name contains this text")
     ap.add_argument("--no-cpu", action="store_true")
