@@ -501,6 +501,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dom) if (N, S) == (1024, 3) else None,
+            "traffic_source": "FETCH_SIZE + WRITE_SIZE (L2 to fabric traffic, part of which the "
+                              "256 MB Infinity Cache may serve) from the committed counter profile",
             "kernel": names[dom], "avg_us": round(times[dom], 3),
             "algorithmic_bytes_per_launch": byt,
             "other_kernel": {"name": names[1 - dom], "avg_us": round(times[1 - dom], 3),
