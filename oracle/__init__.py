@@ -16,9 +16,11 @@ and the step order of Algorithms 1 and 2 in the paper's notation.
 Modules:
   model     forward model y_k = sum_s h_{k,s} * x_s (Eq. forward model), its
             adjoint, dense block matrix H for tiny grids (Eq. forwardModel).
-  priors    analysis operators T (2D DCT, anisotropic TV 2D/3D), soft
-            thresholding (Eq. solt_trans), patch extraction P_j (Eq.
-            patch_based), convolutional dictionary synthesis (Eq. conv_dic).
+  priors    analysis operators T (2D/3D DCT, wavelet x DCT, anisotropic TV
+            2D/3D), isotropic TV per slice and coupled along the slices
+            (Chambolle's algorithm), soft thresholding (Eq. solt_trans),
+            patch extraction P_j (Eq. patch_based), convolutional dictionary
+            synthesis (Eq. conv_dic).
   xupdate   x-update solvers: dense normal equations (Eq. solx_Trans /
             solx_synt), per-frequency S x S solves (Eq. solx_Trans_DFT /
             solx_synt_DFT), recursive 2x2 block inversion (Eq. recinv).

@@ -48,9 +48,10 @@ class AnalysisADMM:
     """Algorithm 1 for T in {dct2d, dct3d, tv2d, tv3d, wdct3d (Symmlet-8
     wavelet per slice, `levels` levels, then DCT along the bands)} and
     Phi = l1, and for
-    isotropic TV ("itv2d": T = I, Phi = TV, t-update by Chambolle's
-    algorithm with `inner` iterations per ADMM iteration, warm-started from
-    the previous dual p, step 1/8)."""
+    isotropic TV ("itv2d": T = I, Phi = TV of every slice, t-update by
+    Chambolle's algorithm with `inner` iterations per ADMM iteration,
+    warm-started from the previous dual p, step 1/8; "itv3d": the same with
+    the gradient coupled along the slices, step 1/12)."""
 
     def __init__(self, psf, kind, lam, rho, beta=1.0, tier="auto", inner=20, levels=3):
         K, S, N1, N2 = psf.shape
@@ -71,6 +72,11 @@ class AnalysisADMM:
             if p is None:
                 p = np.zeros((2,) + v.shape[1:])
             t, p = priors.chambolle(v[0], kappa, p, self.inner)
+            return t[None], p
+        if self.kind == "itv3d":
+            if p is None:
+                p = np.zeros((3,) + v.shape[1:])
+            t, p = priors.chambolle3(v[0], kappa, p, self.inner)
             return t[None], p
         return priors.soft(v, kappa), None
 

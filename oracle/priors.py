@@ -12,6 +12,10 @@
   - T = 2D Symmlet-8 wavelet transform of each slice followed by the
     orthonormal DCT-II along the band axis (the Kronecker basis used for the
     analysis prior in Section V-A).
+* Isotropic TV (Phi = TV with T = I, Section III-A): the Euclidean norm of
+  the per-slice gradient, or of the gradient with its band component (the
+  same band difference as the 3D anisotropic case), and its proximal map by
+  Chambolle's projection algorithm.
 * Soft thresholding, the l1 proximal map (Eq. solt_trans), sign(0) = -1.
 * Patch extraction P_j for Q x Q x T patches spanning all bands (Eq.
   patch_based), extracted circularly at a fixed stride.
@@ -249,7 +253,8 @@ class TV3D(TV2D):
 
 class Identity:
     """T = I: the analysis split used with isotropic TV (Phi(Tx) = TV(x) with
-    T = I, Section III-A); the t-update is then the TV proximal map."""
+    T = I, Section III-A; per slice, or coupled along the slices); the
+    t-update is then the TV proximal map."""
 
     name = "itv2d"
 
@@ -271,7 +276,7 @@ def make_transform(kind: str, S: int, N1: int, N2: int, levels: int = 3):
     if kind == "wdct3d":
         return WaveletDCT(S, N1, N2, levels)
     return {"dct2d": DCT2D, "dct3d": DCT3D, "tv2d": TV2D, "tv3d": TV3D,
-            "itv2d": Identity}[kind](S, N1, N2)
+            "itv2d": Identity, "itv3d": Identity}[kind](S, N1, N2)
 
 
 # ---------------------------------------------------------------- isotropic TV
@@ -304,6 +309,49 @@ def chambolle(f: np.ndarray, mu: float, p: np.ndarray, iters: int, tau: float = 
         nrm = np.sqrt(g[0] ** 2 + g[1] ** 2)
         p = (p + tau * g) / (1.0 + tau * nrm)
     return f - mu * div2(p), p
+
+
+# ------------------------------------------------- isotropic TV coupled along the slices
+def grad3(x: np.ndarray) -> np.ndarray:
+    """Circular forward differences along both image axes and the forward
+    difference along the slices (none after the last slice: that component
+    is 0 there), shape (3,) + x.shape."""
+    gb = np.zeros_like(x)
+    gb[:-1] = x[1:] - x[:-1]
+    return np.stack([np.roll(x, -1, axis=-2) - x, np.roll(x, -1, axis=-1) - x, gb])
+
+
+def div3(p: np.ndarray) -> np.ndarray:
+    """Discrete divergence, the negative adjoint of grad3: div2 of the image
+    components plus p2[s] - p2[s - 1] along the slices (p2[-1] = 0; the last
+    slice's p2, which grad3 never fills, is read as 0)."""
+    b = p[2].copy()
+    b[-1] = 0.0
+    db = b.copy()
+    db[1:] -= b[:-1]
+    return div2(p[:2]) + db
+
+
+def tv_iso3(x: np.ndarray) -> float:
+    """Isotropic TV of the whole cube, sum over voxels of |grad3 x|."""
+    g = grad3(x)
+    return float(np.sum(np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)))
+
+
+def chambolle3(f: np.ndarray, mu: float, p: np.ndarray, iters: int, tau: float = 1.0 / 12.0):
+    """Chambolle's projection algorithm for the proximal map of the isotropic
+    TV coupled along the slices, argmin_t 1/2 ||t - f||^2 + mu TV3(t):
+        p <- (p + tau grad3(div3 p - f / mu)) / (1 + tau |grad3(div3 p - f / mu)|),
+    t = f - mu div3 p. ||div3||^2 <= 12 (two circular axes and a path along
+    the slices, each <= 4), so tau <= 1/12 keeps Chambolle's convergence
+    argument. Starts from the dual p given (shape (3,) + f.shape) and
+    returns (t, p)."""
+    p = p.copy()
+    for _ in range(iters):
+        g = grad3(div3(p) - f / mu)
+        nrm = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+        p = (p + tau * g) / (1.0 + tau * nrm)
+    return f - mu * div3(p), p
 
 
 # ---------------------------------------------------------------- patches

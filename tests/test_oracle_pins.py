@@ -1048,6 +1048,99 @@ def test_itv_admm_with_identity_blur_is_the_tv_prox():
     assert np.linalg.norm(xa - x) > 1e-3 * np.linalg.norm(x)
 
 
+def test_grad3_is_the_explicit_difference_and_div3_its_negative_adjoint():
+    """grad3 written out voxel by voxel (circular along the image axes, the
+    next slice minus this one along the slices, 0 after the last slice), and
+    <grad3 x, p> = -<x, div3 p> for any p (the last slice's band component
+    included, which the gradient never fills)."""
+    S, N1, N2 = 3, 4, 5
+    x = _rng(110).standard_normal((S, N1, N2))
+    g = priors.grad3(x)
+    for s in range(S):
+        for i in range(N1):
+            for j in range(N2):
+                assert g[0, s, i, j] == x[s, (i + 1) % N1, j] - x[s, i, j]
+                assert g[1, s, i, j] == x[s, i, (j + 1) % N2] - x[s, i, j]
+                assert g[2, s, i, j] == (x[s + 1, i, j] - x[s, i, j] if s + 1 < S else 0.0)
+    p = _rng(111).standard_normal((3, S, N1, N2))
+    assert np.isclose(np.vdot(g, p), -np.vdot(x, priors.div3(p)), rtol=1e-12)
+
+
+def test_div3_grad3_norm_is_below_twelve():
+    """The largest eigenvalue of -div3 grad3 on a small cube, from its
+    assembled matrix, is 8 + 2 - 2 cos(pi (S - 1) / S) (the circular
+    Laplacian's 8 plus the path Laplacian's largest eigenvalue), below 12:
+    the step 1/12 meets Chambolle's condition."""
+    S, N1, N2 = 3, 4, 4
+    n = S * N1 * N2
+    A = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        A[:, k] = -priors.div3(priors.grad3(e.reshape(S, N1, N2))).ravel()
+    assert np.allclose(A, A.T, atol=1e-12)
+    lmax = np.linalg.eigvalsh(A).max()
+    assert np.isclose(lmax, 8.0 + 2.0 - 2.0 * np.cos(np.pi * (S - 1) / S), rtol=1e-12)
+    assert lmax < 12.0
+
+
+def test_chambolle3_meets_the_coupled_tv_prox_optimality_conditions():
+    """At convergence t = f - mu div3 p with |p| <= 1 and p . grad3 t =
+    -|grad3 t| where grad3 t != 0 (the three components' joint norm): the
+    optimality conditions of argmin 1/2 ||t - f||^2 + mu TV3(t). The
+    objective is lower than at perturbed points."""
+    f = _rng(112).standard_normal((3, 6, 6))
+    mu = 0.3
+    t, p = priors.chambolle3(f, mu, np.zeros((3, 3, 6, 6)), 30000)
+    assert np.allclose(t, f - mu * priors.div3(p), atol=1e-14)
+    g = priors.grad3(t)
+    ng = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+    assert np.max(np.sqrt(p[0] ** 2 + p[1] ** 2 + p[2] ** 2)) <= 1.0 + 1e-12
+    on = ng > 1e-3          # a few voxels' gradients are still shrinking to 0 (below 2e-4)
+    assert np.max(np.abs(p[0] * g[0] + p[1] * g[1] + p[2] * g[2] + ng)[on]) < 1e-8
+    obj = lambda z: 0.5 * np.sum((z - f) ** 2) + mu * priors.tv_iso3(z)
+    for k in range(5):
+        assert obj(t) <= obj(t + 1e-3 * _rng(113 + k).standard_normal(t.shape))
+
+
+def test_chambolle3_special_cases():
+    """Slices that are all equal have no band variation, so the coupled prox
+    is the per-slice prox of one slice, repeated; a single slice is the
+    per-slice prox; a weight far above the total variation gives the mean of
+    the whole cube (per-slice TV gives each slice's own mean)."""
+    f1 = _rng(114).standard_normal((1, 6, 6))
+    mu = 0.25
+    ref, _ = priors.chambolle(f1, mu, np.zeros((2, 1, 6, 6)), 20000)
+    t1, _ = priors.chambolle3(f1, mu, np.zeros((3, 1, 6, 6)), 20000)
+    assert np.allclose(t1, ref, atol=1e-9)
+    f3 = np.repeat(f1, 3, axis=0)
+    t3, _ = priors.chambolle3(f3, mu, np.zeros((3, 3, 6, 6)), 30000)
+    assert np.allclose(t3, np.repeat(ref, 3, axis=0), atol=1e-7)
+    f = _rng(115).standard_normal((3, 5, 5)) + np.arange(3)[:, None, None]
+    tb, _ = priors.chambolle3(f, 100.0, np.zeros((3, 3, 5, 5)), 40000)
+    assert np.allclose(tb, f.mean(), atol=1e-5)
+    ts, _ = priors.chambolle(f, 100.0, np.zeros((2, 3, 5, 5)), 20000)
+    assert np.allclose(ts, f.mean(axis=(1, 2), keepdims=True), atol=1e-6)
+
+
+def test_itv3_admm_with_identity_blur_is_the_coupled_tv_prox():
+    """With H = I the band-coupled isotropic-TV problem is coupled TV
+    denoising of y with weight lambda / beta; ADMM (T = I, Chambolle
+    t-update along the slices) reaches it, and it differs from the per-slice
+    isotropic-TV answer on data that varies along the slices."""
+    S, N = 3, 8
+    psf = np.zeros((S, S, N, N))
+    for s in range(S):
+        psf[s, s, 0, 0] = 1.0
+    y = _rng(116).standard_normal((S, N, N))
+    lam, beta, rho = 0.2, 1.0, 0.5
+    x, _, _ = admm.AnalysisADMM(psf, "itv3d", lam, rho, beta, tier="freq", inner=50).run(y, 600)
+    ref, _ = priors.chambolle3(y, lam / beta, np.zeros((3, S, N, N)), 30000)
+    assert np.allclose(x, ref, atol=1e-6)
+    x2 = admm.AnalysisADMM(psf, "itv2d", lam, rho, beta, tier="freq", inner=50).run(y, 600)[0]
+    assert np.linalg.norm(x2 - x) > 1e-2 * np.linalg.norm(x)
+
+
 # ---------------------------------------------------------------- pins added for the larger tiers
 @pytest.mark.slow
 @pytest.mark.parametrize("N,kind,iters", [(32, "tv2d", 20), (32, "dct2d", 20), (32, "tv3d", 10),
