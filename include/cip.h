@@ -97,6 +97,15 @@ typedef enum {
    * (Psi = rho I + beta Lambda^H Lambda); Phi = l1. N1 and N2 must be
    * multiples of 2^wt_levels. */
   CIP_PRIOR_WDCT3D = 8,
+  /* Isotropic TV of the whole cube (Section III-A with the
+   * multidimensional derivative operators): the Euclidean norm at every
+   * voxel of the gradient (circular forward differences along both image
+   * axes, forward difference along the planes, none after the last plane).
+   * T = I; the t-update is the proximal map of this TV by Chambolle's
+   * algorithm with step 1/12, `tv_inner` iterations per ADMM iteration,
+   * dual warm-started from the previous ADMM iteration. With S = 1 it is
+   * CIP_PRIOR_ITV2D run at the smaller step. */
+  CIP_PRIOR_ITV3D = 9,
 } cip_prior_kind;
 
 typedef struct {
@@ -120,7 +129,7 @@ typedef struct {
                            DL_PriorHP_conv for 2D correlations (forward
                            differences along both axes); 0 = none, >= 0;
                            must be 0 for CIP_PRIOR_CONV3D                   */
-  /* CIP_PRIOR_ITV2D only:                                                    */
+  /* CIP_PRIOR_ITV2D and CIP_PRIOR_ITV3D only:                                */
   int tv_inner;         /* Chambolle iterations per ADMM iteration (0: 20)    */
   /* All priors:                                                             */
   int flags;            /* CIP_PLAN_ADAPTIVE: keep what cip_solve_adaptive
@@ -176,9 +185,9 @@ int cip_plan_workspace_bytes(int K, int S, int N1, int N2, const cip_prior_desc*
  * unit-sum kernels and TV). Results are stored in FP32 in the workspace.
  *   d_psf      : [K][S][N1][N2] float32 device array, read during the call only.
  *   rho, lambda: ADMM penalty (> 0) and regularisation weight (>= 0; > 0
- *                for CIP_PRIOR_ITV2D); the soft threshold is lambda / rho
- *                (Eq. solt_trans), the TV proximal weight of CIP_PRIOR_ITV2D
- *                likewise.
+ *                for the isotropic TV priors); the soft threshold is
+ *                lambda / rho (Eq. solt_trans), the TV proximal weight of
+ *                CIP_PRIOR_ITV2D and CIP_PRIOR_ITV3D likewise.
  *   d_workspace: device buffer of at least cip_plan_workspace_bytes bytes,
  *                256-byte aligned, owned by the caller, kept by the plan until
  *                cip_plan_destroy and not touched by the caller meanwhile.
@@ -260,7 +269,8 @@ int cip_plan_destroy(cip_plan_t plan);
  *   r_d = ||D - G||,  s_d = sigma ||G - G_prev||,
  *   sigma <- tau sigma if r_d > mu s_d, sigma / tau if s_d > mu r_d, and the
  *   scaled dual E is rescaled by sigma_old / sigma_new.
- * CIP_EUNSUPPORTED for CIP_PRIOR_ITV2D and CIP_PRIOR_WDCT3D, and for
+ * CIP_EUNSUPPORTED for CIP_PRIOR_ITV2D, CIP_PRIOR_ITV3D and CIP_PRIOR_WDCT3D,
+ * and for
  * adapt_sigma on a plan that does not learn its dictionary.
  * The plan must have been created with CIP_PLAN_ADAPTIVE and must not be an
  * attached plan; its tables are back at its own rho when the call returns.

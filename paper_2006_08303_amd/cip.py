@@ -26,9 +26,11 @@ CIP_PRIOR_DCT3D = 5
 CIP_PRIOR_ITV2D = 6
 CIP_PRIOR_CONV3D = 7
 CIP_PRIOR_WDCT3D = 8
+CIP_PRIOR_ITV3D = 9
 PRIORS = {"tv2d": CIP_PRIOR_TV2D, "tv3d": CIP_PRIOR_TV3D, "dct2d": CIP_PRIOR_DCT2D,
           "patch": CIP_PRIOR_PATCH, "conv2d": CIP_PRIOR_CONV2D, "dct3d": CIP_PRIOR_DCT3D,
-          "itv2d": CIP_PRIOR_ITV2D, "conv3d": CIP_PRIOR_CONV3D, "wdct3d": CIP_PRIOR_WDCT3D}
+          "itv2d": CIP_PRIOR_ITV2D, "conv3d": CIP_PRIOR_CONV3D, "wdct3d": CIP_PRIOR_WDCT3D,
+          "itv3d": CIP_PRIOR_ITV3D}
 
 
 class CipError(RuntimeError):
@@ -168,8 +170,8 @@ def _dev_f32(t, shape, name):
 
 
 def workspace_bytes(K, S, N1, N2, prior="dct2d", beta=1.0, n_atoms=0, n_filters=0, filt_l=0,
-                    flags=0, sigma=0.0, wt_levels=0):
-    desc = _desc(prior, beta, flags=flags, sigma=sigma, wt_levels=wt_levels)
+                    flags=0, sigma=0.0, wt_levels=0, tv_inner=0):
+    desc = _desc(prior, beta, flags=flags, tv_inner=tv_inner, sigma=sigma, wt_levels=wt_levels)
     desc.n_atoms = int(n_atoms)
     desc.n_filters = int(n_filters)
     desc.filt_l = int(filt_l)

@@ -88,6 +88,7 @@ int state_floats_per_voxel(int kind) {
     case CIP_PRIOR_DCT2D: return 1;
     case CIP_PRIOR_DCT3D: return 1;
     case CIP_PRIOR_ITV2D: return 6;  // u, dual p (2 components, double-buffered), f
+    case CIP_PRIOR_ITV3D: return 8;  // u, dual p (3 components, double-buffered), f
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
     case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
@@ -238,7 +239,8 @@ int validate(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
   if (state_floats_per_voxel(prior->kind) < 0)
     return fail(CIP_EUNSUPPORTED, "unsupported prior kind");
   if (!(prior->beta > 0.0)) return fail(CIP_EINVAL, "beta must be > 0");
-  if (prior->kind == CIP_PRIOR_ITV2D && (prior->tv_inner < 0 || prior->tv_inner > 10000))
+  if ((prior->kind == CIP_PRIOR_ITV2D || prior->kind == CIP_PRIOR_ITV3D) &&
+      (prior->tv_inner < 0 || prior->tv_inner > 10000))
     return fail(CIP_EINVAL, "tv_inner must be in [0, 10000]");
   if (prior->kind == CIP_PRIOR_WDCT3D) {
     const int lv = prior->wt_levels > 0 ? prior->wt_levels : 3;
@@ -323,6 +325,10 @@ struct cip_plan_s {
 
 bool is_dct(const cip_plan_s* p) {
   return p->kind == CIP_PRIOR_DCT2D || p->kind == CIP_PRIOR_DCT3D;
+}
+
+bool is_itv(const cip_plan_s* p) {
+  return p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_ITV3D;
 }
 
 // ---------------------------------------------------------------- launch helpers
@@ -440,16 +446,36 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
 // starts from the buffer where pass l - 1 left it (A for l = 1, zeroed by the
 // prep kernel).
 // Chambolle iterations per launch (= tile halo). Measured at 1024^2 x 3 with
-// 20 iterations: 4 -> 204 us, 5 -> 189 us, 8 -> 204 us, 10 -> 207 us per ADMM
-// row pass; the results are bitwise the same for every halo.
+// 20 iterations (per-plane TV): 4 -> 204 us, 5 -> 189 us, 8 -> 204 us,
+// 10 -> 207 us per ADMM row pass; the results are bitwise the same for every
+// halo.
 constexpr int ITV_KB = 5;
+
+// Band-coupled Chambolle launch: the tile side is 32 where all S planes of a
+// 42 x 42 region fit in 64 KiB of LDS (S <= 3) and the grid allows it, else 16.
+constexpr int ITV3_NT = 512;
+template <int S_>
+hipError_t itv3_launch(bool t32, int grid32, int grid16, hipStream_t st, const float* f,
+                       float* const* in, float* const* out, int N1, int N2, int m, float inv_mu) {
+  if constexpr (S_ <= 3) {
+    if (t32)
+      return launch(k_itv3_chambolle<S_, 32, ITV_KB, ITV3_NT>, grid32, ITV3_NT, 0, st, f, in[0],
+                    in[1], in[2], out[0], out[1], out[2], N1, N2, m, inv_mu, 1.f / 12.f);
+  }
+  return launch(k_itv3_chambolle<S_, 16, ITV_KB, ITV3_NT>, grid16, ITV3_NT, 0, st, f, in[0],
+                in[1], in[2], out[0], out[1], out[2], N1, N2, m, inv_mu, 1.f / 12.f);
+}
+
 hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
   const Layout& L = p->L;
   const float mu = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
   const size_t n = (size_t)p->S * p->N1 * p->N2;
+  const bool band = p->kind == CIP_PRIOR_ITV3D;
+  const int nc = band ? 3 : 2;   // dual components
   float* u = p->at<float>(L.state);
-  float* pd[2][2] = {{u + n, u + 2 * n}, {u + 3 * n, u + 4 * n}};
-  float* f = u + 5 * n;
+  float* pd[2][3] = {{u + n, u + 2 * n, band ? u + 3 * n : nullptr},
+                     {u + (1 + nc) * n, u + (2 + nc) * n, band ? u + 6 * n : nullptr}};
+  float* f = u + (1 + 2 * nc) * n;
   const int nl = (p->tv_inner + ITV_KB - 1) / ITV_KB;
   const int start = (int)(((long long)(l - 1) * nl) & 1);
   const int grid = p->S * (p->N1 / RT);
@@ -458,33 +484,49 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
     e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), u, f,
-               pd[start][0], pd[start][1], p->N1, p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
+               pd[start][0], pd[start][1], pd[start][2], p->N1,
+               p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
   });
   if (e != hipSuccess) return e;
   const bool t32 = p->N1 % 32 == 0 && p->N2 % 32 == 0;
   const int ts = t32 ? 32 : 16;
   const int cgrid = p->S * (p->N1 / ts) * (p->N2 / ts);
+  const int g32 = t32 ? (p->N1 / 32) * (p->N2 / 32) : 0, g16 = (p->N1 / 16) * (p->N2 / 16);
   for (int j = 0; j < nl; ++j) {
     const int in = (start + j) & 1, out = in ^ 1;
     const int m = std::min(ITV_KB, p->tv_inner - j * ITV_KB);
-    e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
-                     pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f)
-            : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
-                     pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f);
+    if (band) {
+      switch (p->S) {
+#define ITV3_CASE(SS)                                                                         \
+  case SS:                                                                                    \
+    e = itv3_launch<SS>(t32, g32, g16, st, f, pd[in], pd[out], p->N1, p->N2, m, 1.f / mu);    \
+    break;
+        ITV3_CASE(1) ITV3_CASE(2) ITV3_CASE(3) ITV3_CASE(4)
+        ITV3_CASE(5) ITV3_CASE(6) ITV3_CASE(7) ITV3_CASE(8)
+#undef ITV3_CASE
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
+                       pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f)
+              : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
+                       pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f);
+    }
     if (e != hipSuccess) return e;
   }
   const int fin = (start + nl) & 1;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    return launch(k_itv_finish<NN>, grid, PAIRS * T, lds, st, f, pd[fin][0], pd[fin][1], u,
-                  p->at<cx<float>>(L.bufA), p->N1, p->at<const cx<float>>(L.twN2f), mu);
+    return launch(k_itv_finish<NN>, grid, PAIRS * T, lds, st, f, pd[fin][0], pd[fin][1],
+                  pd[fin][2], p->S, u, p->at<cx<float>>(L.bufA), p->N1,
+                  p->at<const cx<float>>(L.twN2f), mu);
   });
   return hipSuccess;
 }
 
 hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
-  if (p->kind == CIP_PRIOR_ITV2D) return itv_row(p, l, st, rho);
+  if (is_itv(p)) return itv_row(p, l, st, rho);
   if (is_dct(p))
     return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr, rho, sc);
   return admm_row_tv(p, l, st, rho, sc);
@@ -1319,7 +1361,7 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   if (rc) return rc;
   if (!d_psf || !d_workspace || !out) return fail(CIP_EINVAL, "NULL pointer argument");
   if (!(rho > 0.0) || !(lambda >= 0.0)) return fail(CIP_EINVAL, "need rho > 0 and lambda >= 0");
-  if (prior->kind == CIP_PRIOR_ITV2D && !(lambda > 0.0))
+  if ((prior->kind == CIP_PRIOR_ITV2D || prior->kind == CIP_PRIOR_ITV3D) && !(lambda > 0.0))
     return fail(CIP_EINVAL, "isotropic TV: lambda must be > 0");
   if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
     return fail(CIP_EINVAL, "workspace must be 256-byte aligned");
@@ -1360,7 +1402,9 @@ int cip_plan_create(int K, int S, int N1, int N2, const float* d_psf, const cip_
   p->filt_l = prior->filt_l;
   p->row_np = PAIRS;
   p->row_ppt = ppt_row_n(N2);
-  p->tv_inner = prior->kind == CIP_PRIOR_ITV2D ? (prior->tv_inner > 0 ? prior->tv_inner : 20) : 0;
+  p->tv_inner = (prior->kind == CIP_PRIOR_ITV2D || prior->kind == CIP_PRIOR_ITV3D)
+                    ? (prior->tv_inner > 0 ? prior->tv_inner : 20)
+                    : 0;
   p->wt_levels =
       prior->kind == CIP_PRIOR_WDCT3D ? (prior->wt_levels > 0 ? prior->wt_levels : 3) : 0;
 
@@ -1591,7 +1635,7 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
   const bool synthesis = p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D ||
                          p->kind == CIP_PRIOR_CONV3D;
-  if (p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
+  if (is_itv(p) || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED,
                 "adaptive penalty: l1 analysis priors and the synthesis priors");
   if (prm->adapt_sigma && !p->learn)
@@ -1933,7 +1977,7 @@ int cip_plan_autotune(cip_plan_t p, int reps, void* stream, cip_tuning* out) {
   if (!p || reps < 1) return fail(CIP_EINVAL, "bad argument");
   if (!p->solved_once) return fail(CIP_EINVAL, "run cip_solve on this plan first");
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
-      p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
+      is_itv(p) || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED, "autotuning covers the l1 analysis row passes");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool dct = is_dct(p);
@@ -1988,7 +2032,7 @@ int cip_plan_set_tuning(cip_plan_t p, int row_np, int row_ppt) {
   const int pd = ppt_row_n(p->N2);
   const bool has8 = is_pow2(p->N2) && pd != 8 && (dct || p->N2 <= 1024);
   if (p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D || p->kind == CIP_PRIOR_CONV3D ||
-      p->kind == CIP_PRIOR_ITV2D || p->kind == CIP_PRIOR_WDCT3D)
+      is_itv(p) || p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED, "tuning covers the l1 analysis row passes");
   if (!(row_np == PAIRS || row_np == 2)) return fail(CIP_EINVAL, "row_np must be 4 or 2");
   if (!(row_ppt == pd || (has8 && row_ppt == 8)))

@@ -1,28 +1,32 @@
-// Isotropic TV prior (Section III-A: Phi(Tx) = TV(x) with T = I, one 2D TV
-// per plane). The x-update is that of a unitary T (tau = 1); the t-update is
-// the TV proximal map of f = x + u with weight mu = lambda / rho, computed with
-// Chambolle's projection algorithm (circular forward differences, step 1/8),
+// Isotropic TV prior (Section III-A: Phi(Tx) = TV(x) with T = I), either one
+// 2D TV per plane or one TV of the whole cube whose gradient also has the
+// forward difference along the planes (none after the last plane). The
+// x-update is that of a unitary T (tau = 1); the t-update is the TV proximal
+// map of f = x + u with weight mu = lambda / rho, computed with Chambolle's
+// projection algorithm (circular forward differences along the image axes),
 // whose dual p is kept in the state and warm-starts the next ADMM iteration:
 //   q = div p - f / mu,   p <- (p + tau grad q) / (1 + tau |grad q|),
 //   t = f - mu div p,     u <- u + x - t = f - t,
-// with div p = (p0[n1] - p0[n1-1]) + (p1[n2] - p1[n2-1]) (the negative adjoint
-// of the forward differences). Per ADMM iteration: k_itv_prep (inverse row
-// FFT, f = x + u), ceil(inner / KB) launches of k_itv_chambolle (up to KB
-// iterations each, in LDS), k_itv_finish (t, u, forward row FFT of t - u for
-// the next column pass).
-// State planes [S][N1][N2] each: u, dual buffer A (p0, p1), dual buffer B
-// (p0, p1), f.
+// with div p = (p0[n1] - p0[n1-1]) + (p1[n2] - p1[n2-1]) [+ p2[s] - p2[s-1]]
+// (the negative adjoint of the forward differences; p2 of the last plane is
+// 0). The step is 1/8 per plane and 1/12 along the planes (the squared norm
+// of div is at most 8, resp. 12). Per ADMM iteration: k_itv_prep (inverse
+// row FFT, f = x + u), ceil(inner / KB) launches of k_itv_chambolle or
+// k_itv3_chambolle (up to KB iterations each, in LDS), k_itv_finish (t, u,
+// forward row FFT of t - u for the next column pass).
+// State planes [S][N1][N2] each: u, dual buffer A (p0, p1[, p2]), dual
+// buffer B (p0, p1[, p2]), f.
 #pragma once
 #include "kernels.hpp"
 
 namespace cip {
 
 // Inverse row FFT of the column-pass output (x rows), f = x + u; on the
-// first iteration u = 0 and the dual starts at p = 0.
+// first iteration u = 0 and the dual starts at p = 0 (p2 is null per plane).
 template <int N2>
 __global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
 k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float* __restrict__ f,
-           float* __restrict__ p0, float* __restrict__ p1, int N1,
+           float* __restrict__ p0, float* __restrict__ p1, float* __restrict__ p2, int N1,
            const cx<float>* __restrict__ twg, int first) {
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
@@ -52,6 +56,7 @@ k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float
     if (first) {
       p0[oa + n] = p0[ob + n] = 0.f;
       p1[oa + n] = p1[ob + n] = 0.f;
+      if (p2) p2[oa + n] = p2[ob + n] = 0.f;
     }
   }
 }
@@ -144,12 +149,122 @@ k_itv_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
   }
 }
 
+// Band-coupled form: one work-group per TS x TS tile holds every plane, and
+// each thread keeps the S values of its pixel columns in registers, so the
+// band differences of div and grad are register arithmetic; LDS carries the
+// in-plane neighbours as in k_itv_chambolle, whose halo argument holds
+// unchanged (the coupling along the planes does not widen the spatial
+// dependence). Per iteration, at every plane s:
+//   q = (p0 - p0[n1-1]) + (p1 - p1[n2-1]) + (p2[s] - p2[s-1]) - f / mu
+//   g = (q[n1+1] - q, q[n2+1] - q, q[s+1] - q), the last plane's g2 = 0
+//   p <- (p + tau g) / (1 + tau |g|)
+// with p2[-1] = 0; p2 of the last plane starts at 0, so it stays 0 and is
+// written as 0. The interior is written from registers.
+template <int S, int TS, int KB, int NT>
+__global__ void __launch_bounds__(NT)
+k_itv3_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
+                 const float* __restrict__ pi1, const float* __restrict__ pi2,
+                 float* __restrict__ po0, float* __restrict__ po1, float* __restrict__ po2,
+                 int N1, int N2, int iters, float inv_mu, float tau) {
+  constexpr int W = TS + 2 * KB;
+  constexpr int R = W * W;
+  constexpr int NSLOT = (R + NT - 1) / NT;
+  static_assert(3 * S * R * 4 <= 65536, "tile does not fit in 64 KiB of LDS");
+  __shared__ float P0[S * R], P1[S * R], Q[S * R];
+  const int tx = N2 / TS;
+  const int r0 = ((int)blockIdx.x / tx) * TS - KB, c0 = ((int)blockIdx.x % tx) * TS - KB;
+  const size_t pn = (size_t)N1 * N2;
+  float rp0[NSLOT][S], rp1[NSLOT][S], rp2[NSLOT][S], rf[NSLOT][S], rq[NSLOT][S];
+  size_t gi[NSLOT];
+  unsigned qm = 0, pm = 0, om = 0;
+#pragma unroll
+  for (int k = 0; k < NSLOT; ++k) {
+    const int e = threadIdx.x + NT * k;
+    const int a = e / W, c = e % W;
+    gi[k] = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) rp0[k][s] = rp1[k][s] = rp2[k][s] = rf[k][s] = rq[k][s] = 0.f;
+    if (e < R) {
+      // r0 + a lies in [-KB, N1 + KB) and KB < N1 (likewise for columns)
+      int gr = r0 + a, gc = c0 + c;
+      gr += gr < 0 ? N1 : (gr >= N1 ? -N1 : 0);
+      gc += gc < 0 ? N2 : (gc >= N2 ? -N2 : 0);
+      gi[k] = (size_t)gr * N2 + gc;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const size_t i = s * pn + gi[k];
+        rp0[k][s] = pi0[i];
+        rp1[k][s] = pi1[i];
+        if (s < S - 1) rp2[k][s] = pi2[i];
+        rf[k][s] = f[i];
+        P0[s * R + e] = rp0[k][s];
+        P1[s * R + e] = rp1[k][s];
+      }
+      if (a >= 1 && c >= 1) {
+        qm |= 1u << k;
+        if (a <= W - 2 && c <= W - 2) pm |= 1u << k;
+      }
+      if (a >= KB && a < KB + TS && c >= KB && c < KB + TS) om |= 1u << k;
+    }
+  }
+  for (int it = 0; it < iters; ++it) {
+    __syncthreads();   // P0, P1 hold the current dual
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) {
+      const int e = threadIdx.x + NT * k;
+      if ((qm >> k) & 1u) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const float b = s > 0 ? rp2[k][s] - rp2[k][s - 1] : rp2[k][s];
+          rq[k][s] = (rp0[k][s] - P0[s * R + e - W]) + (rp1[k][s] - P1[s * R + e - 1]) + b -
+                     rf[k][s] * inv_mu;
+          Q[s * R + e] = rq[k][s];
+        }
+      }
+    }
+    __syncthreads();   // Q complete; P0, P1 no longer read this iteration
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) {
+      const int e = threadIdx.x + NT * k;
+      if ((pm >> k) & 1u) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const float g0 = Q[s * R + e + W] - rq[k][s], g1 = Q[s * R + e + 1] - rq[k][s];
+          const float g2 = s < S - 1 ? rq[k][s + 1] - rq[k][s] : 0.f;
+          // hardware square root and reciprocal (about 1 ulp each)
+          const float inv = __builtin_amdgcn_rcpf(
+              1.f + tau * __builtin_amdgcn_sqrtf(g0 * g0 + g1 * g1 + g2 * g2));
+          rp0[k][s] = (rp0[k][s] + tau * g0) * inv;
+          rp1[k][s] = (rp1[k][s] + tau * g1) * inv;
+          if (s < S - 1) rp2[k][s] = (rp2[k][s] + tau * g2) * inv;
+          P0[s * R + e] = rp0[k][s];
+          P1[s * R + e] = rp1[k][s];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NSLOT; ++k) {
+    if ((om >> k) & 1u) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const size_t i = s * pn + gi[k];
+        po0[i] = rp0[k][s];
+        po1[i] = rp1[k][s];
+        po2[i] = rp2[k][s];
+      }
+    }
+  }
+}
+
 // t = f - mu div p, u = f - t, and the forward row FFT of t - u (two rows
-// per group) -> RT tile of the next column pass.
+// per group) -> RT tile of the next column pass. p2 is null per plane;
+// otherwise div has the band term p2[s] - p2[s-1] (no p2[S-1] term).
 template <int N2>
 __global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
 k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
-             const float* __restrict__ p1, float* __restrict__ u, cx<float>* __restrict__ Gout,
+             const float* __restrict__ p1, const float* __restrict__ p2, int S,
+             float* __restrict__ u, cx<float>* __restrict__ Gout,
              int N1, const cx<float>* __restrict__ twg, float mu) {
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
@@ -175,8 +290,12 @@ k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
     for (int r = 0; r < 2; ++r) {
       const int n1 = ra + r, nu = n1 == 0 ? N1 - 1 : n1 - 1;
       const size_t i = pl + (size_t)n1 * N2 + n;
-      const float dv = (p0[i] - p0[pl + (size_t)nu * N2 + n]) +
-                       (p1[i] - p1[pl + (size_t)n1 * N2 + nl]);
+      float dv = (p0[i] - p0[pl + (size_t)nu * N2 + n]) +
+                 (p1[i] - p1[pl + (size_t)n1 * N2 + nl]);
+      if (p2) {
+        if (s < S - 1) dv += p2[i];
+        if (s > 0) dv -= p2[i - (size_t)N1 * N2];
+      }
       const float fi = f[i];
       const float ti = fi - mu * dv;
       const float ui = fi - ti;

@@ -198,3 +198,19 @@ def test_batch_solve_and_descriptor_fields_are_checked_on_the_host(L):
         d = cip._PriorDesc(cip.CIP_PRIOR_CONV2D, 8.0)
         d.n_filters, d.filt_l, d.per_band = 32, 11, pb
         assert L.cip_plan_workspace_bytes(3, 3, 256, 256, ctypes.byref(d), ctypes.byref(n)) == rc
+
+
+def test_band_coupled_isotropic_tv_validation(L):
+    """The band-coupled isotropic TV keeps a third dual component in both
+    dual buffers (8 floats per voxel against 6 for the per-plane form) and
+    checks its inner iteration count like the per-plane form."""
+    from paper_2006_08303_amd import cip
+    K, S, N = 3, 3, 256
+    d2 = cip.workspace_bytes(K, S, N, N, "itv2d")
+    d3 = cip.workspace_bytes(K, S, N, N, "itv3d")
+    assert d3 - d2 == 2 * S * N * N * 4
+    assert cip.workspace_bytes(8, 8, 16, 16, "itv3d", tv_inner=10000) > 0
+    for bad in (-1, 10001):
+        with pytest.raises(cip.CipError) as e:
+            cip.workspace_bytes(K, S, N, N, "itv3d", tv_inner=bad)
+        assert e.value.code == -1
