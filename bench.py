@@ -157,14 +157,15 @@ def parity_vs_oracle(plan, x_ref, y_ref, x_true, n_iter, dev):
                 round(10 * np.log10(1.0 / float(np.mean((x_ref - x_true) ** 2))), 3)}
 
 
-PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0), "itv2d": (1e-3, 1e-2, 1.0)}
+PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0), "itv2d": (1e-3, 1e-2, 1.0),
+                "itv3d": (1e-3, 1e-2, 1.0)}
 ITV_INNER = 20   # Chambolle iterations per ADMM iteration (isotropic TV)
 
 
 def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     lam, rho, beta = PRIOR_PARAMS[prior]
     plan = cip.Plan(psf_t, prior, rho, lam, beta,
-                    **({"tv_inner": ITV_INNER} if prior == "itv2d" else {}))
+                    **({"tv_inner": ITV_INNER} if prior in ("itv2d", "itv3d") else {}))
     # measurements: y = H x + w, H applied by the library, sigma_k for 30 dB
     hx = plan.forward(x_t)
     sig = hx.pow(2).mean(dim=(1, 2)).sqrt() * 10 ** (-30.0 / 20.0)
@@ -173,7 +174,8 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     print(f"[bench] {prior}: N={N} K=S={S} iters={args.iters} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
     plan.solve(y_t, 2, out=out)
-    tuning = plan.autotune(reps=20) if not (args.no_autotune or prior == "itv2d") else None
+    tuning = (plan.autotune(reps=20)
+              if not (args.no_autotune or prior in ("itv2d", "itv3d")) else None)
     print(f"[bench] {prior}: row-pass shape {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.solve(y_t, args.iters, out=out)
@@ -191,7 +193,10 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     times = {w: plan.time_kernel(w, args.kernel_reps) for w in (0, 1)}
     row_name = {"dct2d": "row pass (k_admm_row_dct)", "tv2d": "row pass (k_admm_row_tv)",
                 "itv2d": f"row passes + {ITV_INNER} Chambolle iterations (k_itv_prep, "
-                         f"k_itv_chambolle x {(ITV_INNER + 4) // 5}, k_itv_finish)"}[prior]
+                         f"k_itv_chambolle x {(ITV_INNER + 4) // 5}, k_itv_finish)",
+                "itv3d": f"row passes + {ITV_INNER} band-coupled Chambolle iterations "
+                         f"(k_itv_prep, k_itv3_chambolle x {(ITV_INNER + 4) // 5}, "
+                         f"k_itv_finish)"}[prior]
     names = {0: row_name, 1: "column pass + per-frequency solve (k_admm_col)"}
     print(f"[bench] {prior}: row {times[0]:.2f} us, col {times[1]:.2f} us", file=sys.stderr,
           flush=True)
@@ -536,6 +541,14 @@ def main():
                         f"iterations per ADMM iteration)", "value": round(itv_value, 1),
                "ms_per_step": round(itv_ms, 4),
                "kernels_avg_us": {itv_names[w]: round(itv_times[w], 3) for w in itv_times}}
+    itv3 = None
+    if not args.no_tv:
+        _, _, _, _, _, itv3_value, itv3_ms, itv3_times, itv3_names, _ = run_prior(
+            "itv3d", N, K, S, args, psf_t, x_t, noise_t)
+        itv3 = {"prior": f"isotropic tv coupled along the bands (lambda=1e-3, rho=1e-2, beta=1, "
+                         f"{ITV_INNER} Chambolle iterations per ADMM iteration)",
+                "value": round(itv3_value, 1), "ms_per_step": round(itv3_ms, 4),
+                "kernels_avg_us": {itv3_names[w]: round(itv3_times[w], 3) for w in itv3_times}}
     if args.copy_calib:
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -589,6 +602,7 @@ def main():
         "parity": parity,
         "tv2d": tv,
         "itv2d": itv,
+        "itv3d": itv3,
         "concurrent_1024": conc,
         "adaptive": adaptive,
         "other_priors": others,

@@ -518,9 +518,12 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    return launch(k_itv_finish<NN>, grid, PAIRS * T, lds, st, f, pd[fin][0], pd[fin][1],
-                  pd[fin][2], p->S, u, p->at<cx<float>>(L.bufA), p->N1,
-                  p->at<const cx<float>>(L.twN2f), mu);
+    return band ? launch(k_itv_finish<NN, true>, grid, PAIRS * T, lds, st, f, pd[fin][0],
+                         pd[fin][1], pd[fin][2], p->S, u, p->at<cx<float>>(L.bufA), p->N1,
+                         p->at<const cx<float>>(L.twN2f), mu)
+                : launch(k_itv_finish<NN, false>, grid, PAIRS * T, lds, st, f, pd[fin][0],
+                         pd[fin][1], pd[fin][2], p->S, u, p->at<cx<float>>(L.bufA), p->N1,
+                         p->at<const cx<float>>(L.twN2f), mu);
   });
   return hipSuccess;
 }

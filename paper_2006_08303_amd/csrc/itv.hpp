@@ -258,9 +258,10 @@ k_itv3_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
 }
 
 // t = f - mu div p, u = f - t, and the forward row FFT of t - u (two rows
-// per group) -> RT tile of the next column pass. p2 is null per plane;
-// otherwise div has the band term p2[s] - p2[s-1] (no p2[S-1] term).
-template <int N2>
+// per group) -> RT tile of the next column pass. BAND: div has the band term
+// p2[s] - p2[s-1] (no p2[S-1] term); both loads are made on every plane (at
+// in-range addresses) and the terms selected, so they issue with the others.
+template <int N2, bool BAND>
 __global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
 k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
              const float* __restrict__ p1, const float* __restrict__ p2, int S,
@@ -280,7 +281,8 @@ k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   lds_load_table(tw, twg, N2);
   const int ra = row0 + 2 * g;
-  const size_t pl = (size_t)s * N1 * N2;
+  const size_t pn = (size_t)N1 * N2, pl = (size_t)s * pn;
+  const bool has_next = s < S - 1, has_prev = s > 0;
   cx<float> v[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -292,9 +294,10 @@ k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
       const size_t i = pl + (size_t)n1 * N2 + n;
       float dv = (p0[i] - p0[pl + (size_t)nu * N2 + n]) +
                  (p1[i] - p1[pl + (size_t)n1 * N2 + nl]);
-      if (p2) {
-        if (s < S - 1) dv += p2[i];
-        if (s > 0) dv -= p2[i - (size_t)N1 * N2];
+      if constexpr (BAND) {
+        const float a2 = p2[i], b2 = p2[has_prev ? i - pn : i];
+        dv += has_next ? a2 : 0.f;
+        dv -= has_prev ? b2 : 0.f;
       }
       const float fi = f[i];
       const float ti = fi - mu * dv;
