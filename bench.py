@@ -86,41 +86,59 @@ def make_workload(N, K, S, dev, snr_db=30.0, seed_config=3):
     return x, psf, noise, psf_t, x_t, noise_t
 
 
-def cpu_baseline(x, psf, noise, lam, rho, beta, n_iter):
+def cpu_baseline(x, psf, noise, lam, rho, beta, n_iter, n_iter_1t=10):
     """FP64 oracle (frequency tier) on a bounded sample of the same workload.
 
     The oracle forms its own measurements from the generated scene, kernels
     and noise (y = H x + w in space, 30 dB, rounded to float32 so that the GPU
     can be given exactly the same y), runs n_iter iterations of Algorithm 1
-    and returns (record, x after n_iter iterations, y)."""
+    and returns (record, x after n_iter iterations, y). `cores` is the number
+    of threads the loop kept busy on average (process CPU time over wall
+    time: NumPy's FFTs and einsum run on one thread, the BLAS products of the
+    explicit DCT matrices on the whole pool); a second, shorter run is limited
+    to one thread."""
     from oracle import admm, model, priors
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        pool = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count()
+        threadpool_limits = None
+        pool = os.cpu_count()
     y = model.measure(x, psf, noise, 30.0).astype(np.float32).astype(np.float64)
     alg = admm.AnalysisADMM(psf, "dct2d", lam, rho, beta, tier="freq")
     data = alg.solver.data_term(y)
     T = alg.T
-    t_ = np.zeros(T.shape)
-    u_ = np.zeros(T.shape)
     kappa = lam / rho
-    xx = None
-    t0 = time.perf_counter()
-    for _ in range(n_iter):
-        xx = alg.x_update(data, t_, u_)
-        w = T.T(xx)
-        tn = priors.soft(w + u_, kappa)
-        u_ = u_ + w - tn
-        t_ = tn
-    dt = time.perf_counter() - t0
+
+    def run(iters):
+        t_ = np.zeros(T.shape)
+        u_ = np.zeros(T.shape)
+        xx = None
+        c0, t0 = time.process_time(), time.perf_counter()
+        for _ in range(iters):
+            xx = alg.x_update(data, t_, u_)
+            w = T.T(xx)
+            tn = priors.soft(w + u_, kappa)
+            u_ = u_ + w - tn
+            t_ = tn
+        return xx, time.perf_counter() - t0, time.process_time() - c0
+
+    xx, dt, cpu = run(n_iter)
     N1, N2 = psf.shape[-2:]
-    rec = {"value": N1 * N2 * n_iter / dt / 1e6, "unit": "Mpixel*ADMM-iter/s", "cores": int(cores),
-           "kind": "oracle", "cpu_model": cpu_model(),
+    busy = cpu / dt
+    rec = {"value": N1 * N2 * n_iter / dt / 1e6, "unit": "Mpixel*ADMM-iter/s",
+           "cores": max(1, int(round(busy))), "kind": "oracle", "cpu_model": cpu_model(),
+           "threads_available": int(pool), "cpu_time_over_wall": round(busy, 2),
            "sample": f"{n_iter} ADMM iterations (x-update, prox, dual) of the same "
-                     f"{N1}x{N2} K=S={psf.shape[1]} DCT-l1 problem in FP64 NumPy on {cores} "
-                     f"threads, per-solve setup excluded; {dt:.1f} s"}
+                     f"{N1}x{N2} K=S={psf.shape[1]} DCT-l1 problem in FP64 NumPy "
+                     f"(thread pools of {pool}; {busy:.2f} threads busy on average), "
+                     f"per-solve setup excluded; {dt:.1f} s"}
+    if threadpool_limits is not None and n_iter_1t > 0:
+        with threadpool_limits(limits=1):
+            _, dt1, _ = run(n_iter_1t)
+        rec["one_thread"] = {"value": round(N1 * N2 * n_iter_1t / dt1 / 1e6, 3),
+                             "sample": f"{n_iter_1t} iterations, thread pools limited to 1; "
+                                       f"{dt1:.1f} s"}
     return rec, xx, y
 
 
