@@ -133,3 +133,25 @@ def test_itv3_rejects_zero_lambda_and_bad_inner_count():
         cip.Plan(_t(psf), "itv3d", 1e-2, 0.0, 1.0)
     with pytest.raises(RuntimeError):
         cip.Plan(_t(psf), "itv3d", 1e-2, 1e-3, 1.0, tv_inner=10001)
+
+
+@pytest.mark.parametrize("prior,N1,N2,K,S,iters,inner", [("itv2d", 64, 128, 2, 2, 6, 7),
+                                                         ("itv2d", 384, 256, 3, 3, 3, 10),
+                                                         ("itv3d", 128, 64, 2, 3, 6, 7),
+                                                         ("itv3d", 16, 64, 2, 2, 5, 6),
+                                                         ("itv3d", 256, 384, 3, 3, 3, 10),
+                                                         ("itv3d", 64, 32, 4, 5, 4, 5)])
+def test_itv_rectangular_grids(prior, N1, N2, K, S, iters, inner):
+    """Grids with N1 != N2 (tile counts differ along the two axes; 16-row
+    grids take 16 x 16 tiles): smooth bands blurred by defocus disks, 30 dB."""
+    print(f"{prior} N1={N1} N2={N2} K={K} S={S} iters={iters} inner={inner}", flush=True)
+    x = synth.smooth_images(synth.rng_for(12, 0), S, N1, N2).astype(np.float32).astype(np.float64)
+    psf = synth.disk_psfs(K, S, N1, N2).astype(np.float32).astype(np.float64)
+    noise = synth.unit_noise(synth.rng_for(12, 2), K, N1, N2).astype(np.float32).astype(np.float64)
+    hx = model.forward(x, psf)
+    y = (hx + model.snr_noise_scale(hx, 30.0)[:, None, None] * noise).astype(np.float32)
+    y = y.astype(np.float64)
+    lam, rho = 1e-3, 1e-2
+    ref = admm.AnalysisADMM(psf, prior, lam, rho, 1.0, tier="freq", inner=inner).run(y, iters)[0]
+    got = _np(cip.Plan(_t(psf), prior, rho, lam, 1.0, tv_inner=inner).solve(_t(y), iters))
+    parity.check(got, ref, 1e-4)
