@@ -138,7 +138,9 @@ typedef struct {
                            (K*S*N1*(N2/2+1)*16 more bytes), the FP64 filter
                            spectra for the conv priors (M*N1*(N2/2+1)*16,
                            times S for CONV3D), a host copy of D for the
-                           patch prior;
+                           patch prior, and t of the iteration before a
+                           check for the isotropic TV priors
+                           (S*N1*N2*4);
                            CIP_PLAN_DICT_UPDATE (CIP_PRIOR_PATCH,
                            CIP_PRIOR_CONV2D and CIP_PRIOR_CONV3D): learn
                            the dictionary online during every solve         */
@@ -232,10 +234,11 @@ int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* st
  *   X = [P_1 x | ... | P_J x] and the codes Z of the iteration,
  *   D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1, G = (D + E) / ||D + E||_F
  *   (the constraint ||D||_F = 1 of Eq. patch_based_dic), E <- E + G - D;
- *   the code update's tables (G and M1 = G^T (rho I + G G^T)^-1, BF16) are
- *   rebuilt from G on the GPU (X Z^T and Z Z^T from split BF16 operands with
- *   FP32 accumulation, about 16 significant bits; FP32 Cholesky factors and
- *   triangular solves).
+ *   D is formed in FP64 on the GPU (X Z^T and Z Z^T on FP64 MFMA from the
+ *   FP32 image and the FP32 codes, the FP64 Cholesky factor of
+ *   Z Z^T + sigma I and FP64 triangular solves); the code update's tables
+ *   (G and M1 = G^T (rho I + G G^T)^-1) are rebuilt from G in FP32 and
+ *   stored in BF16.
  * This call copies g of the last solve (the layout of the plan's dictionary:
  * [n][A], [M][L][L] or [M][S][L][L] float32) to the device buffer d_filters,
  * asynchronously on `stream`. CIP_EINVAL if the plan does not learn its
@@ -253,7 +256,9 @@ int cip_plan_destroy(cip_plan_t plan);
  * stops with x^l when c < tol; otherwise sets rho <- tau rho if r > mu s,
  * rho <- rho / tau if s > mu r, rescales the scaled dual u by the inverse
  * factor and recomputes the FP64 per-frequency inverses for the new rho
- * before the next x-update.
+ * before the next x-update. For the isotropic TV priors T = I, t^l is the
+ * TV proximal map at weight lambda / rho, and Chambolle's dual is kept as
+ * the warm start across a change.
  * Algorithm 2 (CIP_PRIOR_PATCH, CIP_PRIOR_CONV2D, CIP_PRIOR_CONV3D with a
  * fixed dictionary) from z = t = u = 0, the split z = t: the same rule with
  *   r = ||z^l - t^l||,  s = rho ||t^l - t^(l-1)||,
@@ -269,9 +274,8 @@ int cip_plan_destroy(cip_plan_t plan);
  *   r_d = ||D - G||,  s_d = sigma ||G - G_prev||,
  *   sigma <- tau sigma if r_d > mu s_d, sigma / tau if s_d > mu r_d, and the
  *   scaled dual E is rescaled by sigma_old / sigma_new.
- * CIP_EUNSUPPORTED for CIP_PRIOR_ITV2D, CIP_PRIOR_ITV3D and CIP_PRIOR_WDCT3D,
- * and for
- * adapt_sigma on a plan that does not learn its dictionary.
+ * CIP_EUNSUPPORTED for CIP_PRIOR_WDCT3D, and for adapt_sigma on a plan that
+ * does not learn its dictionary.
  * The plan must have been created with CIP_PLAN_ADAPTIVE and must not be an
  * attached plan; its tables are back at its own rho when the call returns.
  * Synchronous: waits on `stream` at every check and returns when x is in

@@ -78,6 +78,7 @@ struct Layout {
   size_t wband, wcoef, wtmp;            // wavelet (x) DCT: band DCT, coefficients, staging
   size_t filt0, gtap, gehat, dsp, ecdl, dpl;                 // 3D dictionary update
   size_t gprev;                         // conv learning with adaptive penalties: G_prev taps
+  size_t tprev;                         // isotropic TV with adaptive penalties: t of the last store
   size_t tables;                        // bytes of the table region
   size_t state_bytes;                   // bytes of the state region
   size_t total;                         // tables + state_bytes
@@ -157,6 +158,8 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
     }
     L.sums = sta(nsum * 4);
   }
+  if (adaptive && (kind == CIP_PRIOR_ITV2D || kind == CIP_PRIOR_ITV3D))
+    L.tprev = sta((size_t)S * N1 * N2 * 4);
   L.rt64 = scr(F * 16);
   L.pl64 = scr((size_t)N1 * N2 * 8);
   if (kind == CIP_PRIOR_WDCT3D) {
@@ -466,25 +469,68 @@ hipError_t itv3_launch(bool t32, int grid32, int grid16, hipStream_t st, const f
                 in[1], in[2], out[0], out[1], out[2], N1, N2, m, inv_mu, 1.f / 12.f);
 }
 
-hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
-  const Layout& L = p->L;
-  const float mu = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
+// Dual buffers of the isotropic TV state: pd[b][c] is component c of buffer b
+// (component 2 only when coupled along the bands).
+struct ItvState {
+  float* u;
+  float* pd[2][3];
+  float* f;
+  int nl;   // Chambolle launches per ADMM iteration
+};
+
+ItvState itv_state(cip_plan_t p) {
   const size_t n = (size_t)p->S * p->N1 * p->N2;
   const bool band = p->kind == CIP_PRIOR_ITV3D;
-  const int nc = band ? 3 : 2;   // dual components
-  float* u = p->at<float>(L.state);
-  float* pd[2][3] = {{u + n, u + 2 * n, band ? u + 3 * n : nullptr},
-                     {u + (1 + nc) * n, u + (2 + nc) * n, band ? u + 6 * n : nullptr}};
-  float* f = u + (1 + 2 * nc) * n;
-  const int nl = (p->tv_inner + ITV_KB - 1) / ITV_KB;
+  const int nc = band ? 3 : 2;
+  ItvState s;
+  s.u = p->at<float>(p->L.state);
+  float* u = s.u;
+  s.pd[0][0] = u + n;
+  s.pd[0][1] = u + 2 * n;
+  s.pd[0][2] = band ? u + 3 * n : nullptr;
+  s.pd[1][0] = u + (1 + nc) * n;
+  s.pd[1][1] = u + (2 + nc) * n;
+  s.pd[1][2] = band ? u + 6 * n : nullptr;
+  s.f = u + (1 + 2 * nc) * n;
+  s.nl = (p->tv_inner + ITV_KB - 1) / ITV_KB;
+  return s;
+}
+
+// Closing row pass of iteration l: t = f - mu div p, u = c (f - t), spectrum
+// of t - u to bufA. Pass l leaves the dual in buffer (l nl) mod 2.
+hipError_t itv_finish(cip_plan_t p, int l, float mu, float c, hipStream_t st) {
+  const ItvState S = itv_state(p);
+  const int fin = (int)(((long long)l * S.nl) & 1);
+  const int grid = p->S * (p->N1 / RT);
+  const bool band = p->kind == CIP_PRIOR_ITV3D;
+  DISPATCH_N(p->N2, {
+    const int T = NN / ppt_row<NN>();
+    size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
+    return band ? launch(k_itv_finish<NN, true>, grid, PAIRS * T, lds, st, S.f, S.pd[fin][0],
+                         S.pd[fin][1], S.pd[fin][2], p->S, S.u, p->at<cx<float>>(p->L.bufA),
+                         p->N1, p->at<const cx<float>>(p->L.twN2f), mu, c)
+                : launch(k_itv_finish<NN, false>, grid, PAIRS * T, lds, st, S.f, S.pd[fin][0],
+                         S.pd[fin][1], S.pd[fin][2], p->S, S.u, p->at<cx<float>>(p->L.bufA),
+                         p->N1, p->at<const cx<float>>(p->L.twN2f), mu, c);
+  });
+  return hipSuccess;
+}
+
+// xo: when given, x^l is also written there (adaptive checks).
+hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho, float* xo = nullptr) {
+  const Layout& L = p->L;
+  const float mu = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
+  const bool band = p->kind == CIP_PRIOR_ITV3D;
+  const ItvState S = itv_state(p);
+  const int nl = S.nl;
   const int start = (int)(((long long)(l - 1) * nl) & 1);
   const int grid = p->S * (p->N1 / RT);
   hipError_t e = hipSuccess;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), u, f,
-               pd[start][0], pd[start][1], pd[start][2], p->N1,
+    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), S.u,
+               S.f, S.pd[start][0], S.pd[start][1], S.pd[start][2], xo, p->N1,
                p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
   });
   if (e != hipSuccess) return e;
@@ -495,11 +541,13 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
   for (int j = 0; j < nl; ++j) {
     const int in = (start + j) & 1, out = in ^ 1;
     const int m = std::min(ITV_KB, p->tv_inner - j * ITV_KB);
+    float* const* pin = S.pd[in];
+    float* const* pout = S.pd[out];
     if (band) {
       switch (p->S) {
-#define ITV3_CASE(SS)                                                                         \
-  case SS:                                                                                    \
-    e = itv3_launch<SS>(t32, g32, g16, st, f, pd[in], pd[out], p->N1, p->N2, m, 1.f / mu);    \
+#define ITV3_CASE(SS)                                                                       \
+  case SS:                                                                                  \
+    e = itv3_launch<SS>(t32, g32, g16, st, S.f, pin, pout, p->N1, p->N2, m, 1.f / mu);     \
     break;
         ITV3_CASE(1) ITV3_CASE(2) ITV3_CASE(3) ITV3_CASE(4)
         ITV3_CASE(5) ITV3_CASE(6) ITV3_CASE(7) ITV3_CASE(8)
@@ -507,25 +555,14 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho) {
         default: return hipErrorInvalidValue;
       }
     } else {
-      e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
-                       pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f)
-              : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, f, pd[in][0], pd[in][1],
-                       pd[out][0], pd[out][1], p->N1, p->N2, m, 1.f / mu, 0.125f);
+      e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, S.f, pin[0], pin[1],
+                       pout[0], pout[1], p->N1, p->N2, m, 1.f / mu, 0.125f)
+              : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, S.f, pin[0], pin[1],
+                       pout[0], pout[1], p->N1, p->N2, m, 1.f / mu, 0.125f);
     }
     if (e != hipSuccess) return e;
   }
-  const int fin = (start + nl) & 1;
-  DISPATCH_N(p->N2, {
-    const int T = NN / ppt_row<NN>();
-    size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    return band ? launch(k_itv_finish<NN, true>, grid, PAIRS * T, lds, st, f, pd[fin][0],
-                         pd[fin][1], pd[fin][2], p->S, u, p->at<cx<float>>(L.bufA), p->N1,
-                         p->at<const cx<float>>(L.twN2f), mu)
-                : launch(k_itv_finish<NN, false>, grid, PAIRS * T, lds, st, f, pd[fin][0],
-                         pd[fin][1], pd[fin][2], p->S, u, p->at<cx<float>>(L.bufA), p->N1,
-                         p->at<const cx<float>>(L.twN2f), mu);
-  });
-  return hipSuccess;
+  return itv_finish(p, l, mu, 1.f, st);
 }
 
 hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
@@ -1631,6 +1668,104 @@ int cip_plan_destroy(cip_plan_t p) {
   return CIP_OK;
 }
 
+// Algorithm 1 with an isotropic TV prior and the penalty rule of Eq. paramS
+// (T = I). At a checked iteration l < iters, after the t-update:
+//   r = ||x^l - t^l||,  s = rho ||t^l - t^(l-1)||,  stop on the iterate change,
+//   else rho <- tau rho if r > mu s, rho / tau if s > mu r;
+// on a change the closing row pass runs again with c = rho / rho' (the scaled
+// dual rescaled, the spectrum of t - u' re-emitted), Psi^+ and x_hat0 are
+// rebuilt, and Chambolle's dual stays as the next warm start. x^l comes from
+// the prep pass (kept at the checks and the iterations before them), t^(l-1)
+// from the norm pass of the iteration before a check.
+int solve_itv_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params* prm,
+                       float* d_x, hipStream_t st, cip_solve_info& out) {
+  const Layout& L = p->L;
+  const int iters = prm->max_iters, every = prm->every;
+  const double rho0 = p->rho;
+  double rho = rho0;
+  const size_t n = (size_t)p->S * p->N1 * p->N2;
+  float* xb0 = p->at<float>(L.xbuf);
+  float* xb1 = xb0 + n;
+  auto xbuf = [&](int l) { return (l & 1) ? xb1 : xb0; };
+  float* tprev = p->at<float>(L.tprev);
+  const ItvState S = itv_state(p);
+  const int groups = p->S * (p->N1 / RT);
+  std::vector<float> sums((size_t)groups * 4);
+  auto xhat0 = [&]() -> hipError_t {
+    // Alg. 1 step 2 with the current tables: x_hat0 = Psi^+ beta Lambda^H F y / (N1 N2)
+    hipError_t e = row_r2c<float>(d_y, p->at<cx<float>>(L.bufB), p->K, p->N1, p->N2,
+                                  p->at<const cx<float>>(L.twN2f), st);
+    if (e != hipSuccess) return e;
+    return col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufB), p->at<void>(L.xh0), p->K, p->S,
+                                   p->N1, p->H2, p->at<const cx<float>>(L.twN1f),
+                                   p->at<const cx<float>>(L.Mm), 0, st);
+  };
+  auto body = [&]() -> int {
+    HIP_TRY(xhat0());
+    HIP_TRY(admm_col(p, 1, 0, st));   // x^1 (t = u = 0)
+    for (int l = 1;; ++l) {
+      if (l == iters) {   // the last iterate is returned without a check
+        out.iters = l;
+        HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
+        break;
+      }
+      const bool check = l % every == 0;
+      const bool store = (l + 1) % every == 0;   // keep x^l and t^l for the next check
+      float* xo = (check || store) ? xbuf(l) : nullptr;
+      HIP_TRY(itv_row(p, l, st, rho, xo));
+      double next = rho;
+      bool stop = false;
+      if (check || store) {
+        HIP_TRY(launch(k_itv_norm, groups, 256, 0, st, S.f, S.u, xo, tprev,
+                       check && l > 1 ? xbuf(l - 1) : nullptr, RT * p->N2, l == 1 ? 1 : 0,
+                       store ? 1 : 0, p->at<float>(L.sums)));
+        if (check) {
+          HIP_TRY(hipMemcpyAsync(sums.data(), p->at<float>(L.sums), sums.size() * 4,
+                                 hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipStreamSynchronize(st));
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int b = 0; b < groups; ++b)
+            for (int i = 0; i < 4; ++i) acc[i] += (double)sums[(size_t)b * 4 + i];
+          const double r = std::sqrt(acc[0]), sres = rho * std::sqrt(acc[1]);
+          out.r_norm = r;
+          out.s_norm = sres;
+          if (l > 1) {
+            out.rel_change = acc[3] > 0.0 ? std::sqrt(acc[2] / acc[3]) : 0.0;
+            stop = out.rel_change < prm->tol;
+          }
+          if (!stop) {
+            if (r > prm->mu * sres) next = prm->tau * rho;
+            else if (sres > prm->mu * r) next = rho / prm->tau;
+          }
+        }
+      }
+      if (stop) {   // x^l: its spectrum is still the column-pass output
+        out.iters = l;
+        HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
+        break;
+      }
+      if (next != rho) {
+        HIP_TRY(itv_finish(p, l, (float)(p->lambda / rho), (float)(rho / next), st));
+        HIP_TRY(gram(p, st, next));
+        HIP_TRY(xhat0());
+        rho = next;
+        ++out.rho_changes;
+      }
+      HIP_TRY(admm_col(p, 0, 0, st));
+    }
+    return CIP_OK;
+  };
+  int rc = body();
+  out.rho = rho;
+  if (rho != rho0) {   // leave the plan's tables at its own penalty
+    hipError_t e = gram(p, st, rho0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess && rc == CIP_OK)
+      rc = fail(CIP_EHIP, std::string("restoring the tables: ") + hipGetErrorString(e));
+  }
+  return rc;
+}
+
 int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params* prm, float* d_x,
                        void* stream, cip_solve_info* info) {
   if (!p || !d_y || !d_x || !prm) return fail(CIP_EINVAL, "NULL argument");
@@ -1638,9 +1773,9 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
   const bool synthesis = p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D ||
                          p->kind == CIP_PRIOR_CONV3D;
-  if (is_itv(p) || p->kind == CIP_PRIOR_WDCT3D)
+  if (p->kind == CIP_PRIOR_WDCT3D)
     return fail(CIP_EUNSUPPORTED,
-                "adaptive penalty: l1 analysis priors and the synthesis priors");
+                "adaptive penalty: not for the wavelet prior");
   if (prm->adapt_sigma && !p->learn)
     return fail(CIP_EUNSUPPORTED, "adapt_sigma: the plan does not learn its dictionary");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
@@ -1659,6 +1794,14 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
     out.rel_change = -1.0;
     const int rc = p->kind == CIP_PRIOR_PATCH ? solve_patch_adaptive(p, prm, d_x, st, out)
                                               : solve_conv_adaptive(p, prm, d_x, st, out);
+    p->solved_once = true;
+    if (info) *info = out;
+    return rc;
+  }
+  if (is_itv(p)) {
+    cip_solve_info out{};
+    out.rel_change = -1.0;
+    const int rc = solve_itv_adaptive(p, d_y, prm, d_x, st, out);
     p->solved_once = true;
     if (info) *info = out;
     return rc;

@@ -23,11 +23,12 @@ namespace cip {
 
 // Inverse row FFT of the column-pass output (x rows), f = x + u; on the
 // first iteration u = 0 and the dual starts at p = 0 (p2 is null per plane).
+// x is also written to xo when given (the iterate of an adaptive check).
 template <int N2>
 __global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
 k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float* __restrict__ f,
-           float* __restrict__ p0, float* __restrict__ p1, float* __restrict__ p2, int N1,
-           const cx<float>* __restrict__ twg, int first) {
+           float* __restrict__ p0, float* __restrict__ p1, float* __restrict__ p2,
+           float* __restrict__ xo, int N1, const cx<float>* __restrict__ twg, int first) {
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
@@ -53,6 +54,10 @@ k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float
     const int n = t + T * q;
     f[oa + n] = v[q].x + (first ? 0.f : u[oa + n]);
     f[ob + n] = v[q].y + (first ? 0.f : u[ob + n]);
+    if (xo) {
+      xo[oa + n] = v[q].x;
+      xo[ob + n] = v[q].y;
+    }
     if (first) {
       p0[oa + n] = p0[ob + n] = 0.f;
       p1[oa + n] = p1[ob + n] = 0.f;
@@ -257,8 +262,11 @@ k_itv3_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
   }
 }
 
-// t = f - mu div p, u = f - t, and the forward row FFT of t - u (two rows
-// per group) -> RT tile of the next column pass. BAND: div has the band term
+// t = f - mu div p, u = c (f - t), and the forward row FFT of t - u (two
+// rows per group) -> RT tile of the next column pass. c = 1, or
+// rho / rho' when an adaptive solve changes the penalty after this
+// iteration's t-update (the scaled dual is rescaled; f and p are unchanged,
+// so the pass can run again with the new c). BAND: div has the band term
 // p2[s] - p2[s-1] (no p2[S-1] term); both loads are made on every plane (at
 // in-range addresses) and the terms selected, so they issue with the others.
 template <int N2, bool BAND>
@@ -266,7 +274,7 @@ __global__ void __launch_bounds__(PAIRS * (N2 / ppt_row<N2>()))
 k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
              const float* __restrict__ p1, const float* __restrict__ p2, int S,
              float* __restrict__ u, cx<float>* __restrict__ Gout,
-             int N1, const cx<float>* __restrict__ twg, float mu) {
+             int N1, const cx<float>* __restrict__ twg, float mu, float c) {
   constexpr int PPT = ppt_row<N2>();
   constexpr int T = N2 / PPT;
   constexpr int H2 = N2 / 2 + 1;
@@ -301,7 +309,7 @@ k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
       }
       const float fi = f[i];
       const float ti = fi - mu * dv;
-      const float ui = fi - ti;
+      const float ui = c * (fi - ti);
       u[i] = ui;
       o[r] = ti - ui;
     }

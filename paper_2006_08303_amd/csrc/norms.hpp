@@ -42,6 +42,35 @@ __device__ __forceinline__ void block_sum4(const float (&a)[4], float* red, floa
   if (tid < 4) out[tid] = red[tid * NTP];
 }
 
+// Isotropic TV priors (T = I), after the t-update of iteration l: with
+// t^l = f - u^l (f = x^l + u^(l-1), u^l the updated dual), the work-group of
+// `count` consecutive values (RT rows of one plane) sums (x^l - t^l)^2,
+// (t^l - t^(l-1))^2 (t^(l-1) = 0 when first), and (x^l - x^(l-1))^2 and
+// (x^(l-1))^2 when xprev is given, to sums[4 b]; when keep, t^l replaces
+// t^(l-1) in tprev (read first, element by element).
+__global__ void __launch_bounds__(256)
+k_itv_norm(const float* __restrict__ f, const float* __restrict__ u, const float* __restrict__ x,
+           float* __restrict__ tprev, const float* __restrict__ xprev, int count, int first,
+           int keep, float* __restrict__ sums) {
+  __shared__ float red[4 * 256];
+  const size_t base = (size_t)blockIdx.x * count;
+  float a[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int i = threadIdx.x; i < count; i += 256) {
+    const size_t k = base + i;
+    const float xv = x[k], tv = f[k] - u[k];
+    const float tp = first ? 0.f : tprev[k];
+    a[0] += (xv - tv) * (xv - tv);
+    a[1] += (tv - tp) * (tv - tp);
+    if (xprev) {
+      const float pv = xprev[k];
+      a[2] += (xv - pv) * (xv - pv);
+      a[3] += pv * pv;
+    }
+    if (keep) tprev[k] = tv;
+  }
+  block_sum4<256>(a, red, sums + 4 * blockIdx.x);
+}
+
 // One constraint element: w = (T x)_i, p = current state value.
 __device__ __forceinline__ void residual_terms(float w, float p, float kappa, float (&acc)[4]) {
   const float tp = soft_f(p, kappa);

@@ -71,6 +71,59 @@ def test_adaptive_without_changes_equals_plain_solve():
         assert torch.equal(a, b), prior
 
 
+# Isotropic TV (T = I, Chambolle t-update with `inner` iterations, dual kept
+# across a change); oracle traces in the comments
+@pytest.mark.parametrize("prior,N,K,S,rho0,every,tol,maxit,inner", [
+    ("itv2d", 64, 3, 3, 1e-4, 2, 1e-4, 120, 10),    # 10 changes, runs to the cap
+    ("itv2d", 64, 3, 3, 1.0, 3, 1e-4, 120, 10),     # 2 changes, runs to the cap
+    ("itv3d", 64, 3, 3, 1e-4, 2, 1e-4, 120, 10),    # 11 changes, stops at 26
+    ("itv3d", 128, 2, 3, 1.0, 5, 1e-4, 100, 10),    # 1 change, stops at 55
+    ("itv3d", 64, 3, 3, 1e-2, 1, 1e-4, 60, 5),      # 4 changes, stops at 17
+])
+def test_itv_adaptive_matches_oracle(prior, N, K, S, rho0, every, tol, maxit, inner):
+    print(f"adaptive {prior} N={N} K={K} S={S} rho0={rho0} every={every} inner={inner}",
+          flush=True)
+    lam = 1e-3
+    x, psf, y = _problem(N, K, S, 9)
+    ref, rinfo = admm.AnalysisADMM(psf, prior, lam, rho0, 1.0, tier="freq",
+                                   inner=inner).run_adaptive(y, maxit, every=every, tol=tol)
+    plan = cip.Plan(_t(psf), prior, rho0, lam, 1.0, adaptive=True, tv_inner=inner)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=every, tol=tol)
+    got = _np(got)
+    changes = sum(1 for a, b in zip(rinfo["rhos"], rinfo["rhos"][1:]) if a != b)
+    err = admm.rel_l2(got, ref)
+    print(f"  oracle: iters {rinfo['iters']} rho {rinfo['rho']:.3g} changes {changes}; "
+          f"gpu: iters {ginfo['iters']} rho {ginfo['rho']:.3g} changes {ginfo['rho_changes']}; "
+          f"rel_l2 {err:.3e}", flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == changes
+    parity.check(got, ref, 1e-4)
+
+
+def test_itv_adaptive_without_changes_equals_plain_solve_and_restores_tables():
+    """No change and no stop: the same kernels as cip_solve (the norm pass
+    only reads the state), bit for bit; after a solve with changes the plan
+    solves as before. The wavelet prior refuses an adaptive solve."""
+    x, psf, y = _problem(64, 3, 3, 9)
+    for prior in ("itv2d", "itv3d"):
+        plan = cip.Plan(_t(psf), prior, 0.05, 1e-3, 1.0, adaptive=True, tv_inner=7)
+        a, info = plan.solve_adaptive(_t(y), 12, every=1, mu=1e30, tol=0.0)
+        b = plan.solve(_t(y), 12)
+        torch.cuda.synchronize()
+        assert info["rho_changes"] == 0 and info["iters"] == 12
+        assert torch.equal(a, b), prior
+        _, info = plan.solve_adaptive(_t(y), 30, every=1, tol=0.0, mu=1.5)
+        assert info["rho_changes"] > 0
+        c = plan.solve(_t(y), 12)
+        torch.cuda.synchronize()
+        assert torch.equal(c, b), prior
+    wd = cip.Plan(_t(psf), "wdct3d", 0.1, 1e-2, 1.0, adaptive=True)
+    with pytest.raises(cip.CipError) as e:
+        wd.solve_adaptive(_t(y), 10)
+    assert e.value.code == -2
+
+
 def test_adaptive_leaves_tables_at_plan_rho():
     x, psf, y = _problem(128, 3, 3, 9)
     plan = cip.Plan(_t(psf), "dct2d", 1e-3, 1e-2, 1.0, adaptive=True)
