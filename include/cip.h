@@ -258,7 +258,8 @@ int cip_plan_destroy(cip_plan_t plan);
  * factor and recomputes the FP64 per-frequency inverses for the new rho
  * before the next x-update. For the isotropic TV priors T = I, t^l is the
  * TV proximal map at weight lambda / rho, and Chambolle's dual is kept as
- * the warm start across a change.
+ * the warm start across a change; for the wavelet (x) DCT prior the
+ * residuals are summed in the coefficient domain (T orthonormal).
  * Algorithm 2 (CIP_PRIOR_PATCH, CIP_PRIOR_CONV2D, CIP_PRIOR_CONV3D with a
  * fixed dictionary) from z = t = u = 0, the split z = t: the same rule with
  *   r = ||z^l - t^l||,  s = rho ||t^l - t^(l-1)||,
@@ -274,8 +275,8 @@ int cip_plan_destroy(cip_plan_t plan);
  *   r_d = ||D - G||,  s_d = sigma ||G - G_prev||,
  *   sigma <- tau sigma if r_d > mu s_d, sigma / tau if s_d > mu r_d, and the
  *   scaled dual E is rescaled by sigma_old / sigma_new.
- * CIP_EUNSUPPORTED for CIP_PRIOR_WDCT3D, and for adapt_sigma on a plan that
- * does not learn its dictionary.
+ * CIP_EUNSUPPORTED for adapt_sigma on a plan that does not learn its
+ * dictionary.
  * The plan must have been created with CIP_PLAN_ADAPTIVE and must not be an
  * attached plan; its tables are back at its own rho when the call returns.
  * Synchronous: waits on `stream` at every check and returns when x is in

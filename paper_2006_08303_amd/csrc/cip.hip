@@ -156,6 +156,11 @@ Layout make_layout(int K, int S, int N1, int N2, const cip_prior_desc* prior) {
                         2 * XCHANGE_GROUPS + 4 + 2 * CDL_RES_GROUPS + 4;
       if (cs > nsum) nsum = cs;
     }
+    if (kind == CIP_PRIOR_WDCT3D) {
+      // state-pass residuals, k_xchange sums, two FP64 totals
+      const size_t ws = 2 * (size_t)wavelet_state_groups(N1, N2) + 2 * XCHANGE_GROUPS + 4;
+      if (ws > nsum) nsum = ws;
+    }
     L.sums = sta(nsum * 4);
   }
   if (adaptive && (kind == CIP_PRIOR_ITV2D || kind == CIP_PRIOR_ITV3D))
@@ -881,6 +886,113 @@ hipError_t solve_wdct(cip_plan_t p, int iters, float* d_x, hipStream_t st) {
     if ((e = wavelet_inverse(coef, r, tmp, S, N1, N2, lv, st)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Algorithm 1 with the wavelet (x) DCT prior and the penalty rule of Eq.
+// paramS: at a checked iteration l < iters the state pass sums
+//   r^2 = sum (T x^l - t^l)^2 = sum (clip(v^l) - clip(v^(l-1)))^2,
+//   (s / rho)^2 = sum (soft(v^l) - soft(v^(l-1)))^2
+// per work-group (FP64 total on the device), k_xchange gives
+// c = ||x^l - x^(l-1)|| / ||x^(l-1)|| (x^l is in d_x); stop with x^l when
+// c < tol, else rho changes by tau when one residual exceeds mu times the
+// other: the state is re-expressed for the new threshold and C_S^T (t - u')
+// emitted for the inverse transform, Psi^+ and x_hat0 are rebuilt.
+hipError_t gram(cip_plan_t p, hipStream_t st, double rho);
+
+int solve_wdct_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params* prm,
+                        float* d_x, hipStream_t st, cip_solve_info& out) {
+  const Layout& L = p->L;
+  const int S = p->S, N1 = p->N1, N2 = p->N2, lv = p->wt_levels;
+  const int iters = prm->max_iters, every = prm->every;
+  const double rho0 = p->rho;
+  double rho = rho0;
+  float* coef = p->at<float>(L.wcoef);
+  float* tmp = p->at<float>(L.wtmp);
+  float* r = p->at<float>(L.rimg);
+  float* v = p->at<float>(L.state);
+  const float* cs = p->at<const float>(L.wband);
+  const int groups = wavelet_state_groups(N1, N2);
+  float* rs = p->at<float>(L.sums);
+  float* xs = rs + 2 * (size_t)groups;
+  double* tot = reinterpret_cast<double*>(xs + 2 * XCHANGE_GROUPS);
+  float* xprev = p->at<float>(L.xbuf);
+  const size_t nx = (size_t)S * N1 * N2;
+  std::vector<float> hs(2 * XCHANGE_GROUPS + 4);
+  auto xhat0 = [&]() -> hipError_t {
+    // Alg. 1 step 2 with the current tables: x_hat0 = Psi^+ beta Lambda^H F y / (N1 N2)
+    hipError_t e = row_r2c<float>(d_y, p->at<cx<float>>(L.bufA), p->K, N1, N2,
+                                  p->at<const cx<float>>(L.twN2f), st);
+    if (e != hipSuccess) return e;
+    return col_op<float, OP_XHAT0>(p->at<const cx<float>>(L.bufA), p->at<void>(L.xh0), p->K, S,
+                                   N1, p->H2, p->at<const cx<float>>(L.twN1f),
+                                   p->at<const cx<float>>(L.Mm), 0, st);
+  };
+  auto body = [&]() -> int {
+    HIP_TRY(xhat0());
+    for (int l = 1;; ++l) {
+      if (l > 1)
+        HIP_TRY(row_r2c<float>(r, p->at<cx<float>>(L.bufA), S, N1, N2,
+                               p->at<const cx<float>>(L.twN2f), st));
+      HIP_TRY(admm_col(p, l == 1 ? 1 : 0, 0, st));
+      HIP_TRY(row_c2r(p->at<const cx<float>>(L.bufB), d_x, S, N1, N2, 1.0f,
+                      p->at<const cx<float>>(L.twN2f), st));
+      if (l == iters) {
+        out.iters = l;
+        break;
+      }
+      const bool check = l % every == 0;
+      const bool store = (l + 1) % every == 0;
+      const float kappa = (float)(p->lambda / rho);
+      HIP_TRY(wavelet_forward(d_x, coef, tmp, S, N1, N2, lv, st));
+      HIP_TRY(wavelet_state(coef, v, cs, S, N1, N2, kappa, l == 1 ? 1 : 0, st,
+                            check ? rs : nullptr));
+      if (check || store)
+        HIP_TRY(launch(k_xchange, XCHANGE_GROUPS, 256, 0, st, (const float*)d_x, xprev, xs, nx,
+                       check && l > 1 ? 1 : 0));
+      if (check) {
+        HIP_TRY(launch(k_sum_pairs, 1, 256, 0, st, (const float*)rs, (size_t)groups, tot));
+        HIP_TRY(hipMemcpyAsync(hs.data(), xs, hs.size() * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double d2 = 0.0, p2 = 0.0, tt[2];
+        for (int b = 0; b < XCHANGE_GROUPS; ++b) {
+          d2 += hs[2 * b];
+          p2 += hs[2 * b + 1];
+        }
+        std::memcpy(tt, hs.data() + 2 * XCHANGE_GROUPS, sizeof tt);
+        const double rr = std::sqrt(tt[0]), sres = rho * std::sqrt(tt[1]);
+        out.r_norm = rr;
+        out.s_norm = sres;
+        if (l > 1) {
+          out.rel_change = p2 > 0.0 ? std::sqrt(d2 / p2) : 0.0;
+          if (out.rel_change < prm->tol) {
+            out.iters = l;   // x^l is in d_x
+            break;
+          }
+        }
+        double next = rho;
+        if (rr > prm->mu * sres) next = prm->tau * rho;
+        else if (sres > prm->mu * rr) next = rho / prm->tau;
+        if (next != rho) {
+          HIP_TRY(wavelet_emit(coef, v, cs, S, N1, N2, kappa, (float)(rho / next), st));
+          HIP_TRY(gram(p, st, next));
+          HIP_TRY(xhat0());
+          rho = next;
+          ++out.rho_changes;
+        }
+      }
+      HIP_TRY(wavelet_inverse(coef, r, tmp, S, N1, N2, lv, st));
+    }
+    return CIP_OK;
+  };
+  int rc = body();
+  out.rho = rho;
+  if (rho != rho0) {   // leave the plan's tables at its own penalty
+    hipError_t e = gram(p, st, rho0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess && rc == CIP_OK)
+      rc = fail(CIP_EHIP, std::string("restoring the tables: ") + hipGetErrorString(e));
+  }
+  return rc;
 }
 
 // Frequency pass of the conv prior (2D form, or the 3D form with its band
@@ -1773,9 +1885,6 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   if (p->attached) return fail(CIP_EINVAL, "an adaptive solve rewrites the tables: not on an attached plan");
   const bool synthesis = p->kind == CIP_PRIOR_PATCH || p->kind == CIP_PRIOR_CONV2D ||
                          p->kind == CIP_PRIOR_CONV3D;
-  if (p->kind == CIP_PRIOR_WDCT3D)
-    return fail(CIP_EUNSUPPORTED,
-                "adaptive penalty: not for the wavelet prior");
   if (prm->adapt_sigma && !p->learn)
     return fail(CIP_EUNSUPPORTED, "adapt_sigma: the plan does not learn its dictionary");
   if (prm->max_iters < 1 || prm->every < 1 || !(prm->tau > 1.0) || !(prm->mu > 1.0) ||
@@ -1798,10 +1907,11 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
     if (info) *info = out;
     return rc;
   }
-  if (is_itv(p)) {
+  if (is_itv(p) || p->kind == CIP_PRIOR_WDCT3D) {
     cip_solve_info out{};
     out.rel_change = -1.0;
-    const int rc = solve_itv_adaptive(p, d_y, prm, d_x, st, out);
+    const int rc = is_itv(p) ? solve_itv_adaptive(p, d_y, prm, d_x, st, out)
+                             : solve_wdct_adaptive(p, d_y, prm, d_x, st, out);
     p->solved_once = true;
     if (info) *info = out;
     return rc;

@@ -64,13 +64,30 @@ hipError_t wavelet_inverse(float* coef, float* x, float* tmp, int planes, int N1
 }
 
 hipError_t wavelet_state(float* coef, float* v, const float* cs, int S, int N1, int N2,
-                         float kappa, int first, hipStream_t st) {
+                         float kappa, int first, hipStream_t st, float* rs) {
   const size_t plane = (size_t)N1 * N2;
   switch (S) {
-#define CIP_WS(SS) \
-  case SS: return launch(k_wdct_state<SS>, blocks(plane), 256, 0, st, coef, v, cs, plane, kappa, first);
+#define CIP_WS(SS)                                                                            \
+  case SS:                                                                                    \
+    return launch(k_wdct_state<SS>, blocks(plane), 256, 0, st, coef, v, cs, plane, kappa, first, \
+                  rs);
     CIP_WS(1) CIP_WS(2) CIP_WS(3) CIP_WS(4) CIP_WS(5) CIP_WS(6) CIP_WS(7) CIP_WS(8)
 #undef CIP_WS
+  }
+  return hipErrorInvalidValue;
+}
+
+int wavelet_state_groups(int N1, int N2) { return blocks((size_t)N1 * N2); }
+
+hipError_t wavelet_emit(float* coef, float* v, const float* cs, int S, int N1, int N2,
+                        float kappa, float sc, hipStream_t st) {
+  const size_t plane = (size_t)N1 * N2;
+  switch (S) {
+#define CIP_WE(SS)                                                                             \
+  case SS:                                                                                     \
+    return launch(k_wdct_emit<SS>, blocks(plane), 256, 0, st, coef, v, cs, plane, kappa, sc);
+    CIP_WE(1) CIP_WE(2) CIP_WE(3) CIP_WE(4) CIP_WE(5) CIP_WE(6) CIP_WE(7) CIP_WE(8)
+#undef CIP_WE
   }
   return hipErrorInvalidValue;
 }

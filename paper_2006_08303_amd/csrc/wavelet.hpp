@@ -195,25 +195,83 @@ k_idwt2(const float* __restrict__ ll, const float* __restrict__ coef, float* __r
 // Band DCT, soft threshold and dual update at every coefficient position
 // (S planes): c' = C_S c, v <- c' + clip(v) (v = 0 on the first
 // iteration), w = t - u = 2 soft(v) - v, coef <- C_S^T w (in place).
-// cs: C_S row-major (S x S); v: the state, [S][N1][N2].
+// cs: C_S row-major (S x S); v: the state, [S][N1][N2]. When rs is given
+// (adaptive penalty, Section IV-C) every work-group of 256 positions writes
+//   rs[2 b] = sum (c' - t)^2 = sum (clip(v_new) - clip(v_old))^2 and
+//   rs[2 b + 1] = sum (t - t_prev)^2 = sum (soft(v_new) - soft(v_old))^2
+// (v_old = 0 on the first iteration), summed in a fixed order.
 template <int S>
-__global__ void k_wdct_state(float* __restrict__ coef, float* __restrict__ v,
-                             const float* __restrict__ cs, size_t plane, float kappa, int first) {
+__global__ void __launch_bounds__(256)
+k_wdct_state(float* __restrict__ coef, float* __restrict__ v, const float* __restrict__ cs,
+             size_t plane, float kappa, int first, float* __restrict__ rs) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float r2 = 0.f, s2 = 0.f;
+  if (i < plane) {
+    float c[S], w[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) c[s] = coef[s * plane + i];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      float acc = 0.f;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc = fmaf(cs[k * S + s], c[s], acc);
+      const float vo = first ? 0.f : v[k * plane + i];
+      const float vn = acc + fminf(fmaxf(vo, -kappa), kappa);
+      v[k * plane + i] = vn;
+      const float t = vn > kappa ? vn - kappa : (vn < -kappa ? vn + kappa : 0.f);
+      w[k] = 2.f * t - vn;
+      if (rs) {
+        const float to = vo > kappa ? vo - kappa : (vo < -kappa ? vo + kappa : 0.f);
+        const float d = fminf(fmaxf(vn, -kappa), kappa) - fminf(fmaxf(vo, -kappa), kappa);
+        r2 += d * d;
+        s2 += (t - to) * (t - to);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc = fmaf(cs[k * S + s], w[k], acc);
+      coef[s * plane + i] = acc;
+    }
+  }
+  if (rs) {
+    __shared__ float red[2][4];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      r2 += __shfl_xor(r2, off, 64);
+      s2 += __shfl_xor(s2, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = r2;
+      red[1][threadIdx.x >> 6] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      rs[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+      rs[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+  }
+}
+
+// After a penalty change (adaptive solve): with t = soft(v, kappa),
+// u = clip(v, kappa) of the updated state, v <- t + sc u (sc = rho / rho',
+// the v-form for kappa' = lambda / rho') and coef <- C_S^T (t - sc u), the
+// input of the inverse transform for the next x-update.
+template <int S>
+__global__ void __launch_bounds__(256)
+k_wdct_emit(float* __restrict__ coef, float* __restrict__ v, const float* __restrict__ cs,
+            size_t plane, float kappa, float sc) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= plane) return;
-  float c[S], w[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) c[s] = coef[s * plane + i];
+  float w[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) {
-    float acc = 0.f;
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc = fmaf(cs[k * S + s], c[s], acc);
-    const float vo = first ? 0.f : v[k * plane + i];
-    const float vn = acc + fminf(fmaxf(vo, -kappa), kappa);
-    v[k * plane + i] = vn;
-    const float t = vn > kappa ? vn - kappa : (vn < -kappa ? vn + kappa : 0.f);
-    w[k] = 2.f * t - vn;
+    const float vo = v[k * plane + i];
+    const float t = vo > kappa ? vo - kappa : (vo < -kappa ? vo + kappa : 0.f);
+    const float u = sc * fminf(fmaxf(vo, -kappa), kappa);
+    v[k * plane + i] = t + u;
+    w[k] = t - u;
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {

@@ -12,8 +12,15 @@ hipError_t wavelet_forward(const float* x, float* coef, float* tmp, int planes, 
 // Inverse: coef (destroyed) -> x; tmp is staging.
 hipError_t wavelet_inverse(float* coef, float* x, float* tmp, int planes, int N1, int N2,
                            int levels, hipStream_t st);
-// Band DCT, soft threshold, dual update and back (see wavelet.hpp), S <= 8.
+// Band DCT, soft threshold, dual update and back (see wavelet.hpp), S <= 8;
+// rs: when given, two residual partial sums per work-group
+// (wavelet_state_groups of them).
 hipError_t wavelet_state(float* coef, float* v, const float* cs, int S, int N1, int N2,
-                         float kappa, int first, hipStream_t st);
+                         float kappa, int first, hipStream_t st, float* rs = nullptr);
+int wavelet_state_groups(int N1, int N2);
+// After a penalty change: v re-expressed for the new threshold (u scaled by
+// sc) and coef = C_S^T (t - u') for the inverse transform.
+hipError_t wavelet_emit(float* coef, float* v, const float* cs, int S, int N1, int N2,
+                        float kappa, float sc, hipStream_t st);
 
 }  // namespace cip

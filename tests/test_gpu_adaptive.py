@@ -104,7 +104,7 @@ def test_itv_adaptive_matches_oracle(prior, N, K, S, rho0, every, tol, maxit, in
 def test_itv_adaptive_without_changes_equals_plain_solve_and_restores_tables():
     """No change and no stop: the same kernels as cip_solve (the norm pass
     only reads the state), bit for bit; after a solve with changes the plan
-    solves as before. The wavelet prior refuses an adaptive solve."""
+    solves as before."""
     x, psf, y = _problem(64, 3, 3, 9)
     for prior in ("itv2d", "itv3d"):
         plan = cip.Plan(_t(psf), prior, 0.05, 1e-3, 1.0, adaptive=True, tv_inner=7)
@@ -118,10 +118,49 @@ def test_itv_adaptive_without_changes_equals_plain_solve_and_restores_tables():
         c = plan.solve(_t(y), 12)
         torch.cuda.synchronize()
         assert torch.equal(c, b), prior
-    wd = cip.Plan(_t(psf), "wdct3d", 0.1, 1e-2, 1.0, adaptive=True)
-    with pytest.raises(cip.CipError) as e:
-        wd.solve_adaptive(_t(y), 10)
-    assert e.value.code == -2
+
+
+# Wavelet (Symmlet-8) (x) DCT prior; oracle traces in the comments (the
+# first and third keep their stop and change count when tol moves by 10%)
+@pytest.mark.parametrize("N,K,S,lam,rho0,every,tol,maxit,levels", [
+    (64, 3, 3, 1e-2, 1e-3, 2, 1e-4, 200, 3),      # 9 changes, stops at 28
+    (64, 3, 3, 1e-2, 10.0, 5, 1e-3, 200, 3),      # 3 changes, stops at 30
+    (64, 3, 3, 1e-3, 1e-4, 3, 1e-4, 150, 4),      # 9 changes, stops at 30
+    (128, 2, 3, 1e-2, 1.0, 2, 1e-4, 150, 2),      # 1 change, stops at 62
+])
+def test_wavelet_adaptive_matches_oracle(N, K, S, lam, rho0, every, tol, maxit, levels):
+    print(f"adaptive wdct3d N={N} K={K} S={S} rho0={rho0} every={every} levels={levels}",
+          flush=True)
+    x, psf, y = _problem(N, K, S, 9)
+    ref, rinfo = admm.AnalysisADMM(psf, "wdct3d", lam, rho0, 1.0, tier="freq",
+                                   levels=levels).run_adaptive(y, maxit, every=every, tol=tol)
+    plan = cip.Plan(_t(psf), "wdct3d", rho0, lam, 1.0, adaptive=True, wt_levels=levels)
+    got, ginfo = plan.solve_adaptive(_t(y), maxit, every=every, tol=tol)
+    got = _np(got)
+    changes = sum(1 for a, b in zip(rinfo["rhos"], rinfo["rhos"][1:]) if a != b)
+    err = admm.rel_l2(got, ref)
+    print(f"  oracle: iters {rinfo['iters']} rho {rinfo['rho']:.3g} changes {changes}; "
+          f"gpu: iters {ginfo['iters']} rho {ginfo['rho']:.3g} changes {ginfo['rho_changes']}; "
+          f"rel_l2 {err:.3e}", flush=True)
+    assert ginfo["iters"] == rinfo["iters"]
+    assert ginfo["rho"] == pytest.approx(rinfo["rho"], rel=1e-12)
+    assert ginfo["rho_changes"] == changes
+    parity.check(got, ref, 1e-4)
+
+
+def test_wavelet_adaptive_without_changes_equals_plain_solve_and_restores_tables():
+    x, psf, y = _problem(64, 3, 3, 9)
+    plan = cip.Plan(_t(psf), "wdct3d", 0.05, 1e-2, 1.0, adaptive=True)
+    a, info = plan.solve_adaptive(_t(y), 15, every=1, mu=1e30, tol=0.0)
+    b = plan.solve(_t(y), 15)
+    torch.cuda.synchronize()
+    assert info["rho_changes"] == 0 and info["iters"] == 15
+    assert torch.equal(a, b)
+    _, info = plan.solve_adaptive(_t(y), 30, every=1, tol=0.0, mu=1.5)
+    assert info["rho_changes"] > 0
+    c = plan.solve(_t(y), 15)
+    torch.cuda.synchronize()
+    assert torch.equal(c, b)
 
 
 def test_adaptive_leaves_tables_at_plan_rho():
