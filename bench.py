@@ -236,7 +236,6 @@ def run_other_priors(args, dev, psf_t, y_t):
     Dn = synth.random_unit_atoms(rng, 64 * S, 256)
     D = torch.tensor(Dn, dtype=torch.float32, device=dev)
     D1 = torch.tensor(Dn / np.linalg.norm(Dn), dtype=torch.float32, device=dev)   # ||D||_F = 1
-    J = (N // 4) ** 2
     f2 = torch.tensor(synth.random_unit_filters(synth.rng_for(3, 5), 32, 11), dtype=torch.float32,
                       device=dev)
     f3 = torch.tensor(synth.random_unit_filters_3d(synth.rng_for(3, 6), 32, S, 11),
@@ -246,9 +245,9 @@ def run_other_priors(args, dev, psf_t, y_t):
         ("wavelet (x) DCT (Symmlet-8, 3 levels)", dict(prior="wdct3d", rho=0.1, lam=1e-2,
                                                      beta=1.0), None),
         ("patch (A = 256)", dict(prior="patch", rho=1e-4, lam=5e-6, beta=500.0, dictionary=D), 2),
-        ("patch + online dictionary update (A = 256, sigma = 1000 J)",
-         dict(prior="patch", rho=1e-4, lam=5e-5, beta=500.0, dictionary=D1, dict_update=True,
-              sigma=1000.0 * J), 2),
+        ("patch + online dictionary update (A = 256, sigma = 1)",
+         dict(prior="patch", rho=1e-4, lam=5e-5, beta=500.0, dictionary=D1, dict_update=True),
+         2),
         ("conv2d (M = 32, L = 11)", dict(prior="conv2d", rho=1e-4, lam=1.875e-6, beta=8.0,
                                          filters=f2), 2),
         ("conv2d + gradient term (mu = 0.01)", dict(prior="conv2d", rho=1e-4, lam=1.875e-6,
