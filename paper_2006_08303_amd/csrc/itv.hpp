@@ -288,32 +288,55 @@ k_itv_finish(const float* __restrict__ f, const float* __restrict__ p0,
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   lds_load_table(tw, twg, N2);
-  const int ra = row0 + 2 * g;
+  const int ra = row0 + 2 * g, rup = ra == 0 ? N1 - 1 : ra - 1;
   const size_t pn = (size_t)N1 * N2, pl = (size_t)s * pn;
   const bool has_next = s < S - 1, has_prev = s > 0;
   cx<float> v[PPT];
+  // QC points of both rows at a time: every load of a chunk is issued before
+  // its arithmetic (p0 of the row above the pair once; the second row's
+  // "above" is the first row's own p0)
+  constexpr int QC = 4;
+  static_assert(PPT % QC == 0, "points per thread must be a multiple of the chunk");
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    const int n = t + T * q, nl = n == 0 ? N2 - 1 : n - 1;
-    float o[2];
+  for (int q0 = 0; q0 < PPT; q0 += QC) {
+    float fv[QC][2], a0[QC][3], a1[QC][2], a1l[QC][2], b2[QC][2], b2p[QC][2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int n1 = ra + r, nu = n1 == 0 ? N1 - 1 : n1 - 1;
-      const size_t i = pl + (size_t)n1 * N2 + n;
-      float dv = (p0[i] - p0[pl + (size_t)nu * N2 + n]) +
-                 (p1[i] - p1[pl + (size_t)n1 * N2 + nl]);
-      if constexpr (BAND) {
-        const float a2 = p2[i], b2 = p2[has_prev ? i - pn : i];
-        dv += has_next ? a2 : 0.f;
-        dv -= has_prev ? b2 : 0.f;
+    for (int k = 0; k < QC; ++k) {
+      const int n = t + T * (q0 + k), nl = n == 0 ? N2 - 1 : n - 1;
+      a0[k][0] = p0[pl + (size_t)rup * N2 + n];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const size_t i = pl + (size_t)(ra + r) * N2 + n;
+        fv[k][r] = f[i];
+        a0[k][r + 1] = p0[i];
+        a1[k][r] = p1[i];
+        a1l[k][r] = p1[pl + (size_t)(ra + r) * N2 + nl];
+        if constexpr (BAND) {
+          b2[k][r] = p2[i];
+          b2p[k][r] = p2[has_prev ? i - pn : i];
+        }
       }
-      const float fi = f[i];
-      const float ti = fi - mu * dv;
-      const float ui = c * (fi - ti);
-      u[i] = ui;
-      o[r] = ti - ui;
     }
-    v[q] = cx<float>{o[0], o[1]};
+#pragma unroll
+    for (int k = 0; k < QC; ++k) {
+      const int n = t + T * (q0 + k);
+      float o[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const size_t i = pl + (size_t)(ra + r) * N2 + n;
+        float dv = (a0[k][r + 1] - a0[k][r]) + (a1[k][r] - a1l[k][r]);
+        if constexpr (BAND) {
+          dv += has_next ? b2[k][r] : 0.f;
+          dv -= has_prev ? b2p[k][r] : 0.f;
+        }
+        const float fi = fv[k][r];
+        const float ti = fi - mu * dv;
+        const float ui = c * (fi - ti);
+        u[i] = ui;
+        o[r] = ti - ui;
+      }
+      v[q0 + k] = cx<float>{o[0], o[1]};
+    }
   }
   __syncthreads();   // twiddle table ready
   fft_group<N2, PPT, +1>(v, cb, t, tw);
