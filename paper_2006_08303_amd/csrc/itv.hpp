@@ -41,6 +41,16 @@ k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float
   const int s = b / tiles, row0 = (b % tiles) * RT;
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
+  const size_t oa = ((size_t)s * N1 + row0 + 2 * g) * N2, ob = oa + N2;
+  // the dual of both rows, loaded before the transform so that the loads
+  // overlap it
+  float ua[PPT], ub[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = t + T * q;
+    ua[q] = first ? 0.f : u[oa + n];
+    ub[q] = first ? 0.f : u[ob + n];
+  }
   lds_load_table(tw, twg, N2);
   tile_to_staging(Yin + rt_tile_base(s, row0, N1, H2), stg, H2 * RT);
   __syncthreads();
@@ -48,12 +58,11 @@ k_itv_prep(const cx<float>* __restrict__ Yin, const float* __restrict__ u, float
   staging_to_pair<N2, PPT>(v, stg, g, t);
   __syncthreads();
   fft_group<N2, PPT, -1>(v, cb, t, tw);
-  const size_t oa = ((size_t)s * N1 + row0 + 2 * g) * N2, ob = oa + N2;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int n = t + T * q;
-    f[oa + n] = v[q].x + (first ? 0.f : u[oa + n]);
-    f[ob + n] = v[q].y + (first ? 0.f : u[ob + n]);
+    f[oa + n] = v[q].x + ua[q];
+    f[ob + n] = v[q].y + ub[q];
     if (xo) {
       xo[oa + n] = v[q].x;
       xo[ob + n] = v[q].y;
