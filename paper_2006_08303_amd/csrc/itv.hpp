@@ -103,22 +103,29 @@ k_itv_chambolle(const float* __restrict__ f, const float* __restrict__ pi0,
   const int r0 = (rem / tx) * TS - KB, c0 = (rem % tx) * TS - KB;
   const size_t pl = (size_t)s * N1 * N2;
   float rp0[NSLOT], rp1[NSLOT], rf[NSLOT], rq[NSLOT];
-  // which cells take part in the q and p updates
-  unsigned qm = 0, pm = 0;
+  // every slot's loads first (all in flight together), then the LDS copies
 #pragma unroll
   for (int k = 0; k < NSLOT; ++k) {
     const int e = threadIdx.x + 256 * k;
-    const int a = e / W, c = e % W;
     rp0[k] = rp1[k] = rf[k] = rq[k] = 0.f;
     if (e < R) {
       // r0 + a lies in [-KB, N1 + KB) and KB < N1 (likewise for columns)
-      int gr = r0 + a, gc = c0 + c;
+      int gr = r0 + e / W, gc = c0 + e % W;
       gr += gr < 0 ? N1 : (gr >= N1 ? -N1 : 0);
       gc += gc < 0 ? N2 : (gc >= N2 ? -N2 : 0);
       const size_t i = pl + (size_t)gr * N2 + gc;
       rp0[k] = pi0[i];
       rp1[k] = pi1[i];
       rf[k] = f[i];
+    }
+  }
+  // which cells take part in the q and p updates
+  unsigned qm = 0, pm = 0;
+#pragma unroll
+  for (int k = 0; k < NSLOT; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    const int a = e / W, c = e % W;
+    if (e < R) {
       P0[e] = rp0[k];
       P1[e] = rp1[k];
       if (a >= 1 && c >= 1) {
