@@ -139,23 +139,35 @@ k_conv_freq(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat,
     xhat[(size_t)s * F + f] = acc;
   }
   if (!do_z) return;
+  // the loads of all filter slots are unconditional (slots m >= M read slot
+  // M - 1, finite values, and are multiplied by 0), so that they are issued
+  // together rather than one per branch
   cx<float> t[CONV_MMAX];
 #pragma unroll
-  for (int m = 0; m < CONV_MMAX; ++m) t[m] = m < M ? th[(size_t)m * F + f] : cx<float>{0.f, 0.f};
+  for (int m = 0; m < CONV_MMAX; ++m) {
+    const cx<float> tm = th[(size_t)(m < M ? m : M - 1) * F + f];
+    const float w = m < M ? 1.f : 0.f;
+    t[m] = cx<float>{w * tm.x, w * tm.y};
+  }
   const float gm = gam[f], et = eta[f];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     cx<float> g[CONV_MMAX];
     cx<float> ag = {0.f, 0.f};   // a^H g = sum_m theta_m g_m
+    if (zero_g) {
 #pragma unroll
-    for (int m = 0; m < CONV_MMAX; ++m) {
-      g[m] = cx<float>{0.f, 0.f};
-      if (m < M && !zero_g) {
-        const cx<float> gg = gv[((size_t)m * S + s) * F + f];
-        g[m] = cx<float>{et * gg.x, et * gg.y};
+      for (int m = 0; m < CONV_MMAX; ++m) g[m] = cx<float>{0.f, 0.f};
+    } else {
+#pragma unroll
+      for (int m = 0; m < CONV_MMAX; ++m) {
+        const cx<float> gg = gv[((size_t)(m < M ? m : M - 1) * S + s) * F + f];
+        const float em = m < M ? et : 0.f;
+        g[m] = cx<float>{em * gg.x, em * gg.y};
       }
-      if (m < M) ag = ag + cmul(t[m], g[m]);
     }
+#pragma unroll
+    for (int m = 0; m < CONV_MMAX; ++m)
+      if (m < M) ag = ag + cmul(t[m], g[m]);
     const cx<float> r = {(xs[s].x - ag.x) * gm, (xs[s].y - ag.y) * gm};
     cx<float> dn = {0.f, 0.f};
 #pragma unroll

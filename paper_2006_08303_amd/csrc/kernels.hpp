@@ -71,10 +71,28 @@ template <typename Re> __device__ __forceinline__ void stc(cx<Re>* b, int i, cx<
 __device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
 constexpr int pad8_len(int n) { return n + (n >> 3) + 1; }
 
+// Global -> LDS copies of the whole work-group with U loads of every thread
+// in flight before their LDS stores (a plain strided loop waits for each
+// load in turn): idx(i) gives the source and staging index of element i.
+template <int U, typename T, typename Src, typename Dst>
+__device__ __forceinline__ void batched_to_lds(int n, Src src, Dst dst) {
+  const int step = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + (U - 1) * step < n; i += U * step) {
+    T r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = src(i + u * step);
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst(i + u * step, r[u]);
+  }
+  for (; i < n; i += step) dst(i, src(i));
+}
+
 // Copy n complex values from global memory into LDS (whole work-group).
 template <typename Re>
 __device__ __forceinline__ void lds_load_table(cx<Re>* dst, const cx<Re>* __restrict__ src, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  batched_to_lds<4, cx<Re>>(
+      n, [&](int i) { return src[i]; }, [&](int i, const cx<Re>& v) { dst[i] = v; });
 }
 
 // Floats of LDS used by a row-pass work-group of NG row pairs (staging holds
@@ -89,7 +107,8 @@ template <int N2, typename Re> constexpr int row_work_floats(int ng, bool staged
 // array (complex, padded with pad8).
 __device__ __forceinline__ void tile_to_staging(const cx<float>* __restrict__ src, cx<float>* stg,
                                                 int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) stg[pad8(i)] = src[i];
+  batched_to_lds<8, cx<float>>(
+      n, [&](int i) { return src[i]; }, [&](int i, const cx<float>& v) { stg[pad8(i)] = v; });
 }
 __device__ __forceinline__ void staging_to_tile(cx<float>* __restrict__ dst, const cx<float>* stg,
                                                 int n) {
@@ -101,8 +120,9 @@ __device__ __forceinline__ void staging_to_tile(cx<float>* __restrict__ dst, con
 template <int SW>
 __device__ __forceinline__ void subtile_to_staging(const cx<float>* __restrict__ tile, cx<float>* stg,
                                                    int h2, int r0) {
-  for (int i = threadIdx.x; i < h2 * SW; i += blockDim.x)
-    stg[pad8(i)] = tile[(i / SW) * RT + r0 + i % SW];
+  batched_to_lds<8, cx<float>>(
+      h2 * SW, [&](int i) { return tile[(i / SW) * RT + r0 + i % SW]; },
+      [&](int i, const cx<float>& v) { stg[pad8(i)] = v; });
 }
 template <int SW>
 __device__ __forceinline__ void staging_to_subtile(cx<float>* __restrict__ tile, const cx<float>* stg,
