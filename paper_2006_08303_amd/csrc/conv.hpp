@@ -258,17 +258,31 @@ k_conv_freq3(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat, cx<float>
     ag[k] = cx<float>{0.f, 0.f};
     dn[k] = cx<float>{0.f, 0.f};
   }
+  // the codes are visited in chunks of CH filters whose loads are issued
+  // together (slots past M read filter M - 1 and are multiplied by 0)
+  constexpr int CH = S <= 2 ? 8 : (S <= 4 ? 4 : 2);
   if (!zero_g) {
-    for (int m = 0; m < M; ++m) {
-      cx<float> g[S];
+    for (int m0 = 0; m0 < M; m0 += CH) {
+      cx<float> g[CH][S], t[CH][S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) g[s] = gv[((size_t)m * S + s) * F + f];
+      for (int c = 0; c < CH; ++c) {
+        const size_t m = (size_t)(m0 + c < M ? m0 + c : M - 1);
 #pragma unroll
-      for (int k = 0; k < S; ++k) {
-        cx<float> G = {0.f, 0.f};
+        for (int s = 0; s < S; ++s) {
+          g[c][s] = gv[(m * S + s) * F + f];
+          t[c][s] = th[(m * S + s) * F + f];
+        }
+      }
 #pragma unroll
-        for (int s = 0; s < S; ++s) G = G + cmul(g[s], bw[k * S + s]);
-        ag[k] = ag[k] + cmul(th[((size_t)m * S + k) * F + f], G);
+      for (int c = 0; c < CH; ++c) {
+        const float w = m0 + c < M ? 1.f : 0.f;
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          cx<float> G = {0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < S; ++s) G = G + cmul(g[c][s], bw[k * S + s]);
+          ag[k] = ag[k] + cmul(cx<float>{w * t[c][k].x, w * t[c][k].y}, G);
+        }
       }
     }
   }
@@ -278,26 +292,40 @@ k_conv_freq3(cx<float>* __restrict__ gv, cx<float>* __restrict__ dhat, cx<float>
     r[k] = cx<float>{(X[k].x - ag[k].x) * gm, (X[k].y - ag[k].y) * gm};
   }
   const float invS = 1.f / (float)S;
-  for (int m = 0; m < M; ++m) {
-    cx<float> g[S], V[S];
+  for (int m0 = 0; m0 < M; m0 += CH) {
+    cx<float> g[CH][S], t[CH][S];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-      g[s] = zero_g ? cx<float>{0.f, 0.f} : gv[((size_t)m * S + s) * F + f];
+    for (int c = 0; c < CH; ++c) {
+      const size_t m = (size_t)(m0 + c < M ? m0 + c : M - 1);
 #pragma unroll
-    for (int k = 0; k < S; ++k) {
-      cx<float> G = {0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < S; ++s) G = G + cmul(g[s], bw[k * S + s]);
-      const cx<float> t = th[((size_t)m * S + k) * F + f];
-      V[k] = G + cmulc(r[k], t);   // G + conj(theta) r
-      dn[k] = dn[k] + cmul(t, V[k]);
+      for (int s = 0; s < S; ++s) {
+        g[c][s] = zero_g ? cx<float>{0.f, 0.f} : gv[(m * S + s) * F + f];
+        t[c][s] = th[(m * S + s) * F + f];
+      }
     }
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      cx<float> acc = {0.f, 0.f};
+    for (int c = 0; c < CH; ++c) {
+      const int m = m0 + c;
+      const float w = m < M ? 1.f : 0.f;
+      cx<float> V[S];
 #pragma unroll
-      for (int k = 0; k < S; ++k) acc = acc + cmulc(V[k], bw[k * S + s]);
-      gv[((size_t)m * S + s) * F + f] = cx<float>{acc.x * invS, acc.y * invS};
+      for (int k = 0; k < S; ++k) {
+        cx<float> G = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) G = G + cmul(g[c][s], bw[k * S + s]);
+        const cx<float> tk = {w * t[c][k].x, w * t[c][k].y};
+        V[k] = G + cmulc(r[k], tk);   // G + conj(theta) r
+        dn[k] = dn[k] + cmul(tk, V[k]);
+      }
+      if (m < M) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          cx<float> acc = {0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < S; ++k) acc = acc + cmulc(V[k], bw[k * S + s]);
+          gv[((size_t)m * S + s) * F + f] = cx<float>{acc.x * invS, acc.y * invS};
+        }
+      }
     }
   }
 #pragma unroll
