@@ -376,25 +376,37 @@ __global__ void k_patch_assemble(const float* __restrict__ tb, float* __restrict
   const int RA = G.RR * G.RC;
   const int tr0 = R / TH, lr0 = R - tr0 * TH;
   const int tc0 = C / TW, lc0 = C - tc0 * TW;
-  float4 sum = {0.f, 0.f, 0.f, 0.f};
+  // the four candidate tiles are loaded unconditionally (a tile that does
+  // not cover the pixel is read at its own row / column 0 and weighted 0),
+  // so that the loads are in flight together; the sum keeps its order
+  float4 q[2][2];
+  float wq[2][2];
 #pragma unroll
   for (int dr = 0; dr < 2; ++dr) {
-    if (dr == 1 && lr0 >= PATCH_Q - PATCH_ST) break;
+    const bool rin = dr == 0 || lr0 < PATCH_Q - PATCH_ST;
     const int tr = dr ? (tr0 + ntr - 1) % ntr : tr0;
-    const int lr = dr ? lr0 + TH : lr0;
+    const int lr = dr ? (rin ? lr0 + TH : 0) : lr0;
 #pragma unroll
     for (int dc = 0; dc < 2; ++dc) {
-      if (dc == 1 && lc0 >= PATCH_Q - PATCH_ST) break;
+      const bool cin = dc == 0 || lc0 < PATCH_Q - PATCH_ST;
       const int tc = dc ? (tc0 + G.ntc - 1) % G.ntc : tc0;
-      const int lc = dc ? lc0 + TW : lc0;
+      const int lc = dc ? (cin ? lc0 + TW : 0) : lc0;
       const size_t t = (size_t)tr * G.ntc + tc;
-      const float4 q = *reinterpret_cast<const float4*>(tb + (t * S + s) * RA + lr * G.RC + lc);
-      sum.x += q.x;
-      sum.y += q.y;
-      sum.z += q.z;
-      sum.w += q.w;
+      q[dr][dc] = *reinterpret_cast<const float4*>(tb + (t * S + s) * RA + lr * G.RC + lc);
+      wq[dr][dc] = rin && cin ? 1.f : 0.f;
     }
   }
+  float4 sum = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+    for (int dc = 0; dc < 2; ++dc) {
+      if (wq[dr][dc] == 0.f) continue;
+      sum.x += q[dr][dc].x;
+      sum.y += q[dr][dc].y;
+      sum.z += q[dr][dc].z;
+      sum.w += q[dr][dc].w;
+    }
   *reinterpret_cast<float4*>(r + idx) = sum;
 }
 

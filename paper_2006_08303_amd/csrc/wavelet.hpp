@@ -207,15 +207,20 @@ k_wdct_state(float* __restrict__ coef, float* __restrict__ v, const float* __res
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   float r2 = 0.f, s2 = 0.f;
   if (i < plane) {
-    float c[S], w[S];
+    float c[S], w[S], vp[S];
+    // every load before the first store of the state (the planes of v are
+    // not known to be distinct to the compiler)
 #pragma unroll
-    for (int s = 0; s < S; ++s) c[s] = coef[s * plane + i];
+    for (int s = 0; s < S; ++s) {
+      c[s] = coef[s * plane + i];
+      vp[s] = first ? 0.f : v[s * plane + i];
+    }
 #pragma unroll
     for (int k = 0; k < S; ++k) {
       float acc = 0.f;
 #pragma unroll
       for (int s = 0; s < S; ++s) acc = fmaf(cs[k * S + s], c[s], acc);
-      const float vo = first ? 0.f : v[k * plane + i];
+      const float vo = vp[k];
       const float vn = acc + fminf(fmaxf(vo, -kappa), kappa);
       v[k * plane + i] = vn;
       const float t = vn > kappa ? vn - kappa : (vn < -kappa ? vn + kappa : 0.f);
@@ -264,10 +269,12 @@ k_wdct_emit(float* __restrict__ coef, float* __restrict__ v, const float* __rest
             size_t plane, float kappa, float sc) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= plane) return;
-  float w[S];
+  float w[S], vp[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) vp[k] = v[k * plane + i];
 #pragma unroll
   for (int k = 0; k < S; ++k) {
-    const float vo = v[k * plane + i];
+    const float vo = vp[k];
     const float t = vo > kappa ? vo - kappa : (vo < -kappa ? vo + kappa : 0.f);
     const float u = sc * fminf(fmaxf(vo, -kappa), kappa);
     v[k * plane + i] = t + u;
