@@ -172,19 +172,43 @@ k_patch_z(const float* __restrict__ x, float* __restrict__ v, float* __restrict_
   if constexpr (MODE == PZ_SYNTH) {
     // codes from zf, as bf16 rows WB[patch][atom] (lanes over patches: the
     // zf reads are contiguous)
-    for (int it = threadIdx.x; it < PATCH_NP * NA / 4; it += 256) {
+    constexpr int NIT = PATCH_NP * NA / 4 / 256;
+    float zl[NIT][4];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int it = threadIdx.x + 256 * k;
       const int jl = it & (PATCH_NP - 1), a = 4 * (it >> 6);
       const float* zp = zf + (size_t)a * J + j0 + jl;
+      zl[k][0] = zp[0];
+      zl[k][1] = zp[J];
+      zl[k][2] = zp[2 * J];
+      zl[k][3] = zp[3 * J];
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int it = threadIdx.x + 256 * k;
+      const int jl = it & (PATCH_NP - 1), a = 4 * (it >> 6);
       *reinterpret_cast<uint2*>(WB + jl * WS + a) =
-          pack_bf16x4(zp[0], zp[J], zp[2 * J], zp[3 * J]);
+          pack_bf16x4(zl[k][0], zl[k][1], zl[k][2], zl[k][3]);
     }
     __syncthreads();
   } else {
-    // 0. w = t - u = 2 soft(v) - v, as bf16 rows WB[patch][atom]
-    for (int it = threadIdx.x; it < PATCH_NP * NA / 4; it += 256) {
+    // 0. w = t - u = 2 soft(v) - v, as bf16 rows WB[patch][atom]; every
+    // thread's state loads are issued before the first conversion
+    constexpr int NIT = PATCH_NP * NA / 4 / 256;
+    float4 vl[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int it = threadIdx.x + 256 * k;
       const int jl = it / (NA / 4), a = 4 * (it % (NA / 4));
-      float4 vv = first ? float4{0.f, 0.f, 0.f, 0.f}
-                        : *reinterpret_cast<const float4*>(vt + jl * NA + a);
+      vl[k] = first ? float4{0.f, 0.f, 0.f, 0.f}
+                    : *reinterpret_cast<const float4*>(vt + jl * NA + a);
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int it = threadIdx.x + 256 * k;
+      const int jl = it / (NA / 4), a = 4 * (it % (NA / 4));
+      const float4 vv = vl[k];
       *reinterpret_cast<uint2*>(WB + jl * WS + a) =
           pack_bf16x4(2.f * soft_f(vv.x, kappa) - vv.x, 2.f * soft_f(vv.y, kappa) - vv.y,
                       2.f * soft_f(vv.z, kappa) - vv.z, 2.f * soft_f(vv.w, kappa) - vv.w);
