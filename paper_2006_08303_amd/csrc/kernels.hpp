@@ -626,17 +626,14 @@ __device__ __forceinline__ void tv_stage_rows(const cx<float>* __restrict__ Yin,
   using G = TvGeo<N2, PPT_, NP>;
   constexpr int H2 = G::H2, NR = G::NR, SW = G::SW;
   const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
-  for (int i = threadIdx.x; i < H2 * SW; i += blockDim.x) {
-    const int k2 = i / SW, r = i % SW;
-    stg[pad8(k2 * NR + r + 1)] = tile[k2 * RT + r0 + r];
-  }
+  batched_to_lds<8, cx<float>>(
+      H2 * SW, [&](int i) { return tile[(i / SW) * RT + r0 + i % SW]; },
+      [&](int i, const cx<float>& v) { stg[pad8((i / SW) * NR + i % SW + 1)] = v; });
   const int rb = row0 + r0;
   const int lo = (rb - 1 + N1) % N1, hi = (rb + SW) % N1;
-  for (int i = threadIdx.x; i < 2 * H2; i += blockDim.x) {
-    const int k2 = i % H2, h = i / H2;
-    const int r = h ? NR - 1 : 0;
-    stg[pad8(k2 * NR + r)] = Yin[rt_idx(s, h ? hi : lo, k2, N1, H2)];
-  }
+  batched_to_lds<4, cx<float>>(
+      2 * H2, [&](int i) { return Yin[rt_idx(s, i / H2 ? hi : lo, i % H2, N1, H2)]; },
+      [&](int i, const cx<float>& v) { stg[pad8((i % H2) * NR + (i / H2 ? NR - 1 : 0))] = v; });
 }
 
 // Load the vertical / horizontal state this thread updates in tv_spatial
