@@ -496,10 +496,27 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   const int ra = row0 + r0 + 2 * g;
   cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
   cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
-  lds_load_table(tw, twg, N2);
-  if (mode != ROW_FINAL) lds_load_table(ew, ewg, N2);
-  subtile_to_staging<SW>(Yin + rt_tile_base(s, row0, N1, H2), stg, H2, r0);
-  // prefetch the state of rows a, b (latency overlaps the two FFTs below)
+  // Every global load of the prologue is issued before the first LDS store:
+  // the twiddle and DCT tables, the rows of the tile, and the state of rows
+  // a, b (its latency also overlaps the two transforms below).
+  constexpr int NT = NP * T;                          // threads
+  constexpr int NTAB = (N2 + NT - 1) / NT;            // table values per thread
+  constexpr int NSTG = (H2 * SW + NT - 1) / NT;       // tile values per thread
+  const cx<float>* tile = Yin + rt_tile_base(s, row0, N1, H2);
+  cx<float> rtw[NTAB], rew[NTAB], rst[NSTG];
+#pragma unroll
+  for (int k = 0; k < NTAB; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < N2) {
+      rtw[k] = twg[i];
+      if (mode != ROW_FINAL) rew[k] = ewg[i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NSTG; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < H2 * SW) rst[k] = tile[(i / SW) * RT + r0 + i % SW];
+  }
   float* va = vstate + ((size_t)s * N1 + ra) * N2;
   float* vb = va + N2;
   float oa[PPT], ob[PPT];
@@ -512,6 +529,19 @@ k_admm_row_dct(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   } else {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) oa[q] = ob[q] = 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < NTAB; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < N2) {
+      tw[i] = rtw[k];
+      if (mode != ROW_FINAL) ew[i] = rew[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NSTG; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < H2 * SW) stg[pad8(i)] = rst[k];
   }
   __syncthreads();
   cx<float> v[PPT];
