@@ -504,18 +504,18 @@ ItvState itv_state(cip_plan_t p) {
 // Closing row pass of iteration l: t = f - mu div p, u = c (f - t), spectrum
 // of t - u to bufA. Pass l leaves the dual in buffer (l nl) mod 2.
 hipError_t itv_finish(cip_plan_t p, int l, float mu, float c, hipStream_t st) {
-  const ItvState S = itv_state(p);
-  const int fin = (int)(((long long)l * S.nl) & 1);
+  const ItvState sv = itv_state(p);
+  const int fin = (int)(((long long)l * sv.nl) & 1);
   const int grid = p->S * (p->N1 / RT);
   const bool band = p->kind == CIP_PRIOR_ITV3D;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    return band ? launch(k_itv_finish<NN, true>, grid, PAIRS * T, lds, st, S.f, S.pd[fin][0],
-                         S.pd[fin][1], S.pd[fin][2], p->S, S.u, p->at<cx<float>>(p->L.bufA),
+    return band ? launch(k_itv_finish<NN, true>, grid, PAIRS * T, lds, st, sv.f, sv.pd[fin][0],
+                         sv.pd[fin][1], sv.pd[fin][2], p->S, sv.u, p->at<cx<float>>(p->L.bufA),
                          p->N1, p->at<const cx<float>>(p->L.twN2f), mu, c)
-                : launch(k_itv_finish<NN, false>, grid, PAIRS * T, lds, st, S.f, S.pd[fin][0],
-                         S.pd[fin][1], S.pd[fin][2], p->S, S.u, p->at<cx<float>>(p->L.bufA),
+                : launch(k_itv_finish<NN, false>, grid, PAIRS * T, lds, st, sv.f, sv.pd[fin][0],
+                         sv.pd[fin][1], sv.pd[fin][2], p->S, sv.u, p->at<cx<float>>(p->L.bufA),
                          p->N1, p->at<const cx<float>>(p->L.twN2f), mu, c);
   });
   return hipSuccess;
@@ -526,16 +526,16 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho, float* xo = 
   const Layout& L = p->L;
   const float mu = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
   const bool band = p->kind == CIP_PRIOR_ITV3D;
-  const ItvState S = itv_state(p);
-  const int nl = S.nl;
+  const ItvState sv = itv_state(p);
+  const int nl = sv.nl;
   const int start = (int)(((long long)(l - 1) * nl) & 1);
   const int grid = p->S * (p->N1 / RT);
   hipError_t e = hipSuccess;
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + row_work_floats<NN, float>(PAIRS, true)) * 4;
-    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), S.u,
-               S.f, S.pd[start][0], S.pd[start][1], S.pd[start][2], xo, p->N1,
+    e = launch(k_itv_prep<NN>, grid, PAIRS * T, lds, st, p->at<const cx<float>>(L.bufB), sv.u,
+               sv.f, sv.pd[start][0], sv.pd[start][1], sv.pd[start][2], xo, p->N1,
                p->at<const cx<float>>(L.twN2f), l == 1 ? 1 : 0);
   });
   if (e != hipSuccess) return e;
@@ -546,13 +546,13 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho, float* xo = 
   for (int j = 0; j < nl; ++j) {
     const int in = (start + j) & 1, out = in ^ 1;
     const int m = std::min(ITV_KB, p->tv_inner - j * ITV_KB);
-    float* const* pin = S.pd[in];
-    float* const* pout = S.pd[out];
+    float* const* pin = sv.pd[in];
+    float* const* pout = sv.pd[out];
     if (band) {
       switch (p->S) {
 #define ITV3_CASE(SS)                                                                       \
   case SS:                                                                                  \
-    e = itv3_launch<SS>(t32, g32, g16, st, S.f, pin, pout, p->N1, p->N2, m, 1.f / mu);     \
+    e = itv3_launch<SS>(t32, g32, g16, st, sv.f, pin, pout, p->N1, p->N2, m, 1.f / mu);     \
     break;
         ITV3_CASE(1) ITV3_CASE(2) ITV3_CASE(3) ITV3_CASE(4)
         ITV3_CASE(5) ITV3_CASE(6) ITV3_CASE(7) ITV3_CASE(8)
@@ -560,9 +560,9 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho, float* xo = 
         default: return hipErrorInvalidValue;
       }
     } else {
-      e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, S.f, pin[0], pin[1],
+      e = t32 ? launch(k_itv_chambolle<32, ITV_KB>, cgrid, 256, 0, st, sv.f, pin[0], pin[1],
                        pout[0], pout[1], p->N1, p->N2, m, 1.f / mu, 0.125f)
-              : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, S.f, pin[0], pin[1],
+              : launch(k_itv_chambolle<16, ITV_KB>, cgrid, 256, 0, st, sv.f, pin[0], pin[1],
                        pout[0], pout[1], p->N1, p->N2, m, 1.f / mu, 0.125f);
     }
     if (e != hipSuccess) return e;
@@ -1800,7 +1800,7 @@ int solve_itv_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
   float* xb1 = xb0 + n;
   auto xbuf = [&](int l) { return (l & 1) ? xb1 : xb0; };
   float* tprev = p->at<float>(L.tprev);
-  const ItvState S = itv_state(p);
+  const ItvState sv = itv_state(p);
   const int groups = p->S * (p->N1 / RT);
   std::vector<float> sums((size_t)groups * 4);
   auto xhat0 = [&]() -> hipError_t {
@@ -1828,7 +1828,7 @@ int solve_itv_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
       double next = rho;
       bool stop = false;
       if (check || store) {
-        HIP_TRY(launch(k_itv_norm, groups, 256, 0, st, S.f, S.u, xo, tprev,
+        HIP_TRY(launch(k_itv_norm, groups, 256, 0, st, sv.f, sv.u, xo, tprev,
                        check && l > 1 ? xbuf(l - 1) : nullptr, RT * p->N2, l == 1 ? 1 : 0,
                        store ? 1 : 0, p->at<float>(L.sums)));
         if (check) {
