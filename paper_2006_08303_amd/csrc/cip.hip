@@ -91,7 +91,7 @@ int state_floats_per_voxel(int kind) {
     case CIP_PRIOR_ITV2D: return 6;  // u, dual p (2 components, double-buffered), f
     case CIP_PRIOR_ITV3D: return 8;  // u, dual p (3 components, double-buffered), f
     case CIP_PRIOR_TV2D: return 4;   // 2 components, double-buffered
-    case CIP_PRIOR_TV3D: return 6;   // 3 components, double-buffered
+    case CIP_PRIOR_TV3D: return 7;   // 3 components, double-buffered; x
     case CIP_PRIOR_PATCH: return 0;  // codes live in their own region
     case CIP_PRIOR_CONV2D: return 0;
     case CIP_PRIOR_CONV3D: return 0;
@@ -426,6 +426,18 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
                   p->N1, p->at<const cx<float>>(use8 ? L.twN2f8 : L.twN2f), kappa,
                   l == 1 ? 1 : 0, sc);
   };
+  // TV3D: x of every plane in image space once (after both state buffers),
+  // then the row pass reads the neighbouring planes' rows from it
+  float* xim = p->at<float>(L.state) + 2 * buf;
+  auto run3 = [&](auto kern, int threads, size_t work_floats, bool use8, int parts = 1) {
+    hipError_t e = row_c2r(p->at<const cx<float>>(L.bufB), xim, p->S, p->N1, p->N2, 1.0f,
+                           p->at<const cx<float>>(L.twN2f), st);
+    if (e != hipSuccess) return e;
+    return launch(kern, p->S * (p->N1 / RT) * parts, threads,
+                  (size_t)(2 * p->N2 + work_floats) * 4, st, (const float*)xim,
+                  p->at<cx<float>>(L.bufA), vin, vout, p->S, p->N1,
+                  p->at<const cx<float>>(use8 ? L.twN2f8 : L.twN2f), kappa, l == 1 ? 1 : 0, sc);
+  };
   DISPATCH_N(p->N2, {
     constexpr int PD = ppt_row<NN>();
     // 8 points per thread only where the work-group stays within 1024 threads
@@ -435,14 +447,14 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
     if (p->row_np == 2) {   // half tiles: 2 own row pairs per work-group
       const int th2 = 3 * (NN / (use8 ? P8 : PD));
       if (band)
-        return use8 ? run(k_admm_row_tv3<NN, P8, 2>, th2, tv_work_floats<NN, 2>(), true, RT / 4)
-                    : run(k_admm_row_tv3<NN, PD, 2>, th2, tv_work_floats<NN, 2>(), false, RT / 4);
+        return use8 ? run3(k_admm_row_tv3<NN, P8, 2>, th2, tv_work_floats<NN, 2>(), true, RT / 4)
+                    : run3(k_admm_row_tv3<NN, PD, 2>, th2, tv_work_floats<NN, 2>(), false, RT / 4);
       return use8 ? run(k_admm_row_tv<NN, P8, 2>, th2, tv_work_floats<NN, 2>(), true, RT / 4)
                   : run(k_admm_row_tv<NN, PD, 2>, th2, tv_work_floats<NN, 2>(), false, RT / 4);
     }
     if (band)
-      return use8 ? run(k_admm_row_tv3<NN, P8>, threads, tv_work_floats<NN>(), true)
-                  : run(k_admm_row_tv3<NN, PD>, threads, tv_work_floats<NN>(), false);
+      return use8 ? run3(k_admm_row_tv3<NN, P8>, threads, tv_work_floats<NN>(), true)
+                  : run3(k_admm_row_tv3<NN, PD>, threads, tv_work_floats<NN>(), false);
     return use8 ? run(k_admm_row_tv<NN, P8>, threads, tv_work_floats<NN>(), true)
                 : run(k_admm_row_tv<NN, PD>, threads, tv_work_floats<NN>(), false);
   });

@@ -881,20 +881,21 @@ k_admm_row_tv(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
 
 // Row pass of the TV3D prior: T adds the band difference w_b[s] = x[s+1] -
 // x[s] (s < S - 1; none after the last plane), whose adjoint adds
-// q_b[s-1] - q_b[s] to g of plane s. One work-group per (plane s, row tile),
-// as for TV2D; to form the band terms it also inverse-transforms the same
-// rows of planes s - 1 and s + 1 (x of a neighbouring plane is recomputed
-// rather than exchanged between work-groups). q_b[s] is computed identically
-// by the work-groups of planes s and s + 1 (same inputs, same arithmetic);
-// only the former stores the band state of plane s.
+// q_b[s-1] - q_b[s] to g of plane s. x of every plane is first brought to
+// image space once by k_row_c2r (xin [S][N1][N2]); one work-group per (plane
+// s, row tile) as for TV2D stages rows rb-1 .. rb+SW of plane s from xin and
+// reads the own rows of planes s -/+ 1 from it directly, so no neighbouring
+// plane is transformed again. q_b[s] is computed identically by the
+// work-groups of planes s and s + 1 (same inputs, same arithmetic); only the
+// former stores the band state of plane s.
 // State buffer layout [3][S][N1][N2] (vertical, horizontal, band).
 template <int N2, int PPT_ = ppt_row<N2>(), int NP = PAIRS>
 __global__ void __launch_bounds__((NP + 1) * (N2 / PPT_))
-k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
-               const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
-               const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
+k_admm_row_tv3(const float* __restrict__ xin, cx<float>* __restrict__ Gout,
+                const float* __restrict__ vin, float* __restrict__ vout, int S, int N1,
+                const cx<float>* __restrict__ twg, float kappa, int first, float sc) {
   using G = TvGeo<N2, PPT_, NP>;
-  constexpr int PPT = G::PPT, T = G::T;
+  constexpr int PPT = G::PPT, T = G::T, NR = G::NR;
   constexpr int PARTS = RT / G::SW;   // work-groups per RT-row tile
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* tw = reinterpret_cast<cx<float>*>(smem_raw);
@@ -904,21 +905,26 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int s = b / (tiles * PARTS), rem = b % (tiles * PARTS);
   const int row0 = (rem / PARTS) * RT, r0 = (rem % PARTS) * G::SW, rb = row0 + r0;
-  cx<float>* cb = reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2);
-  cx<float>* stg = reinterpret_cast<cx<float>*>(lds);
   const unsigned plane = (unsigned)N1 * N2;
   const unsigned cstride = (unsigned)S * plane;
   const bool active = g < NP;
-  // own elements of this thread: rows rb + 2g, rb + 2g + 1 at columns
-  // t + T q (local LDS rows 1 + 2g, 2 + 2g)
   const unsigned oa = (unsigned)(rb + 2 * g) * N2 + t;
   const float* Xa = lds + (1 + 2 * g) * N2 + t;
   const float* Xb = Xa + N2;
   lds_load_table(tw, twg, N2);
-  tv_stage_rows<N2, PPT_, NP>(Yin, stg, s, row0, N1, r0);
+  // X rows 0 .. NR-1 are the image rows rb-1 .. rb+SW of plane s (circular)
+  const float* xs = xin + (size_t)s * plane;
+  batched_to_lds<8, float>(
+      NR * N2,
+      [&](int e) {
+        int gr = rb - 1 + e / N2;
+        gr += gr < 0 ? N1 : (gr >= N1 ? -N1 : 0);
+        return xs[(size_t)gr * N2 + e % N2];
+      },
+      [&](int e, const float& v) { lds[e] = v; });
   float pov[G::PER], poh[G::PER];
   tv_prefetch<N2, PPT_, NP>(vin, pov, poh, s, rb, N1, cstride, first);
-  tv_inverse_rows<N2, PPT_, NP>(stg, cb, tw, lds, g, t);
+  __syncthreads();
   float xa[PPT], xb[PPT];   // x of plane s, own elements
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -930,44 +936,46 @@ k_admm_row_tv3(const cx<float>* __restrict__ Yin, cx<float>* __restrict__ Gout,
   // band terms: first + q_b[s-1] (from plane s-1), then - q_b[s] (plane s+1)
   for (int d = 0; d < 2; ++d) {
     const int sn = d == 0 ? s - 1 : s + 1;   // neighbouring plane
-    if (sn < 0 || sn >= S) continue;         // uniform over the work-group
-    tv_stage_rows<N2, PPT_, NP>(Yin, stg, sn, row0, N1, r0);
-    tv_inverse_rows<N2, PPT_, NP>(stg, cb, tw, lds, g, t);
+    if (sn < 0 || sn >= S || !active) continue;
     const unsigned bo = 2 * cstride + (unsigned)(d == 0 ? s - 1 : s) * plane + oa;
+    const float* xn = xin + (size_t)sn * plane + oa;
+    float na_[PPT], nb_[PPT], pa_[PPT], pb_[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-      if (active) {
-        const float pa = first ? 0.f : ld_off(vin, bo + T * q);
-        const float pb = first ? 0.f : ld_off(vin, bo + N2 + T * q);
-        const float wa = d == 0 ? xa[q] - Xa[T * q] : Xa[T * q] - xa[q];
-        const float wb = d == 0 ? xb[q] - Xb[T * q] : Xb[T * q] - xb[q];
-        const float na = wa + clip_f(pa, kappa);
-        const float nb = wb + clip_f(pb, kappa);
-        float qa, qb, sa = na, sb = nb;
-        if (sc == 1.f) {
-          qa = 2.f * soft_f(na, kappa) - na;
-          qb = 2.f * soft_f(nb, kappa) - nb;
-        } else {
-          const float ta = soft_f(na, kappa), ua = sc * (na - ta);
-          const float tb = soft_f(nb, kappa), ub = sc * (nb - tb);
-          qa = ta - ua;
-          qb = tb - ub;
-          sa = ta + ua;
-          sb = tb + ub;
-        }
-        if (d == 0) {
-          v[q] = cx<float>{v[q].x + qa, v[q].y + qb};
-        } else {
-          st_off(vout, bo + T * q, sa);
-          st_off(vout, bo + N2 + T * q, sb);
-          v[q] = cx<float>{v[q].x - qa, v[q].y - qb};
-        }
+      na_[q] = xn[T * q];
+      nb_[q] = xn[N2 + T * q];
+      pa_[q] = first ? 0.f : ld_off(vin, bo + T * q);
+      pb_[q] = first ? 0.f : ld_off(vin, bo + N2 + T * q);
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const float wa = d == 0 ? xa[q] - na_[q] : na_[q] - xa[q];
+      const float wb = d == 0 ? xb[q] - nb_[q] : nb_[q] - xb[q];
+      const float na = wa + clip_f(pa_[q], kappa);
+      const float nb = wb + clip_f(pb_[q], kappa);
+      float qa, qb, sa = na, sb = nb;
+      if (sc == 1.f) {
+        qa = 2.f * soft_f(na, kappa) - na;
+        qb = 2.f * soft_f(nb, kappa) - nb;
+      } else {
+        const float ta = soft_f(na, kappa), ua = sc * (na - ta);
+        const float tb = soft_f(nb, kappa), ub = sc * (nb - tb);
+        qa = ta - ua;
+        qb = tb - ub;
+        sa = ta + ua;
+        sb = tb + ub;
+      }
+      if (d == 0) {
+        v[q] = cx<float>{v[q].x + qa, v[q].y + qb};
+      } else {
+        st_off(vout, bo + T * q, sa);
+        st_off(vout, bo + N2 + T * q, sb);
+        v[q] = cx<float>{v[q].x - qa, v[q].y - qb};
       }
     }
-    __syncthreads();   // X is read above; the next staging overwrites it
   }
-  tv_forward_rows<N2, PPT_, NP>(v, lds, cb, tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t,
-                                r0);
+  tv_forward_rows<N2, PPT_, NP>(v, lds, reinterpret_cast<cx<float>*>(lds) + g * padded_len(N2),
+                                tw, Gout + rt_tile_base(s, row0, N1, G::H2), g, t, r0);
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int S) {  // i < j
