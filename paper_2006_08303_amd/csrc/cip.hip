@@ -412,7 +412,10 @@ hipError_t admm_row_dct(cip_plan_t p, int mode, hipStream_t st, float* xout, dou
 
 // Row pass of the TV priors; pass number l >= 1 of the solve (state buffers
 // alternate so that halo rows of the previous state stay readable).
-hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
+// x_ready (TV3D): the x buffer already holds x of the current spectra (the
+// norm pass of this iteration wrote it).
+hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f,
+                       bool x_ready = false) {
   const Layout& L = p->L;
   float kappa = (float)(p->lambda / (rho > 0.0 ? rho : p->rho));
   const bool band = p->kind == CIP_PRIOR_TV3D;
@@ -430,9 +433,11 @@ hipError_t admm_row_tv(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, fl
   // then the row pass reads the neighbouring planes' rows from it
   float* xim = p->at<float>(L.state) + 2 * buf;
   auto run3 = [&](auto kern, int threads, size_t work_floats, bool use8, int parts = 1) {
-    hipError_t e = row_c2r(p->at<const cx<float>>(L.bufB), xim, p->S, p->N1, p->N2, 1.0f,
-                           p->at<const cx<float>>(L.twN2f), st);
-    if (e != hipSuccess) return e;
+    if (!x_ready) {
+      hipError_t e = row_c2r(p->at<const cx<float>>(L.bufB), xim, p->S, p->N1, p->N2, 1.0f,
+                             p->at<const cx<float>>(L.twN2f), st);
+      if (e != hipSuccess) return e;
+    }
     return launch(kern, p->S * (p->N1 / RT) * parts, threads,
                   (size_t)(2 * p->N2 + work_floats) * 4, st, (const float*)xim,
                   p->at<cx<float>>(L.bufA), vin, vout, p->S, p->N1,
@@ -582,11 +587,12 @@ hipError_t itv_row(cip_plan_t p, int l, hipStream_t st, double rho, float* xo = 
   return itv_finish(p, l, mu, 1.f, st);
 }
 
-hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f) {
+hipError_t admm_row(cip_plan_t p, int l, hipStream_t st, double rho = 0.0, float sc = 1.f,
+                     bool x_ready = false) {
   if (is_itv(p)) return itv_row(p, l, st, rho);
   if (is_dct(p))
     return admm_row_dct(p, l == 1 ? ROW_FIRST : ROW_FULL, st, nullptr, rho, sc);
-  return admm_row_tv(p, l, st, rho, sc);
+  return admm_row_tv(p, l, st, rho, sc, x_ready);
 }
 
 // Norm pass of a checked iteration l (see norms.hpp): partial sums to
@@ -612,6 +618,14 @@ hipError_t norm_pass(cip_plan_t p, int l, double rho, float* xcur, const float* 
   const bool band = p->kind == CIP_PRIOR_TV3D;
   const size_t buf = (size_t)(band ? 3 : 2) * p->S * p->N1 * p->N2;
   const float* vin = p->at<float>(L.state) + (size_t)((l + 1) & 1) * buf;
+  // TV3D: x of every plane to the x buffer of the state (the row pass that
+  // follows on the same spectra is told that it is there)
+  float* xim = p->at<float>(L.state) + 2 * buf;
+  if (band) {
+    hipError_t e = row_c2r(p->at<const cx<float>>(L.bufB), xim, p->S, p->N1, p->N2, 1.0f,
+                           p->at<const cx<float>>(L.twN2f), st);
+    if (e != hipSuccess) return e;
+  }
   DISPATCH_N(p->N2, {
     const int T = NN / ppt_row<NN>();
     size_t lds = (size_t)(2 * NN + tv_work_floats<NN>()) * 4;
@@ -619,11 +633,11 @@ hipError_t norm_pass(cip_plan_t p, int l, double rho, float* xcur, const float* 
       return launch(k_norm_tv<NN, true>, grid, (PAIRS + 1) * T, lds, st,
                     p->at<const cx<float>>(L.bufB), vin, p->S, p->N1,
                     p->at<const cx<float>>(L.twN2f), kappa, first, xcur, xprev,
-                    p->at<float>(L.sums));
+                    p->at<float>(L.sums), (const float*)xim);
     return launch(k_norm_tv<NN, false>, grid, (PAIRS + 1) * T, lds, st,
                   p->at<const cx<float>>(L.bufB), vin, p->S, p->N1,
                   p->at<const cx<float>>(L.twN2f), kappa, first, xcur, xprev,
-                  p->at<float>(L.sums));
+                  p->at<float>(L.sums), (const float*)nullptr);
   });
   return hipSuccess;
 }
@@ -1991,7 +2005,7 @@ int cip_solve_adaptive(cip_plan_t p, const float* d_y, const cip_adaptive_params
         HIP_TRY(admm_row_dct(p, ROW_FINAL, st, d_x));
         break;
       }
-      HIP_TRY(admm_row(p, l, st, rho, (float)(rho / next)));
+      HIP_TRY(admm_row(p, l, st, rho, (float)(rho / next), check || store));
       if (next != rho) {
         HIP_TRY(gram(p, st, next));
         HIP_TRY(xhat0());

@@ -136,12 +136,14 @@ k_norm_dct(const cx<float>* __restrict__ Yin, const float* __restrict__ vstate, 
 }
 
 // TV priors (BAND: TV3D): same tiling as the TV row passes; the band term of
-// plane s needs x of plane s + 1, transformed here as well.
+// plane s needs x of plane s + 1, read from xall ([S][N1][N2], x of every
+// plane from the same spectra, written by k_row_c2r before this pass).
 template <int N2, bool BAND>
 __global__ void __launch_bounds__((PAIRS + 1) * (N2 / ppt_row<N2>()))
 k_norm_tv(const cx<float>* __restrict__ Yin, const float* __restrict__ vin, int S, int N1,
           const cx<float>* __restrict__ twg, float kappa, int first, float* __restrict__ xcur,
-          const float* __restrict__ xprev, float* __restrict__ sums) {
+          const float* __restrict__ xprev, float* __restrict__ sums,
+          const float* __restrict__ xall) {
   using G = TvGeo<N2>;
   constexpr int NTP = next_pow2((int)G::NT);
   constexpr int PERO = (RT * N2 + (int)G::NT - 1) / (int)G::NT;   // own elements per thread
@@ -182,17 +184,14 @@ k_norm_tv(const cx<float>* __restrict__ Yin, const float* __restrict__ vin, int 
     }
   }
   if (BAND && s + 1 < S) {
-    __syncthreads();   // X is read above; the staging below overwrites it
-    tv_stage_rows<N2>(Yin, stg, s + 1, row0, N1);
-    tv_inverse_rows<N2>(stg, cb, tw, lds, g, t);
+    const float* xn = xall + (size_t)(s + 1) * plane;
 #pragma unroll
     for (int it = 0; it < PERO; ++it) {
       const unsigned e = threadIdx.x + it * G::NT;
       if (e < (unsigned)(RT * N2)) {
-        const unsigned lr = 1 + e / N2, n2 = e % N2;
-        const unsigned o = s * plane + (unsigned)(row0 - 1 + (int)lr) * N2 + n2;
-        const float wb = X[lr * N2 + n2] - xo[it];
-        residual_terms(wb, first ? 0.f : ld_off(vin, 2 * cstride + o), kappa, acc);
+        const unsigned o = (unsigned)row0 * N2 + e;   // own element e of the tile
+        const float wb = ld_off(xn, o) - xo[it];
+        residual_terms(wb, first ? 0.f : ld_off(vin, 2 * cstride + s * plane + o), kappa, acc);
       }
     }
   }
