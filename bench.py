@@ -65,16 +65,20 @@ def algorithmic_bytes(which, S, N1, N2, prior):
 
     Row pass: read the column-pass output Y (S N1 H2 complex), read and write
     the state (one float per voxel and constraint component: 1 for DCT, 2 for
-    TV2D), write the next row spectrum G (S N1 H2 complex):
-        2 * S N1 H2 * 8 + 2 * comps * S N1 N2 * 4.
-    (The TV halo rows, 2 extra rows per 8-row tile, are not counted.)
+    TV2D, 3 for TV3D), write the next row spectrum G (S N1 H2 complex):
+        2 * S N1 H2 * 8 + 2 * comps * S N1 N2 * 4;
+    TV3D adds x of every plane written by the C2R and read back by the band
+    pass (2 * S N1 N2 * 4). (The TV halo rows, 2 extra rows per 8-row tile,
+    and the neighbouring planes' rows re-read by the band pass are not
+    counted.)
     Column pass: read G, the packed Hermitian A (S reals + S(S-1)/2 complex per
     frequency) and x_hat0, write Y: F * (8S + 4S + 8 S(S-1)/2 + 8S + 8S)."""
     H2 = N2 // 2 + 1
     F = N1 * H2
     if which == 0:
-        comps = 1 if prior == "dct2d" else 2
-        return 2 * S * F * 8 + 2 * comps * S * N1 * N2 * 4
+        comps = {"dct2d": 1, "tv2d": 2, "tv3d": 3}[prior]
+        xbuf = 2 * S * N1 * N2 * 4 if prior == "tv3d" else 0
+        return 2 * S * F * 8 + 2 * comps * S * N1 * N2 * 4 + xbuf
     return F * (8 * S + 4 * S + 8 * (S * (S - 1) // 2) + 8 * S + 8 * S)
 
 
@@ -175,7 +179,8 @@ def parity_vs_oracle(plan, x_ref, y_ref, x_true, n_iter, dev):
                 round(10 * np.log10(1.0 / float(np.mean((x_ref - x_true) ** 2))), 3)}
 
 
-PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0), "itv2d": (1e-3, 1e-2, 1.0),
+PRIOR_PARAMS = {"dct2d": (1e-2, 0.1, 1.0), "tv2d": (1e-3, 1e-2, 1.0), "tv3d": (1e-3, 1e-2, 1.0),
+                "itv2d": (1e-3, 1e-2, 1.0),
                 "itv3d": (1e-3, 1e-2, 1.0)}
 ITV_INNER = 20   # Chambolle iterations per ADMM iteration (isotropic TV)
 
@@ -210,6 +215,7 @@ def run_prior(prior, N, K, S, args, psf_t, x_t, noise_t):
     # per-kernel device time (HIP events recorded on the launch stream)
     times = {w: plan.time_kernel(w, args.kernel_reps) for w in (0, 1)}
     row_name = {"dct2d": "row pass (k_admm_row_dct)", "tv2d": "row pass (k_admm_row_tv)",
+                "tv3d": "row pass (k_row_c2r + k_admm_row_tv3)",
                 "itv2d": f"row passes + {ITV_INNER} Chambolle iterations (k_itv_prep, "
                          f"k_itv_chambolle x {(ITV_INNER + 4) // 5}, k_itv_finish)",
                 "itv3d": f"row passes + {ITV_INNER} band-coupled Chambolle iterations "
@@ -550,6 +556,15 @@ def main():
               "kernels_avg_us": {tv_names[w]: round(tv_times[w], 3) for w in tv_times},
               "algorithmic_bytes_per_launch": {tv_names[w]: algorithmic_bytes(w, S, N, N, "tv2d")
                                                for w in tv_times}}
+    tv3 = None
+    if not args.no_tv:
+        _, _, _, _, _, tv3_value, tv3_ms, tv3_times, tv3_names, tv3_tuning = run_prior(
+            "tv3d", N, K, S, args, psf_t, x_t, noise_t)
+        tv3 = {"prior": "tv3d (lambda=1e-3, rho=1e-2, beta=1)", "value": round(tv3_value, 1),
+               "ms_per_step": round(tv3_ms, 4), "row_shape": tv3_tuning,
+               "kernels_avg_us": {tv3_names[w]: round(tv3_times[w], 3) for w in tv3_times},
+               "algorithmic_bytes_per_launch": {tv3_names[w]: algorithmic_bytes(w, S, N, N, "tv3d")
+                                                for w in tv3_times}}
     itv = None
     if not args.no_tv:
         _, _, _, _, _, itv_value, itv_ms, itv_times, itv_names, _ = run_prior(
@@ -618,6 +633,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "tv2d": tv,
+        "tv3d": tv3,
         "itv2d": itv,
         "itv3d": itv3,
         "concurrent_1024": conc,
