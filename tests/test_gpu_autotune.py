@@ -41,6 +41,7 @@ PARAMS = {"dct2d": (1e-2, 0.1), "tv2d": (1e-3, 1e-2), "tv3d": (1e-3, 1e-2)}
     ("tv2d", 384, [(4, 12), (2, 12)]),
     ("tv3d", 128, [(4, 16), (4, 8), (2, 16), (2, 8)]),
     ("tv3d", 16, [(2, 16)]),
+    ("tv3d", 384, [(4, 12), (2, 12)]),
 ])
 def test_every_shape_matches_oracle(prior, N, shapes):
     K, S = 3, 3

@@ -147,7 +147,7 @@ def test_tv2d_solve_matches_oracle(N, K, S, iters, kind):
     parity.check(got, ref, 1e-4)
 
 
-@pytest.mark.parametrize("prior", ["dct2d", "tv2d"])
+@pytest.mark.parametrize("prior", ["dct2d", "tv2d", "tv3d"])
 def test_rectangular_grid(prior):
     """N1 != N2 (64 x 128 and 128 x 32)."""
     for (N1, N2) in [(64, 128), (128, 32)]:
