@@ -42,6 +42,13 @@ __device__ __forceinline__ int wrap_idx(int i, int n) {
   return i;
 }
 
+// i mod n; `once` (uniform) states that i lies in [-n, 2n), where one
+// conditional correction is enough
+__device__ __forceinline__ int wrap_fast(int i, int n, bool once) {
+  if (once) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return wrap_idx(i, n);
+}
+
 // One forward level on the R x C corner (both axes fused through LDS). A
 // work-group produces the coefficients k1 in [K1, K1 + T), k2 in
 // [K2, K2 + T) of the four bands of one plane from the (2T + 14)^2 input
@@ -64,21 +71,27 @@ k_dwt2(const float* __restrict__ src, float* __restrict__ ll, float* __restrict_
   const int K1 = blockIdx.y * DWT_T, K2 = blockIdx.x * DWT_T;
   const size_t po = (size_t)blockIdx.z * N1 * N2;
   const float* in = src + po;
-  // all of a thread's loads are issued before its LDS stores (latency overlap)
-  constexpr int NL = (DWT_IN * DWT_IN + 255) / 256;
-  float val[NL];
+  // thread (ph, v) loads column v of the input tile, rows ph, ph + LP, ...
+  // (the column index is wrapped once, rows by one correction where the
+  // level is at least a tile's reach); every load is issued, at a clamped
+  // valid position, before the LDS stores, which skip the clamped ones
+  constexpr int LP = 256 / DWT_IN, NJ = (DWT_IN + LP - 1) / LP;
+  const int ph = threadIdx.x / DWT_IN, v = threadIdx.x % DWT_IN;
+  const bool act = ph < LP;
+  const int phc = act ? ph : LP - 1;
+  const bool once = R >= DWT_IN && C >= DWT_IN;
+  const int gc = wrap_fast(2 * K2 + v, C, once);
+  float val[NJ];
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e < DWT_IN * DWT_IN) {
-      const int u = e / DWT_IN, v = e % DWT_IN;
-      val[q] = in[(size_t)wrap_idx(2 * K1 + u, R) * N2 + wrap_idx(2 * K2 + v, C)];
-    }
+  for (int j = 0; j < NJ; ++j) {
+    const int u = min(phc + LP * j, DWT_IN - 1);
+    const int gr = wrap_fast(2 * K1 + u, R, once);
+    val[j] = in[(unsigned)gr * (unsigned)N2 + (unsigned)gc];
   }
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e < DWT_IN * DWT_IN) X[e / DWT_IN][e % DWT_IN] = val[q];
+  for (int j = 0; j < NJ; ++j) {
+    const int u = ph + LP * j;
+    if (act && u < DWT_IN) X[u][v] = val[j];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < DWT_IN * DWT_T; e += 256) {
@@ -130,28 +143,31 @@ k_idwt2(const float* __restrict__ ll, const float* __restrict__ coef, float* __r
   const int M1 = blockIdx.y * DWT_T, M2 = blockIdx.x * DWT_T;
   const size_t po = (size_t)blockIdx.z * N1 * N2;
   // band b: 0 low-low, 1 low rows / high columns, 2 high rows / low columns, 3 high-high
-  // all of a thread's loads are issued before its LDS stores (latency overlap)
-  constexpr int NB = IDWT_IN * IDWT_IN, NL = (4 * NB + 255) / 256;
-  float val[NL];
+  // The four bands' tiles are one array of 4 IDWT_IN rows (band-rows br =
+  // b IDWT_IN + u); thread (ph, v) loads column v of band-rows ph, ph + LP,
+  // ... As in the forward level, every load is issued at a clamped valid
+  // position before the LDS stores.
+  constexpr int NBR = 4 * IDWT_IN, LP = 256 / IDWT_IN, NJ = (NBR + LP - 1) / LP;
+  const int ph = threadIdx.x / IDWT_IN, v = threadIdx.x % IDWT_IN;
+  const bool act = ph < LP;
+  const int phc = act ? ph : LP - 1;
+  const bool once = h1 >= IDWT_IN && h2 >= IDWT_IN;
+  const int k2 = wrap_fast(M2 - 7 + v, h2, once);
+  const float* llp = ll + po;
+  const float* cfp = coef + po;
+  float val[NJ];
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e < 4 * NB) {
-      const int b = e / NB, r = e % NB;
-      const int u = r / IDWT_IN, v = r % IDWT_IN;
-      const int k1 = wrap_idx(M1 - 7 + u, h1), k2 = wrap_idx(M2 - 7 + v, h2);
-      const float* base =
-          b == 0 ? ll + po : coef + po + (size_t)((b >> 1) * h1) * N2 + (b & 1) * h2;
-      val[q] = base[(size_t)k1 * N2 + k2];
-    }
+  for (int j = 0; j < NJ; ++j) {
+    const int br = min(phc + LP * j, NBR - 1);
+    const int b = br / IDWT_IN, u = br % IDWT_IN;
+    const int k1 = wrap_fast(M1 - 7 + u, h1, once);
+    const unsigned off = (unsigned)(k1 + (b >> 1) * h1) * (unsigned)N2 + (unsigned)(k2 + (b & 1) * h2);
+    val[j] = (b == 0 ? llp : cfp)[off];
   }
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e < 4 * NB) {
-      const int r = e % NB;
-      B[e / NB][r / IDWT_IN][r % IDWT_IN] = val[q];
-    }
+  for (int j = 0; j < NJ; ++j) {
+    const int br = ph + LP * j;
+    if (act && br < NBR) B[br / IDWT_IN][br % IDWT_IN][v] = val[j];
   }
   __syncthreads();
   // along the rows: Y[u][2 m + e] for the low and the high row families
