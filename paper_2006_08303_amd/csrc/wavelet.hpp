@@ -94,36 +94,55 @@ k_dwt2(const float* __restrict__ src, float* __restrict__ ll, float* __restrict_
     if (act && u < DWT_IN) X[u][v] = val[j];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < DWT_IN * DWT_T; e += 256) {
-    const int u = e / DWT_T, k = e % DWT_T;
-    float a = 0.f, d = 0.f;
+  // along the rows: outputs k = 2j, 2j + 1 of row u from one window of 18
+  // samples (consecutive lanes take consecutive rows: odd LDS pitch)
+  for (int e = threadIdx.x; e < DWT_IN * (DWT_T / 2); e += 256) {
+    const int u = e % DWT_IN, j = e / DWT_IN;
+    float w[18];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const float v = X[u][2 * k + t];
-      a = fmaf(kSym8[t], v, a);
-      d = fmaf(sym8_g(t), v, d);
+    for (int t = 0; t < 18; ++t) w[t] = X[u][4 * j + t];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      float a = 0.f, d = 0.f;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        a = fmaf(kSym8[t], w[2 * o + t], a);
+        d = fmaf(sym8_g(t), w[2 * o + t], d);
+      }
+      RA[u][2 * j + o] = a;
+      RD[u][2 * j + o] = d;
     }
-    RA[u][k] = a;
-    RD[u][k] = d;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < DWT_T * DWT_T; e += 256) {
-    const int i = e / DWT_T, k = e % DWT_T;
-    const int k1 = K1 + i, k2 = K2 + k;
-    if (k1 >= h1 || k2 >= h2) continue;
-    float aa = 0.f, ad = 0.f, da = 0.f, dd = 0.f;
+  // along the columns: outputs i = 2m, 2m + 1 of column k from one window of
+  // 18 rows of RA and RD
+  for (int e = threadIdx.x; e < (DWT_T / 2) * DWT_T; e += 256) {
+    const int m = e / DWT_T, k = e % DWT_T;
+    const int k2 = K2 + k;
+    float ra[18], rd[18];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const float ra = RA[2 * i + t][k], rd = RD[2 * i + t][k];
-      aa = fmaf(kSym8[t], ra, aa);
-      ad = fmaf(kSym8[t], rd, ad);
-      da = fmaf(sym8_g(t), ra, da);
-      dd = fmaf(sym8_g(t), rd, dd);
+    for (int t = 0; t < 18; ++t) {
+      ra[t] = RA[4 * m + t][k];
+      rd[t] = RD[4 * m + t][k];
     }
-    ll[po + (size_t)k1 * N2 + k2] = aa;
-    coef[po + (size_t)k1 * N2 + h2 + k2] = ad;
-    coef[po + (size_t)(h1 + k1) * N2 + k2] = da;
-    coef[po + (size_t)(h1 + k1) * N2 + h2 + k2] = dd;
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const int k1 = K1 + 2 * m + o;
+      float aa = 0.f, ad = 0.f, da = 0.f, dd = 0.f;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        aa = fmaf(kSym8[t], ra[2 * o + t], aa);
+        ad = fmaf(kSym8[t], rd[2 * o + t], ad);
+        da = fmaf(sym8_g(t), ra[2 * o + t], da);
+        dd = fmaf(sym8_g(t), rd[2 * o + t], dd);
+      }
+      if (k1 < h1 && k2 < h2) {
+        ll[po + (size_t)k1 * N2 + k2] = aa;
+        coef[po + (size_t)k1 * N2 + h2 + k2] = ad;
+        coef[po + (size_t)(h1 + k1) * N2 + k2] = da;
+        coef[po + (size_t)(h1 + k1) * N2 + h2 + k2] = dd;
+      }
+    }
   }
 }
 
