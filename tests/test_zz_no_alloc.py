@@ -27,7 +27,8 @@ def _case(N, K, S, kind, cfg):
 @pytest.mark.timeout(300)
 def test_solve_static_equals_plan_solve_twice_shrinking():
     cases = [(512, 3, 3, "smooth_disk", 2, "dct2d", 0.1, 1e-2, 30),
-             (128, 2, 3, "rects_gauss", 1, "tv2d", 1e-2, 1e-3, 20)]
+             (128, 2, 3, "rects_gauss", 1, "tv2d", 1e-2, 1e-3, 20),
+             (64, 3, 3, "smooth_disk", 4, "tv3d", 1e-2, 1e-3, 15)]
     for N, K, S, kind, cfg, prior, rho, lam, iters in cases:
         print(f"solve_static {prior} N={N} K={K} S={S} iters={iters}", flush=True)
         psf, y = _case(N, K, S, kind, cfg)
