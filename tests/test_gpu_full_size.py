@@ -54,7 +54,8 @@ ROW_SHAPES = [(4, 16), (4, 8), (2, 16), (2, 8)]
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prior,lam,rho", [("dct2d", 1e-2, 0.1), ("tv2d", 1e-3, 1e-2)])
+@pytest.mark.parametrize("prior,lam,rho", [("dct2d", 1e-2, 0.1), ("tv2d", 1e-3, 1e-2),
+                                           ("tv3d", 1e-3, 1e-2)])
 def test_headline_1024_100_iterations(prior, lam, rho):
     N, K, S, iters = 1024, 3, 3, 100
     print(f"headline {prior} {N}^2 K=S={S}, {iters} iterations", flush=True)
