@@ -37,7 +37,7 @@ def _problem(N1, N2, K, S, cfg=10):
 @pytest.mark.parametrize("N1,N2,K,S,levels,iters", [
     (64, 64, 3, 3, 3, 20), (128, 64, 2, 2, 4, 15), (32, 32, 1, 1, 2, 25),
     (384, 384, 3, 3, 3, 8), (256, 256, 3, 5, 5, 10), (16, 16, 2, 3, 1, 12),
-    (64, 64, 3, 3, 6, 10),
+    (64, 64, 3, 3, 6, 10), (256, 256, 3, 3, 3, 100),
 ])
 def test_wavelet_dct_solve_matches_oracle(N1, N2, K, S, levels, iters):
     print(f"wdct3d N1={N1} N2={N2} K={K} S={S} levels={levels} iters={iters}", flush=True)
