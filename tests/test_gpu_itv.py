@@ -32,6 +32,7 @@ def _problem(kind, N, K, S, cfg=12):
 @pytest.mark.parametrize("kind,N,K,S,iters,inner", [("rects_gauss", 64, 2, 2, 20, 20),
                                                     ("smooth_disk", 64, 3, 3, 10, 20),
                                                     ("smooth_disk", 128, 3, 3, 8, 10),
+                                                    ("smooth_disk", 128, 3, 3, 100, 20),
                                                     ("rects_gauss", 256, 2, 3, 5, 20),
                                                     ("smooth_disk", 384, 3, 3, 4, 15),
                                                     ("smooth_disk", 64, 3, 3, 1, 20),
@@ -85,6 +86,7 @@ def test_itv_rejects_zero_lambda():
 @pytest.mark.parametrize("kind,N,K,S,iters,inner", [("rects_gauss", 64, 2, 2, 20, 20),
                                                     ("smooth_disk", 64, 3, 3, 10, 20),
                                                     ("smooth_disk", 128, 3, 3, 8, 10),
+                                                    ("smooth_disk", 128, 3, 3, 100, 20),
                                                     ("rects_gauss", 16, 2, 2, 6, 3),
                                                     ("smooth_disk", 48 * 8, 3, 3, 4, 15),
                                                     ("rects_gauss", 64, 2, 1, 6, 7),
