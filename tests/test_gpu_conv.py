@@ -86,7 +86,7 @@ def _conv3_problem(N, K, S, M, L, cfg=3):
 @pytest.mark.parametrize("N,K,S,M,L,iters", [(64, 3, 3, 8, 5, 1), (64, 3, 3, 8, 5, 12),
                                              (128, 3, 3, 16, 7, 8), (32, 2, 2, 4, 3, 10),
                                              (64, 5, 5, 8, 5, 6), (32, 8, 8, 4, 3, 4),
-                                             (384, 3, 3, 8, 5, 3)])
+                                             (384, 3, 3, 8, 5, 3), (128, 3, 3, 32, 11, 100)])
 def test_conv3d_solve_matches_oracle(N, K, S, M, L, iters):
     """3D filters and codes: band DFTs inside the frequency pass."""
     print(f"conv3d solve N={N} K={K} S={S} M={M} L={L} iters={iters}", flush=True)

@@ -31,7 +31,7 @@ def _problem(N, K, S, cfg=11):
 
 @pytest.mark.parametrize("N,K,S,iters", [(64, 3, 3, 30), (128, 5, 5, 12), (64, 2, 1, 10),
                                          (256, 3, 8, 6), (384, 3, 3, 5), (1024, 3, 3, 3),
-                                         (32, 8, 8, 10), (64, 3, 3, 1)])
+                                         (32, 8, 8, 10), (64, 3, 3, 1), (256, 3, 3, 100)])
 def test_dct3d_solve_matches_oracle(N, K, S, iters):
     print(f"dct3d N={N} K={K} S={S} iters={iters}", flush=True)
     x, psf, y = _problem(N, K, S)
