@@ -289,10 +289,14 @@ class PatchADMM:
             t = t_new
             if self.dict_update:
                 # one D, G, E step per outer iteration (Eqs. ADMM0, ADMM1,
-                # subh); the next x- and z-updates use the feasible G
+                # subh); the next x- and z-updates use the feasible G. The
+                # scaled dual of the penalty sigma/2 ||D - G + E||^2 that
+                # ADMM0 and ADMM1 minimise moves by the split residual D - G
+                # (the sign printed with Eq. subh, G - D, makes E double
+                # every step where D follows G - E, and the solve diverge)
                 d = self.d_update(x, z)
                 g = self.g_update(d)
-                self.e = self.e + g - d
+                self.e = self.e + d - g
                 self.g = g
                 self.set_dictionary(g)
             if callback is not None:
@@ -458,7 +462,7 @@ class ConvADMM:
                 # z-updates use the feasible dictionary g
                 d = self.d_update(x, z)
                 g = self.g_update(d)
-                self.e = self.e + g - d
+                self.e = self.e + d - g      # Eq. h_admm, sign as for Eq. subh
                 self.g = g
                 self.set_dictionary(g)
             if callback is not None:
@@ -531,7 +535,7 @@ def synthesis_run_adaptive(alg, y, max_iters, tau=2.0, mu=10.0, every=1, tol=1e-
             g_prev = alg.g
             d = alg.d_update(x, z)
             g = alg.g_update(d)
-            alg.e = alg.e + g - d
+            alg.e = alg.e + d - g
             alg.g = g
             if check and adapt_sigma:
                 rd = float(np.linalg.norm(d - g))

@@ -607,15 +607,18 @@ k_cdl_project(const float* __restrict__ dpl, const float* __restrict__ e, float*
 // The dual e is kept as plane spectra (the transforms are linear): with
 // s = d^ + e^ (from the d-update) and g^ the spectra of the placed g,
 // elementwise over [P][F]:
-//   e^ <- e^ + g^ - d^ = g^ + 2 e^ - s,  ge <- g^ - e^ (the next right-hand
-//   side),  gs <- g^.
+//   e^ <- e^ + d^ - g^ = s - g^,  ge <- g^ - e^ (the next right-hand side),
+//   gs <- g^.
+// (e is the scaled dual of the penalty sigma/2 ||d - g + e||^2 of Eqs.
+// d_admm and g_admm, so it moves by the split residual d - g; the sign
+// printed with Eq. h_admm makes e double every step and the solve diverge.)
 // ge holds g^ on entry; gs may alias sd (s is read first).
 __global__ void k_cdl_fdual(cx<float>* __restrict__ e, cx<float>* ge, const cx<float>* sd,
                             cx<float>* gs, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const cx<float> g = ge[i], sv = sd[i], eo = e[i];
-  const cx<float> en = g + eo + eo - sv;
+  const cx<float> g = ge[i], sv = sd[i];
+  const cx<float> en = sv - g;
   e[i] = en;
   ge[i] = g - en;
   gs[i] = g;
@@ -624,7 +627,7 @@ __global__ void k_cdl_fdual(cx<float>* __restrict__ e, cx<float>* ge, const cx<f
 // k_cdl_fdual at a check of the dictionary penalty (the rule of Section IV-C
 // applied to sigma): the same updates, grid-stride over the work-groups, and
 // per work-group b
-//   part[2 b] = sum w |e^_new - e^_old|^2 = sum w |g^ - d^|^2, w = 1 on the
+//   part[2 b] = sum w |e^_new - e^_old|^2 = sum w |d^ - g^|^2, w = 1 on the
 //     half-spectrum columns k2 = 0 and N2 / 2 and 2 elsewhere, so that the
 //     total is N1 N2 ||D - G||^2 (Parseval, unnormalised transforms);
 //   part[2 b + 1] = sum (gtap - gprev)^2 over the ntaps filter taps
@@ -638,7 +641,7 @@ k_cdl_fdual_res(cx<float>* __restrict__ e, cx<float>* ge, const cx<float>* sd, c
   float a = 0.f, b = 0.f;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const cx<float> g = ge[i], sv = sd[i], eo = e[i];
-    const cx<float> en = g + eo + eo - sv;
+    const cx<float> en = sv - g;
     e[i] = en;
     ge[i] = g - en;
     gs[i] = g;

@@ -3,7 +3,10 @@
 // taken after the sparse-code update with the image x and the codes Z:
 //   D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1     Eq. sold_patch
 //   G = (D + E) / ||D + E||_F                              Eq. ADMM1
-//   E = E + G - D                                          Eq. subh
+//   E = E + D - G                                          Eq. subh
+// (E is the scaled dual of the penalty sigma/2 ||D - G + E||^2 of Eqs. ADMM0
+// and ADMM1, so it moves by the split residual D - G; the sign printed with
+// Eq. subh makes E double every step and the solve diverge)
 // with X = [P_1 x | ... | P_J x] (n x J, n = 64 S) and Z (A x J). The next x-
 // and code updates use G: its BF16 copy and M1 = G^T (rho I + G G^T)^-1.
 //
@@ -633,7 +636,7 @@ k_pdl_trsolve64(const double* __restrict__ lt, const double* __restrict__ lt2, i
   }
 }
 
-// G = (D + E) / ||D + E||_F, E <- E + G - D from the FP64 D, G and E stored
+// G = (D + E) / ||D + E||_F, E <- E + D - G from the FP64 D, G and E stored
 // in FP32 and G in BF16 (count = n A entries, one work-group of 1024
 // threads; the squared norm is summed in FP64 in a fixed order). res (optional, a check of the dictionary penalty):
 // res[0] = ||D - G||^2, res[1] = ||G - G_prev||^2 in FP64.
@@ -665,7 +668,7 @@ k_pdl_project(const double* __restrict__ d, float* __restrict__ g, float* __rest
       sd += b * b;
     }
     g[i] = gv;
-    e[i] = (float)(ev + gd - dv);
+    e[i] = (float)(ev + dv - gd);
     gbf[i] = f2bf(gv);
   }
   if (res) {

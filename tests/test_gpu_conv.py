@@ -139,7 +139,8 @@ def _taps(g, L):
 
 @pytest.mark.parametrize("N,K,S,M,L,iters,sigma", [(32, 2, 2, 4, 3, 6, 10.0), (64, 3, 3, 8, 5, 8, 10.0),
                                                    (64, 3, 3, 8, 5, 8, 1.0), (32, 4, 4, 4, 3, 5, 10.0),
-                                                   (128, 3, 3, 16, 7, 4, 10.0), (64, 3, 3, 8, 5, 1, 10.0)])
+                                                   (128, 3, 3, 16, 7, 4, 10.0), (64, 3, 3, 8, 5, 1, 10.0),
+                                                   (64, 3, 3, 8, 5, 100, 10.0)])
 def test_conv3d_dictionary_learning_matches_oracle(N, K, S, M, L, iters, sigma):
     """Online update of the 3D dictionary (one d, g, e step per outer
     iteration): x and the learned filters against the FP64 oracle."""
@@ -186,7 +187,8 @@ def test_conv3d_dictionary_learning_full_size_1024():
                                                       (64, 3, 3, 8, 5, 8, 1.0, 0.01),
                                                       (32, 5, 5, 4, 3, 5, 10.0, 0.0),
                                                       (32, 8, 8, 4, 3, 4, 10.0, 0.0),
-                                                      (128, 3, 3, 16, 7, 4, 10.0, 0.0)])
+                                                      (128, 3, 3, 16, 7, 4, 10.0, 0.0),
+                                                      (64, 3, 3, 8, 5, 100, 10.0, 0.0)])
 def test_conv2d_dictionary_learning_matches_oracle(N, K, S, M, L, iters, sigma, mu):
     """Online update of the common 2D dictionary (Woodbury form with an S x S
     Cholesky per frequency on the GPU, a dense M x M solve in the oracle)."""
