@@ -229,11 +229,14 @@ int cip_solve(cip_plan_t plan, const float* d_y, int iters, float* d_x, void* st
  *   size (3D: Sherman-Morrison at every 3D frequency; 2D: the rank-S system
  *   of the common filters per 2D frequency, by the Woodbury identity),
  *   g = d + e cropped to the filter support and scaled to unit norm per
- *   filter, e <- e + g - d.
+ *   filter, e <- e + d - g (e is the scaled dual of the split d = g that the
+ *   d- and g-updates' penalty sigma/2 ||d - g + e||^2 defines; the sign printed
+ *   with Eq. h_admm, g - d, would double e every step).
  *   Patch prior (Eqs. ADMM0, sold_patch, ADMM1, subh): with the patch matrix
  *   X = [P_1 x | ... | P_J x] and the codes Z of the iteration,
  *   D = (X Z^T + sigma (G - E)) (Z Z^T + sigma I)^-1, G = (D + E) / ||D + E||_F
- *   (the constraint ||D||_F = 1 of Eq. patch_based_dic), E <- E + G - D;
+ *   (the constraint ||D||_F = 1 of Eq. patch_based_dic), E <- E + D - G (the
+ *   scaled dual of D = G, signed as for the convolutional priors);
  *   D is formed in FP64 on the GPU (X Z^T and Z Z^T on FP64 MFMA from the
  *   FP32 image and the FP32 codes, the FP64 Cholesky factor of
  *   Z Z^T + sigma I and FP64 triangular solves); the code update's tables

@@ -1082,7 +1082,7 @@ hipError_t cdl_start(cip_plan_t p, hipStream_t st) {
 // d^ (3D: Sherman-Morrison per 3D frequency; 2D: Woodbury with an S x S
 // Cholesky per frequency), returned as d^ + e^ (the dual is kept as plane
 // spectra); d + e to space; g = projection of d + e; the spectra g^ of
-// the placed g; e^ += g^ - d^ and the spectra of g - e; filter tables from
+// the placed g; e^ += d^ - g^ and the spectra of g - e; filter tables from
 // g^; d^ = D(g) z for the next x-update. Two batched 2D FFTs of the filter
 // planes per step.
 // One D, G, E step with penalty sigma; the code tables for the next

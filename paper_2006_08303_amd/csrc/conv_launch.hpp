@@ -37,10 +37,10 @@ hipError_t conv_dhat2(const cx<float>* zh, const cx<float>* th, cx<float>* dhat,
 hipError_t cdl_project(const float* dpl, const float* e, float* gtap, int M, int S, int N1, int N2,
                        int L, hipStream_t st);
 // frequency-domain dual (see conv.hpp): from s = d^ + e^ and g^,
-// e^ += g^ - d^, ge = g^ - e^, gs = g^
+// e^ += d^ - g^ (= s - g^), ge = g^ - e^, gs = g^
 hipError_t cdl_fdual(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs, size_t n,
                      hipStream_t st);
-// the same at a check of sigma: partial sums of |g^ - d^|^2 (half-spectrum
+// the same at a check of sigma: partial sums of |d^ - g^|^2 (half-spectrum
 // weights) and of |gtap - gprev|^2, one pair per work-group (CDL_RES_GROUPS)
 constexpr int CDL_RES_GROUPS = 1024;
 hipError_t cdl_fdual_res(cx<float>* e, cx<float>* ge, const cx<float>* sd, cx<float>* gs,
