@@ -182,6 +182,27 @@ def test_conv3d_dictionary_learning_full_size_1024():
     parity.check(got, ref, 1e-4)
 
 
+@pytest.mark.parametrize("prior", ["conv2d", "conv3d"])
+def test_dictionary_learning_1024_100_iterations_stays_feasible(prior):
+    """The timed learning configuration (1024^2 x 3, 32 filters of 11 x 11 or
+    3 x 11 x 11, sigma = 10, 100 iterations), beyond what the oracle runs in
+    seconds: properties that hold at any size. Every learned filter has unit
+    norm on its support, x is finite, and the dictionary moved. (With the
+    dual of the split growing every step, the filter norms overflowed FP32
+    near iteration 75 and the filters became zero.)"""
+    x, psf, y, filt = (_conv_problem if prior == "conv2d" else _conv3_problem)(1024, 3, 3, 32, 11)
+    plan = cip.Plan(_t(psf), prior, 1.0, 1e-3, 8.0, filters=_t(filt), dict_update=True)
+    got = _np(plan.solve(_t(y), 100))
+    g = _np(plan.dictionary())
+    norms = np.sqrt((g.reshape(g.shape[0], -1) ** 2).sum(axis=1))
+    moved = admm.rel_l2(g, filt)
+    print(f"{prior} 1024^2 learning x 100: filter norms {norms.min():.7f} .. {norms.max():.7f}, "
+          f"moved {moved:.3e}", flush=True)
+    assert np.isfinite(got).all()
+    assert np.abs(norms - 1.0).max() < 1e-5
+    assert moved > 1e-3
+
+
 @pytest.mark.parametrize("N,K,S,M,L,iters,sigma,mu", [(32, 2, 2, 4, 3, 6, 10.0, 0.0),
                                                       (64, 3, 3, 8, 5, 8, 10.0, 0.0),
                                                       (64, 3, 3, 8, 5, 8, 1.0, 0.01),
