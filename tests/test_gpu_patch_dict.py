@@ -249,3 +249,21 @@ def test_dictionary_learning_plans_are_not_captured():
     b.launch()
     torch.cuda.synchronize()
     assert torch.equal(xs, ref)
+
+
+def test_patch_dictionary_learning_1024_100_iterations_stays_feasible():
+    """The timed learning configuration (1024^2 x 3, A = 256, the paper's
+    sigma = 1, 100 iterations), beyond what the oracle runs in seconds:
+    properties that hold at any size. G has unit Frobenius norm (Eq.
+    patch_based_dic), x is finite, and the dictionary moved."""
+    x, psf, y, D = _problem(1024, 3, 3, 256)
+    plan = cip.Plan(_t(psf), "patch", RHO, LAM, BETA, dictionary=_t(D), dict_update=True,
+                    sigma=1.0)
+    got = _np(plan.solve(_t(y), 100))
+    g = _np(plan.dictionary())
+    moved = np.linalg.norm(g - D)
+    print(f"patch 1024^2 learning x 100: ||G||_F {np.linalg.norm(g):.7f}, G moved {moved:.3e}",
+          flush=True)
+    assert np.isfinite(got).all()
+    assert abs(np.linalg.norm(g) - 1.0) < 1e-5
+    assert moved > 1e-3
